@@ -1,0 +1,77 @@
+"""Pins for oracle.expansions: the addition theorem (eq. 12) and the
+translation identities, checked pointwise against direct evaluation."""
+import numpy as np
+import pytest
+
+from oracle import expansions as ex
+from oracle.fmm import direct_sum, green
+from oracle.special import regular_all, singular_all
+
+
+def test_addition_theorem_eq12():
+    k = 2.3
+    rng = np.random.default_rng(1)
+    y = rng.normal(size=3) * 0.2
+    x = np.array([1.1, -0.6, 0.9])
+    exact = green(k, x, y)
+    P = 24
+    R = regular_all(P, k, y[None])[0]
+    S = singular_all(P, k, x[None])[0]
+    # G = ik sum R_n^{-m}(y) S_n^m(x) with R_n^{-m} = conj(R_n^m) for real k
+    approx = 1j * k * (np.conj(R) * S).sum()
+    assert abs(approx - exact) / abs(exact) < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["rr", "sr", "ss"])
+def test_translation_pointwise(kind):
+    k = 1.7
+    rng = np.random.default_rng(2)
+    t = np.array([0.9, -0.7, 1.2])
+    r = rng.normal(size=3)
+    r *= (0.25 if kind == "sr" else 8.0 if kind == "ss" else 0.6) / np.linalg.norm(r)
+    Pin, Pout = 6, 26
+    if kind == "rr":
+        lhs = regular_all(Pin, k, (r + t)[None])[0]
+        T = ex.rr_matrix(t, k, Pout, Pin)
+        rhs = regular_all(Pout, k, r[None])[0] @ T
+    elif kind == "sr":
+        lhs = singular_all(Pin, k, (r + t)[None])[0]
+        T = ex.sr_matrix(t, k, Pout, Pin)
+        rhs = regular_all(Pout, k, r[None])[0] @ T
+    else:
+        lhs = singular_all(Pin, k, (r + t)[None])[0]
+        T = ex.rr_matrix(t, k, Pout, Pin)
+        rhs = singular_all(Pout, k, r[None])[0] @ T
+    np.testing.assert_allclose(rhs, lhs, rtol=0, atol=1e-9 * np.abs(lhs).max())
+
+
+def test_p2m_m2l_l2p_error_falls_with_P():
+    """Two well-separated boxes: P2M -> M2L -> L2P vs the direct sum."""
+    k = 2.0
+    rng = np.random.default_rng(4)
+    s = 0.25
+    cs = np.zeros(3)
+    ct = np.array([1.0, 0.0, 0.0])
+    ys = cs + rng.uniform(-s / 2, s / 2, (40, 3))
+    xt = ct + rng.uniform(-s / 2, s / 2, (30, 3))
+    q = rng.normal(size=40) + 1j * rng.normal(size=40)
+    ref = direct_sum(k, xt, ys, q)
+    errs = []
+    for P in (2, 4, 6, 8, 10):
+        M = ex.p2m(P, k, cs, ys, q)
+        L = ex.sr_matrix(ct - cs, k, P) @ M
+        y = ex.l2p(P, k, ct, L, xt)
+        errs.append(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+    assert errs[-1] < 1e-7
+
+
+def test_p2l_matches_m2l_of_point():
+    """A single source: P2L at the target centre equals M2L of its P2M."""
+    k, P = 1.3, 6
+    ys = np.array([[0.05, -0.02, 0.03]])
+    q = np.array([0.7 - 0.2j])
+    ct = np.array([0.8, 0.5, -0.4])
+    L1 = ex.p2l(P, k, ct, ys, q)
+    L2 = ex.sr_matrix(ct, k, P, 30) @ ex.p2m(30, k, np.zeros(3), ys, q)
+    np.testing.assert_allclose(L2, L1, atol=1e-10 * np.abs(L1).max())
