@@ -1,0 +1,179 @@
+/*
+ * hfmm.h -- C ABI of the MI355X Helmholtz FMM / BIE / GMRES library.
+ *
+ * The library computes the dense matrix-vector product of the Helmholtz
+ * single-layer kernel G(x, y) = e^{ikR} / (4 pi R), R = |x - y| (eq. (6) of
+ * arXiv 1803.09948) with a spherical-harmonic fast multipole method over an
+ * adaptive Morton-ordered octree (Sec. 2.3: upward P2M/M2M, traversal M2L/P2P,
+ * downward L2L/L2P), and solves the sound-soft boundary integral equation
+ * eq. (7) with restarted GMRES (Sec. 5.1, Sec. 6.4).  Every step runs as a
+ * hand-written HIP kernel for gfx950.
+ *
+ * Conventions shared by all calls
+ *  - Return value: HFMM_OK (0) on success, a negative code on error, or
+ *    HFMM_ENOTCONV (1) as a warning from the solver.  No C++ exception ever
+ *    crosses this boundary.  On error hfmm_last_error() returns a message for
+ *    the calling thread; no output has been written unless stated.
+ *  - "_host" pointers are host memory owned by the caller and only read
+ *    during the call.  "_dev" pointers are device memory on the current HIP
+ *    device, owned by the caller, and accessed in stream order on `stream`
+ *    (hipStream_t passed as void*; NULL is the default stream).
+ *  - Complex vectors are interleaved (re, im): float2 = 8 bytes, double2 =
+ *    16 bytes per entry.  Vectors are always in the caller's original point
+ *    (or panel) order; the Morton order is internal.
+ *  - Expansion order P counts degrees 0..P-1 (P^2 coefficients; the text
+ *    after eq. (14)).  1 <= P <= 16.
+ *  - A tree handle owns its device memory (allocated at build time and when
+ *    a new (k, P) operator is first prepared; never inside a matvec that
+ *    reuses a prepared operator).  Handles may be used from several host
+ *    threads only with external serialisation.
+ */
+#ifndef HFMM_H
+#define HFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HFMM_OK = 0,
+  HFMM_ENOTCONV = 1,   /* GMRES hit maxit: x holds the last iterate, info filled */
+  HFMM_EINVAL = -1,    /* bad argument; nothing was done */
+  HFMM_ENOMEM = -2,    /* device or host allocation failed */
+  HFMM_EHIP = -3,      /* a HIP call failed; message in hfmm_last_error() */
+  HFMM_EINTERNAL = -4
+};
+
+typedef struct hfmm_tree hfmm_tree;
+
+/* Tree / traversal options (the paper leaves these unspecified, Sec. 3.2). */
+typedef struct {
+  int32_t ncrit;     /* a cell with more than ncrit sources splits (default 64) */
+  int32_t max_level; /* deepest level (default 20, at most 20) */
+  double theta;      /* acceptance: 3 (sA+sB)^2 < theta^2 D2 (default 0.5) */
+  double kappa;      /* and k * cell side <= kappa; < 0 means 0.4 * P (default -1) */
+  double eta;        /* BIE near pattern |c_i - c_j| < eta h_j (default 2) */
+  int32_t near_levels; /* BIE near integrals: 4^near_levels sub-triangles (default 3) */
+  int32_t near_order;  /* BIE near integrals: n x n collapsed Gauss rule (default 6) */
+  int32_t reserved[8];
+} hfmm_opts;
+
+typedef struct {
+  int64_t n_src, n_tgt;       /* bodies */
+  int32_t n_cell, n_leaf, n_level;
+  int32_t point_mode;         /* 1: sources = targets (plain matvec) */
+  double centre[3], half;     /* root cube */
+  int64_t n_m2l, n_p2p;       /* cell pairs of the traversal at (k, P) */
+  int64_t p2p_body_pairs;     /* sum over P2P pairs of n_tgt * n_src */
+  int64_t n_tables;           /* distinct M2L translation operators */
+  int64_t n_near;             /* BIE near-correction nonzeros */
+  int64_t device_bytes;       /* device memory held by the handle */
+} hfmm_stats;
+
+typedef struct {
+  int32_t iters;       /* matrix-vector products inside Arnoldi steps */
+  int32_t restarts;
+  double resid_est;    /* Arnoldi estimate |g_{j+1}| / ||b|| at exit */
+  double resid_true;   /* ||b - A x|| / ||b|| recomputed at exit */
+  double seconds;
+} hfmm_gmres_info;
+
+/* Fills `opts` with the defaults above. */
+int hfmm_default_opts(hfmm_opts* opts);
+
+/* Point-mode tree over n points (sources = targets), Sec. 2.3 and Sec. 3.1.
+ *  xyz_host: n x 3 float32, row-major (x0 y0 z0 x1 ...).
+ *  opts: NULL for defaults.
+ *  EINVAL: n < 1, non-finite coordinates, ncrit < 1, theta <= 0.
+ *  On success *out is a new handle (free with hfmm_tree_free). */
+int hfmm_build_tree(const float* xyz_host, int64_t n, const hfmm_opts* opts,
+                    hfmm_tree** out);
+
+/* BIE handle for a closed flat-triangle surface (eq. (7) discretised by
+ * centroid collocation, Sec. 2.2): the unknown is one density value per
+ * triangle; sources are 3 interior Gauss points per triangle (weight A/3),
+ * targets are the centroids.  Near panels (|c_i - c_j| < eta h_j) get an
+ * accurate panel integral and the diagonal the weakly singular self integral
+ * (Sec. 2.2 and the near/self branches of the P2P listing in Sec. 3.1).
+ *  verts_host: nv x 3 float64;  tris_host: nt x 3 int32 vertex indices.
+ *  EINVAL: nv < 3, nt < 1, index out of range, degenerate triangle. */
+int hfmm_build_bie(const double* verts_host, int64_t nv, const int32_t* tris_host,
+                   int64_t nt, const hfmm_opts* opts, hfmm_tree** out);
+
+/* Builds (once) the traversal lists, translation operators and, for a BIE
+ * handle, the near and self corrections for wavenumber k and order P.
+ * Called implicitly by hfmm_matvec / hfmm_gmres_solve.
+ *  EINVAL: k <= 0 or non-finite, P outside [1, 16]. */
+int hfmm_prepare(hfmm_tree* tree, double k, int32_t P, void* stream);
+
+/* y = A x (Sec. 2.3; eq. (11) for a point handle, the collocation matrix of
+ * eq. (7) for a BIE handle), FP32 arithmetic with FP32 accumulation.
+ *  x_dev: complex64[n] (point handle) or complex64[nt] (BIE handle).
+ *  y_dev: complex64, same length; must not alias x_dev.
+ *  Point handle: y_i = sum_{j, R_ij > 0} x_j G(x_i, x_j) up to FMM truncation. */
+int hfmm_matvec(hfmm_tree* tree, double k, int32_t P, const void* x_dev,
+                void* y_dev, void* stream);
+
+/* Restarted GMRES(restart) for A x = b on a BIE handle (Sec. 5.1: complex
+ * GMRES, exit at a relative residual tol, Sec. 6.4).  The Arnoldi
+ * orthogonalisation (two passes of classical Gram-Schmidt), the Givens
+ * least-squares update and the self-panel diagonal run in FP64 on the
+ * device; the FMM product in FP32.
+ *  b_dev: complex128[nt];  x_dev: complex128[nt], in: initial guess, out: x.
+ *  Returns HFMM_OK when ||b - A x|| / ||b|| <= tol, HFMM_ENOTCONV after maxit
+ *  products (x then holds the last iterate).  EINVAL: tol <= 0, restart < 1,
+ *  restart > 200, maxit < 1, point handle. */
+int hfmm_gmres_solve(hfmm_tree* tree, double k, int32_t P, const void* b_dev,
+                     void* x_dev, double tol, int32_t restart, int32_t maxit,
+                     hfmm_gmres_info* info, void* stream);
+
+/* b_i = exp(i k d . c_i) at the centroids of a BIE handle (complex128[nt],
+ * caller order): the incident plane wave of eq. (7).  dir_host: 3 doubles. */
+int hfmm_bie_plane_wave(hfmm_tree* tree, double k, const double* dir_host,
+                        void* b_dev, void* stream);
+
+/* One fused launch sequence for `count` independent point-mode products
+ * y_i = A_i x_i (each with its own tree, k and P).  Work of all instances is
+ * concatenated into shared work queues, so uneven instances fill the chip.
+ * Results equal those of hfmm_matvec on each instance alone, bit for bit.
+ * trees, ks, Ps, xs_dev, ys_dev: arrays of length count.  EINVAL as for
+ * hfmm_matvec, or count < 1. */
+int hfmm_batch_matvec(int32_t count, hfmm_tree* const* trees, const double* ks,
+                      const int32_t* Ps, const void* const* xs_dev,
+                      void* const* ys_dev, void* stream);
+
+/* Statistics of the tree and, if P > 0, of the prepared (k, P) operator. */
+int hfmm_tree_stats(hfmm_tree* tree, double k, int32_t P, hfmm_stats* out);
+
+/* Host copies of the tree for structural tests (no device access).
+ *  src_perm/tgt_perm: int32[n_src]/[n_tgt], sorted position -> input index.
+ *  cells: int32[n_cell][10] = level, i, j, k (cell coordinates at its level),
+ *  src_begin, src_end, tgt_begin, tgt_end, child_begin, child_end.
+ *  Any pointer may be NULL. */
+int hfmm_tree_export(const hfmm_tree* tree, int32_t* src_perm, int32_t* tgt_perm,
+                     int32_t* cells);
+
+/* Host copies of the traversal lists at (k, P): int32 pairs (target cell,
+ * source cell), n_m2l and n_p2p of them (hfmm_tree_stats gives the counts).
+ * Builds the lists on the host if needed; touches no device memory. */
+int hfmm_lists_export(hfmm_tree* tree, double k, int32_t P, int32_t* m2l_pairs,
+                      int32_t* p2p_pairs);
+
+/* Per-phase device times (ms) of the last hfmm_matvec when timing is on:
+ * [0] P2M, [1] M2M, [2] M2L, [3] L2L, [4] L2P, [5] P2P, [6] BIE corrections,
+ * [7] total.  hfmm_set_timing(tree, 1) records HIP events around each phase
+ * on the call's stream. */
+int hfmm_set_timing(hfmm_tree* tree, int32_t on);
+int hfmm_phase_times(const hfmm_tree* tree, float* ms8);
+
+void hfmm_tree_free(hfmm_tree* tree);
+const char* hfmm_last_error(void);
+int hfmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFMM_H */

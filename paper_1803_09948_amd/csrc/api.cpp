@@ -1,0 +1,609 @@
+// C ABI of the hfmm library: handles, operator preparation and the matvec.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <unordered_map>
+
+#include "hfmm_internal.h"
+
+namespace hfmm {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                \
+      return HFMM_EHIP;                                                            \
+    }                                                                              \
+  } while (0)
+
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+int DevBuf::alloc(size_t n) {
+  if (p) {
+    (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  if (n == 0) n = 16;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    p = nullptr;
+    set_error(std::string("hipMalloc(") + std::to_string(n) + "): " + hipGetErrorString(e));
+    return HFMM_ENOMEM;
+  }
+  bytes = n;
+  return HFMM_OK;
+}
+
+template <class T>
+static int upload(DevBuf& b, const std::vector<T>& v) {
+  int rc = b.alloc(v.size() * sizeof(T));
+  if (rc) return rc;
+  if (!v.empty()) HIP_TRY(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return HFMM_OK;
+}
+
+Tree::~Tree() {
+  if (ev_made)
+    for (auto& e : ev) (void)hipEventDestroy(e);
+}
+
+int upload_geometry(Tree& t) {
+  const HostTree& h = t.h;
+  std::vector<float4> sp(h.nsrc), tp(h.ntgt);
+  for (int64_t i = 0; i < h.nsrc; ++i)
+    sp[i] = make_float4(h.src_xyz[3 * i], h.src_xyz[3 * i + 1], h.src_xyz[3 * i + 2], 0.f);
+  for (int64_t i = 0; i < h.ntgt; ++i)
+    tp[i] = make_float4(h.tgt_xyz[3 * i], h.tgt_xyz[3 * i + 1], h.tgt_xyz[3 * i + 2], 0.f);
+  int rc;
+  if ((rc = upload(t.d_src_pos, sp)) || (rc = upload(t.d_tgt_pos, tp))) return rc;
+  std::vector<int32_t> sidx(h.nsrc);
+  std::vector<float> sw;
+  if (!t.bie) {
+    for (int64_t i = 0; i < h.nsrc; ++i) sidx[i] = h.src_perm[i];
+  } else {
+    // sources are the Gauss points 3*panel + g, weight area/3
+    sw.resize(h.nsrc);
+    for (int64_t i = 0; i < h.nsrc; ++i) {
+      int32_t s = h.src_perm[i];
+      int32_t pnl = s / 3;
+      sidx[i] = pnl;
+      const double* v = t.verts.data();
+      const int32_t* tr = t.tris.data() + 3 * pnl;
+      double a[3], b[3], c[3];
+      for (int d = 0; d < 3; ++d) {
+        a[d] = v[3 * tr[0] + d];
+        b[d] = v[3 * tr[1] + d];
+        c[d] = v[3 * tr[2] + d];
+      }
+      double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+      double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+      double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+      double area = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      sw[i] = (float)(area / 3.0);
+    }
+  }
+  if ((rc = upload(t.d_src_idx, sidx))) return rc;
+  if (t.bie && (rc = upload(t.d_src_w, sw))) return rc;
+  if ((rc = upload(t.d_tgt_perm, h.tgt_perm))) return rc;
+  int nc = h.ncell();
+  std::vector<int4> cells(nc), topo(nc);
+  std::vector<float4> geo(nc);
+  std::vector<int32_t> clev(nc), sl, tl;
+  for (int i = 0; i < nc; ++i) {
+    cells[i] = make_int4(h.sb[i], h.se[i], h.tb[i], h.te[i]);
+    double c[3];
+    h.centre(i, c);
+    geo[i] = make_float4((float)c[0], (float)c[1], (float)c[2], (float)h.half(i));
+    clev[i] = h.level[i];
+    int oct = (h.ijk[3 * i] & 1) | ((h.ijk[3 * i + 1] & 1) << 1) | ((h.ijk[3 * i + 2] & 1) << 2);
+    topo[i] = make_int4(h.cb[i], h.ce[i], h.parent[i], oct | (h.level[i] << 3));
+    if (h.leaf(i)) {
+      if (h.se[i] > h.sb[i]) sl.push_back(i);
+      if (h.te[i] > h.tb[i]) tl.push_back(i);
+    }
+  }
+  if ((rc = upload(t.d_cells, cells)) || (rc = upload(t.d_geo, geo)) || (rc = upload(t.d_clev, clev)) ||
+      (rc = upload(t.d_topo, topo)) || (rc = upload(t.d_src_leaves, sl)) ||
+      (rc = upload(t.d_tgt_leaves, tl)))
+    return rc;
+  t.n_src_leaves = (int32_t)sl.size();
+  t.n_tgt_leaves = (int32_t)tl.size();
+  t.geo_bytes = (int64_t)(t.d_src_pos.bytes + t.d_tgt_pos.bytes + t.d_src_idx.bytes + t.d_src_w.bytes +
+                          t.d_tgt_perm.bytes + t.d_cells.bytes + t.d_geo.bytes + t.d_clev.bytes +
+                          t.d_topo.bytes + t.d_src_leaves.bytes + t.d_tgt_leaves.bytes);
+  return HFMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Operator preparation for (k, P)
+// ---------------------------------------------------------------------------
+struct Key128 {
+  uint64_t a, b;
+  bool operator==(const Key128& o) const { return a == o.a && b == o.b; }
+};
+struct Key128Hash {
+  size_t operator()(const Key128& k) const {
+    uint64_t h = k.a * 0x9E3779B97F4A7C15ull ^ (k.b + 0x7F4A7C159E3779B9ull + (k.a << 6) + (k.a >> 2));
+    return (size_t)(h ^ (h >> 31));
+  }
+};
+
+static int build_lists_host(Tree& t, double k, int P, Plan& pl) {
+  double kappa = t.kappa < 0 ? 0.4 * P : t.kappa;
+  dual_tree_traversal(t.h, k, t.theta, kappa, pl.lists);
+  int64_t pp = 0;
+  for (size_t i = 0; i < pl.lists.p2p_a.size(); ++i) {
+    int a = pl.lists.p2p_a[i], b = pl.lists.p2p_b[i];
+    pp += int64_t(t.h.te[a] - t.h.tb[a]) * int64_t(t.h.se[b] - t.h.sb[b]);
+  }
+  pl.p2p_body_pairs = pp;
+  return HFMM_OK;
+}
+
+int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
+  uint64_t kb;
+  std::memcpy(&kb, &k, 8);
+  auto key = std::make_pair(kb, P);
+  auto it = t.plans.find(key);
+  if (it != t.plans.end() && it->second->d_tables.p) {
+    *out = it->second.get();
+    return HFMM_OK;
+  }
+  int rc;
+  if (!t.d_cells.p && (rc = upload_geometry(t))) return rc;
+  auto plp = std::make_unique<Plan>();
+  Plan& pl = *plp;
+  pl.k = k;
+  pl.P = P;
+  const HostTree& h = t.h;
+  if ((rc = build_lists_host(t, k, P, pl))) return rc;
+  const int P2 = P * P;
+  const int nlev = h.nlevels();
+  pl.rho.resize(nlev);
+  for (int l = 0; l < nlev; ++l) pl.rho[l] = std::min(1.0, k * 2.0 * h.H / double(1 << l));
+  // operators: M2M and L2L per child level and octant
+  std::vector<OpDesc> ops;
+  pl.m2m_base.assign(nlev, 0);
+  pl.l2l_base.assign(nlev, 0);
+  for (int l = 1; l < nlev; ++l) {
+    double hc = h.H / double(1 << l);
+    pl.m2m_base[l] = (int32_t)ops.size();
+    for (int o = 0; o < 8; ++o) {
+      OpDesc d{};
+      for (int dd = 0; dd < 3; ++dd) d.t[dd] = -(2.0 * ((o >> dd) & 1) - 1.0) * hc;
+      d.rho_in = pl.rho[l];
+      d.rho_out = pl.rho[l - 1];
+      d.kind = OP_M2M;
+      ops.push_back(d);
+    }
+    pl.l2l_base[l] = (int32_t)ops.size();
+    for (int o = 0; o < 8; ++o) {
+      OpDesc d{};
+      for (int dd = 0; dd < 3; ++dd) d.t[dd] = (2.0 * ((o >> dd) & 1) - 1.0) * hc;
+      d.rho_in = pl.rho[l - 1];
+      d.rho_out = pl.rho[l];
+      d.kind = OP_L2L;
+      ops.push_back(d);
+    }
+  }
+  // M2L: canonical offsets under the 16 reflections
+  const size_t npair = pl.lists.m2l_a.size();
+  std::unordered_map<Key128, int32_t, Key128Hash> opmap;
+  std::vector<int4> pairs(npair);
+  int32_t m2l_base = (int32_t)ops.size();
+  for (size_t i = 0; i < npair; ++i) {
+    int a = pl.lists.m2l_a[i], b = pl.lists.m2l_b[i];
+    int la = h.level[a], lb = h.level[b];
+    int L = std::max(la, lb);
+    int64_t d[3];
+    for (int dd = 0; dd < 3; ++dd) {
+      int64_t ca = -(int64_t(1) << L) + (2 * (int64_t)h.ijk[3 * a + dd] + 1) * (int64_t(1) << (L - la));
+      int64_t cb = -(int64_t(1) << L) + (2 * (int64_t)h.ijk[3 * b + dd] + 1) * (int64_t(1) << (L - lb));
+      d[dd] = ca - cb;
+    }
+    int g = (d[0] < 0 ? 1 : 0) | (d[1] < 0 ? 2 : 0) | (d[2] < 0 ? 4 : 0);
+    int64_t w[3] = {std::llabs(d[0]), std::llabs(d[1]), std::llabs(d[2])};
+    if (w[0] < w[1]) {
+      std::swap(w[0], w[1]);
+      g |= 8;
+    }
+    Key128 kk{(uint64_t)la | ((uint64_t)lb << 8) | ((uint64_t)w[2] << 16),
+              (uint64_t)w[0] | ((uint64_t)w[1] << 32)};
+    auto f = opmap.find(kk);
+    int32_t op;
+    if (f == opmap.end()) {
+      op = (int32_t)ops.size();
+      opmap.emplace(kk, op);
+      OpDesc dsc{};
+      double u = h.H / double(1 << L);
+      dsc.t[0] = (double)w[0] * u;
+      dsc.t[1] = (double)w[1] * u;
+      dsc.t[2] = (double)w[2] * u;
+      dsc.rho_in = pl.rho[lb];
+      dsc.rho_out = pl.rho[la];
+      dsc.kind = OP_M2L;
+      ops.push_back(dsc);
+    } else {
+      op = f->second;
+    }
+    pairs[i] = make_int4(a, b, g, op);
+  }
+  pl.n_tables = (int64_t)ops.size() - m2l_base;
+  pl.n_ops = (int64_t)ops.size();
+  // group pairs by operator, then target, then source
+  std::vector<int32_t> order(npair);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const int4 &p = pairs[x], &q = pairs[y];
+    if (p.w != q.w) return p.w < q.w;
+    if (p.x != q.x) return p.x < q.x;
+    return p.y < q.y;
+  });
+  std::vector<int4> spairs(npair), chunks;
+  for (size_t i = 0; i < npair; ++i) spairs[i] = pairs[order[i]];
+  const int CH = m2l_chunk_size();
+  for (size_t i = 0; i < npair;) {
+    size_t j = i;
+    while (j < npair && spairs[j].w == spairs[i].w && j - i < (size_t)CH) ++j;
+    chunks.push_back(make_int4(spairs[i].w, (int)i, (int)j, 0));
+    i = j;
+  }
+  pl.n_m2l_chunks = (int32_t)chunks.size();
+  // P2P work: per target leaf, merged source intervals
+  std::vector<int4> work;
+  std::vector<int2> ivals;
+  {
+    const size_t np = pl.lists.p2p_a.size();
+    std::vector<int32_t> ord(np);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+      int ax = pl.lists.p2p_a[x], ay = pl.lists.p2p_a[y];
+      if (ax != ay) return ax < ay;
+      return h.sb[pl.lists.p2p_b[x]] < h.sb[pl.lists.p2p_b[y]];
+    });
+    for (size_t i = 0; i < np;) {
+      int a = pl.lists.p2p_a[ord[i]];
+      int ib = (int)ivals.size();
+      size_t j = i;
+      while (j < np && pl.lists.p2p_a[ord[j]] == a) {
+        int b = pl.lists.p2p_b[ord[j]];
+        int s0 = h.sb[b], s1 = h.se[b];
+        if (!ivals.empty() && (int)ivals.size() > ib && ivals.back().y == s0)
+          ivals.back().y = s1;
+        else
+          ivals.push_back(make_int2(s0, s1));
+        ++j;
+      }
+      work.push_back(make_int4(h.tb[a], h.te[a], ib, (int)ivals.size()));
+      i = j;
+    }
+  }
+  pl.n_p2p_work = (int32_t)work.size();
+  // symmetry maps and their inverses for the outputs
+  std::vector<int32_t> sdst, sph, oidx(16 * P2), oph(16 * P2);
+  symmetry_map(P, sdst, sph);
+  for (int g = 0; g < 16; ++g)
+    for (int o = 0; o < P2; ++o) {
+      int r = sdst[g * P2 + o];
+      oidx[g * P2 + r] = o;
+      oph[g * P2 + r] = (4 - sph[g * P2 + o]) & 3;
+    }
+  // upload
+  if ((rc = upload(pl.d_ops, ops)) || (rc = upload(pl.d_rho, pl.rho)) ||
+      (rc = upload(pl.d_m2m_base, pl.m2m_base)) || (rc = upload(pl.d_l2l_base, pl.l2l_base)) ||
+      (rc = upload(pl.d_m2l_chunks, chunks)) || (rc = upload(pl.d_m2l_pairs, spairs)) ||
+      (rc = upload(pl.d_p2p_work, work)) || (rc = upload(pl.d_p2p_ivals, ivals)) ||
+      (rc = upload(pl.d_symdst, sdst)) || (rc = upload(pl.d_symph, sph)) ||
+      (rc = upload(pl.d_outidx, oidx)) || (rc = upload(pl.d_outph, oph)))
+    return rc;
+  // coupling coefficients and tables
+  const Coupling& cp = coupling(P);
+  std::vector<double2> cv(cp.re.size());
+  for (size_t i = 0; i < cv.size(); ++i) cv[i] = make_double2(cp.re[i], cp.im[i]);
+  DevBuf d_off, d_lm, d_val;
+  if ((rc = upload(d_off, cp.off)) || (rc = upload(d_lm, cp.lm)) || (rc = upload(d_val, cv)))
+    return rc;
+  if ((rc = pl.d_tables.alloc((size_t)pl.n_ops * P2 * P2 * sizeof(float2)))) return rc;
+  launch_gen_tables(pl.d_ops.as<OpDesc>(), (int)pl.n_ops, P, k, d_off.as<int32_t>(),
+                    d_lm.as<int32_t>(), d_val.as<double2>(), pl.d_tables.as<float2>(), s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  pl.device_bytes = (int64_t)(pl.d_ops.bytes + pl.d_tables.bytes + pl.d_rho.bytes + pl.d_m2l_chunks.bytes +
+                              pl.d_m2l_pairs.bytes + pl.d_p2p_work.bytes + pl.d_p2p_ivals.bytes +
+                              pl.d_symdst.bytes * 4);
+  // scratch
+  if (t.scratchP < P) {
+    if ((rc = t.d_q.alloc((size_t)h.nsrc * sizeof(float2))) ||
+        (rc = t.d_M.alloc((size_t)h.ncell() * P2 * sizeof(float2))) ||
+        (rc = t.d_L.alloc((size_t)h.ncell() * P2 * sizeof(float2))) ||
+        (rc = t.d_ys.alloc((size_t)h.ntgt * sizeof(float2))))
+      return rc;
+    t.scratchP = P;
+  }
+  t.plans[key] = std::move(plp);
+  *out = t.plans[key].get();
+  return HFMM_OK;
+}
+
+static int check_kP(double k, int P) {
+  if (!(k > 0.0) || !std::isfinite(k)) {
+    set_error("k must be positive and finite");
+    return HFMM_EINVAL;
+  }
+  if (P < 1 || P > kMaxP) {
+    set_error("P must be in [1, 16]");
+    return HFMM_EINVAL;
+  }
+  return HFMM_OK;
+}
+
+static int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_t s) {
+  const HostTree& h = t.h;
+  const int P = pl.P, P2 = P * P;
+  const float kf = (float)pl.k;
+  auto mark = [&](int i) -> int {
+    if (t.timing) HIP_TRY(hipEventRecord(t.ev[i], s));
+    return HFMM_OK;
+  };
+  int rc;
+  if ((rc = mark(0))) return rc;
+  HIP_TRY(hipMemsetAsync(t.d_M.p, 0, (size_t)h.ncell() * P2 * sizeof(float2), s));
+  HIP_TRY(hipMemsetAsync(t.d_L.p, 0, (size_t)h.ncell() * P2 * sizeof(float2), s));
+  launch_gather(h.nsrc, t.d_src_idx.as<int32_t>(), t.bie ? t.d_src_w.as<float>() : nullptr, x,
+                t.d_q.as<float2>(), s);
+  launch_p2m(t.d_src_leaves.as<int32_t>(), t.n_src_leaves, t.d_cells.as<int4>(), t.d_geo.as<float4>(),
+             t.d_clev.as<int32_t>(), pl.d_rho.as<double>(), t.d_src_pos.as<float4>(),
+             t.d_q.as<float2>(), kf, P, t.d_M.as<float2>(), s);
+  if ((rc = mark(1))) return rc;
+  for (int l = h.nlevels() - 2; l >= 0; --l)
+    launch_m2m(h.level_off[l], h.level_off[l + 1], t.d_topo.as<int4>(), pl.d_m2m_base.as<int32_t>(),
+               pl.d_tables.as<float2>(), P, t.d_M.as<float2>(), s);
+  if ((rc = mark(2))) return rc;
+  launch_m2l(pl.d_m2l_chunks.as<int4>(), pl.n_m2l_chunks, pl.d_m2l_pairs.as<int4>(),
+             pl.d_tables.as<float2>(), pl.d_symdst.as<int32_t>(), pl.d_symph.as<int32_t>(),
+             pl.d_outidx.as<int32_t>(), pl.d_outph.as<int32_t>(), P, t.d_M.as<float2>(),
+             t.d_L.as<float2>(), s);
+  if ((rc = mark(3))) return rc;
+  for (int l = 1; l < h.nlevels(); ++l)
+    launch_l2l(h.level_off[l], h.level_off[l + 1], t.d_topo.as<int4>(), pl.d_l2l_base.as<int32_t>(),
+               pl.d_tables.as<float2>(), P, t.d_L.as<float2>(), s);
+  if ((rc = mark(4))) return rc;
+  launch_l2p(t.d_tgt_leaves.as<int32_t>(), t.n_tgt_leaves, t.d_cells.as<int4>(), t.d_geo.as<float4>(),
+             t.d_clev.as<int32_t>(), pl.d_rho.as<double>(), t.d_tgt_pos.as<float4>(), kf, P,
+             t.d_L.as<float2>(), t.d_ys.as<float2>(), s);
+  if ((rc = mark(5))) return rc;
+  launch_p2p(pl.d_p2p_work.as<int4>(), pl.n_p2p_work, pl.d_p2p_ivals.as<int2>(),
+             t.d_tgt_pos.as<float4>(), t.d_src_pos.as<float4>(), t.d_q.as<float2>(), kf,
+             t.d_ys.as<float2>(), s);
+  if ((rc = mark(6))) return rc;
+  launch_scatter(h.ntgt, t.d_tgt_perm.as<int32_t>(), t.d_ys.as<float2>(), y, s);
+  if ((rc = mark(7))) return rc;
+  if ((rc = mark(8))) return rc;
+  HIP_TRY(hipGetLastError());
+  return HFMM_OK;
+}
+
+}  // namespace hfmm
+
+using namespace hfmm;
+
+#define API_GUARD_BEGIN try {
+#define API_GUARD_END                          \
+  }                                            \
+  catch (const std::bad_alloc&) {              \
+    set_error("host allocation failed");       \
+    return HFMM_ENOMEM;                        \
+  }                                            \
+  catch (const std::exception& e) {            \
+    set_error(e.what());                       \
+    return HFMM_EINTERNAL;                     \
+  }                                            \
+  catch (...) {                                \
+    set_error("unknown exception");            \
+    return HFMM_EINTERNAL;                     \
+  }
+
+extern "C" {
+
+int hfmm_version(void) { return 100; }
+const char* hfmm_last_error(void) { return g_err.c_str(); }
+
+int hfmm_default_opts(hfmm_opts* o) {
+  if (!o) return HFMM_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->ncrit = 64;
+  o->max_level = 20;
+  o->theta = 0.5;
+  o->kappa = -1.0;
+  o->eta = 2.0;
+  o->near_levels = 3;
+  o->near_order = 6;
+  return HFMM_OK;
+}
+
+static int apply_opts(Tree& t, const hfmm_opts* o) {
+  hfmm_opts d;
+  hfmm_default_opts(&d);
+  if (!o) o = &d;
+  if (o->ncrit < 1) return set_error("ncrit must be >= 1"), HFMM_EINVAL;
+  if (o->max_level < 0 || o->max_level > kMaxLevel) return set_error("max_level in [0, 20]"), HFMM_EINVAL;
+  if (!(o->theta > 0.0) || !std::isfinite(o->theta)) return set_error("theta must be > 0"), HFMM_EINVAL;
+  if (!(o->eta > 0.0)) return set_error("eta must be > 0"), HFMM_EINVAL;
+  if (o->near_levels < 0 || o->near_levels > 5 || o->near_order < 1 || o->near_order > 16)
+    return set_error("near_levels in [0,5], near_order in [1,16]"), HFMM_EINVAL;
+  t.ncrit = o->ncrit;
+  t.max_level = o->max_level;
+  t.theta = o->theta;
+  t.kappa = o->kappa;
+  t.eta = o->eta;
+  t.near_levels = o->near_levels;
+  t.near_order = o->near_order;
+  return HFMM_OK;
+}
+
+int hfmm_build_tree(const float* xyz, int64_t n, const hfmm_opts* opts, hfmm_tree** out) {
+  API_GUARD_BEGIN
+  if (!out) return set_error("out is NULL"), HFMM_EINVAL;
+  *out = nullptr;
+  if (!xyz || n < 1 || n > (int64_t(1) << 30)) return set_error("need 1 <= n <= 2^30 points"), HFMM_EINVAL;
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(xyz[i])) return set_error("non-finite coordinate"), HFMM_EINVAL;
+  auto t = std::make_unique<Tree>();
+  int rc = apply_opts(*t, opts);
+  if (rc) return rc;
+  build_tree(xyz, n, nullptr, 0, t->ncrit, t->max_level, t->h);
+  *out = reinterpret_cast<hfmm_tree*>(t.release());
+  return HFMM_OK;
+  API_GUARD_END
+}
+
+int hfmm_prepare(hfmm_tree* tree, double k, int32_t P, void* stream) {
+  API_GUARD_BEGIN
+  if (!tree) return set_error("tree is NULL"), HFMM_EINVAL;
+  int rc = check_kP(k, P);
+  if (rc) return rc;
+  Plan* pl;
+  return prepare(*reinterpret_cast<Tree*>(tree), k, P, (hipStream_t)stream, &pl);
+  API_GUARD_END
+}
+
+int hfmm_matvec(hfmm_tree* tree, double k, int32_t P, const void* x, void* y, void* stream) {
+  API_GUARD_BEGIN
+  if (!tree || !x || !y) return set_error("NULL argument"), HFMM_EINVAL;
+  if (x == y) return set_error("x and y must not alias"), HFMM_EINVAL;
+  int rc = check_kP(k, P);
+  if (rc) return rc;
+  Tree& t = *reinterpret_cast<Tree*>(tree);
+  hipStream_t s = (hipStream_t)stream;
+  Plan* pl;
+  if ((rc = prepare(t, k, P, s, &pl))) return rc;
+  if (t.timing && !t.ev_made) {
+    for (auto& e : t.ev) HIP_TRY(hipEventCreate(&e));
+    t.ev_made = true;
+  }
+  if ((rc = matvec_impl(t, *pl, (const float2*)x, (float2*)y, s))) return rc;
+  if (t.timing) {
+    HIP_TRY(hipEventSynchronize(t.ev[8]));
+    float ms;
+    // phases: P2M (0-1), M2M (1-2), M2L (2-3), L2L (3-4), L2P (4-5), P2P (5-6), BIE (6-7)
+    for (int i = 0; i < 7; ++i) {
+      HIP_TRY(hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]));
+      t.phase_ms[i] = ms;
+    }
+    HIP_TRY(hipEventElapsedTime(&ms, t.ev[0], t.ev[8]));
+    t.phase_ms[7] = ms;
+  }
+  return HFMM_OK;
+  API_GUARD_END
+}
+
+int hfmm_set_timing(hfmm_tree* tree, int32_t on) {
+  if (!tree) return set_error("tree is NULL"), HFMM_EINVAL;
+  reinterpret_cast<Tree*>(tree)->timing = on != 0;
+  return HFMM_OK;
+}
+
+int hfmm_phase_times(const hfmm_tree* tree, float* ms8) {
+  if (!tree || !ms8) return set_error("NULL argument"), HFMM_EINVAL;
+  std::memcpy(ms8, reinterpret_cast<const Tree*>(tree)->phase_ms, 8 * sizeof(float));
+  return HFMM_OK;
+}
+
+int hfmm_tree_stats(hfmm_tree* tree, double k, int32_t P, hfmm_stats* o) {
+  API_GUARD_BEGIN
+  if (!tree || !o) return set_error("NULL argument"), HFMM_EINVAL;
+  Tree& t = *reinterpret_cast<Tree*>(tree);
+  std::memset(o, 0, sizeof(*o));
+  const HostTree& h = t.h;
+  o->n_src = h.nsrc;
+  o->n_tgt = h.ntgt;
+  o->n_cell = h.ncell();
+  int nl = 0;
+  for (int i = 0; i < h.ncell(); ++i) nl += h.leaf(i);
+  o->n_leaf = nl;
+  o->n_level = h.nlevels();
+  o->point_mode = h.point_mode ? 1 : 0;
+  for (int d = 0; d < 3; ++d) o->centre[d] = h.c[d];
+  o->half = h.H;
+  o->device_bytes = t.geo_bytes;
+  if (P > 0) {
+    int rc = check_kP(k, P);
+    if (rc) return rc;
+    uint64_t kb;
+    std::memcpy(&kb, &k, 8);
+    auto it = t.plans.find(std::make_pair(kb, (int)P));
+    if (it != t.plans.end()) {
+      const Plan& pl = *it->second;
+      o->n_m2l = (int64_t)pl.lists.m2l_a.size();
+      o->n_p2p = (int64_t)pl.lists.p2p_a.size();
+      o->p2p_body_pairs = pl.p2p_body_pairs;
+      o->n_tables = pl.n_tables;
+      o->n_near = pl.n_near;
+      o->device_bytes += pl.device_bytes;
+    } else {
+      Plan pl;
+      build_lists_host(t, k, P, pl);
+      o->n_m2l = (int64_t)pl.lists.m2l_a.size();
+      o->n_p2p = (int64_t)pl.lists.p2p_a.size();
+      o->p2p_body_pairs = pl.p2p_body_pairs;
+    }
+  }
+  return HFMM_OK;
+  API_GUARD_END
+}
+
+int hfmm_tree_export(const hfmm_tree* tree, int32_t* src_perm, int32_t* tgt_perm, int32_t* cells) {
+  if (!tree) return set_error("tree is NULL"), HFMM_EINVAL;
+  const HostTree& h = reinterpret_cast<const Tree*>(tree)->h;
+  if (src_perm) std::memcpy(src_perm, h.src_perm.data(), h.nsrc * sizeof(int32_t));
+  if (tgt_perm) std::memcpy(tgt_perm, h.tgt_perm.data(), h.ntgt * sizeof(int32_t));
+  if (cells)
+    for (int i = 0; i < h.ncell(); ++i) {
+      int32_t* c = cells + 10 * i;
+      c[0] = h.level[i];
+      c[1] = h.ijk[3 * i];
+      c[2] = h.ijk[3 * i + 1];
+      c[3] = h.ijk[3 * i + 2];
+      c[4] = h.sb[i];
+      c[5] = h.se[i];
+      c[6] = h.tb[i];
+      c[7] = h.te[i];
+      c[8] = h.cb[i];
+      c[9] = h.ce[i];
+    }
+  return HFMM_OK;
+}
+
+int hfmm_lists_export(hfmm_tree* tree, double k, int32_t P, int32_t* m2l, int32_t* p2p) {
+  API_GUARD_BEGIN
+  if (!tree) return set_error("tree is NULL"), HFMM_EINVAL;
+  int rc = check_kP(k, P);
+  if (rc) return rc;
+  Tree& t = *reinterpret_cast<Tree*>(tree);
+  Plan pl;
+  build_lists_host(t, k, P, pl);
+  for (size_t i = 0; m2l && i < pl.lists.m2l_a.size(); ++i) {
+    m2l[2 * i] = pl.lists.m2l_a[i];
+    m2l[2 * i + 1] = pl.lists.m2l_b[i];
+  }
+  for (size_t i = 0; p2p && i < pl.lists.p2p_a.size(); ++i) {
+    p2p[2 * i] = pl.lists.p2p_a[i];
+    p2p[2 * i + 1] = pl.lists.p2p_b[i];
+  }
+  return HFMM_OK;
+  API_GUARD_END
+}
+
+void hfmm_tree_free(hfmm_tree* tree) { delete reinterpret_cast<Tree*>(tree); }
+
+}  // extern "C"
+
+// Entry points completed in bie.cpp / batch.cpp.

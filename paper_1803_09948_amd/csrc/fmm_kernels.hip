@@ -1,0 +1,594 @@
+// HIP kernels of the Helmholtz FMM matvec for gfx950 (Sec. 2.3, Listing 1).
+//
+// Expansion conventions (eqs. (12)-(14)):
+//   Y_n^m = N_n^|m| P_n^|m|(cos t) e^{i m p} (no Condon-Shortley phase), so
+//   Y_n^{-m} = conj(Y_n^m);  R_n^m(v) = j_n(k|v|) Y_n^m,  S_n^m(v) = h_n(k|v|) Y_n^m;
+//   multipole  M_n^m = sum q R_n^{-m}(y - c),  field ik sum M S(x - c);
+//   local      L_n^m = sum q S_n^{-m}(y - c),  field ik sum L R(x - c).
+// Coefficients are stored scaled per level l to stay inside FP32 range:
+//   M = sigma_n Mt,  Lt = sigma_n L,  sigma_n = rho_l^n / (2n+1)!!,
+//   rho_l = min(1, k * side_l).
+// The translation tables fold these factors in, so the scaling cancels in y.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "fmm_kernels.h"
+
+namespace hfmm {
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline float2 cfma(float2 a, float2 b, float2 c) {  // a*b + c
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
+__device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by i^code
+__device__ inline float2 mul_ipow(float2 a, int code) {
+  switch (code & 3) {
+    case 0: return a;
+    case 1: return make_float2(-a.y, a.x);
+    case 2: return make_float2(-a.x, -a.y);
+    default: return make_float2(a.y, -a.x);
+  }
+}
+
+// Spherical Bessel j_n(x), n < nm <= 2*kMaxP, FP64.  x < 1: power series;
+// x > nm: upward recurrence (stable for n < x); otherwise Miller's downward
+// recurrence normalised by whichever of j_0, j_1 is larger in magnitude.
+__device__ void bessel_j_all(int nm, double x, double* j) {
+  if (x < 1.0) {
+    double h = -0.5 * x * x, xn = 1.0, df = 1.0;  // x^n, (2n+1)!!
+    for (int n = 0; n < nm; ++n) {
+      df *= (2.0 * n + 1.0);
+      double term = 1.0, sum = 1.0;
+      for (int k = 1; k < 30; ++k) {
+        term *= h / (k * (2.0 * n + 2.0 * k + 1.0));
+        sum += term;
+        if (fabs(term) < 1e-17 * fabs(sum)) break;
+      }
+      j[n] = xn / df * sum;
+      xn *= x;
+    }
+    return;
+  }
+  double s = sin(x), c = cos(x);
+  if (x > (double)nm) {
+    j[0] = s / x;
+    if (nm > 1) j[1] = s / (x * x) - c / x;
+    for (int n = 1; n + 1 < nm; ++n) j[n + 1] = (2.0 * n + 1.0) / x * j[n] - j[n - 1];
+    return;
+  }
+  int N = nm + 16 + (int)x;
+  double fp1 = 0.0, f = 1e-30;
+  for (int n = N; n >= 1; --n) {  // f = f_n, fp1 = f_{n+1}; step to f_{n-1}
+    double fm1 = (2.0 * n + 1.0) / x * f - fp1;
+    fp1 = f;
+    f = fm1;
+    if (n - 1 < nm) j[n - 1] = f;
+    if (fabs(f) > 1e250) {
+      fp1 *= 1e-250;
+      f *= 1e-250;
+      for (int m = n - 1; m < nm; ++m) j[m] *= 1e-250;
+    }
+  }
+  double j0 = s / x, j1 = s / (x * x) - c / x;
+  double scale = (fabs(j0) >= fabs(j1)) ? j0 / f : j1 / fp1;
+  for (int n = 0; n < nm; ++n) j[n] *= scale;
+}
+
+// b_n = j_n(x) (2n+1)!! / rho^n, n < nm.
+__device__ void bessel_j_scaled(int nm, double x, double rho, double* b) {
+  double j[kMaxP];
+  bessel_j_all(nm, x, j);
+  double df = 1.0, rp = 1.0;
+  for (int n = 0; n < nm; ++n) {
+    df *= (2.0 * n + 1.0);
+    b[n] = j[n] * df / rp;
+    rp *= rho;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Translation tables.  For operator o and entry (row r = (n',m'), col c=(n,m)):
+//   T[o][c][r] = sum_l coef * H_l^{m-m'}(t) * scale(n, n'),
+// with H = S (M2L) or R (M2M, L2L) and coef = 4 pi i^{n'+l-n} Gaunt.
+// One block per operator; the harmonics of t are built in LDS in FP64.
+// ---------------------------------------------------------------------------
+__global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P, double k,
+                             const int32_t* __restrict__ cp_off, const int32_t* __restrict__ cp_lm,
+                             const double2* __restrict__ cp_val, float2* __restrict__ tables) {
+  const int o = blockIdx.x;
+  if (o >= nops) return;
+  const int L = 2 * P - 1;
+  __shared__ double2 harm[(2 * kMaxP - 1) * (2 * kMaxP - 1)];
+  __shared__ double sig_in[kMaxP], sig_out[kMaxP];
+  const OpDescDev d = ops[o];
+  const double tx = d.t[0], ty = d.t[1], tz = d.t[2];
+  const double r = sqrt(tx * tx + ty * ty + tz * tz);
+  if (threadIdx.x == 0) {
+    // radial functions
+    double jr[2 * kMaxP], yr[2 * kMaxP];
+    double x = k * r;
+    if (d.kind == 2) {
+      // h_l = j_l + i y_l by upward recurrence: stable for y_l, and the error
+      // it leaves in j_l is relative to |h_l|
+      double s = sin(x), c = cos(x);
+      jr[0] = s / x;
+      yr[0] = -c / x;
+      if (L > 1) {
+        jr[1] = s / (x * x) - c / x;
+        yr[1] = -c / (x * x) - s / x;
+      }
+      for (int n = 1; n + 1 < L; ++n) {
+        jr[n + 1] = (2.0 * n + 1.0) / x * jr[n] - jr[n - 1];
+        yr[n + 1] = (2.0 * n + 1.0) / x * yr[n] - yr[n - 1];
+      }
+    } else {
+      bessel_j_all(L, x, jr);
+      for (int n = 0; n < L; ++n) yr[n] = 0.0;
+    }
+    // angular part: pbar_l^|mu|(cos theta) e^{i mu phi}
+    double ct = (r > 0) ? tz / r : 1.0;
+    double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    double ph = atan2(ty, tx);
+    double p[(2 * kMaxP - 1) * (2 * kMaxP - 1)];
+    for (int i = 0; i < L * L; ++i) p[i] = 0.0;
+    p[0] = 1.0 / sqrt(4.0 * M_PI);
+    for (int m = 1; m < L; ++m) p[m * m + 2 * m] = sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * p[(m - 1) * (m - 1) + 2 * (m - 1)];
+    for (int m = 0; m + 1 < L; ++m) p[(m + 1) * (m + 1) + (m + 1) + m] = sqrt(2.0 * m + 3.0) * ct * p[m * m + 2 * m];
+    for (int m = 0; m < L; ++m)
+      for (int n = m + 2; n < L; ++n) {
+        double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+        double bb = sqrt(((double)(n - 1) * (n - 1) - (double)m * m) / (4.0 * (n - 1) * (n - 1) - 1.0));
+        p[n * n + n + m] = a * (ct * p[(n - 1) * (n - 1) + (n - 1) + m] - bb * p[(n - 2) * (n - 2) + (n - 2) + m]);
+      }
+    for (int n = 0; n < L; ++n)
+      for (int m = -n; m <= n; ++m) {
+        double pv = p[n * n + n + (m < 0 ? -m : m)];
+        double cr = cos(m * ph), si = sin(m * ph);
+        double re = jr[n] * pv, im = yr[n] * pv;  // radial (j + i y) times real pbar
+        harm[n * n + n + m] = make_double2(re * cr - im * si, re * si + im * cr);
+      }
+    // scale factors sigma_n(rho) = rho^n / (2n+1)!!
+    double df = 1.0, ri = 1.0, ro = 1.0;
+    for (int n = 0; n < P; ++n) {
+      df *= (2.0 * n + 1.0);
+      sig_in[n] = ri / df;
+      sig_out[n] = ro / df;
+      ri *= d.rho_in;
+      ro *= d.rho_out;
+    }
+  }
+  __syncthreads();
+  const int P2 = P * P;
+  float2* T = tables + (size_t)o * P2 * P2;
+  for (int e = threadIdx.x; e < P2 * P2; e += blockDim.x) {
+    int row = e / P2, col = e % P2;  // row (n',m'), col (n,m)
+    int n2 = (int)sqrt((double)row), n = (int)sqrt((double)col);
+    double re = 0.0, im = 0.0;
+    for (int q = cp_off[e]; q < cp_off[e + 1]; ++q) {
+      double2 cv = cp_val[q];
+      double2 h = harm[cp_lm[q]];
+      re += cv.x * h.x - cv.y * h.y;
+      im += cv.x * h.y + cv.y * h.x;
+    }
+    double sc;
+    if (d.kind == 0) sc = sig_in[n] / sig_out[n2];        // M2M
+    else if (d.kind == 1) sc = sig_out[n2] / sig_in[n];   // L2L
+    else sc = sig_out[n2] * sig_in[n];                    // M2L
+    T[(size_t)col * P2 + row] = make_float2((float)(re * sc), (float)(im * sc));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gather source strengths into Morton order: q_s = w_s * x[unknown_s]
+// ---------------------------------------------------------------------------
+__global__ void k_gather(int64_t n, const int32_t* __restrict__ idx, const float* __restrict__ w,
+                         const float2* __restrict__ x, float2* __restrict__ q) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float2 v = x[idx[i]];
+  if (w) {
+    float s = w[i];
+    v = make_float2(v.x * s, v.y * s);
+  }
+  q[i] = v;
+}
+
+__global__ void k_scatter(int64_t n, const int32_t* __restrict__ perm, const float2* __restrict__ ys,
+                          float2* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[perm[i]] = ys[i];
+}
+
+// Y_n^m (m >= 0) of direction (dx,dy,dz)/r into a[n*(n+1)/2 + m], FP32, via
+// the normalised recurrences with the complex factor w = (x + i y)/r.
+__device__ inline void ylm_pos(int P, float dx, float dy, float dz, float r, float2* a) {
+  float c, wx, wy;
+  if (r > 0.f) {
+    float ir = 1.f / r;
+    c = dz * ir;
+    wx = dx * ir;
+    wy = dy * ir;
+  } else {
+    c = 1.f;
+    wx = 0.f;
+    wy = 0.f;
+  }
+  // a(m,m)
+  float2 pmm = make_float2(0.28209479177387814f, 0.f);  // 1/sqrt(4 pi)
+  for (int m = 0; m < P; ++m) {
+    if (m > 0) {
+      float f = sqrtf((2.f * m + 1.f) / (2.f * m));
+      pmm = make_float2(f * (pmm.x * wx - pmm.y * wy), f * (pmm.x * wy + pmm.y * wx));
+    }
+    a[m * (m + 1) / 2 + m] = pmm;
+    if (m + 1 < P) {
+      float f = sqrtf(2.f * m + 3.f) * c;
+      a[(m + 1) * (m + 2) / 2 + m] = make_float2(f * pmm.x, f * pmm.y);
+    }
+    for (int n = m + 2; n < P; ++n) {
+      float an = sqrtf((4.f * n * n - 1.f) / (float)(n * n - m * m));
+      float bn = sqrtf((float)((n - 1) * (n - 1) - m * m) / (4.f * (n - 1) * (n - 1) - 1.f));
+      float2 p1 = a[(n - 1) * n / 2 + m], p2 = a[(n - 2) * (n - 1) / 2 + m];
+      a[n * (n + 1) / 2 + m] = make_float2(an * (c * p1.x - bn * p2.x), an * (c * p1.y - bn * p2.y));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P2M: one wave per leaf.  Mt_n^m = sum_j q_j b_n(k r_j) conj(Y_n^m(dir_j)),
+// Mt_n^{-m} = sum_j q_j b_n Y_n^m, b_n = j_n (2n+1)!!/rho^n.
+// ---------------------------------------------------------------------------
+constexpr int kP2MChunk = 32;
+
+__global__ void __launch_bounds__(64) k_p2m(const int32_t* __restrict__ leaves, int nleaves,
+                                            const int4* __restrict__ cells,
+                                            const float4* __restrict__ geo,
+                                            const int32_t* __restrict__ clev,
+                                            const double* __restrict__ rho,
+                                            const float4* __restrict__ spos,
+                                            const float2* __restrict__ q, float k, int P,
+                                            float2* __restrict__ M) {
+  const int li = blockIdx.x;
+  if (li >= nleaves) return;
+  const int cell = leaves[li];
+  const int4 rg = cells[cell];
+  const float4 g = geo[cell];
+  const double rh = rho[clev[cell]];
+  const int P2 = P * P, PH = P * (P + 1) / 2;
+  __shared__ float2 sa[kP2MChunk][kMaxP * (kMaxP + 1) / 2];
+  __shared__ float2 sq[kP2MChunk];
+  const int lane = threadIdx.x;
+  float2 acc[4];  // up to 4 coefficients per lane (P2 <= 256)
+  for (int t = 0; t < 4; ++t) acc[t] = make_float2(0.f, 0.f);
+  for (int j0 = rg.x; j0 < rg.y; j0 += kP2MChunk) {
+    int nj = min(kP2MChunk, rg.y - j0);
+    if (lane < nj) {
+      float4 p = spos[j0 + lane];
+      float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
+      float r = sqrtf(dx * dx + dy * dy + dz * dz);
+      double b[kMaxP];
+      bessel_j_scaled(P, (double)k * (double)r, rh, b);
+      float2* a = sa[lane];
+      ylm_pos(P, dx, dy, dz, r, a);
+      for (int n = 0; n < P; ++n) {
+        float bn = (float)b[n];
+        for (int m = 0; m <= n; ++m) {
+          float2 v = a[n * (n + 1) / 2 + m];
+          a[n * (n + 1) / 2 + m] = make_float2(v.x * bn, v.y * bn);
+        }
+      }
+      sq[lane] = q[j0 + lane];
+    }
+    __syncthreads();
+    for (int t = 0; t < 4; ++t) {
+      int e = lane + 64 * t;
+      if (e >= P2) break;
+      int n = (int)sqrtf((float)e + 0.5f);
+      int m = e - n * n - n;
+      int am = m < 0 ? -m : m;
+      int ai = n * (n + 1) / 2 + am;
+      float2 s = acc[t];
+      for (int j = 0; j < nj; ++j) {
+        float2 y = sa[j][ai];
+        if (m >= 0) y.y = -y.y;  // conj for m >= 0
+        s = cfma(sq[j], y, s);
+      }
+      acc[t] = s;
+    }
+    __syncthreads();
+  }
+  for (int t = 0; t < 4; ++t) {
+    int e = lane + 64 * t;
+    if (e < P2) M[(size_t)cell * P2 + e] = acc[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense translation y_out = T y_in for M2M (children -> parent) and L2L
+// (parent -> child).  One block per destination cell.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_m2m(int c0, int c1, const int4* __restrict__ topo,
+                                             const int32_t* __restrict__ m2m_base,
+                                             const float2* __restrict__ tables, int P,
+                                             float2* __restrict__ M) {
+  const int cell = c0 + blockIdx.x;
+  if (cell >= c1) return;
+  const int4 tp = topo[cell];  // (child begin, child end, parent, octant | level << 3)
+  if (tp.x == tp.y) return;
+  const int P2 = P * P;
+  __shared__ float2 sm[kMaxP * kMaxP];
+  float2 acc[1] = {make_float2(0.f, 0.f)};
+  const int r = threadIdx.x;
+  for (int ch = tp.x; ch < tp.y; ++ch) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < P2; e += blockDim.x) sm[e] = M[(size_t)ch * P2 + e];
+    __syncthreads();
+    const int4 tc = topo[ch];
+    const int op = m2m_base[tc.w >> 3] + (tc.w & 7);
+    const float2* T = tables + (size_t)op * P2 * P2;
+    if (r < P2) {
+      float2 s = acc[0];
+      for (int c = 0; c < P2; ++c) s = cfma(T[(size_t)c * P2 + r], sm[c], s);
+      acc[0] = s;
+    }
+  }
+  if (r < P2) M[(size_t)cell * P2 + r] = acc[0];
+}
+
+__global__ void __launch_bounds__(256) k_l2l(int c0, int c1, const int4* __restrict__ topo,
+                                             const int32_t* __restrict__ l2l_base,
+                                             const float2* __restrict__ tables, int P,
+                                             float2* __restrict__ L) {
+  const int cell = c0 + blockIdx.x;
+  if (cell >= c1) return;
+  const int4 tp = topo[cell];
+  const int parent = tp.z;
+  const int P2 = P * P;
+  __shared__ float2 sl[kMaxP * kMaxP];
+  for (int e = threadIdx.x; e < P2; e += blockDim.x) sl[e] = L[(size_t)parent * P2 + e];
+  __syncthreads();
+  const int op = l2l_base[tp.w >> 3] + (tp.w & 7);
+  const float2* T = tables + (size_t)op * P2 * P2;
+  const int r = threadIdx.x;
+  if (r < P2) {
+    float2 s = L[(size_t)cell * P2 + r];
+    for (int c = 0; c < P2; ++c) s = cfma(T[(size_t)c * P2 + r], sl[c], s);
+    L[(size_t)cell * P2 + r] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// M2L (first version, VALU): each block takes a chunk of pairs sharing one
+// operator.  Inputs are mapped by the pair's symmetry (M' = D^T M), the
+// canonical operator applied, and outputs mapped back (L += conj(D) L').
+// ---------------------------------------------------------------------------
+constexpr int kM2LChunk = 16;
+
+__global__ void __launch_bounds__(256) k_m2l_valu(const int4* __restrict__ chunks,
+                                                  const int4* __restrict__ pairs,
+                                                  const float2* __restrict__ tables,
+                                                  const int32_t* __restrict__ symdst,
+                                                  const int32_t* __restrict__ symph,
+                                                  const int32_t* __restrict__ outidx,
+                                                  const int32_t* __restrict__ outph, int P,
+                                                  const float2* __restrict__ M,
+                                                  float2* __restrict__ L) {
+  const int4 ch = chunks[blockIdx.x];
+  const int op = ch.x, pb = ch.y, np = ch.z - ch.y;
+  const int P2 = P * P;
+  __shared__ float2 B[kM2LChunk][kMaxP * kMaxP];
+  for (int e = threadIdx.x; e < np * P2; e += blockDim.x) {
+    int p = e / P2, c = e % P2;
+    int4 pr = pairs[pb + p];
+    int g = pr.z;
+    float2 v = M[(size_t)pr.y * P2 + c];
+    B[p][symdst[g * P2 + c]] = mul_ipow(v, symph[g * P2 + c]);
+  }
+  __syncthreads();
+  const float2* T = tables + (size_t)op * P2 * P2;
+  for (int r = threadIdx.x; r < P2; r += blockDim.x) {
+    float2 acc[kM2LChunk];
+    for (int p = 0; p < kM2LChunk; ++p) acc[p] = make_float2(0.f, 0.f);
+    for (int c = 0; c < P2; ++c) {
+      float2 t = T[(size_t)c * P2 + r];
+#pragma unroll
+      for (int p = 0; p < kM2LChunk; ++p) acc[p] = cfma(t, B[p][c], acc[p]);
+    }
+    for (int p = 0; p < np; ++p) {
+      int4 pr = pairs[pb + p];
+      int g = pr.z;
+      int o = outidx[g * P2 + r];
+      float2 v = mul_ipow(acc[p], outph[g * P2 + r]);
+      atomicAdd(&L[(size_t)pr.x * P2 + o].x, v.x);
+      atomicAdd(&L[(size_t)pr.x * P2 + o].y, v.y);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L2P: one wave per leaf; phi(x) = ik sum Lt_n^m (b_n(k r)) Y_n^m(dir) with
+// b_n = j_n / sigma_n.  Writes (not accumulates) the sorted output.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_l2p(const int32_t* __restrict__ leaves, int nleaves,
+                                            const int4* __restrict__ cells,
+                                            const float4* __restrict__ geo,
+                                            const int32_t* __restrict__ clev,
+                                            const double* __restrict__ rho,
+                                            const float4* __restrict__ tpos, float k, int P,
+                                            const float2* __restrict__ L, float2* __restrict__ ys) {
+  const int li = blockIdx.x;
+  if (li >= nleaves) return;
+  const int cell = leaves[li];
+  const int4 rg = cells[cell];
+  const float4 g = geo[cell];
+  const double rh = rho[clev[cell]];
+  const int P2 = P * P;
+  __shared__ float2 sl[kMaxP * kMaxP];
+  for (int e = threadIdx.x; e < P2; e += blockDim.x) sl[e] = L[(size_t)cell * P2 + e];
+  __syncthreads();
+  float2 a[kMaxP * (kMaxP + 1) / 2];
+  for (int i = rg.z + threadIdx.x; i < rg.w; i += 64) {
+    float4 p = tpos[i];
+    float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
+    float r = sqrtf(dx * dx + dy * dy + dz * dz);
+    double b[kMaxP];
+    bessel_j_scaled(P, (double)k * (double)r, rh, b);
+    ylm_pos(P, dx, dy, dz, r, a);
+    float2 s = make_float2(0.f, 0.f);
+    for (int n = 0; n < P; ++n) {
+      float2 t = cmul(sl[n * n + n], a[n * (n + 1) / 2]);
+      for (int m = 1; m <= n; ++m) {
+        float2 y = a[n * (n + 1) / 2 + m];
+        t = cfma(sl[n * n + n + m], y, t);
+        t = cfma(sl[n * n + n - m], cconj(y), t);
+      }
+      float bn = (float)b[n];
+      s.x = fmaf(bn, t.x, s.x);
+      s.y = fmaf(bn, t.y, s.y);
+    }
+    // times i k
+    ys[i] = make_float2(-k * s.y, k * s.x);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P2P (Listing 1 without the near branch): y_i += sum_j q_j e^{ikR}/(4 pi R),
+// R > 0.  One wave per target leaf; lanes = (target, split), sources staged
+// through LDS 64 at a time; the 1/(4 pi) is folded into k-independent
+// constants.  Deterministic: each target is owned by one wave and the split
+// partial sums are added in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_p2p(const int4* __restrict__ work, int nwork,
+                                             const int2* __restrict__ ivals,
+                                             const float4* __restrict__ tpos,
+                                             const float4* __restrict__ spos,
+                                             const float2* __restrict__ q, float k,
+                                             float2* __restrict__ ys) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = blockIdx.x * 4 + wave;
+  __shared__ float4 sp[4][64];
+  __shared__ float2 sq[4][64];
+  __shared__ float2 red[4][64];
+  if (w >= nwork) return;
+  const int4 wk = work[w];
+  const float krev = k * 0.15915494309189535f;  // k / (2 pi): revolutions per unit length
+  const float inv4pi = 0.07957747154594767f;
+  for (int t0 = wk.x; t0 < wk.y; t0 += 64) {
+    const int tc = min(64, wk.y - t0);
+    const int nsplit = 64 / tc;
+    const int ti = lane % tc, s = lane / tc;
+    const bool active = s < nsplit;
+    float4 xi = tpos[t0 + ti];
+    float ar = 0.f, ai = 0.f;
+    for (int iv = wk.z; iv < wk.w; ++iv) {
+      const int2 rg = ivals[iv];
+      for (int j0 = rg.x; j0 < rg.y; j0 += 64) {
+        const int nj = min(64, rg.y - j0);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nj) {
+          sp[wave][lane] = spos[j0 + lane];
+          sq[wave][lane] = q[j0 + lane];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (active) {
+          for (int j = s; j < nj; j += nsplit) {
+            float4 yj = sp[wave][j];
+            float2 qj = sq[wave][j];
+            float dx = xi.x - yj.x, dy = xi.y - yj.y, dz = xi.z - yj.z;
+            float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            float rinv = (r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
+            float rev = r2 * rinv * krev;
+            float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
+            float gr = cs * rinv, gi = sn * rinv;
+            ar = fmaf(qj.x, gr, fmaf(-qj.y, gi, ar));
+            ai = fmaf(qj.x, gi, fmaf(qj.y, gr, ai));
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    red[wave][lane] = make_float2(ar, ai);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < tc) {
+      float2 sum = make_float2(0.f, 0.f);
+      for (int ss = 0; ss < nsplit; ++ss) {
+        float2 v = red[wave][lane + ss * tc];
+        sum.x += v.x;
+        sum.y += v.y;
+      }
+      float2 o = ys[t0 + lane];
+      o.x = fmaf(sum.x, inv4pi, o.x);
+      o.y = fmaf(sum.y, inv4pi, o.y);
+      ys[t0 + lane] = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
+                       const int32_t* cp_lm, const double2* cp_val, float2* tables,
+                       hipStream_t s) {
+  if (nops <= 0) return;
+  k_gen_tables<<<nops, 256, 0, s>>>(ops, nops, P, k, cp_off, cp_lm, cp_val, tables);
+}
+void launch_gather(int64_t n, const int32_t* idx, const float* w, const float2* x, float2* q,
+                   hipStream_t s) {
+  if (n <= 0) return;
+  k_gather<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, idx, w, x, q);
+}
+void launch_scatter(int64_t n, const int32_t* perm, const float2* ys, float2* y, hipStream_t s) {
+  if (n <= 0) return;
+  k_scatter<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, perm, ys, y);
+}
+void launch_p2m(const int32_t* leaves, int nleaves, const int4* cells, const float4* geo,
+                const int32_t* clev, const double* rho, const float4* spos, const float2* q,
+                float k, int P, float2* M, hipStream_t s) {
+  if (nleaves <= 0) return;
+  k_p2m<<<nleaves, 64, 0, s>>>(leaves, nleaves, cells, geo, clev, rho, spos, q, k, P, M);
+}
+void launch_m2m(int c0, int c1, const int4* topo, const int32_t* base, const float2* tables,
+                int P, float2* M, hipStream_t s) {
+  if (c1 <= c0) return;
+  k_m2m<<<c1 - c0, 256, 0, s>>>(c0, c1, topo, base, tables, P, M);
+}
+void launch_l2l(int c0, int c1, const int4* topo, const int32_t* base, const float2* tables,
+                int P, float2* L, hipStream_t s) {
+  if (c1 <= c0) return;
+  k_l2l<<<c1 - c0, 256, 0, s>>>(c0, c1, topo, base, tables, P, L);
+}
+void launch_m2l(const int4* chunks, int nchunks, const int4* pairs, const float2* tables,
+                const int32_t* symdst, const int32_t* symph, const int32_t* outidx,
+                const int32_t* outph, int P, const float2* M, float2* L, hipStream_t s) {
+  if (nchunks <= 0) return;
+  k_m2l_valu<<<nchunks, 256, 0, s>>>(chunks, pairs, tables, symdst, symph, outidx, outph, P, M, L);
+}
+void launch_l2p(const int32_t* leaves, int nleaves, const int4* cells, const float4* geo,
+                const int32_t* clev, const double* rho, const float4* tpos, float k, int P,
+                const float2* L, float2* ys, hipStream_t s) {
+  if (nleaves <= 0) return;
+  k_l2p<<<nleaves, 64, 0, s>>>(leaves, nleaves, cells, geo, clev, rho, tpos, k, P, L, ys);
+}
+void launch_p2p(const int4* work, int nwork, const int2* ivals, const float4* tpos,
+                const float4* spos, const float2* q, float k, float2* ys, hipStream_t s) {
+  if (nwork <= 0) return;
+  k_p2p<<<(nwork + 3) / 4, 256, 0, s>>>(work, nwork, ivals, tpos, spos, q, k, ys);
+}
+
+int m2l_chunk_size() { return kM2LChunk; }
+
+}  // namespace hfmm

@@ -1,0 +1,157 @@
+// Internal structures of the hfmm library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hfmm.h"
+#include "fmm_kernels.h"
+
+namespace hfmm {
+
+constexpr int kKeyBits = 21;
+constexpr int kMaxLevel = 20;
+
+void set_error(const std::string& msg);
+
+// ---------------------------------------------------------------------------
+// Octree over sources and targets (point mode: the same set).
+// ---------------------------------------------------------------------------
+struct HostTree {
+  bool point_mode = true;
+  int64_t nsrc = 0, ntgt = 0;
+  int ncrit = 64;
+  double c[3] = {0, 0, 0};
+  double H = 1.0;
+  std::vector<int32_t> src_perm, tgt_perm;     // sorted position -> input index
+  std::vector<float> src_xyz, tgt_xyz;         // sorted, 3 floats per body
+  // cells, level by level, Morton order within a level
+  std::vector<int32_t> level, ijk, sb, se, tb, te, cb, ce, parent;
+  std::vector<int32_t> level_off;              // cells of level l: [off[l], off[l+1])
+  int ncell() const { return (int)level.size(); }
+  int nlevels() const { return (int)level_off.size() - 1; }
+  bool leaf(int i) const { return cb[i] == ce[i]; }
+  double half(int i) const { return H / double(1 << level[i]); }
+  void centre(int i, double out[3]) const {
+    double h = half(i);
+    for (int d = 0; d < 3; ++d) out[d] = c[d] - H + (2.0 * ijk[3 * i + d] + 1.0) * h;
+  }
+};
+
+// Builds the tree.  tgt == nullptr: point mode.
+void build_tree(const float* src, int64_t nsrc, const float* tgt, int64_t ntgt,
+                int ncrit, int max_level, HostTree& t);
+
+struct Lists {
+  std::vector<int32_t> m2l_a, m2l_b;  // (target cell, source cell)
+  std::vector<int32_t> p2p_a, p2p_b;  // (target leaf, source leaf)
+};
+
+void dual_tree_traversal(const HostTree& t, double k, double theta, double kappa,
+                         Lists& out);
+
+// ---------------------------------------------------------------------------
+// Translation-operator descriptors (computed on the device in FP64).
+// ---------------------------------------------------------------------------
+enum OpKind : int32_t { OP_M2M = 0, OP_L2L = 1, OP_M2L = 2 };
+
+using OpDesc = OpDescDev;
+
+// Gaunt coupling in CSR over (row = (n',m'), col = (n,m)) entries:
+// coefficient 4 pi i^{n'+l-n} G(n,m;n',m';l) of harmonic index (l, m-m').
+struct Coupling {
+  int P = 0;
+  std::vector<int32_t> off;     // P^4 + 1
+  std::vector<int32_t> lm;      // harmonic index l*l + l + mu
+  std::vector<double> re, im;   // coefficient
+};
+const Coupling& coupling(int P);
+
+// Symmetry maps of the 16 canonicalising reflections: for symmetry g and
+// coefficient index (n,m): Y_n^m(sigma r) = phase * Y_n^{m'}(r); stored as
+// dst index and phase code (0:1, 1:i, 2:-1, 3:-i).
+void symmetry_map(int P, std::vector<int32_t>& dst, std::vector<int32_t>& phase);
+
+// ---------------------------------------------------------------------------
+// Device-side plan for one (k, P)
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf();
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  int alloc(size_t n);
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+struct Plan {
+  double k = 0;
+  int P = 0;
+  Lists lists;
+  int64_t n_tables = 0;          // M2L operators
+  int64_t n_ops = 0;             // all operators
+  int64_t p2p_body_pairs = 0;
+  std::vector<double> rho;       // per level
+  std::vector<int32_t> m2m_base, l2l_base;  // per child level: op index of octant 0
+  DevBuf d_ops, d_tables;        // OpDesc[n_ops]; float2 [n_ops][P^2 in][P^2 out]
+  DevBuf d_rho;                  // double per level
+  DevBuf d_m2m_base, d_l2l_base; // int32 per level
+  DevBuf d_m2l_chunks;           // int4 (op, pair begin, pair end, 0)
+  DevBuf d_m2l_pairs;            // int4 (target cell, source cell, symmetry, 0)
+  int32_t n_m2l_chunks = 0;
+  DevBuf d_p2p_work;             // int4 (tgt begin, tgt end, interval begin, interval end)
+  DevBuf d_p2p_ivals;            // int2 (src begin, src end)
+  int32_t n_p2p_work = 0;
+  DevBuf d_symdst, d_symph, d_outidx, d_outph;  // int32 [16][P^2]
+  // BIE corrections (caller panel order)
+  DevBuf d_near_off, d_near_col, d_near_val;    // CSR, float2 values
+  DevBuf d_self;                                // double2: self integral - 3-point self sum
+  int64_t n_near = 0;
+  int64_t device_bytes = 0;
+};
+
+struct Tree {
+  HostTree h;
+  int ncrit = 64, max_level = 20;
+  double theta = 0.5, kappa = -1.0, eta = 2.0;
+  int near_levels = 3, near_order = 6;
+  // BIE data
+  bool bie = false;
+  int64_t npanel = 0;
+  std::vector<double> verts;    // nv x 3
+  std::vector<int32_t> tris;    // nt x 3
+  // device geometry
+  DevBuf d_src_pos, d_tgt_pos;  // float4, sorted
+  DevBuf d_src_idx;             // int32 per sorted source: caller unknown index
+  DevBuf d_src_w;               // float per sorted source (BIE: area/3)
+  DevBuf d_tgt_perm;            // int32 per sorted target: caller index
+  DevBuf d_cells;               // int4 (sb, se, tb, te)
+  DevBuf d_geo;                 // float4 (cx, cy, cz, half)
+  DevBuf d_clev;                // int32 level
+  DevBuf d_topo;                // int4 (child begin, child end, parent, octant | level << 3)
+  DevBuf d_src_leaves, d_tgt_leaves;  // int32 leaf lists
+  int32_t n_src_leaves = 0, n_tgt_leaves = 0;
+  DevBuf d_panels;              // double [npanel][9] vertex coordinates (BIE)
+  // per-matvec scratch (sized for the largest P used)
+  DevBuf d_q, d_M, d_L, d_ys;
+  int scratchP = 0;
+  int64_t geo_bytes = 0;
+  std::map<std::pair<uint64_t, int>, std::unique_ptr<Plan>> plans;
+  bool timing = false;
+  float phase_ms[8] = {0};
+  hipEvent_t ev[9] = {};
+  bool ev_made = false;
+  ~Tree();
+};
+
+int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out);
+int upload_geometry(Tree& t);
+
+}  // namespace hfmm

@@ -1,0 +1,346 @@
+// Host-side octree, Morton keys and dual tree traversal (Sec. 2.3, 3.1, 3.2).
+//
+// The tree is built once per geometry in deterministic FP64 from the FP32
+// coordinates; every decision uses exact dyadic or integer arithmetic, so the
+// lists are reproducible bit for bit.  Readings of the unspecified details:
+//  - root cube: he = max half-extent of all points (1 if 0); q = largest power
+//    of two <= he/64; centre = nearest multiple of q to the bbox midpoint
+//    (floor(mid/q + 0.5) q); half-width H = smallest power of two >= q with
+//    |x - c| < H on every axis;
+//  - keys: floor(((x - c) + H) / (2H) * 2^21) per axis, clamped, interleaved
+//    with x in the lowest bit; stable sort (ties keep input order);
+//  - a cell splits into its non-empty octants when it holds more than ncrit
+//    sources; cells are stored level by level in Morton order;
+//  - acceptance for M2L: 3 (sA + sB)^2 < theta^2 D2 (half-sides and squared
+//    centre distance in units of the finer half-side) and k * side <= kappa
+//    for the larger cell; traversal from (root, root) splits the cell with
+//    the larger radius (ties: the target), or the other one if it is a leaf.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "hfmm_internal.h"
+
+namespace hfmm {
+
+static void root_cube(const float* a, int64_t na, const float* b, int64_t nb, double c[3],
+                      double& H) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  auto scan = [&](const float* p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+      for (int d = 0; d < 3; ++d) {
+        double v = (double)p[3 * i + d];
+        lo[d] = std::min(lo[d], v);
+        hi[d] = std::max(hi[d], v);
+      }
+  };
+  scan(a, na);
+  if (b) scan(b, nb);
+  double he = 0.0;
+  for (int d = 0; d < 3; ++d) he = std::max(he, (hi[d] - lo[d]) / 2.0);
+  if (he == 0.0) he = 1.0;
+  double q = std::ldexp(1.0, (int)std::floor(std::log2(he / 64.0)));
+  while (q * 2.0 <= he / 64.0) q *= 2.0;
+  while (q > he / 64.0) q /= 2.0;
+  for (int d = 0; d < 3; ++d) c[d] = std::floor(((lo[d] + hi[d]) / 2.0) / q + 0.5) * q;
+  H = q;
+  auto inside = [&](const float* p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+      for (int d = 0; d < 3; ++d)
+        if (!(std::fabs((double)p[3 * i + d] - c[d]) < H)) return false;
+    return true;
+  };
+  while (!(inside(a, na) && (!b || inside(b, nb)))) H *= 2.0;
+}
+
+static uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
+  uint64_t r = 0;
+  for (int b = 0; b < kKeyBits; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+  return r;
+}
+
+static void keys_of(const float* p, int64_t n, const double c[3], double H,
+                    std::vector<uint64_t>& key) {
+  key.resize(n);
+  const double scale = double(1u << kKeyBits);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t k = 0;
+    for (int d = 0; d < 3; ++d) {
+      double f = std::floor((((double)p[3 * i + d] - c[d]) + H) / (2.0 * H) * scale);
+      int64_t kd = (int64_t)f;
+      kd = std::min<int64_t>(std::max<int64_t>(kd, 0), (1 << kKeyBits) - 1);
+      k |= spread3((uint64_t)kd) << d;
+    }
+    key[i] = k;
+  }
+}
+
+static void sort_by_key(const std::vector<uint64_t>& key, std::vector<int32_t>& perm) {
+  perm.resize(key.size());
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(),
+                   [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+}
+
+void build_tree(const float* src, int64_t nsrc, const float* tgt, int64_t ntgt, int ncrit,
+                int max_level, HostTree& t) {
+  t = HostTree();
+  t.point_mode = (tgt == nullptr);
+  t.nsrc = nsrc;
+  t.ntgt = t.point_mode ? nsrc : ntgt;
+  t.ncrit = ncrit;
+  root_cube(src, nsrc, tgt, t.point_mode ? 0 : ntgt, t.c, t.H);
+  std::vector<uint64_t> skey, tkey;
+  keys_of(src, nsrc, t.c, t.H, skey);
+  sort_by_key(skey, t.src_perm);
+  std::vector<uint64_t> sk(nsrc);
+  for (int64_t i = 0; i < nsrc; ++i) sk[i] = skey[t.src_perm[i]];
+  std::vector<uint64_t> tk;
+  if (t.point_mode) {
+    t.tgt_perm = t.src_perm;
+    tk = sk;
+  } else {
+    keys_of(tgt, ntgt, t.c, t.H, tkey);
+    sort_by_key(tkey, t.tgt_perm);
+    tk.resize(ntgt);
+    for (int64_t i = 0; i < ntgt; ++i) tk[i] = tkey[t.tgt_perm[i]];
+  }
+  t.src_xyz.resize(3 * nsrc);
+  for (int64_t i = 0; i < nsrc; ++i)
+    for (int d = 0; d < 3; ++d) t.src_xyz[3 * i + d] = src[3 * (int64_t)t.src_perm[i] + d];
+  if (t.point_mode) {
+    t.tgt_xyz = t.src_xyz;
+  } else {
+    t.tgt_xyz.resize(3 * ntgt);
+    for (int64_t i = 0; i < ntgt; ++i)
+      for (int d = 0; d < 3; ++d) t.tgt_xyz[3 * i + d] = tgt[3 * (int64_t)t.tgt_perm[i] + d];
+  }
+  auto push = [&](int lev, int i, int j, int k, int32_t a, int32_t b, int32_t c0, int32_t d,
+                  int32_t par) {
+    t.level.push_back(lev);
+    t.ijk.push_back(i);
+    t.ijk.push_back(j);
+    t.ijk.push_back(k);
+    t.sb.push_back(a);
+    t.se.push_back(b);
+    t.tb.push_back(c0);
+    t.te.push_back(d);
+    t.cb.push_back(0);
+    t.ce.push_back(0);
+    t.parent.push_back(par);
+  };
+  push(0, 0, 0, 0, 0, (int32_t)nsrc, 0, (int32_t)t.ntgt, -1);
+  t.level_off.push_back(0);
+  std::vector<int32_t> cur = {0}, nxt;
+  int lev = 0;
+  while (!cur.empty()) {
+    t.level_off.push_back((int32_t)t.level.size());  // end of level `lev` is set below
+    t.level_off.back() = cur.back() + 1;
+    nxt.clear();
+    for (int32_t ci : cur) {
+      int32_t ns = t.se[ci] - t.sb[ci];
+      if (ns <= ncrit || lev >= max_level) {
+        t.cb[ci] = t.ce[ci] = (int32_t)t.level.size();
+        continue;
+      }
+      int shift = 3 * (kKeyBits - lev - 1);
+      int32_t first = (int32_t)t.level.size();
+      int32_t s0 = t.sb[ci], t0 = t.tb[ci];
+      for (int o = 0; o < 8; ++o) {
+        auto oct = [&](uint64_t key) { return (int)((key >> shift) & 7ull); };
+        int32_t s1 = s0, t1 = t0;
+        while (s1 < t.se[ci] && oct(sk[s1]) == o) ++s1;
+        while (t1 < t.te[ci] && oct(tk[t1]) == o) ++t1;
+        if (s1 > s0 || t1 > t0) {
+          int i = t.ijk[3 * ci], j = t.ijk[3 * ci + 1], k = t.ijk[3 * ci + 2];
+          push(lev + 1, 2 * i + (o & 1), 2 * j + ((o >> 1) & 1), 2 * k + ((o >> 2) & 1), s0, s1,
+               t0, t1, ci);
+          nxt.push_back((int32_t)t.level.size() - 1);
+        }
+        s0 = s1;
+        t0 = t1;
+      }
+      t.cb[ci] = first;
+      t.ce[ci] = (int32_t)t.level.size();
+    }
+    cur.swap(nxt);
+    ++lev;
+  }
+  // level_off: fix to [start of each level] + end
+  std::vector<int32_t> off;
+  off.push_back(0);
+  for (int i = 1; i < t.ncell(); ++i)
+    if (t.level[i] != t.level[i - 1]) off.push_back(i);
+  off.push_back(t.ncell());
+  t.level_off = off;
+}
+
+static inline bool mac(const HostTree& t, int a, int b, double k, double theta,
+                       double kappa) {
+  int la = t.level[a], lb = t.level[b];
+  int L = std::max(la, lb);
+  int64_t D2 = 0;
+  for (int d = 0; d < 3; ++d) {
+    int64_t ca = -(int64_t(1) << L) + (2 * (int64_t)t.ijk[3 * a + d] + 1) * (int64_t(1) << (L - la));
+    int64_t cb = -(int64_t(1) << L) + (2 * (int64_t)t.ijk[3 * b + d] + 1) * (int64_t(1) << (L - lb));
+    D2 += (ca - cb) * (ca - cb);
+  }
+  int64_t sA = int64_t(1) << (L - la), sB = int64_t(1) << (L - lb);
+  bool geo = 3.0 * double((sA + sB) * (sA + sB)) < (theta * theta) * double(D2);
+  double hmax = t.H / double(1 << std::min(la, lb));
+  return geo && (k * (2.0 * hmax) <= kappa);
+}
+
+void dual_tree_traversal(const HostTree& t, double k, double theta, double kappa, Lists& out) {
+  out = Lists();
+  std::vector<std::pair<int32_t, int32_t>> stack;
+  stack.reserve(4096);
+  stack.push_back({0, 0});
+  while (!stack.empty()) {
+    auto [a, b] = stack.back();
+    stack.pop_back();
+    if (t.te[a] == t.tb[a] || t.se[b] == t.sb[b]) continue;
+    if (mac(t, a, b, k, theta, kappa)) {
+      out.m2l_a.push_back(a);
+      out.m2l_b.push_back(b);
+      continue;
+    }
+    bool la = t.leaf(a), lb = t.leaf(b);
+    if (la && lb) {
+      out.p2p_a.push_back(a);
+      out.p2p_b.push_back(b);
+      continue;
+    }
+    bool split_a = !la && (t.level[a] <= t.level[b] || lb);
+    if (split_a) {
+      for (int ch = t.ce[a] - 1; ch >= t.cb[a]; --ch) stack.push_back({ch, b});
+    } else {
+      for (int ch = t.ce[b] - 1; ch >= t.cb[b]; --ch) stack.push_back({a, ch});
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gaunt coupling: integral of Y_n^m conj(Y_n'^m') conj(Y_l^{m-m'}) over the
+// sphere, with the phi integral done exactly (2 pi) and the cos(theta)
+// integral by Gauss-Legendre quadrature, exact for the polynomial integrand of
+// degree n + n' + l <= 4P - 4.
+// ---------------------------------------------------------------------------
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int j = 2; j <= n; ++j) {
+      double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Normalised associated Legendre values pbar_n^m(x) (no Condon-Shortley
+// phase, orthonormal with the 1/(4 pi) of Y) for n < L, m <= n.
+static void legendre_norm(int L, double x, std::vector<double>& p) {
+  p.assign(L * L, 0.0);
+  double s = std::sqrt(std::max(0.0, 1.0 - x * x));
+  auto at = [&](int n, int m) -> double& { return p[n * n + n + m]; };
+  at(0, 0) = 1.0 / std::sqrt(4.0 * M_PI);
+  for (int m = 1; m < L; ++m) at(m, m) = std::sqrt((2.0 * m + 1.0) / (2.0 * m)) * s * at(m - 1, m - 1);
+  for (int m = 0; m + 1 < L; ++m) at(m + 1, m) = std::sqrt(2.0 * m + 3.0) * x * at(m, m);
+  for (int m = 0; m < L; ++m)
+    for (int n = m + 2; n < L; ++n) {
+      double a = std::sqrt((4.0 * n * n - 1.0) / (double(n) * n - double(m) * m));
+      double b = std::sqrt((double(n - 1) * (n - 1) - double(m) * m) / (4.0 * (n - 1) * (n - 1) - 1.0));
+      at(n, m) = a * (x * at(n - 1, m) - b * at(n - 2, m));
+    }
+}
+
+const Coupling& coupling(int P) {
+  static std::map<int, Coupling> cache;
+  auto it = cache.find(P);
+  if (it != cache.end()) return it->second;
+  Coupling cp;
+  cp.P = P;
+  int L = 2 * P - 1;  // harmonic degrees 0..2P-2
+  int ng = 2 * P + 2;
+  std::vector<double> gx, gw;
+  gauss_legendre(ng, gx, gw);
+  std::vector<std::vector<double>> pl(ng);
+  for (int i = 0; i < ng; ++i) legendre_norm(L, gx[i], pl[i]);
+  auto pbar = [&](int g, int n, int m) { return pl[g][n * n + n + std::abs(m)]; };
+  int P2 = P * P;
+  cp.off.assign(P2 * P2 + 1, 0);
+  for (int n2 = 0; n2 < P; ++n2)
+    for (int m2 = -n2; m2 <= n2; ++m2) {
+      int row = n2 * n2 + n2 + m2;
+      for (int n = 0; n < P; ++n)
+        for (int m = -n; m <= n; ++m) {
+          int col = n * n + n + m;
+          int mu = m - m2;
+          for (int l = std::abs(n - n2); l <= n + n2; ++l) {
+            if (std::abs(mu) > l || ((n + n2 + l) & 1)) continue;
+            double g = 0.0;
+            for (int q = 0; q < ng; ++q) g += gw[q] * pbar(q, n, m) * pbar(q, n2, m2) * pbar(q, l, mu);
+            g *= 2.0 * M_PI;
+            if (std::fabs(g) < 1e-15) continue;
+            int e = ((n2 + l - n) % 4 + 4) % 4;  // i^e
+            double re = (e == 0 ? 1.0 : e == 2 ? -1.0 : 0.0) * 4.0 * M_PI * g;
+            double im = (e == 1 ? 1.0 : e == 3 ? -1.0 : 0.0) * 4.0 * M_PI * g;
+            cp.lm.push_back(l * l + l + mu);
+            cp.re.push_back(re);
+            cp.im.push_back(im);
+          }
+          cp.off[row * P2 + col + 1] = (int32_t)cp.lm.size();
+        }
+    }
+  auto res = cache.emplace(P, std::move(cp));
+  return res.first->second;
+}
+
+// Elementary reflections act on Y_n^m as Y_n^m(sigma r) = phase Y_n^{m'}(r):
+//  x -> -x : m' = -m, phase (-1)^m;   y -> -y : m' = -m, phase 1;
+//  z -> -z : m' = m, phase (-1)^(n+m); swap x,y : m' = -m, phase i^m.
+// Symmetry g = bits (fx, fy, fz, sw) is sigma = Fx^fx Fy^fy Fz^fz Sw^sw; its
+// map is the composition D = D_Fx D_Fy D_Fz D_Sw.
+void symmetry_map(int P, std::vector<int32_t>& dst, std::vector<int32_t>& phase) {
+  int P2 = P * P;
+  dst.assign(16 * P2, 0);
+  phase.assign(16 * P2, 0);
+  for (int g = 0; g < 16; ++g)
+    for (int n = 0; n < P; ++n)
+      for (int m = -n; m <= n; ++m) {
+        int cm = m, ph = 0;
+        auto apply = [&](int which) {
+          if (which == 0) { ph += 2 * (((cm % 2) + 2) % 2); cm = -cm; }
+          else if (which == 1) { cm = -cm; }
+          else if (which == 2) { ph += 2 * ((((n + cm) % 2) + 2) % 2); }
+          else { ph += ((cm % 4) + 4) % 4; cm = -cm; }
+        };
+        if (g & 1) apply(0);
+        if (g & 2) apply(1);
+        if (g & 4) apply(2);
+        if (g & 8) apply(3);
+        dst[g * P2 + n * n + n + m] = n * n + n + cm;
+        phase[g * P2 + n * n + n + m] = ph & 3;
+      }
+}
+
+}  // namespace hfmm

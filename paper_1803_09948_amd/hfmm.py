@@ -1,0 +1,231 @@
+"""ctypes binding of the hfmm C ABI (include/hfmm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device vectors are torch tensors on the current GPU; the binding
+passes their data pointers and torch's current HIP stream.  There is no CPU
+fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libhfmm.so")
+
+HFMM_OK, HFMM_ENOTCONV, HFMM_EINVAL, HFMM_ENOMEM, HFMM_EHIP, HFMM_EINTERNAL = 0, 1, -1, -2, -3, -4
+
+EXPORTS = [
+    "hfmm_default_opts", "hfmm_build_tree", "hfmm_build_bie", "hfmm_prepare", "hfmm_matvec",
+    "hfmm_gmres_solve", "hfmm_bie_plane_wave", "hfmm_batch_matvec", "hfmm_tree_stats",
+    "hfmm_tree_export", "hfmm_lists_export", "hfmm_set_timing", "hfmm_phase_times",
+    "hfmm_tree_free", "hfmm_last_error", "hfmm_version",
+]
+
+
+class Opts(C.Structure):
+    _fields_ = [("ncrit", C.c_int32), ("max_level", C.c_int32), ("theta", C.c_double),
+                ("kappa", C.c_double), ("eta", C.c_double), ("near_levels", C.c_int32),
+                ("near_order", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_src", C.c_int64), ("n_tgt", C.c_int64), ("n_cell", C.c_int32),
+                ("n_leaf", C.c_int32), ("n_level", C.c_int32), ("point_mode", C.c_int32),
+                ("centre", C.c_double * 3), ("half", C.c_double), ("n_m2l", C.c_int64),
+                ("n_p2p", C.c_int64), ("p2p_body_pairs", C.c_int64), ("n_tables", C.c_int64),
+                ("n_near", C.c_int64), ("device_bytes", C.c_int64)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["centre"] = list(self.centre)
+        return d
+
+
+class GmresInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("resid_est", C.c_double),
+                ("resid_true", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class HfmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hfmm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads libhfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run python -m paper_1803_09948_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "hfmm_default_opts": [C.POINTER(Opts)],
+            "hfmm_build_tree": [vp, i64, C.POINTER(Opts), C.POINTER(vp)],
+            "hfmm_build_bie": [vp, i64, vp, i64, C.POINTER(Opts), C.POINTER(vp)],
+            "hfmm_prepare": [vp, dbl, i32, vp],
+            "hfmm_matvec": [vp, dbl, i32, vp, vp, vp],
+            "hfmm_gmres_solve": [vp, dbl, i32, vp, vp, dbl, i32, i32, C.POINTER(GmresInfo), vp],
+            "hfmm_bie_plane_wave": [vp, dbl, vp, vp, vp],
+            "hfmm_batch_matvec": [i32, vp, vp, vp, vp, vp, vp],
+            "hfmm_tree_stats": [vp, dbl, i32, C.POINTER(Stats)],
+            "hfmm_tree_export": [vp, vp, vp, vp],
+            "hfmm_lists_export": [vp, dbl, i32, vp, vp],
+            "hfmm_set_timing": [vp, i32],
+            "hfmm_phase_times": [vp, vp],
+            "hfmm_tree_free": [vp],
+            "hfmm_last_error": [],
+            "hfmm_version": [],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.hfmm_tree_free.restype = None
+        L.hfmm_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise HfmmError(rc, lib().hfmm_last_error().decode())
+    return rc
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    _check(lib().hfmm_default_opts(C.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream(torch, stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+
+
+class Tree:
+    """A tree handle (point mode or BIE); owns its device memory."""
+
+    def __init__(self, handle, n_in: int, n_out: int, bie: bool):
+        self._h = C.c_void_p(handle)
+        self.n_in, self.n_out, self.bie = n_in, n_out, bie
+
+    # construction ---------------------------------------------------------
+    @classmethod
+    def from_points(cls, xyz, **opts) -> "Tree":
+        x = np.ascontiguousarray(xyz, dtype=np.float32)
+        h = C.c_void_p()
+        o = default_opts(**opts)
+        _check(lib().hfmm_build_tree(x.ctypes.data, len(x), C.byref(o), C.byref(h)))
+        return cls(h.value, len(x), len(x), False)
+
+    @classmethod
+    def from_mesh(cls, verts, tris, **opts) -> "Tree":
+        v = np.ascontiguousarray(verts, dtype=np.float64)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        h = C.c_void_p()
+        o = default_opts(**opts)
+        _check(lib().hfmm_build_bie(v.ctypes.data, len(v), t.ctypes.data, len(t), C.byref(o), C.byref(h)))
+        return cls(h.value, len(t), len(t), True)
+
+    def free(self):
+        if self._h and self._h.value:
+            lib().hfmm_tree_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # compute --------------------------------------------------------------
+    def prepare(self, k: float, P: int, stream=None):
+        import torch
+        _check(lib().hfmm_prepare(self._h, float(k), int(P), _stream(torch, stream)))
+
+    def matvec(self, k: float, P: int, x, y=None, stream=None):
+        """y = A x on the GPU; x: complex64 CUDA tensor of length n."""
+        import torch
+        assert x.dtype == torch.complex64 and x.is_cuda and x.is_contiguous() and x.numel() == self.n_in
+        if y is None:
+            y = torch.empty(self.n_out, dtype=torch.complex64, device=x.device)
+        _check(lib().hfmm_matvec(self._h, float(k), int(P), C.c_void_p(x.data_ptr()),
+                                 C.c_void_p(y.data_ptr()), _stream(torch, stream)))
+        return y
+
+    def gmres(self, k: float, P: int, b, x0=None, tol=1e-4, restart=30, maxit=2000, stream=None):
+        import torch
+        assert b.dtype == torch.complex128 and b.is_cuda and b.numel() == self.n_out
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        info = GmresInfo()
+        rc = _check(lib().hfmm_gmres_solve(self._h, float(k), int(P), C.c_void_p(b.data_ptr()),
+                                           C.c_void_p(x.data_ptr()), float(tol), int(restart),
+                                           int(maxit), C.byref(info), _stream(torch, stream)))
+        d = info.as_dict()
+        d["converged"] = rc == HFMM_OK
+        return x, d
+
+    def plane_wave(self, k: float, direction=(0.0, 0.0, 1.0), device="cuda", stream=None):
+        import torch
+        b = torch.empty(self.n_out, dtype=torch.complex128, device=device)
+        d = np.ascontiguousarray(direction, dtype=np.float64)
+        _check(lib().hfmm_bie_plane_wave(self._h, float(k), d.ctypes.data, C.c_void_p(b.data_ptr()),
+                                         _stream(torch, stream)))
+        return b
+
+    # introspection ----------------------------------------------------------
+    def stats(self, k: float = 1.0, P: int = 0) -> dict:
+        s = Stats()
+        _check(lib().hfmm_tree_stats(self._h, float(k), int(P), C.byref(s)))
+        return s.as_dict()
+
+    def export(self):
+        st = self.stats()
+        sp = np.zeros(st["n_src"], np.int32)
+        tp = np.zeros(st["n_tgt"], np.int32)
+        cells = np.zeros((st["n_cell"], 10), np.int32)
+        _check(lib().hfmm_tree_export(self._h, sp.ctypes.data, tp.ctypes.data, cells.ctypes.data))
+        return sp, tp, cells
+
+    def lists(self, k: float, P: int):
+        st = self.stats(k, P)
+        m2l = np.zeros((st["n_m2l"], 2), np.int32)
+        p2p = np.zeros((st["n_p2p"], 2), np.int32)
+        _check(lib().hfmm_lists_export(self._h, float(k), int(P), m2l.ctypes.data, p2p.ctypes.data))
+        return m2l, p2p
+
+    def set_timing(self, on: bool = True):
+        _check(lib().hfmm_set_timing(self._h, 1 if on else 0))
+
+    def phase_times(self):
+        a = np.zeros(8, np.float32)
+        _check(lib().hfmm_phase_times(self._h, a.ctypes.data))
+        return a
+
+
+def batch_matvec(trees, ks, Ps, xs, ys, stream=None):
+    """Fused product over independent point-mode trees: ys[i] = A_i xs[i]."""
+    import torch
+    n = len(trees)
+    H = (C.c_void_p * n)(*[t._h.value for t in trees])
+    K = (C.c_double * n)(*[float(k) for k in ks])
+    PP = (C.c_int32 * n)(*[int(p) for p in Ps])
+    X = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+    Y = (C.c_void_p * n)(*[y.data_ptr() for y in ys])
+    _check(lib().hfmm_batch_matvec(n, H, K, PP, X, Y, _stream(torch, stream)))
+    return ys

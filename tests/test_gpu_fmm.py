@@ -1,0 +1,105 @@
+"""GPU parity of the point-mode FMM matvec against the FP64 oracle.
+
+Bar (stated for FP32 arithmetic): relative 2-norm difference to the CPU FP64
+FMM at the same tree, lists and P <= 1e-5; the FMM truncation error against
+the FP64 direct sum is reported and bounded loosely."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.fmm import FMM, direct_sum
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1803_09948_amd import hfmm  # noqa: E402
+
+
+def _gpu_matvec(x, q, k, P, **opts):
+    t = hfmm.Tree.from_points(x, **opts)
+    qd = torch.from_numpy(q).to("cuda")
+    y = t.matvec(k, P, qd)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), t
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("n,k,P,ncrit,seed", [
+    (4096, 1.0, 8, 64, 11),        # plain matvec workload
+    (4097, 1.0, 8, 64, 12),        # ragged
+    (3000, 9.0, 10, 32, 13),       # higher frequency, kappa active
+    (2000, 2.0, 1, 32, 14),        # P = 1
+])
+def test_matvec_vs_oracle_fmm(n, k, P, ncrit, seed):
+    x = synth.sphere_points(n, seed)
+    q = synth.strengths(n, seed)
+    print(f"case n={n} k={k} P={P} ncrit={ncrit}", flush=True)
+    y, t = _gpu_matvec(x, q, k, P, ncrit=ncrit)
+    f = FMM(x, k=k, P=P, ncrit=ncrit)
+    yo = f.matvec(q)
+    e = rel(y, yo)
+    ed = rel(yo, direct_sum(k, x, x, q))
+    print(f"  gpu vs oracle FMM {e:.3e}; oracle FMM vs direct {ed:.3e}")
+    assert np.all(np.isfinite(y))
+    assert e <= 1e-5
+
+
+def test_largest_P_vs_direct_sum():
+    """P = 16 (the largest order): truncation error is far below FP32 rounding."""
+    n, k = 1500, 3.0
+    x = synth.sphere_points(n, 15)
+    q = synth.strengths(n, 15)
+    y, _ = _gpu_matvec(x, q, k, 16, ncrit=32)
+    e = rel(y, direct_sum(k, x, x, q))
+    print("P=16 vs direct", e)
+    assert e <= 1e-5
+
+
+def test_p2p_only_equals_direct_sum():
+    """theta -> 0: the traversal accepts nothing, so the GPU result is the
+    FP32 direct sum of Listing 1 over all pairs."""
+    n = 3000
+    x = synth.sphere_points(n, 21)
+    q = synth.strengths(n, 21)
+    y, t = _gpu_matvec(x, q, 5.0, 4, ncrit=40, theta=1e-9)
+    assert t.stats(5.0, 4)["n_m2l"] == 0
+    e = rel(y, direct_sum(5.0, x, x, q))
+    print("p2p only vs direct", e)
+    assert e <= 2e-6
+
+
+def test_edge_cases():
+    # one point: nothing to sum
+    y, _ = _gpu_matvec(synth.sphere_points(1, 1), np.array([1 + 1j], np.complex64), 1.0, 4)
+    assert y.shape == (1,) and y[0] == 0
+    # fewer points than ncrit: a single leaf, direct sum
+    x = synth.sphere_points(40, 2)
+    q = synth.strengths(40, 2)
+    y, _ = _gpu_matvec(x, q, 2.0, 6)
+    assert rel(y, direct_sum(2.0, x, x, q)) < 2e-6
+    # duplicated points contribute nothing to each other
+    x = np.repeat(synth.sphere_points(300, 3), 2, axis=0)
+    q = synth.strengths(600, 3)
+    y, _ = _gpu_matvec(x, q, 2.0, 6, ncrit=16)
+    yo = FMM(x, k=2.0, P=6, ncrit=16).matvec(q)
+    assert rel(y, yo) < 1e-5
+    # ellipsoid, non-unit root cube
+    x = synth.scale_axes(synth.sphere_points(2500, 4), (0.5, 2.0, 1.3))
+    q = synth.strengths(2500, 4)
+    y, _ = _gpu_matvec(x, q, 3.0, 8, ncrit=32)
+    assert rel(y, FMM(x, k=3.0, P=8, ncrit=32).matvec(q)) < 1e-5
+
+
+def test_repeat_and_determinism_of_near_field():
+    x = synth.sphere_points(4096, 11)
+    q = synth.strengths(4096, 11)
+    t = hfmm.Tree.from_points(x)
+    qd = torch.from_numpy(q).to("cuda")
+    y1 = t.matvec(1.0, 8, qd).cpu().numpy()
+    y2 = t.matvec(1.0, 8, qd).cpu().numpy()
+    assert rel(y1, y2) < 1e-6

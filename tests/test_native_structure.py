@@ -1,0 +1,71 @@
+"""CPU tests of the native library: symbol exports, argument validation, and
+exact equality of the C++ tree and traversal lists with the oracle's."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.tree import build_tree, dual_tree_traversal
+from paper_1803_09948_amd import hfmm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hfmm.lib()
+    hdr = open(os.path.join(ROOT, "include", "hfmm.h")).read()
+    names = set(re.findall(r"\b(hfmm_[a-z_0-9]+)\s*\(", hdr))
+    assert names, "no declarations parsed"
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert set(hfmm.EXPORTS) == names
+
+
+@pytest.mark.parametrize("n,ncrit,seed,axes", [(4096, 64, 11, (1, 1, 1)), (3001, 17, 5, (0.6, 1.7, 1.1)),
+                                                 (700, 64, 2, (1, 1, 1)), (1, 64, 3, (1, 1, 1))])
+def test_tree_equals_oracle(n, ncrit, seed, axes):
+    x = synth.scale_axes(synth.sphere_points(n, seed), axes)
+    t = hfmm.Tree.from_points(x, ncrit=ncrit)
+    sp, tp, cells = t.export()
+    o = build_tree(x, None, ncrit)
+    np.testing.assert_array_equal(sp, o.src_perm)
+    np.testing.assert_array_equal(tp, o.tgt_perm)
+    ref = np.stack([o.level, o.ijk[:, 0], o.ijk[:, 1], o.ijk[:, 2], o.sb, o.se, o.tb, o.te, o.cb, o.ce], 1)
+    np.testing.assert_array_equal(cells, ref)
+    st = t.stats()
+    assert st["centre"] == list(o.c) and st["half"] == o.H
+
+
+@pytest.mark.parametrize("n,k,P,theta", [(4096, 1.0, 8, 0.5), (6000, 16 * math.pi, 10, 0.5),
+                                         (2500, 7.3, 6, 0.7)])
+def test_lists_equal_oracle(n, k, P, theta):
+    x = synth.sphere_points(n, 7)
+    t = hfmm.Tree.from_points(x, ncrit=32, theta=theta)
+    m2l, p2p = t.lists(k, P)
+    o = build_tree(x, None, 32)
+    om2l, op2p = dual_tree_traversal(o, k, theta, 0.4 * P)
+    assert sorted(map(tuple, m2l.tolist())) == sorted(om2l)
+    assert sorted(map(tuple, p2p.tolist())) == sorted(op2p)
+    # same visit order as well
+    assert [tuple(v) for v in m2l.tolist()] == om2l
+
+
+def test_invalid_arguments():
+    x = synth.sphere_points(100, 1)
+    with pytest.raises(hfmm.HfmmError) as e:
+        hfmm.Tree.from_points(np.zeros((0, 3), np.float32))
+    assert e.value.code == hfmm.HFMM_EINVAL
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.Tree.from_points(x, ncrit=0)
+    bad = x.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.Tree.from_points(bad)
+    t = hfmm.Tree.from_points(x)
+    for k, P in ((0.0, 8), (-1.0, 8), (float("inf"), 8), (1.0, 0), (1.0, 17)):
+        with pytest.raises(hfmm.HfmmError) as e:
+            t.prepare(k, P, stream=0)
+        assert e.value.code == hfmm.HFMM_EINVAL
