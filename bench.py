@@ -1,0 +1,186 @@
+"""Benchmark: FMM matvecs/s for the Helmholtz kernel at 1M points, P=10.
+
+Workload (the headline configuration): N = 1,048,576 points uniform on the
+unit sphere (seeded, FP32-canonical), k = 16 pi (diameter = 16 wavelengths),
+P = 10, ncrit = 64, theta = 0.5, kappa = 0.4 P, complex64 strengths with
+real and imaginary parts uniform in [-1, 1].  Tree, lists and translation
+operators are built before the timed region; inputs are resident in HBM.
+One step = one full FMM matvec (P2M, M2M, M2L, L2L, L2P, P2P).
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12      # MI355X FP32 vector / FP32 MFMA, FLOP/s
+PEAK_HBM = 8.0e12         # B/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(x, q, k, P, ncrit, stats, budget_s=15.0):
+    """The FP64 oracle timed on a bounded sample of the same workload, scaled
+    to a full matvec with the traversal's counts (single thread)."""
+    import oracle.expansions as ex
+    from oracle.fmm import direct_sum
+    rng = np.random.default_rng(0)
+    n = len(x)
+    t0 = time.perf_counter()
+    # P2P: direct sum over a sample of targets against all sources
+    nt = 64
+    ti = rng.choice(n, nt, replace=False)
+    ta = time.perf_counter()
+    direct_sum(k, x[ti], x, q, chunk=8)
+    p2p_rate = nt * n / (time.perf_counter() - ta)                 # pairs / s
+    # M2L: operator construction + apply for a sample of well-separated pairs
+    nm = 40
+    M = (rng.normal(size=P * P) + 1j * rng.normal(size=P * P))
+    ta = time.perf_counter()
+    for i in range(nm):
+        t = np.array([0.5, 0.2, 0.1]) + 0.01 * i
+        ex.sr_matrix(t, k, P) @ M
+    m2l_per_pair = (time.perf_counter() - ta) / nm
+    # P2M / L2P per body, M2M / L2L per cell
+    ta = time.perf_counter()
+    nb = 4096
+    ex.p2m(P, k, np.zeros(3), x[:nb] * 0.01, q[:nb])
+    p2m_per_body = (time.perf_counter() - ta) / nb
+    ta = time.perf_counter()
+    for i in range(8):
+        ex.rr_matrix(np.array([0.01, -0.01, 0.01]) * (i + 1), k, P) @ M
+    m2m_per_cell = (time.perf_counter() - ta) / 8
+    est = (stats["p2p_body_pairs"] / p2p_rate + stats["n_m2l"] * m2l_per_pair
+           + 2 * n * p2m_per_body + 2 * stats["n_cell"] * m2m_per_cell)
+    used = time.perf_counter() - t0
+    return {
+        "value": 1.0 / est, "unit": "matvec/s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle (numpy FP64, 1 thread) timed on {nt} targets x {n} sources of the direct "
+                   f"sum, {nm} M2L operator builds+applies, {nb} P2M bodies and 8 M2M operators "
+                   f"({used:.1f} s), scaled by this workload's counts: {stats['p2p_body_pairs']} P2P "
+                   f"body pairs, {stats['n_m2l']} M2L pairs, {stats['n_cell']} cells"),
+        "seconds_per_matvec": est,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--P", type=int, default=10)
+    ap.add_argument("--k", type=float, default=16.0 * math.pi)
+    ap.add_argument("--ncrit", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check", action="store_true", help="compare 200 sampled outputs with the FP64 direct sum")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1803_09948_amd import hfmm
+
+    dev = torch.device("cuda:0")
+    x = synth.sphere_points(a.n, 23)
+    q = synth.strengths(a.n, 23)
+    t0 = time.perf_counter()
+    tree = hfmm.Tree.from_points(x, ncrit=a.ncrit)
+    t_tree = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    tree.prepare(a.k, a.P)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    st = tree.stats(a.k, a.P)
+    log(f"setup: tree {t_tree:.2f} s, lists+operators {t_prep:.2f} s; {json.dumps(st)}")
+    qd = torch.from_numpy(q).to(dev)
+    yd = torch.empty_like(qd)
+    for _ in range(a.warmup):
+        tree.matvec(a.k, a.P, qd, yd)
+    torch.cuda.synchronize()
+    log("warmup done")
+    # timed region: K full matvecs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        tree.matvec(a.k, a.P, qd, yd)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / a.steps * 1e3
+    log(f"timed {a.steps} steps: {ms:.3f} ms/step")
+    # per-phase device times from HIP events on the launch stream (separate pass)
+    tree.set_timing(True)
+    ph = np.zeros(8)
+    nrep = max(3, min(10, a.steps))
+    for _ in range(nrep):
+        tree.matvec(a.k, a.P, qd, yd)
+        ph += tree.phase_times()
+    ph /= nrep
+    tree.set_timing(False)
+    names = ["p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "bie", "total"]
+    phases = {n: round(float(v), 4) for n, v in zip(names, ph)}
+    log("phases (ms):", phases)
+    P2 = a.P * a.P
+    m2l_flops = 8.0 * a.P ** 4 * st["n_m2l"]
+    p2p_flops = 20.0 * st["p2p_body_pairs"]
+    m2l_ach = m2l_flops / (phases["m2l"] * 1e-3)
+    p2p_ach = p2p_flops / (phases["p2p"] * 1e-3)
+    dominant = "m2l" if phases["m2l"] >= phases["p2p"] else "p2p"
+    if dominant == "m2l":
+        roof = {"kernel": "k_m2l", "bound": "alu", "achieved": m2l_ach / 1e12, "peak": PEAK_FP32 / 1e12,
+                "unit": "TFLOP/s", "frac": m2l_ach / PEAK_FP32, "traffic": None,
+                "per_unit": "8 P^4 FLOP per M2L pair (dense P^2 x P^2 complex operator)",
+                "units_per_launch": st["n_m2l"], "launch_ms": phases["m2l"]}
+    else:
+        roof = {"kernel": "k_p2p", "bound": "alu", "achieved": p2p_ach / 1e12, "peak": PEAK_FP32 / 1e12,
+                "unit": "TFLOP/s", "frac": p2p_ach / PEAK_FP32, "traffic": None,
+                "per_unit": "20 FLOP per body pair (plus rsqrt, sin, cos)",
+                "units_per_launch": st["p2p_body_pairs"], "launch_ms": phases["p2p"]}
+    out = {
+        "metric": "FMM matvecs/s at 1M pts P=10 (% FP32 peak)",
+        "value": 1e3 / ms,
+        "unit": "matvec/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"helmholtz FMM matvec, N={a.n} uniform on the unit sphere, k={a.k:.6g} "
+                               f"(16 wavelengths across), P={a.P}, ncrit={a.ncrit}, theta=0.5, kappa=0.4P",
+                   "n": a.n, "k": a.k, "P": a.P, "ncrit": a.ncrit},
+        "roofline": roof,
+        "phases_ms": phases,
+        "secondary": {"p2p_tflops": p2p_ach / 1e12, "p2p_gpairs_per_s": st["p2p_body_pairs"] / phases["p2p"] / 1e6,
+                      "m2l_tflops": m2l_ach / 1e12, "n_m2l": st["n_m2l"], "p2p_body_pairs": st["p2p_body_pairs"],
+                      "n_tables": st["n_tables"], "setup_s": {"tree": t_tree, "prepare": t_prep}},
+    }
+    if a.check:
+        from oracle.fmm import direct_sum
+        rng = np.random.default_rng(1)
+        idx = rng.choice(a.n, 200, replace=False)
+        ref = direct_sum(a.k, x[idx], x, q, chunk=8)
+        y = yd.cpu().numpy()[idx]
+        out["secondary"]["rel_err_vs_direct_200"] = float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x, q, a.k, a.P, a.ncrit, st)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -149,12 +149,15 @@ int hfmm_batch_matvec(int32_t count, hfmm_tree* const* trees, const double* ks,
 int hfmm_tree_stats(hfmm_tree* tree, double k, int32_t P, hfmm_stats* out);
 
 /* Host copies of the tree for structural tests (no device access).
+ *  P = 0: the base tree (split on ncrit only).  P > 0: the tree used at
+ *  (k, P), where non-empty cells wider than kappa/k also split (such cells
+ *  could never be accepted for M2L).
  *  src_perm/tgt_perm: int32[n_src]/[n_tgt], sorted position -> input index.
  *  cells: int32[n_cell][10] = level, i, j, k (cell coordinates at its level),
- *  src_begin, src_end, tgt_begin, tgt_end, child_begin, child_end.
- *  Any pointer may be NULL. */
-int hfmm_tree_export(const hfmm_tree* tree, int32_t* src_perm, int32_t* tgt_perm,
-                     int32_t* cells);
+ *  src_begin, src_end, tgt_begin, tgt_end, child_begin, child_end
+ *  (n_cell from hfmm_tree_stats with the same k, P).  Any pointer may be NULL. */
+int hfmm_tree_export(hfmm_tree* tree, double k, int32_t P, int32_t* src_perm,
+                     int32_t* tgt_perm, int32_t* cells);
 
 /* Host copies of the traversal lists at (k, P): int32 pairs (target cell,
  * source cell), n_m2l and n_p2p of them (hfmm_tree_stats gives the counts).

@@ -49,7 +49,8 @@ class FMM:
         self.tgt = self.src if targets is None else np.asarray(targets, np.float32)
         self.k, self.P, self.theta = float(k), int(P), float(theta)
         self.kappa = 0.4 * P if kappa is None else float(kappa)
-        self.tree: Tree = build_tree(self.src, None if targets is None else self.tgt, ncrit)
+        self.tree: Tree = build_tree(self.src, None if targets is None else self.tgt, ncrit,
+                                     split_side=self.kappa / self.k)
         self.m2l, self.p2p = dual_tree_traversal(self.tree, self.k, self.theta, self.kappa)
         self._cache: dict = {}
 

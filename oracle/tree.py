@@ -15,7 +15,10 @@ implemented here (restated in the design doc) are:
   coordinates, clamped to [0, 2^21 - 1]; interleaved with x in the lowest bit.
 * Sort.  Stable by key (ties keep input order), sources and targets apart.
 * Split.  A cell splits into its non-empty octants when it holds more than
-  ncrit sources (point mode: sources = targets), down to level 20.
+  ncrit sources (point mode: sources = targets), down to level 20.  With a
+  wavenumber-aware acceptance (below), a non-empty cell whose side exceeds
+  kappa/k always splits: such a cell can never be accepted, so as a leaf all
+  of its targets would interact directly with every source.
 * Cells are stored level by level, each level in Morton order.
 * Acceptance (M2L) between target A and source B, with half-sides hA, hB:
   3 (sA + sB)^2 < theta^2 D2 and k * 2 max(hA, hB) <= kappa, where sA, sB,
@@ -101,8 +104,10 @@ class Tree:
         return self.c - self.H + (2.0 * self.ijk[i].astype(np.float64) + 1.0) * h
 
 
-def build_tree(src_f32: np.ndarray, tgt_f32: np.ndarray | None, ncrit: int) -> Tree:
-    """Octree over sources and targets (targets None: point mode, same set)."""
+def build_tree(src_f32: np.ndarray, tgt_f32: np.ndarray | None, ncrit: int,
+               split_side: float | None = None) -> Tree:
+    """Octree over sources and targets (targets None: point mode, same set).
+    split_side: non-empty cells with side > split_side always split."""
     src = np.asarray(src_f32, np.float32)
     point_mode = tgt_f32 is None
     tgt = src if point_mode else np.asarray(tgt_f32, np.float32)
@@ -129,7 +134,9 @@ def build_tree(src_f32: np.ndarray, tgt_f32: np.ndarray | None, ncrit: int) -> T
         nxt = []
         for ci in cur:
             ns = se[ci] - sb[ci]
-            if ns <= ncrit or lev >= MAXLEVEL:
+            nb = ns if point_mode else ns + (te[ci] - tb[ci])
+            force = split_side is not None and 2.0 * H / (1 << lev) > split_side and nb >= 1
+            if (ns <= ncrit and not force) or lev >= MAXLEVEL:
                 cb[ci] = ce[ci] = len(level)  # leaf: empty child range
                 continue
             shift = 3 * (KEYBITS - lev - 1)

@@ -55,7 +55,7 @@ Tree::~Tree() {
     for (auto& e : ev) (void)hipEventDestroy(e);
 }
 
-int upload_geometry(Tree& t) {
+int upload_bodies(Tree& t) {
   const HostTree& h = t.h;
   std::vector<float4> sp(h.nsrc), tp(h.ntgt);
   for (int64_t i = 0; i < h.nsrc; ++i)
@@ -69,22 +69,18 @@ int upload_geometry(Tree& t) {
   if (!t.bie) {
     for (int64_t i = 0; i < h.nsrc; ++i) sidx[i] = h.src_perm[i];
   } else {
-    // sources are the Gauss points 3*panel + g, weight area/3
+    // sources are the Gauss points 3*panel + g with weight area/3
     sw.resize(h.nsrc);
     for (int64_t i = 0; i < h.nsrc; ++i) {
-      int32_t s = h.src_perm[i];
-      int32_t pnl = s / 3;
+      int32_t pnl = h.src_perm[i] / 3;
       sidx[i] = pnl;
       const double* v = t.verts.data();
       const int32_t* tr = t.tris.data() + 3 * pnl;
-      double a[3], b[3], c[3];
+      double u[3], w[3];
       for (int d = 0; d < 3; ++d) {
-        a[d] = v[3 * tr[0] + d];
-        b[d] = v[3 * tr[1] + d];
-        c[d] = v[3 * tr[2] + d];
+        u[d] = v[3 * tr[1] + d] - v[3 * tr[0] + d];
+        w[d] = v[3 * tr[2] + d] - v[3 * tr[0] + d];
       }
-      double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-      double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
       double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
       double area = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
       sw[i] = (float)(area / 3.0);
@@ -93,6 +89,16 @@ int upload_geometry(Tree& t) {
   if ((rc = upload(t.d_src_idx, sidx))) return rc;
   if (t.bie && (rc = upload(t.d_src_w, sw))) return rc;
   if ((rc = upload(t.d_tgt_perm, h.tgt_perm))) return rc;
+  if ((rc = t.d_q.alloc((size_t)h.nsrc * sizeof(float2))) || (rc = t.d_ys.alloc((size_t)h.ntgt * sizeof(float2))))
+    return rc;
+  t.body_bytes = (int64_t)(t.d_src_pos.bytes + t.d_tgt_pos.bytes + t.d_src_idx.bytes + t.d_src_w.bytes +
+                           t.d_tgt_perm.bytes + t.d_q.bytes + t.d_ys.bytes);
+  t.uploaded = true;
+  return HFMM_OK;
+}
+
+static int upload_cells(Plan& pl) {
+  const HostTree& h = pl.ct;
   int nc = h.ncell();
   std::vector<int4> cells(nc), topo(nc);
   std::vector<float4> geo(nc);
@@ -110,15 +116,13 @@ int upload_geometry(Tree& t) {
       if (h.te[i] > h.tb[i]) tl.push_back(i);
     }
   }
-  if ((rc = upload(t.d_cells, cells)) || (rc = upload(t.d_geo, geo)) || (rc = upload(t.d_clev, clev)) ||
-      (rc = upload(t.d_topo, topo)) || (rc = upload(t.d_src_leaves, sl)) ||
-      (rc = upload(t.d_tgt_leaves, tl)))
+  int rc;
+  if ((rc = upload(pl.d_cells, cells)) || (rc = upload(pl.d_geo, geo)) || (rc = upload(pl.d_clev, clev)) ||
+      (rc = upload(pl.d_topo, topo)) || (rc = upload(pl.d_src_leaves, sl)) ||
+      (rc = upload(pl.d_tgt_leaves, tl)))
     return rc;
-  t.n_src_leaves = (int32_t)sl.size();
-  t.n_tgt_leaves = (int32_t)tl.size();
-  t.geo_bytes = (int64_t)(t.d_src_pos.bytes + t.d_tgt_pos.bytes + t.d_src_idx.bytes + t.d_src_w.bytes +
-                          t.d_tgt_perm.bytes + t.d_cells.bytes + t.d_geo.bytes + t.d_clev.bytes +
-                          t.d_topo.bytes + t.d_src_leaves.bytes + t.d_tgt_leaves.bytes);
+  pl.n_src_leaves = (int32_t)sl.size();
+  pl.n_tgt_leaves = (int32_t)tl.size();
   return HFMM_OK;
 }
 
@@ -136,13 +140,16 @@ struct Key128Hash {
   }
 };
 
-static int build_lists_host(Tree& t, double k, int P, Plan& pl) {
-  double kappa = t.kappa < 0 ? 0.4 * P : t.kappa;
-  dual_tree_traversal(t.h, k, t.theta, kappa, pl.lists);
+double kappa_of(const Tree& t, int P) { return t.kappa < 0 ? 0.4 * P : t.kappa; }
+
+int build_plan_host(Tree& t, double k, int P, Plan& pl) {
+  const double kappa = kappa_of(t, P);
+  build_cells(t.h, t.ncrit, t.max_level, kappa / k, pl.ct);
+  dual_tree_traversal(pl.ct, k, t.theta, kappa, pl.lists);
   int64_t pp = 0;
   for (size_t i = 0; i < pl.lists.p2p_a.size(); ++i) {
     int a = pl.lists.p2p_a[i], b = pl.lists.p2p_b[i];
-    pp += int64_t(t.h.te[a] - t.h.tb[a]) * int64_t(t.h.se[b] - t.h.sb[b]);
+    pp += int64_t(pl.ct.te[a] - pl.ct.tb[a]) * int64_t(pl.ct.se[b] - pl.ct.sb[b]);
   }
   pl.p2p_body_pairs = pp;
   return HFMM_OK;
@@ -158,13 +165,14 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
     return HFMM_OK;
   }
   int rc;
-  if (!t.d_cells.p && (rc = upload_geometry(t))) return rc;
+  if (!t.uploaded && (rc = upload_bodies(t))) return rc;
   auto plp = std::make_unique<Plan>();
   Plan& pl = *plp;
   pl.k = k;
   pl.P = P;
-  const HostTree& h = t.h;
-  if ((rc = build_lists_host(t, k, P, pl))) return rc;
+  if ((rc = build_plan_host(t, k, P, pl))) return rc;
+  if ((rc = upload_cells(pl))) return rc;
+  const HostTree& h = pl.ct;
   const int P2 = P * P;
   const int nlev = h.nlevels();
   pl.rho.resize(nlev);
@@ -260,6 +268,7 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
   // P2P work: per target leaf, merged source intervals
   std::vector<int4> work;
   std::vector<int2> ivals;
+  std::vector<int32_t> totals;
   {
     const size_t np = pl.lists.p2p_a.size();
     std::vector<int32_t> ord(np);
@@ -283,6 +292,9 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
         ++j;
       }
       work.push_back(make_int4(h.tb[a], h.te[a], ib, (int)ivals.size()));
+      int tot = 0;
+      for (int v = ib; v < (int)ivals.size(); ++v) tot += ivals[v].y - ivals[v].x;
+      totals.push_back(tot);
       i = j;
     }
   }
@@ -301,6 +313,7 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
       (rc = upload(pl.d_m2m_base, pl.m2m_base)) || (rc = upload(pl.d_l2l_base, pl.l2l_base)) ||
       (rc = upload(pl.d_m2l_chunks, chunks)) || (rc = upload(pl.d_m2l_pairs, spairs)) ||
       (rc = upload(pl.d_p2p_work, work)) || (rc = upload(pl.d_p2p_ivals, ivals)) ||
+      (rc = upload(pl.d_p2p_total, totals)) ||
       (rc = upload(pl.d_symdst, sdst)) || (rc = upload(pl.d_symph, sph)) ||
       (rc = upload(pl.d_outidx, oidx)) || (rc = upload(pl.d_outph, oph)))
     return rc;
@@ -316,18 +329,15 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
                     d_lm.as<int32_t>(), d_val.as<double2>(), pl.d_tables.as<float2>(), s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
-  pl.device_bytes = (int64_t)(pl.d_ops.bytes + pl.d_tables.bytes + pl.d_rho.bytes + pl.d_m2l_chunks.bytes +
-                              pl.d_m2l_pairs.bytes + pl.d_p2p_work.bytes + pl.d_p2p_ivals.bytes +
-                              pl.d_symdst.bytes * 4);
-  // scratch
-  if (t.scratchP < P) {
-    if ((rc = t.d_q.alloc((size_t)h.nsrc * sizeof(float2))) ||
-        (rc = t.d_M.alloc((size_t)h.ncell() * P2 * sizeof(float2))) ||
-        (rc = t.d_L.alloc((size_t)h.ncell() * P2 * sizeof(float2))) ||
-        (rc = t.d_ys.alloc((size_t)h.ntgt * sizeof(float2))))
-      return rc;
-    t.scratchP = P;
-  }
+  if ((rc = pl.d_M.alloc((size_t)h.ncell() * P2 * sizeof(float2))) ||
+      (rc = pl.d_L.alloc((size_t)h.ncell() * P2 * sizeof(float2))))
+    return rc;
+  pl.device_bytes = 0;
+  for (DevBuf* b : {&pl.d_cells, &pl.d_geo, &pl.d_clev, &pl.d_topo, &pl.d_src_leaves, &pl.d_tgt_leaves,
+                    &pl.d_ops, &pl.d_tables, &pl.d_rho, &pl.d_m2m_base, &pl.d_l2l_base, &pl.d_m2l_chunks,
+                    &pl.d_m2l_pairs, &pl.d_p2p_work, &pl.d_p2p_ivals, &pl.d_p2p_total, &pl.d_symdst,
+                    &pl.d_symph, &pl.d_outidx, &pl.d_outph, &pl.d_M, &pl.d_L})
+    pl.device_bytes += (int64_t)b->bytes;
   t.plans[key] = std::move(plp);
   *out = t.plans[key].get();
   return HFMM_OK;
@@ -346,7 +356,7 @@ static int check_kP(double k, int P) {
 }
 
 static int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_t s) {
-  const HostTree& h = t.h;
+  const HostTree& h = pl.ct;
   const int P = pl.P, P2 = P * P;
   const float kf = (float)pl.k;
   auto mark = [&](int i) -> int {
@@ -355,34 +365,34 @@ static int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_
   };
   int rc;
   if ((rc = mark(0))) return rc;
-  HIP_TRY(hipMemsetAsync(t.d_M.p, 0, (size_t)h.ncell() * P2 * sizeof(float2), s));
-  HIP_TRY(hipMemsetAsync(t.d_L.p, 0, (size_t)h.ncell() * P2 * sizeof(float2), s));
+  HIP_TRY(hipMemsetAsync(pl.d_M.p, 0, (size_t)h.ncell() * P2 * sizeof(float2), s));
+  HIP_TRY(hipMemsetAsync(pl.d_L.p, 0, (size_t)h.ncell() * P2 * sizeof(float2), s));
   launch_gather(h.nsrc, t.d_src_idx.as<int32_t>(), t.bie ? t.d_src_w.as<float>() : nullptr, x,
                 t.d_q.as<float2>(), s);
-  launch_p2m(t.d_src_leaves.as<int32_t>(), t.n_src_leaves, t.d_cells.as<int4>(), t.d_geo.as<float4>(),
-             t.d_clev.as<int32_t>(), pl.d_rho.as<double>(), t.d_src_pos.as<float4>(),
-             t.d_q.as<float2>(), kf, P, t.d_M.as<float2>(), s);
+  launch_p2m(pl.d_src_leaves.as<int32_t>(), pl.n_src_leaves, pl.d_cells.as<int4>(), pl.d_geo.as<float4>(),
+             pl.d_clev.as<int32_t>(), pl.d_rho.as<double>(), t.d_src_pos.as<float4>(),
+             t.d_q.as<float2>(), kf, P, pl.d_M.as<float2>(), s);
   if ((rc = mark(1))) return rc;
   for (int l = h.nlevels() - 2; l >= 0; --l)
-    launch_m2m(h.level_off[l], h.level_off[l + 1], t.d_topo.as<int4>(), pl.d_m2m_base.as<int32_t>(),
-               pl.d_tables.as<float2>(), P, t.d_M.as<float2>(), s);
+    launch_m2m(h.level_off[l], h.level_off[l + 1], pl.d_topo.as<int4>(), pl.d_m2m_base.as<int32_t>(),
+               pl.d_tables.as<float2>(), P, pl.d_M.as<float2>(), s);
   if ((rc = mark(2))) return rc;
   launch_m2l(pl.d_m2l_chunks.as<int4>(), pl.n_m2l_chunks, pl.d_m2l_pairs.as<int4>(),
              pl.d_tables.as<float2>(), pl.d_symdst.as<int32_t>(), pl.d_symph.as<int32_t>(),
-             pl.d_outidx.as<int32_t>(), pl.d_outph.as<int32_t>(), P, t.d_M.as<float2>(),
-             t.d_L.as<float2>(), s);
+             pl.d_outidx.as<int32_t>(), pl.d_outph.as<int32_t>(), P, pl.d_M.as<float2>(),
+             pl.d_L.as<float2>(), s);
   if ((rc = mark(3))) return rc;
   for (int l = 1; l < h.nlevels(); ++l)
-    launch_l2l(h.level_off[l], h.level_off[l + 1], t.d_topo.as<int4>(), pl.d_l2l_base.as<int32_t>(),
-               pl.d_tables.as<float2>(), P, t.d_L.as<float2>(), s);
+    launch_l2l(h.level_off[l], h.level_off[l + 1], pl.d_topo.as<int4>(), pl.d_l2l_base.as<int32_t>(),
+               pl.d_tables.as<float2>(), P, pl.d_L.as<float2>(), s);
   if ((rc = mark(4))) return rc;
-  launch_l2p(t.d_tgt_leaves.as<int32_t>(), t.n_tgt_leaves, t.d_cells.as<int4>(), t.d_geo.as<float4>(),
-             t.d_clev.as<int32_t>(), pl.d_rho.as<double>(), t.d_tgt_pos.as<float4>(), kf, P,
-             t.d_L.as<float2>(), t.d_ys.as<float2>(), s);
+  launch_l2p(pl.d_tgt_leaves.as<int32_t>(), pl.n_tgt_leaves, pl.d_cells.as<int4>(), pl.d_geo.as<float4>(),
+             pl.d_clev.as<int32_t>(), pl.d_rho.as<double>(), t.d_tgt_pos.as<float4>(), kf, P,
+             pl.d_L.as<float2>(), t.d_ys.as<float2>(), s);
   if ((rc = mark(5))) return rc;
   launch_p2p(pl.d_p2p_work.as<int4>(), pl.n_p2p_work, pl.d_p2p_ivals.as<int2>(),
-             t.d_tgt_pos.as<float4>(), t.d_src_pos.as<float4>(), t.d_q.as<float2>(), kf,
-             t.d_ys.as<float2>(), s);
+             pl.d_p2p_total.as<int32_t>(), t.d_tgt_pos.as<float4>(), t.d_src_pos.as<float4>(),
+             t.d_q.as<float2>(), kf, t.d_ys.as<float2>(), s);
   if ((rc = mark(6))) return rc;
   launch_scatter(h.ntgt, t.d_tgt_perm.as<int32_t>(), t.d_ys.as<float2>(), y, s);
   if ((rc = mark(7))) return rc;
@@ -522,18 +532,9 @@ int hfmm_tree_stats(hfmm_tree* tree, double k, int32_t P, hfmm_stats* o) {
   if (!tree || !o) return set_error("NULL argument"), HFMM_EINVAL;
   Tree& t = *reinterpret_cast<Tree*>(tree);
   std::memset(o, 0, sizeof(*o));
-  const HostTree& h = t.h;
-  o->n_src = h.nsrc;
-  o->n_tgt = h.ntgt;
-  o->n_cell = h.ncell();
-  int nl = 0;
-  for (int i = 0; i < h.ncell(); ++i) nl += h.leaf(i);
-  o->n_leaf = nl;
-  o->n_level = h.nlevels();
-  o->point_mode = h.point_mode ? 1 : 0;
-  for (int d = 0; d < 3; ++d) o->centre[d] = h.c[d];
-  o->half = h.H;
-  o->device_bytes = t.geo_bytes;
+  const HostTree* h = &t.h;
+  Plan tmp;
+  const Plan* pl = nullptr;
   if (P > 0) {
     int rc = check_kP(k, P);
     if (rc) return rc;
@@ -541,45 +542,67 @@ int hfmm_tree_stats(hfmm_tree* tree, double k, int32_t P, hfmm_stats* o) {
     std::memcpy(&kb, &k, 8);
     auto it = t.plans.find(std::make_pair(kb, (int)P));
     if (it != t.plans.end()) {
-      const Plan& pl = *it->second;
-      o->n_m2l = (int64_t)pl.lists.m2l_a.size();
-      o->n_p2p = (int64_t)pl.lists.p2p_a.size();
-      o->p2p_body_pairs = pl.p2p_body_pairs;
-      o->n_tables = pl.n_tables;
-      o->n_near = pl.n_near;
-      o->device_bytes += pl.device_bytes;
+      pl = it->second.get();
     } else {
-      Plan pl;
-      build_lists_host(t, k, P, pl);
-      o->n_m2l = (int64_t)pl.lists.m2l_a.size();
-      o->n_p2p = (int64_t)pl.lists.p2p_a.size();
-      o->p2p_body_pairs = pl.p2p_body_pairs;
+      build_plan_host(t, k, P, tmp);
+      pl = &tmp;
     }
+    h = &pl->ct;
+  }
+  o->n_src = h->nsrc;
+  o->n_tgt = h->ntgt;
+  o->n_cell = h->ncell();
+  int nl = 0;
+  for (int i = 0; i < h->ncell(); ++i) nl += h->leaf(i);
+  o->n_leaf = nl;
+  o->n_level = h->nlevels();
+  o->point_mode = h->point_mode ? 1 : 0;
+  for (int d = 0; d < 3; ++d) o->centre[d] = h->c[d];
+  o->half = h->H;
+  o->device_bytes = t.body_bytes;
+  if (pl) {
+    o->n_m2l = (int64_t)pl->lists.m2l_a.size();
+    o->n_p2p = (int64_t)pl->lists.p2p_a.size();
+    o->p2p_body_pairs = pl->p2p_body_pairs;
+    o->n_tables = pl->n_tables;
+    o->n_near = pl->n_near;
+    o->device_bytes += pl->device_bytes;
   }
   return HFMM_OK;
   API_GUARD_END
 }
 
-int hfmm_tree_export(const hfmm_tree* tree, int32_t* src_perm, int32_t* tgt_perm, int32_t* cells) {
+int hfmm_tree_export(hfmm_tree* tree, double k, int32_t P, int32_t* src_perm, int32_t* tgt_perm,
+                     int32_t* cells) {
+  API_GUARD_BEGIN
   if (!tree) return set_error("tree is NULL"), HFMM_EINVAL;
-  const HostTree& h = reinterpret_cast<const Tree*>(tree)->h;
-  if (src_perm) std::memcpy(src_perm, h.src_perm.data(), h.nsrc * sizeof(int32_t));
-  if (tgt_perm) std::memcpy(tgt_perm, h.tgt_perm.data(), h.ntgt * sizeof(int32_t));
+  Tree& t = *reinterpret_cast<Tree*>(tree);
+  Plan tmp;
+  const HostTree* h = &t.h;
+  if (P > 0) {
+    int rc = check_kP(k, P);
+    if (rc) return rc;
+    build_plan_host(t, k, P, tmp);
+    h = &tmp.ct;
+  }
+  if (src_perm) std::memcpy(src_perm, t.h.src_perm.data(), t.h.nsrc * sizeof(int32_t));
+  if (tgt_perm) std::memcpy(tgt_perm, t.h.tgt_perm.data(), t.h.ntgt * sizeof(int32_t));
   if (cells)
-    for (int i = 0; i < h.ncell(); ++i) {
+    for (int i = 0; i < h->ncell(); ++i) {
       int32_t* c = cells + 10 * i;
-      c[0] = h.level[i];
-      c[1] = h.ijk[3 * i];
-      c[2] = h.ijk[3 * i + 1];
-      c[3] = h.ijk[3 * i + 2];
-      c[4] = h.sb[i];
-      c[5] = h.se[i];
-      c[6] = h.tb[i];
-      c[7] = h.te[i];
-      c[8] = h.cb[i];
-      c[9] = h.ce[i];
+      c[0] = h->level[i];
+      c[1] = h->ijk[3 * i];
+      c[2] = h->ijk[3 * i + 1];
+      c[3] = h->ijk[3 * i + 2];
+      c[4] = h->sb[i];
+      c[5] = h->se[i];
+      c[6] = h->tb[i];
+      c[7] = h->te[i];
+      c[8] = h->cb[i];
+      c[9] = h->ce[i];
     }
   return HFMM_OK;
+  API_GUARD_END
 }
 
 int hfmm_lists_export(hfmm_tree* tree, double k, int32_t P, int32_t* m2l, int32_t* p2p) {
@@ -589,7 +612,7 @@ int hfmm_lists_export(hfmm_tree* tree, double k, int32_t P, int32_t* m2l, int32_
   if (rc) return rc;
   Tree& t = *reinterpret_cast<Tree*>(tree);
   Plan pl;
-  build_lists_host(t, k, P, pl);
+  build_plan_host(t, k, P, pl);
   for (size_t i = 0; m2l && i < pl.lists.m2l_a.size(); ++i) {
     m2l[2 * i] = pl.lists.m2l_a[i];
     m2l[2 * i + 1] = pl.lists.m2l_b[i];

@@ -35,8 +35,9 @@ void launch_m2l(const int4* chunks, int nchunks, const int4* pairs, const float2
 void launch_l2p(const int32_t* leaves, int nleaves, const int4* cells, const float4* geo,
                 const int32_t* clev, const double* rho, const float4* tpos, float k, int P,
                 const float2* L, float2* ys, hipStream_t s);
-void launch_p2p(const int4* work, int nwork, const int2* ivals, const float4* tpos,
-                const float4* spos, const float2* q, float k, float2* ys, hipStream_t s);
+void launch_p2p(const int4* work, int nwork, const int2* ivals, const int32_t* ivlen_total,
+                const float4* tpos, const float4* spos, const float2* q, float k, float2* ys,
+                hipStream_t s);
 int m2l_chunk_size();
 
 }  // namespace hfmm

@@ -462,50 +462,88 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t* __restrict__ leaves, 
 
 // ---------------------------------------------------------------------------
 // P2P (Listing 1 without the near branch): y_i += sum_j q_j e^{ikR}/(4 pi R),
-// R > 0.  One wave per target leaf; lanes = (target, split), sources staged
-// through LDS 64 at a time; the 1/(4 pi) is folded into k-independent
-// constants.  Deterministic: each target is owned by one wave and the split
-// partial sums are added in a fixed order.
+// R > 0.  One wave per target leaf.  Each lane owns up to two targets and a
+// residue class of sources (lane = target pair + npair * split).  The source
+// stream of the leaf (its merged source intervals) is cut into full tiles of
+// 64; each tile is staged through LDS while the next one is already being
+// loaded into registers.  Coordinates stay unscaled so that the difference of
+// two nearby FP32 points is exact; the phase in revolutions is R k/(2 pi).
+// Deterministic: each target is owned by one wave and the split partial sums
+// are added in a fixed order.
 // ---------------------------------------------------------------------------
+__device__ inline void p2p_fetch(const int2* __restrict__ ivals, int iv, int ie, int off, int lane,
+                                 const float4* __restrict__ spos, const float2* __restrict__ q,
+                                 float4& p, float2& w) {
+  int pos = off + lane, v = iv;
+  while (v < ie) {
+    int2 r = ivals[v];
+    int len = r.y - r.x;
+    if (pos < len) {
+      p = spos[r.x + pos];
+      w = q[r.x + pos];
+      return;
+    }
+    pos -= len;
+    ++v;
+  }
+  p = make_float4(0.f, 0.f, 0.f, 0.f);
+  w = make_float2(0.f, 0.f);
+}
+
 __global__ void __launch_bounds__(256) k_p2p(const int4* __restrict__ work, int nwork,
                                              const int2* __restrict__ ivals,
+                                             const int32_t* __restrict__ ivlen_total,
                                              const float4* __restrict__ tpos,
                                              const float4* __restrict__ spos,
                                              const float2* __restrict__ q, float k,
                                              float2* __restrict__ ys) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int w = blockIdx.x * 4 + wave;
-  __shared__ float4 sp[4][64];
-  __shared__ float2 sq[4][64];
-  __shared__ float2 red[4][64];
+  __shared__ float4 sp[4][2][64];
+  __shared__ float2 sq[4][2][64];
+  __shared__ float4 red[4][64];
   if (w >= nwork) return;
   const int4 wk = work[w];
-  const float krev = k * 0.15915494309189535f;  // k / (2 pi): revolutions per unit length
-  const float inv4pi = 0.07957747154594767f;
+  const int total = ivlen_total[w];
+  const float krev = k * 0.15915494309189535f;  // k / (2 pi)
   for (int t0 = wk.x; t0 < wk.y; t0 += 64) {
     const int tc = min(64, wk.y - t0);
-    const int nsplit = 64 / tc;
-    const int ti = lane % tc, s = lane / tc;
+    const int np = (tc + 1) >> 1;                 // target pairs
+    const int nsplit = 64 / np;
+    const int pi = lane % np, s = lane / np;
     const bool active = s < nsplit;
-    float4 xi = tpos[t0 + ti];
-    float ar = 0.f, ai = 0.f;
-    for (int iv = wk.z; iv < wk.w; ++iv) {
-      const int2 rg = ivals[iv];
-      for (int j0 = rg.x; j0 < rg.y; j0 += 64) {
-        const int nj = min(64, rg.y - j0);
-        __builtin_amdgcn_wave_barrier();
-        if (lane < nj) {
-          sp[wave][lane] = spos[j0 + lane];
-          sq[wave][lane] = q[j0 + lane];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (active) {
-          for (int j = s; j < nj; j += nsplit) {
-            float4 yj = sp[wave][j];
-            float2 qj = sq[wave][j];
-            float dx = xi.x - yj.x, dy = xi.y - yj.y, dz = xi.z - yj.z;
+    const int ia = t0 + 2 * pi, ib = min(ia + 1, t0 + tc - 1);
+    const bool has_b = (2 * pi + 1) < tc;
+    const float4 xa = tpos[ia], xb = tpos[ib];
+    float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
+    // stream cursor (wave-uniform): interval iv, offset off
+    int iv = wk.z, off = 0;
+    float4 np4;
+    float2 nq;
+    p2p_fetch(ivals, iv, wk.w, off, lane, spos, q, np4, nq);
+    for (int base = 0; base < total; base += 64) {
+      const int nj = min(64, total - base);
+      const int buf = (base >> 6) & 1;
+      sp[wave][buf][lane] = np4;
+      sq[wave][buf][lane] = nq;
+      // advance the cursor by 64 and prefetch the next tile
+      off += 64;
+      while (iv < wk.w && off >= ivals[iv].y - ivals[iv].x) {
+        off -= ivals[iv].y - ivals[iv].x;
+        ++iv;
+      }
+      if (base + 64 < total) p2p_fetch(ivals, iv, wk.w, off, lane, spos, q, np4, nq);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (active) {
+        const float4* P = sp[wave][buf];
+        const float2* Q = sq[wave][buf];
+        for (int j = s; j < nj; j += nsplit) {
+          const float4 yj = P[j];
+          const float2 qj = Q[j];
+          {
+            float dx = xa.x - yj.x, dy = xa.y - yj.y, dz = xa.z - yj.z;
             float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             float rinv = (r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
             float rev = r2 * rinv * krev;
@@ -514,26 +552,41 @@ __global__ void __launch_bounds__(256) k_p2p(const int4* __restrict__ work, int 
             ar = fmaf(qj.x, gr, fmaf(-qj.y, gi, ar));
             ai = fmaf(qj.x, gi, fmaf(qj.y, gr, ai));
           }
+          {
+            float dx = xb.x - yj.x, dy = xb.y - yj.y, dz = xb.z - yj.z;
+            float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            float rinv = (r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
+            float rev = r2 * rinv * krev;
+            float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
+            float gr = cs * rinv, gi = sn * rinv;
+            br = fmaf(qj.x, gr, fmaf(-qj.y, gi, br));
+            bi = fmaf(qj.x, gi, fmaf(qj.y, gr, bi));
+          }
         }
       }
+      __builtin_amdgcn_wave_barrier();
     }
     __builtin_amdgcn_wave_barrier();
-    red[wave][lane] = make_float2(ar, ai);
+    red[wave][lane] = make_float4(ar, ai, br, bi);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // lanes 0..tc-1 finalise target t0 + lane: pair lane/2, slot lane&1
     if (lane < tc) {
-      float2 sum = make_float2(0.f, 0.f);
+      const int pp = lane >> 1, slot = lane & 1;
+      float sr = 0.f, si = 0.f;
       for (int ss = 0; ss < nsplit; ++ss) {
-        float2 v = red[wave][lane + ss * tc];
-        sum.x += v.x;
-        sum.y += v.y;
+        float4 v = red[wave][pp + ss * np];
+        sr += slot ? v.z : v.x;
+        si += slot ? v.w : v.y;
       }
+      const float scale = 0.07957747154594767f;  // 1 / (4 pi)
       float2 o = ys[t0 + lane];
-      o.x = fmaf(sum.x, inv4pi, o.x);
-      o.y = fmaf(sum.y, inv4pi, o.y);
+      o.x = fmaf(sr, scale, o.x);
+      o.y = fmaf(si, scale, o.y);
       ys[t0 + lane] = o;
     }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -583,10 +636,11 @@ void launch_l2p(const int32_t* leaves, int nleaves, const int4* cells, const flo
   if (nleaves <= 0) return;
   k_l2p<<<nleaves, 64, 0, s>>>(leaves, nleaves, cells, geo, clev, rho, tpos, k, P, L, ys);
 }
-void launch_p2p(const int4* work, int nwork, const int2* ivals, const float4* tpos,
-                const float4* spos, const float2* q, float k, float2* ys, hipStream_t s) {
+void launch_p2p(const int4* work, int nwork, const int2* ivals, const int32_t* ivlen_total,
+                const float4* tpos, const float4* spos, const float2* q, float k, float2* ys,
+                hipStream_t s) {
   if (nwork <= 0) return;
-  k_p2p<<<(nwork + 3) / 4, 256, 0, s>>>(work, nwork, ivals, tpos, spos, q, k, ys);
+  k_p2p<<<(nwork + 3) / 4, 256, 0, s>>>(work, nwork, ivals, ivlen_total, tpos, spos, q, k, ys);
 }
 
 int m2l_chunk_size() { return kM2LChunk; }

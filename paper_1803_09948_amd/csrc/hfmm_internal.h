@@ -30,6 +30,7 @@ struct HostTree {
   double H = 1.0;
   std::vector<int32_t> src_perm, tgt_perm;     // sorted position -> input index
   std::vector<float> src_xyz, tgt_xyz;         // sorted, 3 floats per body
+  std::vector<uint64_t> skey, tkey;            // sorted Morton keys (tkey empty in point mode)
   // cells, level by level, Morton order within a level
   std::vector<int32_t> level, ijk, sb, se, tb, te, cb, ce, parent;
   std::vector<int32_t> level_off;              // cells of level l: [off[l], off[l+1])
@@ -43,9 +44,13 @@ struct HostTree {
   }
 };
 
-// Builds the tree.  tgt == nullptr: point mode.
+// Sorts the bodies and builds the base cells.  tgt == nullptr: point mode.
 void build_tree(const float* src, int64_t nsrc, const float* tgt, int64_t ntgt,
                 int ncrit, int max_level, HostTree& t);
+// Cells over the sorted bodies of `b` into `t` (which may be `b`): a cell splits
+// when it holds more than ncrit sources, or when it is non-empty and its side
+// exceeds split_side.
+void build_cells(const HostTree& b, int ncrit, int max_level, double split_side, HostTree& t);
 
 struct Lists {
   std::vector<int32_t> m2l_a, m2l_b;  // (target cell, source cell)
@@ -94,31 +99,42 @@ struct DevBuf {
 struct Plan {
   double k = 0;
   int P = 0;
+  HostTree ct;                   // cells of this plan (wavenumber-aware splitting)
   Lists lists;
   int64_t n_tables = 0;          // M2L operators
   int64_t n_ops = 0;             // all operators
   int64_t p2p_body_pairs = 0;
   std::vector<double> rho;       // per level
   std::vector<int32_t> m2m_base, l2l_base;  // per child level: op index of octant 0
+  // device cells
+  DevBuf d_cells;                // int4 (sb, se, tb, te)
+  DevBuf d_geo;                  // float4 (cx, cy, cz, half)
+  DevBuf d_clev;                 // int32 level
+  DevBuf d_topo;                 // int4 (child begin, child end, parent, octant | level << 3)
+  DevBuf d_src_leaves, d_tgt_leaves;
+  int32_t n_src_leaves = 0, n_tgt_leaves = 0;
+  // operators and work lists
   DevBuf d_ops, d_tables;        // OpDesc[n_ops]; float2 [n_ops][P^2 in][P^2 out]
   DevBuf d_rho;                  // double per level
   DevBuf d_m2m_base, d_l2l_base; // int32 per level
   DevBuf d_m2l_chunks;           // int4 (op, pair begin, pair end, 0)
-  DevBuf d_m2l_pairs;            // int4 (target cell, source cell, symmetry, 0)
+  DevBuf d_m2l_pairs;            // int4 (target cell, source cell, symmetry, op)
   int32_t n_m2l_chunks = 0;
   DevBuf d_p2p_work;             // int4 (tgt begin, tgt end, interval begin, interval end)
   DevBuf d_p2p_ivals;            // int2 (src begin, src end)
+  DevBuf d_p2p_total;            // int32 sources per work item
   int32_t n_p2p_work = 0;
   DevBuf d_symdst, d_symph, d_outidx, d_outph;  // int32 [16][P^2]
+  DevBuf d_M, d_L;               // float2 [ncell][P^2]
   // BIE corrections (caller panel order)
   DevBuf d_near_off, d_near_col, d_near_val;    // CSR, float2 values
-  DevBuf d_self;                                // double2: self integral - 3-point self sum
+  DevBuf d_diag;                                // double2: self integral - 3-point self sum
   int64_t n_near = 0;
   int64_t device_bytes = 0;
 };
 
 struct Tree {
-  HostTree h;
+  HostTree h;                   // bodies and base cells
   int ncrit = 64, max_level = 20;
   double theta = 0.5, kappa = -1.0, eta = 2.0;
   int near_levels = 3, near_order = 6;
@@ -127,22 +143,15 @@ struct Tree {
   int64_t npanel = 0;
   std::vector<double> verts;    // nv x 3
   std::vector<int32_t> tris;    // nt x 3
-  // device geometry
+  // device bodies
+  bool uploaded = false;
   DevBuf d_src_pos, d_tgt_pos;  // float4, sorted
   DevBuf d_src_idx;             // int32 per sorted source: caller unknown index
   DevBuf d_src_w;               // float per sorted source (BIE: area/3)
   DevBuf d_tgt_perm;            // int32 per sorted target: caller index
-  DevBuf d_cells;               // int4 (sb, se, tb, te)
-  DevBuf d_geo;                 // float4 (cx, cy, cz, half)
-  DevBuf d_clev;                // int32 level
-  DevBuf d_topo;                // int4 (child begin, child end, parent, octant | level << 3)
-  DevBuf d_src_leaves, d_tgt_leaves;  // int32 leaf lists
-  int32_t n_src_leaves = 0, n_tgt_leaves = 0;
   DevBuf d_panels;              // double [npanel][9] vertex coordinates (BIE)
-  // per-matvec scratch (sized for the largest P used)
-  DevBuf d_q, d_M, d_L, d_ys;
-  int scratchP = 0;
-  int64_t geo_bytes = 0;
+  DevBuf d_q, d_ys;             // float2 per source / target
+  int64_t body_bytes = 0;
   std::map<std::pair<uint64_t, int>, std::unique_ptr<Plan>> plans;
   bool timing = false;
   float phase_ms[8] = {0};
@@ -151,7 +160,9 @@ struct Tree {
   ~Tree();
 };
 
+double kappa_of(const Tree& t, int P);
+int build_plan_host(Tree& t, double k, int P, Plan& pl);   // cells + lists (host only)
 int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out);
-int upload_geometry(Tree& t);
+int upload_bodies(Tree& t);
 
 }  // namespace hfmm

@@ -10,7 +10,9 @@
 //  - keys: floor(((x - c) + H) / (2H) * 2^21) per axis, clamped, interleaved
 //    with x in the lowest bit; stable sort (ties keep input order);
 //  - a cell splits into its non-empty octants when it holds more than ncrit
-//    sources; cells are stored level by level in Morton order;
+//    sources, or (per wavenumber) when it is non-empty and wider than kappa/k,
+//    since such a cell can never take part in M2L; cells are stored level by
+//    level in Morton order;
 //  - acceptance for M2L: 3 (sA + sB)^2 < theta^2 D2 (half-sides and squared
 //    centre distance in units of the finer half-side) and k * side <= kappa
 //    for the larger cell; traversal from (root, root) splits the cell with
@@ -94,17 +96,15 @@ void build_tree(const float* src, int64_t nsrc, const float* tgt, int64_t ntgt, 
   std::vector<uint64_t> skey, tkey;
   keys_of(src, nsrc, t.c, t.H, skey);
   sort_by_key(skey, t.src_perm);
-  std::vector<uint64_t> sk(nsrc);
-  for (int64_t i = 0; i < nsrc; ++i) sk[i] = skey[t.src_perm[i]];
-  std::vector<uint64_t> tk;
+  t.skey.resize(nsrc);
+  for (int64_t i = 0; i < nsrc; ++i) t.skey[i] = skey[t.src_perm[i]];
   if (t.point_mode) {
     t.tgt_perm = t.src_perm;
-    tk = sk;
   } else {
     keys_of(tgt, ntgt, t.c, t.H, tkey);
     sort_by_key(tkey, t.tgt_perm);
-    tk.resize(ntgt);
-    for (int64_t i = 0; i < ntgt; ++i) tk[i] = tkey[t.tgt_perm[i]];
+    t.tkey.resize(ntgt);
+    for (int64_t i = 0; i < ntgt; ++i) t.tkey[i] = tkey[t.tgt_perm[i]];
   }
   t.src_xyz.resize(3 * nsrc);
   for (int64_t i = 0; i < nsrc; ++i)
@@ -116,31 +116,47 @@ void build_tree(const float* src, int64_t nsrc, const float* tgt, int64_t ntgt, 
     for (int64_t i = 0; i < ntgt; ++i)
       for (int d = 0; d < 3; ++d) t.tgt_xyz[3 * i + d] = tgt[3 * (int64_t)t.tgt_perm[i] + d];
   }
-  auto push = [&](int lev, int i, int j, int k, int32_t a, int32_t b, int32_t c0, int32_t d,
+  build_cells(t, ncrit, max_level, INFINITY, t);
+}
+
+void build_cells(const HostTree& b, int ncrit, int max_level, double split_side, HostTree& t) {
+  const std::vector<uint64_t>& sk = b.skey;
+  const std::vector<uint64_t>& tk = b.point_mode ? b.skey : b.tkey;
+  if (&t != &b) {
+    t.point_mode = b.point_mode;
+    t.nsrc = b.nsrc;
+    t.ntgt = b.ntgt;
+    for (int d = 0; d < 3; ++d) t.c[d] = b.c[d];
+    t.H = b.H;
+  }
+  t.ncrit = ncrit;
+  t.level.clear(); t.ijk.clear(); t.sb.clear(); t.se.clear(); t.tb.clear(); t.te.clear();
+  t.cb.clear(); t.ce.clear(); t.parent.clear(); t.level_off.clear();
+  auto push = [&](int lev, int i, int j, int k, int32_t a, int32_t bb, int32_t c0, int32_t d,
                   int32_t par) {
     t.level.push_back(lev);
     t.ijk.push_back(i);
     t.ijk.push_back(j);
     t.ijk.push_back(k);
     t.sb.push_back(a);
-    t.se.push_back(b);
+    t.se.push_back(bb);
     t.tb.push_back(c0);
     t.te.push_back(d);
     t.cb.push_back(0);
     t.ce.push_back(0);
     t.parent.push_back(par);
   };
-  push(0, 0, 0, 0, 0, (int32_t)nsrc, 0, (int32_t)t.ntgt, -1);
-  t.level_off.push_back(0);
+  push(0, 0, 0, 0, 0, (int32_t)t.nsrc, 0, (int32_t)t.ntgt, -1);
   std::vector<int32_t> cur = {0}, nxt;
   int lev = 0;
   while (!cur.empty()) {
-    t.level_off.push_back((int32_t)t.level.size());  // end of level `lev` is set below
-    t.level_off.back() = cur.back() + 1;
     nxt.clear();
+    const double side = 2.0 * t.H / double(1 << lev);
     for (int32_t ci : cur) {
       int32_t ns = t.se[ci] - t.sb[ci];
-      if (ns <= ncrit || lev >= max_level) {
+      int32_t nb = t.point_mode ? ns : ns + (t.te[ci] - t.tb[ci]);
+      bool force = side > split_side && nb >= 1;
+      if ((ns <= ncrit && !force) || lev >= max_level) {
         t.cb[ci] = t.ce[ci] = (int32_t)t.level.size();
         continue;
       }
@@ -167,13 +183,10 @@ void build_tree(const float* src, int64_t nsrc, const float* tgt, int64_t ntgt, 
     cur.swap(nxt);
     ++lev;
   }
-  // level_off: fix to [start of each level] + end
-  std::vector<int32_t> off;
-  off.push_back(0);
+  t.level_off.push_back(0);
   for (int i = 1; i < t.ncell(); ++i)
-    if (t.level[i] != t.level[i - 1]) off.push_back(i);
-  off.push_back(t.ncell());
-  t.level_off = off;
+    if (t.level[i] != t.level[i - 1]) t.level_off.push_back(i);
+  t.level_off.push_back(t.ncell());
 }
 
 static inline bool mac(const HostTree& t, int a, int b, double k, double theta,

@@ -79,7 +79,7 @@ def lib():
             "hfmm_bie_plane_wave": [vp, dbl, vp, vp, vp],
             "hfmm_batch_matvec": [i32, vp, vp, vp, vp, vp, vp],
             "hfmm_tree_stats": [vp, dbl, i32, C.POINTER(Stats)],
-            "hfmm_tree_export": [vp, vp, vp, vp],
+            "hfmm_tree_export": [vp, dbl, i32, vp, vp, vp],
             "hfmm_lists_export": [vp, dbl, i32, vp, vp],
             "hfmm_set_timing": [vp, i32],
             "hfmm_phase_times": [vp, vp],
@@ -194,12 +194,14 @@ class Tree:
         _check(lib().hfmm_tree_stats(self._h, float(k), int(P), C.byref(s)))
         return s.as_dict()
 
-    def export(self):
-        st = self.stats()
+    def export(self, k: float = 1.0, P: int = 0):
+        """(src_perm, tgt_perm, cells) of the base tree (P = 0) or of the tree at (k, P)."""
+        st = self.stats(k, P)
         sp = np.zeros(st["n_src"], np.int32)
         tp = np.zeros(st["n_tgt"], np.int32)
         cells = np.zeros((st["n_cell"], 10), np.int32)
-        _check(lib().hfmm_tree_export(self._h, sp.ctypes.data, tp.ctypes.data, cells.ctypes.data))
+        _check(lib().hfmm_tree_export(self._h, float(k), int(P), sp.ctypes.data, tp.ctypes.data,
+                                      cells.ctypes.data))
         return sp, tp, cells
 
     def lists(self, k: float, P: int):

@@ -45,7 +45,10 @@ def test_lists_equal_oracle(n, k, P, theta):
     x = synth.sphere_points(n, 7)
     t = hfmm.Tree.from_points(x, ncrit=32, theta=theta)
     m2l, p2p = t.lists(k, P)
-    o = build_tree(x, None, 32)
+    o = build_tree(x, None, 32, split_side=0.4 * P / k)
+    _, _, cells = t.export(k, P)
+    ref = np.stack([o.level, o.ijk[:, 0], o.ijk[:, 1], o.ijk[:, 2], o.sb, o.se, o.tb, o.te, o.cb, o.ce], 1)
+    np.testing.assert_array_equal(cells, ref)
     om2l, op2p = dual_tree_traversal(o, k, theta, 0.4 * P)
     assert sorted(map(tuple, m2l.tolist())) == sorted(om2l)
     assert sorted(map(tuple, p2p.tolist())) == sorted(op2p)
