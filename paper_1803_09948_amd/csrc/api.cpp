@@ -257,7 +257,7 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
   });
   std::vector<int4> spairs(npair), chunks;
   for (size_t i = 0; i < npair; ++i) spairs[i] = pairs[order[i]];
-  const int CH = m2l_chunk_size();
+  const int CH = m2l_pairs_per_chunk(P);
   for (size_t i = 0; i < npair;) {
     size_t j = i;
     while (j < npair && spairs[j].w == spairs[i].w && j - i < (size_t)CH) ++j;
@@ -324,7 +324,9 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
   DevBuf d_off, d_lm, d_val;
   if ((rc = upload(d_off, cp.off)) || (rc = upload(d_lm, cp.lm)) || (rc = upload(d_val, cv)))
     return rc;
-  if ((rc = pl.d_tables.alloc((size_t)pl.n_ops * P2 * P2 * sizeof(float2)))) return rc;
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
+  if ((rc = pl.d_tables.alloc((size_t)pl.n_ops * Kp * Rp * sizeof(float2)))) return rc;
   launch_gen_tables(pl.d_ops.as<OpDesc>(), (int)pl.n_ops, P, k, d_off.as<int32_t>(),
                     d_lm.as<int32_t>(), d_val.as<double2>(), pl.d_tables.as<float2>(), s);
   HIP_TRY(hipGetLastError());
@@ -377,10 +379,10 @@ static int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_
     launch_m2m(h.level_off[l], h.level_off[l + 1], pl.d_topo.as<int4>(), pl.d_m2m_base.as<int32_t>(),
                pl.d_tables.as<float2>(), P, pl.d_M.as<float2>(), s);
   if ((rc = mark(2))) return rc;
-  launch_m2l(pl.d_m2l_chunks.as<int4>(), pl.n_m2l_chunks, pl.d_m2l_pairs.as<int4>(),
-             pl.d_tables.as<float2>(), pl.d_symdst.as<int32_t>(), pl.d_symph.as<int32_t>(),
-             pl.d_outidx.as<int32_t>(), pl.d_outph.as<int32_t>(), P, pl.d_M.as<float2>(),
-             pl.d_L.as<float2>(), s);
+  launch_m2l_mfma(pl.d_m2l_chunks.as<int4>(), pl.n_m2l_chunks, pl.d_m2l_pairs.as<int4>(),
+                  pl.d_tables.as<float2>(), P, pl.d_symdst.as<int32_t>(), pl.d_symph.as<int32_t>(),
+                  pl.d_outidx.as<int32_t>(), pl.d_outph.as<int32_t>(), pl.d_M.as<float2>(),
+                  pl.d_L.as<float2>(), s);
   if ((rc = mark(3))) return rc;
   for (int l = 1; l < h.nlevels(); ++l)
     launch_l2l(h.level_off[l], h.level_off[l + 1], pl.d_topo.as<int4>(), pl.d_l2l_base.as<int32_t>(),

@@ -16,6 +16,8 @@ struct OpDescDev {         // translation operator descriptor (48 bytes)
   int32_t pad;
 };
 
+// Padded table dimensions: Kp = 4 ceil(P^2/4) inputs, Rp = 16 ceil(P^2/16) outputs.
+void table_dims(int P, int* Kp, int* Rp);
 void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
                        const int32_t* cp_lm, const double2* cp_val, float2* tables,
                        hipStream_t s);
@@ -39,5 +41,10 @@ void launch_p2p(const int4* work, int nwork, const int2* ivals, const int32_t* i
                 const float4* tpos, const float4* spos, const float2* q, float k, float2* ys,
                 hipStream_t s);
 int m2l_chunk_size();
+// Matrix-core M2L over padded tables [op][Kp][Rp] (see fmm_kernels.hip).
+int m2l_pairs_per_chunk(int P);
+void launch_m2l_mfma(const int4* chunks, int nchunks, const int4* pairs, const float2* tables, int P,
+                     const int32_t* symdst, const int32_t* symph, const int32_t* outidx,
+                     const int32_t* outph, const float2* M, float2* L, hipStream_t s);
 
 }  // namespace hfmm

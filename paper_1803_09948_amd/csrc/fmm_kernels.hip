@@ -102,7 +102,8 @@ __device__ void bessel_j_scaled(int nm, double x, double rho, double* b) {
 // ---------------------------------------------------------------------------
 __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P, double k,
                              const int32_t* __restrict__ cp_off, const int32_t* __restrict__ cp_lm,
-                             const double2* __restrict__ cp_val, float2* __restrict__ tables) {
+                             const double2* __restrict__ cp_val, int Kp, int Rp,
+                             float2* __restrict__ tables) {
   const int o = blockIdx.x;
   if (o >= nops) return;
   const int L = 2 * P - 1;
@@ -167,9 +168,14 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
   }
   __syncthreads();
   const int P2 = P * P;
-  float2* T = tables + (size_t)o * P2 * P2;
-  for (int e = threadIdx.x; e < P2 * P2; e += blockDim.x) {
-    int row = e / P2, col = e % P2;  // row (n',m'), col (n,m)
+  float2* T = tables + (size_t)o * Kp * Rp;
+  for (int f = threadIdx.x; f < Kp * Rp; f += blockDim.x) {
+    const int col = f / Rp, row = f % Rp;  // col (n,m) = input, row (n',m') = output
+    if (col >= P2 || row >= P2) {
+      T[f] = make_float2(0.f, 0.f);
+      continue;
+    }
+    const int e = row * P2 + col;
     int n2 = (int)sqrt((double)row), n = (int)sqrt((double)col);
     double re = 0.0, im = 0.0;
     for (int q = cp_off[e]; q < cp_off[e + 1]; ++q) {
@@ -182,7 +188,7 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
     if (d.kind == 0) sc = sig_in[n] / sig_out[n2];        // M2M
     else if (d.kind == 1) sc = sig_out[n2] / sig_in[n];   // L2L
     else sc = sig_out[n2] * sig_in[n];                    // M2L
-    T[(size_t)col * P2 + row] = make_float2((float)(re * sc), (float)(im * sc));
+    T[f] = make_float2((float)(re * sc), (float)(im * sc));
   }
 }
 
@@ -318,8 +324,8 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t* __restrict__ leaves, 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_m2m(int c0, int c1, const int4* __restrict__ topo,
                                              const int32_t* __restrict__ m2m_base,
-                                             const float2* __restrict__ tables, int P,
-                                             float2* __restrict__ M) {
+                                             const float2* __restrict__ tables, int P, int Kp,
+                                             int Rp, float2* __restrict__ M) {
   const int cell = c0 + blockIdx.x;
   if (cell >= c1) return;
   const int4 tp = topo[cell];  // (child begin, child end, parent, octant | level << 3)
@@ -334,10 +340,10 @@ __global__ void __launch_bounds__(256) k_m2m(int c0, int c1, const int4* __restr
     __syncthreads();
     const int4 tc = topo[ch];
     const int op = m2m_base[tc.w >> 3] + (tc.w & 7);
-    const float2* T = tables + (size_t)op * P2 * P2;
+    const float2* T = tables + (size_t)op * Kp * Rp;
     if (r < P2) {
       float2 s = acc[0];
-      for (int c = 0; c < P2; ++c) s = cfma(T[(size_t)c * P2 + r], sm[c], s);
+      for (int c = 0; c < P2; ++c) s = cfma(T[(size_t)c * Rp + r], sm[c], s);
       acc[0] = s;
     }
   }
@@ -346,8 +352,8 @@ __global__ void __launch_bounds__(256) k_m2m(int c0, int c1, const int4* __restr
 
 __global__ void __launch_bounds__(256) k_l2l(int c0, int c1, const int4* __restrict__ topo,
                                              const int32_t* __restrict__ l2l_base,
-                                             const float2* __restrict__ tables, int P,
-                                             float2* __restrict__ L) {
+                                             const float2* __restrict__ tables, int P, int Kp,
+                                             int Rp, float2* __restrict__ L) {
   const int cell = c0 + blockIdx.x;
   if (cell >= c1) return;
   const int4 tp = topo[cell];
@@ -357,11 +363,11 @@ __global__ void __launch_bounds__(256) k_l2l(int c0, int c1, const int4* __restr
   for (int e = threadIdx.x; e < P2; e += blockDim.x) sl[e] = L[(size_t)parent * P2 + e];
   __syncthreads();
   const int op = l2l_base[tp.w >> 3] + (tp.w & 7);
-  const float2* T = tables + (size_t)op * P2 * P2;
+  const float2* T = tables + (size_t)op * Kp * Rp;
   const int r = threadIdx.x;
   if (r < P2) {
     float2 s = L[(size_t)cell * P2 + r];
-    for (int c = 0; c < P2; ++c) s = cfma(T[(size_t)c * P2 + r], sl[c], s);
+    for (int c = 0; c < P2; ++c) s = cfma(T[(size_t)c * Rp + r], sl[c], s);
     L[(size_t)cell * P2 + r] = s;
   }
 }
@@ -379,8 +385,8 @@ __global__ void __launch_bounds__(256) k_m2l_valu(const int4* __restrict__ chunk
                                                   const int32_t* __restrict__ symdst,
                                                   const int32_t* __restrict__ symph,
                                                   const int32_t* __restrict__ outidx,
-                                                  const int32_t* __restrict__ outph, int P,
-                                                  const float2* __restrict__ M,
+                                                  const int32_t* __restrict__ outph, int P, int Kp,
+                                                  int Rp, const float2* __restrict__ M,
                                                   float2* __restrict__ L) {
   const int4 ch = chunks[blockIdx.x];
   const int op = ch.x, pb = ch.y, np = ch.z - ch.y;
@@ -394,12 +400,12 @@ __global__ void __launch_bounds__(256) k_m2l_valu(const int4* __restrict__ chunk
     B[p][symdst[g * P2 + c]] = mul_ipow(v, symph[g * P2 + c]);
   }
   __syncthreads();
-  const float2* T = tables + (size_t)op * P2 * P2;
+  const float2* T = tables + (size_t)op * Kp * Rp;
   for (int r = threadIdx.x; r < P2; r += blockDim.x) {
     float2 acc[kM2LChunk];
     for (int p = 0; p < kM2LChunk; ++p) acc[p] = make_float2(0.f, 0.f);
     for (int c = 0; c < P2; ++c) {
-      float2 t = T[(size_t)c * P2 + r];
+      float2 t = T[(size_t)c * Rp + r];
 #pragma unroll
       for (int p = 0; p < kM2LChunk; ++p) acc[p] = cfma(t, B[p][c], acc[p]);
     }
@@ -412,6 +418,182 @@ __global__ void __launch_bounds__(256) k_m2l_valu(const int4* __restrict__ chunk
       atomicAdd(&L[(size_t)pr.x * P2 + o].y, v.y);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// M2L on the matrix cores.  One wave takes up to 16*NCT pairs that share one
+// canonical operator T (P^2 x P^2 complex).  The inputs M' = D^T M of the
+// pairs are staged in LDS as the B matrix (k = input coefficient, column =
+// pair); T streams from memory as the A matrix (row = output coefficient);
+// the complex product is four real 16x16x4 FP32 MFMAs per tile and k-step:
+//   Cr += Tr Br - Ti Bi,   Ci += Tr Bi + Ti Br.
+// Outputs are mapped back (L += conj(D) C) and added to L with atomics.
+// Tables are laid out [op][k < Kp][r < Rp] with zero padding, Kp = 4 ceil(P^2/4),
+// Rp = 16 ceil(P^2/16).  Blocks are mapped so that each XCD works through a
+// contiguous range of chunks (chunks are sorted by operator), which keeps an
+// operator's table in that XCD's L2 while its chunks run.
+//
+// MFMA 16x16x4 f32 lane layout: A[i][k] from lane i + 16k, B[k][j] from lane
+// j + 16k, D[4q + v][j] in lane j + 16q, register v.
+// ---------------------------------------------------------------------------
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Image of coefficient (n, m) under the reflection g = (fx, fy, fz, swap):
+// Y_n^m(sigma r) = i^ph Y_n^{m'}(r).  Returns m' and sets ph; the map is an
+// involution on m, so it also gives the inverse needed for the inputs.
+__device__ inline int sym_m(int g, int n, int m, int& ph) {
+  int p = 0;
+  if (g & 1) { p += 2 * (m & 1); m = -m; }
+  if (g & 2) { m = -m; }
+  if (g & 4) { p += 2 * ((n + m) & 1); }
+  if (g & 8) { p += m & 3; m = -m; }
+  ph = p & 3;
+  return m;
+}
+
+template <int RT, int NCT>
+__global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks, int nchunks,
+                                                 int per_xcd, const int4* __restrict__ pairs,
+                                                 const float2* __restrict__ tables, int Kp, int Rp,
+                                                 const int32_t* __restrict__ outidx,
+                                                 const int32_t* __restrict__ outph, int P2,
+                                                 const float2* __restrict__ M,
+                                                 float2* __restrict__ L) {
+  constexpr int NP = 16 * NCT;      // pairs per wave
+  extern __shared__ float2 Cs[];    // [NP][16 RT + 1] output transpose
+  const int b = blockIdx.x;
+  const int chunk = (b & 7) * per_xcd + (b >> 3);
+  if (chunk >= nchunks) return;
+  const int4 ch = chunks[chunk];
+  const int op = ch.x, pb = ch.y, np = ch.z - ch.y;
+  const int lane = threadIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
+  // this lane's B columns: pair 16 t + li
+  int src[NCT], gs[NCT];
+#pragma unroll
+  for (int t = 0; t < NCT; ++t) {
+    const int p = 16 * t + li;
+    if (p < np) {
+      const int4 pr = pairs[pb + p];
+      src[t] = pr.y;
+      gs[t] = pr.z;
+    } else {
+      src[t] = -1;
+      gs[t] = 0;
+    }
+  }
+  // B[k][p] = (D^T M_src)[k] = i^ph(c) M_src[c] with c the image of k under g
+  auto load_b = [&](int k, float2* out) {
+    const int n = (int)sqrtf((float)k + 0.5f);
+    const int m = k - n * n - n;
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) {
+      float2 v = make_float2(0.f, 0.f);
+      if (k < P2 && src[t] >= 0) {
+        int ph0, ph1;
+        const int mc = sym_m(gs[t], n, m, ph0);       // c = (n, mc)
+        sym_m(gs[t], n, mc, ph1);                     // phase of c under g
+        v = mul_ipow(M[(size_t)src[t] * P2 + n * n + n + mc], ph1);
+      }
+      out[t] = v;
+    }
+  };
+  floatx4 cr[NCT][RT], ci[NCT][RT];
+#pragma unroll
+  for (int t = 0; t < NCT; ++t)
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      cr[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+      ci[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  const float2* T = tables + (size_t)op * Kp * Rp;
+  const int KS = Kp >> 2;
+  float2 a[RT], an[RT], bv[NCT], bn[NCT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) a[r] = T[(size_t)lk * Rp + 16 * r + li];
+  load_b(lk, bv);
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = 4 * ks + lk;
+    if (ks + 1 < KS) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) an[r] = T[(size_t)(k + 4) * Rp + 16 * r + li];
+      load_b(k + 4, bn);
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const float ar = a[r].x, ai = a[r].y, nai = -a[r].y;
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) {
+        cr[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bv[t].x, cr[t][r], 0, 0, 0);
+        cr[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bv[t].y, cr[t][r], 0, 0, 0);
+        ci[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bv[t].y, ci[t][r], 0, 0, 0);
+        ci[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bv[t].x, ci[t][r], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) a[r] = an[r];
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) bv[t] = bn[t];
+  }
+  // transpose C through LDS, then add each pair's outputs to its target with
+  // atomics over that target's contiguous coefficient range
+  constexpr int CS = 16 * RT + 1;
+#pragma unroll
+  for (int t = 0; t < NCT; ++t)
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Cs[(16 * t + li) * CS + 16 * r + 4 * lk + v] = make_float2(cr[t][r][v], ci[t][r][v]);
+  __syncthreads();
+  for (int p = 0; p < np; ++p) {
+    const int4 pr = pairs[pb + p];
+    const int g = pr.z;
+    float2* Lt = L + (size_t)pr.x * P2;
+    for (int row = lane; row < P2; row += 64) {
+      const int o = outidx[g * P2 + row];
+      const float2 val = mul_ipow(Cs[p * CS + row], outph[g * P2 + row]);
+      atomicAdd(&Lt[o].x, val.x);
+      atomicAdd(&Lt[o].y, val.y);
+    }
+  }
+}
+
+template <int RT, int NCT>
+static void launch_m2l_mfma_t(const int4* chunks, int nchunks, const int4* pairs, const float2* tables,
+                              int Kp, int Rp, const int32_t* symdst, const int32_t* symph,
+                              const int32_t* outidx, const int32_t* outph, int P2, const float2* M,
+                              float2* L, hipStream_t s) {
+  const int per = (nchunks + 7) / 8;
+  const size_t lds = (size_t)(16 * NCT) * (16 * RT + 1) * sizeof(float2);
+  k_m2l_mfma<RT, NCT><<<8 * per, 64, lds, s>>>(chunks, nchunks, per, pairs, tables, Kp, Rp, outidx,
+                                                outph, P2, M, L);
+}
+
+int m2l_pairs_per_chunk(int P) { return P * P > 240 ? 16 : 32; }
+
+void launch_m2l_mfma(const int4* chunks, int nchunks, const int4* pairs, const float2* tables, int P,
+                     const int32_t* symdst, const int32_t* symph, const int32_t* outidx,
+                     const int32_t* outph, const float2* M, float2* L, hipStream_t s) {
+  if (nchunks <= 0) return;
+  const int P2 = P * P, Kp = 4 * ((P2 + 3) / 4), Rp = 16 * ((P2 + 15) / 16);
+  const int RT = Rp / 16;
+#define M2L_CASE(R)                                                                                 \
+  case R:                                                                                           \
+    if (P2 > 240)                                                                                   \
+      launch_m2l_mfma_t<R, 1>(chunks, nchunks, pairs, tables, Kp, Rp, symdst, symph, outidx, outph, \
+                              P2, M, L, s);                                                         \
+    else                                                                                            \
+      launch_m2l_mfma_t<R, 2>(chunks, nchunks, pairs, tables, Kp, Rp, symdst, symph, outidx, outph, \
+                              P2, M, L, s);                                                         \
+    break;
+  switch (RT) {
+    M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6) M2L_CASE(7) M2L_CASE(8)
+    M2L_CASE(9) M2L_CASE(10) M2L_CASE(11) M2L_CASE(12) M2L_CASE(13) M2L_CASE(14) M2L_CASE(15)
+    M2L_CASE(16)
+    default: break;
+  }
+#undef M2L_CASE
 }
 
 // ---------------------------------------------------------------------------
@@ -593,11 +775,17 @@ __global__ void __launch_bounds__(256) k_p2p(const int4* __restrict__ work, int 
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
+void table_dims(int P, int* Kp, int* Rp) {
+  *Kp = 4 * ((P * P + 3) / 4);
+  *Rp = 16 * ((P * P + 15) / 16);
+}
 void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
                        const int32_t* cp_lm, const double2* cp_val, float2* tables,
                        hipStream_t s) {
   if (nops <= 0) return;
-  k_gen_tables<<<nops, 256, 0, s>>>(ops, nops, P, k, cp_off, cp_lm, cp_val, tables);
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
+  k_gen_tables<<<nops, 256, 0, s>>>(ops, nops, P, k, cp_off, cp_lm, cp_val, Kp, Rp, tables);
 }
 void launch_gather(int64_t n, const int32_t* idx, const float* w, const float2* x, float2* q,
                    hipStream_t s) {
@@ -617,18 +805,25 @@ void launch_p2m(const int32_t* leaves, int nleaves, const int4* cells, const flo
 void launch_m2m(int c0, int c1, const int4* topo, const int32_t* base, const float2* tables,
                 int P, float2* M, hipStream_t s) {
   if (c1 <= c0) return;
-  k_m2m<<<c1 - c0, 256, 0, s>>>(c0, c1, topo, base, tables, P, M);
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
+  k_m2m<<<c1 - c0, 256, 0, s>>>(c0, c1, topo, base, tables, P, Kp, Rp, M);
 }
 void launch_l2l(int c0, int c1, const int4* topo, const int32_t* base, const float2* tables,
                 int P, float2* L, hipStream_t s) {
   if (c1 <= c0) return;
-  k_l2l<<<c1 - c0, 256, 0, s>>>(c0, c1, topo, base, tables, P, L);
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
+  k_l2l<<<c1 - c0, 256, 0, s>>>(c0, c1, topo, base, tables, P, Kp, Rp, L);
 }
 void launch_m2l(const int4* chunks, int nchunks, const int4* pairs, const float2* tables,
                 const int32_t* symdst, const int32_t* symph, const int32_t* outidx,
                 const int32_t* outph, int P, const float2* M, float2* L, hipStream_t s) {
   if (nchunks <= 0) return;
-  k_m2l_valu<<<nchunks, 256, 0, s>>>(chunks, pairs, tables, symdst, symph, outidx, outph, P, M, L);
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
+  k_m2l_valu<<<nchunks, 256, 0, s>>>(chunks, pairs, tables, symdst, symph, outidx, outph, P, Kp, Rp,
+                                     M, L);
 }
 void launch_l2p(const int32_t* leaves, int nleaves, const int4* cells, const float4* geo,
                 const int32_t* clev, const double* rho, const float4* tpos, float k, int P,
