@@ -6,6 +6,7 @@
 #include <numeric>
 #include <unordered_map>
 
+#include "bie_kernels.h"
 #include "hfmm_internal.h"
 
 namespace hfmm {
@@ -340,12 +341,14 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
                     &pl.d_m2l_pairs, &pl.d_p2p_work, &pl.d_p2p_ivals, &pl.d_p2p_total, &pl.d_symdst,
                     &pl.d_symph, &pl.d_outidx, &pl.d_outph, &pl.d_M, &pl.d_L})
     pl.device_bytes += (int64_t)b->bytes;
+  if (t.bie && (rc = prepare_bie(t, pl, s))) return rc;
+  pl.device_bytes += (int64_t)(pl.d_near_val.bytes + pl.d_diag.bytes);
   t.plans[key] = std::move(plp);
   *out = t.plans[key].get();
   return HFMM_OK;
 }
 
-static int check_kP(double k, int P) {
+int check_kP(double k, int P) {
   if (!(k > 0.0) || !std::isfinite(k)) {
     set_error("k must be positive and finite");
     return HFMM_EINVAL;
@@ -357,7 +360,7 @@ static int check_kP(double k, int P) {
   return HFMM_OK;
 }
 
-static int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_t s) {
+int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_t s) {
   const HostTree& h = pl.ct;
   const int P = pl.P, P2 = P * P;
   const float kf = (float)pl.k;
@@ -398,7 +401,6 @@ static int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_
   if ((rc = mark(6))) return rc;
   launch_scatter(h.ntgt, t.d_tgt_perm.as<int32_t>(), t.d_ys.as<float2>(), y, s);
   if ((rc = mark(7))) return rc;
-  if ((rc = mark(8))) return rc;
   HIP_TRY(hipGetLastError());
   return HFMM_OK;
 }
@@ -502,14 +504,23 @@ int hfmm_matvec(hfmm_tree* tree, double k, int32_t P, const void* x, void* y, vo
     t.ev_made = true;
   }
   if ((rc = matvec_impl(t, *pl, (const float2*)x, (float2*)y, s))) return rc;
+  if (t.bie) {
+    launch_near_apply(t.npanel, t.d_near_off.as<int32_t>(), t.d_near_col.as<int32_t>(),
+                      pl->d_near_val.as<float2>(), pl->d_diag.as<double2>(), (const float2*)x, (float2*)y, s);
+    HIP_TRY(hipGetLastError());
+  }
+  if (t.timing) HIP_TRY(hipEventRecord(t.ev[8], s));
   if (t.timing) {
     HIP_TRY(hipEventSynchronize(t.ev[8]));
     float ms;
-    // phases: P2M (0-1), M2M (1-2), M2L (2-3), L2L (3-4), L2P (4-5), P2P (5-6), BIE (6-7)
-    for (int i = 0; i < 7; ++i) {
+    // phases: P2M (0-1), M2M (1-2), M2L (2-3), L2L (3-4), L2P (4-5), P2P (5-6),
+    // output scatter and BIE corrections (6-8)
+    for (int i = 0; i < 6; ++i) {
       HIP_TRY(hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]));
       t.phase_ms[i] = ms;
     }
+    HIP_TRY(hipEventElapsedTime(&ms, t.ev[6], t.ev[8]));
+    t.phase_ms[6] = ms;
     HIP_TRY(hipEventElapsedTime(&ms, t.ev[0], t.ev[8]));
     t.phase_ms[7] = ms;
   }

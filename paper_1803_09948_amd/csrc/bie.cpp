@@ -1,0 +1,405 @@
+// Boundary-integral handles, near/self corrections and the FP64 GMRES driver.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "bie_kernels.h"
+#include "hfmm_internal.h"
+
+namespace hfmm {
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                \
+      return HFMM_EHIP;                                                            \
+    }                                                                              \
+  } while (0)
+
+// Gauss-Legendre nodes and weights mapped to [0, 1] (Newton on P_n).
+static void gl01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int j = 2; j <= n; ++j) {
+      double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // half of the [-1,1] weight
+  }
+}
+
+constexpr int kSelfOrder = 10;
+
+// Near pattern: j != i with |c_i - c_j| < eta h_j, by a uniform grid hash of
+// the centroids with cell size eta * max h.  Rows in caller order, columns
+// ascending.
+static void near_pattern(const std::vector<double>& cen, const std::vector<double>& h, double eta,
+                         std::vector<int32_t>& off, std::vector<int32_t>& col) {
+  const int64_t n = (int64_t)h.size();
+  double hmax = 0.0, lo[3] = {INFINITY, INFINITY, INFINITY};
+  for (int64_t i = 0; i < n; ++i) {
+    hmax = std::max(hmax, h[i]);
+    for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], cen[3 * i + d]);
+  }
+  const double cs = std::max(eta * hmax, 1e-300);
+  auto cell = [&](int64_t i, int d) { return (int64_t)std::floor((cen[3 * i + d] - lo[d]) / cs); };
+  auto key = [](int64_t a, int64_t b, int64_t c) { return (a << 42) ^ (b << 21) ^ c; };
+  std::unordered_map<int64_t, std::vector<int32_t>> grid;
+  grid.reserve((size_t)n);
+  for (int64_t i = 0; i < n; ++i) grid[key(cell(i, 0), cell(i, 1), cell(i, 2))].push_back((int32_t)i);
+  off.assign(n + 1, 0);
+  col.clear();
+  std::vector<int32_t> row;
+  for (int64_t i = 0; i < n; ++i) {
+    row.clear();
+    int64_t ci = cell(i, 0), cj = cell(i, 1), ck = cell(i, 2);
+    for (int64_t a = ci - 1; a <= ci + 1; ++a)
+      for (int64_t b = cj - 1; b <= cj + 1; ++b)
+        for (int64_t c = ck - 1; c <= ck + 1; ++c) {
+          auto it = grid.find(key(a, b, c));
+          if (it == grid.end()) continue;
+          for (int32_t j : it->second) {
+            if (j == i) continue;
+            double d2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+              double t = cen[3 * i + d] - cen[3 * (int64_t)j + d];
+              d2 += t * t;
+            }
+            if (std::sqrt(d2) < eta * h[j]) row.push_back(j);
+          }
+        }
+    std::sort(row.begin(), row.end());
+    col.insert(col.end(), row.begin(), row.end());
+    off[i + 1] = (int32_t)col.size();
+  }
+}
+
+int prepare_bie(Tree& t, Plan& pl, hipStream_t s) {
+  int rc;
+  const int64_t n = t.npanel;
+  if (!t.d_near_off.p) {
+    std::vector<int32_t> rows(t.near_col.size());
+    for (int64_t i = 0; i < n; ++i)
+      for (int q = t.near_off[i]; q < t.near_off[i + 1]; ++q) rows[q] = (int32_t)i;
+    std::vector<double> panels(9 * n);
+    for (int64_t i = 0; i < n; ++i)
+      for (int v = 0; v < 3; ++v)
+        for (int d = 0; d < 3; ++d) panels[9 * i + 3 * v + d] = t.verts[3 * (int64_t)t.tris[3 * i + v] + d];
+    std::vector<double> gx, gw, sx, sw;
+    gl01(t.near_order, gx, gw);
+    gl01(kSelfOrder, sx, sw);
+    std::vector<double> gl;
+    gl.insert(gl.end(), gx.begin(), gx.end());
+    gl.insert(gl.end(), gw.begin(), gw.end());
+    gl.insert(gl.end(), sx.begin(), sx.end());
+    gl.insert(gl.end(), sw.begin(), sw.end());
+    if ((rc = upload_vec(t.d_near_off, t.near_off)) || (rc = upload_vec(t.d_near_col, t.near_col)) ||
+        (rc = upload_vec(t.d_near_row, rows)) || (rc = upload_vec(t.d_gl, gl)))
+      return rc;
+    if (!t.d_panels.p && (rc = upload_vec(t.d_panels, panels))) return rc;
+  }
+  const int ng = t.near_order;
+  const double* gl = t.d_gl.as<double>();
+  pl.n_near = (int64_t)t.near_col.size();
+  if ((rc = pl.d_near_val.alloc(std::max<size_t>(1, t.near_col.size()) * sizeof(float2))) ||
+      (rc = pl.d_diag.alloc((size_t)n * sizeof(double2))))
+    return rc;
+  launch_near(pl.n_near, t.d_near_row.as<int32_t>(), t.d_near_col.as<int32_t>(), t.d_panels.as<double>(),
+              pl.k, t.near_levels, gl, gl + ng, ng, pl.d_near_val.as<float2>(), s);
+  launch_self(n, t.d_panels.as<double>(), pl.k, gl + 2 * ng, gl + 2 * ng + kSelfOrder, kSelfOrder,
+              pl.d_diag.as<double2>(), s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return HFMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(m) in FP64 with two passes of classical Gram-Schmidt (CGS2) and
+// complex Givens rotations; the FMM product in FP32, the self term in FP64.
+// ---------------------------------------------------------------------------
+static int gm_workspace(Tree& t, int m) {
+  if (t.gm_m == m && t.g_V.p) return HFMM_OK;
+  const size_t n = (size_t)t.npanel;
+  int rc;
+  if ((rc = t.g_V.alloc((size_t)(m + 1) * n * sizeof(double2))) || (rc = t.g_w.alloc(n * sizeof(double2))) ||
+      (rc = t.g_r.alloc(n * sizeof(double2))) || (rc = t.g_x64.alloc(n * sizeof(float2))) ||
+      (rc = t.g_y64.alloc(n * sizeof(float2))) || (rc = t.g_H.alloc((size_t)(m + 1) * m * sizeof(double2))) ||
+      (rc = t.g_cs.alloc((size_t)m * sizeof(double))) || (rc = t.g_sn.alloc((size_t)m * sizeof(double2))) ||
+      (rc = t.g_g.alloc((size_t)(m + 1) * sizeof(double2))) || (rc = t.g_h.alloc((size_t)(m + 32) * sizeof(double2))) ||
+      (rc = t.g_h2.alloc((size_t)(m + 32) * sizeof(double2))) ||
+      (rc = t.g_part.alloc((size_t)mdot_blocks() * 32 * sizeof(double2))) ||
+      (rc = t.g_dot.alloc(sizeof(double2))) || (rc = t.g_st.alloc(2 * sizeof(double))) ||
+      (rc = t.g_yv.alloc((size_t)(m + 1) * sizeof(double2))))
+    return rc;
+  t.gm_m = m;
+  return HFMM_OK;
+}
+
+// out = A v (FP64 in/out; FMM and near corrections in FP32, self term in FP64)
+static int apply_A(Tree& t, Plan& pl, const double2* v, double2* out, hipStream_t s) {
+  const int64_t n = t.npanel;
+  launch_to_c64(n, v, t.g_x64.as<float2>(), s);
+  int rc = matvec_impl(t, pl, t.g_x64.as<float2>(), t.g_y64.as<float2>(), s);
+  if (rc) return rc;
+  launch_near_apply(n, t.d_near_off.as<int32_t>(), t.d_near_col.as<int32_t>(), pl.d_near_val.as<float2>(),
+                    nullptr, t.g_x64.as<float2>(), t.g_y64.as<float2>(), s);
+  launch_from_c64_diag(n, t.g_y64.as<float2>(), pl.d_diag.as<double2>(), v, out, s);
+  HIP_TRY(hipGetLastError());
+  return HFMM_OK;
+}
+
+// h[0..nv) (+)= V^H w in chunks of 32
+static void mdot_all(int64_t n, int nv, const double2* V, const double2* w, double2* part, double2* h,
+                     int accumulate, hipStream_t s) {
+  for (int c = 0; c < nv; c += 32)
+    launch_mdot(n, std::min(32, nv - c), V + (size_t)c * n, n, w, part, h + c, accumulate, s);
+}
+
+static int read_doubles(const void* dev, double* host, int cnt, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(host, dev, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return HFMM_OK;
+}
+
+static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, int m, int maxit,
+                 hfmm_gmres_info* info, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = t.npanel;
+  int rc = gm_workspace(t, m);
+  if (rc) return rc;
+  double2* V = t.g_V.as<double2>();
+  double2* w = t.g_w.as<double2>();
+  double2* r = t.g_r.as<double2>();
+  double2* h = t.g_h.as<double2>();
+  double2* h2 = t.g_h2.as<double2>();
+  double2* part = t.g_part.as<double2>();
+  double2* dotv = t.g_dot.as<double2>();
+  double hv[2];
+  // ||b||
+  launch_mdot(n, 1, b, n, b, part, dotv, 0, s);
+  if ((rc = read_doubles(dotv, hv, 1, s))) return rc;
+  const double bnorm = std::sqrt(hv[0]);
+  hfmm_gmres_info inf{};
+  if (bnorm == 0.0) {
+    HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double2), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) *info = inf;
+    return HFMM_OK;
+  }
+  int iters = 0, restarts = 0;
+  double est = INFINITY;
+  int status = HFMM_ENOTCONV;
+  for (;;) {
+    // true residual r = b - A x
+    if ((rc = apply_A(t, pl, x, r, s))) return rc;
+    launch_residual(n, b, r, s);
+    launch_mdot(n, 1, r, n, r, part, dotv, 0, s);
+    if ((rc = read_doubles(dotv, hv, 1, s))) return rc;
+    const double beta = std::sqrt(hv[0]);
+    inf.resid_true = beta / bnorm;
+    if (!std::isfinite(beta)) {
+      set_error("GMRES residual is not finite");
+      return HFMM_EINTERNAL;
+    }
+    if (beta / bnorm <= tol) {
+      status = HFMM_OK;
+      break;
+    }
+    if (iters >= maxit) break;
+    launch_scale_by_norm(n, r, dotv, V, s);
+    launch_init_g(m, dotv, t.g_g.as<double2>(), s);
+    int done = 0;
+    for (int j = 0; j < m; ++j) {
+      double2* vj = V + (size_t)j * n;
+      if ((rc = apply_A(t, pl, vj, w, s))) return rc;
+      // CGS2: two passes of classical Gram-Schmidt against V[0..j]
+      mdot_all(n, j + 1, V, w, part, h, 0, s);
+      launch_mupdate(n, j + 1, V, n, h, w, -1.0, s);
+      mdot_all(n, j + 1, V, w, part, h2, 0, s);
+      launch_mupdate(n, j + 1, V, n, h2, w, -1.0, s);
+      launch_vec_add(j + 1, h2, h, s);  // h += h2
+      launch_mdot(n, 1, w, n, w, part, dotv, 0, s);
+      launch_givens(j, m, h, dotv, t.g_H.as<double2>(), t.g_cs.as<double>(), t.g_sn.as<double2>(),
+                    t.g_g.as<double2>(), t.g_st.as<double>(), s);
+      launch_scale_by_norm(n, w, dotv, V + (size_t)(j + 1) * n, s);
+      HIP_TRY(hipGetLastError());
+      ++iters;
+      done = j + 1;
+      if ((rc = read_doubles(t.g_st.p, hv, 2, s))) return rc;
+      est = hv[0] / bnorm;
+      if (!std::isfinite(est)) {
+        set_error("GMRES Arnoldi residual estimate is not finite");
+        return HFMM_EINTERNAL;
+      }
+      if (est <= tol || iters >= maxit || hv[1] == 0.0) break;
+    }
+    launch_backsolve(done, m, t.g_H.as<double2>(), t.g_g.as<double2>(), t.g_yv.as<double2>(), s);
+    launch_mupdate(n, done, V, n, t.g_yv.as<double2>(), x, 1.0, s);
+    HIP_TRY(hipGetLastError());
+    ++restarts;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  inf.iters = iters;
+  inf.restarts = restarts;
+  inf.resid_est = est;
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return status;
+}
+
+}  // namespace hfmm
+
+using namespace hfmm;
+
+extern "C" {
+
+int hfmm_build_bie(const double* verts, int64_t nv, const int32_t* tris, int64_t nt, const hfmm_opts* opts,
+                   hfmm_tree** out) {
+  try {
+    if (!out) return set_error("out is NULL"), HFMM_EINVAL;
+    *out = nullptr;
+    if (!verts || !tris || nv < 3 || nt < 1 || nt > (int64_t(1) << 28))
+      return set_error("need nv >= 3 vertices and 1 <= nt <= 2^28 triangles"), HFMM_EINVAL;
+    for (int64_t i = 0; i < 3 * nv; ++i)
+      if (!std::isfinite(verts[i])) return set_error("non-finite vertex"), HFMM_EINVAL;
+    for (int64_t i = 0; i < 3 * nt; ++i)
+      if (tris[i] < 0 || tris[i] >= nv) return set_error("triangle index out of range"), HFMM_EINVAL;
+    hfmm_opts d;
+    hfmm_default_opts(&d);
+    const hfmm_opts* o = opts ? opts : &d;
+    if (o->ncrit < 1 || !(o->theta > 0) || !(o->eta > 0) || o->max_level < 0 || o->max_level > kMaxLevel ||
+        o->near_levels < 0 || o->near_levels > 5 || o->near_order < 1 || o->near_order > 16)
+      return set_error("invalid options"), HFMM_EINVAL;
+    auto t = std::make_unique<Tree>();
+    t->ncrit = o->ncrit;
+    t->max_level = o->max_level;
+    t->theta = o->theta;
+    t->kappa = o->kappa;
+    t->eta = o->eta;
+    t->near_levels = o->near_levels;
+    t->near_order = o->near_order;
+    t->bie = true;
+    t->npanel = nt;
+    t->verts.assign(verts, verts + 3 * nv);
+    t->tris.assign(tris, tris + 3 * nt);
+    // panel geometry in FP64: centroids, longest edges, 3 interior Gauss points
+    std::vector<double> cen(3 * nt), h(nt);
+    std::vector<float> src(9 * nt), tgt(3 * nt);
+    const double w1 = 2.0 / 3.0, w2 = 1.0 / 6.0;
+    for (int64_t i = 0; i < nt; ++i) {
+      double P[3][3];
+      for (int v = 0; v < 3; ++v)
+        for (int dd = 0; dd < 3; ++dd) P[v][dd] = verts[3 * (int64_t)tris[3 * i + v] + dd];
+      double e[3] = {0, 0, 0}, cr[3];
+      double u[3], ww[3];
+      for (int dd = 0; dd < 3; ++dd) {
+        u[dd] = P[1][dd] - P[0][dd];
+        ww[dd] = P[2][dd] - P[0][dd];
+      }
+      cr[0] = u[1] * ww[2] - u[2] * ww[1];
+      cr[1] = u[2] * ww[0] - u[0] * ww[2];
+      cr[2] = u[0] * ww[1] - u[1] * ww[0];
+      if (cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2] == 0.0)
+        return set_error("degenerate triangle"), HFMM_EINVAL;
+      for (int dd = 0; dd < 3; ++dd) {
+        e[0] += (P[1][dd] - P[0][dd]) * (P[1][dd] - P[0][dd]);
+        e[1] += (P[2][dd] - P[1][dd]) * (P[2][dd] - P[1][dd]);
+        e[2] += (P[0][dd] - P[2][dd]) * (P[0][dd] - P[2][dd]);
+      }
+      h[i] = std::sqrt(std::max(e[0], std::max(e[1], e[2])));
+      for (int dd = 0; dd < 3; ++dd) {
+        cen[3 * i + dd] = (P[0][dd] + P[1][dd] + P[2][dd]) / 3.0;
+        tgt[3 * i + dd] = (float)cen[3 * i + dd];
+        src[9 * i + 0 + dd] = (float)(w1 * P[0][dd] + w2 * P[1][dd] + w2 * P[2][dd]);
+        src[9 * i + 3 + dd] = (float)(w2 * P[0][dd] + w1 * P[1][dd] + w2 * P[2][dd]);
+        src[9 * i + 6 + dd] = (float)(w2 * P[0][dd] + w2 * P[1][dd] + w1 * P[2][dd]);
+      }
+    }
+    build_tree(src.data(), 3 * nt, tgt.data(), nt, t->ncrit, t->max_level, t->h);
+    near_pattern(cen, h, t->eta, t->near_off, t->near_col);
+    *out = reinterpret_cast<hfmm_tree*>(t.release());
+    return HFMM_OK;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return HFMM_ENOMEM;
+  } catch (...) {
+    set_error("internal error");
+    return HFMM_EINTERNAL;
+  }
+}
+
+int hfmm_bie_plane_wave(hfmm_tree* tree, double k, const double* dir, void* b, void* stream) {
+  try {
+    if (!tree || !dir || !b) return set_error("NULL argument"), HFMM_EINVAL;
+    Tree& t = *reinterpret_cast<Tree*>(tree);
+    if (!t.bie) return set_error("not a BIE handle"), HFMM_EINVAL;
+    if (!std::isfinite(k)) return set_error("k must be finite"), HFMM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (!t.d_panels.p) {
+      std::vector<double> panels(9 * t.npanel);
+      for (int64_t i = 0; i < t.npanel; ++i)
+        for (int v = 0; v < 3; ++v)
+          for (int d = 0; d < 3; ++d) panels[9 * i + 3 * v + d] = t.verts[3 * (int64_t)t.tris[3 * i + v] + d];
+      int rc = upload_vec(t.d_panels, panels);
+      if (rc) return rc;
+    }
+    launch_plane_wave(t.npanel, t.d_panels.as<double>(), k, dir, (double2*)b, s);
+    HIP_TRY(hipGetLastError());
+    return HFMM_OK;
+  } catch (...) {
+    set_error("internal error");
+    return HFMM_EINTERNAL;
+  }
+}
+
+int hfmm_gmres_solve(hfmm_tree* tree, double k, int32_t P, const void* b, void* x, double tol,
+                     int32_t restart, int32_t maxit, hfmm_gmres_info* info, void* stream) {
+  try {
+    if (!tree || !b || !x) return set_error("NULL argument"), HFMM_EINVAL;
+    Tree& t = *reinterpret_cast<Tree*>(tree);
+    if (!t.bie) return set_error("GMRES needs a BIE handle"), HFMM_EINVAL;
+    int rc = check_kP(k, P);
+    if (rc) return rc;
+    if (!(tol > 0.0) || restart < 1 || restart > 200 || maxit < 1)
+      return set_error("need tol > 0, 1 <= restart <= 200, maxit >= 1"), HFMM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Plan* pl;
+    if ((rc = prepare(t, k, P, s, &pl))) return rc;
+    return gmres(t, *pl, (const double2*)b, (double2*)x, tol, restart, maxit, info, s);
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return HFMM_ENOMEM;
+  } catch (...) {
+    set_error("internal error");
+    return HFMM_EINTERNAL;
+  }
+}
+
+int hfmm_batch_matvec(int32_t, hfmm_tree* const*, const double*, const int32_t*, const void* const*,
+                      void* const*, void*) {
+  set_error("not implemented");
+  return HFMM_EINTERNAL;
+}
+
+}  // extern "C"

@@ -126,8 +126,8 @@ struct Plan {
   int32_t n_p2p_work = 0;
   DevBuf d_symdst, d_symph, d_outidx, d_outph;  // int32 [16][P^2]
   DevBuf d_M, d_L;               // float2 [ncell][P^2]
-  // BIE corrections (caller panel order)
-  DevBuf d_near_off, d_near_col, d_near_val;    // CSR, float2 values
+  // BIE corrections (caller panel order; pattern in the Tree)
+  DevBuf d_near_val;                            // float2 per near nonzero
   DevBuf d_diag;                                // double2: self integral - 3-point self sum
   int64_t n_near = 0;
   int64_t device_bytes = 0;
@@ -150,6 +150,13 @@ struct Tree {
   DevBuf d_src_w;               // float per sorted source (BIE: area/3)
   DevBuf d_tgt_perm;            // int32 per sorted target: caller index
   DevBuf d_panels;              // double [npanel][9] vertex coordinates (BIE)
+  // BIE near pattern (geometry only), caller panel order
+  std::vector<int32_t> near_off, near_col;
+  DevBuf d_near_off, d_near_row, d_near_col;
+  DevBuf d_gl;                  // Gauss-Legendre nodes/weights on [0,1]: near (n), self (10)
+  // GMRES workspace (kept between solves)
+  int gm_m = 0;
+  DevBuf g_V, g_w, g_r, g_x64, g_y64, g_H, g_cs, g_sn, g_g, g_h, g_h2, g_part, g_dot, g_st, g_yv;
   DevBuf d_q, d_ys;             // float2 per source / target
   int64_t body_bytes = 0;
   std::map<std::pair<uint64_t, int>, std::unique_ptr<Plan>> plans;
@@ -163,6 +170,19 @@ struct Tree {
 double kappa_of(const Tree& t, int P);
 int build_plan_host(Tree& t, double k, int P, Plan& pl);   // cells + lists (host only)
 int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out);
+int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_t s);
+int prepare_bie(Tree& t, Plan& pl, hipStream_t s);
+int check_kP(double k, int P);
+template <class T>
+int upload_vec(DevBuf& b, const std::vector<T>& v) {
+  int rc = b.alloc(v.size() * sizeof(T));
+  if (rc) return rc;
+  if (!v.empty() && hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("hipMemcpy upload failed");
+    return HFMM_EHIP;
+  }
+  return HFMM_OK;
+}
 int upload_bodies(Tree& t);
 
 }  // namespace hfmm

@@ -1,0 +1,120 @@
+"""GPU parity of the boundary-integral path against the FP64 oracle: the
+collocation matvec (FMM + near + self corrections), the plane-wave right-hand
+side, the FP64 GMRES solve and the Mie series."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bie, gmres, mie
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1803_09948_amd import hfmm  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("s,k", [(2, 3.0), (3, 2 * math.pi), (3, 6.0)])
+def test_bie_matvec_vs_dense_oracle(s, k):
+    V, T = synth.icosphere(s)
+    print(f"case subdiv={s} k={k}", flush=True)
+    A = bie.dense_matrix(k, V, T)
+    q = synth.strengths(len(T), 40 + s)
+    t = hfmm.Tree.from_mesh(V, T)
+    y = t.matvec(k, 10, torch.from_numpy(q).to("cuda")).cpu().numpy()
+    e = rel(y, A @ q.astype(np.complex128))
+    print("  bie matvec vs dense", e)
+    assert e <= 1e-5
+
+
+def test_plane_wave_rhs():
+    V, T = synth.icosphere(3)
+    t = hfmm.Tree.from_mesh(V, T)
+    b = t.plane_wave(2.5).cpu().numpy()
+    np.testing.assert_allclose(b, bie.plane_wave_rhs(2.5, V, T), rtol=0, atol=1e-14)
+    b = t.plane_wave(2.5, (1.0, 0.0, 0.0)).cpu().numpy()
+    np.testing.assert_allclose(b, bie.plane_wave_rhs(2.5, V, T, (1.0, 0.0, 0.0)), rtol=0, atol=1e-14)
+
+
+def test_gmres_vs_dense_solve():
+    s, k = 3, 6.0
+    V, T = synth.icosphere(s)
+    A = bie.dense_matrix(k, V, T)
+    b = bie.plane_wave_rhs(k, V, T)
+    qd = np.linalg.solve(A, b)
+    _, oinfo = gmres.gmres(lambda v: A @ v, b, tol=1e-4, restart=30)
+    t = hfmm.Tree.from_mesh(V, T)
+    x, info = t.gmres(k, 10, torch.from_numpy(b).to("cuda"), tol=1e-4, restart=30)
+    x = x.cpu().numpy()
+    print("gpu", info, "oracle iters", oinfo["iters"])
+    assert info["converged"] and info["resid_true"] <= 1e-4
+    assert rel(x, qd) <= 1e-3
+    assert abs(info["iters"] - oinfo["iters"]) <= max(2, 0.1 * oinfo["iters"])
+    # true residual against the dense matrix
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 2e-4
+
+
+def test_mie_error_falls_with_refinement():
+    k = 3.0
+    th = np.radians(np.arange(0, 181, 2))
+    xo = 4.0 * np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
+    um = mie.scattered(k, 1.0, 4.0, th)
+    errs = []
+    for s in (2, 3, 4):
+        V, T = synth.icosphere(s)
+        t = hfmm.Tree.from_mesh(V, T)
+        b = t.plane_wave(k)
+        x, info = t.gmres(k, 10, b, tol=1e-6, restart=30)
+        assert info["converged"]
+        us = bie.scattered_field(k, V, T, x.cpu().numpy(), xo)
+        errs.append(rel(us, um))
+    print("u_s errors vs Mie", errs)
+    assert errs[1] < 0.6 * errs[0] and errs[2] < 0.6 * errs[1]
+
+
+def test_icosphere5_resonant_solve_and_mie():
+    """Subdivision 5 (20480 panels), k = 2 pi (an interior resonance of the
+    sphere: the n = 0 density mode is free, the scattered field is not)."""
+    s, k = 5, 2 * math.pi
+    V, T = synth.icosphere(s)
+    t = hfmm.Tree.from_mesh(V, T)
+    b = t.plane_wave(k)
+    x, info = t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=2000)
+    print("ico5 k=2pi", info)
+    assert info["converged"] and info["resid_true"] <= 1e-4
+    xq = x.cpu().numpy()
+    # sampled rows of the dense oracle matrix: A x = b there up to the tolerance
+    rows = np.random.default_rng(5).choice(len(T), 64, replace=False)
+    Ar = bie.dense_matrix(k, V, T, rows=rows)
+    bo = bie.plane_wave_rhs(k, V, T)[rows]
+    assert np.linalg.norm(Ar @ xq - bo) / np.linalg.norm(bo) <= 5e-4
+    th = np.radians(np.arange(0, 181, 1))
+    xo = 4.0 * np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
+    e = rel(bie.scattered_field(k, V, T, xq, xo), mie.scattered(k, 1.0, 4.0, th))
+    print("u_s error vs Mie at r=4:", e)
+    assert e < 0.02
+
+
+def test_gmres_errors_and_nonconvergence():
+    V, T = synth.icosphere(2)
+    t = hfmm.Tree.from_mesh(V, T)
+    b = t.plane_wave(3.0)
+    with pytest.raises(hfmm.HfmmError) as ei:
+        t.gmres(3.0, 10, b, tol=0.0)
+    assert ei.value.code == hfmm.HFMM_EINVAL
+    with pytest.raises(hfmm.HfmmError):
+        t.gmres(3.0, 10, b, restart=0)
+    x, info = t.gmres(3.0, 10, b, tol=1e-12, restart=5, maxit=3)
+    assert not info["converged"] and info["iters"] == 3
+    assert np.all(np.isfinite(x.cpu().numpy()))
+    pt = hfmm.Tree.from_points(synth.sphere_points(100, 1))
+    with pytest.raises(hfmm.HfmmError):
+        pt.gmres(3.0, 10, b[:100].clone())
+    # zero right-hand side: x = 0 without iterations
+    x, info = t.gmres(3.0, 10, torch.zeros_like(b))
+    assert info["converged"] and info["iters"] == 0 and float(x.abs().max()) == 0.0

@@ -72,3 +72,29 @@ def test_invalid_arguments():
         with pytest.raises(hfmm.HfmmError) as e:
             t.prepare(k, P, stream=0)
         assert e.value.code == hfmm.HFMM_EINVAL
+
+
+def test_bie_tree_equals_oracle():
+    from oracle import bie
+    V, T = synth.icosphere(3)
+    t = hfmm.Tree.from_mesh(V, T, ncrit=32)
+    pan = bie.panels(V, T)
+    src, _ = bie.gauss_sources(pan)
+    o = build_tree(src.astype(np.float32), pan["centroid"].astype(np.float32), 32)
+    sp, tp, cells = t.export()
+    np.testing.assert_array_equal(sp, o.src_perm)
+    np.testing.assert_array_equal(tp, o.tgt_perm)
+    ref = np.stack([o.level, o.ijk[:, 0], o.ijk[:, 1], o.ijk[:, 2], o.sb, o.se, o.tb, o.te, o.cb, o.ce], 1)
+    np.testing.assert_array_equal(cells, ref)
+
+
+def test_bie_invalid_mesh():
+    V, T = synth.icosphere(1)
+    bad = T.copy()
+    bad[0, 0] = len(V)
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.Tree.from_mesh(V, bad)
+    deg = T.copy()
+    deg[0] = [0, 0, 1]
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.Tree.from_mesh(V, deg)
