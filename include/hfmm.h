@@ -136,11 +136,15 @@ int hfmm_bie_plane_wave(hfmm_tree* tree, double k, const double* dir_host,
                         void* b_dev, void* stream);
 
 /* One fused launch sequence for `count` independent point-mode products
- * y_i = A_i x_i (each with its own tree, k and P).  Work of all instances is
- * concatenated into shared work queues, so uneven instances fill the chip.
- * Results equal those of hfmm_matvec on each instance alone, bit for bit.
+ * y_i = A_i x_i (each with its own tree and k; one P for all).  The work
+ * lists of all instances are concatenated, so each phase (and each tree
+ * level) is a single launch over every instance and uneven instances fill
+ * the chip together; the sequence is captured once as a HIP graph (per set of
+ * trees, k and P) and replayed on later calls.  Each result equals
+ * hfmm_matvec on that instance alone up to the order of the FP32 atomic
+ * additions in M2L (relative differences of order 1e-7).
  * trees, ks, Ps, xs_dev, ys_dev: arrays of length count.  EINVAL as for
- * hfmm_matvec, or count < 1. */
+ * hfmm_matvec, count < 1, differing P, or a BIE handle. */
 int hfmm_batch_matvec(int32_t count, hfmm_tree* const* trees, const double* ks,
                       const int32_t* Ps, const void* const* xs_dev,
                       void* const* ys_dev, void* stream);

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <atomic>
 #include <unordered_map>
 
 #include "bie_kernels.h"
@@ -13,6 +14,9 @@ namespace hfmm {
 
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
+
+static std::atomic<uint64_t> g_uid{1};
+uint64_t next_uid() { return g_uid.fetch_add(1); }
 
 #define HIP_TRY(expr)                                                              \
   do {                                                                             \
@@ -119,11 +123,8 @@ static int upload_cells(Plan& pl) {
   }
   int rc;
   if ((rc = upload(pl.d_cells, cells)) || (rc = upload(pl.d_geo, geo)) || (rc = upload(pl.d_clev, clev)) ||
-      (rc = upload(pl.d_topo, topo)) || (rc = upload(pl.d_src_leaves, sl)) ||
-      (rc = upload(pl.d_tgt_leaves, tl)))
+      (rc = upload(pl.d_topo, topo)))
     return rc;
-  pl.n_src_leaves = (int32_t)sl.size();
-  pl.n_tgt_leaves = (int32_t)tl.size();
   return HFMM_OK;
 }
 
@@ -266,6 +267,25 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
     i = j;
   }
   pl.n_m2l_chunks = (int32_t)chunks.size();
+  pl.m2l_chunks_h = chunks;
+  // per-cell operator indices and per-level work lists
+  std::vector<int2> cops(h.ncell(), make_int2(0, 0));
+  pl.m2m_cells.assign(nlev, {});
+  pl.l2l_cells.assign(nlev, {});
+  for (int i = 0; i < h.ncell(); ++i) {
+    const int l = h.level[i];
+    if (l >= 1) {
+      int oct = (h.ijk[3 * i] & 1) | ((h.ijk[3 * i + 1] & 1) << 1) | ((h.ijk[3 * i + 2] & 1) << 2);
+      cops[i] = make_int2(pl.m2m_base[l] + oct, pl.l2l_base[l] + oct);
+      pl.l2l_cells[l].push_back(i);
+    }
+    if (!h.leaf(i)) pl.m2m_cells[l].push_back(i);
+    else {
+      if (h.se[i] > h.sb[i]) pl.src_leaves.push_back(i);
+      if (h.te[i] > h.tb[i]) pl.tgt_leaves.push_back(i);
+    }
+  }
+  if ((rc = upload(pl.d_cops, cops))) return rc;
   // P2P work: per target leaf, merged source intervals
   std::vector<int4> work;
   std::vector<int2> ivals;
@@ -311,11 +331,9 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
     }
   // upload
   if ((rc = upload(pl.d_ops, ops)) || (rc = upload(pl.d_rho, pl.rho)) ||
-      (rc = upload(pl.d_m2m_base, pl.m2m_base)) || (rc = upload(pl.d_l2l_base, pl.l2l_base)) ||
-      (rc = upload(pl.d_m2l_chunks, chunks)) || (rc = upload(pl.d_m2l_pairs, spairs)) ||
+      (rc = upload(pl.d_m2l_pairs, spairs)) ||
       (rc = upload(pl.d_p2p_work, work)) || (rc = upload(pl.d_p2p_ivals, ivals)) ||
       (rc = upload(pl.d_p2p_total, totals)) ||
-      (rc = upload(pl.d_symdst, sdst)) || (rc = upload(pl.d_symph, sph)) ||
       (rc = upload(pl.d_outidx, oidx)) || (rc = upload(pl.d_outph, oph)))
     return rc;
   // coupling coefficients and tables
@@ -336,10 +354,9 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
       (rc = pl.d_L.alloc((size_t)h.ncell() * P2 * sizeof(float2))))
     return rc;
   pl.device_bytes = 0;
-  for (DevBuf* b : {&pl.d_cells, &pl.d_geo, &pl.d_clev, &pl.d_topo, &pl.d_src_leaves, &pl.d_tgt_leaves,
-                    &pl.d_ops, &pl.d_tables, &pl.d_rho, &pl.d_m2m_base, &pl.d_l2l_base, &pl.d_m2l_chunks,
-                    &pl.d_m2l_pairs, &pl.d_p2p_work, &pl.d_p2p_ivals, &pl.d_p2p_total, &pl.d_symdst,
-                    &pl.d_symph, &pl.d_outidx, &pl.d_outph, &pl.d_M, &pl.d_L})
+  for (DevBuf* b : {&pl.d_cells, &pl.d_geo, &pl.d_clev, &pl.d_topo, &pl.d_ops, &pl.d_tables, &pl.d_rho,
+                    &pl.d_m2l_pairs, &pl.d_p2p_work, &pl.d_p2p_ivals, &pl.d_p2p_total, &pl.d_outidx,
+                    &pl.d_outph, &pl.d_M, &pl.d_L, &pl.d_cops})
     pl.device_bytes += (int64_t)b->bytes;
   if (t.bie && (rc = prepare_bie(t, pl, s))) return rc;
   pl.device_bytes += (int64_t)(pl.d_near_val.bytes + pl.d_diag.bytes);
@@ -361,48 +378,17 @@ int check_kP(double k, int P) {
 }
 
 int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_t s) {
-  const HostTree& h = pl.ct;
-  const int P = pl.P, P2 = P * P;
-  const float kf = (float)pl.k;
-  auto mark = [&](int i) -> int {
-    if (t.timing) HIP_TRY(hipEventRecord(t.ev[i], s));
-    return HFMM_OK;
-  };
-  int rc;
-  if ((rc = mark(0))) return rc;
-  HIP_TRY(hipMemsetAsync(pl.d_M.p, 0, (size_t)h.ncell() * P2 * sizeof(float2), s));
-  HIP_TRY(hipMemsetAsync(pl.d_L.p, 0, (size_t)h.ncell() * P2 * sizeof(float2), s));
-  launch_gather(h.nsrc, t.d_src_idx.as<int32_t>(), t.bie ? t.d_src_w.as<float>() : nullptr, x,
-                t.d_q.as<float2>(), s);
-  launch_p2m(pl.d_src_leaves.as<int32_t>(), pl.n_src_leaves, pl.d_cells.as<int4>(), pl.d_geo.as<float4>(),
-             pl.d_clev.as<int32_t>(), pl.d_rho.as<double>(), t.d_src_pos.as<float4>(),
-             t.d_q.as<float2>(), kf, P, pl.d_M.as<float2>(), s);
-  if ((rc = mark(1))) return rc;
-  for (int l = h.nlevels() - 2; l >= 0; --l)
-    launch_m2m(h.level_off[l], h.level_off[l + 1], pl.d_topo.as<int4>(), pl.d_m2m_base.as<int32_t>(),
-               pl.d_tables.as<float2>(), P, pl.d_M.as<float2>(), s);
-  if ((rc = mark(2))) return rc;
-  launch_m2l_mfma(pl.d_m2l_chunks.as<int4>(), pl.n_m2l_chunks, pl.d_m2l_pairs.as<int4>(),
-                  pl.d_tables.as<float2>(), P, pl.d_symdst.as<int32_t>(), pl.d_symph.as<int32_t>(),
-                  pl.d_outidx.as<int32_t>(), pl.d_outph.as<int32_t>(), pl.d_M.as<float2>(),
-                  pl.d_L.as<float2>(), s);
-  if ((rc = mark(3))) return rc;
-  for (int l = 1; l < h.nlevels(); ++l)
-    launch_l2l(h.level_off[l], h.level_off[l + 1], pl.d_topo.as<int4>(), pl.d_l2l_base.as<int32_t>(),
-               pl.d_tables.as<float2>(), P, pl.d_L.as<float2>(), s);
-  if ((rc = mark(4))) return rc;
-  launch_l2p(pl.d_tgt_leaves.as<int32_t>(), pl.n_tgt_leaves, pl.d_cells.as<int4>(), pl.d_geo.as<float4>(),
-             pl.d_clev.as<int32_t>(), pl.d_rho.as<double>(), t.d_tgt_pos.as<float4>(), kf, P,
-             pl.d_L.as<float2>(), t.d_ys.as<float2>(), s);
-  if ((rc = mark(5))) return rc;
-  launch_p2p(pl.d_p2p_work.as<int4>(), pl.n_p2p_work, pl.d_p2p_ivals.as<int2>(),
-             pl.d_p2p_total.as<int32_t>(), t.d_tgt_pos.as<float4>(), t.d_src_pos.as<float4>(),
-             t.d_q.as<float2>(), kf, t.d_ys.as<float2>(), s);
-  if ((rc = mark(6))) return rc;
-  launch_scatter(h.ntgt, t.d_tgt_perm.as<int32_t>(), t.d_ys.as<float2>(), y, s);
-  if ((rc = mark(7))) return rc;
-  HIP_TRY(hipGetLastError());
-  return HFMM_OK;
+  if (!pl.self) {
+    pl.self = std::make_unique<Batch>();
+    int rc = build_batch({&t}, {&pl}, *pl.self);
+    if (rc) {
+      pl.self.reset();
+      return rc;
+    }
+  }
+  const float2* xs[1] = {x};
+  float2* ys[1] = {y};
+  return run_batch(*pl.self, xs, ys, s, false, t.timing ? &t : nullptr);
 }
 
 }  // namespace hfmm
@@ -474,6 +460,7 @@ int hfmm_build_tree(const float* xyz, int64_t n, const hfmm_opts* opts, hfmm_tre
   int rc = apply_opts(*t, opts);
   if (rc) return rc;
   build_tree(xyz, n, nullptr, 0, t->ncrit, t->max_level, t->h);
+  t->uid = next_uid();
   *out = reinterpret_cast<hfmm_tree*>(t.release());
   return HFMM_OK;
   API_GUARD_END
@@ -638,7 +625,11 @@ int hfmm_lists_export(hfmm_tree* tree, double k, int32_t P, int32_t* m2l, int32_
   API_GUARD_END
 }
 
-void hfmm_tree_free(hfmm_tree* tree) { delete reinterpret_cast<Tree*>(tree); }
+void hfmm_tree_free(hfmm_tree* tree) {
+  if (!tree) return;
+  forget_tree_batches(reinterpret_cast<Tree*>(tree)->uid);
+  delete reinterpret_cast<Tree*>(tree);
+}
 
 }  // extern "C"
 

@@ -1,0 +1,263 @@
+// Fused execution of FMM matvecs over one or many instances.
+//
+// Every kernel is instance-aware: a work item names its instance, whose
+// pointers come from a device table.  A batch therefore only concatenates the
+// per-instance work lists (cells, M2L chunks, P2P work); tables, bodies and
+// expansions stay where each instance's plan put them.  The whole sequence is
+// one launch per phase and level for all instances together, and can be
+// captured once as a hipGraph and replayed.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "hfmm_internal.h"
+
+namespace hfmm {
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                \
+      return HFMM_EHIP;                                                            \
+    }                                                                              \
+  } while (0)
+
+Batch::~Batch() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (ev_in) (void)hipEventDestroy(ev_in);
+  if (ev_out) (void)hipEventDestroy(ev_out);
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+static InstDev make_inst(Tree& t, Plan& pl) {
+  InstDev I{};
+  I.spos = t.d_src_pos.as<float4>();
+  I.tpos = t.d_tgt_pos.as<float4>();
+  I.src_idx = t.d_src_idx.as<int32_t>();
+  I.src_w = t.bie ? t.d_src_w.as<float>() : nullptr;
+  I.tgt_perm = t.d_tgt_perm.as<int32_t>();
+  I.q = t.d_q.as<float2>();
+  I.ys = t.d_ys.as<float2>();
+  I.cells = pl.d_cells.as<int4>();
+  I.geo = pl.d_geo.as<float4>();
+  I.clev = pl.d_clev.as<int32_t>();
+  I.topo = pl.d_topo.as<int4>();
+  I.cops = pl.d_cops.as<int2>();
+  I.rho = pl.d_rho.as<double>();
+  I.tables = pl.d_tables.as<float2>();
+  I.M = pl.d_M.as<float2>();
+  I.L = pl.d_L.as<float2>();
+  I.m2l_pairs = pl.d_m2l_pairs.as<int4>();
+  I.p2p_work = pl.d_p2p_work.as<int4>();
+  I.p2p_ivals = pl.d_p2p_ivals.as<int2>();
+  I.p2p_total = pl.d_p2p_total.as<int32_t>();
+  I.nsrc = pl.ct.nsrc;
+  I.ntgt = pl.ct.ntgt;
+  I.ncellP2 = (int64_t)pl.ct.ncell() * pl.P * pl.P;
+  I.k = (float)pl.k;
+  return I;
+}
+
+template <class T>
+static int up(DevBuf& b, const std::vector<T>& v) {
+  return upload_vec(b, v);
+}
+
+int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans, Batch& b) {
+  b.count = (int)trees.size();
+  b.P = plans[0]->P;
+  b.trees = trees;
+  b.plans = plans;
+  b.hinst.clear();
+  const int ch = elem_chunk();
+  std::vector<int2> zero, gather, scatter, p2m, l2p, p2p;
+  std::vector<int4> m2l;
+  b.maxlev = 0;
+  for (int i = 0; i < b.count; ++i) {
+    Plan& pl = *plans[i];
+    b.hinst.push_back(make_inst(*trees[i], pl));
+    b.maxlev = std::max(b.maxlev, pl.ct.nlevels());
+    const InstDev& I = b.hinst.back();
+    for (int64_t e = 0; e * ch < I.ncellP2; ++e) zero.push_back(make_int2(i, (int)e));
+    for (int64_t e = 0; e * ch < I.nsrc; ++e) gather.push_back(make_int2(i, (int)e));
+    for (int64_t e = 0; e * ch < I.ntgt; ++e) scatter.push_back(make_int2(i, (int)e));
+    for (int c : pl.src_leaves) p2m.push_back(make_int2(i, c));
+    for (int c : pl.tgt_leaves) l2p.push_back(make_int2(i, c));
+    for (int w = 0; w < pl.n_p2p_work; ++w) p2p.push_back(make_int2(i, w));
+    for (const int4& c : pl.m2l_chunks_h) m2l.push_back(make_int4(i, c.x, c.y, c.z));
+  }
+  // per-level M2M (parents, deepest first) and L2L (children, root first) lists
+  std::vector<int2> m2m, l2l;
+  b.m2m_off.assign(b.maxlev + 1, 0);
+  b.l2l_off.assign(b.maxlev + 1, 0);
+  for (int l = 0; l < b.maxlev; ++l) {
+    b.m2m_off[l] = (int)m2m.size();
+    b.l2l_off[l] = (int)l2l.size();
+    for (int i = 0; i < b.count; ++i) {
+      Plan& pl = *plans[i];
+      if (l < (int)pl.m2m_cells.size())
+        for (int c : pl.m2m_cells[l]) m2m.push_back(make_int2(i, c));
+      if (l < (int)pl.l2l_cells.size())
+        for (int c : pl.l2l_cells[l]) l2l.push_back(make_int2(i, c));
+    }
+  }
+  b.m2m_off[b.maxlev] = (int)m2m.size();
+  b.l2l_off[b.maxlev] = (int)l2l.size();
+  int rc;
+  if ((rc = up(b.d_inst, b.hinst)) || (rc = up(b.d_zero, zero)) || (rc = up(b.d_gather, gather)) ||
+      (rc = up(b.d_scatter, scatter)) || (rc = up(b.d_p2m, p2m)) || (rc = up(b.d_l2p, l2p)) ||
+      (rc = up(b.d_p2p, p2p)) || (rc = up(b.d_m2l, m2l)) || (rc = up(b.d_m2m, m2m)) || (rc = up(b.d_l2l, l2l)))
+    return rc;
+  b.n_zero = (int)zero.size();
+  b.n_gather = (int)gather.size();
+  b.n_scatter = (int)scatter.size();
+  b.n_p2m = (int)p2m.size();
+  b.n_l2p = (int)l2p.size();
+  b.n_p2p = (int)p2p.size();
+  b.n_m2l = (int)m2l.size();
+  return HFMM_OK;
+}
+
+// The fused sequence: zero, gather, P2M, M2M (levels up), M2L, L2L (levels
+// down), L2P, P2P, scatter.  Events are recorded only when `ev` is given.
+static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
+  const InstDev* I = b.d_inst.as<InstDev>();
+  const int P = b.P;
+  const Plan& p0 = *b.plans[0];
+  auto mark = [&](int i) -> int {
+    if (ev) HIP_TRY(hipEventRecord(ev[i], s));
+    return HFMM_OK;
+  };
+  int rc;
+  if ((rc = mark(0))) return rc;
+  launch_zero(b.d_zero.as<int2>(), b.n_zero, I, s);
+  launch_gather(b.d_gather.as<int2>(), b.n_gather, I, s);
+  launch_p2m(b.d_p2m.as<int2>(), b.n_p2m, I, P, s);
+  if ((rc = mark(1))) return rc;
+  for (int l = b.maxlev - 2; l >= 0; --l)
+    launch_m2m(b.d_m2m.as<int2>() + b.m2m_off[l], b.m2m_off[l + 1] - b.m2m_off[l], I, P, s);
+  if ((rc = mark(2))) return rc;
+  launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, P, p0.d_outidx.as<int32_t>(), p0.d_outph.as<int32_t>(), s);
+  if ((rc = mark(3))) return rc;
+  for (int l = 1; l < b.maxlev; ++l)
+    launch_l2l(b.d_l2l.as<int2>() + b.l2l_off[l], b.l2l_off[l + 1] - b.l2l_off[l], I, P, s);
+  if ((rc = mark(4))) return rc;
+  launch_l2p(b.d_l2p.as<int2>(), b.n_l2p, I, P, s);
+  if ((rc = mark(5))) return rc;
+  launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, s);
+  if ((rc = mark(6))) return rc;
+  launch_scatter(b.d_scatter.as<int2>(), b.n_scatter, I, s);
+  if ((rc = mark(7))) return rc;
+  HIP_TRY(hipGetLastError());
+  return HFMM_OK;
+}
+
+int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t s, bool use_graph,
+              Tree* timing) {
+  for (int base = 0; base < b.count; base += 64) {
+    XYPtrs p{};
+    const int n = std::min(64, b.count - base);
+    for (int i = 0; i < n; ++i) {
+      p.x[i] = xs[base + i];
+      p.y[i] = ys[base + i];
+    }
+    launch_set_xy(n, base, p, b.d_inst.as<InstDev>(), s);
+  }
+  HIP_TRY(hipGetLastError());
+  if (!use_graph) return sequence(b, s, timing ? timing->ev : nullptr);
+  if (!b.stream) {
+    HIP_TRY(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&b.ev_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&b.ev_out, hipEventDisableTiming));
+  }
+  if (!b.exec) {
+    HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
+    int rc = sequence(b, b.stream, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b.stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) {
+      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      return HFMM_EHIP;
+    }
+    b.graph = g;
+    HIP_TRY(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipEventRecord(b.ev_in, s));
+  HIP_TRY(hipStreamWaitEvent(b.stream, b.ev_in, 0));
+  HIP_TRY(hipGraphLaunch(b.exec, b.stream));
+  HIP_TRY(hipEventRecord(b.ev_out, b.stream));
+  HIP_TRY(hipStreamWaitEvent(s, b.ev_out, 0));
+  return HFMM_OK;
+}
+
+// Batches built by hfmm_batch_matvec, keyed by the instances' (uid, k, P).
+static std::mutex g_batch_mu;
+static std::map<std::vector<uint64_t>, std::unique_ptr<Batch>> g_batches;
+
+void forget_tree_batches(uint64_t uid) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (auto it = g_batches.begin(); it != g_batches.end();) {
+    bool uses = false;
+    for (size_t i = 0; i < it->first.size(); i += 3) uses |= it->first[i] == uid;
+    it = uses ? g_batches.erase(it) : std::next(it);
+  }
+}
+
+}  // namespace hfmm
+
+using namespace hfmm;
+
+extern "C" int hfmm_batch_matvec(int32_t count, hfmm_tree* const* trees, const double* ks, const int32_t* Ps,
+                                 const void* const* xs, void* const* ys, void* stream) {
+  try {
+    if (count < 1 || !trees || !ks || !Ps || !xs || !ys) return set_error("bad batch arguments"), HFMM_EINVAL;
+    std::vector<uint64_t> key;
+    for (int i = 0; i < count; ++i) {
+      if (!trees[i] || !xs[i] || !ys[i]) return set_error("NULL instance argument"), HFMM_EINVAL;
+      if (xs[i] == ys[i]) return set_error("x and y must not alias"), HFMM_EINVAL;
+      int rc = check_kP(ks[i], Ps[i]);
+      if (rc) return rc;
+      if (Ps[i] != Ps[0]) return set_error("all instances of a batch need the same P"), HFMM_EINVAL;
+      Tree& t = *reinterpret_cast<Tree*>(trees[i]);
+      if (t.bie) return set_error("batched products take point-mode handles"), HFMM_EINVAL;
+      uint64_t kb;
+      std::memcpy(&kb, &ks[i], 8);
+      key.push_back(t.uid);
+      key.push_back(kb);
+      key.push_back((uint64_t)Ps[i]);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto it = g_batches.find(key);
+    if (it == g_batches.end()) {
+      std::vector<Tree*> tv;
+      std::vector<Plan*> pv;
+      for (int i = 0; i < count; ++i) {
+        Tree& t = *reinterpret_cast<Tree*>(trees[i]);
+        Plan* pl;
+        int rc = prepare(t, ks[i], Ps[i], s, &pl);
+        if (rc) return rc;
+        tv.push_back(&t);
+        pv.push_back(pl);
+      }
+      auto b = std::make_unique<Batch>();
+      int rc = build_batch(tv, pv, *b);
+      if (rc) return rc;
+      it = g_batches.emplace(key, std::move(b)).first;
+    }
+    return run_batch(*it->second, (const float2* const*)xs, (float2* const*)ys, s, true, nullptr);
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return HFMM_ENOMEM;
+  } catch (...) {
+    set_error("internal error");
+    return HFMM_EINTERNAL;
+  }
+}

@@ -337,6 +337,7 @@ int hfmm_build_bie(const double* verts, int64_t nv, const int32_t* tris, int64_t
       }
     }
     build_tree(src.data(), 3 * nt, tgt.data(), nt, t->ncrit, t->max_level, t->h);
+    t->uid = next_uid();
     near_pattern(cen, h, t->eta, t->near_off, t->near_col);
     *out = reinterpret_cast<hfmm_tree*>(t.release());
     return HFMM_OK;
@@ -394,12 +395,6 @@ int hfmm_gmres_solve(hfmm_tree* tree, double k, int32_t P, const void* b, void* 
     set_error("internal error");
     return HFMM_EINTERNAL;
   }
-}
-
-int hfmm_batch_matvec(int32_t, hfmm_tree* const*, const double*, const int32_t*, const void* const*,
-                      void* const*, void*) {
-  set_error("not implemented");
-  return HFMM_EINTERNAL;
 }
 
 }  // extern "C"

@@ -21,30 +21,53 @@ void table_dims(int P, int* Kp, int* Rp);
 void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
                        const int32_t* cp_lm, const double2* cp_val, float2* tables,
                        hipStream_t s);
-void launch_gather(int64_t n, const int32_t* idx, const float* w, const float2* x, float2* q,
-                   hipStream_t s);
-void launch_scatter(int64_t n, const int32_t* perm, const float2* ys, float2* y, hipStream_t s);
-void launch_p2m(const int32_t* leaves, int nleaves, const int4* cells, const float4* geo,
-                const int32_t* clev, const double* rho, const float4* spos, const float2* q,
-                float k, int P, float2* M, hipStream_t s);
-void launch_m2m(int c0, int c1, const int4* topo, const int32_t* base, const float2* tables,
-                int P, float2* M, hipStream_t s);
-void launch_l2l(int c0, int c1, const int4* topo, const int32_t* base, const float2* tables,
-                int P, float2* L, hipStream_t s);
-void launch_m2l(const int4* chunks, int nchunks, const int4* pairs, const float2* tables,
-                const int32_t* symdst, const int32_t* symph, const int32_t* outidx,
-                const int32_t* outph, int P, const float2* M, float2* L, hipStream_t s);
-void launch_l2p(const int32_t* leaves, int nleaves, const int4* cells, const float4* geo,
-                const int32_t* clev, const double* rho, const float4* tpos, float k, int P,
-                const float2* L, float2* ys, hipStream_t s);
-void launch_p2p(const int4* work, int nwork, const int2* ivals, const int32_t* ivlen_total,
-                const float4* tpos, const float4* spos, const float2* q, float k, float2* ys,
-                hipStream_t s);
-int m2l_chunk_size();
-// Matrix-core M2L over padded tables [op][Kp][Rp] (see fmm_kernels.hip).
+// Pointers of one problem instance, read by every instance-aware kernel.
+struct InstDev {
+  const float4* spos;       // sorted sources (x, y, z, -)
+  const float4* tpos;       // sorted targets
+  const int32_t* src_idx;   // sorted source -> caller unknown
+  const float* src_w;       // source weights or NULL
+  const int32_t* tgt_perm;  // sorted target -> caller index
+  const float2* x;          // caller input (set per call)
+  float2* y;                // caller output (set per call)
+  float2* q;                // sorted source strengths
+  float2* ys;               // sorted outputs
+  const int4* cells;        // (sb, se, tb, te)
+  const float4* geo;        // (cx, cy, cz, half)
+  const int32_t* clev;      // level
+  const int4* topo;         // (child begin, child end, parent, octant | level << 3)
+  const int2* cops;         // per cell: (M2M op as child, L2L op as child)
+  const double* rho;        // per level scale
+  const float2* tables;     // [op][Kp][Rp]
+  float2* M;                // multipoles [ncell][P^2]
+  float2* L;                // locals [ncell][P^2]
+  const int4* m2l_pairs;    // (target, source, symmetry, op)
+  const int4* p2p_work;     // (tgt begin, tgt end, interval begin, interval end)
+  const int2* p2p_ivals;    // (src begin, src end)
+  const int32_t* p2p_total; // sources per work item
+  int64_t nsrc, ntgt, ncellP2;
+  float k;
+  int32_t pad;
+};
+
+struct XYPtrs {
+  const float2* x[64];
+  float2* y[64];
+};
+
+int elem_chunk();
+void launch_set_xy(int count, int base, const XYPtrs& p, InstDev* insts, hipStream_t s);
+void launch_zero(const int2* items, int n, const InstDev* insts, hipStream_t s);
+void launch_gather(const int2* items, int n, const InstDev* insts, hipStream_t s);
+void launch_scatter(const int2* items, int n, const InstDev* insts, hipStream_t s);
+void launch_p2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
+void launch_m2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
+void launch_l2l(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
+void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
+void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s);
 int m2l_pairs_per_chunk(int P);
-void launch_m2l_mfma(const int4* chunks, int nchunks, const int4* pairs, const float2* tables, int P,
-                     const int32_t* symdst, const int32_t* symph, const int32_t* outidx,
-                     const int32_t* outph, const float2* M, float2* L, hipStream_t s);
+// chunks: (instance, op, pair begin, pair end), sorted by (instance, op)
+void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, const int32_t* outidx,
+                const int32_t* outph, hipStream_t s);
 
 }  // namespace hfmm

@@ -193,25 +193,47 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
 }
 
 // ---------------------------------------------------------------------------
-// Gather source strengths into Morton order: q_s = w_s * x[unknown_s]
+// Instance-aware kernels.  Every work item names an instance; its pointers
+// come from the instance table, so one launch can serve many independent
+// problems (a single matvec is a batch of one).
 // ---------------------------------------------------------------------------
-__global__ void k_gather(int64_t n, const int32_t* __restrict__ idx, const float* __restrict__ w,
-                         const float2* __restrict__ x, float2* __restrict__ q) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float2 v = x[idx[i]];
-  if (w) {
-    float s = w[i];
-    v = make_float2(v.x * s, v.y * s);
+constexpr int kChunk = 4096;   // elements per block for zero / gather / scatter
+
+// M = L = 0 for the listed instances (items: instance, element offset)
+__global__ void k_zero(const int2* __restrict__ items, int n, const InstDev* __restrict__ insts) {
+  const int2 it = items[blockIdx.x];
+  const InstDev& I = insts[it.x];
+  const int64_t e0 = (int64_t)it.y * kChunk;
+  const int64_t e1 = min(e0 + kChunk, (int64_t)I.ncellP2);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    I.M[e] = make_float2(0.f, 0.f);
+    I.L[e] = make_float2(0.f, 0.f);
   }
-  q[i] = v;
 }
 
-__global__ void k_scatter(int64_t n, const int32_t* __restrict__ perm, const float2* __restrict__ ys,
-                          float2* __restrict__ y) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  y[perm[i]] = ys[i];
+// q_s = w_s x[unknown_s] in Morton order (items: instance, body offset)
+__global__ void k_gather(const int2* __restrict__ items, const InstDev* __restrict__ insts) {
+  const int2 it = items[blockIdx.x];
+  const InstDev& I = insts[it.x];
+  const int64_t e0 = (int64_t)it.y * kChunk;
+  const int64_t e1 = min(e0 + kChunk, I.nsrc);
+  for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) {
+    float2 v = I.x[I.src_idx[i]];
+    if (I.src_w) {
+      const float s = I.src_w[i];
+      v = make_float2(v.x * s, v.y * s);
+    }
+    I.q[i] = v;
+  }
+}
+
+// y[perm_i] = ys_i (items: instance, body offset)
+__global__ void k_scatter(const int2* __restrict__ items, const InstDev* __restrict__ insts) {
+  const int2 it = items[blockIdx.x];
+  const InstDev& I = insts[it.x];
+  const int64_t e0 = (int64_t)it.y * kChunk;
+  const int64_t e1 = min(e0 + kChunk, I.ntgt);
+  for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) I.y[I.tgt_perm[i]] = I.ys[i];
 }
 
 // Y_n^m (m >= 0) of direction (dx,dy,dz)/r into a[n*(n+1)/2 + m], FP32, via
@@ -255,30 +277,25 @@ __device__ inline void ylm_pos(int P, float dx, float dy, float dz, float r, flo
 // ---------------------------------------------------------------------------
 constexpr int kP2MChunk = 32;
 
-__global__ void __launch_bounds__(64) k_p2m(const int32_t* __restrict__ leaves, int nleaves,
-                                            const int4* __restrict__ cells,
-                                            const float4* __restrict__ geo,
-                                            const int32_t* __restrict__ clev,
-                                            const double* __restrict__ rho,
-                                            const float4* __restrict__ spos,
-                                            const float2* __restrict__ q, float k, int P,
-                                            float2* __restrict__ M) {
-  const int li = blockIdx.x;
-  if (li >= nleaves) return;
-  const int cell = leaves[li];
-  const int4 rg = cells[cell];
-  const float4 g = geo[cell];
-  const double rh = rho[clev[cell]];
-  const int P2 = P * P, PH = P * (P + 1) / 2;
+__global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items,
+                                            const InstDev* __restrict__ insts, int P) {
+  const int2 it = items[blockIdx.x];
+  const InstDev& I = insts[it.x];
+  const int cell = it.y;
+  const int4 rg = I.cells[cell];
+  const float4 g = I.geo[cell];
+  const double rh = I.rho[I.clev[cell]];
+  const float k = I.k;
+  const int P2 = P * P;
   __shared__ float2 sa[kP2MChunk][kMaxP * (kMaxP + 1) / 2];
   __shared__ float2 sq[kP2MChunk];
   const int lane = threadIdx.x;
-  float2 acc[4];  // up to 4 coefficients per lane (P2 <= 256)
+  float2 acc[4];
   for (int t = 0; t < 4; ++t) acc[t] = make_float2(0.f, 0.f);
   for (int j0 = rg.x; j0 < rg.y; j0 += kP2MChunk) {
     int nj = min(kP2MChunk, rg.y - j0);
     if (lane < nj) {
-      float4 p = spos[j0 + lane];
+      float4 p = I.spos[j0 + lane];
       float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
       float r = sqrtf(dx * dx + dy * dy + dz * dz);
       double b[kMaxP];
@@ -292,7 +309,7 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t* __restrict__ leaves, 
           a[n * (n + 1) / 2 + m] = make_float2(v.x * bn, v.y * bn);
         }
       }
-      sq[lane] = q[j0 + lane];
+      sq[lane] = I.q[j0 + lane];
     }
     __syncthreads();
     for (int t = 0; t < 4; ++t) {
@@ -314,124 +331,69 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t* __restrict__ leaves, 
   }
   for (int t = 0; t < 4; ++t) {
     int e = lane + 64 * t;
-    if (e < P2) M[(size_t)cell * P2 + e] = acc[t];
+    if (e < P2) I.M[(size_t)cell * P2 + e] = acc[t];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Dense translation y_out = T y_in for M2M (children -> parent) and L2L
-// (parent -> child).  One block per destination cell.
+// M2M (children -> parent) and L2L (parent -> child): dense P^2 x P^2
+// translations, one block per destination cell.  cops[c] = (op of c's M2M
+// as a child, op of c's L2L as a child).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_m2m(int c0, int c1, const int4* __restrict__ topo,
-                                             const int32_t* __restrict__ m2m_base,
-                                             const float2* __restrict__ tables, int P, int Kp,
-                                             int Rp, float2* __restrict__ M) {
-  const int cell = c0 + blockIdx.x;
-  if (cell >= c1) return;
-  const int4 tp = topo[cell];  // (child begin, child end, parent, octant | level << 3)
-  if (tp.x == tp.y) return;
+__global__ void __launch_bounds__(256) k_m2m(const int2* __restrict__ items,
+                                             const InstDev* __restrict__ insts, int P, int Kp, int Rp) {
+  const int2 it = items[blockIdx.x];
+  const InstDev& I = insts[it.x];
+  const int cell = it.y;
+  const int4 tp = I.topo[cell];  // (child begin, child end, parent, octant | level << 3)
   const int P2 = P * P;
   __shared__ float2 sm[kMaxP * kMaxP];
-  float2 acc[1] = {make_float2(0.f, 0.f)};
+  float2 acc = make_float2(0.f, 0.f);
   const int r = threadIdx.x;
   for (int ch = tp.x; ch < tp.y; ++ch) {
     __syncthreads();
-    for (int e = threadIdx.x; e < P2; e += blockDim.x) sm[e] = M[(size_t)ch * P2 + e];
+    for (int e = threadIdx.x; e < P2; e += blockDim.x) sm[e] = I.M[(size_t)ch * P2 + e];
     __syncthreads();
-    const int4 tc = topo[ch];
-    const int op = m2m_base[tc.w >> 3] + (tc.w & 7);
-    const float2* T = tables + (size_t)op * Kp * Rp;
-    if (r < P2) {
-      float2 s = acc[0];
-      for (int c = 0; c < P2; ++c) s = cfma(T[(size_t)c * Rp + r], sm[c], s);
-      acc[0] = s;
-    }
+    const float2* T = I.tables + (size_t)I.cops[ch].x * Kp * Rp;
+    if (r < P2)
+      for (int c = 0; c < P2; ++c) acc = cfma(T[(size_t)c * Rp + r], sm[c], acc);
   }
-  if (r < P2) M[(size_t)cell * P2 + r] = acc[0];
+  if (r < P2) I.M[(size_t)cell * P2 + r] = acc;
 }
 
-__global__ void __launch_bounds__(256) k_l2l(int c0, int c1, const int4* __restrict__ topo,
-                                             const int32_t* __restrict__ l2l_base,
-                                             const float2* __restrict__ tables, int P, int Kp,
-                                             int Rp, float2* __restrict__ L) {
-  const int cell = c0 + blockIdx.x;
-  if (cell >= c1) return;
-  const int4 tp = topo[cell];
-  const int parent = tp.z;
+__global__ void __launch_bounds__(256) k_l2l(const int2* __restrict__ items,
+                                             const InstDev* __restrict__ insts, int P, int Kp, int Rp) {
+  const int2 it = items[blockIdx.x];
+  const InstDev& I = insts[it.x];
+  const int cell = it.y;
+  const int parent = I.topo[cell].z;
   const int P2 = P * P;
   __shared__ float2 sl[kMaxP * kMaxP];
-  for (int e = threadIdx.x; e < P2; e += blockDim.x) sl[e] = L[(size_t)parent * P2 + e];
+  for (int e = threadIdx.x; e < P2; e += blockDim.x) sl[e] = I.L[(size_t)parent * P2 + e];
   __syncthreads();
-  const int op = l2l_base[tp.w >> 3] + (tp.w & 7);
-  const float2* T = tables + (size_t)op * Kp * Rp;
+  const float2* T = I.tables + (size_t)I.cops[cell].y * Kp * Rp;
   const int r = threadIdx.x;
   if (r < P2) {
-    float2 s = L[(size_t)cell * P2 + r];
+    float2 s = I.L[(size_t)cell * P2 + r];
     for (int c = 0; c < P2; ++c) s = cfma(T[(size_t)c * Rp + r], sl[c], s);
-    L[(size_t)cell * P2 + r] = s;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// M2L (first version, VALU): each block takes a chunk of pairs sharing one
-// operator.  Inputs are mapped by the pair's symmetry (M' = D^T M), the
-// canonical operator applied, and outputs mapped back (L += conj(D) L').
-// ---------------------------------------------------------------------------
-constexpr int kM2LChunk = 16;
-
-__global__ void __launch_bounds__(256) k_m2l_valu(const int4* __restrict__ chunks,
-                                                  const int4* __restrict__ pairs,
-                                                  const float2* __restrict__ tables,
-                                                  const int32_t* __restrict__ symdst,
-                                                  const int32_t* __restrict__ symph,
-                                                  const int32_t* __restrict__ outidx,
-                                                  const int32_t* __restrict__ outph, int P, int Kp,
-                                                  int Rp, const float2* __restrict__ M,
-                                                  float2* __restrict__ L) {
-  const int4 ch = chunks[blockIdx.x];
-  const int op = ch.x, pb = ch.y, np = ch.z - ch.y;
-  const int P2 = P * P;
-  __shared__ float2 B[kM2LChunk][kMaxP * kMaxP];
-  for (int e = threadIdx.x; e < np * P2; e += blockDim.x) {
-    int p = e / P2, c = e % P2;
-    int4 pr = pairs[pb + p];
-    int g = pr.z;
-    float2 v = M[(size_t)pr.y * P2 + c];
-    B[p][symdst[g * P2 + c]] = mul_ipow(v, symph[g * P2 + c]);
-  }
-  __syncthreads();
-  const float2* T = tables + (size_t)op * Kp * Rp;
-  for (int r = threadIdx.x; r < P2; r += blockDim.x) {
-    float2 acc[kM2LChunk];
-    for (int p = 0; p < kM2LChunk; ++p) acc[p] = make_float2(0.f, 0.f);
-    for (int c = 0; c < P2; ++c) {
-      float2 t = T[(size_t)c * Rp + r];
-#pragma unroll
-      for (int p = 0; p < kM2LChunk; ++p) acc[p] = cfma(t, B[p][c], acc[p]);
-    }
-    for (int p = 0; p < np; ++p) {
-      int4 pr = pairs[pb + p];
-      int g = pr.z;
-      int o = outidx[g * P2 + r];
-      float2 v = mul_ipow(acc[p], outph[g * P2 + r]);
-      atomicAdd(&L[(size_t)pr.x * P2 + o].x, v.x);
-      atomicAdd(&L[(size_t)pr.x * P2 + o].y, v.y);
-    }
+    I.L[(size_t)cell * P2 + r] = s;
   }
 }
 
 // ---------------------------------------------------------------------------
 // M2L on the matrix cores.  One wave takes up to 16*NCT pairs that share one
-// canonical operator T (P^2 x P^2 complex).  The inputs M' = D^T M of the
-// pairs are staged in LDS as the B matrix (k = input coefficient, column =
-// pair); T streams from memory as the A matrix (row = output coefficient);
-// the complex product is four real 16x16x4 FP32 MFMAs per tile and k-step:
-//   Cr += Tr Br - Ti Bi,   Ci += Tr Bi + Ti Br.
-// Outputs are mapped back (L += conj(D) C) and added to L with atomics.
-// Tables are laid out [op][k < Kp][r < Rp] with zero padding, Kp = 4 ceil(P^2/4),
-// Rp = 16 ceil(P^2/16).  Blocks are mapped so that each XCD works through a
-// contiguous range of chunks (chunks are sorted by operator), which keeps an
-// operator's table in that XCD's L2 while its chunks run.
+// canonical operator T (P^2 x P^2 complex).  The B matrix (k = input
+// coefficient, column = pair) holds M' = D^T M, gathered straight from the
+// multipoles with the reflection applied arithmetically; T streams from
+// memory as the A matrix (row = output coefficient).  The complex product is
+// four real 16x16x4 FP32 MFMAs per tile and k-step:
+//   Cr += Tr Br - Ti Bi,   Ci += Tr Bi + Ti Br,
+// with A and B prefetched one k-step ahead.  Outputs are mapped back
+// (L += conj(D) C), transposed through LDS and added per target with atomics
+// over the target's contiguous coefficients.  Tables are [op][k < Kp][r < Rp]
+// with zero padding.  Blocks are mapped so that each XCD walks a contiguous
+// range of chunks (sorted by operator), keeping an operator's table in that
+// XCD's L2 while its chunks run.
 //
 // MFMA 16x16x4 f32 lane layout: A[i][k] from lane i + 16k, B[k][j] from lane
 // j + 16k, D[4q + v][j] in lane j + 16q, register v.
@@ -453,22 +415,20 @@ __device__ inline int sym_m(int g, int n, int m, int& ph) {
 
 template <int RT, int NCT>
 __global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks, int nchunks,
-                                                 int per_xcd, const int4* __restrict__ pairs,
-                                                 const float2* __restrict__ tables, int Kp, int Rp,
-                                                 const int32_t* __restrict__ outidx,
-                                                 const int32_t* __restrict__ outph, int P2,
-                                                 const float2* __restrict__ M,
-                                                 float2* __restrict__ L) {
-  constexpr int NP = 16 * NCT;      // pairs per wave
-  extern __shared__ float2 Cs[];    // [NP][16 RT + 1] output transpose
+                                                 int per_xcd, const InstDev* __restrict__ insts,
+                                                 int Kp, int Rp, const int32_t* __restrict__ outidx,
+                                                 const int32_t* __restrict__ outph, int P2) {
+  extern __shared__ float2 Cs[];    // [16 NCT][16 RT + 1] output transpose
   const int b = blockIdx.x;
   const int chunk = (b & 7) * per_xcd + (b >> 3);
   if (chunk >= nchunks) return;
-  const int4 ch = chunks[chunk];
-  const int op = ch.x, pb = ch.y, np = ch.z - ch.y;
+  const int4 ch = chunks[chunk];    // (instance, op, pair begin, pair end)
+  const InstDev& I = insts[ch.x];
+  const int op = ch.y, pb = ch.z, np = ch.w - ch.z;
+  const int4* __restrict__ pairs = I.m2l_pairs;
+  const float2* __restrict__ M = I.M;
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
-  // this lane's B columns: pair 16 t + li
   int src[NCT], gs[NCT];
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
@@ -491,8 +451,8 @@ __global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks
       float2 v = make_float2(0.f, 0.f);
       if (k < P2 && src[t] >= 0) {
         int ph0, ph1;
-        const int mc = sym_m(gs[t], n, m, ph0);       // c = (n, mc)
-        sym_m(gs[t], n, mc, ph1);                     // phase of c under g
+        const int mc = sym_m(gs[t], n, m, ph0);
+        sym_m(gs[t], n, mc, ph1);
         v = mul_ipow(M[(size_t)src[t] * P2 + n * n + n + mc], ph1);
       }
       out[t] = v;
@@ -506,7 +466,7 @@ __global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks
       cr[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
       ci[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  const float2* T = tables + (size_t)op * Kp * Rp;
+  const float2* T = I.tables + (size_t)op * Kp * Rp;
   const int KS = Kp >> 2;
   float2 a[RT], an[RT], bv[NCT], bn[NCT];
 #pragma unroll
@@ -535,8 +495,6 @@ __global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks
 #pragma unroll
     for (int t = 0; t < NCT; ++t) bv[t] = bn[t];
   }
-  // transpose C through LDS, then add each pair's outputs to its target with
-  // atomics over that target's contiguous coefficient range
   constexpr int CS = 16 * RT + 1;
 #pragma unroll
   for (int t = 0; t < NCT; ++t)
@@ -549,7 +507,7 @@ __global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks
   for (int p = 0; p < np; ++p) {
     const int4 pr = pairs[pb + p];
     const int g = pr.z;
-    float2* Lt = L + (size_t)pr.x * P2;
+    float2* Lt = I.L + (size_t)pr.x * P2;
     for (int row = lane; row < P2; row += 64) {
       const int o = outidx[g * P2 + row];
       const float2 val = mul_ipow(Cs[p * CS + row], outph[g * P2 + row]);
@@ -559,67 +517,26 @@ __global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks
   }
 }
 
-template <int RT, int NCT>
-static void launch_m2l_mfma_t(const int4* chunks, int nchunks, const int4* pairs, const float2* tables,
-                              int Kp, int Rp, const int32_t* symdst, const int32_t* symph,
-                              const int32_t* outidx, const int32_t* outph, int P2, const float2* M,
-                              float2* L, hipStream_t s) {
-  const int per = (nchunks + 7) / 8;
-  const size_t lds = (size_t)(16 * NCT) * (16 * RT + 1) * sizeof(float2);
-  k_m2l_mfma<RT, NCT><<<8 * per, 64, lds, s>>>(chunks, nchunks, per, pairs, tables, Kp, Rp, outidx,
-                                                outph, P2, M, L);
-}
-
-int m2l_pairs_per_chunk(int P) { return P * P > 240 ? 16 : 32; }
-
-void launch_m2l_mfma(const int4* chunks, int nchunks, const int4* pairs, const float2* tables, int P,
-                     const int32_t* symdst, const int32_t* symph, const int32_t* outidx,
-                     const int32_t* outph, const float2* M, float2* L, hipStream_t s) {
-  if (nchunks <= 0) return;
-  const int P2 = P * P, Kp = 4 * ((P2 + 3) / 4), Rp = 16 * ((P2 + 15) / 16);
-  const int RT = Rp / 16;
-#define M2L_CASE(R)                                                                                 \
-  case R:                                                                                           \
-    if (P2 > 240)                                                                                   \
-      launch_m2l_mfma_t<R, 1>(chunks, nchunks, pairs, tables, Kp, Rp, symdst, symph, outidx, outph, \
-                              P2, M, L, s);                                                         \
-    else                                                                                            \
-      launch_m2l_mfma_t<R, 2>(chunks, nchunks, pairs, tables, Kp, Rp, symdst, symph, outidx, outph, \
-                              P2, M, L, s);                                                         \
-    break;
-  switch (RT) {
-    M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6) M2L_CASE(7) M2L_CASE(8)
-    M2L_CASE(9) M2L_CASE(10) M2L_CASE(11) M2L_CASE(12) M2L_CASE(13) M2L_CASE(14) M2L_CASE(15)
-    M2L_CASE(16)
-    default: break;
-  }
-#undef M2L_CASE
-}
-
 // ---------------------------------------------------------------------------
-// L2P: one wave per leaf; phi(x) = ik sum Lt_n^m (b_n(k r)) Y_n^m(dir) with
-// b_n = j_n / sigma_n.  Writes (not accumulates) the sorted output.
+// L2P: one wave per leaf; phi(x) = ik sum Lt_n^m (j_n(k r)/sigma_n) Y_n^m(dir).
+// Writes (not accumulates) the sorted output.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_l2p(const int32_t* __restrict__ leaves, int nleaves,
-                                            const int4* __restrict__ cells,
-                                            const float4* __restrict__ geo,
-                                            const int32_t* __restrict__ clev,
-                                            const double* __restrict__ rho,
-                                            const float4* __restrict__ tpos, float k, int P,
-                                            const float2* __restrict__ L, float2* __restrict__ ys) {
-  const int li = blockIdx.x;
-  if (li >= nleaves) return;
-  const int cell = leaves[li];
-  const int4 rg = cells[cell];
-  const float4 g = geo[cell];
-  const double rh = rho[clev[cell]];
+__global__ void __launch_bounds__(64) k_l2p(const int2* __restrict__ items,
+                                            const InstDev* __restrict__ insts, int P) {
+  const int2 it = items[blockIdx.x];
+  const InstDev& I = insts[it.x];
+  const int cell = it.y;
+  const int4 rg = I.cells[cell];
+  const float4 g = I.geo[cell];
+  const double rh = I.rho[I.clev[cell]];
+  const float k = I.k;
   const int P2 = P * P;
   __shared__ float2 sl[kMaxP * kMaxP];
-  for (int e = threadIdx.x; e < P2; e += blockDim.x) sl[e] = L[(size_t)cell * P2 + e];
+  for (int e = threadIdx.x; e < P2; e += blockDim.x) sl[e] = I.L[(size_t)cell * P2 + e];
   __syncthreads();
   float2 a[kMaxP * (kMaxP + 1) / 2];
   for (int i = rg.z + threadIdx.x; i < rg.w; i += 64) {
-    float4 p = tpos[i];
+    float4 p = I.tpos[i];
     float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
     float r = sqrtf(dx * dx + dy * dy + dz * dz);
     double b[kMaxP];
@@ -637,8 +554,7 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t* __restrict__ leaves, 
       s.x = fmaf(bn, t.x, s.x);
       s.y = fmaf(bn, t.y, s.y);
     }
-    // times i k
-    ys[i] = make_float2(-k * s.y, k * s.x);
+    I.ys[i] = make_float2(-k * s.y, k * s.x);  // times i k
   }
 }
 
@@ -672,22 +588,22 @@ __device__ inline void p2p_fetch(const int2* __restrict__ ivals, int iv, int ie,
   w = make_float2(0.f, 0.f);
 }
 
-__global__ void __launch_bounds__(256) k_p2p(const int4* __restrict__ work, int nwork,
-                                             const int2* __restrict__ ivals,
-                                             const int32_t* __restrict__ ivlen_total,
-                                             const float4* __restrict__ tpos,
-                                             const float4* __restrict__ spos,
-                                             const float2* __restrict__ q, float k,
-                                             float2* __restrict__ ys) {
+__global__ void __launch_bounds__(256) k_p2p(const int2* __restrict__ items, int nitems,
+                                             const InstDev* __restrict__ insts) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int w = blockIdx.x * 4 + wave;
   __shared__ float4 sp[4][2][64];
   __shared__ float2 sq[4][2][64];
   __shared__ float4 red[4][64];
-  if (w >= nwork) return;
-  const int4 wk = work[w];
-  const int total = ivlen_total[w];
-  const float krev = k * 0.15915494309189535f;  // k / (2 pi)
+  if (w >= nitems) return;
+  const int2 it = items[w];
+  const InstDev& I = insts[it.x];
+  const int4 wk = I.p2p_work[it.y];
+  const int total = I.p2p_total[it.y];
+  const int2* __restrict__ ivals = I.p2p_ivals;
+  const float4* __restrict__ spos = I.spos;
+  const float2* __restrict__ q = I.q;
+  const float krev = I.k * 0.15915494309189535f;  // k / (2 pi)
   for (int t0 = wk.x; t0 < wk.y; t0 += 64) {
     const int tc = min(64, wk.y - t0);
     const int np = (tc + 1) >> 1;                 // target pairs
@@ -695,10 +611,8 @@ __global__ void __launch_bounds__(256) k_p2p(const int4* __restrict__ work, int 
     const int pi = lane % np, s = lane / np;
     const bool active = s < nsplit;
     const int ia = t0 + 2 * pi, ib = min(ia + 1, t0 + tc - 1);
-    const bool has_b = (2 * pi + 1) < tc;
-    const float4 xa = tpos[ia], xb = tpos[ib];
+    const float4 xa = I.tpos[ia], xb = I.tpos[ib];
     float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
-    // stream cursor (wave-uniform): interval iv, offset off
     int iv = wk.z, off = 0;
     float4 np4;
     float2 nq;
@@ -708,7 +622,6 @@ __global__ void __launch_bounds__(256) k_p2p(const int4* __restrict__ work, int 
       const int buf = (base >> 6) & 1;
       sp[wave][buf][lane] = np4;
       sq[wave][buf][lane] = nq;
-      // advance the cursor by 64 and prefetch the next tile
       off += 64;
       while (iv < wk.w && off >= ivals[iv].y - ivals[iv].x) {
         off -= ivals[iv].y - ivals[iv].x;
@@ -753,7 +666,6 @@ __global__ void __launch_bounds__(256) k_p2p(const int4* __restrict__ work, int 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // lanes 0..tc-1 finalise target t0 + lane: pair lane/2, slot lane&1
     if (lane < tc) {
       const int pp = lane >> 1, slot = lane & 1;
       float sr = 0.f, si = 0.f;
@@ -763,12 +675,21 @@ __global__ void __launch_bounds__(256) k_p2p(const int4* __restrict__ work, int 
         si += slot ? v.w : v.y;
       }
       const float scale = 0.07957747154594767f;  // 1 / (4 pi)
-      float2 o = ys[t0 + lane];
+      float2 o = I.ys[t0 + lane];
       o.x = fmaf(sr, scale, o.x);
       o.y = fmaf(si, scale, o.y);
-      ys[t0 + lane] = o;
+      I.ys[t0 + lane] = o;
     }
     __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Per-call caller vectors of each instance.
+__global__ void k_set_xy(int count, int base, XYPtrs p, InstDev* __restrict__ insts) {
+  const int i = threadIdx.x;
+  if (i < count) {
+    insts[base + i].x = p.x[i];
+    insts[base + i].y = p.y[i];
   }
 }
 
@@ -787,57 +708,72 @@ void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, const in
   table_dims(P, &Kp, &Rp);
   k_gen_tables<<<nops, 256, 0, s>>>(ops, nops, P, k, cp_off, cp_lm, cp_val, Kp, Rp, tables);
 }
-void launch_gather(int64_t n, const int32_t* idx, const float* w, const float2* x, float2* q,
-                   hipStream_t s) {
+int elem_chunk() { return kChunk; }
+void launch_set_xy(int count, int base, const XYPtrs& p, InstDev* insts, hipStream_t s) {
+  k_set_xy<<<1, 64, 0, s>>>(count, base, p, insts);
+}
+void launch_zero(const int2* items, int n, const InstDev* insts, hipStream_t s) {
+  if (n > 0) k_zero<<<n, 256, 0, s>>>(items, n, insts);
+}
+void launch_gather(const int2* items, int n, const InstDev* insts, hipStream_t s) {
+  if (n > 0) k_gather<<<n, 256, 0, s>>>(items, insts);
+}
+void launch_scatter(const int2* items, int n, const InstDev* insts, hipStream_t s) {
+  if (n > 0) k_scatter<<<n, 256, 0, s>>>(items, insts);
+}
+void launch_p2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
+  if (n > 0) k_p2m<<<n, 64, 0, s>>>(items, insts, P);
+}
+void launch_m2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
   if (n <= 0) return;
-  k_gather<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, idx, w, x, q);
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
+  k_m2m<<<n, 256, 0, s>>>(items, insts, P, Kp, Rp);
 }
-void launch_scatter(int64_t n, const int32_t* perm, const float2* ys, float2* y, hipStream_t s) {
+void launch_l2l(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
   if (n <= 0) return;
-  k_scatter<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, perm, ys, y);
-}
-void launch_p2m(const int32_t* leaves, int nleaves, const int4* cells, const float4* geo,
-                const int32_t* clev, const double* rho, const float4* spos, const float2* q,
-                float k, int P, float2* M, hipStream_t s) {
-  if (nleaves <= 0) return;
-  k_p2m<<<nleaves, 64, 0, s>>>(leaves, nleaves, cells, geo, clev, rho, spos, q, k, P, M);
-}
-void launch_m2m(int c0, int c1, const int4* topo, const int32_t* base, const float2* tables,
-                int P, float2* M, hipStream_t s) {
-  if (c1 <= c0) return;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  k_m2m<<<c1 - c0, 256, 0, s>>>(c0, c1, topo, base, tables, P, Kp, Rp, M);
+  k_l2l<<<n, 256, 0, s>>>(items, insts, P, Kp, Rp);
 }
-void launch_l2l(int c0, int c1, const int4* topo, const int32_t* base, const float2* tables,
-                int P, float2* L, hipStream_t s) {
-  if (c1 <= c0) return;
-  int Kp, Rp;
-  table_dims(P, &Kp, &Rp);
-  k_l2l<<<c1 - c0, 256, 0, s>>>(c0, c1, topo, base, tables, P, Kp, Rp, L);
+void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
+  if (n > 0) k_l2p<<<n, 64, 0, s>>>(items, insts, P);
 }
-void launch_m2l(const int4* chunks, int nchunks, const int4* pairs, const float2* tables,
-                const int32_t* symdst, const int32_t* symph, const int32_t* outidx,
-                const int32_t* outph, int P, const float2* M, float2* L, hipStream_t s) {
-  if (nchunks <= 0) return;
-  int Kp, Rp;
-  table_dims(P, &Kp, &Rp);
-  k_m2l_valu<<<nchunks, 256, 0, s>>>(chunks, pairs, tables, symdst, symph, outidx, outph, P, Kp, Rp,
-                                     M, L);
-}
-void launch_l2p(const int32_t* leaves, int nleaves, const int4* cells, const float4* geo,
-                const int32_t* clev, const double* rho, const float4* tpos, float k, int P,
-                const float2* L, float2* ys, hipStream_t s) {
-  if (nleaves <= 0) return;
-  k_l2p<<<nleaves, 64, 0, s>>>(leaves, nleaves, cells, geo, clev, rho, tpos, k, P, L, ys);
-}
-void launch_p2p(const int4* work, int nwork, const int2* ivals, const int32_t* ivlen_total,
-                const float4* tpos, const float4* spos, const float2* q, float k, float2* ys,
-                hipStream_t s) {
-  if (nwork <= 0) return;
-  k_p2p<<<(nwork + 3) / 4, 256, 0, s>>>(work, nwork, ivals, ivlen_total, tpos, spos, q, k, ys);
+void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s) {
+  if (n > 0) k_p2p<<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
 }
 
-int m2l_chunk_size() { return kM2LChunk; }
+template <int RT, int NCT>
+static void launch_m2l_mfma_t(const int4* chunks, int nchunks, const InstDev* insts, int Kp, int Rp,
+                              const int32_t* outidx, const int32_t* outph, int P2, hipStream_t s) {
+  const int per = (nchunks + 7) / 8;
+  const size_t lds = (size_t)(16 * NCT) * (16 * RT + 1) * sizeof(float2);
+  k_m2l_mfma<RT, NCT><<<8 * per, 64, lds, s>>>(chunks, nchunks, per, insts, Kp, Rp, outidx, outph, P2);
+}
+
+int m2l_pairs_per_chunk(int P) { return P * P > 240 ? 16 : 32; }
+
+void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, const int32_t* outidx,
+                const int32_t* outph, hipStream_t s) {
+  if (nchunks <= 0) return;
+  const int P2 = P * P;
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
+  const int RT = Rp / 16;
+#define M2L_CASE(R)                                                                             \
+  case R:                                                                                       \
+    if (P2 > 240)                                                                               \
+      launch_m2l_mfma_t<R, 1>(chunks, nchunks, insts, Kp, Rp, outidx, outph, P2, s);            \
+    else                                                                                        \
+      launch_m2l_mfma_t<R, 2>(chunks, nchunks, insts, Kp, Rp, outidx, outph, P2, s);            \
+    break;
+  switch (RT) {
+    M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6) M2L_CASE(7) M2L_CASE(8)
+    M2L_CASE(9) M2L_CASE(10) M2L_CASE(11) M2L_CASE(12) M2L_CASE(13) M2L_CASE(14) M2L_CASE(15)
+    M2L_CASE(16)
+    default: break;
+  }
+#undef M2L_CASE
+}
 
 }  // namespace hfmm

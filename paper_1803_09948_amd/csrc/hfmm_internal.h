@@ -111,27 +111,52 @@ struct Plan {
   DevBuf d_geo;                  // float4 (cx, cy, cz, half)
   DevBuf d_clev;                 // int32 level
   DevBuf d_topo;                 // int4 (child begin, child end, parent, octant | level << 3)
-  DevBuf d_src_leaves, d_tgt_leaves;
-  int32_t n_src_leaves = 0, n_tgt_leaves = 0;
   // operators and work lists
   DevBuf d_ops, d_tables;        // OpDesc[n_ops]; float2 [n_ops][P^2 in][P^2 out]
   DevBuf d_rho;                  // double per level
-  DevBuf d_m2m_base, d_l2l_base; // int32 per level
-  DevBuf d_m2l_chunks;           // int4 (op, pair begin, pair end, 0)
   DevBuf d_m2l_pairs;            // int4 (target cell, source cell, symmetry, op)
   int32_t n_m2l_chunks = 0;
   DevBuf d_p2p_work;             // int4 (tgt begin, tgt end, interval begin, interval end)
   DevBuf d_p2p_ivals;            // int2 (src begin, src end)
   DevBuf d_p2p_total;            // int32 sources per work item
   int32_t n_p2p_work = 0;
-  DevBuf d_symdst, d_symph, d_outidx, d_outph;  // int32 [16][P^2]
+  DevBuf d_outidx, d_outph;      // int32 [16][P^2]: output map of each reflection
   DevBuf d_M, d_L;               // float2 [ncell][P^2]
+  DevBuf d_cops;                 // int2 per cell: (M2M op as child, L2L op as child)
+  // host work lists (cells / chunks of this instance)
+  std::vector<int32_t> src_leaves, tgt_leaves;
+  std::vector<std::vector<int32_t>> m2m_cells, l2l_cells;  // per level
+  std::vector<int4> m2l_chunks_h;                          // (op, pair begin, pair end, 0)
+  std::unique_ptr<struct Batch> self;                      // single-instance execution
   // BIE corrections (caller panel order; pattern in the Tree)
   DevBuf d_near_val;                            // float2 per near nonzero
   DevBuf d_diag;                                // double2: self integral - 3-point self sum
   int64_t n_near = 0;
   int64_t device_bytes = 0;
 };
+
+// Fused execution of one or more instances (instance-aware kernels).
+struct Batch {
+  int count = 0, P = 0, maxlev = 0;
+  std::vector<struct Tree*> trees;
+  std::vector<Plan*> plans;
+  std::vector<InstDev> hinst;
+  DevBuf d_inst;
+  DevBuf d_zero, d_gather, d_scatter, d_p2m, d_l2p, d_p2p, d_m2l, d_m2m, d_l2l, d_outidx, d_outph;
+  int n_zero = 0, n_gather = 0, n_scatter = 0, n_p2m = 0, n_l2p = 0, n_p2p = 0, n_m2l = 0;
+  std::vector<int> m2m_off, l2l_off;  // per level offsets into d_m2m / d_l2l
+  hipStream_t stream = nullptr;       // private stream for graph capture / replay
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~Batch();
+};
+
+int build_batch(const std::vector<struct Tree*>& trees, const std::vector<Plan*>& plans, Batch& b);
+// Runs the fused FMM sequence; xs/ys are caller vectors per instance.  With
+// use_graph the sequence is captured once and replayed on a private stream.
+int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t s, bool use_graph,
+              struct Tree* timing);
 
 struct Tree {
   HostTree h;                   // bodies and base cells
@@ -164,6 +189,7 @@ struct Tree {
   float phase_ms[8] = {0};
   hipEvent_t ev[9] = {};
   bool ev_made = false;
+  uint64_t uid = 0;
   ~Tree();
 };
 
@@ -173,6 +199,8 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out);
 int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_t s);
 int prepare_bie(Tree& t, Plan& pl, hipStream_t s);
 int check_kP(double k, int P);
+uint64_t next_uid();
+void forget_tree_batches(uint64_t uid);
 template <class T>
 int upload_vec(DevBuf& b, const std::vector<T>& v) {
   int rc = b.alloc(v.size() * sizeof(T));
