@@ -149,6 +149,43 @@ int hfmm_batch_matvec(int32_t count, hfmm_tree* const* trees, const double* ks,
                       const int32_t* Ps, const void* const* xs_dev,
                       void* const* ys_dev, void* stream);
 
+/* Host half of hfmm_prepare: builds the cells, traversal lists, operator
+ * descriptors and work lists for (k, P) without touching the device, and
+ * reports the exact device bytes the operator will take (plus the bodies if
+ * not yet resident).  Safe to call for different handles from different
+ * threads.  footprint_bytes may be NULL.  EINVAL as for hfmm_prepare. */
+int hfmm_prepare_host(hfmm_tree* tree, double k, int32_t P, int64_t* footprint_bytes);
+
+/* ---- Continuous-batching solve server -----------------------------------
+ * Serves many BIE solves at once.  Submitted solves wait in a queue; every
+ * hfmm_server_step admits queued solves (first come, first served) while
+ * fewer than max_active run and their device footprint fits the budget
+ * (0 = no limit), then advances each running solve by one GMRES product: a
+ * single fused FMM launch sequence for all of them, then each solve's FP64
+ * Arnoldi / residual work, and one host synchronisation for all.  Solves
+ * join and leave at step boundaries; each result is that of
+ * hfmm_gmres_solve on the same system up to FP32 rounding in the fused M2L.
+ * Handles, b and x must stay valid until the solve is done; one solve per
+ * handle at a time.  Not thread-safe: drive a server from one thread. */
+typedef struct hfmm_server hfmm_server;
+
+int hfmm_server_create(int64_t hbm_budget_bytes, int32_t max_active, hfmm_server** out);
+/* Queues a solve; *ticket identifies it, *footprint_bytes (may be NULL) is
+ * the device memory it will hold while active.  ENOMEM if it can never fit. */
+int hfmm_server_submit(hfmm_server* server, hfmm_tree* tree, double k, int32_t P,
+                       const void* b_dev, void* x_dev, double tol, int32_t restart,
+                       int32_t maxit, int64_t* ticket, int64_t* footprint_bytes);
+int hfmm_server_step(hfmm_server* server, void* stream, int32_t* n_active, int32_t* n_queued);
+/* state: 0 queued, 1 active, 2 converged, 3 not converged (maxit), -1 failed.
+ * times3 (may be NULL): submit, admit and completion times (seconds, steady
+ * clock). */
+int hfmm_server_poll(hfmm_server* server, int64_t ticket, int32_t* state,
+                     hfmm_gmres_info* info, double* times3);
+/* Forgets a finished ticket. */
+int hfmm_server_release(hfmm_server* server, int64_t ticket);
+int hfmm_server_used_bytes(hfmm_server* server, int64_t* used);
+void hfmm_server_free(hfmm_server* server);
+
 /* Statistics of the tree and, if P > 0, of the prepared (k, P) operator. */
 int hfmm_tree_stats(hfmm_tree* tree, double k, int32_t P, hfmm_stats* out);
 

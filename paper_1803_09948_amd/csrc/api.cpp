@@ -27,8 +27,15 @@ uint64_t next_uid() { return g_uid.fetch_add(1); }
     }                                                                              \
   } while (0)
 
-DevBuf::~DevBuf() {
+DevBuf::~DevBuf() { reset(); }
+int DevBuf::ensure(size_t n) {
+  if (p && bytes >= n) return HFMM_OK;
+  return alloc(n);
+}
+void DevBuf::reset() {
   if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
 }
 int DevBuf::alloc(size_t n) {
   if (p) {
@@ -157,30 +164,30 @@ int build_plan_host(Tree& t, double k, int P, Plan& pl) {
   return HFMM_OK;
 }
 
-int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
+int prepare_host(Tree& t, double k, int P, Plan** out) {
   uint64_t kb;
   std::memcpy(&kb, &k, 8);
   auto key = std::make_pair(kb, P);
   auto it = t.plans.find(key);
-  if (it != t.plans.end() && it->second->d_tables.p) {
+  if (it != t.plans.end()) {
     *out = it->second.get();
     return HFMM_OK;
   }
   int rc;
-  if (!t.uploaded && (rc = upload_bodies(t))) return rc;
   auto plp = std::make_unique<Plan>();
   Plan& pl = *plp;
   pl.k = k;
   pl.P = P;
+  pl.hd = std::make_unique<HostPlanData>();
+  HostPlanData& hd = *pl.hd;
   if ((rc = build_plan_host(t, k, P, pl))) return rc;
-  if ((rc = upload_cells(pl))) return rc;
   const HostTree& h = pl.ct;
   const int P2 = P * P;
   const int nlev = h.nlevels();
   pl.rho.resize(nlev);
   for (int l = 0; l < nlev; ++l) pl.rho[l] = std::min(1.0, k * 2.0 * h.H / double(1 << l));
   // operators: M2M and L2L per child level and octant
-  std::vector<OpDesc> ops;
+  std::vector<OpDesc>& ops = hd.ops;
   pl.m2m_base.assign(nlev, 0);
   pl.l2l_base.assign(nlev, 0);
   for (int l = 1; l < nlev; ++l) {
@@ -257,7 +264,9 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
     if (p.x != q.x) return p.x < q.x;
     return p.y < q.y;
   });
-  std::vector<int4> spairs(npair), chunks;
+  std::vector<int4>& spairs = hd.spairs;
+  spairs.resize(npair);
+  std::vector<int4> chunks;
   for (size_t i = 0; i < npair; ++i) spairs[i] = pairs[order[i]];
   const int CH = m2l_pairs_per_chunk(P);
   for (size_t i = 0; i < npair;) {
@@ -269,7 +278,8 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
   pl.n_m2l_chunks = (int32_t)chunks.size();
   pl.m2l_chunks_h = chunks;
   // per-cell operator indices and per-level work lists
-  std::vector<int2> cops(h.ncell(), make_int2(0, 0));
+  std::vector<int2>& cops = hd.cops;
+  cops.assign(h.ncell(), make_int2(0, 0));
   pl.m2m_cells.assign(nlev, {});
   pl.l2l_cells.assign(nlev, {});
   for (int i = 0; i < h.ncell(); ++i) {
@@ -285,11 +295,10 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
       if (h.te[i] > h.tb[i]) pl.tgt_leaves.push_back(i);
     }
   }
-  if ((rc = upload(pl.d_cops, cops))) return rc;
   // P2P work: per target leaf, merged source intervals
-  std::vector<int4> work;
-  std::vector<int2> ivals;
-  std::vector<int32_t> totals;
+  std::vector<int4>& work = hd.work;
+  std::vector<int2>& ivals = hd.ivals;
+  std::vector<int32_t>& totals = hd.totals;
   {
     const size_t np = pl.lists.p2p_a.size();
     std::vector<int32_t> ord(np);
@@ -321,7 +330,11 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
   }
   pl.n_p2p_work = (int32_t)work.size();
   // symmetry maps and their inverses for the outputs
-  std::vector<int32_t> sdst, sph, oidx(16 * P2), oph(16 * P2);
+  std::vector<int32_t> sdst, sph;
+  std::vector<int32_t>& oidx = hd.oidx;
+  std::vector<int32_t>& oph = hd.oph;
+  oidx.assign(16 * P2, 0);
+  oph.assign(16 * P2, 0);
   symmetry_map(P, sdst, sph);
   for (int g = 0; g < 16; ++g)
     for (int o = 0; o < P2; ++o) {
@@ -329,12 +342,39 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
       oidx[g * P2 + r] = o;
       oph[g * P2 + r] = (4 - sph[g * P2 + o]) & 3;
     }
-  // upload
-  if ((rc = upload(pl.d_ops, ops)) || (rc = upload(pl.d_rho, pl.rho)) ||
-      (rc = upload(pl.d_m2l_pairs, spairs)) ||
-      (rc = upload(pl.d_p2p_work, work)) || (rc = upload(pl.d_p2p_ivals, ivals)) ||
-      (rc = upload(pl.d_p2p_total, totals)) ||
-      (rc = upload(pl.d_outidx, oidx)) || (rc = upload(pl.d_outph, oph)))
+  pl.n_ops = (int64_t)ops.size();
+  // exact device footprint of this plan (and of the bodies if not yet resident)
+  {
+    int Kp, Rp;
+    table_dims(P, &Kp, &Rp);
+    const int64_t nc = h.ncell();
+    int64_t b = nc * (int64_t)(sizeof(int4) * 2 + sizeof(float4) + sizeof(int32_t) + sizeof(int2));
+    b += (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)Kp * Rp * sizeof(float2));
+    b += (int64_t)pl.rho.size() * 8 + (int64_t)spairs.size() * 16 + (int64_t)work.size() * 20 +
+         (int64_t)ivals.size() * 8 + 2 * 16 * (int64_t)P2 * 4 + 2 * nc * P2 * (int64_t)sizeof(float2);
+    if (t.bie) b += (int64_t)t.near_col.size() * 8 + t.npanel * 16;
+    if (!t.uploaded) b += t.h.nsrc * 40 + t.h.ntgt * 32;
+    pl.est_bytes = b;
+  }
+  t.plans[key] = std::move(plp);
+  *out = t.plans[key].get();
+  return HFMM_OK;
+}
+
+int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
+  if (pl.d_tables.p) return HFMM_OK;
+  int rc;
+  if (!t.uploaded && (rc = upload_bodies(t))) return rc;
+  if ((rc = upload_cells(pl))) return rc;
+  HostPlanData& hd = *pl.hd;
+  const HostTree& h = pl.ct;
+  const int P = pl.P, P2 = P * P;
+  const double k = pl.k;
+  if ((rc = upload(pl.d_ops, hd.ops)) || (rc = upload(pl.d_rho, pl.rho)) ||
+      (rc = upload(pl.d_m2l_pairs, hd.spairs)) || (rc = upload(pl.d_cops, hd.cops)) ||
+      (rc = upload(pl.d_p2p_work, hd.work)) || (rc = upload(pl.d_p2p_ivals, hd.ivals)) ||
+      (rc = upload(pl.d_p2p_total, hd.totals)) ||
+      (rc = upload(pl.d_outidx, hd.oidx)) || (rc = upload(pl.d_outph, hd.oph)))
     return rc;
   // coupling coefficients and tables
   const Coupling& cp = coupling(P);
@@ -358,10 +398,21 @@ int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
                     &pl.d_m2l_pairs, &pl.d_p2p_work, &pl.d_p2p_ivals, &pl.d_p2p_total, &pl.d_outidx,
                     &pl.d_outph, &pl.d_M, &pl.d_L, &pl.d_cops})
     pl.device_bytes += (int64_t)b->bytes;
-  if (t.bie && (rc = prepare_bie(t, pl, s))) return rc;
+  if (t.bie && (rc = prepare_bie(t, pl, s))) {
+    pl.d_tables.reset();  // not device-ready: the next prepare retries
+    return rc;
+  }
   pl.device_bytes += (int64_t)(pl.d_near_val.bytes + pl.d_diag.bytes);
-  t.plans[key] = std::move(plp);
-  *out = t.plans[key].get();
+  pl.hd.reset();
+  return HFMM_OK;
+}
+
+int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
+  Plan* pl;
+  int rc = prepare_host(t, k, P, &pl);
+  if (rc) return rc;
+  if ((rc = prepare_device(t, *pl, s))) return rc;
+  *out = pl;
   return HFMM_OK;
 }
 
@@ -462,6 +513,19 @@ int hfmm_build_tree(const float* xyz, int64_t n, const hfmm_opts* opts, hfmm_tre
   build_tree(xyz, n, nullptr, 0, t->ncrit, t->max_level, t->h);
   t->uid = next_uid();
   *out = reinterpret_cast<hfmm_tree*>(t.release());
+  return HFMM_OK;
+  API_GUARD_END
+}
+
+int hfmm_prepare_host(hfmm_tree* tree, double k, int32_t P, int64_t* footprint) {
+  API_GUARD_BEGIN
+  if (!tree) return set_error("tree is NULL"), HFMM_EINVAL;
+  int rc = check_kP(k, P);
+  if (rc) return rc;
+  Plan* pl;
+  Tree& t = *reinterpret_cast<Tree*>(tree);
+  if ((rc = prepare_host(t, k, P, &pl))) return rc;
+  if (footprint) *footprint = pl->d_tables.p ? 0 : pl->est_bytes;
   return HFMM_OK;
   API_GUARD_END
 }

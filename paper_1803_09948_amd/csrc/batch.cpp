@@ -63,10 +63,14 @@ static InstDev make_inst(Tree& t, Plan& pl) {
 
 template <class T>
 static int up(DevBuf& b, const std::vector<T>& v) {
-  return upload_vec(b, v);
+  return upload_vec(b, v, true);
 }
 
 int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans, Batch& b) {
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.graph) (void)hipGraphDestroy(b.graph);
+  b.exec = nullptr;
+  b.graph = nullptr;
   b.count = (int)trees.size();
   b.P = plans[0]->P;
   b.trees = trees;

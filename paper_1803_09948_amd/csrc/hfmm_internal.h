@@ -93,7 +93,17 @@ struct DevBuf {
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   int alloc(size_t n);
+  int ensure(size_t n);  // grow-only: keeps the buffer if it is large enough
+  void reset();
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// Host-side results of plan preparation, kept until the device upload.
+struct HostPlanData {
+  std::vector<OpDesc> ops;
+  std::vector<int4> spairs, work;
+  std::vector<int2> ivals, cops;
+  std::vector<int32_t> totals, oidx, oph;
 };
 
 struct Plan {
@@ -133,6 +143,8 @@ struct Plan {
   DevBuf d_diag;                                // double2: self integral - 3-point self sum
   int64_t n_near = 0;
   int64_t device_bytes = 0;
+  int64_t est_bytes = 0;                 // footprint computed before any allocation
+  std::unique_ptr<HostPlanData> hd;      // present between host and device preparation
 };
 
 // Fused execution of one or more instances (instance-aware kernels).
@@ -196,14 +208,16 @@ struct Tree {
 double kappa_of(const Tree& t, int P);
 int build_plan_host(Tree& t, double k, int P, Plan& pl);   // cells + lists (host only)
 int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out);
+int prepare_host(Tree& t, double k, int P, Plan** out);   // lists, operators, work (host only)
+int prepare_device(Tree& t, Plan& pl, hipStream_t s);      // upload and table generation
 int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_t s);
 int prepare_bie(Tree& t, Plan& pl, hipStream_t s);
 int check_kP(double k, int P);
 uint64_t next_uid();
 void forget_tree_batches(uint64_t uid);
 template <class T>
-int upload_vec(DevBuf& b, const std::vector<T>& v) {
-  int rc = b.alloc(v.size() * sizeof(T));
+int upload_vec(DevBuf& b, const std::vector<T>& v, bool grow_only = false) {
+  int rc = grow_only ? b.ensure(v.size() * sizeof(T)) : b.alloc(v.size() * sizeof(T));
   if (rc) return rc;
   if (!v.empty() && hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
     set_error("hipMemcpy upload failed");

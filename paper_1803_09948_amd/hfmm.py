@@ -21,7 +21,9 @@ EXPORTS = [
     "hfmm_default_opts", "hfmm_build_tree", "hfmm_build_bie", "hfmm_prepare", "hfmm_matvec",
     "hfmm_gmres_solve", "hfmm_bie_plane_wave", "hfmm_batch_matvec", "hfmm_tree_stats",
     "hfmm_tree_export", "hfmm_lists_export", "hfmm_set_timing", "hfmm_phase_times",
-    "hfmm_tree_free", "hfmm_last_error", "hfmm_version",
+    "hfmm_tree_free", "hfmm_last_error", "hfmm_version", "hfmm_prepare_host",
+    "hfmm_server_create", "hfmm_server_submit", "hfmm_server_step", "hfmm_server_poll",
+    "hfmm_server_release", "hfmm_server_used_bytes", "hfmm_server_free",
 ]
 
 
@@ -86,12 +88,21 @@ def lib():
             "hfmm_tree_free": [vp],
             "hfmm_last_error": [],
             "hfmm_version": [],
+            "hfmm_prepare_host": [vp, dbl, i32, C.POINTER(i64)],
+            "hfmm_server_create": [i64, i32, C.POINTER(vp)],
+            "hfmm_server_submit": [vp, vp, dbl, i32, vp, vp, dbl, i32, i32, C.POINTER(i64), C.POINTER(i64)],
+            "hfmm_server_step": [vp, vp, C.POINTER(i32), C.POINTER(i32)],
+            "hfmm_server_poll": [vp, i64, C.POINTER(i32), C.POINTER(GmresInfo), C.POINTER(dbl)],
+            "hfmm_server_release": [vp, i64],
+            "hfmm_server_used_bytes": [vp, C.POINTER(i64)],
+            "hfmm_server_free": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = C.c_int
         L.hfmm_tree_free.restype = None
+        L.hfmm_server_free.restype = None
         L.hfmm_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -154,6 +165,12 @@ class Tree:
             pass
 
     # compute --------------------------------------------------------------
+    def prepare_host(self, k: float, P: int) -> int:
+        """Host-side plan for (k, P); returns the device bytes it will need."""
+        fp = C.c_int64()
+        _check(lib().hfmm_prepare_host(self._h, float(k), int(P), C.byref(fp)))
+        return fp.value
+
     def prepare(self, k: float, P: int, stream=None):
         import torch
         _check(lib().hfmm_prepare(self._h, float(k), int(P), _stream(torch, stream)))
@@ -231,3 +248,57 @@ def batch_matvec(trees, ks, Ps, xs, ys, stream=None):
     Y = (C.c_void_p * n)(*[y.data_ptr() for y in ys])
     _check(lib().hfmm_batch_matvec(n, H, K, PP, X, Y, _stream(torch, stream)))
     return ys
+
+
+class Server:
+    """Continuous-batching solve server (see hfmm_server_* in include/hfmm.h)."""
+
+    QUEUED, ACTIVE, CONVERGED, NOTCONV, FAILED = 0, 1, 2, 3, -1
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_active: int = 16):
+        h = C.c_void_p()
+        _check(lib().hfmm_server_create(int(hbm_budget_bytes), int(max_active), C.byref(h)))
+        self._h = h
+
+    def submit(self, tree: Tree, k: float, P: int, b, x, tol=1e-4, restart=30, maxit=2000):
+        """Queues A x = b on a BIE handle; b, x complex128 CUDA tensors."""
+        import torch
+        assert b.dtype == torch.complex128 and x.dtype == torch.complex128 and b.is_cuda and x.is_cuda
+        t = C.c_int64()
+        fp = C.c_int64()
+        _check(lib().hfmm_server_submit(self._h, tree._h, float(k), int(P), C.c_void_p(b.data_ptr()),
+                                        C.c_void_p(x.data_ptr()), float(tol), int(restart), int(maxit),
+                                        C.byref(t), C.byref(fp)))
+        return t.value, fp.value
+
+    def step(self, stream=None):
+        import torch
+        na, nq = C.c_int32(), C.c_int32()
+        _check(lib().hfmm_server_step(self._h, _stream(torch, stream), C.byref(na), C.byref(nq)))
+        return na.value, nq.value
+
+    def poll(self, ticket: int):
+        st = C.c_int32()
+        info = GmresInfo()
+        times = (C.c_double * 3)()
+        _check(lib().hfmm_server_poll(self._h, int(ticket), C.byref(st), C.byref(info), times))
+        return st.value, info.as_dict(), list(times)
+
+    def release(self, ticket: int):
+        _check(lib().hfmm_server_release(self._h, int(ticket)))
+
+    def used_bytes(self) -> int:
+        u = C.c_int64()
+        _check(lib().hfmm_server_used_bytes(self._h, C.byref(u)))
+        return u.value
+
+    def free(self):
+        if self._h and self._h.value:
+            lib().hfmm_server_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
