@@ -7,6 +7,15 @@ real and imaginary parts uniform in [-1, 1].  Tree, lists and translation
 operators are built before the timed region; inputs are resident in HBM.
 One step = one full FMM matvec (P2M, M2M, M2L, L2L, L2P, P2P).
 
+Other workloads (`--workload`):
+  batch  64 instances (N log-uniform in [2048, 65536], k uniform in [1, 20],
+         spheres and ellipsoids alternating, P = 10): aggregate matvecs/s of
+         one fused, graph-replayed launch sequence vs 64 sequential matvecs;
+  serve  Poisson arrivals at 50/s of sound-soft scattering solves
+         (icosphere subdivision 3..6, sphere or ellipsoid, k uniform in
+         [1, 30], P = 10, GMRES(30) to 1e-4): solves/s and p50/p99 latency of
+         the continuous-batching server vs the one-at-a-time path.
+
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
 one GPU.
 """
@@ -76,8 +85,118 @@ def cpu_baseline(x, q, k, P, ncrit, stats, budget_s=15.0):
     }
 
 
+def traffic_of(a, kernel):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter
+    summaries (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known
+    size), if they were taken for this exact kernel build; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        e = d[kernel]
+        if e.get("source_sha") != _kernel_source_sha():
+            return None
+        return e["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _kernel_source_sha():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1803_09948_amd", "csrc", "fmm_kernels.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def bench_copy(a):
+    """A plain device copy of known size (calibrates the traffic counters)."""
+    import torch
+    n = a.copy_mib << 20
+    x = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n, "launches": 3}))
+
+
+def bench_batch(a):
+    import torch
+
+    import synth
+    from paper_1803_09948_amd import hfmm
+
+    inst = synth.batch_instances(count=a.count, seed=4242)
+    P = 10
+    trees = [hfmm.Tree.from_points(d["points"]) for d in inst]
+    ks = [d["k"] for d in inst]
+    xs = [torch.from_numpy(d["q"]).to("cuda") for d in inst]
+    ys = [torch.empty_like(x) for x in xs]
+    t0 = time.perf_counter()
+    for t, k in zip(trees, ks):
+        t.prepare(k, P)
+    torch.cuda.synchronize()
+    log(f"setup {time.perf_counter() - t0:.2f} s; total points {sum(d['n'] for d in inst)}")
+    for _ in range(a.warmup):
+        hfmm.batch_matvec(trees, ks, [P] * len(trees), xs, ys)
+        for t, k, x, y in zip(trees, ks, xs, ys):
+            t.matvec(k, P, x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        hfmm.batch_matvec(trees, ks, [P] * len(trees), xs, ys)
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / a.steps
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        for t, k, x, y in zip(trees, ks, xs, ys):
+            t.matvec(k, P, x, y)
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t0) / a.steps
+    out = {
+        "metric": "batched FMM matvecs/s (64 instances, one fused graph launch)",
+        "value": len(trees) / dt_b, "unit": "matvec/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt_b * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(trees)} instances, N log-uniform [2048, 65536] "
+                               f"(total {sum(d['n'] for d in inst)}), k uniform [1, 20], P=10, "
+                               "spheres and ellipsoids alternating"},
+        "sequential": {"value": len(trees) / dt_s, "ms_per_step": dt_s * 1e3},
+        "speedup_vs_sequential": dt_s / dt_b,
+    }
+    print(json.dumps(out))
+
+
+def bench_serve(a):
+    import synth
+    from paper_1803_09948_amd import serve
+
+    trace = synth.serve_trace(nreq=a.nreq, rate=50.0, seed=777)
+    log(f"serving {a.nreq} requests")
+    st = serve.serve(trace, max_active=a.slots, log=log)
+    log("served", st)
+    sp = serve.serve_plain(trace, log=log) if not a.no_plain else None
+    log("plain", sp)
+    out = {
+        "metric": "served BIE solves/s and p99 latency (Poisson 50 req/s)",
+        "value": st["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": st["n"], "warmup": 0,
+        "ms_per_step": st["mean_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{a.nreq} requests, Poisson 50/s, icosphere subdivision 3..6, sphere or "
+                               "ellipsoid, k uniform [1, 30], P=10, GMRES(30) to 1e-4", "slots": a.slots},
+        "served": st, "plain": sp,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "copy"], default="matvec")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--count", type=int, default=64, help="instances (batch workload)")
+    ap.add_argument("--nreq", type=int, default=24, help="requests (serve workload)")
+    ap.add_argument("--slots", type=int, default=16, help="concurrent solves (serve workload)")
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
@@ -92,6 +211,12 @@ def main():
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if a.workload == "batch":
+        return bench_batch(a)
+    if a.workload == "serve":
+        return bench_serve(a)
+    if a.workload == "copy":
+        return bench_copy(a)
 
     import torch
 
@@ -128,26 +253,24 @@ def main():
     log(f"timed {a.steps} steps: {ms:.3f} ms/step")
     # per-phase device times from HIP events on the launch stream (separate pass)
     tree.set_timing(True)
-    ph = np.zeros(8)
+    acc = {}
     nrep = max(3, min(10, a.steps))
     for _ in range(nrep):
         tree.matvec(a.k, a.P, qd, yd)
-        ph += tree.phase_times()
-    ph /= nrep
+        for kk, v in tree.phase_times().items():
+            acc[kk] = acc.get(kk, 0.0) + v / nrep
     tree.set_timing(False)
-    names = ["p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "bie", "total"]
-    phases = {n: round(float(v), 4) for n, v in zip(names, ph)}
+    phases = {n: round(v, 4) for n, v in acc.items()}
     log("phases (ms):", phases)
-    P2 = a.P * a.P
     m2l_flops = 8.0 * a.P ** 4 * st["n_m2l"]
     p2p_flops = 20.0 * st["p2p_body_pairs"]
     m2l_ach = m2l_flops / (phases["m2l"] * 1e-3)
     p2p_ach = p2p_flops / (phases["p2p"] * 1e-3)
     dominant = "m2l" if phases["m2l"] >= phases["p2p"] else "p2p"
     if dominant == "m2l":
-        roof = {"kernel": "k_m2l", "bound": "alu", "achieved": m2l_ach / 1e12, "peak": PEAK_FP32 / 1e12,
-                "unit": "TFLOP/s", "frac": m2l_ach / PEAK_FP32, "traffic": None,
-                "per_unit": "8 P^4 FLOP per M2L pair (dense P^2 x P^2 complex operator)",
+        roof = {"kernel": "k_m2l_mfma", "bound": "mfma", "achieved": m2l_ach / 1e12, "peak": PEAK_FP32 / 1e12,
+                "unit": "TFLOP/s", "frac": m2l_ach / PEAK_FP32, "traffic": traffic_of(a, "k_m2l_mfma"),
+                "per_unit": "8 P^4 FLOP per M2L pair (dense P^2 x P^2 complex operator, FP32 MFMA)",
                 "units_per_launch": st["n_m2l"], "launch_ms": phases["m2l"]}
     else:
         roof = {"kernel": "k_p2p", "bound": "alu", "achieved": p2p_ach / 1e12, "peak": PEAK_FP32 / 1e12,

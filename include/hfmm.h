@@ -206,12 +206,14 @@ int hfmm_tree_export(hfmm_tree* tree, double k, int32_t P, int32_t* src_perm,
 int hfmm_lists_export(hfmm_tree* tree, double k, int32_t P, int32_t* m2l_pairs,
                       int32_t* p2p_pairs);
 
-/* Per-phase device times (ms) of the last hfmm_matvec when timing is on:
- * [0] P2M, [1] M2M, [2] M2L, [3] L2L, [4] L2P, [5] P2P, [6] BIE corrections,
- * [7] total.  hfmm_set_timing(tree, 1) records HIP events around each phase
- * on the call's stream. */
+/* Per-phase device times (ms) of the last hfmm_matvec while timing is on,
+ * from HIP events recorded on the call's stream around each launch group:
+ * [0] P2M (with clearing and gathering the strengths), [1] M2M, [2] M2L
+ * matrix-core kernel, [3] M2L reduction, [4] L2L, [5] L2P, [6] P2P, [7]
+ * output scatter and BIE corrections, [8] total, [9] unused.
+ * hfmm_set_timing(tree, 1) turns the events on (they add a little overhead). */
 int hfmm_set_timing(hfmm_tree* tree, int32_t on);
-int hfmm_phase_times(const hfmm_tree* tree, float* ms8);
+int hfmm_phase_times(const hfmm_tree* tree, float* ms10);
 
 void hfmm_tree_free(hfmm_tree* tree);
 const char* hfmm_last_error(void);

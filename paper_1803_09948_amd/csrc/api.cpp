@@ -264,15 +264,40 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     if (p.x != q.x) return p.x < q.x;
     return p.y < q.y;
   });
+  // staging slots: pairs ordered by (target, source), so each target's
+  // slots are contiguous and summed in a fixed order
+  std::vector<int32_t> slot(npair);
+  {
+    std::vector<int32_t> bytgt(npair);
+    std::iota(bytgt.begin(), bytgt.end(), 0);
+    std::sort(bytgt.begin(), bytgt.end(), [&](int32_t x, int32_t y) {
+      const int4 &p = pairs[x], &q = pairs[y];
+      if (p.x != q.x) return p.x < q.x;
+      return p.y < q.y;
+    });
+    hd.soff.assign(h.ncell() + 1, 0);
+    for (size_t r = 0; r < npair; ++r) {
+      slot[bytgt[r]] = (int32_t)r;
+      hd.soff[pairs[bytgt[r]].x + 1]++;
+    }
+    for (int c = 0; c < h.ncell(); ++c) {
+      if (hd.soff[c + 1] > 0) pl.m2l_targets.push_back(c);
+      hd.soff[c + 1] += hd.soff[c];
+    }
+  }
   std::vector<int4>& spairs = hd.spairs;
   spairs.resize(npair);
   std::vector<int4> chunks;
-  for (size_t i = 0; i < npair; ++i) spairs[i] = pairs[order[i]];
+  for (size_t i = 0; i < npair; ++i) {
+    const int4& p = pairs[order[i]];
+    spairs[i] = make_int4(p.x, p.y, p.z, slot[order[i]]);
+  }
   const int CH = m2l_pairs_per_chunk(P);
   for (size_t i = 0; i < npair;) {
     size_t j = i;
-    while (j < npair && spairs[j].w == spairs[i].w && j - i < (size_t)CH) ++j;
-    chunks.push_back(make_int4(spairs[i].w, (int)i, (int)j, 0));
+    const int op = pairs[order[i]].w;
+    while (j < npair && pairs[order[j]].w == op && j - i < (size_t)CH) ++j;
+    chunks.push_back(make_int4(op, (int)i, (int)j, 0));
     i = j;
   }
   pl.n_m2l_chunks = (int32_t)chunks.size();
@@ -335,12 +360,17 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
   std::vector<int32_t>& oph = hd.oph;
   oidx.assign(16 * P2, 0);
   oph.assign(16 * P2, 0);
+  int Kp0, Rp0;
+  table_dims(P, &Kp0, &Rp0);
+  hd.inmap.assign(16 * Kp0, 4);  // padding rows: zero
   symmetry_map(P, sdst, sph);
   for (int g = 0; g < 16; ++g)
     for (int o = 0; o < P2; ++o) {
       int r = sdst[g * P2 + o];
       oidx[g * P2 + r] = o;
       oph[g * P2 + r] = (4 - sph[g * P2 + o]) & 3;
+      // inputs: B[k] = i^ph(c) M[c] with c the image of k (the map is an involution)
+      hd.inmap[g * Kp0 + r] = (o << 3) | sph[g * P2 + o];
     }
   pl.n_ops = (int64_t)ops.size();
   // exact device footprint of this plan (and of the bodies if not yet resident)
@@ -350,6 +380,7 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     const int64_t nc = h.ncell();
     int64_t b = nc * (int64_t)(sizeof(int4) * 2 + sizeof(float4) + sizeof(int32_t) + sizeof(int2));
     b += (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)Kp * Rp * sizeof(float2));
+    b += (int64_t)spairs.size() * (16 + (int64_t)P2 * (int64_t)sizeof(float2)) + (nc + 1) * 4;
     b += (int64_t)pl.rho.size() * 8 + (int64_t)spairs.size() * 16 + (int64_t)work.size() * 20 +
          (int64_t)ivals.size() * 8 + 2 * 16 * (int64_t)P2 * 4 + 2 * nc * P2 * (int64_t)sizeof(float2);
     if (t.bie) b += (int64_t)t.near_col.size() * 8 + t.npanel * 16;
@@ -372,9 +403,12 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   const double k = pl.k;
   if ((rc = upload(pl.d_ops, hd.ops)) || (rc = upload(pl.d_rho, pl.rho)) ||
       (rc = upload(pl.d_m2l_pairs, hd.spairs)) || (rc = upload(pl.d_cops, hd.cops)) ||
+      (rc = upload(pl.d_m2l_soff, hd.soff)) ||
+      (rc = pl.d_stage.alloc(std::max<size_t>(1, hd.spairs.size()) * (size_t)P2 * sizeof(float2))) ||
       (rc = upload(pl.d_p2p_work, hd.work)) || (rc = upload(pl.d_p2p_ivals, hd.ivals)) ||
       (rc = upload(pl.d_p2p_total, hd.totals)) ||
-      (rc = upload(pl.d_outidx, hd.oidx)) || (rc = upload(pl.d_outph, hd.oph)))
+      (rc = upload(pl.d_outidx, hd.oidx)) || (rc = upload(pl.d_outph, hd.oph)) ||
+      (rc = upload(pl.d_inmap, hd.inmap)))
     return rc;
   // coupling coefficients and tables
   const Coupling& cp = coupling(P);
@@ -396,7 +430,8 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   pl.device_bytes = 0;
   for (DevBuf* b : {&pl.d_cells, &pl.d_geo, &pl.d_clev, &pl.d_topo, &pl.d_ops, &pl.d_tables, &pl.d_rho,
                     &pl.d_m2l_pairs, &pl.d_p2p_work, &pl.d_p2p_ivals, &pl.d_p2p_total, &pl.d_outidx,
-                    &pl.d_outph, &pl.d_M, &pl.d_L, &pl.d_cops})
+                    &pl.d_outph, &pl.d_M, &pl.d_L, &pl.d_cops, &pl.d_stage, &pl.d_m2l_soff,
+                    &pl.d_inmap})
     pl.device_bytes += (int64_t)b->bytes;
   if (t.bie && (rc = prepare_bie(t, pl, s))) {
     pl.d_tables.reset();  // not device-ready: the next prepare retries
@@ -564,16 +599,16 @@ int hfmm_matvec(hfmm_tree* tree, double k, int32_t P, const void* x, void* y, vo
   if (t.timing) {
     HIP_TRY(hipEventSynchronize(t.ev[8]));
     float ms;
-    // phases: P2M (0-1), M2M (1-2), M2L (2-3), L2L (3-4), L2P (4-5), P2P (5-6),
-    // output scatter and BIE corrections (6-8)
-    for (int i = 0; i < 6; ++i) {
+    // phases: P2M (0-1), M2M (1-2), M2L matrix-core kernel (2-3), M2L
+    // reduction (3-4), L2L (4-5), L2P (5-6), P2P (6-7), output scatter and
+    // BIE corrections (7-8), total (0-8)
+    for (int i = 0; i < 8; ++i) {
       HIP_TRY(hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]));
       t.phase_ms[i] = ms;
     }
-    HIP_TRY(hipEventElapsedTime(&ms, t.ev[6], t.ev[8]));
-    t.phase_ms[6] = ms;
     HIP_TRY(hipEventElapsedTime(&ms, t.ev[0], t.ev[8]));
-    t.phase_ms[7] = ms;
+    t.phase_ms[8] = ms;
+    t.phase_ms[9] = 0.f;
   }
   return HFMM_OK;
   API_GUARD_END
@@ -585,9 +620,9 @@ int hfmm_set_timing(hfmm_tree* tree, int32_t on) {
   return HFMM_OK;
 }
 
-int hfmm_phase_times(const hfmm_tree* tree, float* ms8) {
-  if (!tree || !ms8) return set_error("NULL argument"), HFMM_EINVAL;
-  std::memcpy(ms8, reinterpret_cast<const Tree*>(tree)->phase_ms, 8 * sizeof(float));
+int hfmm_phase_times(const hfmm_tree* tree, float* ms10) {
+  if (!tree || !ms10) return set_error("NULL argument"), HFMM_EINVAL;
+  std::memcpy(ms10, reinterpret_cast<const Tree*>(tree)->phase_ms, 10 * sizeof(float));
   return HFMM_OK;
 }
 

@@ -51,6 +51,8 @@ static InstDev make_inst(Tree& t, Plan& pl) {
   I.M = pl.d_M.as<float2>();
   I.L = pl.d_L.as<float2>();
   I.m2l_pairs = pl.d_m2l_pairs.as<int4>();
+  I.stage = pl.d_stage.as<float2>();
+  I.m2l_soff = pl.d_m2l_soff.as<int32_t>();
   I.p2p_work = pl.d_p2p_work.as<int4>();
   I.p2p_ivals = pl.d_p2p_ivals.as<int2>();
   I.p2p_total = pl.d_p2p_total.as<int32_t>();
@@ -77,7 +79,7 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
   b.plans = plans;
   b.hinst.clear();
   const int ch = elem_chunk();
-  std::vector<int2> zero, gather, scatter, p2m, l2p, p2p;
+  std::vector<int2> zero, gather, scatter, p2m, l2p, p2p, red;
   std::vector<int4> m2l;
   b.maxlev = 0;
   for (int i = 0; i < b.count; ++i) {
@@ -92,6 +94,7 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
     for (int c : pl.tgt_leaves) l2p.push_back(make_int2(i, c));
     for (int w = 0; w < pl.n_p2p_work; ++w) p2p.push_back(make_int2(i, w));
     for (const int4& c : pl.m2l_chunks_h) m2l.push_back(make_int4(i, c.x, c.y, c.z));
+    for (int c : pl.m2l_targets) red.push_back(make_int2(i, c));
   }
   // per-level M2M (parents, deepest first) and L2L (children, root first) lists
   std::vector<int2> m2m, l2l;
@@ -113,7 +116,8 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
   int rc;
   if ((rc = up(b.d_inst, b.hinst)) || (rc = up(b.d_zero, zero)) || (rc = up(b.d_gather, gather)) ||
       (rc = up(b.d_scatter, scatter)) || (rc = up(b.d_p2m, p2m)) || (rc = up(b.d_l2p, l2p)) ||
-      (rc = up(b.d_p2p, p2p)) || (rc = up(b.d_m2l, m2l)) || (rc = up(b.d_m2m, m2m)) || (rc = up(b.d_l2l, l2l)))
+      (rc = up(b.d_p2p, p2p)) || (rc = up(b.d_m2l, m2l)) || (rc = up(b.d_m2m, m2m)) || (rc = up(b.d_l2l, l2l)) ||
+      (rc = up(b.d_red, red)))
     return rc;
   b.n_zero = (int)zero.size();
   b.n_gather = (int)gather.size();
@@ -122,6 +126,7 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
   b.n_l2p = (int)l2p.size();
   b.n_p2p = (int)p2p.size();
   b.n_m2l = (int)m2l.size();
+  b.n_red = (int)red.size();
   return HFMM_OK;
 }
 
@@ -144,17 +149,19 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   for (int l = b.maxlev - 2; l >= 0; --l)
     launch_m2m(b.d_m2m.as<int2>() + b.m2m_off[l], b.m2m_off[l + 1] - b.m2m_off[l], I, P, s);
   if ((rc = mark(2))) return rc;
-  launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, P, p0.d_outidx.as<int32_t>(), p0.d_outph.as<int32_t>(), s);
+  launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, P, p0.d_outidx.as<int32_t>(), p0.d_outph.as<int32_t>(),
+             p0.d_inmap.as<int32_t>(), s);
   if ((rc = mark(3))) return rc;
+  launch_m2l_reduce(b.d_red.as<int2>(), b.n_red, I, P, s);
+  if ((rc = mark(4))) return rc;
   for (int l = 1; l < b.maxlev; ++l)
     launch_l2l(b.d_l2l.as<int2>() + b.l2l_off[l], b.l2l_off[l + 1] - b.l2l_off[l], I, P, s);
-  if ((rc = mark(4))) return rc;
-  launch_l2p(b.d_l2p.as<int2>(), b.n_l2p, I, P, s);
   if ((rc = mark(5))) return rc;
-  launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, s);
+  launch_l2p(b.d_l2p.as<int2>(), b.n_l2p, I, P, s);
   if ((rc = mark(6))) return rc;
-  launch_scatter(b.d_scatter.as<int2>(), b.n_scatter, I, s);
+  launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, s);
   if ((rc = mark(7))) return rc;
+  launch_scatter(b.d_scatter.as<int2>(), b.n_scatter, I, s);
   HIP_TRY(hipGetLastError());
   return HFMM_OK;
 }

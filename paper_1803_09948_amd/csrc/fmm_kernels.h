@@ -41,7 +41,9 @@ struct InstDev {
   const float2* tables;     // [op][Kp][Rp]
   float2* M;                // multipoles [ncell][P^2]
   float2* L;                // locals [ncell][P^2]
-  const int4* m2l_pairs;    // (target, source, symmetry, op)
+  const int4* m2l_pairs;    // (target, source, symmetry, staging slot)
+  float2* stage;            // M2L staging [n pairs][P^2], slots ordered by target
+  const int32_t* m2l_soff;  // per cell: first staging slot (ncell + 1 entries)
   const int4* p2p_work;     // (tgt begin, tgt end, interval begin, interval end)
   const int2* p2p_ivals;    // (src begin, src end)
   const int32_t* p2p_total; // sources per work item
@@ -67,7 +69,10 @@ void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream
 void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s);
 int m2l_pairs_per_chunk(int P);
 // chunks: (instance, op, pair begin, pair end), sorted by (instance, op)
+// L[t] = sum of the staging slots of t (items: instance, target cell)
+void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
+// inmap[g][k] = (c << 3) | (zero << 2) | phase: input map of reflection g, k < Kp
 void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, const int32_t* outidx,
-                const int32_t* outph, hipStream_t s);
+                const int32_t* outph, const int32_t* inmap, hipStream_t s);
 
 }  // namespace hfmm

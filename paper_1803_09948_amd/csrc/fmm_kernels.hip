@@ -413,12 +413,31 @@ __device__ inline int sym_m(int g, int n, int m, int& ph) {
   return m;
 }
 
+// Global-address-space views of pointers read from the instance table (so
+// that loads through them are global loads, not flat ones).
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) f2v gcfloat2;
+typedef __attribute__((address_space(1))) f2v gfloat2;
+__device__ inline float2 ld2(gcfloat2* p) {
+  const f2v v = *p;
+  return make_float2(v.x, v.y);
+}
+
+// Branch-free multiply by i^code.
+__device__ inline float2 mul_ipow_sel(float2 a, int code) {
+  const bool sw = code & 1;
+  const float x = sw ? a.y : a.x, y = sw ? a.x : a.y;
+  const bool nx = (code == 1) | (code == 2), ny = code >= 2;
+  return make_float2(nx ? -x : x, ny ? -y : y);
+}
+
 template <int RT, int NCT>
 __global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks, int nchunks,
                                                  int per_xcd, const InstDev* __restrict__ insts,
                                                  int Kp, int Rp, const int32_t* __restrict__ outidx,
-                                                 const int32_t* __restrict__ outph, int P2) {
-  extern __shared__ float2 Cs[];    // [16 NCT][16 RT + 1] output transpose
+                                                 const int32_t* __restrict__ outph,
+                                                 const int32_t* __restrict__ inmap, int P2) {
+  extern __shared__ float2 Cs[];    // [16 NCT][16 RT + 1] output transpose, then input map
   const int b = blockIdx.x;
   const int chunk = (b & 7) * per_xcd + (b >> 3);
   if (chunk >= nchunks) return;
@@ -426,36 +445,45 @@ __global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks
   const InstDev& I = insts[ch.x];
   const int op = ch.y, pb = ch.z, np = ch.w - ch.z;
   const int4* __restrict__ pairs = I.m2l_pairs;
-  const float2* __restrict__ M = I.M;
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
-  int src[NCT], gs[NCT];
+  // LDS: [0, CS*16) output transpose of one 16-pair tile; then the reflections' input map
+  // inmap[g][k] = (c << 3) | (zero << 2) | phase (B[k] = i^phase M[c]), their
+  // output map outmap[g][r] = o | (phase << 16), and this chunk's pairs
+  constexpr int CS = 16 * RT + 1;
+  int* smap = reinterpret_cast<int*>(Cs + CS * 16);
+  int* somap = smap + 16 * Kp;
+  int4* spr = reinterpret_cast<int4*>(somap + 16 * P2 + 4 - ((16 * Kp + 16 * P2) & 3));
+  for (int e = lane; e < 16 * Kp; e += 64) smap[e] = inmap[e];
+  for (int e = lane; e < 16 * P2; e += 64) somap[e] = outidx[e] | (outph[e] << 16);
+  if (lane < np) spr[lane] = pairs[pb + lane];
+  __syncthreads();
+  gcfloat2* Ms[NCT];
+  int grow[NCT];
+  float okc[NCT];
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
     const int p = 16 * t + li;
-    if (p < np) {
-      const int4 pr = pairs[pb + p];
-      src[t] = pr.y;
-      gs[t] = pr.z;
-    } else {
-      src[t] = -1;
-      gs[t] = 0;
-    }
+    const bool ok = p < np;
+    const int4 pr = spr[ok ? p : 0];
+    Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
+    grow[t] = pr.z * Kp;
+    okc[t] = ok ? 1.f : 0.f;
   }
-  // B[k][p] = (D^T M_src)[k] = i^ph(c) M_src[c] with c the image of k under g
-  auto load_b = [&](int k, float2* out) {
-    const int n = (int)sqrtf((float)k + 0.5f);
-    const int m = k - n * n - n;
+  // B gather: issue the loads now, apply scale and phase when the step runs
+  auto load_b = [&](int k, float2* raw, int* code) {
 #pragma unroll
     for (int t = 0; t < NCT; ++t) {
-      float2 v = make_float2(0.f, 0.f);
-      if (k < P2 && src[t] >= 0) {
-        int ph0, ph1;
-        const int mc = sym_m(gs[t], n, m, ph0);
-        sym_m(gs[t], n, mc, ph1);
-        v = mul_ipow(M[(size_t)src[t] * P2 + n * n + n + mc], ph1);
-      }
-      out[t] = v;
+      const int e = smap[grow[t] + k];
+      raw[t] = ld2(Ms[t] + (e >> 3));
+      code[t] = e & 7;
+    }
+  };
+  auto finish_b = [&](const float2* raw, const int* code, float2* out) {
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) {
+      const float sc = (code[t] & 4) ? 0.f : okc[t];
+      out[t] = mul_ipow_sel(make_float2(raw[t].x * sc, raw[t].y * sc), code[t] & 3);
     }
   };
   floatx4 cr[NCT][RT], ci[NCT][RT];
@@ -466,54 +494,111 @@ __global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks
       cr[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
       ci[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  const float2* T = I.tables + (size_t)op * Kp * Rp;
+  gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li;
   const int KS = Kp >> 2;
-  float2 a[RT], an[RT], bv[NCT], bn[NCT];
+  // two register buffers, alternating k-steps; the loads of one step are in
+  // flight while the other step's MFMAs run (a straight-line loop body keeps
+  // the compiler's wait counts exact)
+  float2 a0[RT], a1[RT], b0[NCT], b1[NCT], bv[NCT];
+  int c0[NCT], c1[NCT];
+  auto load_a = [&](int k, float2* out) {
 #pragma unroll
-  for (int r = 0; r < RT; ++r) a[r] = T[(size_t)lk * Rp + 16 * r + li];
-  load_b(lk, bv);
-  for (int ks = 0; ks < KS; ++ks) {
-    const int k = 4 * ks + lk;
-    if (ks + 1 < KS) {
-#pragma unroll
-      for (int r = 0; r < RT; ++r) an[r] = T[(size_t)(k + 4) * Rp + 16 * r + li];
-      load_b(k + 4, bn);
-    }
+    for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * r);
+  };
+  auto mma = [&](const float2* a, const float2* bv) {
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
       const float ar = a[r].x, ai = a[r].y, nai = -a[r].y;
 #pragma unroll
       for (int t = 0; t < NCT; ++t) {
         cr[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bv[t].x, cr[t][r], 0, 0, 0);
-        cr[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bv[t].y, cr[t][r], 0, 0, 0);
         ci[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bv[t].y, ci[t][r], 0, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) {
+        cr[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bv[t].y, cr[t][r], 0, 0, 0);
         ci[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bv[t].x, ci[t][r], 0, 0, 0);
       }
     }
-#pragma unroll
-    for (int r = 0; r < RT; ++r) a[r] = an[r];
-#pragma unroll
-    for (int t = 0; t < NCT; ++t) bv[t] = bn[t];
+  };
+  const int klast = Kp - 4 + lk;  // clamp: redundant in-bounds loads past the end are unused
+  load_a(lk, a0);
+  load_b(lk, b0, c0);
+  int ks = 0;
+  for (; ks + 2 <= KS; ks += 2) {
+    const int k1 = 4 * (ks + 1) + lk, k2 = min(4 * (ks + 2) + lk, klast);
+    load_a(k1, a1);
+    load_b(k1, b1, c1);
+    __builtin_amdgcn_sched_barrier(0);  // issue the next step's loads before these MFMAs
+    finish_b(b0, c0, bv);
+    mma(a0, bv);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(k2, a0);
+    load_b(k2, b0, c0);
+    __builtin_amdgcn_sched_barrier(0);
+    finish_b(b1, c1, bv);
+    mma(a1, bv);
+    __builtin_amdgcn_sched_barrier(0);
   }
-  constexpr int CS = 16 * RT + 1;
+  if (ks < KS) {
+    finish_b(b0, c0, bv);
+    mma(a0, bv);
+  }
+  // each pair owns a staging slot (slots are ordered by target); the
+  // reduction kernel below adds a target's slots in a fixed order.  One
+  // 16-pair tile at a time goes through the LDS transpose.
 #pragma unroll
-  for (int t = 0; t < NCT; ++t)
+  for (int t = 0; t < NCT; ++t) {
+    if (t) __syncthreads();
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        Cs[(16 * t + li) * CS + 16 * r + 4 * lk + v] = make_float2(cr[t][r][v], ci[t][r][v]);
-  __syncthreads();
-  for (int p = 0; p < np; ++p) {
-    const int4 pr = pairs[pb + p];
-    const int g = pr.z;
-    float2* Lt = I.L + (size_t)pr.x * P2;
-    for (int row = lane; row < P2; row += 64) {
-      const int o = outidx[g * P2 + row];
-      const float2 val = mul_ipow(Cs[p * CS + row], outph[g * P2 + row]);
-      atomicAdd(&Lt[o].x, val.x);
-      atomicAdd(&Lt[o].y, val.y);
+      for (int v = 0; v < 4; ++v) Cs[li * CS + 16 * r + 4 * lk + v] = make_float2(cr[t][r][v], ci[t][r][v]);
+    __syncthreads();
+    const int pend = min(np, 16 * (t + 1));
+    for (int p = 16 * t; p < pend; ++p) {
+      const int4 pr = spr[p];
+      const int* om = somap + pr.z * P2;
+      gfloat2* St = (gfloat2*)(I.stage + (size_t)pr.w * P2);
+      const float2* C = Cs + (p - 16 * t) * CS;
+      for (int row = lane; row < P2; row += 64) {
+        const int m = om[row];
+        const float2 v = mul_ipow_sel(C[row], m >> 16);
+        St[m & 0xffff] = f2v{v.x, v.y};
+      }
     }
+  }
+}
+
+// L[t] = sum of t's staging slots, in slot order (deterministic).  Items:
+// (instance, target cell); the cell's slots are [soff[t], soff[t+1]).
+__global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ items,
+                                                    const InstDev* __restrict__ insts, int P2) {
+  const int2 it = items[blockIdx.x];
+  const InstDev& I = insts[it.x];
+  const int cell = it.y;
+  const int s0 = I.m2l_soff[cell], s1 = I.m2l_soff[cell + 1];
+  for (int c = threadIdx.x; c < P2; c += blockDim.x) {
+    float sr = 0.f, si = 0.f;
+    gcfloat2* S = (gcfloat2*)(I.stage + (size_t)s0 * P2 + c);
+    int q = s0;
+    for (; q + 4 <= s1; q += 4, S += 4 * P2) {  // four loads in flight, added in slot order
+      const float2 v0 = ld2(S), v1 = ld2(S + P2), v2 = ld2(S + 2 * P2), v3 = ld2(S + 3 * P2);
+      sr += v0.x;
+      si += v0.y;
+      sr += v1.x;
+      si += v1.y;
+      sr += v2.x;
+      si += v2.y;
+      sr += v3.x;
+      si += v3.y;
+    }
+    for (; q < s1; ++q, S += P2) {
+      const float2 v = ld2(S);
+      sr += v.x;
+      si += v.y;
+    }
+    I.L[(size_t)cell * P2 + c] = make_float2(sr, si);
   }
 }
 
@@ -739,22 +824,27 @@ void launch_l2l(const int2* items, int n, const InstDev* insts, int P, hipStream
 void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
   if (n > 0) k_l2p<<<n, 64, 0, s>>>(items, insts, P);
 }
+void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
+  if (n > 0) k_m2l_reduce<<<n, 128, 0, s>>>(items, insts, P * P);
+}
 void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s) {
   if (n > 0) k_p2p<<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
 }
 
 template <int RT, int NCT>
 static void launch_m2l_mfma_t(const int4* chunks, int nchunks, const InstDev* insts, int Kp, int Rp,
-                              const int32_t* outidx, const int32_t* outph, int P2, hipStream_t s) {
+                              const int32_t* outidx, const int32_t* outph, const int32_t* inmap, int P2,
+                              hipStream_t s) {
   const int per = (nchunks + 7) / 8;
-  const size_t lds = (size_t)(16 * NCT) * (16 * RT + 1) * sizeof(float2);
-  k_m2l_mfma<RT, NCT><<<8 * per, 64, lds, s>>>(chunks, nchunks, per, insts, Kp, Rp, outidx, outph, P2);
+  const size_t lds = (size_t)16 * (16 * RT + 1) * sizeof(float2) +
+                     ((size_t)16 * Kp + 16 * P2 + 4) * sizeof(int) + (size_t)(16 * NCT) * sizeof(int4);
+  k_m2l_mfma<RT, NCT><<<8 * per, 64, lds, s>>>(chunks, nchunks, per, insts, Kp, Rp, outidx, outph, inmap, P2);
 }
 
 int m2l_pairs_per_chunk(int P) { return P * P > 240 ? 16 : 32; }
 
 void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, const int32_t* outidx,
-                const int32_t* outph, hipStream_t s) {
+                const int32_t* outph, const int32_t* inmap, hipStream_t s) {
   if (nchunks <= 0) return;
   const int P2 = P * P;
   int Kp, Rp;
@@ -763,9 +853,9 @@ void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, co
 #define M2L_CASE(R)                                                                             \
   case R:                                                                                       \
     if (P2 > 240)                                                                               \
-      launch_m2l_mfma_t<R, 1>(chunks, nchunks, insts, Kp, Rp, outidx, outph, P2, s);            \
+      launch_m2l_mfma_t<R, 1>(chunks, nchunks, insts, Kp, Rp, outidx, outph, inmap, P2, s);     \
     else                                                                                        \
-      launch_m2l_mfma_t<R, 2>(chunks, nchunks, insts, Kp, Rp, outidx, outph, P2, s);            \
+      launch_m2l_mfma_t<R, 2>(chunks, nchunks, insts, Kp, Rp, outidx, outph, inmap, P2, s);     \
     break;
   switch (RT) {
     M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6) M2L_CASE(7) M2L_CASE(8)

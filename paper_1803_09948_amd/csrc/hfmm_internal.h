@@ -103,7 +103,7 @@ struct HostPlanData {
   std::vector<OpDesc> ops;
   std::vector<int4> spairs, work;
   std::vector<int2> ivals, cops;
-  std::vector<int32_t> totals, oidx, oph;
+  std::vector<int32_t> totals, oidx, oph, soff, inmap;
 };
 
 struct Plan {
@@ -131,8 +131,12 @@ struct Plan {
   DevBuf d_p2p_total;            // int32 sources per work item
   int32_t n_p2p_work = 0;
   DevBuf d_outidx, d_outph;      // int32 [16][P^2]: output map of each reflection
+  DevBuf d_inmap;                // int32 [16][Kp]: input map of each reflection
   DevBuf d_M, d_L;               // float2 [ncell][P^2]
   DevBuf d_cops;                 // int2 per cell: (M2M op as child, L2L op as child)
+  DevBuf d_stage;                // float2 [n M2L pairs][P^2] staging, slots ordered by target
+  DevBuf d_m2l_soff;             // int32 [ncell + 1]: first staging slot of each target cell
+  std::vector<int32_t> m2l_targets;  // cells that receive M2L
   // host work lists (cells / chunks of this instance)
   std::vector<int32_t> src_leaves, tgt_leaves;
   std::vector<std::vector<int32_t>> m2m_cells, l2l_cells;  // per level
@@ -154,8 +158,8 @@ struct Batch {
   std::vector<Plan*> plans;
   std::vector<InstDev> hinst;
   DevBuf d_inst;
-  DevBuf d_zero, d_gather, d_scatter, d_p2m, d_l2p, d_p2p, d_m2l, d_m2m, d_l2l, d_outidx, d_outph;
-  int n_zero = 0, n_gather = 0, n_scatter = 0, n_p2m = 0, n_l2p = 0, n_p2p = 0, n_m2l = 0;
+  DevBuf d_zero, d_gather, d_scatter, d_p2m, d_l2p, d_p2p, d_m2l, d_m2m, d_l2l, d_red;
+  int n_zero = 0, n_gather = 0, n_scatter = 0, n_p2m = 0, n_l2p = 0, n_p2p = 0, n_m2l = 0, n_red = 0;
   std::vector<int> m2m_off, l2l_off;  // per level offsets into d_m2m / d_l2l
   hipStream_t stream = nullptr;       // private stream for graph capture / replay
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -198,8 +202,8 @@ struct Tree {
   int64_t body_bytes = 0;
   std::map<std::pair<uint64_t, int>, std::unique_ptr<Plan>> plans;
   bool timing = false;
-  float phase_ms[8] = {0};
-  hipEvent_t ev[9] = {};
+  float phase_ms[10] = {0};
+  hipEvent_t ev[10] = {};
   bool ev_made = false;
   uint64_t uid = 0;
   ~Tree();

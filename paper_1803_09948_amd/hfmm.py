@@ -231,10 +231,13 @@ class Tree:
     def set_timing(self, on: bool = True):
         _check(lib().hfmm_set_timing(self._h, 1 if on else 0))
 
-    def phase_times(self):
-        a = np.zeros(8, np.float32)
+    PHASES = ["p2m", "m2m", "m2l", "m2l_reduce", "l2l", "l2p", "p2p", "scatter_bie", "total"]
+
+    def phase_times(self) -> dict:
+        """Per-phase device milliseconds of the last matvec (timing on)."""
+        a = np.zeros(10, np.float32)
         _check(lib().hfmm_phase_times(self._h, a.ctypes.data))
-        return a
+        return {n: float(v) for n, v in zip(self.PHASES, a)}
 
 
 def batch_matvec(trees, ks, Ps, xs, ys, stream=None):
