@@ -354,24 +354,6 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     }
   }
   pl.n_p2p_work = (int32_t)work.size();
-  // symmetry maps and their inverses for the outputs
-  std::vector<int32_t> sdst, sph;
-  std::vector<int32_t>& oidx = hd.oidx;
-  std::vector<int32_t>& oph = hd.oph;
-  oidx.assign(16 * P2, 0);
-  oph.assign(16 * P2, 0);
-  int Kp0, Rp0;
-  table_dims(P, &Kp0, &Rp0);
-  hd.inmap.assign(16 * Kp0, 4);  // padding rows: zero
-  symmetry_map(P, sdst, sph);
-  for (int g = 0; g < 16; ++g)
-    for (int o = 0; o < P2; ++o) {
-      int r = sdst[g * P2 + o];
-      oidx[g * P2 + r] = o;
-      oph[g * P2 + r] = (4 - sph[g * P2 + o]) & 3;
-      // inputs: B[k] = i^ph(c) M[c] with c the image of k (the map is an involution)
-      hd.inmap[g * Kp0 + r] = (o << 3) | sph[g * P2 + o];
-    }
   pl.n_ops = (int64_t)ops.size();
   // exact device footprint of this plan (and of the bodies if not yet resident)
   {
@@ -382,7 +364,7 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     b += (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)Kp * Rp * sizeof(float2));
     b += (int64_t)spairs.size() * (16 + (int64_t)P2 * (int64_t)sizeof(float2)) + (nc + 1) * 4;
     b += (int64_t)pl.rho.size() * 8 + (int64_t)spairs.size() * 16 + (int64_t)work.size() * 20 +
-         (int64_t)ivals.size() * 8 + 2 * 16 * (int64_t)P2 * 4 + 2 * nc * P2 * (int64_t)sizeof(float2);
+         (int64_t)ivals.size() * 8 + 2 * nc * P2 * (int64_t)sizeof(float2);
     if (t.bie) b += (int64_t)t.near_col.size() * 8 + t.npanel * 16;
     if (!t.uploaded) b += t.h.nsrc * 40 + t.h.ntgt * 32;
     pl.est_bytes = b;
@@ -406,9 +388,7 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
       (rc = upload(pl.d_m2l_soff, hd.soff)) ||
       (rc = pl.d_stage.alloc(std::max<size_t>(1, hd.spairs.size()) * (size_t)P2 * sizeof(float2))) ||
       (rc = upload(pl.d_p2p_work, hd.work)) || (rc = upload(pl.d_p2p_ivals, hd.ivals)) ||
-      (rc = upload(pl.d_p2p_total, hd.totals)) ||
-      (rc = upload(pl.d_outidx, hd.oidx)) || (rc = upload(pl.d_outph, hd.oph)) ||
-      (rc = upload(pl.d_inmap, hd.inmap)))
+      (rc = upload(pl.d_p2p_total, hd.totals)))
     return rc;
   // coupling coefficients and tables
   const Coupling& cp = coupling(P);
@@ -429,9 +409,8 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
     return rc;
   pl.device_bytes = 0;
   for (DevBuf* b : {&pl.d_cells, &pl.d_geo, &pl.d_clev, &pl.d_topo, &pl.d_ops, &pl.d_tables, &pl.d_rho,
-                    &pl.d_m2l_pairs, &pl.d_p2p_work, &pl.d_p2p_ivals, &pl.d_p2p_total, &pl.d_outidx,
-                    &pl.d_outph, &pl.d_M, &pl.d_L, &pl.d_cops, &pl.d_stage, &pl.d_m2l_soff,
-                    &pl.d_inmap})
+                    &pl.d_m2l_pairs, &pl.d_p2p_work, &pl.d_p2p_ivals, &pl.d_p2p_total, &pl.d_M,
+                    &pl.d_L, &pl.d_cops, &pl.d_stage, &pl.d_m2l_soff})
     pl.device_bytes += (int64_t)b->bytes;
   if (t.bie && (rc = prepare_bie(t, pl, s))) {
     pl.d_tables.reset();  // not device-ready: the next prepare retries

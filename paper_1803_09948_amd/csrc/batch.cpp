@@ -149,8 +149,7 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   for (int l = b.maxlev - 2; l >= 0; --l)
     launch_m2m(b.d_m2m.as<int2>() + b.m2m_off[l], b.m2m_off[l + 1] - b.m2m_off[l], I, P, s);
   if ((rc = mark(2))) return rc;
-  launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, P, p0.d_outidx.as<int32_t>(), p0.d_outph.as<int32_t>(),
-             p0.d_inmap.as<int32_t>(), s);
+  launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, P, s);
   if ((rc = mark(3))) return rc;
   launch_m2l_reduce(b.d_red.as<int2>(), b.n_red, I, P, s);
   if ((rc = mark(4))) return rc;

@@ -71,8 +71,7 @@ int m2l_pairs_per_chunk(int P);
 // chunks: (instance, op, pair begin, pair end), sorted by (instance, op)
 // L[t] = sum of the staging slots of t (items: instance, target cell)
 void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
-// inmap[g][k] = (c << 3) | (zero << 2) | phase: input map of reflection g, k < Kp
-void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, const int32_t* outidx,
-                const int32_t* outph, const int32_t* inmap, hipStream_t s);
+// per pair: reflected multipoles through the canonical operator into the pair's staging slot
+void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, hipStream_t s);
 
 }  // namespace hfmm

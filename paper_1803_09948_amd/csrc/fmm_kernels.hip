@@ -384,34 +384,42 @@ __global__ void __launch_bounds__(256) k_l2l(const int2* __restrict__ items,
 // M2L on the matrix cores.  One wave takes up to 16*NCT pairs that share one
 // canonical operator T (P^2 x P^2 complex).  The B matrix (k = input
 // coefficient, column = pair) holds M' = D^T M, gathered straight from the
-// multipoles with the reflection applied arithmetically; T streams from
-// memory as the A matrix (row = output coefficient).  The complex product is
-// four real 16x16x4 FP32 MFMAs per tile and k-step:
+// multipoles with the pair's reflection applied arithmetically; T streams
+// from memory as the A matrix (row = output coefficient).  The complex
+// product is four real 16x16x4 FP32 MFMAs per tile and k-step:
 //   Cr += Tr Br - Ti Bi,   Ci += Tr Bi + Ti Br,
-// with A and B prefetched one k-step ahead.  Outputs are mapped back
-// (L += conj(D) C), transposed through LDS and added per target with atomics
-// over the target's contiguous coefficients.  Tables are [op][k < Kp][r < Rp]
-// with zero padding.  Blocks are mapped so that each XCD walks a contiguous
-// range of chunks (sorted by operator), keeping an operator's table in that
-// XCD's L2 while its chunks run.
+// with A and B prefetched one k-step ahead.  Each pair's result is mapped
+// back (conj(D) C) and written from the accumulators to the pair's staging
+// slot; no LDS is used, so many waves fit on a CU.  Tables are [op][k < Kp]
+// [r < Rp] with zero padding.  Blocks are mapped so that each XCD walks a
+// contiguous range of chunks (sorted by operator), keeping an operator's
+// table in that XCD's L2 while its chunks run.
 //
 // MFMA 16x16x4 f32 lane layout: A[i][k] from lane i + 16k, B[k][j] from lane
 // j + 16k, D[4q + v][j] in lane j + 16q, register v.
 // ---------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// Image of coefficient (n, m) under the reflection g = (fx, fy, fz, swap):
-// Y_n^m(sigma r) = i^ph Y_n^{m'}(r).  Returns m' and sets ph; the map is an
-// involution on m, so it also gives the inverse needed for the inputs.
-__device__ inline int sym_m(int g, int n, int m, int& ph) {
-  int p = 0;
+// Reflection g = bits (fx, fy, fz, swap x<->y) of the cube acts on the
+// harmonics as Y_n^m(sigma r) = i^ph Y_n^{m'}(r), m' = +-m; x -> -x gives
+// m' = -m, ph = 2m;  y -> -y: m' = -m;  z -> -z: ph = 2(n + m);  swap:
+// m' = -m, ph = m (applied in that order).  For the canonical-frame order
+// mr this returns the order mo whose image is mr (the sign map is an
+// involution) and sets ph to the phase of (n, mo).
+__device__ inline int refl_m(int g, int n, int mr, int& ph) {
+  const int flip = (g ^ (g >> 1) ^ (g >> 3)) & 1;
+  const int mo = flip ? -mr : mr;
+  int m = mo, p = 0;
   if (g & 1) { p += 2 * (m & 1); m = -m; }
   if (g & 2) { m = -m; }
   if (g & 4) { p += 2 * ((n + m) & 1); }
-  if (g & 8) { p += m & 3; m = -m; }
+  if (g & 8) { p += m & 3; }
   ph = p & 3;
-  return m;
+  return mo;
 }
+
+// degree of the coefficient index e = n^2 + n + m (e < 2^16)
+__device__ inline int coef_degree(int e) { return (int)__builtin_sqrtf((float)e + 0.5f); }
 
 // Global-address-space views of pointers read from the instance table (so
 // that loads through them are global loads, not flat ones).
@@ -432,51 +440,43 @@ __device__ inline float2 mul_ipow_sel(float2 a, int code) {
 }
 
 template <int RT, int NCT>
-__global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks, int nchunks,
-                                                 int per_xcd, const InstDev* __restrict__ insts,
-                                                 int Kp, int Rp, const int32_t* __restrict__ outidx,
-                                                 const int32_t* __restrict__ outph,
-                                                 const int32_t* __restrict__ inmap, int P2) {
-  extern __shared__ float2 Cs[];    // [16 NCT][16 RT + 1] output transpose, then input map
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l_mfma(const int4* __restrict__ chunks, int nchunks, int per_xcd,
+           const InstDev* __restrict__ insts, int Kp, int Rp, int P2) {
   const int b = blockIdx.x;
   const int chunk = (b & 7) * per_xcd + (b >> 3);
   if (chunk >= nchunks) return;
   const int4 ch = chunks[chunk];    // (instance, op, pair begin, pair end)
   const InstDev& I = insts[ch.x];
   const int op = ch.y, pb = ch.z, np = ch.w - ch.z;
-  const int4* __restrict__ pairs = I.m2l_pairs;
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
-  // LDS: [0, CS*16) output transpose of one 16-pair tile; then the reflections' input map
-  // inmap[g][k] = (c << 3) | (zero << 2) | phase (B[k] = i^phase M[c]), their
-  // output map outmap[g][r] = o | (phase << 16), and this chunk's pairs
-  constexpr int CS = 16 * RT + 1;
-  int* smap = reinterpret_cast<int*>(Cs + CS * 16);
-  int* somap = smap + 16 * Kp;
-  int4* spr = reinterpret_cast<int4*>(somap + 16 * P2 + 4 - ((16 * Kp + 16 * P2) & 3));
-  for (int e = lane; e < 16 * Kp; e += 64) smap[e] = inmap[e];
-  for (int e = lane; e < 16 * P2; e += 64) somap[e] = outidx[e] | (outph[e] << 16);
-  if (lane < np) spr[lane] = pairs[pb + lane];
-  __syncthreads();
+  // column t of this lane is pair 16 t + li: (target, source, reflection, slot)
   gcfloat2* Ms[NCT];
-  int grow[NCT];
+  int gs[NCT], slot[NCT];
   float okc[NCT];
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
     const int p = 16 * t + li;
     const bool ok = p < np;
-    const int4 pr = spr[ok ? p : 0];
+    const int4 pr = I.m2l_pairs[pb + (ok ? p : 0)];
     Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
-    grow[t] = pr.z * Kp;
+    gs[t] = pr.z;
+    slot[t] = ok ? pr.w : -1;
     okc[t] = ok ? 1.f : 0.f;
   }
-  // B gather: issue the loads now, apply scale and phase when the step runs
+  // B gather: B[k] = i^ph M[n^2 + n + mo] for the column's reflection, zero
+  // past P^2; the loads issue now, scale and phase apply when the step runs
   auto load_b = [&](int k, float2* raw, int* code) {
+    const int n = coef_degree(k);
+    const int mr = k - n * n - n;
+    const bool pad = k >= P2;
 #pragma unroll
     for (int t = 0; t < NCT; ++t) {
-      const int e = smap[grow[t] + k];
-      raw[t] = ld2(Ms[t] + (e >> 3));
-      code[t] = e & 7;
+      int ph;
+      const int mo = refl_m(gs[t], n, mr, ph);
+      raw[t] = ld2(Ms[t] + (pad ? 0 : n * n + n + mo));
+      code[t] = ph | (pad ? 4 : 0);
     }
   };
   auto finish_b = [&](const float2* raw, const int* code, float2* out) {
@@ -545,28 +545,25 @@ __global__ void __launch_bounds__(64) k_m2l_mfma(const int4* __restrict__ chunks
     mma(a0, bv);
   }
   // each pair owns a staging slot (slots are ordered by target); the
-  // reduction kernel below adds a target's slots in a fixed order.  One
-  // 16-pair tile at a time goes through the LDS transpose.
+  // reduction kernel below adds a target's slots in a fixed order.  Lane
+  // (j, q) holds rows 4q..4q+3 of every 16-row tile of column j.
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
-    if (t) __syncthreads();
+    if (slot[t] < 0) continue;
+    gfloat2* St = (gfloat2*)(I.stage + (size_t)slot[t] * P2);
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Cs[li * CS + 16 * r + 4 * lk + v] = make_float2(cr[t][r][v], ci[t][r][v]);
-    __syncthreads();
-    const int pend = min(np, 16 * (t + 1));
-    for (int p = 16 * t; p < pend; ++p) {
-      const int4 pr = spr[p];
-      const int* om = somap + pr.z * P2;
-      gfloat2* St = (gfloat2*)(I.stage + (size_t)pr.w * P2);
-      const float2* C = Cs + (p - 16 * t) * CS;
-      for (int row = lane; row < P2; row += 64) {
-        const int m = om[row];
-        const float2 v = mul_ipow_sel(C[row], m >> 16);
-        St[m & 0xffff] = f2v{v.x, v.y};
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * r + 4 * lk + v;
+        if (row < P2) {
+          const int n = coef_degree(row);
+          int ph;
+          const int mo = refl_m(gs[t], n, row - n * n - n, ph);
+          const float2 o = mul_ipow_sel(make_float2(cr[t][r][v], ci[t][r][v]), (4 - ph) & 3);
+          St[n * n + n + mo] = f2v{o.x, o.y};
+        }
       }
-    }
   }
 }
 
@@ -833,29 +830,30 @@ void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s) {
 
 template <int RT, int NCT>
 static void launch_m2l_mfma_t(const int4* chunks, int nchunks, const InstDev* insts, int Kp, int Rp,
-                              const int32_t* outidx, const int32_t* outph, const int32_t* inmap, int P2,
-                              hipStream_t s) {
+                              int P2, hipStream_t s) {
   const int per = (nchunks + 7) / 8;
-  const size_t lds = (size_t)16 * (16 * RT + 1) * sizeof(float2) +
-                     ((size_t)16 * Kp + 16 * P2 + 4) * sizeof(int) + (size_t)(16 * NCT) * sizeof(int4);
-  k_m2l_mfma<RT, NCT><<<8 * per, 64, lds, s>>>(chunks, nchunks, per, insts, Kp, Rp, outidx, outph, inmap, P2);
+  k_m2l_mfma<RT, NCT><<<8 * per, 64, 0, s>>>(chunks, nchunks, per, insts, Kp, Rp, P2);
 }
 
-int m2l_pairs_per_chunk(int P) { return P * P > 240 ? 16 : 32; }
+// Two 16-pair column tiles per wave while the accumulators of 2 x RT row
+// tiles fit two waves per SIMD (RT <= 10, i.e. P <= 12); one beyond.
+static int m2l_col_tiles(int P) {
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
+  return Rp / 16 <= 10 ? 2 : 1;
+}
 
-void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, const int32_t* outidx,
-                const int32_t* outph, const int32_t* inmap, hipStream_t s) {
+int m2l_pairs_per_chunk(int P) { return 16 * m2l_col_tiles(P); }
+
+void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, hipStream_t s) {
   if (nchunks <= 0) return;
   const int P2 = P * P;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
   const int RT = Rp / 16;
-#define M2L_CASE(R)                                                                             \
-  case R:                                                                                       \
-    if (P2 > 240)                                                                               \
-      launch_m2l_mfma_t<R, 1>(chunks, nchunks, insts, Kp, Rp, outidx, outph, inmap, P2, s);     \
-    else                                                                                        \
-      launch_m2l_mfma_t<R, 2>(chunks, nchunks, insts, Kp, Rp, outidx, outph, inmap, P2, s);     \
+#define M2L_CASE(R)                                                                 \
+  case R:                                                                           \
+    launch_m2l_mfma_t<R, (R <= 10 ? 2 : 1)>(chunks, nchunks, insts, Kp, Rp, P2, s); \
     break;
   switch (RT) {
     M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6) M2L_CASE(7) M2L_CASE(8)

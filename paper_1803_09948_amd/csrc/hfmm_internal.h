@@ -80,7 +80,6 @@ const Coupling& coupling(int P);
 // Symmetry maps of the 16 canonicalising reflections: for symmetry g and
 // coefficient index (n,m): Y_n^m(sigma r) = phase * Y_n^{m'}(r); stored as
 // dst index and phase code (0:1, 1:i, 2:-1, 3:-i).
-void symmetry_map(int P, std::vector<int32_t>& dst, std::vector<int32_t>& phase);
 
 // ---------------------------------------------------------------------------
 // Device-side plan for one (k, P)
@@ -103,7 +102,7 @@ struct HostPlanData {
   std::vector<OpDesc> ops;
   std::vector<int4> spairs, work;
   std::vector<int2> ivals, cops;
-  std::vector<int32_t> totals, oidx, oph, soff, inmap;
+  std::vector<int32_t> totals, soff;
 };
 
 struct Plan {
@@ -130,8 +129,6 @@ struct Plan {
   DevBuf d_p2p_ivals;            // int2 (src begin, src end)
   DevBuf d_p2p_total;            // int32 sources per work item
   int32_t n_p2p_work = 0;
-  DevBuf d_outidx, d_outph;      // int32 [16][P^2]: output map of each reflection
-  DevBuf d_inmap;                // int32 [16][Kp]: input map of each reflection
   DevBuf d_M, d_L;               // float2 [ncell][P^2]
   DevBuf d_cops;                 // int2 per cell: (M2M op as child, L2L op as child)
   DevBuf d_stage;                // float2 [n M2L pairs][P^2] staging, slots ordered by target

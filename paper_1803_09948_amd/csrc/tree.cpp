@@ -328,32 +328,4 @@ const Coupling& coupling(int P) {
   return res.first->second;
 }
 
-// Elementary reflections act on Y_n^m as Y_n^m(sigma r) = phase Y_n^{m'}(r):
-//  x -> -x : m' = -m, phase (-1)^m;   y -> -y : m' = -m, phase 1;
-//  z -> -z : m' = m, phase (-1)^(n+m); swap x,y : m' = -m, phase i^m.
-// Symmetry g = bits (fx, fy, fz, sw) is sigma = Fx^fx Fy^fy Fz^fz Sw^sw; its
-// map is the composition D = D_Fx D_Fy D_Fz D_Sw.
-void symmetry_map(int P, std::vector<int32_t>& dst, std::vector<int32_t>& phase) {
-  int P2 = P * P;
-  dst.assign(16 * P2, 0);
-  phase.assign(16 * P2, 0);
-  for (int g = 0; g < 16; ++g)
-    for (int n = 0; n < P; ++n)
-      for (int m = -n; m <= n; ++m) {
-        int cm = m, ph = 0;
-        auto apply = [&](int which) {
-          if (which == 0) { ph += 2 * (((cm % 2) + 2) % 2); cm = -cm; }
-          else if (which == 1) { cm = -cm; }
-          else if (which == 2) { ph += 2 * ((((n + cm) % 2) + 2) % 2); }
-          else { ph += ((cm % 4) + 4) % 4; cm = -cm; }
-        };
-        if (g & 1) apply(0);
-        if (g & 2) apply(1);
-        if (g & 4) apply(2);
-        if (g & 8) apply(3);
-        dst[g * P2 + n * n + n + m] = n * n + n + cm;
-        phase[g * P2 + n * n + n + m] = ph & 3;
-      }
-}
-
 }  // namespace hfmm
