@@ -259,9 +259,22 @@ def main():
         tree.matvec(a.k, a.P, qd, yd)
         for kk, v in tree.phase_times().items():
             acc[kk] = acc.get(kk, 0.0) + v / nrep
+    # M2L time of every launch shape (the autotuner picked one on the first product)
+    tuned = tree.variant(a.k, a.P)
+    shape_ms = []
+    try:
+        for v in range(hfmm.variant_count(a.P)):
+            hfmm.set_variant(v)
+            s = 0.0
+            for _ in range(3):
+                tree.matvec(a.k, a.P, qd, yd)
+                s += tree.phase_times()["m2l"] / 3
+            shape_ms.append(round(s, 4))
+    finally:
+        hfmm.set_variant(-1)
     tree.set_timing(False)
     phases = {n: round(v, 4) for n, v in acc.items()}
-    log("phases (ms):", phases)
+    log("phases (ms):", phases, "M2L shapes (ms):", shape_ms, "tuned:", tuned)
     m2l_flops = 8.0 * a.P ** 4 * st["n_m2l"]
     p2p_flops = 20.0 * st["p2p_body_pairs"]
     m2l_ach = m2l_flops / (phases["m2l"] * 1e-3)
@@ -291,7 +304,8 @@ def main():
         "phases_ms": phases,
         "secondary": {"p2p_tflops": p2p_ach / 1e12, "p2p_gpairs_per_s": st["p2p_body_pairs"] / phases["p2p"] / 1e6,
                       "m2l_tflops": m2l_ach / 1e12, "n_m2l": st["n_m2l"], "p2p_body_pairs": st["p2p_body_pairs"],
-                      "n_tables": st["n_tables"], "setup_s": {"tree": t_tree, "prepare": t_prep}},
+                      "n_tables": st["n_tables"], "setup_s": {"tree": t_tree, "prepare": t_prep},
+                      "m2l_shapes": {"tuned": tuned, "ms": shape_ms}},
     }
     if a.check:
         from oracle.fmm import direct_sum

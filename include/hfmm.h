@@ -215,6 +215,23 @@ int hfmm_lists_export(hfmm_tree* tree, double k, int32_t P, int32_t* m2l_pairs,
 int hfmm_set_timing(hfmm_tree* tree, int32_t on);
 int hfmm_phase_times(const hfmm_tree* tree, float* ms10);
 
+/* Launch-shape autotuning of the fused matvec.  Phase 0 is the M2L
+ * matrix-core kernel.  Its shapes (pairs per wave, waves per SIMD) compute
+ * bit-identical results; by default the first product of each fused
+ * sequence (a tree's plain matvec, a batch, a server composition) times
+ * every shape on its own work, outside any graph capture, and keeps the
+ * fastest, cached per (phase, P, log2 of the work size).
+ *  hfmm_variant_count: number of shapes of `phase` at order P (>= 1), or
+ *    HFMM_EINVAL.
+ *  hfmm_set_variant: variant >= 0 forces that shape (ignored where it does
+ *    not exist for P); -1 restores tuning.  Process-wide; a captured graph
+ *    is re-captured when its shape changes.
+ *  hfmm_tree_variant: the shape the plain matvec of (tree, k, P) uses, or -1
+ *    before its first product. */
+int hfmm_variant_count(int32_t phase, int32_t P);
+int hfmm_set_variant(int32_t phase, int32_t variant);
+int hfmm_tree_variant(hfmm_tree* tree, double k, int32_t P, int32_t phase, int32_t* variant);
+
 void hfmm_tree_free(hfmm_tree* tree);
 const char* hfmm_last_error(void);
 int hfmm_version(void);

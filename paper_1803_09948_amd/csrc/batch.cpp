@@ -7,9 +7,11 @@
 // one launch per phase and level for all instances together, and can be
 // captured once as a hipGraph and replayed.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 
 #include "hfmm_internal.h"
 
@@ -149,7 +151,7 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   for (int l = b.maxlev - 2; l >= 0; --l)
     launch_m2m(b.d_m2m.as<int2>() + b.m2m_off[l], b.m2m_off[l + 1] - b.m2m_off[l], I, P, s);
   if ((rc = mark(2))) return rc;
-  launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, P, s);
+  launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, P, batch_variant(b, kPhaseM2L), s);
   if ((rc = mark(3))) return rc;
   launch_m2l_reduce(b.d_red.as<int2>(), b.n_red, I, P, s);
   if ((rc = mark(4))) return rc;
@@ -165,6 +167,85 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   return HFMM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner.  Shapes of a phase compute identical results; the first run of
+// a batch times every shape of the phase on the batch's own work (eagerly,
+// outside any capture: M2L only writes its staging slots, which the real
+// sequence overwrites) and keeps the fastest.  Choices are cached per
+// (phase, P, log2 of the work size), so rebuilt batches of similar size do
+// not time again.
+// ---------------------------------------------------------------------------
+static std::atomic<int> g_override[kNumTunedPhases] = {{-1}};
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tuned;
+
+int set_variant_override(int phase, int variant) {
+  if (phase < 0 || phase >= kNumTunedPhases || variant < -1) return set_error("bad phase or variant"), HFMM_EINVAL;
+  g_override[phase].store(variant);
+  return HFMM_OK;
+}
+
+int batch_variant(const Batch& b, int phase) {
+  const int o = g_override[phase].load();
+  if (phase == kPhaseM2L && o >= 0 && o < m2l_variant_count(b.P)) return o;
+  return b.m2l_variant < 0 ? 0 : b.m2l_variant;
+}
+
+static int tune_batch(Batch& b, hipStream_t s) {
+  const int nv = m2l_variant_count(b.P);
+  if (b.m2l_variant >= 0 || g_override[kPhaseM2L].load() >= 0) return HFMM_OK;
+  if (nv <= 1 || b.n_m2l == 0) {
+    b.m2l_variant = 0;
+    return HFMM_OK;
+  }
+  int lg = 0;
+  while ((1 << (lg + 1)) <= b.n_m2l) ++lg;
+  const auto key = std::make_tuple((int)kPhaseM2L, b.P, lg);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      b.m2l_variant = it->second;
+      return HFMM_OK;
+    }
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const InstDev* I = b.d_inst.as<InstDev>();
+  float best = 0.f;
+  int pick = 0;
+  int rc = HFMM_OK;
+  for (int rep = 0; rep < 2 && rc == HFMM_OK; ++rep)  // the first round warms caches and code
+    for (int v = 0; v < nv; ++v) {
+      hipError_t e = hipEventRecord(e0, s);
+      if (e == hipSuccess) {
+        launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, b.P, v, s);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        set_error(std::string("autotuner: ") + hipGetErrorString(e));
+        rc = HFMM_EHIP;
+        break;
+      }
+      if (rep == 1 && (v == 0 || ms < best)) {
+        best = ms;
+        pick = v;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  b.m2l_variant = pick;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = pick;
+  return HFMM_OK;
+}
+
 int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t s, bool use_graph,
               Tree* timing) {
   for (int base = 0; base < b.count; base += 64) {
@@ -177,15 +258,25 @@ int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t 
     launch_set_xy(n, base, p, b.d_inst.as<InstDev>(), s);
   }
   HIP_TRY(hipGetLastError());
+  int rc = tune_batch(b, s);
+  if (rc) return rc;
+  b.ran = true;
   if (!use_graph) return sequence(b, s, timing ? timing->ev : nullptr);
   if (!b.stream) {
     HIP_TRY(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&b.ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&b.ev_out, hipEventDisableTiming));
   }
+  if (b.exec && b.graph_m2l_variant != batch_variant(b, kPhaseM2L)) {  // shape forced since capture
+    (void)hipGraphExecDestroy(b.exec);
+    (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+  }
   if (!b.exec) {
     HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
-    int rc = sequence(b, b.stream, nullptr);
+    b.graph_m2l_variant = batch_variant(b, kPhaseM2L);
+    rc = sequence(b, b.stream, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b.stream, &g);
     if (rc) {

@@ -72,6 +72,8 @@ int m2l_pairs_per_chunk(int P);
 // L[t] = sum of the staging slots of t (items: instance, target cell)
 void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
 // per pair: reflected multipoles through the canonical operator into the pair's staging slot
-void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, hipStream_t s);
+// variant < m2l_variant_count(P) selects the launch shape (results are identical)
+int m2l_variant_count(int P);
+void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, int variant, hipStream_t s);
 
 }  // namespace hfmm

@@ -439,31 +439,38 @@ __device__ inline float2 mul_ipow_sel(float2 a, int code) {
   return make_float2(nx ? -x : x, ny ? -y : y);
 }
 
-template <int RT, int NCT>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
-k_m2l_mfma(const int4* __restrict__ chunks, int nchunks, int per_xcd,
+// One wave per item; an item is column group h < sub of chunk item / sub,
+// i.e. pairs [16 NCT h, 16 NCT (h + 1)) of the chunk.  The complex product
+// uses three real MFMAs per tile and k-step (Gauss):
+//   K1 += (Tr + Ti) Br,  K2 += Tr (Bi - Br),  K3 += Ti (Br + Bi),
+//   C = (K1 - K3) + i (K1 + K2).
+// WPE is the number of waves per SIMD the register budget is sized for.
+template <int RT, int NCT, int WPE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
            const InstDev* __restrict__ insts, int Kp, int Rp, int P2) {
   const int b = blockIdx.x;
-  const int chunk = (b & 7) * per_xcd + (b >> 3);
-  if (chunk >= nchunks) return;
-  const int4 ch = chunks[chunk];    // (instance, op, pair begin, pair end)
+  const int item = (b & 7) * per_xcd + (b >> 3);
+  if (item >= nitems) return;
+  const int ci = item / sub;
+  const int4 ch = chunks[ci];       // (instance, op, pair begin, pair end)
   const InstDev& I = insts[ch.x];
-  const int op = ch.y, pb = ch.z, np = ch.w - ch.z;
+  const int op = ch.y, pb = ch.z + 16 * NCT * (item - ci * sub);
+  const int np = min(ch.w - pb, 16 * NCT);
+  if (np <= 0) return;
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
-  // column t of this lane is pair 16 t + li: (target, source, reflection, slot)
+  // column t of this lane is pair 16 t + li: (target, source, reflection,
+  // slot); bit 4 of gs marks a column past the item's end (B = 0)
   gcfloat2* Ms[NCT];
-  int gs[NCT], slot[NCT];
-  float okc[NCT];
+  int gs[NCT];
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
     const int p = 16 * t + li;
     const bool ok = p < np;
     const int4 pr = I.m2l_pairs[pb + (ok ? p : 0)];
     Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
-    gs[t] = pr.z;
-    slot[t] = ok ? pr.w : -1;
-    okc[t] = ok ? 1.f : 0.f;
+    gs[t] = pr.z | (ok ? 0 : 16);
   }
   // B gather: B[k] = i^ph M[n^2 + n + mo] for the column's reflection, zero
   // past P^2; the loads issue now, scale and phase apply when the step runs
@@ -476,49 +483,51 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nchunks, int per_xcd,
       int ph;
       const int mo = refl_m(gs[t], n, mr, ph);
       raw[t] = ld2(Ms[t] + (pad ? 0 : n * n + n + mo));
-      code[t] = ph | (pad ? 4 : 0);
+      code[t] = ph | ((pad | (gs[t] >> 4)) << 2);
     }
   };
-  auto finish_b = [&](const float2* raw, const int* code, float2* out) {
+  // the three B operands of the Gauss product
+  float bu[NCT], bd[NCT], bs[NCT];
+  auto finish_b = [&](const float2* raw, const int* code) {
 #pragma unroll
     for (int t = 0; t < NCT; ++t) {
-      const float sc = (code[t] & 4) ? 0.f : okc[t];
-      out[t] = mul_ipow_sel(make_float2(raw[t].x * sc, raw[t].y * sc), code[t] & 3);
+      const float sc = (code[t] & 4) ? 0.f : 1.f;
+      const float2 v = mul_ipow_sel(make_float2(raw[t].x * sc, raw[t].y * sc), code[t] & 3);
+      bu[t] = v.x;
+      bd[t] = v.y - v.x;
+      bs[t] = v.x + v.y;
     }
   };
-  floatx4 cr[NCT][RT], ci[NCT][RT];
+  floatx4 k1[NCT][RT], k2[NCT][RT], k3[NCT][RT];
 #pragma unroll
   for (int t = 0; t < NCT; ++t)
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
-      cr[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-      ci[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+      k1[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+      k2[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+      k3[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
   gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li;
   const int KS = Kp >> 2;
   // two register buffers, alternating k-steps; the loads of one step are in
   // flight while the other step's MFMAs run (a straight-line loop body keeps
   // the compiler's wait counts exact)
-  float2 a0[RT], a1[RT], b0[NCT], b1[NCT], bv[NCT];
+  float2 a0[RT], a1[RT], b0[NCT], b1[NCT];
   int c0[NCT], c1[NCT];
   auto load_a = [&](int k, float2* out) {
 #pragma unroll
     for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * r);
   };
-  auto mma = [&](const float2* a, const float2* bv) {
+  auto mma = [&](const float2* a) {
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
-      const float ar = a[r].x, ai = a[r].y, nai = -a[r].y;
+      const float ar = a[r].x, ai = a[r].y, as = ar + ai;
 #pragma unroll
-      for (int t = 0; t < NCT; ++t) {
-        cr[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bv[t].x, cr[t][r], 0, 0, 0);
-        ci[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bv[t].y, ci[t][r], 0, 0, 0);
-      }
+      for (int t = 0; t < NCT; ++t) k1[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bu[t], k1[t][r], 0, 0, 0);
 #pragma unroll
-      for (int t = 0; t < NCT; ++t) {
-        cr[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bv[t].y, cr[t][r], 0, 0, 0);
-        ci[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bv[t].x, ci[t][r], 0, 0, 0);
-      }
+      for (int t = 0; t < NCT; ++t) k2[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bd[t], k2[t][r], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) k3[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bs[t], k3[t][r], 0, 0, 0);
     }
   };
   const int klast = Kp - 4 + lk;  // clamp: redundant in-bounds loads past the end are unused
@@ -526,31 +535,32 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nchunks, int per_xcd,
   load_b(lk, b0, c0);
   int ks = 0;
   for (; ks + 2 <= KS; ks += 2) {
-    const int k1 = 4 * (ks + 1) + lk, k2 = min(4 * (ks + 2) + lk, klast);
-    load_a(k1, a1);
-    load_b(k1, b1, c1);
+    const int ka = 4 * (ks + 1) + lk, kb = min(4 * (ks + 2) + lk, klast);
+    load_a(ka, a1);
+    load_b(ka, b1, c1);
     __builtin_amdgcn_sched_barrier(0);  // issue the next step's loads before these MFMAs
-    finish_b(b0, c0, bv);
-    mma(a0, bv);
+    finish_b(b0, c0);
+    mma(a0);
     __builtin_amdgcn_sched_barrier(0);
-    load_a(k2, a0);
-    load_b(k2, b0, c0);
+    load_a(kb, a0);
+    load_b(kb, b0, c0);
     __builtin_amdgcn_sched_barrier(0);
-    finish_b(b1, c1, bv);
-    mma(a1, bv);
+    finish_b(b1, c1);
+    mma(a1);
     __builtin_amdgcn_sched_barrier(0);
   }
   if (ks < KS) {
-    finish_b(b0, c0, bv);
-    mma(a0, bv);
+    finish_b(b0, c0);
+    mma(a0);
   }
   // each pair owns a staging slot (slots are ordered by target); the
   // reduction kernel below adds a target's slots in a fixed order.  Lane
   // (j, q) holds rows 4q..4q+3 of every 16-row tile of column j.
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
-    if (slot[t] < 0) continue;
-    gfloat2* St = (gfloat2*)(I.stage + (size_t)slot[t] * P2);
+    if (gs[t] & 16) continue;
+    const int slot = I.m2l_pairs[pb + 16 * t + li].w;
+    gfloat2* St = (gfloat2*)(I.stage + (size_t)slot * P2);
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
@@ -560,7 +570,8 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nchunks, int per_xcd,
           const int n = coef_degree(row);
           int ph;
           const int mo = refl_m(gs[t], n, row - n * n - n, ph);
-          const float2 o = mul_ipow_sel(make_float2(cr[t][r][v], ci[t][r][v]), (4 - ph) & 3);
+          const float c1v = k1[t][r][v];
+          const float2 o = mul_ipow_sel(make_float2(c1v - k3[t][r][v], c1v + k2[t][r][v]), (4 - ph) & 3);
           St[n * n + n + mo] = f2v{o.x, o.y};
         }
       }
@@ -828,34 +839,50 @@ void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s) {
   if (n > 0) k_p2p<<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
 }
 
-template <int RT, int NCT>
-static void launch_m2l_mfma_t(const int4* chunks, int nchunks, const InstDev* insts, int Kp, int Rp,
-                              int P2, hipStream_t s) {
-  const int per = (nchunks + 7) / 8;
-  k_m2l_mfma<RT, NCT><<<8 * per, 64, 0, s>>>(chunks, nchunks, per, insts, Kp, Rp, P2);
+template <int RT, int NCT, int WPE>
+static void launch_m2l_t(const int4* chunks, int nchunks, int sub, const InstDev* insts, int Kp, int Rp,
+                         int P2, hipStream_t s) {
+  const int nitems = nchunks * sub;
+  const int per = (nitems + 7) / 8;
+  k_m2l_mfma<RT, NCT, WPE><<<8 * per, 64, 0, s>>>(chunks, nitems, per, sub, insts, Kp, Rp, P2);
 }
 
-// Two 16-pair column tiles per wave while the accumulators of 2 x RT row
-// tiles fit two waves per SIMD (RT <= 10, i.e. P <= 12); one beyond.
-static int m2l_col_tiles(int P) {
+// Chunks hold 32 pairs while two 16-pair column tiles of three accumulator
+// sets fit two waves per SIMD (RT <= 7, P <= 10), else 16.
+int m2l_pairs_per_chunk(int P) {
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  return Rp / 16 <= 10 ? 2 : 1;
+  return Rp / 16 <= 7 ? 32 : 16;
 }
 
-int m2l_pairs_per_chunk(int P) { return 16 * m2l_col_tiles(P); }
+// Launch shapes: 0 = one wave per chunk (two column tiles when the chunk
+// holds 32 pairs); 1 = one wave per 16-pair column tile (32-pair chunks
+// only), with a smaller register budget and more waves per SIMD.
+int m2l_variant_count(int P) { return m2l_pairs_per_chunk(P) == 32 ? 2 : 1; }
 
-void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, hipStream_t s) {
+// waves per SIMD of the one-tile shape: accumulators and A buffers take
+// about 16 RT registers
+constexpr int m2l_narrow_wpe(int RT) { return RT <= 3 ? 4 : RT <= 7 ? 3 : RT <= 12 ? 2 : 1; }
+
+template <int RT>
+static void launch_m2l_r(bool wide, int sub, const int4* chunks, int nchunks, const InstDev* insts, int Kp,
+                         int Rp, int P2, hipStream_t s) {
+  if constexpr (RT <= 7) {
+    if (wide) return launch_m2l_t<RT, 2, 2>(chunks, nchunks, 1, insts, Kp, Rp, P2, s);
+  }
+  launch_m2l_t<RT, 1, m2l_narrow_wpe(RT)>(chunks, nchunks, sub, insts, Kp, Rp, P2, s);
+}
+
+void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, int variant, hipStream_t s) {
   if (nchunks <= 0) return;
   const int P2 = P * P;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  const int RT = Rp / 16;
-#define M2L_CASE(R)                                                                 \
-  case R:                                                                           \
-    launch_m2l_mfma_t<R, (R <= 10 ? 2 : 1)>(chunks, nchunks, insts, Kp, Rp, P2, s); \
-    break;
-  switch (RT) {
+  const int sub = m2l_pairs_per_chunk(P) / 16;
+  const bool wide = sub == 2 && variant == 0;
+#define M2L_CASE(R) \
+  case R: launch_m2l_r<R>(wide, sub, chunks, nchunks, insts, Kp, Rp, P2, s); break;
+  switch (Rp / 16) {
     M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6) M2L_CASE(7) M2L_CASE(8)
     M2L_CASE(9) M2L_CASE(10) M2L_CASE(11) M2L_CASE(12) M2L_CASE(13) M2L_CASE(14) M2L_CASE(15)
     M2L_CASE(16)

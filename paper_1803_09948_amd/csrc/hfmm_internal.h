@@ -162,10 +162,18 @@ struct Batch {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int m2l_variant = -1;               // launch shape chosen by the autotuner
+  int graph_m2l_variant = -1;         // shape captured in the graph
+  bool ran = false;                   // has run at least once
   ~Batch();
 };
 
 int build_batch(const std::vector<struct Tree*>& trees, const std::vector<Plan*>& plans, Batch& b);
+// Launch-shape autotuning: forced shape per phase (-1: tuned), the shape a
+// batch uses, and the per-phase shape counts.
+enum { kPhaseM2L = 0, kNumTunedPhases = 1 };
+int set_variant_override(int phase, int variant);
+int batch_variant(const Batch& b, int phase);
 // Runs the fused FMM sequence; xs/ys are caller vectors per instance.  With
 // use_graph the sequence is captured once and replayed on a private stream.
 int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t s, bool use_graph,

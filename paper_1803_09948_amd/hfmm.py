@@ -24,6 +24,7 @@ EXPORTS = [
     "hfmm_tree_free", "hfmm_last_error", "hfmm_version", "hfmm_prepare_host",
     "hfmm_server_create", "hfmm_server_submit", "hfmm_server_step", "hfmm_server_poll",
     "hfmm_server_release", "hfmm_server_used_bytes", "hfmm_server_free",
+    "hfmm_variant_count", "hfmm_set_variant", "hfmm_tree_variant",
 ]
 
 
@@ -96,6 +97,9 @@ def lib():
             "hfmm_server_release": [vp, i64],
             "hfmm_server_used_bytes": [vp, C.POINTER(i64)],
             "hfmm_server_free": [vp],
+            "hfmm_variant_count": [i32, i32],
+            "hfmm_set_variant": [i32, i32],
+            "hfmm_tree_variant": [vp, dbl, i32, i32, C.POINTER(i32)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -238,6 +242,29 @@ class Tree:
         a = np.zeros(10, np.float32)
         _check(lib().hfmm_phase_times(self._h, a.ctypes.data))
         return {n: float(v) for n, v in zip(self.PHASES, a)}
+
+
+    def variant(self, k: float, P: int, phase: int = 0) -> int:
+        """Launch shape the plain matvec at (k, P) uses (-1 before its first product)."""
+        v = C.c_int32()
+        _check(lib().hfmm_tree_variant(self._h, float(k), int(P), int(phase), C.byref(v)))
+        return v.value
+
+
+PHASE_M2L = 0
+
+
+def variant_count(P: int, phase: int = PHASE_M2L) -> int:
+    """Number of launch shapes of a tuned phase at order P."""
+    n = lib().hfmm_variant_count(int(phase), int(P))
+    if n < 0:
+        _check(n)
+    return n
+
+
+def set_variant(variant: int, phase: int = PHASE_M2L):
+    """Forces launch shape `variant` of a phase (-1 restores autotuning)."""
+    _check(lib().hfmm_set_variant(int(phase), int(variant)))
 
 
 def batch_matvec(trees, ks, Ps, xs, ys, stream=None):

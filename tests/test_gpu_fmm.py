@@ -103,3 +103,29 @@ def test_repeat_and_determinism_of_near_field():
     y1 = t.matvec(1.0, 8, qd).cpu().numpy()
     y2 = t.matvec(1.0, 8, qd).cpu().numpy()
     assert rel(y1, y2) < 1e-6
+
+
+@pytest.mark.parametrize("P", [4, 8, 10, 12])
+def test_m2l_launch_shapes_bit_identical(P):
+    """Every launch shape of the matrix-core M2L gives the same bits, and the
+    autotuner reports the shape it chose."""
+    n, k = 20000, 12.0
+    x = synth.sphere_points(n, 31)
+    q = torch.from_numpy(synth.strengths(n, 31)).to("cuda")
+    nv = hfmm.variant_count(P)
+    assert nv >= 1
+    t = hfmm.Tree.from_points(x)
+    outs = []
+    try:
+        for v in range(nv):
+            hfmm.set_variant(v)
+            outs.append(t.matvec(k, P, q).cpu().numpy())
+            assert t.variant(k, P) == v
+    finally:
+        hfmm.set_variant(-1)
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    t2 = hfmm.Tree.from_points(x)
+    y = t2.matvec(k, P, q).cpu().numpy()
+    assert 0 <= t2.variant(k, P) < nv
+    np.testing.assert_array_equal(y, outs[0])
