@@ -362,9 +362,9 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     const int64_t nc = h.ncell();
     int64_t b = nc * (int64_t)(sizeof(int4) * 2 + sizeof(float4) + sizeof(int32_t) + sizeof(int2));
     b += (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)Kp * Rp * sizeof(float2));
-    b += (int64_t)spairs.size() * (16 + (int64_t)P2 * (int64_t)sizeof(float2)) + (nc + 1) * 4;
+    b += (int64_t)spairs.size() * (17 + (int64_t)Kp * (int64_t)sizeof(float2)) + (nc + 1) * 4;
     b += (int64_t)pl.rho.size() * 8 + (int64_t)spairs.size() * 16 + (int64_t)work.size() * 20 +
-         (int64_t)ivals.size() * 8 + 2 * nc * P2 * (int64_t)sizeof(float2);
+         (int64_t)ivals.size() * 8 + (17 * (int64_t)Kp + 16 * P2) * 4 + 2 * nc * P2 * (int64_t)sizeof(float2);
     if (t.bie) b += (int64_t)t.near_col.size() * 8 + t.npanel * 16;
     if (!t.uploaded) b += t.h.nsrc * 40 + t.h.ntgt * 32;
     pl.est_bytes = b;
@@ -383,13 +383,23 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   const HostTree& h = pl.ct;
   const int P = pl.P, P2 = P * P;
   const double k = pl.k;
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
   if ((rc = upload(pl.d_ops, hd.ops)) || (rc = upload(pl.d_rho, pl.rho)) ||
       (rc = upload(pl.d_m2l_pairs, hd.spairs)) || (rc = upload(pl.d_cops, hd.cops)) ||
       (rc = upload(pl.d_m2l_soff, hd.soff)) ||
-      (rc = pl.d_stage.alloc(std::max<size_t>(1, hd.spairs.size()) * (size_t)P2 * sizeof(float2))) ||
+      (rc = pl.d_stage.alloc(std::max<size_t>(1, hd.spairs.size()) * (size_t)Kp * sizeof(float2))) ||
       (rc = upload(pl.d_p2p_work, hd.work)) || (rc = upload(pl.d_p2p_ivals, hd.ivals)) ||
       (rc = upload(pl.d_p2p_total, hd.totals)))
     return rc;
+  {
+    std::vector<int32_t> in, out;
+    m2l_reflection_codes(P, Kp, in, out);
+    std::vector<uint8_t> slot_g(std::max<size_t>(1, hd.spairs.size()), 0);
+    for (const int4& p : hd.spairs) slot_g[p.w] = (uint8_t)p.z;
+    if ((rc = upload(pl.d_bmap, in)) || (rc = upload(pl.d_omap, out)) || (rc = upload(pl.d_slot_g, slot_g)))
+      return rc;
+  }
   // coupling coefficients and tables
   const Coupling& cp = coupling(P);
   std::vector<double2> cv(cp.re.size());
@@ -397,8 +407,6 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   DevBuf d_off, d_lm, d_val;
   if ((rc = upload(d_off, cp.off)) || (rc = upload(d_lm, cp.lm)) || (rc = upload(d_val, cv)))
     return rc;
-  int Kp, Rp;
-  table_dims(P, &Kp, &Rp);
   if ((rc = pl.d_tables.alloc((size_t)pl.n_ops * Kp * Rp * sizeof(float2)))) return rc;
   launch_gen_tables(pl.d_ops.as<OpDesc>(), (int)pl.n_ops, P, k, d_off.as<int32_t>(),
                     d_lm.as<int32_t>(), d_val.as<double2>(), pl.d_tables.as<float2>(), s);
@@ -410,7 +418,8 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   pl.device_bytes = 0;
   for (DevBuf* b : {&pl.d_cells, &pl.d_geo, &pl.d_clev, &pl.d_topo, &pl.d_ops, &pl.d_tables, &pl.d_rho,
                     &pl.d_m2l_pairs, &pl.d_p2p_work, &pl.d_p2p_ivals, &pl.d_p2p_total, &pl.d_M,
-                    &pl.d_L, &pl.d_cops, &pl.d_stage, &pl.d_m2l_soff})
+                    &pl.d_L, &pl.d_cops, &pl.d_stage, &pl.d_m2l_soff, &pl.d_bmap, &pl.d_omap,
+                    &pl.d_slot_g})
     pl.device_bytes += (int64_t)b->bytes;
   if (t.bie && (rc = prepare_bie(t, pl, s))) {
     pl.d_tables.reset();  // not device-ready: the next prepare retries

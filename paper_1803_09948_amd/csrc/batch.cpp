@@ -54,6 +54,7 @@ static InstDev make_inst(Tree& t, Plan& pl) {
   I.L = pl.d_L.as<float2>();
   I.m2l_pairs = pl.d_m2l_pairs.as<int4>();
   I.stage = pl.d_stage.as<float2>();
+  I.slot_g = pl.d_slot_g.as<uint8_t>();
   I.m2l_soff = pl.d_m2l_soff.as<int32_t>();
   I.p2p_work = pl.d_p2p_work.as<int4>();
   I.p2p_ivals = pl.d_p2p_ivals.as<int2>();
@@ -151,9 +152,9 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   for (int l = b.maxlev - 2; l >= 0; --l)
     launch_m2m(b.d_m2m.as<int2>() + b.m2m_off[l], b.m2m_off[l + 1] - b.m2m_off[l], I, P, s);
   if ((rc = mark(2))) return rc;
-  launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, P, batch_variant(b, kPhaseM2L), s);
+  launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, p0.d_bmap.as<int32_t>(), P, batch_variant(b, kPhaseM2L), s);
   if ((rc = mark(3))) return rc;
-  launch_m2l_reduce(b.d_red.as<int2>(), b.n_red, I, P, s);
+  launch_m2l_reduce(b.d_red.as<int2>(), b.n_red, I, p0.d_omap.as<int32_t>(), P, s);
   if ((rc = mark(4))) return rc;
   for (int l = 1; l < b.maxlev; ++l)
     launch_l2l(b.d_l2l.as<int2>() + b.l2l_off[l], b.l2l_off[l + 1] - b.l2l_off[l], I, P, s);
@@ -220,7 +221,7 @@ static int tune_batch(Batch& b, hipStream_t s) {
     for (int v = 0; v < nv; ++v) {
       hipError_t e = hipEventRecord(e0, s);
       if (e == hipSuccess) {
-        launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, b.P, v, s);
+        launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, b.plans[0]->d_bmap.as<int32_t>(), b.P, v, s);
         e = hipGetLastError();
       }
       if (e == hipSuccess) e = hipEventRecord(e1, s);

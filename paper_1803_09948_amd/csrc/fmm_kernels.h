@@ -42,7 +42,8 @@ struct InstDev {
   float2* M;                // multipoles [ncell][P^2]
   float2* L;                // locals [ncell][P^2]
   const int4* m2l_pairs;    // (target, source, symmetry, staging slot)
-  float2* stage;            // M2L staging [n pairs][P^2], slots ordered by target
+  float2* stage;            // M2L staging [n pairs][Kp] (canonical frame), slots ordered by target
+  const uint8_t* slot_g;    // per staging slot: reflection of its pair
   const int32_t* m2l_soff;  // per cell: first staging slot (ncell + 1 entries)
   const int4* p2p_work;     // (tgt begin, tgt end, interval begin, interval end)
   const int2* p2p_ivals;    // (src begin, src end)
@@ -69,11 +70,14 @@ void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream
 void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s);
 int m2l_pairs_per_chunk(int P);
 // chunks: (instance, op, pair begin, pair end), sorted by (instance, op)
-// L[t] = sum of the staging slots of t (items: instance, target cell)
-void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
+// L[t] = sum of the staging slots of t, each mapped back by its reflection's
+// output codes omap [16][P^2] (items: instance, target cell)
+void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int32_t* omap, int P, hipStream_t s);
 // per pair: reflected multipoles through the canonical operator into the pair's staging slot
 // variant < m2l_variant_count(P) selects the launch shape (results are identical)
 int m2l_variant_count(int P);
-void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, int variant, hipStream_t s);
+// bmap: [17][Kp] input codes of the reflections (m2l_input_codes)
+void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, const int32_t* bmap, int P, int variant,
+                hipStream_t s);
 
 }  // namespace hfmm

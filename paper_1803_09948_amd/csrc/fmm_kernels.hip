@@ -400,35 +400,25 @@ __global__ void __launch_bounds__(256) k_l2l(const int2* __restrict__ items,
 // ---------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// Reflection g = bits (fx, fy, fz, swap x<->y) of the cube acts on the
-// harmonics as Y_n^m(sigma r) = i^ph Y_n^{m'}(r), m' = +-m; x -> -x gives
-// m' = -m, ph = 2m;  y -> -y: m' = -m;  z -> -z: ph = 2(n + m);  swap:
-// m' = -m, ph = m (applied in that order).  For the canonical-frame order
-// mr this returns the order mo whose image is mr (the sign map is an
-// involution) and sets ph to the phase of (n, mo).
-__device__ inline int refl_m(int g, int n, int mr, int& ph) {
-  const int flip = (g ^ (g >> 1) ^ (g >> 3)) & 1;
-  const int mo = flip ? -mr : mr;
-  int m = mo, p = 0;
-  if (g & 1) { p += 2 * (m & 1); m = -m; }
-  if (g & 2) { m = -m; }
-  if (g & 4) { p += 2 * ((n + m) & 1); }
-  if (g & 8) { p += m & 3; }
-  ph = p & 3;
-  return mo;
-}
-
-// degree of the coefficient index e = n^2 + n + m (e < 2^16)
-__device__ inline int coef_degree(int e) { return (int)__builtin_sqrtf((float)e + 0.5f); }
-
 // Global-address-space views of pointers read from the instance table (so
 // that loads through them are global loads, not flat ones).
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef const __attribute__((address_space(1))) f2v gcfloat2;
 typedef __attribute__((address_space(1))) f2v gfloat2;
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) f4v gfloat4;
 __device__ inline float2 ld2(gcfloat2* p) {
   const f2v v = *p;
   return make_float2(v.x, v.y);
+}
+
+// i^ph (x + iy) for a reflection code (swap bit 16, sign of the real part
+// bit 31, of the imaginary part bit 30).
+__device__ inline float2 apply_code(float x0, float y0, int e) {
+  const bool swap = e & (1 << 16);
+  const float x = swap ? y0 : x0, y = swap ? x0 : y0;
+  return make_float2(__int_as_float(__float_as_int(x) ^ (e & (int)0x80000000)),
+                     __int_as_float(__float_as_int(y) ^ ((e << 1) & (int)0x80000000)));
 }
 
 // Branch-free multiply by i^code.
@@ -448,7 +438,8 @@ __device__ inline float2 mul_ipow_sel(float2 a, int code) {
 template <int RT, int NCT, int WPE>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
-           const InstDev* __restrict__ insts, int Kp, int Rp, int P2) {
+           const InstDev* __restrict__ insts, const int32_t* __restrict__ bmap, int Kp, int Rp, int P2) {
+  extern __shared__ int smap[];     // [17][Kp] input codes (see m2l_input_codes)
   const int b = blockIdx.x;
   const int item = (b & 7) * per_xcd + (b >> 3);
   if (item >= nitems) return;
@@ -460,30 +451,42 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
   if (np <= 0) return;
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
+  {  // copy the code table: all loads in flight before the LDS writes (indices
+     // are clamped, so a lane past the end copies the last entry again)
+    const int4* src = reinterpret_cast<const int4*>(bmap);
+    int4* dst = reinterpret_cast<int4*>(smap);
+    const int n4 = 17 * Kp / 4;
+    constexpr int U = 8;
+    for (int base = 0; base < n4; base += 64 * U) {
+      int4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = src[min(base + lane + 64 * u, n4 - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) dst[min(base + lane + 64 * u, n4 - 1)] = v[u];
+    }
+  }
   // column t of this lane is pair 16 t + li: (target, source, reflection,
-  // slot); bit 4 of gs marks a column past the item's end (B = 0)
+  // slot); a column past the item's end reads the all-zero code row 16
   gcfloat2* Ms[NCT];
-  int gs[NCT];
+  int gs[NCT], goff[NCT];
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
     const int p = 16 * t + li;
     const bool ok = p < np;
     const int4 pr = I.m2l_pairs[pb + (ok ? p : 0)];
     Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
-    gs[t] = pr.z | (ok ? 0 : 16);
+    gs[t] = ok ? pr.z : 16;
+    goff[t] = gs[t] * Kp + lk;
   }
-  // B gather: B[k] = i^ph M[n^2 + n + mo] for the column's reflection, zero
-  // past P^2; the loads issue now, scale and phase apply when the step runs
-  auto load_b = [&](int k, float2* raw, int* code) {
-    const int n = coef_degree(k);
-    const int mr = k - n * n - n;
-    const bool pad = k >= P2;
+  __syncthreads();
+  // B gather: B[k] = i^ph M[c] from the column's code; the loads issue now,
+  // phase and zeroing apply when the step runs
+  auto load_b = [&](int k4, float2* raw, int* code) {
 #pragma unroll
     for (int t = 0; t < NCT; ++t) {
-      int ph;
-      const int mo = refl_m(gs[t], n, mr, ph);
-      raw[t] = ld2(Ms[t] + (pad ? 0 : n * n + n + mo));
-      code[t] = ph | ((pad | (gs[t] >> 4)) << 2);
+      const int e = smap[goff[t] + k4];
+      raw[t] = ld2(Ms[t] + (e & 0xffff));
+      code[t] = e;
     }
   };
   // the three B operands of the Gauss product
@@ -491,11 +494,13 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
   auto finish_b = [&](const float2* raw, const int* code) {
 #pragma unroll
     for (int t = 0; t < NCT; ++t) {
-      const float sc = (code[t] & 4) ? 0.f : 1.f;
-      const float2 v = mul_ipow_sel(make_float2(raw[t].x * sc, raw[t].y * sc), code[t] & 3);
-      bu[t] = v.x;
-      bd[t] = v.y - v.x;
-      bs[t] = v.x + v.y;
+      const int e = code[t];
+      const bool zero = e & (1 << 17);
+      const float2 v = apply_code(raw[t].x, raw[t].y, e);
+      const float x = zero ? 0.f : v.x, y = zero ? 0.f : v.y;
+      bu[t] = x;
+      bd[t] = y - x;
+      bs[t] = x + y;
     }
   };
   floatx4 k1[NCT][RT], k2[NCT][RT], k3[NCT][RT];
@@ -530,19 +535,19 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
       for (int t = 0; t < NCT; ++t) k3[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bs[t], k3[t][r], 0, 0, 0);
     }
   };
-  const int klast = Kp - 4 + lk;  // clamp: redundant in-bounds loads past the end are unused
+  const int klast = Kp - 4;  // clamp: redundant in-bounds loads past the end are unused
   load_a(lk, a0);
-  load_b(lk, b0, c0);
+  load_b(0, b0, c0);
   int ks = 0;
   for (; ks + 2 <= KS; ks += 2) {
-    const int ka = 4 * (ks + 1) + lk, kb = min(4 * (ks + 2) + lk, klast);
-    load_a(ka, a1);
+    const int ka = 4 * (ks + 1), kb = min(4 * (ks + 2), klast);
+    load_a(ka + lk, a1);
     load_b(ka, b1, c1);
     __builtin_amdgcn_sched_barrier(0);  // issue the next step's loads before these MFMAs
     finish_b(b0, c0);
     mma(a0);
     __builtin_amdgcn_sched_barrier(0);
-    load_a(kb, a0);
+    load_a(kb + lk, a0);
     load_b(kb, b0, c0);
     __builtin_amdgcn_sched_barrier(0);
     finish_b(b1, c1);
@@ -553,58 +558,87 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
     finish_b(b0, c0);
     mma(a0);
   }
-  // each pair owns a staging slot (slots are ordered by target); the
-  // reduction kernel below adds a target's slots in a fixed order.  Lane
-  // (j, q) holds rows 4q..4q+3 of every 16-row tile of column j.
+  // each pair owns a staging slot (slots are ordered by target) holding its
+  // result in the canonical frame; the reduction kernel below maps it back
+  // and adds a target's slots in a fixed order.  Lane (j, q) holds rows
+  // 4q..4q+3 of every 16-row tile of column j: two 16-byte stores each.
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
-    if (gs[t] & 16) continue;
+    if (gs[t] == 16) continue;
     const int slot = I.m2l_pairs[pb + 16 * t + li].w;
-    gfloat2* St = (gfloat2*)(I.stage + (size_t)slot * P2);
+    gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * Kp);
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 16 * r + 4 * lk + v;
-        if (row < P2) {
-          const int n = coef_degree(row);
-          int ph;
-          const int mo = refl_m(gs[t], n, row - n * n - n, ph);
-          const float c1v = k1[t][r][v];
-          const float2 o = mul_ipow_sel(make_float2(c1v - k3[t][r][v], c1v + k2[t][r][v]), (4 - ph) & 3);
-          St[n * n + n + mo] = f2v{o.x, o.y};
-        }
+    for (int r = 0; r < RT; ++r) {
+      const int row = 16 * r + 4 * lk;
+      if (row < Kp) {
+        f4v lo, hi;
+        lo.x = k1[t][r][0] - k3[t][r][0];
+        lo.y = k1[t][r][0] + k2[t][r][0];
+        lo.z = k1[t][r][1] - k3[t][r][1];
+        lo.w = k1[t][r][1] + k2[t][r][1];
+        hi.x = k1[t][r][2] - k3[t][r][2];
+        hi.y = k1[t][r][2] + k2[t][r][2];
+        hi.z = k1[t][r][3] - k3[t][r][3];
+        hi.w = k1[t][r][3] + k2[t][r][3];
+        St[row / 2] = lo;
+        St[row / 2 + 1] = hi;
       }
+    }
   }
 }
 
-// L[t] = sum of t's staging slots, in slot order (deterministic).  Items:
-// (instance, target cell); the cell's slots are [soff[t], soff[t+1]).
-__global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ items,
-                                                    const InstDev* __restrict__ insts, int P2) {
+// L[t] = sum of t's staging slots in slot order (deterministic), each slot's
+// canonical-frame result mapped back by the output codes of its pair's
+// reflection.  Items: (instance, target cell); the cell's slots are
+// [soff[t], soff[t+1]).
+__global__ void __launch_bounds__(128) k_m2l_reduce(const int2* __restrict__ items,
+                                                    const InstDev* __restrict__ insts,
+                                                    const int32_t* __restrict__ omap, int P2, int Kp) {
+  __shared__ int som[16 * kMaxP * kMaxP];
+  {  // all loads of the code table in flight before the LDS writes (clamped indices)
+    const int4* src = reinterpret_cast<const int4*>(omap);
+    int4* dst = reinterpret_cast<int4*>(som);
+    const int n4 = 4 * P2;
+    constexpr int U = 4;
+    for (int base = 0; base < n4; base += 128 * U) {
+      int4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = src[min(base + (int)threadIdx.x + 128 * u, n4 - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) dst[min(base + (int)threadIdx.x + 128 * u, n4 - 1)] = v[u];
+    }
+  }
   const int2 it = items[blockIdx.x];
   const InstDev& I = insts[it.x];
   const int cell = it.y;
   const int s0 = I.m2l_soff[cell], s1 = I.m2l_soff[cell + 1];
+  __syncthreads();
   for (int c = threadIdx.x; c < P2; c += blockDim.x) {
     float sr = 0.f, si = 0.f;
-    gcfloat2* S = (gcfloat2*)(I.stage + (size_t)s0 * P2 + c);
+    gcfloat2* S = (gcfloat2*)(I.stage + (size_t)s0 * Kp);
     int q = s0;
-    for (; q + 4 <= s1; q += 4, S += 4 * P2) {  // four loads in flight, added in slot order
-      const float2 v0 = ld2(S), v1 = ld2(S + P2), v2 = ld2(S + 2 * P2), v3 = ld2(S + 3 * P2);
-      sr += v0.x;
-      si += v0.y;
-      sr += v1.x;
-      si += v1.y;
-      sr += v2.x;
-      si += v2.y;
-      sr += v3.x;
-      si += v3.y;
+    for (; q + 4 <= s1; q += 4, S += 4 * Kp) {  // four loads in flight, added in slot order
+      const int e0 = som[I.slot_g[q] * P2 + c], e1 = som[I.slot_g[q + 1] * P2 + c];
+      const int e2 = som[I.slot_g[q + 2] * P2 + c], e3 = som[I.slot_g[q + 3] * P2 + c];
+      const float2 v0 = ld2(S + (e0 & 0xffff)), v1 = ld2(S + Kp + (e1 & 0xffff));
+      const float2 v2 = ld2(S + 2 * Kp + (e2 & 0xffff)), v3 = ld2(S + 3 * Kp + (e3 & 0xffff));
+      const float2 w0 = apply_code(v0.x, v0.y, e0), w1 = apply_code(v1.x, v1.y, e1);
+      const float2 w2 = apply_code(v2.x, v2.y, e2), w3 = apply_code(v3.x, v3.y, e3);
+      sr += w0.x;
+      si += w0.y;
+      sr += w1.x;
+      si += w1.y;
+      sr += w2.x;
+      si += w2.y;
+      sr += w3.x;
+      si += w3.y;
     }
-    for (; q < s1; ++q, S += P2) {
-      const float2 v = ld2(S);
-      sr += v.x;
-      si += v.y;
+    for (; q < s1; ++q, S += Kp) {
+      const int e = som[I.slot_g[q] * P2 + c];
+      const float2 v = ld2(S + (e & 0xffff));
+      const float2 w = apply_code(v.x, v.y, e);
+      sr += w.x;
+      si += w.y;
     }
     I.L[(size_t)cell * P2 + c] = make_float2(sr, si);
   }
@@ -832,19 +866,22 @@ void launch_l2l(const int2* items, int n, const InstDev* insts, int P, hipStream
 void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
   if (n > 0) k_l2p<<<n, 64, 0, s>>>(items, insts, P);
 }
-void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
-  if (n > 0) k_m2l_reduce<<<n, 128, 0, s>>>(items, insts, P * P);
+void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int32_t* omap, int P, hipStream_t s) {
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
+  if (n > 0) k_m2l_reduce<<<n, 128, 0, s>>>(items, insts, omap, P * P, Kp);
 }
 void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s) {
   if (n > 0) k_p2p<<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
 }
 
 template <int RT, int NCT, int WPE>
-static void launch_m2l_t(const int4* chunks, int nchunks, int sub, const InstDev* insts, int Kp, int Rp,
-                         int P2, hipStream_t s) {
+static void launch_m2l_t(const int4* chunks, int nchunks, int sub, const InstDev* insts, const int32_t* bmap,
+                         int Kp, int Rp, int P2, hipStream_t s) {
   const int nitems = nchunks * sub;
   const int per = (nitems + 7) / 8;
-  k_m2l_mfma<RT, NCT, WPE><<<8 * per, 64, 0, s>>>(chunks, nitems, per, sub, insts, Kp, Rp, P2);
+  k_m2l_mfma<RT, NCT, WPE><<<8 * per, 64, 17 * Kp * sizeof(int), s>>>(chunks, nitems, per, sub, insts, bmap,
+                                                                      Kp, Rp, P2);
 }
 
 // Chunks hold 32 pairs while two 16-pair column tiles of three accumulator
@@ -865,15 +902,16 @@ int m2l_variant_count(int P) { return m2l_pairs_per_chunk(P) == 32 ? 2 : 1; }
 constexpr int m2l_narrow_wpe(int RT) { return RT <= 3 ? 4 : RT <= 7 ? 3 : RT <= 12 ? 2 : 1; }
 
 template <int RT>
-static void launch_m2l_r(bool wide, int sub, const int4* chunks, int nchunks, const InstDev* insts, int Kp,
-                         int Rp, int P2, hipStream_t s) {
+static void launch_m2l_r(bool wide, int sub, const int4* chunks, int nchunks, const InstDev* insts,
+                         const int32_t* bmap, int Kp, int Rp, int P2, hipStream_t s) {
   if constexpr (RT <= 7) {
-    if (wide) return launch_m2l_t<RT, 2, 2>(chunks, nchunks, 1, insts, Kp, Rp, P2, s);
+    if (wide) return launch_m2l_t<RT, 2, 2>(chunks, nchunks, 1, insts, bmap, Kp, Rp, P2, s);
   }
-  launch_m2l_t<RT, 1, m2l_narrow_wpe(RT)>(chunks, nchunks, sub, insts, Kp, Rp, P2, s);
+  launch_m2l_t<RT, 1, m2l_narrow_wpe(RT)>(chunks, nchunks, sub, insts, bmap, Kp, Rp, P2, s);
 }
 
-void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, int variant, hipStream_t s) {
+void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, const int32_t* bmap, int P, int variant,
+                hipStream_t s) {
   if (nchunks <= 0) return;
   const int P2 = P * P;
   int Kp, Rp;
@@ -881,7 +919,7 @@ void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, int P, in
   const int sub = m2l_pairs_per_chunk(P) / 16;
   const bool wide = sub == 2 && variant == 0;
 #define M2L_CASE(R) \
-  case R: launch_m2l_r<R>(wide, sub, chunks, nchunks, insts, Kp, Rp, P2, s); break;
+  case R: launch_m2l_r<R>(wide, sub, chunks, nchunks, insts, bmap, Kp, Rp, P2, s); break;
   switch (Rp / 16) {
     M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6) M2L_CASE(7) M2L_CASE(8)
     M2L_CASE(9) M2L_CASE(10) M2L_CASE(11) M2L_CASE(12) M2L_CASE(13) M2L_CASE(14) M2L_CASE(15)

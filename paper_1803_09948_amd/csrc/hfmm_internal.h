@@ -77,9 +77,13 @@ struct Coupling {
 };
 const Coupling& coupling(int P);
 
-// Symmetry maps of the 16 canonicalising reflections: for symmetry g and
-// coefficient index (n,m): Y_n^m(sigma r) = phase * Y_n^{m'}(r); stored as
-// dst index and phase code (0:1, 1:i, 2:-1, 3:-i).
+// Reflection codes of the matrix-core M2L.  A code idx | swap << 16 |
+// zero << 17 | neg_im << 30 | neg_re << 31 stands for i^ph v[idx], with
+// i^ph (x + iy) = (+-x or +-y) + i (+-y or +-x).  in[g][k], k < Kp (16
+// reflections and a 17th all-zero row): input row k of a pair with
+// reflection g is B[k] = i^ph M[idx].  out[g][c], c < P^2: output
+// coefficient c of such a pair is i^-ph C[idx].
+void m2l_reflection_codes(int P, int Kp, std::vector<int32_t>& in, std::vector<int32_t>& out);
 
 // ---------------------------------------------------------------------------
 // Device-side plan for one (k, P)
@@ -129,9 +133,12 @@ struct Plan {
   DevBuf d_p2p_ivals;            // int2 (src begin, src end)
   DevBuf d_p2p_total;            // int32 sources per work item
   int32_t n_p2p_work = 0;
+  DevBuf d_bmap;                 // int32 [17][Kp]: M2L input codes
+  DevBuf d_omap;                 // int32 [16][P^2]: M2L output codes
+  DevBuf d_slot_g;               // uint8 per staging slot: the pair's reflection
   DevBuf d_M, d_L;               // float2 [ncell][P^2]
   DevBuf d_cops;                 // int2 per cell: (M2M op as child, L2L op as child)
-  DevBuf d_stage;                // float2 [n M2L pairs][P^2] staging, slots ordered by target
+  DevBuf d_stage;                // float2 [n M2L pairs][Kp] staging, slots ordered by target
   DevBuf d_m2l_soff;             // int32 [ncell + 1]: first staging slot of each target cell
   std::vector<int32_t> m2l_targets;  // cells that receive M2L
   // host work lists (cells / chunks of this instance)

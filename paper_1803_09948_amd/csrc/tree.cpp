@@ -328,4 +328,37 @@ const Coupling& coupling(int P) {
   return res.first->second;
 }
 
+// Reflection g = bits (fx, fy, fz, swap x<->y) of the cube acts on the
+// harmonics as Y_n^m(sigma r) = i^ph Y_n^{m'}(r): x -> -x gives m' = -m and
+// ph = 2m; y -> -y gives m' = -m; z -> -z gives ph = 2(n + m); the x<->y
+// swap gives m' = -m and ph = m; g applies them in that order.  For a pair
+// translated through the canonical operator, the input row k = (n, m') takes
+// B[k] = i^ph M[c] with c = (n, m), and the output row k goes back to c as
+// L[c] += i^-ph C[k].
+static int32_t phase_code(int idx, int ph) {
+  // i^ph (x + iy): 0 -> (x, y), 1 -> (-y, x), 2 -> (-x, -y), 3 -> (y, -x)
+  const uint32_t swap = ph & 1, neg_re = (ph == 1 || ph == 2), neg_im = ph >= 2;
+  return (int32_t)((uint32_t)idx | swap << 16 | neg_im << 30 | neg_re << 31);
+}
+
+void m2l_reflection_codes(int P, int Kp, std::vector<int32_t>& in, std::vector<int32_t>& out) {
+  const int P2 = P * P;
+  in.assign(17 * (size_t)Kp, 1 << 17);
+  out.assign(16 * (size_t)P2, 0);
+  for (int g = 0; g < 16; ++g)
+    for (int n = 0; n < P; ++n)
+      for (int m = -n; m <= n; ++m) {
+        int cm = m, ph = 0;
+        if (g & 1) { ph += 2 * std::abs(cm % 2); cm = -cm; }
+        if (g & 2) { cm = -cm; }
+        if (g & 4) { ph += 2 * std::abs((n + cm) % 2); }
+        if (g & 8) { ph += ((cm % 4) + 4) % 4; cm = -cm; }
+        ph &= 3;
+        const int k = n * n + n + cm;   // row in the canonical frame
+        const int c = n * n + n + m;
+        in[(size_t)g * Kp + k] = phase_code(c, ph);
+        out[(size_t)g * P2 + c] = phase_code(k, (4 - ph) & 3);
+      }
+}
+
 }  // namespace hfmm
