@@ -82,18 +82,6 @@ __device__ void bessel_j_all(int nm, double x, double* j) {
   for (int n = 0; n < nm; ++n) j[n] *= scale;
 }
 
-// b_n = j_n(x) (2n+1)!! / rho^n, n < nm.
-__device__ void bessel_j_scaled(int nm, double x, double rho, double* b) {
-  double j[kMaxP];
-  bessel_j_all(nm, x, j);
-  double df = 1.0, rp = 1.0;
-  for (int n = 0; n < nm; ++n) {
-    df *= (2.0 * n + 1.0);
-    b[n] = j[n] * df / rp;
-    rp *= rho;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Translation tables.  For operator o and entry (row r = (n',m'), col c=(n,m)):
 //   T[o][c][r] = sum_l coef * H_l^{m-m'}(t) * scale(n, n'),
@@ -236,49 +224,135 @@ __global__ void k_scatter(const int2* __restrict__ items, const InstDev* __restr
   for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) I.y[I.tgt_perm[i]] = I.ys[i];
 }
 
-// Y_n^m (m >= 0) of direction (dx,dy,dz)/r into a[n*(n+1)/2 + m], FP32, via
-// the normalised recurrences with the complex factor w = (x + i y)/r.
-__device__ inline void ylm_pos(int P, float dx, float dy, float dz, float r, float2* a) {
-  float c, wx, wy;
+// Coefficients of the normalised Legendre recurrences (no Condon-Shortley
+// phase), evaluated at compile time:
+//   Pb_m^m = f_m (x + iy)/r Pb_{m-1}^{m-1},  f_m = sqrt((2m+1)/(2m)),
+//   Pb_{m+1}^m = g_m cos(theta) Pb_m^m,      g_m = sqrt(2m+3),
+//   Pb_n^m = a_nm (cos(theta) Pb_{n-1}^m - b_nm Pb_{n-2}^m),
+//   a_nm = sqrt((4n^2-1)/(n^2-m^2)),  b_nm = sqrt(((n-1)^2-m^2)/(4(n-1)^2-1)).
+constexpr double cx_sqrt(double x) {
+  if (x <= 0.0) return 0.0;
+  double r = x > 1.0 ? x : 1.0;
+  for (int i = 0; i < 200; ++i) r = 0.5 * (r + x / r);
+  return r;
+}
+struct YlmTab {
+  float a[kMaxP][kMaxP], b[kMaxP][kMaxP], f[kMaxP], g[kMaxP];
+};
+constexpr YlmTab make_ylm_tab() {
+  YlmTab t{};
+  for (int n = 0; n < kMaxP; ++n)
+    for (int m = 0; m + 2 <= n; ++m) {
+      t.a[n][m] = (float)cx_sqrt((4.0 * n * n - 1.0) / (double)(n * n - m * m));
+      t.b[n][m] = (float)cx_sqrt((double)((n - 1) * (n - 1) - m * m) / (4.0 * (n - 1) * (n - 1) - 1.0));
+    }
+  for (int m = 0; m < kMaxP; ++m) {
+    t.f[m] = m > 0 ? (float)cx_sqrt((2.0 * m + 1.0) / (2.0 * m)) : 0.f;
+    t.g[m] = (float)cx_sqrt(2.0 * m + 3.0);
+  }
+  return t;
+}
+__constant__ YlmTab c_ylm = make_ylm_tab();
+
+// Visits Y_n^m (m >= 0, FP32) of the direction (dx, dy, dz)/r in the order
+// m = 0..P-1, n = m..P-1, calling f(n, m, Y).  P is a compile-time order, so
+// every index is static.
+template <int P, class F>
+__device__ inline void ylm_visit(float dx, float dy, float dz, float r, F&& f) {
+  float c = 1.f, wx = 0.f, wy = 0.f;
   if (r > 0.f) {
-    float ir = 1.f / r;
+    const float ir = 1.f / r;
     c = dz * ir;
     wx = dx * ir;
     wy = dy * ir;
-  } else {
-    c = 1.f;
-    wx = 0.f;
-    wy = 0.f;
   }
-  // a(m,m)
   float2 pmm = make_float2(0.28209479177387814f, 0.f);  // 1/sqrt(4 pi)
+#pragma unroll
   for (int m = 0; m < P; ++m) {
     if (m > 0) {
-      float f = sqrtf((2.f * m + 1.f) / (2.f * m));
-      pmm = make_float2(f * (pmm.x * wx - pmm.y * wy), f * (pmm.x * wy + pmm.y * wx));
+      const float fm = c_ylm.f[m];
+      pmm = make_float2(fm * (pmm.x * wx - pmm.y * wy), fm * (pmm.x * wy + pmm.y * wx));
     }
-    a[m * (m + 1) / 2 + m] = pmm;
+    f(m, m, pmm);
     if (m + 1 < P) {
-      float f = sqrtf(2.f * m + 3.f) * c;
-      a[(m + 1) * (m + 2) / 2 + m] = make_float2(f * pmm.x, f * pmm.y);
-    }
-    for (int n = m + 2; n < P; ++n) {
-      float an = sqrtf((4.f * n * n - 1.f) / (float)(n * n - m * m));
-      float bn = sqrtf((float)((n - 1) * (n - 1) - m * m) / (4.f * (n - 1) * (n - 1) - 1.f));
-      float2 p1 = a[(n - 1) * n / 2 + m], p2 = a[(n - 2) * (n - 1) / 2 + m];
-      a[n * (n + 1) / 2 + m] = make_float2(an * (c * p1.x - bn * p2.x), an * (c * p1.y - bn * p2.y));
+      const float gm = c_ylm.g[m] * c;
+      float2 p2 = pmm, p1 = make_float2(gm * pmm.x, gm * pmm.y);
+      f(m + 1, m, p1);
+#pragma unroll
+      for (int n = m + 2; n < P; ++n) {
+        const float an = c_ylm.a[n][m], bn = c_ylm.b[n][m];
+        const float2 p = make_float2(an * (c * p1.x - bn * p2.x), an * (c * p1.y - bn * p2.y));
+        f(n, m, p);
+        p2 = p1;
+        p1 = p;
+      }
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// P2M: one wave per leaf.  Mt_n^m = sum_j q_j b_n(k r_j) conj(Y_n^m(dir_j)),
-// Mt_n^{-m} = sum_j q_j b_n Y_n^m, b_n = j_n (2n+1)!!/rho^n.
-// ---------------------------------------------------------------------------
-constexpr int kP2MChunk = 32;
+// b_n = j_n(x) (2n+1)!! / rho^n, n < P (FP64 recurrences, one division):
+// x < 1e-3: the first two terms of the series of j_n; x > P: upward
+// recurrence; otherwise Miller's downward recurrence, normalised by j_0 or
+// j_1.
+template <int P>
+__device__ inline void radial_scaled(double x, double rho, float* b) {
+  if (x < 1e-3) {
+    const double xr = x / rho, x2 = x * x;
+    double p = 1.0;
+#pragma unroll
+    for (int n = 0; n < P; ++n) {
+      b[n] = (float)(p * (1.0 - x2 / (4.0 * n + 6.0)));
+      p *= xr;
+    }
+    return;
+  }
+  double j[P];
+  const double ix = 1.0 / x, s = sin(x), c = cos(x);
+  const double j0 = s * ix, j1 = (s * ix - c) * ix;
+  if (x > (double)P) {
+    j[0] = j0;
+    if constexpr (P > 1) j[1] = j1;
+#pragma unroll
+    for (int n = 1; n + 1 < P; ++n) j[n + 1] = (2.0 * n + 1.0) * ix * j[n] - j[n - 1];
+  } else {
+    // start above P; x >= 1e-3 keeps the values below 1e250 over these steps
+    const int N = P + 16 + (int)x;
+    double fp1 = 0.0, f = 1e-30;
+    for (int n = N; n > P; --n) {
+      const double fm1 = (2.0 * n + 1.0) * ix * f - fp1;
+      fp1 = f;
+      f = fm1;
+    }
+    // f = f_P, fp1 = f_{P+1}
+#pragma unroll
+    for (int n = P; n >= 1; --n) {
+      const double fm1 = (2.0 * n + 1.0) * ix * f - fp1;
+      fp1 = f;
+      f = fm1;
+      j[n - 1] = f;
+    }
+    // f = f_0, fp1 = f_1
+    const double scale = (fabs(j0) >= fabs(j1)) ? j0 / f : j1 / fp1;
+#pragma unroll
+    for (int n = 0; n < P; ++n) j[n] *= scale;
+  }
+  double df = 1.0, rp = 1.0;
+#pragma unroll
+  for (int n = 0; n < P; ++n) {
+    df *= (2.0 * n + 1.0);
+    b[n] = (float)(j[n] * df / rp);
+    rp *= rho;
+  }
+}
 
-__global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items,
-                                            const InstDev* __restrict__ insts, int P) {
+// ---------------------------------------------------------------------------
+// P2M: one wave per leaf, up to 32 bodies per pass (keeps the LDS per wave
+// small enough for several waves per SIMD).
+// Mt_n^m = sum_j q_j b_n(k r_j) conj(Y_n^m(dir_j)), Mt_n^{-m} = sum_j q_j b_n Y_n^m.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items, const InstDev* __restrict__ insts) {
+  constexpr int NY = P * (P + 1) / 2, P2 = P * P;
   const int2 it = items[blockIdx.x];
   const InstDev& I = insts[it.x];
   const int cell = it.y;
@@ -286,51 +360,50 @@ __global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items,
   const float4 g = I.geo[cell];
   const double rh = I.rho[I.clev[cell]];
   const float k = I.k;
-  const int P2 = P * P;
-  __shared__ float2 sa[kP2MChunk][kMaxP * (kMaxP + 1) / 2];
-  __shared__ float2 sq[kP2MChunk];
+  constexpr int CH = 32;
+  __shared__ float2 sa[CH][NY];
+  __shared__ float2 sq[CH];
   const int lane = threadIdx.x;
   float2 acc[4];
+#pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = make_float2(0.f, 0.f);
-  for (int j0 = rg.x; j0 < rg.y; j0 += kP2MChunk) {
-    int nj = min(kP2MChunk, rg.y - j0);
+  for (int j0 = rg.x; j0 < rg.y; j0 += CH) {
+    const int nj = min(CH, rg.y - j0);
     if (lane < nj) {
-      float4 p = I.spos[j0 + lane];
-      float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
-      float r = sqrtf(dx * dx + dy * dy + dz * dz);
-      double b[kMaxP];
-      bessel_j_scaled(P, (double)k * (double)r, rh, b);
+      const float4 p = I.spos[j0 + lane];
+      const float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
+      const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+      float b[P];
+      radial_scaled<P>((double)k * (double)r, rh, b);
       float2* a = sa[lane];
-      ylm_pos(P, dx, dy, dz, r, a);
-      for (int n = 0; n < P; ++n) {
-        float bn = (float)b[n];
-        for (int m = 0; m <= n; ++m) {
-          float2 v = a[n * (n + 1) / 2 + m];
-          a[n * (n + 1) / 2 + m] = make_float2(v.x * bn, v.y * bn);
-        }
-      }
+      ylm_visit<P>(dx, dy, dz, r, [&](int n, int m, float2 y) {
+        a[n * (n + 1) / 2 + m] = make_float2(y.x * b[n], y.y * b[n]);
+      });
       sq[lane] = I.q[j0 + lane];
     }
     __syncthreads();
+#pragma unroll
     for (int t = 0; t < 4; ++t) {
-      int e = lane + 64 * t;
-      if (e >= P2) break;
-      int n = (int)sqrtf((float)e + 0.5f);
-      int m = e - n * n - n;
-      int am = m < 0 ? -m : m;
-      int ai = n * (n + 1) / 2 + am;
-      float2 s = acc[t];
-      for (int j = 0; j < nj; ++j) {
-        float2 y = sa[j][ai];
-        if (m >= 0) y.y = -y.y;  // conj for m >= 0
-        s = cfma(sq[j], y, s);
+      const int e = lane + 64 * t;
+      if (e < P2) {
+        const int n = (int)sqrtf((float)e + 0.5f);
+        const int m = e - n * n - n;
+        const int ai = n * (n + 1) / 2 + (m < 0 ? -m : m);
+        const float sgn = m >= 0 ? -1.f : 1.f;  // conj for m >= 0
+        float2 s = acc[t];
+        for (int j = 0; j < nj; ++j) {
+          float2 y = sa[j][ai];
+          y.y *= sgn;
+          s = cfma(sq[j], y, s);
+        }
+        acc[t] = s;
       }
-      acc[t] = s;
     }
     __syncthreads();
   }
+#pragma unroll
   for (int t = 0; t < 4; ++t) {
-    int e = lane + 64 * t;
+    const int e = lane + 64 * t;
     if (e < P2) I.M[(size_t)cell * P2 + e] = acc[t];
   }
 }
@@ -407,8 +480,19 @@ typedef const __attribute__((address_space(1))) f2v gcfloat2;
 typedef __attribute__((address_space(1))) f2v gfloat2;
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) f4v gfloat4;
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) i4v gcint4;
+__device__ inline int4 ld_int4(const int4* p) {
+  const i4v v = *(gcint4*)p;
+  return make_int4(v.x, v.y, v.z, v.w);
+}
 __device__ inline float2 ld2(gcfloat2* p) {
   const f2v v = *p;
+  return make_float2(v.x, v.y);
+}
+// load of data read once (non-temporal: no reuse expected in the caches)
+__device__ inline float2 ld2_once(gcfloat2* p) {
+  const f2v v = __builtin_nontemporal_load(p);
   return make_float2(v.x, v.y);
 }
 
@@ -473,7 +557,7 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
   for (int t = 0; t < NCT; ++t) {
     const int p = 16 * t + li;
     const bool ok = p < np;
-    const int4 pr = I.m2l_pairs[pb + (ok ? p : 0)];
+    const int4 pr = ld_int4(I.m2l_pairs + pb + (ok ? p : 0));
     Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
     gs[t] = ok ? pr.z : 16;
     goff[t] = gs[t] * Kp + lk;
@@ -565,7 +649,7 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
     if (gs[t] == 16) continue;
-    const int slot = I.m2l_pairs[pb + 16 * t + li].w;
+    const int slot = ld_int4(I.m2l_pairs + pb + 16 * t + li).w;
     gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * Kp);
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
@@ -580,8 +664,8 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
         hi.y = k1[t][r][2] + k2[t][r][2];
         hi.z = k1[t][r][3] - k3[t][r][3];
         hi.w = k1[t][r][3] + k2[t][r][3];
-        St[row / 2] = lo;
-        St[row / 2 + 1] = hi;
+        __builtin_nontemporal_store(lo, &St[row / 2]);  // written once, read once by the reduction
+        __builtin_nontemporal_store(hi, &St[row / 2 + 1]);
       }
     }
   }
@@ -620,8 +704,8 @@ __global__ void __launch_bounds__(128) k_m2l_reduce(const int2* __restrict__ ite
     for (; q + 4 <= s1; q += 4, S += 4 * Kp) {  // four loads in flight, added in slot order
       const int e0 = som[I.slot_g[q] * P2 + c], e1 = som[I.slot_g[q + 1] * P2 + c];
       const int e2 = som[I.slot_g[q + 2] * P2 + c], e3 = som[I.slot_g[q + 3] * P2 + c];
-      const float2 v0 = ld2(S + (e0 & 0xffff)), v1 = ld2(S + Kp + (e1 & 0xffff));
-      const float2 v2 = ld2(S + 2 * Kp + (e2 & 0xffff)), v3 = ld2(S + 3 * Kp + (e3 & 0xffff));
+      const float2 v0 = ld2_once(S + (e0 & 0xffff)), v1 = ld2_once(S + Kp + (e1 & 0xffff));
+      const float2 v2 = ld2_once(S + 2 * Kp + (e2 & 0xffff)), v3 = ld2_once(S + 3 * Kp + (e3 & 0xffff));
       const float2 w0 = apply_code(v0.x, v0.y, e0), w1 = apply_code(v1.x, v1.y, e1);
       const float2 w2 = apply_code(v2.x, v2.y, e2), w3 = apply_code(v3.x, v3.y, e3);
       sr += w0.x;
@@ -635,7 +719,7 @@ __global__ void __launch_bounds__(128) k_m2l_reduce(const int2* __restrict__ ite
     }
     for (; q < s1; ++q, S += Kp) {
       const int e = som[I.slot_g[q] * P2 + c];
-      const float2 v = ld2(S + (e & 0xffff));
+      const float2 v = ld2_once(S + (e & 0xffff));
       const float2 w = apply_code(v.x, v.y, e);
       sr += w.x;
       si += w.y;
@@ -645,11 +729,14 @@ __global__ void __launch_bounds__(128) k_m2l_reduce(const int2* __restrict__ ite
 }
 
 // ---------------------------------------------------------------------------
-// L2P: one wave per leaf; phi(x) = ik sum Lt_n^m (j_n(k r)/sigma_n) Y_n^m(dir).
-// Writes (not accumulates) the sorted output.
+// L2P: one wave per leaf, one target per lane;
+// phi(x) = ik sum_n b_n(k r) sum_m Lt_n^m Y_n^m(dir), accumulated per degree
+// while the harmonics are generated.  Writes (not accumulates) the sorted
+// output.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_l2p(const int2* __restrict__ items,
-                                            const InstDev* __restrict__ insts, int P) {
+template <int P>
+__global__ void __launch_bounds__(64) k_l2p(const int2* __restrict__ items, const InstDev* __restrict__ insts) {
+  constexpr int P2 = P * P;
   const int2 it = items[blockIdx.x];
   const InstDev& I = insts[it.x];
   const int cell = it.y;
@@ -657,29 +744,31 @@ __global__ void __launch_bounds__(64) k_l2p(const int2* __restrict__ items,
   const float4 g = I.geo[cell];
   const double rh = I.rho[I.clev[cell]];
   const float k = I.k;
-  const int P2 = P * P;
-  __shared__ float2 sl[kMaxP * kMaxP];
+  __shared__ float2 sl[P2];
   for (int e = threadIdx.x; e < P2; e += blockDim.x) sl[e] = I.L[(size_t)cell * P2 + e];
   __syncthreads();
-  float2 a[kMaxP * (kMaxP + 1) / 2];
   for (int i = rg.z + threadIdx.x; i < rg.w; i += 64) {
-    float4 p = I.tpos[i];
-    float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
-    float r = sqrtf(dx * dx + dy * dy + dz * dz);
-    double b[kMaxP];
-    bessel_j_scaled(P, (double)k * (double)r, rh, b);
-    ylm_pos(P, dx, dy, dz, r, a);
-    float2 s = make_float2(0.f, 0.f);
-    for (int n = 0; n < P; ++n) {
-      float2 t = cmul(sl[n * n + n], a[n * (n + 1) / 2]);
-      for (int m = 1; m <= n; ++m) {
-        float2 y = a[n * (n + 1) / 2 + m];
-        t = cfma(sl[n * n + n + m], y, t);
-        t = cfma(sl[n * n + n - m], cconj(y), t);
+    const float4 p = I.tpos[i];
+    const float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
+    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+    float b[P];
+    radial_scaled<P>((double)k * (double)r, rh, b);
+    float2 u[P];
+#pragma unroll
+    for (int n = 0; n < P; ++n) u[n] = make_float2(0.f, 0.f);
+    ylm_visit<P>(dx, dy, dz, r, [&](int n, int m, float2 y) {
+      if (m == 0) {
+        u[n] = cfma(sl[n * n + n], y, u[n]);
+      } else {
+        u[n] = cfma(sl[n * n + n + m], y, u[n]);
+        u[n] = cfma(sl[n * n + n - m], cconj(y), u[n]);
       }
-      float bn = (float)b[n];
-      s.x = fmaf(bn, t.x, s.x);
-      s.y = fmaf(bn, t.y, s.y);
+    });
+    float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int n = 0; n < P; ++n) {
+      s.x = fmaf(b[n], u[n].x, s.x);
+      s.y = fmaf(b[n], u[n].y, s.y);
     }
     I.ys[i] = make_float2(-k * s.y, k * s.x);  // times i k
   }
@@ -848,8 +937,17 @@ void launch_gather(const int2* items, int n, const InstDev* insts, hipStream_t s
 void launch_scatter(const int2* items, int n, const InstDev* insts, hipStream_t s) {
   if (n > 0) k_scatter<<<n, 256, 0, s>>>(items, insts);
 }
+#define HFMM_P_CASES(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 void launch_p2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
-  if (n > 0) k_p2m<<<n, 64, 0, s>>>(items, insts, P);
+  if (n <= 0) return;
+  switch (P) {
+#define X(p) \
+  case p: k_p2m<p><<<n, 64, 0, s>>>(items, insts); break;
+    HFMM_P_CASES(X)
+#undef X
+    default: break;
+  }
 }
 void launch_m2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
   if (n <= 0) return;
@@ -864,7 +962,14 @@ void launch_l2l(const int2* items, int n, const InstDev* insts, int P, hipStream
   k_l2l<<<n, 256, 0, s>>>(items, insts, P, Kp, Rp);
 }
 void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
-  if (n > 0) k_l2p<<<n, 64, 0, s>>>(items, insts, P);
+  if (n <= 0) return;
+  switch (P) {
+#define X(p) \
+  case p: k_l2p<p><<<n, 64, 0, s>>>(items, insts); break;
+    HFMM_P_CASES(X)
+#undef X
+    default: break;
+  }
 }
 void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int32_t* omap, int P, hipStream_t s) {
   int Kp, Rp;
