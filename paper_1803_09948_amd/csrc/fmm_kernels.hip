@@ -674,58 +674,69 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 // L[t] = sum of t's staging slots in slot order (deterministic), each slot's
 // canonical-frame result mapped back by the output codes of its pair's
 // reflection.  Items: (instance, target cell); the cell's slots are
-// [soff[t], soff[t+1]).
-__global__ void __launch_bounds__(128) k_m2l_reduce(const int2* __restrict__ items,
+// [soff[t], soff[t+1]).  One thread per output coefficient; the slots'
+// reflections are staged in LDS per group of kRedGroup slots, and eight
+// slots' loads are in flight per thread.
+constexpr int kRedGroup = 512;
+
+__global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ items,
                                                     const InstDev* __restrict__ insts,
                                                     const int32_t* __restrict__ omap, int P2, int Kp) {
-  __shared__ int som[16 * kMaxP * kMaxP];
+  extern __shared__ int red_lds[];
+  int* som = red_lds;              // [16][P2] output codes
+  int* sgo = red_lds + 16 * P2;    // [kRedGroup] reflection * P2 of each slot of the group
+  const int tid = threadIdx.x, nth = blockDim.x;
   {  // all loads of the code table in flight before the LDS writes (clamped indices)
     const int4* src = reinterpret_cast<const int4*>(omap);
     int4* dst = reinterpret_cast<int4*>(som);
     const int n4 = 4 * P2;
     constexpr int U = 4;
-    for (int base = 0; base < n4; base += 128 * U) {
+    for (int base = 0; base < n4; base += nth * U) {
       int4 v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = src[min(base + (int)threadIdx.x + 128 * u, n4 - 1)];
+      for (int u = 0; u < U; ++u) v[u] = src[min(base + tid + nth * u, n4 - 1)];
 #pragma unroll
-      for (int u = 0; u < U; ++u) dst[min(base + (int)threadIdx.x + 128 * u, n4 - 1)] = v[u];
+      for (int u = 0; u < U; ++u) dst[min(base + tid + nth * u, n4 - 1)] = v[u];
     }
   }
   const int2 it = items[blockIdx.x];
   const InstDev& I = insts[it.x];
   const int cell = it.y;
   const int s0 = I.m2l_soff[cell], s1 = I.m2l_soff[cell + 1];
-  __syncthreads();
-  for (int c = threadIdx.x; c < P2; c += blockDim.x) {
-    float sr = 0.f, si = 0.f;
-    gcfloat2* S = (gcfloat2*)(I.stage + (size_t)s0 * Kp);
-    int q = s0;
-    for (; q + 4 <= s1; q += 4, S += 4 * Kp) {  // four loads in flight, added in slot order
-      const int e0 = som[I.slot_g[q] * P2 + c], e1 = som[I.slot_g[q + 1] * P2 + c];
-      const int e2 = som[I.slot_g[q + 2] * P2 + c], e3 = som[I.slot_g[q + 3] * P2 + c];
-      const float2 v0 = ld2_once(S + (e0 & 0xffff)), v1 = ld2_once(S + Kp + (e1 & 0xffff));
-      const float2 v2 = ld2_once(S + 2 * Kp + (e2 & 0xffff)), v3 = ld2_once(S + 3 * Kp + (e3 & 0xffff));
-      const float2 w0 = apply_code(v0.x, v0.y, e0), w1 = apply_code(v1.x, v1.y, e1);
-      const float2 w2 = apply_code(v2.x, v2.y, e2), w3 = apply_code(v3.x, v3.y, e3);
-      sr += w0.x;
-      si += w0.y;
-      sr += w1.x;
-      si += w1.y;
-      sr += w2.x;
-      si += w2.y;
-      sr += w3.x;
-      si += w3.y;
+  const int c = tid;
+  float sr = 0.f, si = 0.f;
+  for (int g0 = s0; g0 < s1; g0 += kRedGroup) {
+    const int ng = min(kRedGroup, s1 - g0);
+    __syncthreads();
+    for (int e = tid; e < ng; e += nth) sgo[e] = (int)I.slot_g[g0 + e] * P2;
+    __syncthreads();
+    if (c < P2) {
+      gcfloat2* S = (gcfloat2*)(I.stage + (size_t)g0 * Kp);
+      int q = 0;
+      for (; q + 8 <= ng; q += 8, S += 8 * Kp) {  // eight loads in flight, added in slot order
+        int e[8];
+        float2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = som[sgo[q + u] + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ld2_once(S + u * Kp + (e[u] & 0xffff));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const float2 w = apply_code(v[u].x, v[u].y, e[u]);
+          sr += w.x;
+          si += w.y;
+        }
+      }
+      for (; q < ng; ++q, S += Kp) {
+        const int e = som[sgo[q] + c];
+        const float2 v = ld2_once(S + (e & 0xffff));
+        const float2 w = apply_code(v.x, v.y, e);
+        sr += w.x;
+        si += w.y;
+      }
     }
-    for (; q < s1; ++q, S += Kp) {
-      const int e = som[I.slot_g[q] * P2 + c];
-      const float2 v = ld2_once(S + (e & 0xffff));
-      const float2 w = apply_code(v.x, v.y, e);
-      sr += w.x;
-      si += w.y;
-    }
-    I.L[(size_t)cell * P2 + c] = make_float2(sr, si);
   }
+  if (c < P2) I.L[(size_t)cell * P2 + c] = make_float2(sr, si);
 }
 
 // ---------------------------------------------------------------------------
@@ -974,7 +985,9 @@ void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream
 void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int32_t* omap, int P, hipStream_t s) {
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  if (n > 0) k_m2l_reduce<<<n, 128, 0, s>>>(items, insts, omap, P * P, Kp);
+  const int nth = 64 * ((P * P + 63) / 64);  // one thread per coefficient
+  const size_t lds = (16 * (size_t)P * P + kRedGroup) * sizeof(int);
+  if (n > 0) k_m2l_reduce<<<n, nth, lds, s>>>(items, insts, omap, P * P, Kp);
 }
 void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s) {
   if (n > 0) k_p2p<<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
