@@ -99,8 +99,11 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
     for (const int4& c : pl.m2l_chunks_h) m2l.push_back(make_int4(i, c.x, c.y, c.z));
     for (int c : pl.m2l_targets) red.push_back(make_int2(i, c));
   }
-  // per-level M2M (parents, deepest first) and L2L (children, root first) lists
-  std::vector<int2> m2m, l2l;
+  // per-level M2M (parents, deepest first) and L2L (children, root first)
+  // items: up to 16 destination cells of one instance, level (and, for L2L,
+  // octant) per item
+  std::vector<int4> m2m, l2l;
+  std::vector<int32_t> m2m_cols, l2l_cols;
   b.m2m_off.assign(b.maxlev + 1, 0);
   b.l2l_off.assign(b.maxlev + 1, 0);
   for (int l = 0; l < b.maxlev; ++l) {
@@ -108,10 +111,37 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
     b.l2l_off[l] = (int)l2l.size();
     for (int i = 0; i < b.count; ++i) {
       Plan& pl = *plans[i];
-      if (l < (int)pl.m2m_cells.size())
-        for (int c : pl.m2m_cells[l]) m2m.push_back(make_int2(i, c));
-      if (l < (int)pl.l2l_cells.size())
-        for (int c : pl.l2l_cells[l]) l2l.push_back(make_int2(i, c));
+      const HostTree& h = pl.ct;
+      auto octant = [&](int c) {
+        return (h.ijk[3 * c] & 1) | ((h.ijk[3 * c + 1] & 1) << 1) | ((h.ijk[3 * c + 2] & 1) << 2);
+      };
+      if (l < (int)pl.m2m_cells.size() && !pl.m2m_cells[l].empty()) {
+        const std::vector<int>& par = pl.m2m_cells[l];
+        for (size_t j = 0; j < par.size(); j += 16) {
+          const int cnt = (int)std::min<size_t>(16, par.size() - j);
+          m2m.push_back(make_int4(i, pl.m2m_base[l + 1], (int)(m2m_cols.size() / 9), cnt));
+          for (int u = 0; u < cnt; ++u) {
+            const int p = par[j + u];
+            int ch[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+            for (int c = h.cb[p]; c < h.ce[p]; ++c) ch[octant(c)] = c;
+            m2m_cols.push_back(p);
+            m2m_cols.insert(m2m_cols.end(), ch, ch + 8);
+          }
+        }
+      }
+      if (l < (int)pl.l2l_cells.size() && !pl.l2l_cells[l].empty()) {
+        std::vector<int> by[8];
+        for (int c : pl.l2l_cells[l]) by[octant(c)].push_back(c);
+        for (int o = 0; o < 8; ++o)
+          for (size_t j = 0; j < by[o].size(); j += 16) {
+            const int cnt = (int)std::min<size_t>(16, by[o].size() - j);
+            l2l.push_back(make_int4(i, pl.l2l_base[l] + o, (int)(l2l_cols.size() / 2), cnt));
+            for (int u = 0; u < cnt; ++u) {
+              l2l_cols.push_back(by[o][j + u]);
+              l2l_cols.push_back(h.parent[by[o][j + u]]);
+            }
+          }
+      }
     }
   }
   b.m2m_off[b.maxlev] = (int)m2m.size();
@@ -120,6 +150,7 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
   if ((rc = up(b.d_inst, b.hinst)) || (rc = up(b.d_zero, zero)) || (rc = up(b.d_gather, gather)) ||
       (rc = up(b.d_scatter, scatter)) || (rc = up(b.d_p2m, p2m)) || (rc = up(b.d_l2p, l2p)) ||
       (rc = up(b.d_p2p, p2p)) || (rc = up(b.d_m2l, m2l)) || (rc = up(b.d_m2m, m2m)) || (rc = up(b.d_l2l, l2l)) ||
+      (rc = up(b.d_m2m_cols, m2m_cols)) || (rc = up(b.d_l2l_cols, l2l_cols)) ||
       (rc = up(b.d_red, red)))
     return rc;
   b.n_zero = (int)zero.size();
@@ -150,14 +181,16 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   launch_p2m(b.d_p2m.as<int2>(), b.n_p2m, I, P, s);
   if ((rc = mark(1))) return rc;
   for (int l = b.maxlev - 2; l >= 0; --l)
-    launch_m2m(b.d_m2m.as<int2>() + b.m2m_off[l], b.m2m_off[l + 1] - b.m2m_off[l], I, P, s);
+    launch_m2m(b.d_m2m.as<int4>() + b.m2m_off[l], b.m2m_off[l + 1] - b.m2m_off[l], b.d_m2m_cols.as<int32_t>(), I,
+               P, s);
   if ((rc = mark(2))) return rc;
   launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, p0.d_bmap.as<int32_t>(), P, batch_variant(b, kPhaseM2L), s);
   if ((rc = mark(3))) return rc;
   launch_m2l_reduce(b.d_red.as<int2>(), b.n_red, I, p0.d_omap.as<int32_t>(), P, s);
   if ((rc = mark(4))) return rc;
   for (int l = 1; l < b.maxlev; ++l)
-    launch_l2l(b.d_l2l.as<int2>() + b.l2l_off[l], b.l2l_off[l + 1] - b.l2l_off[l], I, P, s);
+    launch_l2l(b.d_l2l.as<int4>() + b.l2l_off[l], b.l2l_off[l + 1] - b.l2l_off[l], b.d_l2l_cols.as<int32_t>(), I,
+               P, s);
   if ((rc = mark(5))) return rc;
   launch_l2p(b.d_l2p.as<int2>(), b.n_l2p, I, P, s);
   if ((rc = mark(6))) return rc;

@@ -64,8 +64,12 @@ void launch_zero(const int2* items, int n, const InstDev* insts, hipStream_t s);
 void launch_gather(const int2* items, int n, const InstDev* insts, hipStream_t s);
 void launch_scatter(const int2* items, int n, const InstDev* insts, hipStream_t s);
 void launch_p2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
-void launch_m2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
-void launch_l2l(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
+// M2M / L2L items: (instance, op, first column entry, count <= 16).  M2M
+// column entries are 9 int32 (parent, child of octant 0..7 or -1) and op is
+// the octant-0 operator of the child level; L2L entries are 2 int32 (child,
+// parent), all children of one item sharing the operator op.
+void launch_m2m(const int4* items, int n, const int32_t* cols, const InstDev* insts, int P, hipStream_t s);
+void launch_l2l(const int4* items, int n, const int32_t* cols, const InstDev* insts, int P, hipStream_t s);
 void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
 void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s);
 int m2l_pairs_per_chunk(int P);

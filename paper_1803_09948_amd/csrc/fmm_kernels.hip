@@ -409,51 +409,6 @@ __global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items, cons
 }
 
 // ---------------------------------------------------------------------------
-// M2M (children -> parent) and L2L (parent -> child): dense P^2 x P^2
-// translations, one block per destination cell.  cops[c] = (op of c's M2M
-// as a child, op of c's L2L as a child).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_m2m(const int2* __restrict__ items,
-                                             const InstDev* __restrict__ insts, int P, int Kp, int Rp) {
-  const int2 it = items[blockIdx.x];
-  const InstDev& I = insts[it.x];
-  const int cell = it.y;
-  const int4 tp = I.topo[cell];  // (child begin, child end, parent, octant | level << 3)
-  const int P2 = P * P;
-  __shared__ float2 sm[kMaxP * kMaxP];
-  float2 acc = make_float2(0.f, 0.f);
-  const int r = threadIdx.x;
-  for (int ch = tp.x; ch < tp.y; ++ch) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < P2; e += blockDim.x) sm[e] = I.M[(size_t)ch * P2 + e];
-    __syncthreads();
-    const float2* T = I.tables + (size_t)I.cops[ch].x * Kp * Rp;
-    if (r < P2)
-      for (int c = 0; c < P2; ++c) acc = cfma(T[(size_t)c * Rp + r], sm[c], acc);
-  }
-  if (r < P2) I.M[(size_t)cell * P2 + r] = acc;
-}
-
-__global__ void __launch_bounds__(256) k_l2l(const int2* __restrict__ items,
-                                             const InstDev* __restrict__ insts, int P, int Kp, int Rp) {
-  const int2 it = items[blockIdx.x];
-  const InstDev& I = insts[it.x];
-  const int cell = it.y;
-  const int parent = I.topo[cell].z;
-  const int P2 = P * P;
-  __shared__ float2 sl[kMaxP * kMaxP];
-  for (int e = threadIdx.x; e < P2; e += blockDim.x) sl[e] = I.L[(size_t)parent * P2 + e];
-  __syncthreads();
-  const float2* T = I.tables + (size_t)I.cops[cell].y * Kp * Rp;
-  const int r = threadIdx.x;
-  if (r < P2) {
-    float2 s = I.L[(size_t)cell * P2 + r];
-    for (int c = 0; c < P2; ++c) s = cfma(T[(size_t)c * Rp + r], sl[c], s);
-    I.L[(size_t)cell * P2 + r] = s;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // M2L on the matrix cores.  One wave takes up to 16*NCT pairs that share one
 // canonical operator T (P^2 x P^2 complex).  The B matrix (k = input
 // coefficient, column = pair) holds M' = D^T M, gathered straight from the
@@ -669,6 +624,104 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// M2M (children -> parent) and L2L (parent -> child) on the matrix cores.
+// One wave owns up to 16 destination cells of one instance and level, so
+// it writes them directly (no staging, no atomics).  Items: (instance, op,
+// first column entry, count).  M2M (MODE 0): a column entry is (parent,
+// child of octant 0..7 or -1); op is the level's octant-0 operator and the
+// wave runs the 8 octant operators in order, M[parent] = sum_o T_o M[child_o].
+// L2L (MODE 1): an entry is (child, parent), all of one octant operator op;
+// L[child] += T_op L[parent].  Same tiles and Gauss product as M2L.
+// ---------------------------------------------------------------------------
+template <int RT, int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT <= 12 ? 2 : 1)))
+k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
+          const InstDev* __restrict__ insts, int Kp, int Rp, int P2) {
+  constexpr int STRIDE = MODE == 0 ? 9 : 2;
+  const int4 it = items[blockIdx.x];
+  const InstDev& I = insts[it.x];
+  const int lane = threadIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool ok = li < it.w;
+  const int32_t* cj = cols + (size_t)(it.z + (ok ? li : 0)) * STRIDE;
+  const int dst = cj[0];
+  float2* X = MODE == 0 ? I.M : I.L;
+  floatx4 k1[RT], k2[RT], k3[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    k1[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    k2[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    k3[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int KS = Kp >> 2;
+  auto run = [&](int op, int src) {  // acc += T_op X[src] (src < 0: zero column)
+    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li;
+    const bool zc = !ok || src < 0;
+    gcfloat2* B = (gcfloat2*)(X + (size_t)(zc ? 0 : src) * P2);
+    float2 a0[RT], a1[RT], b0, b1;
+    auto load_a = [&](int k, float2* out) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * r);
+    };
+    auto load_b = [&](int k) { return ld2(B + min(k, P2 - 1)); };
+    auto mma = [&](const float2* a, float2 bv, int k) {
+      const bool z = zc || k >= P2;
+      const float x = z ? 0.f : bv.x, y = z ? 0.f : bv.y;
+      const float bu = x, bd = y - x, bs = x + y;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        const float ar = a[r].x, ai = a[r].y, as = ar + ai;
+        k1[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bu, k1[r], 0, 0, 0);
+        k2[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bd, k2[r], 0, 0, 0);
+        k3[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bs, k3[r], 0, 0, 0);
+      }
+    };
+    load_a(lk, a0);
+    b0 = load_b(lk);
+    int ks = 0;
+    for (; ks + 2 <= KS; ks += 2) {
+      const int ka = 4 * (ks + 1) + lk, kb = min(4 * (ks + 2), Kp - 4) + lk;
+      load_a(ka, a1);
+      b1 = load_b(ka);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(a0, b0, 4 * ks + lk);
+      __builtin_amdgcn_sched_barrier(0);
+      load_a(kb, a0);
+      b0 = load_b(kb);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(a1, b1, ka);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (ks < KS) mma(a0, b0, 4 * ks + lk);
+  };
+  if constexpr (MODE == 0) {
+    for (int o = 0; o < 8; ++o) {
+      const int src = cj[1 + o];
+      if (__any(ok && src >= 0)) run(it.y + o, src);  // skip octants no column has
+    }
+  } else {
+    run(it.y, cj[1]);
+  }
+  if (!ok) return;
+  float2* D = X + (size_t)dst * P2;
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * r + 4 * lk + v;
+      if (row < P2) {
+        float2 val = make_float2(k1[r][v] - k3[r][v], k1[r][v] + k2[r][v]);
+        if (MODE == 1) {
+          const float2 old = D[row];
+          val.x += old.x;
+          val.y += old.y;
+        }
+        D[row] = val;
+      }
+    }
 }
 
 // L[t] = sum of t's staging slots in slot order (deterministic), each slot's
@@ -960,17 +1013,24 @@ void launch_p2m(const int2* items, int n, const InstDev* insts, int P, hipStream
     default: break;
   }
 }
-void launch_m2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
+template <int MODE>
+static void launch_tr(const int4* items, int n, const int32_t* cols, const InstDev* insts, int P, hipStream_t s) {
   if (n <= 0) return;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  k_m2m<<<n, 256, 0, s>>>(items, insts, P, Kp, Rp);
+  switch (Rp / 16) {
+#define X(R) \
+  case R: k_tr_mfma<R, MODE><<<n, 64, 0, s>>>(items, cols, insts, Kp, Rp, P * P); break;
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#undef X
+    default: break;
+  }
 }
-void launch_l2l(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
-  if (n <= 0) return;
-  int Kp, Rp;
-  table_dims(P, &Kp, &Rp);
-  k_l2l<<<n, 256, 0, s>>>(items, insts, P, Kp, Rp);
+void launch_m2m(const int4* items, int n, const int32_t* cols, const InstDev* insts, int P, hipStream_t s) {
+  launch_tr<0>(items, n, cols, insts, P, s);
+}
+void launch_l2l(const int4* items, int n, const int32_t* cols, const InstDev* insts, int P, hipStream_t s) {
+  launch_tr<1>(items, n, cols, insts, P, s);
 }
 void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
   if (n <= 0) return;

@@ -163,6 +163,7 @@ struct Batch {
   std::vector<InstDev> hinst;
   DevBuf d_inst;
   DevBuf d_zero, d_gather, d_scatter, d_p2m, d_l2p, d_p2p, d_m2l, d_m2m, d_l2l, d_red;
+  DevBuf d_m2m_cols, d_l2l_cols;      // M2M / L2L column entries (see launch_m2m / launch_l2l)
   int n_zero = 0, n_gather = 0, n_scatter = 0, n_p2m = 0, n_l2p = 0, n_p2p = 0, n_m2l = 0, n_red = 0;
   std::vector<int> m2m_off, l2l_off;  // per level offsets into d_m2m / d_l2l
   hipStream_t stream = nullptr;       // private stream for graph capture / replay
