@@ -14,7 +14,9 @@ Other workloads (`--workload`):
   serve  Poisson arrivals at 50/s of sound-soft scattering solves
          (icosphere subdivision 3..6, sphere or ellipsoid, k uniform in
          [1, 30], P = 10, GMRES(30) to 1e-4): solves/s and p50/p99 latency of
-         the continuous-batching server vs the one-at-a-time path.
+         the continuous-batching server vs the one-at-a-time path;
+  precision  FP32 product vs its FP64 variant (same tree, lists, P) vs the
+         FP64 direct sum on 1000 seeded targets, N = 2^20 and 2^23, P = 8/10/12.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
 one GPU.
@@ -189,9 +191,78 @@ def bench_serve(a):
     print(json.dumps(out))
 
 
+def bench_precision(a):
+    """FP32 product vs its FP64 variant (same tree, lists and P) vs the FP64
+    direct sum on 1000 seeded sampled targets, N in a.prec_n, P in 8/10/12,
+    k = 16 pi (16 wavelengths across the unit sphere)."""
+    import torch
+
+    import synth
+    from paper_1803_09948_amd import hfmm
+
+    k = 16.0 * math.pi
+    rows = []
+    for n in [int(v) for v in a.prec_n.split(",")]:
+        x = synth.sphere_points(n, 23)
+        q = synth.strengths(n, 23)
+        xd = torch.from_numpy(x).to("cuda")
+        q32 = torch.from_numpy(q).to("cuda")
+        q64 = q32.to(torch.complex128)
+        idx = np.sort(np.random.default_rng(5).choice(n, 1000, replace=False))
+        idt = torch.from_numpy(idx).to("cuda")
+        t0 = time.perf_counter()
+        ref = hfmm.direct64(xd, q64, xd[idt], k)
+        torch.cuda.synchronize()
+        log(f"n={n}: FP64 direct sum on 1000 targets in {time.perf_counter() - t0:.1f} s")
+        for P in [int(v) for v in a.prec_P.split(",")]:
+            t0 = time.perf_counter()
+            tree = hfmm.Tree.from_points(x, ncrit=a.ncrit)
+            tree.prepare(k, P)
+            torch.cuda.synchronize()
+            t_prep = time.perf_counter() - t0
+            y32 = tree.matvec(k, P, q32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tree.matvec(k, P, q32, y32)
+            torch.cuda.synchronize()
+            t32 = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            y64 = tree.matvec64(k, P, q64)
+            torch.cuda.synchronize()
+            t64 = time.perf_counter() - t0
+
+            def err(u, v):
+                return float(torch.linalg.vector_norm(u - v) / torch.linalg.vector_norm(v))
+
+            s32, s64 = y32[idt].to(torch.complex128), y64[idt]
+            st = tree.stats(k, P)
+            row = {"n": n, "P": P, "err_fp32_vs_direct": err(s32, ref), "err_fp64_vs_direct": err(s64, ref),
+                   "err_fp32_vs_fp64_sampled": err(s32, s64),
+                   "err_fp32_vs_fp64_all": err(y32.to(torch.complex128), y64),
+                   "ms_fp32": t32 * 1e3, "ms_fp64": t64 * 1e3, "setup_s": t_prep,
+                   "n_m2l": st["n_m2l"], "p2p_body_pairs": st["p2p_body_pairs"]}
+            rows.append(row)
+            log(json.dumps(row))
+            del y32, y64
+            tree.free()
+            torch.cuda.empty_cache()
+    out = {
+        "metric": "relative error vs FP64 direct sum on 1000 sampled targets (FP32 product and FP64 variant)",
+        "value": next((r["err_fp32_vs_direct"] for r in rows if r["P"] == 10), rows[0]["err_fp32_vs_direct"]),
+        "unit": "relative 2-norm", "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (and f64 reference)", "data": "synthetic",
+        "config": {"workload": f"N in {a.prec_n} uniform on the unit sphere, k=16 pi, P in {a.prec_P}, "
+                               f"ncrit={a.ncrit}, theta=0.5, kappa=0.4P, 1000 seeded targets"},
+        "results": rows,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "copy"], default="matvec")
+    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "precision", "copy"], default="matvec")
+    ap.add_argument("--prec-n", default="1048576,8388608", help="sizes of the precision workload")
+    ap.add_argument("--prec-P", default="8,10,12", help="orders of the precision workload")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--count", type=int, default=64, help="instances (batch workload)")
     ap.add_argument("--nreq", type=int, default=24, help="requests (serve workload)")
@@ -217,6 +288,8 @@ def main():
         return bench_serve(a)
     if a.workload == "copy":
         return bench_copy(a)
+    if a.workload == "precision":
+        return bench_precision(a)
 
     import torch
 

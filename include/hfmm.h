@@ -58,7 +58,9 @@ typedef struct {
   double eta;        /* BIE near pattern |c_i - c_j| < eta h_j (default 2) */
   int32_t near_levels; /* BIE near integrals: 4^near_levels sub-triangles (default 3) */
   int32_t near_order;  /* BIE near integrals: n x n collapsed Gauss rule (default 6) */
-  int32_t reserved[8];
+  int32_t stage_mb;    /* M2L staging budget in MiB (default 32768; <= 0: default): larger
+                          problems run the M2L in segments of targets whose staging fits */
+  int32_t reserved[7];
 } hfmm_opts;
 
 typedef struct {
@@ -116,6 +118,27 @@ int hfmm_prepare(hfmm_tree* tree, double k, int32_t P, void* stream);
  *  Point handle: y_i = sum_{j, R_ij > 0} x_j G(x_i, x_j) up to FMM truncation. */
 int hfmm_matvec(hfmm_tree* tree, double k, int32_t P, const void* x_dev,
                 void* y_dev, void* stream);
+
+/* FP64 variant of hfmm_matvec for a point handle: the same tree, lists,
+ * translation operators and P (eq. 12-14 truncated at P), every step in
+ * FP64, so that its difference to hfmm_matvec is the FP32 rounding of the
+ * product and its difference to the direct sum the truncation error.  A
+ * precision reference, not a fast path (plain kernels; M2L accumulates with
+ * FP64 atomics, so the last bits may vary between calls).
+ *  x_dev, y_dev: complex128[n] device, caller order; must not alias.
+ *  Allocates FP64 tables and expansions on first use for (k, P).
+ *  EINVAL: BIE handle, NULL, k or P as for hfmm_matvec.  ENOMEM, EHIP. */
+int hfmm_matvec64(hfmm_tree* tree, double k, int32_t P, const void* x_dev,
+                  void* y_dev, void* stream);
+
+/* Direct sum in FP64 on the device (eq. (11) with the kernel of eq. (6)):
+ * y_i = sum_{j: R_ij > 0} q_j exp(i k R_ij) / (4 pi R_ij), R_ij = |t_i - s_j|.
+ *  src_dev: float[n][3], q_dev: complex128[n], tgt_dev: float[m][3],
+ *  y_dev: complex128[m]; all device memory owned by the caller.
+ *  EINVAL: n or m negative, NULL pointers, k negative or non-finite. */
+int hfmm_direct64(const float* src_dev, const void* q_dev, int64_t n,
+                  const float* tgt_dev, int64_t m, double k, void* y_dev,
+                  void* stream);
 
 /* Restarted GMRES(restart) for A x = b on a BIE handle (Sec. 5.1: complex
  * GMRES, exit at a relative residual tol, Sec. 6.4).  The Arnoldi

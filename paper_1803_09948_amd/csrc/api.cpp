@@ -255,17 +255,10 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
   }
   pl.n_tables = (int64_t)ops.size() - m2l_base;
   pl.n_ops = (int64_t)ops.size();
-  // group pairs by operator, then target, then source
-  std::vector<int32_t> order(npair);
-  std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    const int4 &p = pairs[x], &q = pairs[y];
-    if (p.w != q.w) return p.w < q.w;
-    if (p.x != q.x) return p.x < q.x;
-    return p.y < q.y;
-  });
   // staging slots: pairs ordered by (target, source), so each target's
   // slots are contiguous and summed in a fixed order
+  int Kp0, Rp0;
+  table_dims(P, &Kp0, &Rp0);
   std::vector<int32_t> slot(npair);
   {
     std::vector<int32_t> bytgt(npair);
@@ -285,21 +278,64 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
       hd.soff[c + 1] += hd.soff[c];
     }
   }
+  // staging segments: runs of consecutive targets whose slots fit the
+  // staging budget (a target with more slots than the budget gets its own)
+  std::vector<int32_t> seg_of(h.ncell(), 0);
+  pl.m2l_segs.clear();
+  {
+    const int64_t budget = std::max<int64_t>(1, t.stage_bytes / ((int64_t)Kp0 * (int64_t)sizeof(float2)));
+    M2LSeg cur{};
+    for (size_t i = 0; i < pl.m2l_targets.size(); ++i) {
+      const int c = pl.m2l_targets[i];
+      const int64_t n = hd.soff[c + 1] - hd.soff[c];
+      if (cur.slot_e > cur.slot_b && (cur.slot_e - cur.slot_b) + n > budget) {
+        pl.m2l_segs.push_back(cur);
+        cur = M2LSeg{};
+        cur.slot_b = cur.slot_e = hd.soff[c];
+        cur.tgt_b = cur.tgt_e = (int)i;
+      }
+      if (cur.tgt_e == cur.tgt_b) {
+        cur.slot_b = hd.soff[c];
+        cur.tgt_b = (int)i;
+      }
+      cur.slot_e = hd.soff[c + 1];
+      cur.tgt_e = (int)i + 1;
+      seg_of[c] = (int)pl.m2l_segs.size();
+    }
+    if (cur.tgt_e > cur.tgt_b) pl.m2l_segs.push_back(cur);
+  }
+  // group pairs by segment, then operator, then target, then source
+  std::vector<int32_t> order(npair);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const int4 &p = pairs[x], &q = pairs[y];
+    if (seg_of[p.x] != seg_of[q.x]) return seg_of[p.x] < seg_of[q.x];
+    if (p.w != q.w) return p.w < q.w;
+    if (p.x != q.x) return p.x < q.x;
+    return p.y < q.y;
+  });
   std::vector<int4>& spairs = hd.spairs;
   spairs.resize(npair);
   std::vector<int4> chunks;
-  for (size_t i = 0; i < npair; ++i) {
+  hd.slot_g.assign(std::max<size_t>(1, npair), 0);
+  for (size_t i = 0; i < npair; ++i) {  // slots are local to the pair's segment
     const int4& p = pairs[order[i]];
-    spairs[i] = make_int4(p.x, p.y, p.z, slot[order[i]]);
+    spairs[i] = make_int4(p.x, p.y, p.z, slot[order[i]] - pl.m2l_segs[seg_of[p.x]].slot_b);
+    hd.slot_g[slot[order[i]]] = (uint8_t)p.z;
   }
   const int CH = m2l_pairs_per_chunk(P);
   for (size_t i = 0; i < npair;) {
     size_t j = i;
-    const int op = pairs[order[i]].w;
-    while (j < npair && pairs[order[j]].w == op && j - i < (size_t)CH) ++j;
+    const int4& pi = pairs[order[i]];
+    const int op = pi.w, sg = seg_of[pi.x];
+    if (pl.m2l_segs[sg].chunk_e == 0) pl.m2l_segs[sg].chunk_b = (int)chunks.size();
+    while (j < npair && pairs[order[j]].w == op && seg_of[pairs[order[j]].x] == sg && j - i < (size_t)CH) ++j;
     chunks.push_back(make_int4(op, (int)i, (int)j, 0));
+    pl.m2l_segs[sg].chunk_e = (int)chunks.size();
     i = j;
   }
+  pl.max_seg_slots = 0;
+  for (const M2LSeg& sgm : pl.m2l_segs) pl.max_seg_slots = std::max<int64_t>(pl.max_seg_slots, sgm.slot_e - sgm.slot_b);
   pl.n_m2l_chunks = (int32_t)chunks.size();
   pl.m2l_chunks_h = chunks;
   // per-cell operator indices and per-level work lists
@@ -362,7 +398,7 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     const int64_t nc = h.ncell();
     int64_t b = nc * (int64_t)(sizeof(int4) * 2 + sizeof(float4) + sizeof(int32_t) + sizeof(int2));
     b += (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)Kp * Rp * sizeof(float2));
-    b += (int64_t)spairs.size() * (17 + (int64_t)Kp * (int64_t)sizeof(float2)) + (nc + 1) * 4;
+    b += (int64_t)spairs.size() * 17 + pl.max_seg_slots * (int64_t)Kp * (int64_t)sizeof(float2) + (nc + 1) * 4;
     b += (int64_t)pl.rho.size() * 8 + (int64_t)spairs.size() * 16 + (int64_t)work.size() * 20 +
          (int64_t)ivals.size() * 8 + (17 * (int64_t)Kp + 16 * P2) * 4 + 2 * nc * P2 * (int64_t)sizeof(float2);
     if (t.bie) b += (int64_t)t.near_col.size() * 8 + t.npanel * 16;
@@ -388,16 +424,14 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   if ((rc = upload(pl.d_ops, hd.ops)) || (rc = upload(pl.d_rho, pl.rho)) ||
       (rc = upload(pl.d_m2l_pairs, hd.spairs)) || (rc = upload(pl.d_cops, hd.cops)) ||
       (rc = upload(pl.d_m2l_soff, hd.soff)) ||
-      (rc = pl.d_stage.alloc(std::max<size_t>(1, hd.spairs.size()) * (size_t)Kp * sizeof(float2))) ||
+      (rc = pl.d_stage.alloc((size_t)std::max<int64_t>(1, pl.max_seg_slots) * (size_t)Kp * sizeof(float2))) ||
       (rc = upload(pl.d_p2p_work, hd.work)) || (rc = upload(pl.d_p2p_ivals, hd.ivals)) ||
       (rc = upload(pl.d_p2p_total, hd.totals)))
     return rc;
   {
     std::vector<int32_t> in, out;
     m2l_reflection_codes(P, Kp, in, out);
-    std::vector<uint8_t> slot_g(std::max<size_t>(1, hd.spairs.size()), 0);
-    for (const int4& p : hd.spairs) slot_g[p.w] = (uint8_t)p.z;
-    if ((rc = upload(pl.d_bmap, in)) || (rc = upload(pl.d_omap, out)) || (rc = upload(pl.d_slot_g, slot_g)))
+    if ((rc = upload(pl.d_bmap, in)) || (rc = upload(pl.d_omap, out)) || (rc = upload(pl.d_slot_g, hd.slot_g)))
       return rc;
   }
   // coupling coefficients and tables
@@ -500,6 +534,7 @@ int hfmm_default_opts(hfmm_opts* o) {
   o->eta = 2.0;
   o->near_levels = 3;
   o->near_order = 6;
+  o->stage_mb = 32768;
   return HFMM_OK;
 }
 
@@ -514,6 +549,7 @@ static int apply_opts(Tree& t, const hfmm_opts* o) {
   if (o->near_levels < 0 || o->near_levels > 5 || o->near_order < 1 || o->near_order > 16)
     return set_error("near_levels in [0,5], near_order in [1,16]"), HFMM_EINVAL;
   t.ncrit = o->ncrit;
+  t.stage_bytes = (int64_t)(o->stage_mb > 0 ? o->stage_mb : 32768) << 20;
   t.max_level = o->max_level;
   t.theta = o->theta;
   t.kappa = o->kappa;

@@ -96,9 +96,35 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
     for (int c : pl.src_leaves) p2m.push_back(make_int2(i, c));
     for (int c : pl.tgt_leaves) l2p.push_back(make_int2(i, c));
     for (int w = 0; w < pl.n_p2p_work; ++w) p2p.push_back(make_int2(i, w));
-    for (const int4& c : pl.m2l_chunks_h) m2l.push_back(make_int4(i, c.x, c.y, c.z));
-    for (int c : pl.m2l_targets) red.push_back(make_int2(i, c));
   }
+  // M2L chunks and reduction items, segment by segment (several staging
+  // segments are allowed for a single instance only)
+  b.nseg = 1;
+  for (int i = 0; i < b.count; ++i) b.nseg = std::max(b.nseg, (int)plans[i]->m2l_segs.size());
+  if (b.nseg > 1 && b.count > 1) {
+    set_error("an instance whose M2L staging exceeds its budget cannot join a fused batch");
+    return HFMM_EINVAL;
+  }
+  b.m2l_seg_off.assign(b.nseg + 1, 0);
+  b.red_seg_off.assign(b.nseg + 1, 0);
+  b.seg_slot_base.assign(b.nseg, 0);
+  for (int sg = 0; sg < b.nseg; ++sg) {
+    b.m2l_seg_off[sg] = (int)m2l.size();
+    b.red_seg_off[sg] = (int)red.size();
+    for (int i = 0; i < b.count; ++i) {
+      const Plan& pl = *plans[i];
+      if (sg >= (int)pl.m2l_segs.size()) continue;
+      const M2LSeg& S = pl.m2l_segs[sg];
+      for (int c = S.chunk_b; c < S.chunk_e; ++c) {
+        const int4& ch = pl.m2l_chunks_h[c];
+        m2l.push_back(make_int4(i, ch.x, ch.y, ch.z));
+      }
+      for (int t = S.tgt_b; t < S.tgt_e; ++t) red.push_back(make_int2(i, pl.m2l_targets[t]));
+      if (b.count == 1) b.seg_slot_base[sg] = S.slot_b;
+    }
+  }
+  b.m2l_seg_off[b.nseg] = (int)m2l.size();
+  b.red_seg_off[b.nseg] = (int)red.size();
   // per-level M2M (parents, deepest first) and L2L (children, root first)
   // items: up to 16 destination cells of one instance, level (and, for L2L,
   // octant) per item
@@ -184,9 +210,16 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
     launch_m2m(b.d_m2m.as<int4>() + b.m2m_off[l], b.m2m_off[l + 1] - b.m2m_off[l], b.d_m2m_cols.as<int32_t>(), I,
                P, s);
   if ((rc = mark(2))) return rc;
-  launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, p0.d_bmap.as<int32_t>(), P, batch_variant(b, kPhaseM2L), s);
-  if ((rc = mark(3))) return rc;
-  launch_m2l_reduce(b.d_red.as<int2>(), b.n_red, I, p0.d_omap.as<int32_t>(), P, s);
+  // M2L and its reduction per staging segment (marks 3 and 4 split the two
+  // phases when there is one segment; with several, phase 3 holds both)
+  for (int sg = 0; sg < b.nseg; ++sg) {
+    launch_m2l(b.d_m2l.as<int4>() + b.m2l_seg_off[sg], b.m2l_seg_off[sg + 1] - b.m2l_seg_off[sg], I,
+               p0.d_bmap.as<int32_t>(), P, batch_variant(b, kPhaseM2L), s);
+    if (b.nseg == 1 && (rc = mark(3))) return rc;
+    launch_m2l_reduce(b.d_red.as<int2>() + b.red_seg_off[sg], b.red_seg_off[sg + 1] - b.red_seg_off[sg], I,
+                      p0.d_omap.as<int32_t>(), P, b.seg_slot_base[sg], s);
+  }
+  if (b.nseg > 1 && (rc = mark(3))) return rc;
   if ((rc = mark(4))) return rc;
   for (int l = 1; l < b.maxlev; ++l)
     launch_l2l(b.d_l2l.as<int4>() + b.l2l_off[l], b.l2l_off[l + 1] - b.l2l_off[l], b.d_l2l_cols.as<int32_t>(), I,
@@ -254,7 +287,7 @@ static int tune_batch(Batch& b, hipStream_t s) {
     for (int v = 0; v < nv; ++v) {
       hipError_t e = hipEventRecord(e0, s);
       if (e == hipSuccess) {
-        launch_m2l(b.d_m2l.as<int4>(), b.n_m2l, I, b.plans[0]->d_bmap.as<int32_t>(), b.P, v, s);
+        launch_m2l(b.d_m2l.as<int4>(), b.m2l_seg_off[1], I, b.plans[0]->d_bmap.as<int32_t>(), b.P, v, s);
         e = hipGetLastError();
       }
       if (e == hipSuccess) e = hipEventRecord(e1, s);

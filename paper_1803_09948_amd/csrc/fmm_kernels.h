@@ -21,6 +21,9 @@ void table_dims(int P, int* Kp, int* Rp);
 void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
                        const int32_t* cp_lm, const double2* cp_val, float2* tables,
                        hipStream_t s);
+// The same tables in FP64 (precision reference).
+void launch_gen_tables64(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
+                         const int32_t* cp_lm, const double2* cp_val, double2* tables, hipStream_t s);
 // Pointers of one problem instance, read by every instance-aware kernel.
 struct InstDev {
   const float4* spos;       // sorted sources (x, y, z, -)
@@ -76,7 +79,10 @@ int m2l_pairs_per_chunk(int P);
 // chunks: (instance, op, pair begin, pair end), sorted by (instance, op)
 // L[t] = sum of the staging slots of t, each mapped back by its reflection's
 // output codes omap [16][P^2] (items: instance, target cell)
-void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int32_t* omap, int P, hipStream_t s);
+// slot_base: first staging slot of the segment (the staging buffer holds
+// slots [slot_base, ...) of the targets in items)
+void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int32_t* omap, int P,
+                       int64_t slot_base, hipStream_t s);
 // per pair: reflected multipoles through the canonical operator into the pair's staging slot
 // variant < m2l_variant_count(P) selects the launch shape (results are identical)
 int m2l_variant_count(int P);

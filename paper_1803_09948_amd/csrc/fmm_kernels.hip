@@ -88,10 +88,14 @@ __device__ void bessel_j_all(int nm, double x, double* j) {
 // with H = S (M2L) or R (M2M, L2L) and coef = 4 pi i^{n'+l-n} Gaunt.
 // One block per operator; the harmonics of t are built in LDS in FP64.
 // ---------------------------------------------------------------------------
+__device__ inline void store_entry(float2* p, double re, double im) { *p = make_float2((float)re, (float)im); }
+__device__ inline void store_entry(double2* p, double re, double im) { *p = make_double2(re, im); }
+
+template <class C2>
 __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P, double k,
                              const int32_t* __restrict__ cp_off, const int32_t* __restrict__ cp_lm,
                              const double2* __restrict__ cp_val, int Kp, int Rp,
-                             float2* __restrict__ tables) {
+                             C2* __restrict__ tables) {
   const int o = blockIdx.x;
   if (o >= nops) return;
   const int L = 2 * P - 1;
@@ -156,11 +160,11 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
   }
   __syncthreads();
   const int P2 = P * P;
-  float2* T = tables + (size_t)o * Kp * Rp;
+  C2* T = tables + (size_t)o * Kp * Rp;
   for (int f = threadIdx.x; f < Kp * Rp; f += blockDim.x) {
     const int col = f / Rp, row = f % Rp;  // col (n,m) = input, row (n',m') = output
     if (col >= P2 || row >= P2) {
-      T[f] = make_float2(0.f, 0.f);
+      store_entry(T + f, 0.0, 0.0);
       continue;
     }
     const int e = row * P2 + col;
@@ -176,7 +180,7 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
     if (d.kind == 0) sc = sig_in[n] / sig_out[n2];        // M2M
     else if (d.kind == 1) sc = sig_out[n2] / sig_in[n];   // L2L
     else sc = sig_out[n2] * sig_in[n];                    // M2L
-    T[f] = make_float2((float)(re * sc), (float)(im * sc));
+    store_entry(T + f, re * sc, im * sc);
   }
 }
 
@@ -734,7 +738,8 @@ constexpr int kRedGroup = 512;
 
 __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ items,
                                                     const InstDev* __restrict__ insts,
-                                                    const int32_t* __restrict__ omap, int P2, int Kp) {
+                                                    const int32_t* __restrict__ omap, int P2, int Kp,
+                                                    int64_t slot_base) {
   extern __shared__ int red_lds[];
   int* som = red_lds;              // [16][P2] output codes
   int* sgo = red_lds + 16 * P2;    // [kRedGroup] reflection * P2 of each slot of the group
@@ -764,7 +769,7 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ ite
     for (int e = tid; e < ng; e += nth) sgo[e] = (int)I.slot_g[g0 + e] * P2;
     __syncthreads();
     if (c < P2) {
-      gcfloat2* S = (gcfloat2*)(I.stage + (size_t)g0 * Kp);
+      gcfloat2* S = (gcfloat2*)(I.stage + (size_t)(g0 - slot_base) * Kp);
       int q = 0;
       for (; q + 8 <= ng; q += 8, S += 8 * Kp) {  // eight loads in flight, added in slot order
         int e[8];
@@ -986,7 +991,14 @@ void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, const in
   if (nops <= 0) return;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  k_gen_tables<<<nops, 256, 0, s>>>(ops, nops, P, k, cp_off, cp_lm, cp_val, Kp, Rp, tables);
+  k_gen_tables<float2><<<nops, 256, 0, s>>>(ops, nops, P, k, cp_off, cp_lm, cp_val, Kp, Rp, tables);
+}
+void launch_gen_tables64(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
+                         const int32_t* cp_lm, const double2* cp_val, double2* tables, hipStream_t s) {
+  if (nops <= 0) return;
+  int Kp, Rp;
+  table_dims(P, &Kp, &Rp);
+  k_gen_tables<double2><<<nops, 256, 0, s>>>(ops, nops, P, k, cp_off, cp_lm, cp_val, Kp, Rp, tables);
 }
 int elem_chunk() { return kChunk; }
 void launch_set_xy(int count, int base, const XYPtrs& p, InstDev* insts, hipStream_t s) {
@@ -1042,12 +1054,13 @@ void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream
     default: break;
   }
 }
-void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int32_t* omap, int P, hipStream_t s) {
+void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int32_t* omap, int P,
+                       int64_t slot_base, hipStream_t s) {
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
   const int nth = 64 * ((P * P + 63) / 64);  // one thread per coefficient
   const size_t lds = (16 * (size_t)P * P + kRedGroup) * sizeof(int);
-  if (n > 0) k_m2l_reduce<<<n, nth, lds, s>>>(items, insts, omap, P * P, Kp);
+  if (n > 0) k_m2l_reduce<<<n, nth, lds, s>>>(items, insts, omap, P * P, Kp, slot_base);
 }
 void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s) {
   if (n > 0) k_p2p<<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);

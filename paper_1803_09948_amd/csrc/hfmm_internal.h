@@ -107,6 +107,15 @@ struct HostPlanData {
   std::vector<int4> spairs, work;
   std::vector<int2> ivals, cops;
   std::vector<int32_t> totals, soff;
+  std::vector<uint8_t> slot_g;    // reflection of the pair of each (global) staging slot
+};
+
+// A staging segment of the M2L: targets m2l_targets[tgt_b, tgt_e) own the
+// staging slots [slot_b, slot_e) (pair slots are stored relative to slot_b),
+// and their pairs form the chunks [chunk_b, chunk_e).
+struct M2LSeg {
+  int64_t slot_b = 0, slot_e = 0;
+  int tgt_b = 0, tgt_e = 0, chunk_b = 0, chunk_e = 0;
 };
 
 struct Plan {
@@ -141,11 +150,14 @@ struct Plan {
   DevBuf d_stage;                // float2 [n M2L pairs][Kp] staging, slots ordered by target
   DevBuf d_m2l_soff;             // int32 [ncell + 1]: first staging slot of each target cell
   std::vector<int32_t> m2l_targets;  // cells that receive M2L
+  std::vector<M2LSeg> m2l_segs;      // staging segments (one unless the staging budget is exceeded)
+  int64_t max_seg_slots = 0;
   // host work lists (cells / chunks of this instance)
   std::vector<int32_t> src_leaves, tgt_leaves;
   std::vector<std::vector<int32_t>> m2m_cells, l2l_cells;  // per level
   std::vector<int4> m2l_chunks_h;                          // (op, pair begin, pair end, 0)
   std::unique_ptr<struct Batch> self;                      // single-instance execution
+  std::unique_ptr<struct Plan64> fp64;                     // FP64 variant (allocated on first use)
   // BIE corrections (caller panel order; pattern in the Tree)
   DevBuf d_near_val;                            // float2 per near nonzero
   DevBuf d_diag;                                // double2: self integral - 3-point self sum
@@ -153,6 +165,16 @@ struct Plan {
   int64_t device_bytes = 0;
   int64_t est_bytes = 0;                 // footprint computed before any allocation
   std::unique_ptr<HostPlanData> hd;      // present between host and device preparation
+};
+
+// Device data of the FP64 variant of a plan's product.
+struct Plan64 {
+  DevBuf d_tables, d_M, d_L;               // double2
+  DevBuf d_src_leaves, d_tgt_leaves;       // int32
+  DevBuf d_m2m, d_l2l;                     // int32 cells, level by level
+  std::vector<int> m2m_off, l2l_off;       // per level offsets
+  DevBuf d_chunks;                         // int4 (op, pair begin, pair end, 0)
+  int n_chunks = 0;
 };
 
 // Fused execution of one or more instances (instance-aware kernels).
@@ -166,6 +188,9 @@ struct Batch {
   DevBuf d_m2m_cols, d_l2l_cols;      // M2M / L2L column entries (see launch_m2m / launch_l2l)
   int n_zero = 0, n_gather = 0, n_scatter = 0, n_p2m = 0, n_l2p = 0, n_p2p = 0, n_m2l = 0, n_red = 0;
   std::vector<int> m2m_off, l2l_off;  // per level offsets into d_m2m / d_l2l
+  int nseg = 1;                       // M2L staging segments
+  std::vector<int> m2l_seg_off, red_seg_off;  // per segment offsets into d_m2l / d_red
+  std::vector<int64_t> seg_slot_base;         // first staging slot of each segment
   hipStream_t stream = nullptr;       // private stream for graph capture / replay
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraph_t graph = nullptr;
@@ -191,6 +216,7 @@ struct Tree {
   HostTree h;                   // bodies and base cells
   int ncrit = 64, max_level = 20;
   double theta = 0.5, kappa = -1.0, eta = 2.0;
+  int64_t stage_bytes = int64_t(32) << 30;  // M2L staging budget
   int near_levels = 3, near_order = 6;
   // BIE data
   bool bie = false;
@@ -212,6 +238,7 @@ struct Tree {
   int gm_m = 0;
   DevBuf g_V, g_w, g_r, g_x64, g_y64, g_H, g_cs, g_sn, g_g, g_h, g_h2, g_part, g_dot, g_st, g_yv;
   DevBuf d_q, d_ys;             // float2 per source / target
+  DevBuf d_q64, d_ys64;         // double2 per source / target (FP64 variant)
   int64_t body_bytes = 0;
   std::map<std::pair<uint64_t, int>, std::unique_ptr<Plan>> plans;
   bool timing = false;

@@ -24,14 +24,14 @@ EXPORTS = [
     "hfmm_tree_free", "hfmm_last_error", "hfmm_version", "hfmm_prepare_host",
     "hfmm_server_create", "hfmm_server_submit", "hfmm_server_step", "hfmm_server_poll",
     "hfmm_server_release", "hfmm_server_used_bytes", "hfmm_server_free",
-    "hfmm_variant_count", "hfmm_set_variant", "hfmm_tree_variant",
+    "hfmm_variant_count", "hfmm_set_variant", "hfmm_tree_variant", "hfmm_matvec64", "hfmm_direct64",
 ]
 
 
 class Opts(C.Structure):
     _fields_ = [("ncrit", C.c_int32), ("max_level", C.c_int32), ("theta", C.c_double),
                 ("kappa", C.c_double), ("eta", C.c_double), ("near_levels", C.c_int32),
-                ("near_order", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("near_order", C.c_int32), ("stage_mb", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
 class Stats(C.Structure):
@@ -100,6 +100,8 @@ def lib():
             "hfmm_variant_count": [i32, i32],
             "hfmm_set_variant": [i32, i32],
             "hfmm_tree_variant": [vp, dbl, i32, i32, C.POINTER(i32)],
+            "hfmm_matvec64": [vp, dbl, i32, vp, vp, vp],
+            "hfmm_direct64": [vp, vp, i64, vp, i64, dbl, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -189,6 +191,16 @@ class Tree:
                                  C.c_void_p(y.data_ptr()), _stream(torch, stream)))
         return y
 
+    def matvec64(self, k: float, P: int, x, y=None, stream=None):
+        """FP64 variant of matvec (same tree, lists and P); x: complex128 CUDA tensor."""
+        import torch
+        assert x.dtype == torch.complex128 and x.is_cuda and x.is_contiguous() and x.numel() == self.n_in
+        if y is None:
+            y = torch.empty(self.n_out, dtype=torch.complex128, device=x.device)
+        _check(lib().hfmm_matvec64(self._h, float(k), int(P), C.c_void_p(x.data_ptr()),
+                                   C.c_void_p(y.data_ptr()), _stream(torch, stream)))
+        return y
+
     def gmres(self, k: float, P: int, b, x0=None, tol=1e-4, restart=30, maxit=2000, stream=None):
         import torch
         assert b.dtype == torch.complex128 and b.is_cuda and b.numel() == self.n_out
@@ -252,6 +264,20 @@ class Tree:
 
 
 PHASE_M2L = 0
+
+
+def direct64(src, q, tgt, k, stream=None):
+    """FP64 direct sum on the GPU: src, tgt float32 CUDA tensors [n][3], [m][3];
+    q complex128 CUDA tensor [n]; returns complex128 [m]."""
+    import torch
+    assert src.dtype == torch.float32 and tgt.dtype == torch.float32 and q.dtype == torch.complex128
+    assert src.is_cuda and tgt.is_cuda and q.is_cuda
+    src, tgt, q = src.contiguous(), tgt.contiguous(), q.contiguous()
+    y = torch.empty(tgt.shape[0], dtype=torch.complex128, device=tgt.device)
+    _check(lib().hfmm_direct64(C.c_void_p(src.data_ptr()), C.c_void_p(q.data_ptr()), int(src.shape[0]),
+                               C.c_void_p(tgt.data_ptr()), int(tgt.shape[0]), float(k),
+                               C.c_void_p(y.data_ptr()), _stream(torch, stream)))
+    return y
 
 
 def variant_count(P: int, phase: int = PHASE_M2L) -> int:

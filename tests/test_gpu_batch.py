@@ -57,3 +57,16 @@ def test_batch_argument_errors():
     xm = torch.ones(len(T), dtype=torch.complex64, device="cuda")
     with pytest.raises(hfmm.HfmmError):
         hfmm.batch_matvec([a, m], [1.0, 1.0], [8, 8], [xa, xm], [xa.clone(), xm.clone()])
+
+
+def test_batch_refuses_segmented_instances():
+    """An instance whose M2L staging is split into segments runs alone, not
+    inside a fused batch."""
+    a = hfmm.Tree.from_points(synth.sphere_points(20000, 5), stage_mb=1)
+    b = hfmm.Tree.from_points(synth.sphere_points(3000, 6))
+    xa = torch.ones(20000, dtype=torch.complex64, device="cuda")
+    xb = torch.ones(3000, dtype=torch.complex64, device="cuda")
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.batch_matvec([a, b], [12.0, 12.0], [8, 8], [xa, xb], [xa.clone(), xb.clone()])
+    ya = a.matvec(12.0, 8, xa)  # alone it runs
+    assert torch.isfinite(torch.view_as_real(ya)).all()

@@ -129,3 +129,14 @@ def test_m2l_launch_shapes_bit_identical(P):
     y = t2.matvec(k, P, q).cpu().numpy()
     assert 0 <= t2.variant(k, P) < nv
     np.testing.assert_array_equal(y, outs[0])
+
+
+def test_m2l_staging_segments_bit_identical():
+    """A staging budget far below the M2L's needs splits the M2L and its
+    reduction into many target segments; results are the same bits."""
+    n, k, P = 20000, 12.0, 8
+    x = synth.sphere_points(n, 33)
+    q = torch.from_numpy(synth.strengths(n, 33)).to("cuda")
+    y1 = hfmm.Tree.from_points(x).matvec(k, P, q).cpu().numpy()
+    y2 = hfmm.Tree.from_points(x, stage_mb=1).matvec(k, P, q).cpu().numpy()
+    np.testing.assert_array_equal(y1, y2)
