@@ -45,7 +45,7 @@ struct InstDev {
   float2* M;                // multipoles [ncell][P^2]
   float2* L;                // locals [ncell][P^2]
   const int4* m2l_pairs;    // (target, source, symmetry, staging slot)
-  float2* stage;            // M2L staging [n pairs][Kp] (canonical frame), slots ordered by target
+  float2* stage;            // M2L staging [slots][Rp] (canonical frame), slots ordered by target
   const uint8_t* slot_g;    // per staging slot: reflection of its pair
   const int32_t* m2l_soff;  // per cell: first staging slot (ncell + 1 entries)
   const int4* p2p_work;     // (tgt begin, tgt end, interval begin, interval end)

@@ -602,18 +602,20 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
     mma(a0);
   }
   // each pair owns a staging slot (slots are ordered by target) holding its
-  // result in the canonical frame; the reduction kernel below maps it back
-  // and adds a target's slots in a fixed order.  Lane (j, q) holds rows
-  // 4q..4q+3 of every 16-row tile of column j: two 16-byte stores each.
+  // result in the canonical frame, all Rp rows (a whole number of 128-byte
+  // lines); the reduction kernel below maps it back and adds a target's
+  // slots in a fixed order.  Lane (j, q) holds rows 4q..4q+3 of every
+  // 16-row tile of column j: two 16-byte stores, and the four lanes of a
+  // column write one full line per tile.
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
     if (gs[t] == 16) continue;
     const int slot = ld_int4(I.m2l_pairs + pb + 16 * t + li).w;
-    gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * Kp);
+    gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * Rp);
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
       const int row = 16 * r + 4 * lk;
-      if (row < Kp) {
+      {
         f4v lo, hi;
         lo.x = k1[t][r][0] - k3[t][r][0];
         lo.y = k1[t][r][0] + k2[t][r][0];
@@ -640,12 +642,17 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 // L2L (MODE 1): an entry is (child, parent), all of one octant operator op;
 // L[child] += T_op L[parent].  Same tiles and Gauss product as M2L.
 // ---------------------------------------------------------------------------
-template <int RT, int MODE>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT <= 12 ? 2 : 1)))
+// RW row tiles per wave: wave (item, b) computes output tiles
+// [b RW, min(RT, (b + 1) RW)), so the short operator chains of the coarse
+// levels run on several waves at once.
+template <int RT, int RW, int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RW <= 12 ? 2 : 1)))
 k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
           const InstDev* __restrict__ insts, int Kp, int Rp, int P2) {
   constexpr int STRIDE = MODE == 0 ? 9 : 2;
-  const int4 it = items[blockIdx.x];
+  constexpr int NB = (RT + RW - 1) / RW;
+  const int rb = blockIdx.x % NB, r0 = rb * RW;
+  const int4 it = items[blockIdx.x / NB];
   const InstDev& I = insts[it.x];
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
@@ -653,9 +660,9 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
   const int32_t* cj = cols + (size_t)(it.z + (ok ? li : 0)) * STRIDE;
   const int dst = cj[0];
   float2* X = MODE == 0 ? I.M : I.L;
-  floatx4 k1[RT], k2[RT], k3[RT];
+  floatx4 k1[RW], k2[RW], k3[RW];
 #pragma unroll
-  for (int r = 0; r < RT; ++r) {
+  for (int r = 0; r < RW; ++r) {
     k1[r] = floatx4{0.f, 0.f, 0.f, 0.f};
     k2[r] = floatx4{0.f, 0.f, 0.f, 0.f};
     k3[r] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -665,10 +672,10 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
     gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li;
     const bool zc = !ok || src < 0;
     gcfloat2* B = (gcfloat2*)(X + (size_t)(zc ? 0 : src) * P2);
-    float2 a0[RT], a1[RT], b0, b1;
-    auto load_a = [&](int k, float2* out) {
+    float2 a0[RW], a1[RW], b0, b1;
+    auto load_a = [&](int k, float2* out) {  // tiles past RT repeat the last one (unused)
 #pragma unroll
-      for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * r);
+      for (int r = 0; r < RW; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * min(r0 + r, RT - 1));
     };
     auto load_b = [&](int k) { return ld2(B + min(k, P2 - 1)); };
     auto mma = [&](const float2* a, float2 bv, int k) {
@@ -676,7 +683,7 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
       const float x = z ? 0.f : bv.x, y = z ? 0.f : bv.y;
       const float bu = x, bd = y - x, bs = x + y;
 #pragma unroll
-      for (int r = 0; r < RT; ++r) {
+      for (int r = 0; r < RW; ++r) {
         const float ar = a[r].x, ai = a[r].y, as = ar + ai;
         k1[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bu, k1[r], 0, 0, 0);
         k2[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bd, k2[r], 0, 0, 0);
@@ -712,11 +719,11 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
   if (!ok) return;
   float2* D = X + (size_t)dst * P2;
 #pragma unroll
-  for (int r = 0; r < RT; ++r)
+  for (int r = 0; r < RW; ++r)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = 16 * r + 4 * lk + v;
-      if (row < P2) {
+      const int row = 16 * (r0 + r) + 4 * lk + v;
+      if (r0 + r < RT && row < P2) {
         float2 val = make_float2(k1[r][v] - k3[r][v], k1[r][v] + k2[r][v]);
         if (MODE == 1) {
           const float2 old = D[row];
@@ -738,7 +745,7 @@ constexpr int kRedGroup = 512;
 
 __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ items,
                                                     const InstDev* __restrict__ insts,
-                                                    const int32_t* __restrict__ omap, int P2, int Kp,
+                                                    const int32_t* __restrict__ omap, int P2, int Sp,
                                                     int64_t slot_base) {
   extern __shared__ int red_lds[];
   int* som = red_lds;              // [16][P2] output codes
@@ -769,15 +776,15 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ ite
     for (int e = tid; e < ng; e += nth) sgo[e] = (int)I.slot_g[g0 + e] * P2;
     __syncthreads();
     if (c < P2) {
-      gcfloat2* S = (gcfloat2*)(I.stage + (size_t)(g0 - slot_base) * Kp);
+      gcfloat2* S = (gcfloat2*)(I.stage + (size_t)(g0 - slot_base) * Sp);
       int q = 0;
-      for (; q + 8 <= ng; q += 8, S += 8 * Kp) {  // eight loads in flight, added in slot order
+      for (; q + 8 <= ng; q += 8, S += 8 * Sp) {  // eight loads in flight, added in slot order
         int e[8];
         float2 v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) e[u] = som[sgo[q + u] + c];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = ld2_once(S + u * Kp + (e[u] & 0xffff));
+        for (int u = 0; u < 8; ++u) v[u] = ld2_once(S + u * Sp + (e[u] & 0xffff));
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const float2 w = apply_code(v[u].x, v[u].y, e[u]);
@@ -785,7 +792,7 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ ite
           si += w.y;
         }
       }
-      for (; q < ng; ++q, S += Kp) {
+      for (; q < ng; ++q, S += Sp) {
         const int e = som[sgo[q] + c];
         const float2 v = ld2_once(S + (e & 0xffff));
         const float2 w = apply_code(v.x, v.y, e);
@@ -1032,7 +1039,7 @@ static void launch_tr(const int4* items, int n, const int32_t* cols, const InstD
   table_dims(P, &Kp, &Rp);
   switch (Rp / 16) {
 #define X(R) \
-  case R: k_tr_mfma<R, MODE><<<n, 64, 0, s>>>(items, cols, insts, Kp, Rp, P * P); break;
+  case R: k_tr_mfma<R, 1, MODE><<<n * R, 64, 0, s>>>(items, cols, insts, Kp, Rp, P * P); break;
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 #undef X
     default: break;
@@ -1060,7 +1067,7 @@ void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int
   table_dims(P, &Kp, &Rp);
   const int nth = 64 * ((P * P + 63) / 64);  // one thread per coefficient
   const size_t lds = (16 * (size_t)P * P + kRedGroup) * sizeof(int);
-  if (n > 0) k_m2l_reduce<<<n, nth, lds, s>>>(items, insts, omap, P * P, Kp, slot_base);
+  if (n > 0) k_m2l_reduce<<<n, nth, lds, s>>>(items, insts, omap, P * P, Rp, slot_base);
 }
 void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s) {
   if (n > 0) k_p2p<<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
