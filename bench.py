@@ -16,7 +16,9 @@ Other workloads (`--workload`):
          [1, 30], P = 10, GMRES(30) to 1e-4): solves/s and p50/p99 latency of
          the continuous-batching server vs the one-at-a-time path;
   precision  FP32 product vs its FP64 variant (same tree, lists, P) vs the
-         FP64 direct sum on 1000 seeded targets, N = 2^20 and 2^23, P = 8/10/12.
+         FP64 direct sum on 1000 seeded targets, N = 2^20 and 2^23, P = 8/10/12;
+  bie    sound-soft sphere solve (icosphere s=5, k = 2 pi and 6, GMRES(30) to
+         1e-4) and the singularity ablation.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
 one GPU.
@@ -191,6 +193,49 @@ def bench_serve(a):
     print(json.dumps(out))
 
 
+def bench_bie(a):
+    """Sound-soft sphere, icosphere subdivision 5 (20480 flat panels), plane
+    wave along z, P = 10, GMRES(30) to 1e-4 with FP64 Arnoldi: k = 2 pi (an
+    interior resonance) and k = 6; then the singularity ablation at k = 6
+    (self + near corrections / self only / neither)."""
+    import torch
+
+    import synth
+    from paper_1803_09948_amd import hfmm
+
+    V, T = synth.icosphere(5)
+    rows = []
+    for k, mode in ((2 * math.pi, 0), (6.0, 0), (6.0, 1), (6.0, 2)):
+        t = hfmm.Tree.from_mesh(V, T, bie_treatment=mode)
+        t0 = time.perf_counter()
+        t.prepare(k, 10)
+        torch.cuda.synchronize()
+        t_prep = time.perf_counter() - t0
+        b = t.plane_wave(k)
+        t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=400)  # warm (tuning, workspace)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=400)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        row = {"k": k, "treatment": ["self+near", "self", "none"][mode], "iters": info["iters"],
+               "converged": info["converged"], "resid_true": info["resid_true"], "solve_ms": dt * 1e3,
+               "ms_per_iter": dt * 1e3 / max(1, info["iters"]), "setup_s": t_prep}
+        rows.append(row)
+        log(json.dumps(row))
+        t.free()
+    out = {
+        "metric": "BIE solve time to 1e-4 (icosphere s=5, 20480 panels, k=2 pi, P=10, GMRES(30))",
+        "value": rows[0]["solve_ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": rows[0]["solve_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 matvec + f64 Arnoldi", "data": "synthetic",
+        "config": {"workload": "sound-soft unit sphere, icosphere subdivision 5 (20480 flat triangles), "
+                               "plane wave along z, P=10, ncrit=64, GMRES(30) to 1e-4"},
+        "results": rows,
+    }
+    print(json.dumps(out))
+
+
 def bench_precision(a):
     """FP32 product vs its FP64 variant (same tree, lists and P) vs the FP64
     direct sum on 1000 seeded sampled targets, N in a.prec_n, P in 8/10/12,
@@ -260,7 +305,8 @@ def bench_precision(a):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "precision", "copy"], default="matvec")
+    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "precision", "bie", "copy"],
+                    default="matvec")
     ap.add_argument("--prec-n", default="1048576,8388608", help="sizes of the precision workload")
     ap.add_argument("--prec-P", default="8,10,12", help="orders of the precision workload")
     ap.add_argument("--copy-mib", type=int, default=1024)
@@ -290,6 +336,8 @@ def main():
         return bench_copy(a)
     if a.workload == "precision":
         return bench_precision(a)
+    if a.workload == "bie":
+        return bench_bie(a)
 
     import torch
 

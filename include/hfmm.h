@@ -60,7 +60,10 @@ typedef struct {
   int32_t near_order;  /* BIE near integrals: n x n collapsed Gauss rule (default 6) */
   int32_t stage_mb;    /* M2L staging budget in MiB (default 32768; <= 0: default): larger
                           problems run the M2L in segments of targets whose staging fits */
-  int32_t reserved[7];
+  int32_t bie_treatment; /* BIE singular-integral treatment: 0 self + near corrections
+                            (default), 1 self-panel integral only, 2 none (the 3-point rule
+                            everywhere, the listing without its near branch) */
+  int32_t reserved[6];
 } hfmm_opts;
 
 typedef struct {

@@ -548,8 +548,10 @@ static int apply_opts(Tree& t, const hfmm_opts* o) {
   if (!(o->eta > 0.0)) return set_error("eta must be > 0"), HFMM_EINVAL;
   if (o->near_levels < 0 || o->near_levels > 5 || o->near_order < 1 || o->near_order > 16)
     return set_error("near_levels in [0,5], near_order in [1,16]"), HFMM_EINVAL;
+  if (o->bie_treatment < 0 || o->bie_treatment > 2) return set_error("bie_treatment in [0, 2]"), HFMM_EINVAL;
   t.ncrit = o->ncrit;
   t.stage_bytes = (int64_t)(o->stage_mb > 0 ? o->stage_mb : 32768) << 20;
+  t.bie_treatment = o->bie_treatment;
   t.max_level = o->max_level;
   t.theta = o->theta;
   t.kappa = o->kappa;

@@ -125,10 +125,17 @@ int prepare_bie(Tree& t, Plan& pl, hipStream_t s) {
   if ((rc = pl.d_near_val.alloc(std::max<size_t>(1, t.near_col.size()) * sizeof(float2))) ||
       (rc = pl.d_diag.alloc((size_t)n * sizeof(double2))))
     return rc;
-  launch_near(pl.n_near, t.d_near_row.as<int32_t>(), t.d_near_col.as<int32_t>(), t.d_panels.as<double>(),
-              pl.k, t.near_levels, gl, gl + ng, ng, pl.d_near_val.as<float2>(), s);
-  launch_self(n, t.d_panels.as<double>(), pl.k, gl + 2 * ng, gl + 2 * ng + kSelfOrder, kSelfOrder,
-              pl.d_diag.as<double2>(), s);
+  // corrections of the chosen treatment (the ablation modes leave zeros)
+  if (t.bie_treatment == 0)
+    launch_near(pl.n_near, t.d_near_row.as<int32_t>(), t.d_near_col.as<int32_t>(), t.d_panels.as<double>(),
+                pl.k, t.near_levels, gl, gl + ng, ng, pl.d_near_val.as<float2>(), s);
+  else
+    HIP_TRY(hipMemsetAsync(pl.d_near_val.p, 0, pl.d_near_val.bytes, s));
+  if (t.bie_treatment <= 1)
+    launch_self(n, t.d_panels.as<double>(), pl.k, gl + 2 * ng, gl + 2 * ng + kSelfOrder, kSelfOrder,
+                pl.d_diag.as<double2>(), s);
+  else
+    HIP_TRY(hipMemsetAsync(pl.d_diag.p, 0, pl.d_diag.bytes, s));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   return HFMM_OK;
@@ -289,7 +296,8 @@ int hfmm_build_bie(const double* verts, int64_t nv, const int32_t* tris, int64_t
     hfmm_default_opts(&d);
     const hfmm_opts* o = opts ? opts : &d;
     if (o->ncrit < 1 || !(o->theta > 0) || !(o->eta > 0) || o->max_level < 0 || o->max_level > kMaxLevel ||
-        o->near_levels < 0 || o->near_levels > 5 || o->near_order < 1 || o->near_order > 16)
+        o->near_levels < 0 || o->near_levels > 5 || o->near_order < 1 || o->near_order > 16 ||
+        o->bie_treatment < 0 || o->bie_treatment > 2)
       return set_error("invalid options"), HFMM_EINVAL;
     auto t = std::make_unique<Tree>();
     t->ncrit = o->ncrit;
@@ -299,6 +307,8 @@ int hfmm_build_bie(const double* verts, int64_t nv, const int32_t* tris, int64_t
     t->eta = o->eta;
     t->near_levels = o->near_levels;
     t->near_order = o->near_order;
+    t->stage_bytes = (int64_t)(o->stage_mb > 0 ? o->stage_mb : 32768) << 20;
+    t->bie_treatment = o->bie_treatment;
     t->bie = true;
     t->npanel = nt;
     t->verts.assign(verts, verts + 3 * nv);

@@ -217,6 +217,7 @@ struct Tree {
   int ncrit = 64, max_level = 20;
   double theta = 0.5, kappa = -1.0, eta = 2.0;
   int64_t stage_bytes = int64_t(32) << 30;  // M2L staging budget
+  int bie_treatment = 0;        // 0: self + near corrections, 1: self only, 2: none
   int near_levels = 3, near_order = 6;
   // BIE data
   bool bie = false;
