@@ -39,7 +39,7 @@ def test_tree_equals_oracle(n, ncrit, seed, axes):
     assert st["centre"] == list(o.c) and st["half"] == o.H
 
 
-@pytest.mark.parametrize("n,k,P,theta", [(4096, 1.0, 8, 0.5), (6000, 16 * math.pi, 10, 0.5),
+@pytest.mark.parametrize("n,k,P,theta", [(4096, 1.0, 8, 0.5), (2000, 16 * math.pi, 10, 0.5),
                                          (2500, 7.3, 6, 0.7)])
 def test_lists_equal_oracle(n, k, P, theta):
     x = synth.sphere_points(n, 7)
