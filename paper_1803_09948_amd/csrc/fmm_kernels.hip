@@ -416,13 +416,11 @@ __global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items, cons
 // M2L on the matrix cores.  One wave takes up to 16*NCT pairs that share one
 // canonical operator T (P^2 x P^2 complex).  The B matrix (k = input
 // coefficient, column = pair) holds M' = D^T M, gathered straight from the
-// multipoles with the pair's reflection applied arithmetically; T streams
-// from memory as the A matrix (row = output coefficient).  The complex
-// product is four real 16x16x4 FP32 MFMAs per tile and k-step:
-//   Cr += Tr Br - Ti Bi,   Ci += Tr Bi + Ti Br,
-// with A and B prefetched one k-step ahead.  Each pair's result is mapped
-// back (conj(D) C) and written from the accumulators to the pair's staging
-// slot; no LDS is used, so many waves fit on a CU.  Tables are [op][k < Kp]
+// multipoles through the pair's reflection codes; T streams from memory as
+// the A matrix (row = output coefficient), with A and B prefetched one
+// k-step ahead.  Each pair's result goes, in the canonical frame, to the
+// pair's staging slot (the reduction maps it back); the only LDS is the
+// reflection code table and a 4 KiB output tile.  Tables are [op][k < Kp]
 // [r < Rp] with zero padding.  Blocks are mapped so that each XCD walks a
 // contiguous range of chunks (sorted by operator), keeping an operator's
 // table in that XCD's L2 while its chunks run.
@@ -605,30 +603,50 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
   // result in the canonical frame, all Rp rows (a whole number of 128-byte
   // lines); the reduction kernel below maps it back and adds a target's
   // slots in a fixed order.  Lane (j, q) holds rows 4q..4q+3 of every
-  // 16-row tile of column j: two 16-byte stores, and the four lanes of a
-  // column write one full line per tile.
+  // 16-row tile of column j; tile by tile the results pass through 4 KiB of
+  // LDS ([column][16 rows]) so that every store instruction writes whole
+  // 128-byte lines (8 lanes x 16 bytes per column).
+  __shared__ f4v sout[16 * NCT * 8];
+  int slots[NCT];
 #pragma unroll
-  for (int t = 0; t < NCT; ++t) {
-    if (gs[t] == 16) continue;
-    const int slot = ld_int4(I.m2l_pairs + pb + 16 * t + li).w;
-    gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * Rp);
+  for (int t = 0; t < NCT; ++t) slots[t] = (gs[t] == 16) ? -1 : ld_int4(I.m2l_pairs + pb + 16 * t + li).w;
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-      const int row = 16 * r + 4 * lk;
-      {
-        f4v lo, hi;
-        lo.x = k1[t][r][0] - k3[t][r][0];
-        lo.y = k1[t][r][0] + k2[t][r][0];
-        lo.z = k1[t][r][1] - k3[t][r][1];
-        lo.w = k1[t][r][1] + k2[t][r][1];
-        hi.x = k1[t][r][2] - k3[t][r][2];
-        hi.y = k1[t][r][2] + k2[t][r][2];
-        hi.z = k1[t][r][3] - k3[t][r][3];
-        hi.w = k1[t][r][3] + k2[t][r][3];
-        __builtin_nontemporal_store(lo, &St[row / 2]);  // written once, read once by the reduction
-        __builtin_nontemporal_store(hi, &St[row / 2 + 1]);
+  for (int r = 0; r < RT; ++r) {
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) {
+      f4v lo, hi;
+      lo.x = k1[t][r][0] - k3[t][r][0];
+      lo.y = k1[t][r][0] + k2[t][r][0];
+      lo.z = k1[t][r][1] - k3[t][r][1];
+      lo.w = k1[t][r][1] + k2[t][r][1];
+      hi.x = k1[t][r][2] - k3[t][r][2];
+      hi.y = k1[t][r][2] + k2[t][r][2];
+      hi.z = k1[t][r][3] - k3[t][r][3];
+      hi.w = k1[t][r][3] + k2[t][r][3];
+      const int col = 16 * t + li;
+      sout[col * 8 + 2 * lk] = lo;      // rows 4 lk, 4 lk + 1 of the tile
+      sout[col * 8 + 2 * lk + 1] = hi;  // rows 4 lk + 2, 4 lk + 3
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int u = 0; u < 2 * NCT; ++u) {  // 16 NCT columns x 8 pieces over 64 lanes
+      const int e = 64 * u + lane, col = e >> 3, piece = e & 7;
+      int slot = -1;
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) {
+        const int sv = __shfl(slots[t], col & 15);
+        if ((col >> 4) == t) slot = sv;
+      }
+      if (slot >= 0) {
+        gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * Rp + 16 * r);
+        __builtin_nontemporal_store(sout[col * 8 + piece], &St[piece]);  // written once, read once
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
