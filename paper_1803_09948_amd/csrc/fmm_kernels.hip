@@ -660,17 +660,19 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 // L2L (MODE 1): an entry is (child, parent), all of one octant operator op;
 // L[child] += T_op L[parent].  Same tiles and Gauss product as M2L.
 // ---------------------------------------------------------------------------
-// RW row tiles per wave: wave (item, b) computes output tiles
-// [b RW, min(RT, (b + 1) RW)), so the short operator chains of the coarse
-// levels run on several waves at once.
-template <int RT, int RW, int MODE>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RW <= 12 ? 2 : 1)))
+// One row tile per wave: wave (item, b) computes output tile b, so the
+// short operator chains of the coarse levels run on many waves at once.
+// Each operator's A and B loads are issued in groups of 16 k-steps with all
+// loads of a group in flight, so a wave waits about once per group instead
+// of once per k-step.
+template <int RT, int KS, int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT >= 10 ? 1 : 2)))
 k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
           const InstDev* __restrict__ insts, int Kp, int Rp, int P2) {
   constexpr int STRIDE = MODE == 0 ? 9 : 2;
-  constexpr int NB = (RT + RW - 1) / RW;
-  const int rb = blockIdx.x % NB, r0 = rb * RW;
-  const int4 it = items[blockIdx.x / NB];
+  constexpr int G = KS < 16 ? KS : 16;
+  const int r0 = blockIdx.x % RT;
+  const int4 it = items[blockIdx.x / RT];
   const InstDev& I = insts[it.x];
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
@@ -678,53 +680,33 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
   const int32_t* cj = cols + (size_t)(it.z + (ok ? li : 0)) * STRIDE;
   const int dst = cj[0];
   float2* X = MODE == 0 ? I.M : I.L;
-  floatx4 k1[RW], k2[RW], k3[RW];
-#pragma unroll
-  for (int r = 0; r < RW; ++r) {
-    k1[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-    k2[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-    k3[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-  }
-  const int KS = Kp >> 2;
+  floatx4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = k1, k3 = k1;
   auto run = [&](int op, int src) {  // acc += T_op X[src] (src < 0: zero column)
-    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li;
+    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li + 16 * r0;
     const bool zc = !ok || src < 0;
     gcfloat2* B = (gcfloat2*)(X + (size_t)(zc ? 0 : src) * P2);
-    float2 a0[RW], a1[RW], b0, b1;
-    auto load_a = [&](int k, float2* out) {  // tiles past RT repeat the last one (unused)
+    for (int g0 = 0; g0 < KS; g0 += G) {
+      float2 a[G], bv[G];
 #pragma unroll
-      for (int r = 0; r < RW; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * min(r0 + r, RT - 1));
-    };
-    auto load_b = [&](int k) { return ld2(B + min(k, P2 - 1)); };
-    auto mma = [&](const float2* a, float2 bv, int k) {
-      const bool z = zc || k >= P2;
-      const float x = z ? 0.f : bv.x, y = z ? 0.f : bv.y;
-      const float bu = x, bd = y - x, bs = x + y;
-#pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        const float ar = a[r].x, ai = a[r].y, as = ar + ai;
-        k1[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bu, k1[r], 0, 0, 0);
-        k2[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bd, k2[r], 0, 0, 0);
-        k3[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bs, k3[r], 0, 0, 0);
+      for (int u = 0; u < G; ++u) {  // steps past KS repeat the last one (unused)
+        const int k = 4 * min(g0 + u, KS - 1) + lk;
+        a[u] = ld2(T + (size_t)k * Rp);
+        bv[u] = ld2(B + min(k, P2 - 1));
       }
-    };
-    load_a(lk, a0);
-    b0 = load_b(lk);
-    int ks = 0;
-    for (; ks + 2 <= KS; ks += 2) {
-      const int ka = 4 * (ks + 1) + lk, kb = min(4 * (ks + 2), Kp - 4) + lk;
-      load_a(ka, a1);
-      b1 = load_b(ka);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a0, b0, 4 * ks + lk);
-      __builtin_amdgcn_sched_barrier(0);
-      load_a(kb, a0);
-      b0 = load_b(kb);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a1, b1, ka);
-      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_sched_barrier(0);  // the whole group's loads go out first
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        if (g0 + u < KS) {
+          const int k = 4 * (g0 + u) + lk;
+          const bool z = zc || k >= P2;
+          const float x = z ? 0.f : bv[u].x, y = z ? 0.f : bv[u].y;
+          const float ar = a[u].x, ai = a[u].y;
+          k1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar + ai, x, k1, 0, 0, 0);
+          k2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, y - x, k2, 0, 0, 0);
+          k3 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, x + y, k3, 0, 0, 0);
+        }
+      }
     }
-    if (ks < KS) mma(a0, b0, 4 * ks + lk);
   };
   if constexpr (MODE == 0) {
     for (int o = 0; o < 8; ++o) {
@@ -737,20 +719,18 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
   if (!ok) return;
   float2* D = X + (size_t)dst * P2;
 #pragma unroll
-  for (int r = 0; r < RW; ++r)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 16 * (r0 + r) + 4 * lk + v;
-      if (r0 + r < RT && row < P2) {
-        float2 val = make_float2(k1[r][v] - k3[r][v], k1[r][v] + k2[r][v]);
-        if (MODE == 1) {
-          const float2 old = D[row];
-          val.x += old.x;
-          val.y += old.y;
-        }
-        D[row] = val;
+  for (int v = 0; v < 4; ++v) {
+    const int row = 16 * r0 + 4 * lk + v;
+    if (row < P2) {
+      float2 val = make_float2(k1[v] - k3[v], k1[v] + k2[v]);
+      if (MODE == 1) {
+        const float2 old = D[row];
+        val.x += old.x;
+        val.y += old.y;
       }
+      D[row] = val;
     }
+  }
 }
 
 // L[t] = sum of t's staging slots in slot order (deterministic), each slot's
@@ -1055,9 +1035,13 @@ static void launch_tr(const int4* items, int n, const int32_t* cols, const InstD
   if (n <= 0) return;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  switch (Rp / 16) {
-#define X(R) \
-  case R: k_tr_mfma<R, 1, MODE><<<n * R, 64, 0, s>>>(items, cols, insts, Kp, Rp, P * P); break;
+  switch (P) {
+#define X(p)                                                                                      \
+  case p: {                                                                                       \
+    constexpr int RT = (p * p + 15) / 16, KS = (p * p + 3) / 4;                                   \
+    k_tr_mfma<RT, KS, MODE><<<n * RT, 64, 0, s>>>(items, cols, insts, Kp, Rp, p * p);             \
+    break;                                                                                        \
+  }
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 #undef X
     default: break;
