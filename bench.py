@@ -54,13 +54,13 @@ def cpu_baseline(x, q, k, P, ncrit, stats, budget_s=15.0):
     n = len(x)
     t0 = time.perf_counter()
     # P2P: direct sum over a sample of targets against all sources
-    nt = 64
+    nt = 192
     ti = rng.choice(n, nt, replace=False)
     ta = time.perf_counter()
     direct_sum(k, x[ti], x, q, chunk=8)
     p2p_rate = nt * n / (time.perf_counter() - ta)                 # pairs / s
     # M2L: operator construction + apply for a sample of well-separated pairs
-    nm = 40
+    nm = 160
     M = (rng.normal(size=P * P) + 1j * rng.normal(size=P * P))
     ta = time.perf_counter()
     for i in range(nm):
@@ -69,7 +69,7 @@ def cpu_baseline(x, q, k, P, ncrit, stats, budget_s=15.0):
     m2l_per_pair = (time.perf_counter() - ta) / nm
     # P2M / L2P per body, M2M / L2L per cell
     ta = time.perf_counter()
-    nb = 4096
+    nb = 16384
     ex.p2m(P, k, np.zeros(3), x[:nb] * 0.01, q[:nb])
     p2m_per_body = (time.perf_counter() - ta) / nb
     ta = time.perf_counter()
