@@ -18,10 +18,12 @@ Other workloads (`--workload`):
   precision  FP32 product vs its FP64 variant (same tree, lists, P) vs the
          FP64 direct sum on 1000 seeded targets, N = 2^20 and 2^23, P = 8/10/12;
   bie    sound-soft sphere solve (icosphere s=5, k = 2 pi and 6, GMRES(30) to
-         1e-4) and the singularity ablation.
+         1e-4) and the singularity ablation;
+  scaling  matvec time against N = 2^16 ... 2^23 (k = 16 pi, P = 10), and the
+         error at 1M points with and without the wavenumber rule (kappa).
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
-one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the library runs on
+one GPU (no multi-GPU path).
 """
 from __future__ import annotations
 
@@ -303,12 +305,88 @@ def bench_precision(a):
     print(json.dumps(out))
 
 
+def bench_scaling(a):
+    """Matvec time against N (2^16 ... 2^23 points on the unit sphere, k = 16 pi,
+    P = 10): the O(N) check.  Then, at 1M points, the error against the FP64
+    direct sum (1000 seeded targets) with and without the wavenumber rule of
+    the MAC and the split (kappa = 0.4 P vs off)."""
+    import torch
+
+    import synth
+    from paper_1803_09948_amd import hfmm
+
+    k, P = 16.0 * math.pi, a.P
+    rows = []
+    for n in [int(v) for v in a.scale_n.split(",")]:
+        x = synth.sphere_points(n, 23)
+        qd = torch.from_numpy(synth.strengths(n, 23)).to("cuda")
+        t0 = time.perf_counter()
+        tree = hfmm.Tree.from_points(x, ncrit=a.ncrit)
+        tree.prepare(k, P)
+        torch.cuda.synchronize()
+        t_prep = time.perf_counter() - t0
+        yd = tree.matvec(k, P, qd)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            tree.matvec(k, P, qd, yd)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        st = tree.stats(k, P)
+        row = {"n": n, "ms": round(ms, 4), "ns_per_point": round(ms * 1e6 / n, 3), "setup_s": round(t_prep, 2),
+               "n_m2l": st["n_m2l"], "p2p_body_pairs": st["p2p_body_pairs"], "n_cell": st["n_cell"]}
+        rows.append(row)
+        log(json.dumps(row))
+        tree.free()
+        del qd, yd
+        torch.cuda.empty_cache()
+    # wavenumber rule on / off at 1M points
+    n = 1 << 20
+    x = synth.sphere_points(n, 23)
+    q32 = torch.from_numpy(synth.strengths(n, 23)).to("cuda")
+    xd = torch.from_numpy(x).to("cuda")
+    idx = torch.from_numpy(np.sort(np.random.default_rng(5).choice(n, 1000, replace=False))).to("cuda")
+    ref = hfmm.direct64(xd, q32.to(torch.complex128), xd[idx], k)
+    kappa_rows = []
+    for label, kappa in (("kappa=0.4P", -1.0), ("kappa off", 1e30)):
+        tree = hfmm.Tree.from_points(x, ncrit=a.ncrit, kappa=kappa)
+        tree.prepare(k, P)
+        yd = tree.matvec(k, P, q32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            tree.matvec(k, P, q32, yd)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 3 * 1e3
+        s = yd[idx].to(torch.complex128)
+        err = float(torch.linalg.vector_norm(s - ref) / torch.linalg.vector_norm(ref))
+        st = tree.stats(k, P)
+        row = {"rule": label, "ms": round(ms, 4), "err_vs_direct": err, "n_m2l": st["n_m2l"],
+               "p2p_body_pairs": st["p2p_body_pairs"]}
+        kappa_rows.append(row)
+        log(json.dumps(row))
+        tree.free()
+    big = rows[-1]
+    out = {
+        "metric": "FMM matvec time per point vs N (O(N) check)",
+        "value": big["ns_per_point"], "unit": "ns/point", "n_gpus": 1, "steps": 5, "warmup": 1,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"N in {a.scale_n} uniform on the unit sphere, k=16 pi, P={P}, ncrit={a.ncrit}, "
+                               "theta=0.5; kappa on/off at N=1048576"},
+        "results": rows, "kappa": kappa_rows,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "precision", "bie", "copy"],
+    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "precision", "bie", "copy", "scaling"],
                     default="matvec")
     ap.add_argument("--prec-n", default="1048576,8388608", help="sizes of the precision workload")
     ap.add_argument("--prec-P", default="8,10,12", help="orders of the precision workload")
+    ap.add_argument("--scale-n", default=",".join(str(1 << e) for e in range(16, 24)),
+                    help="sizes of the scaling workload")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--count", type=int, default=64, help="instances (batch workload)")
     ap.add_argument("--nreq", type=int, default=24, help="requests (serve workload)")
@@ -325,7 +403,7 @@ def main():
     ap.add_argument("--check", action="store_true", help="compare 200 sampled outputs with the FP64 direct sum")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+        print("bench.py: the library runs on one GPU only (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     if a.workload == "batch":
@@ -338,6 +416,8 @@ def main():
         return bench_precision(a)
     if a.workload == "bie":
         return bench_bie(a)
+    if a.workload == "scaling":
+        return bench_scaling(a)
 
     import torch
 

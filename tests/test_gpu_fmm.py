@@ -49,6 +49,35 @@ def test_matvec_vs_oracle_fmm(n, k, P, ncrit, seed):
     assert e <= 1e-5
 
 
+@pytest.mark.parametrize("P", [3, 5, 6, 7, 9])
+def test_orders_vs_oracle_fmm(P):
+    """Orders whose P^2 leaves 1, 4 or 9 rows past a multiple of 16 (the last
+    16-row tile of the matrix-core M2L is partly padding), against the
+    oracle FMM."""
+    n, k = 1500, 4.0
+    x = synth.sphere_points(n, 40 + P)
+    q = synth.strengths(n, 40 + P)
+    y, t = _gpu_matvec(x, q, k, P, ncrit=32)
+    assert t.stats(k, P)["n_m2l"] > 0
+    e = rel(y, FMM(x, k=k, P=P, ncrit=32).matvec(q))
+    print(f"P={P} gpu vs oracle FMM {e:.3e}")
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("P", [11, 13, 14, 15])
+def test_high_orders_vs_direct_sum(P):
+    """High orders (remainder rows 9, 9, 4, 1): the truncation error is far
+    below FP32 rounding, so the direct sum is the reference."""
+    n, k = 1500, 3.0
+    x = synth.sphere_points(n, 50 + P)
+    q = synth.strengths(n, 50 + P)
+    y, t = _gpu_matvec(x, q, k, P, ncrit=32)
+    assert t.stats(k, P)["n_m2l"] > 0
+    e = rel(y, direct_sum(k, x, x, q))
+    print(f"P={P} vs direct {e:.3e}")
+    assert e <= 1e-5
+
+
 def test_largest_P_vs_direct_sum():
     """P = 16 (the largest order): truncation error is far below FP32 rounding."""
     n, k = 1500, 3.0
