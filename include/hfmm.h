@@ -242,8 +242,9 @@ int hfmm_set_timing(hfmm_tree* tree, int32_t on);
 int hfmm_phase_times(const hfmm_tree* tree, float* ms10);
 
 /* Launch-shape autotuning of the fused matvec.  Phase 0 is the M2L
- * matrix-core kernel.  Its shapes (pairs per wave, waves per SIMD) compute
- * bit-identical results; by default the first product of each fused
+ * matrix-core kernel.  Its shapes (pairs per wave, waves per SIMD, chunks
+ * per wave) compute bit-identical results; by default the first product of
+ * each fused
  * sequence (a tree's plain matvec, a batch, a server composition) times
  * every shape on its own work, outside any graph capture, and keeps the
  * fastest, cached per (phase, P, log2 of the work size).

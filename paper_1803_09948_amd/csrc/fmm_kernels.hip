@@ -476,20 +476,15 @@ __device__ inline float2 mul_ipow_sel(float2 a, int code) {
 //   K1 += (Tr + Ti) Br,  K2 += Tr (Bi - Br),  K3 += Ti (Br + Bi),
 //   C = (K1 - K3) + i (K1 + K2).
 // WPE is the number of waves per SIMD the register budget is sized for.
-template <int RT, int NCT, int WPE>
+template <int P, int NCT, int WPE, int CPW, int AD>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
-           const InstDev* __restrict__ insts, const int32_t* __restrict__ bmap, int Kp, int Rp, int P2) {
+           const InstDev* __restrict__ insts, const int32_t* __restrict__ bmap, int Rp) {
+  constexpr int P2 = P * P, RT = (P2 + 15) / 16, KS = (P2 + 3) / 4, Kp = 4 * KS;
   extern __shared__ int smap[];     // [17][Kp] input codes (see m2l_input_codes)
   const int b = blockIdx.x;
-  const int item = (b & 7) * per_xcd + (b >> 3);
-  if (item >= nitems) return;
-  const int ci = item / sub;
-  const int4 ch = chunks[ci];       // (instance, op, pair begin, pair end)
-  const InstDev& I = insts[ch.x];
-  const int op = ch.y, pb = ch.z + 16 * NCT * (item - ci * sub);
-  const int np = min(ch.w - pb, 16 * NCT);
-  if (np <= 0) return;
+  const int w = (b & 7) * per_xcd + (b >> 3);
+  if (w * CPW >= nitems) return;
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
   {  // copy the code table: all loads in flight before the LDS writes (indices
@@ -506,147 +501,167 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
       for (int u = 0; u < U; ++u) dst[min(base + lane + 64 * u, n4 - 1)] = v[u];
     }
   }
-  // column t of this lane is pair 16 t + li: (target, source, reflection,
-  // slot); a column past the item's end reads the all-zero code row 16
-  gcfloat2* Ms[NCT];
-  int gs[NCT], goff[NCT];
-#pragma unroll
-  for (int t = 0; t < NCT; ++t) {
-    const int p = 16 * t + li;
-    const bool ok = p < np;
-    const int4 pr = ld_int4(I.m2l_pairs + pb + (ok ? p : 0));
-    Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
-    gs[t] = ok ? pr.z : 16;
-    goff[t] = gs[t] * Kp + lk;
-  }
   __syncthreads();
-  // B gather: B[k] = i^ph M[c] from the column's code; the loads issue now,
-  // phase and zeroing apply when the step runs
-  auto load_b = [&](int k4, float2* raw, int* code) {
+  // the wave runs CPW consecutive items (one operator's table stays hot in
+  // L2 and one item's result stores drain while the next item computes)
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int item = w * CPW + c;
+    if (item >= nitems) break;
+    const int ci = item / sub;
+    const int4 ch = chunks[ci];       // (instance, op, pair begin, pair end)
+    const InstDev& I = insts[ch.x];
+    const int op = ch.y, pb = ch.z + 16 * NCT * (item - ci * sub);
+    const int np = min(ch.w - pb, 16 * NCT);
+    if (np <= 0) continue;
+    // column t of this lane is pair 16 t + li: (target, source, reflection,
+    // slot); a column past the item's end reads the all-zero code row 16
+    gcfloat2* Ms[NCT];
+    int gs[NCT], goff[NCT];
 #pragma unroll
     for (int t = 0; t < NCT; ++t) {
-      const int e = smap[goff[t] + k4];
-      raw[t] = ld2(Ms[t] + (e & 0xffff));
-      code[t] = e;
+      const int p = 16 * t + li;
+      const bool ok = p < np;
+      const int4 pr = ld_int4(I.m2l_pairs + pb + (ok ? p : 0));
+      Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
+      gs[t] = ok ? pr.z : 16;
+      goff[t] = gs[t] * Kp + lk;
     }
-  };
-  // the three B operands of the Gauss product
-  float bu[NCT], bd[NCT], bs[NCT];
-  auto finish_b = [&](const float2* raw, const int* code) {
-#pragma unroll
-    for (int t = 0; t < NCT; ++t) {
-      const int e = code[t];
-      const bool zero = e & (1 << 17);
-      const float2 v = apply_code(raw[t].x, raw[t].y, e);
-      const float x = zero ? 0.f : v.x, y = zero ? 0.f : v.y;
-      bu[t] = x;
-      bd[t] = y - x;
-      bs[t] = x + y;
-    }
-  };
-  floatx4 k1[NCT][RT], k2[NCT][RT], k3[NCT][RT];
-#pragma unroll
-  for (int t = 0; t < NCT; ++t)
-#pragma unroll
-    for (int r = 0; r < RT; ++r) {
-      k1[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-      k2[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-      k3[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-  gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li;
-  const int KS = Kp >> 2;
-  // two register buffers, alternating k-steps; the loads of one step are in
-  // flight while the other step's MFMAs run (a straight-line loop body keeps
-  // the compiler's wait counts exact)
-  float2 a0[RT], a1[RT], b0[NCT], b1[NCT];
-  int c0[NCT], c1[NCT];
-  auto load_a = [&](int k, float2* out) {
-#pragma unroll
-    for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * r);
-  };
-  auto mma = [&](const float2* a) {
-#pragma unroll
-    for (int r = 0; r < RT; ++r) {
-      const float ar = a[r].x, ai = a[r].y, as = ar + ai;
-#pragma unroll
-      for (int t = 0; t < NCT; ++t) k1[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bu[t], k1[t][r], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < NCT; ++t) k2[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bd[t], k2[t][r], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < NCT; ++t) k3[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bs[t], k3[t][r], 0, 0, 0);
-    }
-  };
-  const int klast = Kp - 4;  // clamp: redundant in-bounds loads past the end are unused
-  load_a(lk, a0);
-  load_b(0, b0, c0);
-  int ks = 0;
-  for (; ks + 2 <= KS; ks += 2) {
-    const int ka = 4 * (ks + 1), kb = min(4 * (ks + 2), klast);
-    load_a(ka + lk, a1);
-    load_b(ka, b1, c1);
-    __builtin_amdgcn_sched_barrier(0);  // issue the next step's loads before these MFMAs
-    finish_b(b0, c0);
-    mma(a0);
-    __builtin_amdgcn_sched_barrier(0);
-    load_a(kb + lk, a0);
-    load_b(kb, b0, c0);
-    __builtin_amdgcn_sched_barrier(0);
-    finish_b(b1, c1);
-    mma(a1);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  if (ks < KS) {
-    finish_b(b0, c0);
-    mma(a0);
-  }
-  // each pair owns a staging slot (slots are ordered by target) holding its
-  // result in the canonical frame, all Rp rows (a whole number of 128-byte
-  // lines); the reduction kernel below maps it back and adds a target's
-  // slots in a fixed order.  Lane (j, q) holds rows 4q..4q+3 of every
-  // 16-row tile of column j; tile by tile the results pass through 4 KiB of
-  // LDS ([column][16 rows]) so that every store instruction writes whole
-  // 128-byte lines (8 lanes x 16 bytes per column).
-  __shared__ f4v sout[16 * NCT * 8];
-  int slots[NCT];
-#pragma unroll
-  for (int t = 0; t < NCT; ++t) slots[t] = (gs[t] == 16) ? -1 : ld_int4(I.m2l_pairs + pb + 16 * t + li).w;
-#pragma unroll
-  for (int r = 0; r < RT; ++r) {
-#pragma unroll
-    for (int t = 0; t < NCT; ++t) {
-      f4v lo, hi;
-      lo.x = k1[t][r][0] - k3[t][r][0];
-      lo.y = k1[t][r][0] + k2[t][r][0];
-      lo.z = k1[t][r][1] - k3[t][r][1];
-      lo.w = k1[t][r][1] + k2[t][r][1];
-      hi.x = k1[t][r][2] - k3[t][r][2];
-      hi.y = k1[t][r][2] + k2[t][r][2];
-      hi.z = k1[t][r][3] - k3[t][r][3];
-      hi.w = k1[t][r][3] + k2[t][r][3];
-      const int col = 16 * t + li;
-      sout[col * 8 + 2 * lk] = lo;      // rows 4 lk, 4 lk + 1 of the tile
-      sout[col * 8 + 2 * lk + 1] = hi;  // rows 4 lk + 2, 4 lk + 3
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int u = 0; u < 2 * NCT; ++u) {  // 16 NCT columns x 8 pieces over 64 lanes
-      const int e = 64 * u + lane, col = e >> 3, piece = e & 7;
-      int slot = -1;
+    // B gather: B[k] = i^ph M[c] from the column's code; the loads issue now,
+    // phase and zeroing apply when the step runs
+    auto load_b = [&](int k4, float2* raw, int* code) {
 #pragma unroll
       for (int t = 0; t < NCT; ++t) {
-        const int sv = __shfl(slots[t], col & 15);
-        if ((col >> 4) == t) slot = sv;
+        const int e = smap[goff[t] + k4];
+        raw[t] = ld2(Ms[t] + (e & 0xffff));
+        code[t] = e;
       }
-      if (slot >= 0) {
-        gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * Rp + 16 * r);
-        __builtin_nontemporal_store(sout[col * 8 + piece], &St[piece]);  // written once, read once
+    };
+    // the three B operands of the Gauss product
+    float bu[NCT], bd[NCT], bs[NCT];
+    auto finish_b = [&](const float2* raw, const int* code) {
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) {
+        const int e = code[t];
+        const bool zero = e & (1 << 17);
+        const float2 v = apply_code(raw[t].x, raw[t].y, e);
+        const float x = zero ? 0.f : v.x, y = zero ? 0.f : v.y;
+        bu[t] = x;
+        bd[t] = y - x;
+        bs[t] = x + y;
+      }
+    };
+    floatx4 k1[NCT][RT], k2[NCT][RT], k3[NCT][RT];
+#pragma unroll
+    for (int t = 0; t < NCT; ++t)
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        k1[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+        k2[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+        k3[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+      }
+    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li;
+    // the table operand (A) is loaded AD k-steps ahead (2 AD register
+    // buffers), the gathered multipoles (B) one step ahead; a straight-line
+    // loop body of four steps keeps the compiler's wait counts exact
+    constexpr int AM = 2 * AD - 1;
+    float2 av[2 * AD][RT], bv[2][NCT];
+    int cv[2][NCT];
+    auto load_a = [&](int k, float2* out) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * r);
+    };
+    auto mma = [&](const float2* a) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        const float ar = a[r].x, ai = a[r].y, as = ar + ai;
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) k1[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bu[t], k1[t][r], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) k2[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bd[t], k2[t][r], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) k3[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bs[t], k3[t][r], 0, 0, 0);
+      }
+    };
+    // step s: issue A(s + AD) and B(s + 1), then the MFMAs of step s; the
+    // loop runs whole groups of four steps and clamps k (redundant in-bounds
+    // loads past the end are unused), the last KS mod 4 steps follow
+    constexpr int klast = Kp - 4;
+#pragma unroll
+    for (int d = 0; d < AD; ++d)
+      if (d < KS) load_a(4 * d + lk, av[d]);
+    load_b(0, bv[0], cv[0]);
+    int ks = 0;
+    for (; ks + 4 <= KS; ks += 4) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        load_a(min(4 * (ks + j + AD), klast) + lk, av[(j + AD) & AM]);
+        load_b(min(4 * (ks + j + 1), klast), bv[(j + 1) & 1], cv[(j + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);  // loads issue before this step's MFMAs
+        finish_b(bv[j & 1], cv[j & 1]);
+        mma(av[j & AM]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int j = 0; j < KS % 4; ++j) {
+      const int st = (KS / 4) * 4 + j;
+      if (st + AD < KS) load_a(4 * (st + AD) + lk, av[(j + AD) & AM]);
+      if (st + 1 < KS) load_b(4 * (st + 1), bv[(j + 1) & 1], cv[(j + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+      finish_b(bv[j & 1], cv[j & 1]);
+      mma(av[j & AM]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // each pair owns a staging slot (slots are ordered by target) holding its
+    // result in the canonical frame, all Rp rows (a whole number of 128-byte
+    // lines); the reduction kernel below maps it back and adds a target's
+    // slots in a fixed order.  Lane (j, q) holds rows 4q..4q+3 of every
+    // 16-row tile of column j; tile by tile the results pass through 4 KiB of
+    // LDS ([column][16 rows]) so that every store instruction writes whole
+    // 128-byte lines (8 lanes x 16 bytes per column).
+    __shared__ f4v sout[16 * NCT * 8];
+    int slots[NCT];
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) slots[t] = (gs[t] == 16) ? -1 : ld_int4(I.m2l_pairs + pb + 16 * t + li).w;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) {
+        f4v lo, hi;
+        lo.x = k1[t][r][0] - k3[t][r][0];
+        lo.y = k1[t][r][0] + k2[t][r][0];
+        lo.z = k1[t][r][1] - k3[t][r][1];
+        lo.w = k1[t][r][1] + k2[t][r][1];
+        hi.x = k1[t][r][2] - k3[t][r][2];
+        hi.y = k1[t][r][2] + k2[t][r][2];
+        hi.z = k1[t][r][3] - k3[t][r][3];
+        hi.w = k1[t][r][3] + k2[t][r][3];
+        const int col = 16 * t + li;
+        sout[col * 8 + 2 * lk] = lo;      // rows 4 lk, 4 lk + 1 of the tile
+        sout[col * 8 + 2 * lk + 1] = hi;  // rows 4 lk + 2, 4 lk + 3
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int u = 0; u < 2 * NCT; ++u) {  // 16 NCT columns x 8 pieces over 64 lanes
+        const int e = 64 * u + lane, col = e >> 3, piece = e & 7;
+        int slot = -1;
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+          const int sv = __shfl(slots[t], col & 15);
+          if ((col >> 4) == t) slot = sv;
+        }
+        if (slot >= 0) {
+          gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * Rp + 16 * r);
+          __builtin_nontemporal_store(sout[col * 8 + piece], &St[piece]);  // written once, read once
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
   }
 }
 
@@ -1075,13 +1090,14 @@ void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s) {
   if (n > 0) k_p2p<<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
 }
 
-template <int RT, int NCT, int WPE>
+template <int P, int NCT, int WPE, int CPW, int AD>
 static void launch_m2l_t(const int4* chunks, int nchunks, int sub, const InstDev* insts, const int32_t* bmap,
-                         int Kp, int Rp, int P2, hipStream_t s) {
+                         int Kp, int Rp, hipStream_t s) {
   const int nitems = nchunks * sub;
-  const int per = (nitems + 7) / 8;
-  k_m2l_mfma<RT, NCT, WPE><<<8 * per, 64, 17 * Kp * sizeof(int), s>>>(chunks, nitems, per, sub, insts, bmap,
-                                                                      Kp, Rp, P2);
+  const int nwaves = (nitems + CPW - 1) / CPW;
+  const int per = (nwaves + 7) / 8;
+  k_m2l_mfma<P, NCT, WPE, CPW, AD><<<8 * per, 64, 17 * Kp * sizeof(int), s>>>(chunks, nitems, per, sub, insts,
+                                                                              bmap, Rp);
 }
 
 // Chunks hold 32 pairs while two 16-pair column tiles of three accumulator
@@ -1092,41 +1108,54 @@ int m2l_pairs_per_chunk(int P) {
   return Rp / 16 <= 7 ? 32 : 16;
 }
 
-// Launch shapes: 0 = one wave per chunk (two column tiles when the chunk
-// holds 32 pairs); 1 = one wave per 16-pair column tile (32-pair chunks
-// only), with a smaller register budget and more waves per SIMD.
-int m2l_variant_count(int P) { return m2l_pairs_per_chunk(P) == 32 ? 2 : 1; }
+// Launch shapes (all give the same bits).  With 32-pair chunks:
+//   0: one wave per chunk (two column tiles), tables two k-steps ahead;
+//   1: one wave per 16-pair column tile (smaller register budget, more
+//      waves per SIMD), tables one step ahead;
+//   2, 3: shape 0 with each wave running 2 or 4 consecutive chunks, tables
+//      one step ahead (the register budget of two prefetch steps leaves no
+//      room for the second chunk's state).
+// With 16-pair chunks: one wave per chunk running 1, 2 or 4 chunks.
+int m2l_variant_count(int P) { return m2l_pairs_per_chunk(P) == 32 ? 4 : 3; }
 
 // waves per SIMD of the one-tile shape: accumulators and A buffers take
 // about 16 RT registers
 constexpr int m2l_narrow_wpe(int RT) { return RT <= 3 ? 4 : RT <= 7 ? 3 : RT <= 12 ? 2 : 1; }
 
-template <int RT>
-static void launch_m2l_r(bool wide, int sub, const int4* chunks, int nchunks, const InstDev* insts,
-                         const int32_t* bmap, int Kp, int Rp, int P2, hipStream_t s) {
+template <int P>
+static void launch_m2l_p(int variant, int sub, const int4* chunks, int nchunks, const InstDev* insts,
+                         const int32_t* bmap, int Kp, int Rp, hipStream_t s) {
+  constexpr int RT = (P * P + 15) / 16, NW = m2l_narrow_wpe(RT);
   if constexpr (RT <= 7) {
-    if (wide) return launch_m2l_t<RT, 2, 2>(chunks, nchunks, 1, insts, bmap, Kp, Rp, P2, s);
+    if (sub == 2) {
+      switch (variant) {
+        case 1: return launch_m2l_t<P, 1, NW, 1, 1>(chunks, nchunks, 2, insts, bmap, Kp, Rp, s);
+        case 2: return launch_m2l_t<P, 2, 2, 2, 1>(chunks, nchunks, 1, insts, bmap, Kp, Rp, s);
+        case 3: return launch_m2l_t<P, 2, 2, 4, 1>(chunks, nchunks, 1, insts, bmap, Kp, Rp, s);
+        default: return launch_m2l_t<P, 2, 2, 1, 2>(chunks, nchunks, 1, insts, bmap, Kp, Rp, s);
+      }
+    }
   }
-  launch_m2l_t<RT, 1, m2l_narrow_wpe(RT)>(chunks, nchunks, sub, insts, bmap, Kp, Rp, P2, s);
+  switch (variant) {
+    case 1: return launch_m2l_t<P, 1, NW, 2, 1>(chunks, nchunks, sub, insts, bmap, Kp, Rp, s);
+    case 2: return launch_m2l_t<P, 1, NW, 4, 1>(chunks, nchunks, sub, insts, bmap, Kp, Rp, s);
+    default: return launch_m2l_t<P, 1, NW, 1, 1>(chunks, nchunks, sub, insts, bmap, Kp, Rp, s);
+  }
 }
 
 void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, const int32_t* bmap, int P, int variant,
                 hipStream_t s) {
   if (nchunks <= 0) return;
-  const int P2 = P * P;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
   const int sub = m2l_pairs_per_chunk(P) / 16;
-  const bool wide = sub == 2 && variant == 0;
-#define M2L_CASE(R) \
-  case R: launch_m2l_r<R>(wide, sub, chunks, nchunks, insts, bmap, Kp, Rp, P2, s); break;
-  switch (Rp / 16) {
-    M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6) M2L_CASE(7) M2L_CASE(8)
-    M2L_CASE(9) M2L_CASE(10) M2L_CASE(11) M2L_CASE(12) M2L_CASE(13) M2L_CASE(14) M2L_CASE(15)
-    M2L_CASE(16)
+  switch (P) {
+#define X(p) \
+  case p: launch_m2l_p<p>(variant, sub, chunks, nchunks, insts, bmap, Kp, Rp, s); break;
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#undef X
     default: break;
   }
-#undef M2L_CASE
 }
 
 }  // namespace hfmm
