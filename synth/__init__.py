@@ -101,6 +101,27 @@ def icosphere(subdiv: int, radius: float = 1.0):
     return V, f.astype(np.int32)
 
 
+def curved_icosphere(subdiv: int, radius: float = 1.0):
+    """Six-node (quadratic) triangles on the sphere: the icosphere of
+    `icosphere(subdiv)` plus one node per edge at the edge midpoint projected
+    onto the sphere.  Returns (nodes float64 (nn,3), tri6 int32 (nt,6)) with
+    each row (v0, v1, v2, m01, m12, m20), outward counter-clockwise."""
+    V, T = icosphere(subdiv, radius)
+    nodes = [tuple(x) for x in V]
+    cache: dict = {}
+
+    def mid(i: int, j: int) -> int:
+        key = (i, j) if i < j else (j, i)
+        if key not in cache:
+            a = V[i] + V[j]
+            nodes.append(tuple(a / np.linalg.norm(a) * radius))
+            cache[key] = len(nodes) - 1
+        return cache[key]
+
+    tri6 = np.array([[a, b, c, mid(a, b), mid(b, c), mid(c, a)] for (a, b, c) in T.tolist()], dtype=np.int32)
+    return np.asarray(nodes, dtype=np.float64), tri6
+
+
 # --------------------------------------------------------------------------
 # Workloads (sizes and parameters; the recipe is restated in DESIGN.md)
 # --------------------------------------------------------------------------
