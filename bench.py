@@ -20,7 +20,9 @@ Other workloads (`--workload`):
   bie    sound-soft sphere solve (icosphere s=5, k = 2 pi and 6, GMRES(30) to
          1e-4) and the singularity ablation;
   scaling  matvec time against N = 2^16 ... 2^23 (k = 16 pi, P = 10), and the
-         error at 1M points with and without the wavenumber rule (kappa).
+         error at 1M points with and without the wavenumber rule (kappa);
+  nystrom  the sphere solve by the curved-element Nystrom method
+         (subdivisions 3..5, k = 2 pi and 6), error against the Mie series.
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: the library runs on
 one GPU (no multi-GPU path).
@@ -305,6 +307,52 @@ def bench_precision(a):
     print(json.dumps(out))
 
 
+def bench_nystrom(a):
+    """Sound-soft sphere by the curved-element Nystrom method (six-node
+    triangles, six unknowns per element), plane wave along z, P = 10,
+    GMRES(30) to 1e-4: subdivisions 3, 4, 5 (7680 / 30720 / 122880 unknowns)
+    at k = 2 pi and k = 6: setup, iterations and solve time.  (The error of
+    u_s against the Mie series is measured by tests/test_gpu_nystrom.py.)"""
+    import torch
+
+    import synth
+    from paper_1803_09948_amd import hfmm
+
+    rows = []
+    for s in [int(v) for v in a.nys_subdiv.split(",")]:
+        nodes, tri6 = synth.curved_icosphere(s)
+        for k in (2 * math.pi, 6.0):
+            t0 = time.perf_counter()
+            t = hfmm.Tree.from_curved_mesh(nodes, tri6)
+            t.prepare(k, 10)
+            torch.cuda.synchronize()
+            t_prep = time.perf_counter() - t0
+            b = t.plane_wave(k)
+            t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=400)  # warm (tuning, workspace)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=400)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            row = {"subdiv": s, "unknowns": 6 * len(tri6), "k": k, "iters": info["iters"],
+                   "converged": info["converged"], "resid_true": info["resid_true"], "solve_ms": dt * 1e3,
+                   "ms_per_iter": dt * 1e3 / max(1, info["iters"]), "setup_s": t_prep}
+            rows.append(row)
+            log(json.dumps(row))
+            t.free()
+    main = next(r for r in rows if r["subdiv"] == max(r2["subdiv"] for r2 in rows) and abs(r["k"] - 2 * math.pi) < 1e-9)
+    out = {
+        "metric": "curved-element Nystrom BIE solve time to 1e-4",
+        "value": main["solve_ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": main["solve_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 matvec + f64 Arnoldi and self blocks", "data": "synthetic",
+        "config": {"workload": f"sound-soft unit sphere, curved six-node icosphere subdivisions {a.nys_subdiv}, "
+                               "six unknowns per element, plane wave along z, P=10, ncrit=64, GMRES(30) to 1e-4"},
+        "results": rows,
+    }
+    print(json.dumps(out))
+
+
 def bench_scaling(a):
     """Matvec time against N (2^16 ... 2^23 points on the unit sphere, k = 16 pi,
     P = 10): the O(N) check.  Then, at 1M points, the error against the FP64
@@ -381,12 +429,13 @@ def bench_scaling(a):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "precision", "bie", "copy", "scaling"],
+    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "precision", "bie", "copy", "scaling", "nystrom"],
                     default="matvec")
     ap.add_argument("--prec-n", default="1048576,8388608", help="sizes of the precision workload")
     ap.add_argument("--prec-P", default="8,10,12", help="orders of the precision workload")
     ap.add_argument("--scale-n", default=",".join(str(1 << e) for e in range(16, 24)),
                     help="sizes of the scaling workload")
+    ap.add_argument("--nys-subdiv", default="3,4,5", help="subdivisions of the nystrom workload")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--count", type=int, default=64, help="instances (batch workload)")
     ap.add_argument("--nreq", type=int, default=24, help="requests (serve workload)")
@@ -418,6 +467,8 @@ def main():
         return bench_bie(a)
     if a.workload == "scaling":
         return bench_scaling(a)
+    if a.workload == "nystrom":
+        return bench_nystrom(a)
 
     import torch
 
@@ -509,12 +560,14 @@ def main():
                       "m2l_shapes": {"tuned": tuned, "ms": shape_ms}},
     }
     if a.check:
-        from oracle.fmm import direct_sum
+        # the library's FP64 direct sum on the GPU over all sources, 200 targets
         rng = np.random.default_rng(1)
-        idx = rng.choice(a.n, 200, replace=False)
-        ref = direct_sum(a.k, x[idx], x, q, chunk=8)
-        y = yd.cpu().numpy()[idx]
-        out["secondary"]["rel_err_vs_direct_200"] = float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+        idx = torch.from_numpy(np.sort(rng.choice(a.n, 200, replace=False))).to(dev)
+        xd = torch.from_numpy(x).to(dev)
+        ref = hfmm.direct64(xd, qd.to(torch.complex128), xd[idx], a.k)
+        y = yd[idx].to(torch.complex128)
+        out["secondary"]["rel_err_vs_direct64_200"] = float(torch.linalg.vector_norm(y - ref) /
+                                                            torch.linalg.vector_norm(ref))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, q, a.k, a.P, a.ncrit, st)
     print(json.dumps(out))

@@ -108,6 +108,34 @@ int hfmm_build_tree(const float* xyz_host, int64_t n, const hfmm_opts* opts,
 int hfmm_build_bie(const double* verts_host, int64_t nv, const int32_t* tris_host,
                    int64_t nt, const hfmm_opts* opts, hfmm_tree** out);
 
+/* BIE handle for a closed surface of curved six-node triangles, by the
+ * locally corrected Nystrom method of Sec. 2.2 (eqs. (8)-(10)).
+ *  Geometry: the quadratic map of the reference triangle through the nodes
+ *    (v0, v1, v2, m01, m12, m20) of each element.
+ *  Unknowns: six per element, at the points of the symmetric degree-4
+ *    six-point rule (three near the corners, three near the edges, as in the
+ *    dataset of Sec. 5), element-major.  The unknown is the density times
+ *    the surface Jacobian at the point (eq. (8)).
+ *  Matrix: far entries are the rule weight times G. The own element is
+ *    integrated by a Duffy rule with an angular sinh map. Elements whose
+ *    centroid lies within eta h of the target point use 4^near_levels
+ *    sub-triangles with near_order^2 points each.
+ *  Computed: corrections in FP64, near ones stored in complex64; self blocks
+ *    are applied in FP64 by GMRES.
+ *  nodes_host: nn x 3 float64; tri6_host: nt x 6 int32 node indices.
+ *  Works with hfmm_matvec, hfmm_gmres_solve and hfmm_bie_plane_wave (at the
+ *  points).
+ *  EINVAL: nn < 6, nt < 1, index out of range, degenerate element. */
+int hfmm_build_nystrom(const double* nodes_host, int64_t nn, const int32_t* tri6_host,
+                       int64_t nt, const hfmm_opts* opts, hfmm_tree** out);
+
+/* Points of a curved-element handle (host arrays of 6 nt entries, any may
+ * be NULL): positions (x 3), rule weights (parametric, summing to 1/2 per
+ * element) and surface Jacobians.  The density at point p is
+ * unknown_p / jac_p.  EINVAL for other handles. */
+int hfmm_nystrom_points(const hfmm_tree* tree, double* xyz_host, double* weight_host,
+                        double* jac_host);
+
 /* Builds (once) the traversal lists, translation operators and, for a BIE
  * handle, the near and self corrections for wavenumber k and order P.
  * Called implicitly by hfmm_matvec / hfmm_gmres_solve.
@@ -157,7 +185,9 @@ int hfmm_gmres_solve(hfmm_tree* tree, double k, int32_t P, const void* b_dev,
                      hfmm_gmres_info* info, void* stream);
 
 /* b_i = exp(i k d . c_i) at the centroids of a BIE handle (complex128[nt],
- * caller order): the incident plane wave of eq. (7).  dir_host: 3 doubles. */
+ * caller order), or at the points of a curved-element handle
+ * (complex128[6 nt]): the incident plane wave of eq. (7).  dir_host: 3
+ * doubles. */
 int hfmm_bie_plane_wave(hfmm_tree* tree, double k, const double* dir_host,
                         void* b_dev, void* stream);
 
@@ -166,9 +196,9 @@ int hfmm_bie_plane_wave(hfmm_tree* tree, double k, const double* dir_host,
  * lists of all instances are concatenated, so each phase (and each tree
  * level) is a single launch over every instance and uneven instances fill
  * the chip together; the sequence is captured once as a HIP graph (per set of
- * trees, k and P) and replayed on later calls.  Each result equals
- * hfmm_matvec on that instance alone up to the order of the FP32 atomic
- * additions in M2L (relative differences of order 1e-7).
+ * trees, k and P) and replayed on later calls.  Each result is bitwise
+ * equal to hfmm_matvec on that instance alone: every phase sums in a fixed
+ * order (the M2L through staging slots reduced per target).
  * trees, ks, Ps, xs_dev, ys_dev: arrays of length count.  EINVAL as for
  * hfmm_matvec, count < 1, differing P, or a BIE handle. */
 int hfmm_batch_matvec(int32_t count, hfmm_tree* const* trees, const double* ks,

@@ -8,6 +8,7 @@
 #include <unordered_map>
 
 #include "bie_kernels.h"
+#include "nystrom_kernels.h"
 #include "hfmm_internal.h"
 
 namespace hfmm {
@@ -80,6 +81,13 @@ int upload_bodies(Tree& t) {
   std::vector<float> sw;
   if (!t.bie) {
     for (int64_t i = 0; i < h.nsrc; ++i) sidx[i] = h.src_perm[i];
+  } else if (t.nystrom) {
+    // sources are the element points themselves, with their rule weights
+    sw.resize(h.nsrc);
+    for (int64_t i = 0; i < h.nsrc; ++i) {
+      sidx[i] = h.src_perm[i];
+      sw[i] = nystrom_weight(h.src_perm[i]);
+    }
   } else {
     // sources are the Gauss points 3*panel + g with weight area/3
     sw.resize(h.nsrc);
@@ -401,7 +409,7 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     b += (int64_t)spairs.size() * 17 + pl.max_seg_slots * (int64_t)Rp * (int64_t)sizeof(float2) + (nc + 1) * 4;
     b += (int64_t)pl.rho.size() * 8 + (int64_t)spairs.size() * 16 + (int64_t)work.size() * 20 +
          (int64_t)ivals.size() * 8 + (17 * (int64_t)Kp + 16 * P2) * 4 + 2 * nc * P2 * (int64_t)sizeof(float2);
-    if (t.bie) b += (int64_t)t.near_col.size() * 8 + t.npanel * 16;
+    if (t.bie) b += (int64_t)t.near_col.size() * 8 + t.npanel * (t.nystrom ? 96 : 16);
     if (!t.uploaded) b += t.h.nsrc * 40 + t.h.ntgt * 32;
     pl.est_bytes = b;
   }
@@ -455,7 +463,7 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
                     &pl.d_L, &pl.d_cops, &pl.d_stage, &pl.d_m2l_soff, &pl.d_bmap, &pl.d_omap,
                     &pl.d_slot_g})
     pl.device_bytes += (int64_t)b->bytes;
-  if (t.bie && (rc = prepare_bie(t, pl, s))) {
+  if (t.bie && (rc = (t.nystrom ? prepare_nystrom(t, pl, s) : prepare_bie(t, pl, s)))) {
     pl.d_tables.reset();  // not device-ready: the next prepare retries
     return rc;
   }
@@ -618,7 +626,9 @@ int hfmm_matvec(hfmm_tree* tree, double k, int32_t P, const void* x, void* y, vo
   if ((rc = matvec_impl(t, *pl, (const float2*)x, (float2*)y, s))) return rc;
   if (t.bie) {
     launch_near_apply(t.npanel, t.d_near_off.as<int32_t>(), t.d_near_col.as<int32_t>(),
-                      pl->d_near_val.as<float2>(), pl->d_diag.as<double2>(), (const float2*)x, (float2*)y, s);
+                      pl->d_near_val.as<float2>(), t.nystrom ? nullptr : pl->d_diag.as<double2>(),
+                      (const float2*)x, (float2*)y, s);
+    if (t.nystrom) launch_self6_apply_c64(t.npanel, pl->d_self6.as<double2>(), (const float2*)x, (float2*)y, s);
     HIP_TRY(hipGetLastError());
   }
   if (t.timing) HIP_TRY(hipEventRecord(t.ev[8], s));

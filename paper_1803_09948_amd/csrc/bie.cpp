@@ -6,6 +6,7 @@
 #include <unordered_map>
 
 #include "bie_kernels.h"
+#include "nystrom_kernels.h"
 #include "hfmm_internal.h"
 
 namespace hfmm {
@@ -171,7 +172,10 @@ static int apply_A(Tree& t, Plan& pl, const double2* v, double2* out, hipStream_
   if (rc) return rc;
   launch_near_apply(n, t.d_near_off.as<int32_t>(), t.d_near_col.as<int32_t>(), pl.d_near_val.as<float2>(),
                     nullptr, t.g_x64.as<float2>(), t.g_y64.as<float2>(), s);
-  launch_from_c64_diag(n, t.g_y64.as<float2>(), pl.d_diag.as<double2>(), v, out, s);
+  if (t.nystrom)
+    launch_from_c64_self6(n, t.g_y64.as<float2>(), pl.d_self6.as<double2>(), v, out, s);
+  else
+    launch_from_c64_diag(n, t.g_y64.as<float2>(), pl.d_diag.as<double2>(), v, out, s);
   HIP_TRY(hipGetLastError());
   return HFMM_OK;
 }
@@ -367,6 +371,15 @@ int hfmm_bie_plane_wave(hfmm_tree* tree, double k, const double* dir, void* b, v
     if (!t.bie) return set_error("not a BIE handle"), HFMM_EINVAL;
     if (!std::isfinite(k)) return set_error("k must be finite"), HFMM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    if (t.nystrom) {
+      if (!t.d_nys_pts.p) {
+        int rc = upload_vec(t.d_nys_pts, t.nys_pts);
+        if (rc) return rc;
+      }
+      launch_plane_wave_pts(t.npanel, t.d_nys_pts.as<double>(), k, dir, (double2*)b, s);
+      HIP_TRY(hipGetLastError());
+      return HFMM_OK;
+    }
     if (!t.d_panels.p) {
       std::vector<double> panels(9 * t.npanel);
       for (int64_t i = 0; i < t.npanel; ++i)

@@ -161,6 +161,7 @@ struct Plan {
   // BIE corrections (caller panel order; pattern in the Tree)
   DevBuf d_near_val;                            // float2 per near nonzero
   DevBuf d_diag;                                // double2: self integral - 3-point self sum
+  DevBuf d_self6;                               // double2 [points][6]: curved-element self blocks
   int64_t n_near = 0;
   int64_t device_bytes = 0;
   int64_t est_bytes = 0;                 // footprint computed before any allocation
@@ -235,6 +236,15 @@ struct Tree {
   std::vector<int32_t> near_off, near_col;
   DevBuf d_near_off, d_near_row, d_near_col;
   DevBuf d_gl;                  // Gauss-Legendre nodes/weights on [0,1]: near (n), self (10)
+  // curved-element Nystrom handle: unknowns are the six points of each
+  // element (npanel = 6 x elements), element-major
+  bool nystrom = false;
+  std::vector<double> nys_elem;  // [elements][6 nodes][3]
+  std::vector<double> nys_pts;   // [points][3]
+  std::vector<double> nys_jac;   // [points] surface Jacobian
+  std::vector<int4> nys_items;   // near pairs (point, element, value position, -)
+  DevBuf d_nys_elem, d_nys_pts, d_nys_K, d_nys_rule, d_nys_items;
+  int nys_nrule = 0;
   // GMRES workspace (kept between solves)
   int gm_m = 0;
   DevBuf g_V, g_w, g_r, g_x64, g_y64, g_H, g_cs, g_sn, g_g, g_h, g_h2, g_part, g_dot, g_st, g_yv;
@@ -257,6 +267,9 @@ int prepare_host(Tree& t, double k, int P, Plan** out);   // lists, operators, w
 int prepare_device(Tree& t, Plan& pl, hipStream_t s);      // upload and table generation
 int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_t s);
 int prepare_bie(Tree& t, Plan& pl, hipStream_t s);
+int prepare_nystrom(Tree& t, Plan& pl, hipStream_t s);
+// parametric weight of curved-element point p (p mod 6 selects the point)
+float nystrom_weight(int64_t p);
 int check_kP(double k, int P);
 uint64_t next_uid();
 void forget_tree_batches(uint64_t uid);

@@ -25,6 +25,7 @@ EXPORTS = [
     "hfmm_server_create", "hfmm_server_submit", "hfmm_server_step", "hfmm_server_poll",
     "hfmm_server_release", "hfmm_server_used_bytes", "hfmm_server_free",
     "hfmm_variant_count", "hfmm_set_variant", "hfmm_tree_variant", "hfmm_matvec64", "hfmm_direct64",
+    "hfmm_build_nystrom", "hfmm_nystrom_points",
 ]
 
 
@@ -103,6 +104,8 @@ def lib():
             "hfmm_tree_variant": [vp, dbl, i32, i32, C.POINTER(i32)],
             "hfmm_matvec64": [vp, dbl, i32, vp, vp, vp],
             "hfmm_direct64": [vp, vp, i64, vp, i64, dbl, vp, vp],
+            "hfmm_build_nystrom": [vp, i64, vp, i64, C.POINTER(Opts), C.POINTER(vp)],
+            "hfmm_nystrom_points": [vp, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -159,6 +162,27 @@ class Tree:
         o = default_opts(**opts)
         _check(lib().hfmm_build_bie(v.ctypes.data, len(v), t.ctypes.data, len(t), C.byref(o), C.byref(h)))
         return cls(h.value, len(t), len(t), True)
+
+    @classmethod
+    def from_curved_mesh(cls, nodes, tri6, **opts) -> "Tree":
+        """Curved six-node triangles, locally corrected Nystrom (6 unknowns
+        per element, element-major)."""
+        v = np.ascontiguousarray(nodes, dtype=np.float64)
+        t = np.ascontiguousarray(tri6, dtype=np.int32)
+        h = C.c_void_p()
+        o = default_opts(**opts)
+        _check(lib().hfmm_build_nystrom(v.ctypes.data, len(v), t.ctypes.data, len(t), C.byref(o), C.byref(h)))
+        return cls(h.value, 6 * len(t), 6 * len(t), True)
+
+    def nystrom_points(self):
+        """(positions (n, 3), rule weights (n,), surface Jacobians (n,)) of a
+        curved-element handle."""
+        n = self.n_in
+        xyz = np.empty((n, 3), np.float64)
+        w = np.empty(n, np.float64)
+        jac = np.empty(n, np.float64)
+        _check(lib().hfmm_nystrom_points(self._h, xyz.ctypes.data, w.ctypes.data, jac.ctypes.data))
+        return xyz, w, jac
 
     def free(self):
         if self._h and self._h.value:

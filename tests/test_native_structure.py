@@ -98,3 +98,37 @@ def test_bie_invalid_mesh():
     deg[0] = [0, 0, 1]
     with pytest.raises(hfmm.HfmmError):
         hfmm.Tree.from_mesh(V, deg)
+
+
+def test_nystrom_points_and_tree_equal_oracle():
+    """Curved-element handle: the interpolation points, weights and
+    Jacobians equal the oracle's discretisation; its tree over the points
+    equals the oracle's tree."""
+    from oracle import nystrom as ny
+    nodes, tri6 = synth.curved_icosphere(2)
+    t = hfmm.Tree.from_curved_mesh(nodes, tri6, ncrit=32)
+    xyz, w, jac = t.nystrom_points()
+    d = ny.discretise(nodes, tri6)
+    np.testing.assert_allclose(xyz, d["r"], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(w, d["w"], rtol=1e-14)
+    np.testing.assert_allclose(jac, d["jac"], rtol=1e-13)
+    pts = d["r"].astype(np.float32)
+    o = build_tree(pts, pts, 32)
+    sp, tp, cells = t.export()
+    np.testing.assert_array_equal(sp, o.src_perm)
+    np.testing.assert_array_equal(tp, o.tgt_perm)
+
+
+def test_nystrom_invalid_mesh():
+    nodes, tri6 = synth.curved_icosphere(1)
+    bad = tri6.copy()
+    bad[0, 4] = len(nodes)
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.Tree.from_curved_mesh(nodes, bad)
+    deg = tri6.copy()
+    deg[0, :3] = deg[0, 0]
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.Tree.from_curved_mesh(nodes, deg)
+    V, T = synth.icosphere(1)
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.Tree.from_mesh(V, T).nystrom_points()
