@@ -35,12 +35,9 @@ struct v3 {
 };
 __device__ inline v3 vsub(v3 a, v3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ inline double vdot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ inline v3 vcross(v3 a, v3 b) {
-  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
-}
 
 // Quadratic map of element X (6 nodes v0 v1 v2 m01 m12 m20) at (u, v), and
-// optionally its two tangents.
+// its two tangents.
 __device__ inline v3 qmap(const double* X, double u, double v) {
   const double l1 = 1.0 - u - v, l2 = u, l3 = v;
   const double N[6] = {l1 * (2 * l1 - 1), l2 * (2 * l2 - 1), l3 * (2 * l3 - 1), 4 * l1 * l2, 4 * l2 * l3,
@@ -115,7 +112,7 @@ __device__ inline void subtract_rule(const NysConst* K, const double* X, double 
 }  // namespace
 
 // One wave per near pair (target point j, element e); the pair's six values
-// go to val[pos .. pos + 5].  Rule: rule_uvw[3 q + (0, 1, 2)] = (u, v, w).
+// go to val[pos .. pos + 5].  Rule: rule[3 q + (0, 1, 2)] = (u, v, weight).
 __global__ void __launch_bounds__(256) k_nys_near(int64_t nitems, const int4* __restrict__ items,
                                                   const double* __restrict__ pts, const double* __restrict__ elem,
                                                   const NysConst* __restrict__ K, const double* __restrict__ rule,
