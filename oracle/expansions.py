@@ -35,7 +35,7 @@ import numpy as np
 
 from .gaunt import gaunt
 from .special import (cart_to_sph, idx, regular_all, singular_all,
-                      sph_h1, ylm_all)
+                      sph_h1, ylm_all, sph_jn)
 
 
 @lru_cache(maxsize=None)
@@ -85,10 +85,19 @@ def sr_matrix(t, k: float, Pout: int, Pin: int | None = None) -> np.ndarray:
     return _assemble(harm, Pout, Pin)
 
 
-def p2m(P: int, k: float, c, y, q) -> np.ndarray:
-    """M_n^m = sum_j q_j R_n^{-m}(y_j - c) = sum_j q_j conj(R_n^m(y_j - c)) (k real)."""
-    R = regular_all(P, k, np.asarray(y, np.float64) - np.asarray(c, np.float64))
-    return (np.asarray(q, np.complex128)[:, None] * np.conj(R)).sum(axis=0)
+def p2m(P: int, k, c, y, q) -> np.ndarray:
+    """M_n^m = sum_j q_j R_n^{-m}(y_j - c), R_n^{-m}(v) = j_n(k|v|) conj(Y_n^m(v^))
+    (for real k this is conj(R_n^m); a complex k stays unconjugated in j_n)."""
+    v = np.asarray(y, np.float64) - np.asarray(c, np.float64)
+    r, th, ph = cart_to_sph(v)
+    Y = ylm_all(P, th, ph)
+    qq = np.asarray(q, np.complex128)
+    out = np.zeros(P * P, dtype=np.complex128)
+    for n in range(P):
+        jn = sph_jn(n, k * r)
+        sl = slice(n * n, (n + 1) * (n + 1))
+        out[sl] = (qq[:, None] * jn[:, None] * np.conj(Y[:, sl])).sum(axis=0)
+    return out
 
 
 def p2l(P: int, k: float, c, y, q) -> np.ndarray:

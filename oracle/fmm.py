@@ -19,8 +19,9 @@ from . import expansions as ex
 from .tree import Tree, build_tree, dual_tree_traversal
 
 
-def green(k: float, x, y):
-    """G(x, y) = e^{ik|x-y|} / (4 pi |x-y|)  (eq. (6)); zero where x == y."""
+def green(k, x, y):
+    """G(x, y) = e^{ik|x-y|} / (4 pi |x-y|)  (eq. (6)); zero where x == y.
+    k may be complex (k + i k_imag: e^{ikR} = e^{i Re(k) R} e^{-k_imag R})."""
     d = np.asarray(x, np.float64) - np.asarray(y, np.float64)
     R = np.sqrt((d * d).sum(axis=-1))
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -44,14 +45,19 @@ class FMM:
     """Tree, lists and cached operators for one geometry and wavenumber."""
 
     def __init__(self, sources, targets=None, k=1.0, P=8, ncrit=64, theta=0.5,
-                 kappa=None):
+                 kappa=None, k_imag=0.0):
+        """k_imag >= 0: the wavenumber is k + i k_imag (damped waves, the
+        imaginary wavenumber of the P2P listing of Sec. 3.1); the tree's
+        wavelength rules use |k + i k_imag|."""
         self.src = np.asarray(sources, np.float32)
         self.tgt = self.src if targets is None else np.asarray(targets, np.float32)
-        self.k, self.P, self.theta = float(k), int(P), float(theta)
+        self.k = complex(k, k_imag) if k_imag else float(k)
+        self.P, self.theta = int(P), float(theta)
         self.kappa = 0.4 * P if kappa is None else float(kappa)
+        kabs = abs(self.k)
         self.tree: Tree = build_tree(self.src, None if targets is None else self.tgt, ncrit,
-                                     split_side=self.kappa / self.k)
-        self.m2l, self.p2p = dual_tree_traversal(self.tree, self.k, self.theta, self.kappa)
+                                     split_side=self.kappa / kabs)
+        self.m2l, self.p2p = dual_tree_traversal(self.tree, kabs, self.theta, self.kappa)
         self._cache: dict = {}
 
     def _op(self, kind: str, t):

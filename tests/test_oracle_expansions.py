@@ -75,3 +75,52 @@ def test_p2l_matches_m2l_of_point():
     L1 = ex.p2l(P, k, ct, ys, q)
     L2 = ex.sr_matrix(ct, k, P, 30) @ ex.p2m(30, k, np.zeros(3), ys, q)
     np.testing.assert_allclose(L2, L1, atol=1e-10 * np.abs(L1).max())
+
+
+def test_addition_theorem_complex_wavenumber():
+    """Damped waves, k = 2.3 + 0.7i: G = ik sum R_n^{-m}(y) S_n^m(x) with
+    R_n^{-m}(y) = j_n(k|y|) conj(Y_n^m) = conj(R_n^m(y) at conj(k))."""
+    k = 2.3 + 0.7j
+    rng = np.random.default_rng(1)
+    y = rng.normal(size=3) * 0.2
+    x = np.array([1.1, -0.6, 0.9])
+    exact = green(k, x, y)
+    assert abs(exact - np.exp(1j * 2.3 * np.linalg.norm(x - y)) * np.exp(-0.7 * np.linalg.norm(x - y))
+               / (4 * np.pi * np.linalg.norm(x - y))) < 1e-15
+    P = 24
+    Rm = np.conj(regular_all(P, np.conj(k), y[None])[0])
+    S = singular_all(P, k, x[None])[0]
+    approx = 1j * k * (Rm * S).sum()
+    assert abs(approx - exact) / abs(exact) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["rr", "sr"])
+def test_translation_pointwise_complex_wavenumber(kind):
+    k = 1.7 + 0.5j
+    rng = np.random.default_rng(3)
+    t = np.array([0.9, -0.7, 1.2])
+    r = rng.normal(size=3)
+    r *= (0.25 if kind == "sr" else 0.6) / np.linalg.norm(r)
+    Pin, Pout = 6, 26
+    f = regular_all if kind == "rr" else singular_all
+    lhs = f(Pin, k, (r + t)[None])[0]
+    T = (ex.rr_matrix if kind == "rr" else ex.sr_matrix)(t, k, Pout, Pin)
+    rhs = regular_all(Pout, k, r[None])[0] @ T
+    np.testing.assert_allclose(rhs, lhs, rtol=0, atol=1e-9 * np.abs(lhs).max())
+
+
+def test_p2m_m2l_l2p_complex_wavenumber():
+    k = 2.0 + 0.8j
+    rng = np.random.default_rng(5)
+    s = 0.25
+    cs, ct = np.zeros(3), np.array([1.0, 0.0, 0.0])
+    ys = cs + rng.uniform(-s / 2, s / 2, (40, 3))
+    xt = ct + rng.uniform(-s / 2, s / 2, (30, 3))
+    q = rng.normal(size=40) + 1j * rng.normal(size=40)
+    ref = direct_sum(k, xt, ys, q)
+    errs = []
+    for P in (2, 4, 6, 8, 10):
+        L = ex.sr_matrix(ct - cs, k, P) @ ex.p2m(P, k, cs, ys, q)
+        errs.append(np.linalg.norm(ex.l2p(P, k, ct, L, xt) - ref) / np.linalg.norm(ref))
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+    assert errs[-1] < 1e-7

@@ -128,3 +128,26 @@ def test_fmm_error_falls_with_P():
         errs.append(np.linalg.norm(f.matvec(q) - ref) / np.linalg.norm(ref))
     assert all(errs[i + 1] < errs[i] for i in range(3)), errs
     assert errs[-1] < 1e-6
+
+
+def test_complex_wavenumber_fd_residual_and_fmm():
+    """k = 3 + 1i: the direct sum solves lap u + k^2 u = 0 away from the
+    sources, and the FMM (tree rules on |k|) converges to it with P."""
+    k = 3.0 + 1.0j
+    rng = np.random.default_rng(2)
+    src = rng.normal(size=(20, 3)) * 0.3
+    q0 = rng.normal(size=20) + 1j * rng.normal(size=20)
+    x0 = np.array([1.5, 0.2, -0.4])
+    h = 1e-3
+    u = lambda x: direct_sum(k, x[None], src, q0)[0]
+    lap = sum(u(x0 + h * e) + u(x0 - h * e) - 2 * u(x0) for e in np.eye(3)) / h ** 2
+    assert abs(lap + k * k * u(x0)) < 1e-5 * abs(k * k * u(x0))
+    x = synth.sphere_points(1200, 9)
+    q = synth.strengths(1200, 9)
+    ref = direct_sum(k, x, x, q)
+    errs = []
+    for P in (3, 5, 7, 9):
+        f = FMM(x, k=3.0, k_imag=1.0, P=P, ncrit=32)
+        errs.append(np.linalg.norm(f.matvec(q) - ref) / np.linalg.norm(ref))
+    assert all(errs[i + 1] < errs[i] for i in range(3)), errs
+    assert errs[-1] < 1e-6
