@@ -63,7 +63,12 @@ typedef struct {
   int32_t bie_treatment; /* BIE singular-integral treatment: 0 self + near corrections
                             (default), 1 self-panel integral only, 2 none (the 3-point rule
                             everywhere, the listing without its near branch) */
-  int32_t reserved[6];
+  double k_imag;        /* imaginary part of the wavenumber: every call on the handle uses
+                            k + i k_imag (damped waves, the imaginary wavenumber of the P2P
+                            listing of Sec. 3.1); >= 0, default 0.  The tree rules use
+                            |k + i k_imag|; the plane wave becomes exp(i (k + i k_imag) d.x).
+                            The FP64 variant (hfmm_matvec64) takes k_imag = 0 only */
+  int32_t reserved[4];
 } hfmm_opts;
 
 typedef struct {

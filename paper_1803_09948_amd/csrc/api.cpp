@@ -161,8 +161,9 @@ double kappa_of(const Tree& t, int P) { return t.kappa < 0 ? 0.4 * P : t.kappa; 
 
 int build_plan_host(Tree& t, double k, int P, Plan& pl) {
   const double kappa = kappa_of(t, P);
-  build_cells(t.h, t.ncrit, t.max_level, kappa / k, pl.ct);
-  dual_tree_traversal(pl.ct, k, t.theta, kappa, pl.lists);
+  const double kabs = std::hypot(k, t.k_imag);  // wavelength rules on |k + i k_imag|
+  build_cells(t.h, t.ncrit, t.max_level, kappa / kabs, pl.ct);
+  dual_tree_traversal(pl.ct, kabs, t.theta, kappa, pl.lists);
   int64_t pp = 0;
   for (size_t i = 0; i < pl.lists.p2p_a.size(); ++i) {
     int a = pl.lists.p2p_a[i], b = pl.lists.p2p_b[i];
@@ -185,6 +186,7 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
   auto plp = std::make_unique<Plan>();
   Plan& pl = *plp;
   pl.k = k;
+  pl.ki = t.k_imag;
   pl.P = P;
   pl.hd = std::make_unique<HostPlanData>();
   HostPlanData& hd = *pl.hd;
@@ -193,7 +195,7 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
   const int P2 = P * P;
   const int nlev = h.nlevels();
   pl.rho.resize(nlev);
-  for (int l = 0; l < nlev; ++l) pl.rho[l] = std::min(1.0, k * 2.0 * h.H / double(1 << l));
+  for (int l = 0; l < nlev; ++l) pl.rho[l] = std::min(1.0, std::hypot(k, t.k_imag) * 2.0 * h.H / double(1 << l));
   // operators: M2M and L2L per child level and octant
   std::vector<OpDesc>& ops = hd.ops;
   pl.m2m_base.assign(nlev, 0);
@@ -450,7 +452,7 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   if ((rc = upload(d_off, cp.off)) || (rc = upload(d_lm, cp.lm)) || (rc = upload(d_val, cv)))
     return rc;
   if ((rc = pl.d_tables.alloc((size_t)pl.n_ops * Kp * Rp * sizeof(float2)))) return rc;
-  launch_gen_tables(pl.d_ops.as<OpDesc>(), (int)pl.n_ops, P, k, d_off.as<int32_t>(),
+  launch_gen_tables(pl.d_ops.as<OpDesc>(), (int)pl.n_ops, P, k, pl.ki, d_off.as<int32_t>(),
                     d_lm.as<int32_t>(), d_val.as<double2>(), pl.d_tables.as<float2>(), s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
@@ -557,7 +559,9 @@ static int apply_opts(Tree& t, const hfmm_opts* o) {
   if (o->near_levels < 0 || o->near_levels > 5 || o->near_order < 1 || o->near_order > 16)
     return set_error("near_levels in [0,5], near_order in [1,16]"), HFMM_EINVAL;
   if (o->bie_treatment < 0 || o->bie_treatment > 2) return set_error("bie_treatment in [0, 2]"), HFMM_EINVAL;
+  if (!(o->k_imag >= 0.0) || !std::isfinite(o->k_imag)) return set_error("k_imag must be finite and >= 0"), HFMM_EINVAL;
   t.ncrit = o->ncrit;
+  t.k_imag = o->k_imag;
   t.stage_bytes = (int64_t)(o->stage_mb > 0 ? o->stage_mb : 32768) << 20;
   t.bie_treatment = o->bie_treatment;
   t.max_level = o->max_level;

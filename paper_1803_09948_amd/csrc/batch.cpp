@@ -63,6 +63,7 @@ static InstDev make_inst(Tree& t, Plan& pl) {
   I.ntgt = pl.ct.ntgt;
   I.ncellP2 = (int64_t)pl.ct.ncell() * pl.P * pl.P;
   I.k = (float)pl.k;
+  I.ki = (float)pl.ki;
   return I;
 }
 
@@ -81,6 +82,7 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
   b.trees = trees;
   b.plans = plans;
   b.hinst.clear();
+  b.damped = false;
   const int ch = elem_chunk();
   std::vector<int2> zero, gather, scatter, p2m, l2p, p2p, red;
   std::vector<int4> m2l;
@@ -88,6 +90,7 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
   for (int i = 0; i < b.count; ++i) {
     Plan& pl = *plans[i];
     b.hinst.push_back(make_inst(*trees[i], pl));
+    b.damped = b.damped || pl.ki != 0.0;
     b.maxlev = std::max(b.maxlev, pl.ct.nlevels());
     const InstDev& I = b.hinst.back();
     for (int64_t e = 0; e * ch < I.ncellP2; ++e) zero.push_back(make_int2(i, (int)e));
@@ -204,7 +207,7 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   if ((rc = mark(0))) return rc;
   launch_zero(b.d_zero.as<int2>(), b.n_zero, I, s);
   launch_gather(b.d_gather.as<int2>(), b.n_gather, I, s);
-  launch_p2m(b.d_p2m.as<int2>(), b.n_p2m, I, P, s);
+  launch_p2m(b.d_p2m.as<int2>(), b.n_p2m, I, P, b.damped, s);
   if ((rc = mark(1))) return rc;
   for (int l = b.maxlev - 2; l >= 0; --l)
     launch_m2m(b.d_m2m.as<int4>() + b.m2m_off[l], b.m2m_off[l + 1] - b.m2m_off[l], b.d_m2m_cols.as<int32_t>(), I,
@@ -225,9 +228,9 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
     launch_l2l(b.d_l2l.as<int4>() + b.l2l_off[l], b.l2l_off[l + 1] - b.l2l_off[l], b.d_l2l_cols.as<int32_t>(), I,
                P, s);
   if ((rc = mark(5))) return rc;
-  launch_l2p(b.d_l2p.as<int2>(), b.n_l2p, I, P, s);
+  launch_l2p(b.d_l2p.as<int2>(), b.n_l2p, I, P, b.damped, s);
   if ((rc = mark(6))) return rc;
-  launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, s);
+  launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, s);
   if ((rc = mark(7))) return rc;
   launch_scatter(b.d_scatter.as<int2>(), b.n_scatter, I, s);
   HIP_TRY(hipGetLastError());

@@ -129,11 +129,11 @@ int prepare_bie(Tree& t, Plan& pl, hipStream_t s) {
   // corrections of the chosen treatment (the ablation modes leave zeros)
   if (t.bie_treatment == 0)
     launch_near(pl.n_near, t.d_near_row.as<int32_t>(), t.d_near_col.as<int32_t>(), t.d_panels.as<double>(),
-                pl.k, t.near_levels, gl, gl + ng, ng, pl.d_near_val.as<float2>(), s);
+                pl.k, pl.ki, t.near_levels, gl, gl + ng, ng, pl.d_near_val.as<float2>(), s);
   else
     HIP_TRY(hipMemsetAsync(pl.d_near_val.p, 0, pl.d_near_val.bytes, s));
   if (t.bie_treatment <= 1)
-    launch_self(n, t.d_panels.as<double>(), pl.k, gl + 2 * ng, gl + 2 * ng + kSelfOrder, kSelfOrder,
+    launch_self(n, t.d_panels.as<double>(), pl.k, pl.ki, gl + 2 * ng, gl + 2 * ng + kSelfOrder, kSelfOrder,
                 pl.d_diag.as<double2>(), s);
   else
     HIP_TRY(hipMemsetAsync(pl.d_diag.p, 0, pl.d_diag.bytes, s));
@@ -303,6 +303,7 @@ int hfmm_build_bie(const double* verts, int64_t nv, const int32_t* tris, int64_t
         o->near_levels < 0 || o->near_levels > 5 || o->near_order < 1 || o->near_order > 16 ||
         o->bie_treatment < 0 || o->bie_treatment > 2)
       return set_error("invalid options"), HFMM_EINVAL;
+    if (!(o->k_imag >= 0.0) || !std::isfinite(o->k_imag)) return set_error("k_imag must be finite and >= 0"), HFMM_EINVAL;
     auto t = std::make_unique<Tree>();
     t->ncrit = o->ncrit;
     t->max_level = o->max_level;
@@ -313,6 +314,7 @@ int hfmm_build_bie(const double* verts, int64_t nv, const int32_t* tris, int64_t
     t->near_order = o->near_order;
     t->stage_bytes = (int64_t)(o->stage_mb > 0 ? o->stage_mb : 32768) << 20;
     t->bie_treatment = o->bie_treatment;
+    t->k_imag = o->k_imag;
     t->bie = true;
     t->npanel = nt;
     t->verts.assign(verts, verts + 3 * nv);
@@ -376,7 +378,7 @@ int hfmm_bie_plane_wave(hfmm_tree* tree, double k, const double* dir, void* b, v
         int rc = upload_vec(t.d_nys_pts, t.nys_pts);
         if (rc) return rc;
       }
-      launch_plane_wave_pts(t.npanel, t.d_nys_pts.as<double>(), k, dir, (double2*)b, s);
+      launch_plane_wave_pts(t.npanel, t.d_nys_pts.as<double>(), k, t.k_imag, dir, (double2*)b, s);
       HIP_TRY(hipGetLastError());
       return HFMM_OK;
     }
@@ -388,7 +390,7 @@ int hfmm_bie_plane_wave(hfmm_tree* tree, double k, const double* dir, void* b, v
       int rc = upload_vec(t.d_panels, panels);
       if (rc) return rc;
     }
-    launch_plane_wave(t.npanel, t.d_panels.as<double>(), k, dir, (double2*)b, s);
+    launch_plane_wave(t.npanel, t.d_panels.as<double>(), k, t.k_imag, dir, (double2*)b, s);
     HIP_TRY(hipGetLastError());
     return HFMM_OK;
   } catch (...) {

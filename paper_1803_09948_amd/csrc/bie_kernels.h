@@ -7,13 +7,15 @@
 
 namespace hfmm {
 
-void launch_self(int64_t npan, const double* pan, double k, const double* gx, const double* gw, int ng,
+// k + i ki: the wavenumber (ki >= 0 damps)
+void launch_self(int64_t npan, const double* pan, double k, double ki, const double* gx, const double* gw, int ng,
                  double2* diag, hipStream_t s);
-void launch_near(int64_t nnz, const int32_t* rows, const int32_t* cols, const double* pan, double k, int L,
-                 const double* gx, const double* gw, int ng, float2* val, hipStream_t s);
+void launch_near(int64_t nnz, const int32_t* rows, const int32_t* cols, const double* pan, double k, double ki,
+                 int L, const double* gx, const double* gw, int ng, float2* val, hipStream_t s);
 void launch_near_apply(int64_t n, const int32_t* off, const int32_t* col, const float2* val,
                        const double2* diag, const float2* x, float2* y, hipStream_t s);
-void launch_plane_wave(int64_t n, const double* pan, double k, const double* d, double2* b, hipStream_t s);
+void launch_plane_wave(int64_t n, const double* pan, double k, double ki, const double* d, double2* b,
+                       hipStream_t s);
 void launch_to_c64(int64_t n, const double2* a, float2* b, hipStream_t s);
 void launch_from_c64_diag(int64_t n, const float2* y, const double2* diag, const double2* v, double2* out,
                           hipStream_t s);

@@ -38,24 +38,24 @@ __device__ inline d3 vtx(const double* pan, int i, int v) {
   return {p[0], p[1], p[2]};
 }
 
-// G(x, y) = e^{ikR} / (4 pi R)
-__device__ inline double2 green64(double k, d3 x, d3 y) {
+// G(x, y) = e^{ikR} / (4 pi R) for the wavenumber k + i ki
+__device__ inline double2 green64(double k, double ki, d3 x, d3 y) {
   double R = nrm(sub(x, y));
   double s, c;
   sincos(k * R, &s, &c);
-  double f = 1.0 / (4.0 * M_PI * R);
+  double f = exp(-ki * R) / (4.0 * M_PI * R);
   return make_double2(c * f, s * f);
 }
 
 // 3-point interior rule on panel j seen from x: (A/3) sum_g G(x, y_g)
-__device__ inline double2 three_point(double k, d3 x, d3 a, d3 b, d3 c) {
+__device__ inline double2 three_point(double k, double ki, d3 x, d3 a, d3 b, d3 c) {
   double area = 0.5 * nrm(cross(sub(b, a), sub(c, a)));
   double2 s = make_double2(0.0, 0.0);
   const double w1 = 2.0 / 3.0, w2 = 1.0 / 6.0;
   d3 g[3] = {add(add(scl(a, w1), scl(b, w2)), scl(c, w2)), add(add(scl(a, w2), scl(b, w1)), scl(c, w2)),
              add(add(scl(a, w2), scl(b, w2)), scl(c, w1))};
   for (int q = 0; q < 3; ++q) {
-    double2 v = green64(k, x, g[q]);
+    double2 v = green64(k, ki, x, g[q]);
     s.x += v.x;
     s.y += v.y;
   }
@@ -83,7 +83,7 @@ __device__ double laplace_inplane(d3 x, d3 a, d3 b, d3 c) {
 }
 
 // Self term D_i = S_ii - 3pt_ii, one thread per panel.
-__global__ void k_self(int64_t npan, const double* __restrict__ pan, double k,
+__global__ void k_self(int64_t npan, const double* __restrict__ pan, double k, double ki,
                        const double* __restrict__ gx, const double* __restrict__ gw, int ng,
                        double2* __restrict__ diag) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -105,13 +105,14 @@ __global__ void k_self(int64_t npan, const double* __restrict__ pan, double k,
         double w = gw[iu] * gw[iv] * u * a2 / (4.0 * M_PI * R);
         double s, cc;
         sincos(k * R, &s, &cc);
-        // e^{ikR} - 1 = (cos kR - 1) + i sin kR;  cos kR - 1 = -2 sin^2(kR/2)
+        // e^{i(k + i ki)R} - 1 = (e^{-ki R} - 1) cos kR + (cos kR - 1) + i e^{-ki R} sin kR,
+        // with cos kR - 1 = -2 sin^2(kR/2): no cancellation at small R
         double h = sin(0.5 * k * R);
-        sr += w * (-2.0 * h * h);
-        si += w * s;
+        sr += w * (expm1(-ki * R) * cc - 2.0 * h * h);
+        si += w * exp(-ki * R) * s;
       }
   }
-  double2 t3 = three_point(k, x, a, b, c);
+  double2 t3 = three_point(k, ki, x, a, b, c);
   diag[i] = make_double2(lap + sr - t3.x, si - t3.y);
 }
 
@@ -120,7 +121,7 @@ __global__ void k_self(int64_t npan, const double* __restrict__ pan, double k,
 // each) minus the 3-point sum.  Values stored as complex64.
 __global__ void __launch_bounds__(256) k_near(int64_t nnz, const int32_t* __restrict__ rows,
                                               const int32_t* __restrict__ cols,
-                                              const double* __restrict__ pan, double k, int L,
+                                              const double* __restrict__ pan, double k, double ki, int L,
                                               const double* __restrict__ gx,
                                               const double* __restrict__ gw, int ng,
                                               float2* __restrict__ val) {
@@ -161,7 +162,7 @@ __global__ void __launch_bounds__(256) k_near(int64_t nnz, const int32_t* __rest
     for (int t = 0; t < 3; ++t) lam[t] = P0[t] + u * (P1[t] - P0[t]) + u * v * (P2[t] - P1[t]);
     d3 y = add(add(scl(a, lam[0]), scl(b, lam[1])), scl(c, lam[2]));
     double w = gw[iu] * gw[iv] * u * 2.0 * (area / nsub);
-    double2 g = green64(k, x, y);
+    double2 g = green64(k, ki, x, y);
     sr += w * g.x;
     si += w * g.y;
   }
@@ -176,7 +177,7 @@ __global__ void __launch_bounds__(256) k_near(int64_t nnz, const int32_t* __rest
       tr += red[wave][0][l];
       ti += red[wave][1][l];
     }
-    double2 t3 = three_point(k, x, a, b, c);
+    double2 t3 = three_point(k, ki, x, a, b, c);
     val[e] = make_float2((float)(tr - t3.x), (float)(ti - t3.y));
   }
 }
@@ -203,14 +204,16 @@ __global__ void k_near_apply(int64_t n, const int32_t* __restrict__ off, const i
 }
 
 // b_i = exp(i k d . c_i)
-__global__ void k_plane_wave(int64_t n, const double* __restrict__ pan, double k, double dx, double dy,
+__global__ void k_plane_wave(int64_t n, const double* __restrict__ pan, double k, double ki, double dx, double dy,
                              double dz, double2* __restrict__ b) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   d3 x = scl(add(add(vtx(pan, i, 0), vtx(pan, i, 1)), vtx(pan, i, 2)), 1.0 / 3.0);
+  const double ph = dx * x.x + dy * x.y + dz * x.z;
   double s, c;
-  sincos(k * (dx * x.x + dy * x.y + dz * x.z), &s, &c);
-  b[i] = make_double2(c, s);
+  sincos(k * ph, &s, &c);
+  const double a = exp(-ki * ph);  // e^{i (k + i ki) d.x}
+  b[i] = make_double2(a * c, a * s);
 }
 
 // ---------------------------------------------------------------------------
@@ -398,20 +401,21 @@ __global__ void k_init_g(int m, const double2* __restrict__ dotval, double2* __r
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-void launch_self(int64_t npan, const double* pan, double k, const double* gx, const double* gw, int ng,
+void launch_self(int64_t npan, const double* pan, double k, double ki, const double* gx, const double* gw, int ng,
                  double2* diag, hipStream_t s) {
-  if (npan > 0) k_self<<<nblk(npan, 128), 128, 0, s>>>(npan, pan, k, gx, gw, ng, diag);
+  if (npan > 0) k_self<<<nblk(npan, 128), 128, 0, s>>>(npan, pan, k, ki, gx, gw, ng, diag);
 }
-void launch_near(int64_t nnz, const int32_t* rows, const int32_t* cols, const double* pan, double k, int L,
-                 const double* gx, const double* gw, int ng, float2* val, hipStream_t s) {
-  if (nnz > 0) k_near<<<nblk(nnz, 4), 256, 0, s>>>(nnz, rows, cols, pan, k, L, gx, gw, ng, val);
+void launch_near(int64_t nnz, const int32_t* rows, const int32_t* cols, const double* pan, double k, double ki,
+                 int L, const double* gx, const double* gw, int ng, float2* val, hipStream_t s) {
+  if (nnz > 0) k_near<<<nblk(nnz, 4), 256, 0, s>>>(nnz, rows, cols, pan, k, ki, L, gx, gw, ng, val);
 }
 void launch_near_apply(int64_t n, const int32_t* off, const int32_t* col, const float2* val,
                        const double2* diag, const float2* x, float2* y, hipStream_t s) {
   if (n > 0) k_near_apply<<<nblk(n, 256), 256, 0, s>>>(n, off, col, val, diag, x, y);
 }
-void launch_plane_wave(int64_t n, const double* pan, double k, const double* d, double2* b, hipStream_t s) {
-  if (n > 0) k_plane_wave<<<nblk(n, 256), 256, 0, s>>>(n, pan, k, d[0], d[1], d[2], b);
+void launch_plane_wave(int64_t n, const double* pan, double k, double ki, const double* d, double2* b,
+                       hipStream_t s) {
+  if (n > 0) k_plane_wave<<<nblk(n, 256), 256, 0, s>>>(n, pan, k, ki, d[0], d[1], d[2], b);
 }
 void launch_to_c64(int64_t n, const double2* a, float2* b, hipStream_t s) {
   if (n > 0) k_to_c64<<<nblk(n, 256), 256, 0, s>>>(n, a, b);

@@ -18,7 +18,8 @@ struct OpDescDev {         // translation operator descriptor (48 bytes)
 
 // Padded table dimensions: Kp = 4 ceil(P^2/4) inputs, Rp = 16 ceil(P^2/16) outputs.
 void table_dims(int P, int* Kp, int* Rp);
-void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
+// k + i ki: complex wavenumber (ki = 0: real)
+void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, double ki, const int32_t* cp_off,
                        const int32_t* cp_lm, const double2* cp_val, float2* tables,
                        hipStream_t s);
 // The same tables in FP64 (precision reference).
@@ -53,7 +54,7 @@ struct InstDev {
   const int32_t* p2p_total; // sources per work item
   int64_t nsrc, ntgt, ncellP2;
   float k;
-  int32_t pad;
+  float ki;                 // imaginary part of the wavenumber (damping), >= 0
 };
 
 struct XYPtrs {
@@ -66,15 +67,17 @@ void launch_set_xy(int count, int base, const XYPtrs& p, InstDev* insts, hipStre
 void launch_zero(const int2* items, int n, const InstDev* insts, hipStream_t s);
 void launch_gather(const int2* items, int n, const InstDev* insts, hipStream_t s);
 void launch_scatter(const int2* items, int n, const InstDev* insts, hipStream_t s);
-void launch_p2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
+// damped: some instance has ki != 0 (kernels with the complex radial
+// functions / decay factor; they are exact for ki = 0 too)
+void launch_p2m(const int2* items, int n, const InstDev* insts, int P, bool damped, hipStream_t s);
 // M2M / L2L items: (instance, op, first column entry, count <= 16).  M2M
 // column entries are 9 int32 (parent, child of octant 0..7 or -1) and op is
 // the octant-0 operator of the child level; L2L entries are 2 int32 (child,
 // parent), all children of one item sharing the operator op.
 void launch_m2m(const int4* items, int n, const int32_t* cols, const InstDev* insts, int P, hipStream_t s);
 void launch_l2l(const int4* items, int n, const int32_t* cols, const InstDev* insts, int P, hipStream_t s);
-void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream_t s);
-void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s);
+void launch_l2p(const int2* items, int n, const InstDev* insts, int P, bool damped, hipStream_t s);
+void launch_p2p(const int2* items, int n, const InstDev* insts, bool damped, hipStream_t s);
 int m2l_pairs_per_chunk(int P);
 // chunks: (instance, op, pair begin, pair end), sorted by (instance, op)
 // L[t] = sum of the staging slots of t, each mapped back by its reflection's

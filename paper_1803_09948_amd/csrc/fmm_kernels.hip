@@ -82,6 +82,72 @@ __device__ void bessel_j_all(int nm, double x, double* j) {
   for (int n = 0; n < nm; ++n) j[n] *= scale;
 }
 
+// Complex FP64 arithmetic for a complex wavenumber k + i ki (damped waves).
+struct zd {
+  double re, im;
+};
+__device__ inline zd zmul(zd a, zd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline zd zscale(zd a, double s) { return {a.re * s, a.im * s}; }
+__device__ inline zd zsub(zd a, zd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline double zabs2(zd a) { return a.re * a.re + a.im * a.im; }
+__device__ inline zd zinv(zd a) {
+  const double d = 1.0 / zabs2(a);
+  return {a.re * d, -a.im * d};
+}
+__device__ inline zd zsin(zd z) { return {sin(z.re) * cosh(z.im), cos(z.re) * sinh(z.im)}; }
+__device__ inline zd zcos(zd z) { return {cos(z.re) * cosh(z.im), -sin(z.re) * sinh(z.im)}; }
+
+// j_n(z), n < nm, complex z (|z| > 0): power series for |z| < 1, else
+// Miller's downward recurrence normalised by the larger of j_0, j_1.
+__device__ void bessel_j_all_c(int nm, zd z, zd* j) {
+  const double az = sqrt(zabs2(z));
+  if (az < 1.0) {
+    const zd h = zscale(zmul(z, z), -0.5);
+    zd zn = {1.0, 0.0};
+    double df = 1.0;
+    for (int n = 0; n < nm; ++n) {
+      df *= (2.0 * n + 1.0);
+      zd term = {1.0, 0.0}, sum = {1.0, 0.0};
+      for (int k = 1; k < 30; ++k) {
+        term = zscale(zmul(term, h), 1.0 / (k * (2.0 * n + 2.0 * k + 1.0)));
+        sum = {sum.re + term.re, sum.im + term.im};
+        if (zabs2(term) < 1e-34 * zabs2(sum)) break;
+      }
+      j[n] = zscale(zmul(zn, sum), 1.0 / df);
+      zn = zmul(zn, z);
+    }
+    return;
+  }
+  const zd iz = zinv(z), sn = zsin(z), cs = zcos(z);
+  const zd j0 = zmul(sn, iz), j1 = zmul(zsub(zmul(sn, iz), cs), iz);
+  const int N = nm + 16 + (int)az;
+  zd fp1 = {0.0, 0.0}, f = {1e-30, 0.0};
+  for (int n = N; n >= 1; --n) {
+    const zd fm1 = zsub(zscale(zmul(iz, f), 2.0 * n + 1.0), fp1);
+    fp1 = f;
+    f = fm1;
+    if (n - 1 < nm) j[n - 1] = f;
+    if (zabs2(f) > 1e300) {
+      fp1 = zscale(fp1, 1e-250);
+      f = zscale(f, 1e-250);
+      for (int m = n - 1; m < nm; ++m) j[m] = zscale(j[m], 1e-250);
+    }
+  }
+  const zd sc = (zabs2(j0) >= zabs2(j1)) ? zmul(j0, zinv(f)) : zmul(j1, zinv(fp1));
+  for (int n = 0; n < nm; ++n) j[n] = zmul(j[n], sc);
+}
+
+// h_n(z) = j_n + i y_n, n < nm, complex z (|z| > 0), by upward recurrence
+// from h_0 = -i e^{iz} / z and h_1 = -e^{iz} (z + i) / z^2.
+__device__ void hankel_all_c(int nm, zd z, zd* h) {
+  const zd iz = zinv(z);
+  const double ea = exp(-z.im);
+  const zd eiz = {ea * cos(z.re), ea * sin(z.re)};
+  h[0] = zmul({0.0, -1.0}, zmul(eiz, iz));
+  if (nm > 1) h[1] = zscale(zmul(eiz, zmul({z.re, z.im + 1.0}, zmul(iz, iz))), -1.0);
+  for (int n = 1; n + 1 < nm; ++n) h[n + 1] = zsub(zscale(zmul(iz, h[n]), 2.0 * n + 1.0), h[n - 1]);
+}
+
 // ---------------------------------------------------------------------------
 // Translation tables.  For operator o and entry (row r = (n',m'), col c=(n,m)):
 //   T[o][c][r] = sum_l coef * H_l^{m-m'}(t) * scale(n, n'),
@@ -92,7 +158,7 @@ __device__ inline void store_entry(float2* p, double re, double im) { *p = make_
 __device__ inline void store_entry(double2* p, double re, double im) { *p = make_double2(re, im); }
 
 template <class C2>
-__global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P, double k,
+__global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P, double k, double ki,
                              const int32_t* __restrict__ cp_off, const int32_t* __restrict__ cp_lm,
                              const double2* __restrict__ cp_val, int Kp, int Rp,
                              C2* __restrict__ tables) {
@@ -108,7 +174,19 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
     // radial functions
     double jr[2 * kMaxP], yr[2 * kMaxP];
     double x = k * r;
-    if (d.kind == 2) {
+    if (ki != 0.0) {
+      // complex argument: (j + i y) or j as complex numbers, split into the
+      // real and imaginary parts the angular product below expects
+      zd f[2 * kMaxP];
+      if (d.kind == 2)
+        hankel_all_c(L, {x, ki * r}, f);
+      else
+        bessel_j_all_c(L, {x, ki * r}, f);
+      for (int n = 0; n < L; ++n) {
+        jr[n] = f[n].re;
+        yr[n] = f[n].im;
+      }
+    } else if (d.kind == 2) {
       // h_l = j_l + i y_l by upward recurrence: stable for y_l, and the error
       // it leaves in j_l is relative to |h_l|
       double s = sin(x), c = cos(x);
@@ -349,12 +427,59 @@ __device__ inline void radial_scaled(double x, double rho, float* b) {
   }
 }
 
+// The same for a complex argument z = (k + i ki) r: b_n = j_n(z) (2n+1)!! / rho^n.
+// |z| < 1e-3: the first two series terms; else Miller's downward recurrence
+// normalised by the larger of j_0, j_1.
+template <int P>
+__device__ inline void radial_scaled_c(double zr, double zi, double rho, float2* b) {
+  const zd z = {zr, zi};
+  const double az = sqrt(zabs2(z));
+  if (az < 1e-3) {
+    const zd zr_ = zscale(z, 1.0 / rho), z2 = zmul(z, z);
+    zd p = {1.0, 0.0};
+#pragma unroll
+    for (int n = 0; n < P; ++n) {
+      const zd v = zmul(p, {1.0 - z2.re / (4.0 * n + 6.0), -z2.im / (4.0 * n + 6.0)});
+      b[n] = make_float2((float)v.re, (float)v.im);
+      p = zmul(p, zr_);
+    }
+    return;
+  }
+  zd j[P];
+  const zd iz = zinv(z), sn = zsin(z), cs = zcos(z);
+  const zd j0 = zmul(sn, iz), j1 = zmul(zsub(zmul(sn, iz), cs), iz);
+  const int N = P + 16 + (int)az;
+  zd fp1 = {0.0, 0.0}, f = {1e-30, 0.0};
+  for (int n = N; n > P; --n) {
+    const zd fm1 = zsub(zscale(zmul(iz, f), 2.0 * n + 1.0), fp1);
+    fp1 = f;
+    f = fm1;
+  }
+#pragma unroll
+  for (int n = P; n >= 1; --n) {
+    const zd fm1 = zsub(zscale(zmul(iz, f), 2.0 * n + 1.0), fp1);
+    fp1 = f;
+    f = fm1;
+    j[n - 1] = f;
+  }
+  const zd sc = (zabs2(j0) >= zabs2(j1)) ? zmul(j0, zinv(f)) : zmul(j1, zinv(fp1));
+  double df = 1.0, rp = 1.0;
+#pragma unroll
+  for (int n = 0; n < P; ++n) {
+    df *= (2.0 * n + 1.0);
+    const zd v = zscale(zmul(j[n], sc), df / rp);
+    b[n] = make_float2((float)v.re, (float)v.im);
+    rp *= rho;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // P2M: one wave per leaf, up to 32 bodies per pass (keeps the LDS per wave
 // small enough for several waves per SIMD).
 // Mt_n^m = sum_j q_j b_n(k r_j) conj(Y_n^m(dir_j)), Mt_n^{-m} = sum_j q_j b_n Y_n^m.
+// DAMP: complex wavenumber, so b_n is complex and is not conjugated with Y.
 // ---------------------------------------------------------------------------
-template <int P>
+template <int P, bool DAMP>
 __global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items, const InstDev* __restrict__ insts) {
   constexpr int NY = P * (P + 1) / 2, P2 = P * P;
   const int2 it = items[blockIdx.x];
@@ -367,6 +492,7 @@ __global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items, cons
   constexpr int CH = 32;
   __shared__ float2 sa[CH][NY];
   __shared__ float2 sq[CH];
+  __shared__ float2 sb[DAMP ? CH : 1][DAMP ? P : 1];
   const int lane = threadIdx.x;
   float2 acc[4];
 #pragma unroll
@@ -377,12 +503,17 @@ __global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items, cons
       const float4 p = I.spos[j0 + lane];
       const float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
       const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-      float b[P];
-      radial_scaled<P>((double)k * (double)r, rh, b);
       float2* a = sa[lane];
-      ylm_visit<P>(dx, dy, dz, r, [&](int n, int m, float2 y) {
-        a[n * (n + 1) / 2 + m] = make_float2(y.x * b[n], y.y * b[n]);
-      });
+      if constexpr (DAMP) {
+        radial_scaled_c<P>((double)k * (double)r, (double)I.ki * (double)r, rh, sb[lane]);
+        ylm_visit<P>(dx, dy, dz, r, [&](int n, int m, float2 y) { a[n * (n + 1) / 2 + m] = y; });
+      } else {
+        float b[P];
+        radial_scaled<P>((double)k * (double)r, rh, b);
+        ylm_visit<P>(dx, dy, dz, r, [&](int n, int m, float2 y) {
+          a[n * (n + 1) / 2 + m] = make_float2(y.x * b[n], y.y * b[n]);
+        });
+      }
       sq[lane] = I.q[j0 + lane];
     }
     __syncthreads();
@@ -398,6 +529,7 @@ __global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items, cons
         for (int j = 0; j < nj; ++j) {
           float2 y = sa[j][ai];
           y.y *= sgn;
+          if constexpr (DAMP) y = cmul(sb[j][n], y);
           s = cfma(sq[j], y, s);
         }
         acc[t] = s;
@@ -823,7 +955,7 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ ite
 // while the harmonics are generated.  Writes (not accumulates) the sorted
 // output.
 // ---------------------------------------------------------------------------
-template <int P>
+template <int P, bool DAMP>
 __global__ void __launch_bounds__(64) k_l2p(const int2* __restrict__ items, const InstDev* __restrict__ insts) {
   constexpr int P2 = P * P;
   const int2 it = items[blockIdx.x];
@@ -840,8 +972,12 @@ __global__ void __launch_bounds__(64) k_l2p(const int2* __restrict__ items, cons
     const float4 p = I.tpos[i];
     const float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
     const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-    float b[P];
-    radial_scaled<P>((double)k * (double)r, rh, b);
+    float b[DAMP ? 1 : P];
+    float2 bc[DAMP ? P : 1];
+    if constexpr (DAMP)
+      radial_scaled_c<P>((double)k * (double)r, (double)I.ki * (double)r, rh, bc);
+    else
+      radial_scaled<P>((double)k * (double)r, rh, b);
     float2 u[P];
 #pragma unroll
     for (int n = 0; n < P; ++n) u[n] = make_float2(0.f, 0.f);
@@ -854,12 +990,19 @@ __global__ void __launch_bounds__(64) k_l2p(const int2* __restrict__ items, cons
       }
     });
     float2 s = make_float2(0.f, 0.f);
+    if constexpr (DAMP) {
 #pragma unroll
-    for (int n = 0; n < P; ++n) {
-      s.x = fmaf(b[n], u[n].x, s.x);
-      s.y = fmaf(b[n], u[n].y, s.y);
+      for (int n = 0; n < P; ++n) s = cfma(bc[n], u[n], s);
+      // times i (k + i ki) = -ki + i k
+      I.ys[i] = make_float2(-I.ki * s.x - k * s.y, k * s.x - I.ki * s.y);
+    } else {
+#pragma unroll
+      for (int n = 0; n < P; ++n) {
+        s.x = fmaf(b[n], u[n].x, s.x);
+        s.y = fmaf(b[n], u[n].y, s.y);
+      }
+      I.ys[i] = make_float2(-k * s.y, k * s.x);  // times i k
     }
-    I.ys[i] = make_float2(-k * s.y, k * s.x);  // times i k
   }
 }
 
@@ -893,6 +1036,9 @@ __device__ inline void p2p_fetch(const int2* __restrict__ ivals, int iv, int ie,
   w = make_float2(0.f, 0.f);
 }
 
+// DAMP: complex wavenumber k + i ki, G times the decay e^{-ki R} (the
+// imaginary wavenumber of the listing's exponential).
+template <bool DAMP>
 __global__ void __launch_bounds__(256) k_p2p(const int2* __restrict__ items, int nitems,
                                              const InstDev* __restrict__ insts) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -909,6 +1055,7 @@ __global__ void __launch_bounds__(256) k_p2p(const int2* __restrict__ items, int
   const float4* __restrict__ spos = I.spos;
   const float2* __restrict__ q = I.q;
   const float krev = I.k * 0.15915494309189535f;  // k / (2 pi)
+  const float kdec = -I.ki * 1.4426950408889634f;  // -ki log2(e): decay 2^(kdec R)
   for (int t0 = wk.x; t0 < wk.y; t0 += 64) {
     const int tc = min(64, wk.y - t0);
     const int np = (tc + 1) >> 1;                 // target pairs
@@ -948,6 +1095,7 @@ __global__ void __launch_bounds__(256) k_p2p(const int2* __restrict__ items, int
             float rinv = (r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
             float rev = r2 * rinv * krev;
             float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
+            if constexpr (DAMP) rinv *= __builtin_amdgcn_exp2f(r2 * rinv * kdec);
             float gr = cs * rinv, gi = sn * rinv;
             ar = fmaf(qj.x, gr, fmaf(-qj.y, gi, ar));
             ai = fmaf(qj.x, gi, fmaf(qj.y, gr, ai));
@@ -958,6 +1106,7 @@ __global__ void __launch_bounds__(256) k_p2p(const int2* __restrict__ items, int
             float rinv = (r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
             float rev = r2 * rinv * krev;
             float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
+            if constexpr (DAMP) rinv *= __builtin_amdgcn_exp2f(r2 * rinv * kdec);
             float gr = cs * rinv, gi = sn * rinv;
             br = fmaf(qj.x, gr, fmaf(-qj.y, gi, br));
             bi = fmaf(qj.x, gi, fmaf(qj.y, gr, bi));
@@ -1005,20 +1154,20 @@ void table_dims(int P, int* Kp, int* Rp) {
   *Kp = 4 * ((P * P + 3) / 4);
   *Rp = 16 * ((P * P + 15) / 16);
 }
-void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
+void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, double ki, const int32_t* cp_off,
                        const int32_t* cp_lm, const double2* cp_val, float2* tables,
                        hipStream_t s) {
   if (nops <= 0) return;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  k_gen_tables<float2><<<nops, 256, 0, s>>>(ops, nops, P, k, cp_off, cp_lm, cp_val, Kp, Rp, tables);
+  k_gen_tables<float2><<<nops, 256, 0, s>>>(ops, nops, P, k, ki, cp_off, cp_lm, cp_val, Kp, Rp, tables);
 }
 void launch_gen_tables64(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
                          const int32_t* cp_lm, const double2* cp_val, double2* tables, hipStream_t s) {
   if (nops <= 0) return;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  k_gen_tables<double2><<<nops, 256, 0, s>>>(ops, nops, P, k, cp_off, cp_lm, cp_val, Kp, Rp, tables);
+  k_gen_tables<double2><<<nops, 256, 0, s>>>(ops, nops, P, k, 0.0, cp_off, cp_lm, cp_val, Kp, Rp, tables);
 }
 int elem_chunk() { return kChunk; }
 void launch_set_xy(int count, int base, const XYPtrs& p, InstDev* insts, hipStream_t s) {
@@ -1035,11 +1184,16 @@ void launch_scatter(const int2* items, int n, const InstDev* insts, hipStream_t 
 }
 #define HFMM_P_CASES(X) \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
-void launch_p2m(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
+void launch_p2m(const int2* items, int n, const InstDev* insts, int P, bool damped, hipStream_t s) {
   if (n <= 0) return;
   switch (P) {
-#define X(p) \
-  case p: k_p2m<p><<<n, 64, 0, s>>>(items, insts); break;
+#define X(p)                                                           \
+  case p:                                                              \
+    if (damped)                                                        \
+      k_p2m<p, true><<<n, 64, 0, s>>>(items, insts);                   \
+    else                                                               \
+      k_p2m<p, false><<<n, 64, 0, s>>>(items, insts);                  \
+    break;
     HFMM_P_CASES(X)
 #undef X
     default: break;
@@ -1068,11 +1222,16 @@ void launch_m2m(const int4* items, int n, const int32_t* cols, const InstDev* in
 void launch_l2l(const int4* items, int n, const int32_t* cols, const InstDev* insts, int P, hipStream_t s) {
   launch_tr<1>(items, n, cols, insts, P, s);
 }
-void launch_l2p(const int2* items, int n, const InstDev* insts, int P, hipStream_t s) {
+void launch_l2p(const int2* items, int n, const InstDev* insts, int P, bool damped, hipStream_t s) {
   if (n <= 0) return;
   switch (P) {
-#define X(p) \
-  case p: k_l2p<p><<<n, 64, 0, s>>>(items, insts); break;
+#define X(p)                                                           \
+  case p:                                                              \
+    if (damped)                                                        \
+      k_l2p<p, true><<<n, 64, 0, s>>>(items, insts);                   \
+    else                                                               \
+      k_l2p<p, false><<<n, 64, 0, s>>>(items, insts);                  \
+    break;
     HFMM_P_CASES(X)
 #undef X
     default: break;
@@ -1086,8 +1245,12 @@ void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int
   const size_t lds = (16 * (size_t)P * P + kRedGroup) * sizeof(int);
   if (n > 0) k_m2l_reduce<<<n, nth, lds, s>>>(items, insts, omap, P * P, Rp, slot_base);
 }
-void launch_p2p(const int2* items, int n, const InstDev* insts, hipStream_t s) {
-  if (n > 0) k_p2p<<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
+void launch_p2p(const int2* items, int n, const InstDev* insts, bool damped, hipStream_t s) {
+  if (n <= 0) return;
+  if (damped)
+    k_p2p<true><<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
+  else
+    k_p2p<false><<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
 }
 
 template <int P, int NCT, int WPE, int CPW, int AD>

@@ -129,6 +129,7 @@ int hfmm_matvec64(hfmm_tree* tree, double k, int32_t P, const void* x_dev, void*
     if (rc) return rc;
     Tree& t = *reinterpret_cast<Tree*>(tree);
     if (t.bie) return set_error("the FP64 variant takes point-mode handles"), HFMM_EINVAL;
+    if (t.k_imag != 0.0) return set_error("the FP64 variant takes a real wavenumber"), HFMM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     Plan* pl;
     if ((rc = prepare(t, k, P, s, &pl))) return rc;

@@ -162,6 +162,7 @@ struct Plan {
   DevBuf d_near_val;                            // float2 per near nonzero
   DevBuf d_diag;                                // double2: self integral - 3-point self sum
   DevBuf d_self6;                               // double2 [points][6]: curved-element self blocks
+  double ki = 0.0;                              // imaginary part of the wavenumber
   int64_t n_near = 0;
   int64_t device_bytes = 0;
   int64_t est_bytes = 0;                 // footprint computed before any allocation
@@ -181,6 +182,7 @@ struct Plan64 {
 // Fused execution of one or more instances (instance-aware kernels).
 struct Batch {
   int count = 0, P = 0, maxlev = 0;
+  bool damped = false;                // some instance has a complex wavenumber
   std::vector<struct Tree*> trees;
   std::vector<Plan*> plans;
   std::vector<InstDev> hinst;
@@ -217,6 +219,7 @@ struct Tree {
   HostTree h;                   // bodies and base cells
   int ncrit = 64, max_level = 20;
   double theta = 0.5, kappa = -1.0, eta = 2.0;
+  double k_imag = 0.0;          // imaginary part of the wavenumber (damping), point handles
   int64_t stage_bytes = int64_t(32) << 30;  // M2L staging budget
   int bie_treatment = 0;        // 0: self + near corrections, 1: self only, 2: none
   int near_levels = 3, near_order = 6;

@@ -194,12 +194,12 @@ int prepare_nystrom(Tree& t, Plan& pl, hipStream_t s) {
   const NysConst* K = t.d_nys_K.as<NysConst>();
   if (t.bie_treatment == 0)
     launch_nys_near((int64_t)t.nys_items.size(), t.d_nys_items.as<int4>(), t.d_nys_pts.as<double>(),
-                    t.d_nys_elem.as<double>(), K, t.d_nys_rule.as<double>(), t.nys_nrule, pl.k,
+                    t.d_nys_elem.as<double>(), K, t.d_nys_rule.as<double>(), t.nys_nrule, pl.k, pl.ki,
                     pl.d_near_val.as<float2>(), s);
   else
     HIP_TRY(hipMemsetAsync(pl.d_near_val.p, 0, pl.d_near_val.bytes, s));
   if (t.bie_treatment <= 1)
-    launch_nys_self(N, t.d_nys_pts.as<double>(), t.d_nys_elem.as<double>(), K, kNysSelfOrder, pl.k,
+    launch_nys_self(N, t.d_nys_pts.as<double>(), t.d_nys_elem.as<double>(), K, kNysSelfOrder, pl.k, pl.ki,
                     pl.d_self6.as<double2>(), s);
   else
     HIP_TRY(hipMemsetAsync(pl.d_self6.p, 0, pl.d_self6.bytes, s));
@@ -232,6 +232,7 @@ int hfmm_build_nystrom(const double* nodes, int64_t nn, const int32_t* tri6, int
         o->near_levels < 0 || o->near_levels > 5 || o->near_order < 1 || o->near_order > 16 ||
         o->bie_treatment < 0 || o->bie_treatment > 2)
       return set_error("invalid options"), HFMM_EINVAL;
+    if (!(o->k_imag >= 0.0) || !std::isfinite(o->k_imag)) return set_error("k_imag must be finite and >= 0"), HFMM_EINVAL;
     auto t = std::make_unique<Tree>();
     t->ncrit = o->ncrit;
     t->max_level = o->max_level;
@@ -242,6 +243,7 @@ int hfmm_build_nystrom(const double* nodes, int64_t nn, const int32_t* tri6, int
     t->near_order = o->near_order;
     t->stage_bytes = (int64_t)(o->stage_mb > 0 ? o->stage_mb : 32768) << 20;
     t->bie_treatment = o->bie_treatment;
+    t->k_imag = o->k_imag;
     t->bie = true;
     t->nystrom = true;
     const int64_t N = 6 * nt;

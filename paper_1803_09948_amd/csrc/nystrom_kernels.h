@@ -21,14 +21,16 @@ struct NysConst {
 };
 
 // items: (target point, element, position of its six values in val, -)
+// k + i ki: the wavenumber (ki >= 0 damps)
 void launch_nys_near(int64_t nitems, const int4* items, const double* pts, const double* elem, const NysConst* K,
-                     const double* rule, int nrule, double k, float2* val, hipStream_t s);
+                     const double* rule, int nrule, double k, double ki, float2* val, hipStream_t s);
 // self6[6 j + i] for every point j (n x n points per Duffy part, n <= kNysMaxGauss)
 void launch_nys_self(int64_t npts, const double* pts, const double* elem, const NysConst* K, int n, double k,
-                     double2* self6, hipStream_t s);
+                     double ki, double2* self6, hipStream_t s);
 void launch_self6_apply_c64(int64_t n, const double2* S, const float2* x, float2* y, hipStream_t s);
 void launch_from_c64_self6(int64_t n, const float2* y, const double2* S, const double2* v, double2* out,
                            hipStream_t s);
-void launch_plane_wave_pts(int64_t n, const double* pts, double k, const double* d, double2* b, hipStream_t s);
+void launch_plane_wave_pts(int64_t n, const double* pts, double k, double ki, const double* d, double2* b,
+                           hipStream_t s);
 
 }  // namespace hfmm

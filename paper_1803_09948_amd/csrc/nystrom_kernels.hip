@@ -76,11 +76,12 @@ __device__ inline void lagr(const double* C, double u, double v, double* L) {
   }
 }
 
-__device__ inline double2 green(double k, v3 x, v3 y) {
+// G for the wavenumber k + i ki
+__device__ inline double2 green(double k, double ki, v3 x, v3 y) {
   const double R = sqrt(vdot(vsub(x, y), vsub(x, y)));
   double s, c;
   sincos(k * R, &s, &c);
-  const double f = 1.0 / (4.0 * M_PI * R);
+  const double f = exp(-ki * R) / (4.0 * M_PI * R);
   return make_double2(c * f, s * f);
 }
 
@@ -99,11 +100,12 @@ __device__ inline void wave_sum12(double* acc, double (*red)[64], int lane) {
 }
 
 // rule terms w_i G(r_j, r_ie) the FMM holds for element e (R > 0 only)
-__device__ inline void subtract_rule(const NysConst* K, const double* X, double k, v3 x, int skip, double* acc) {
+__device__ inline void subtract_rule(const NysConst* K, const double* X, double k, double ki, v3 x, int skip,
+                                     double* acc) {
   for (int i = 0; i < 6; ++i) {
     if (i == skip) continue;
     const v3 y = qmap(X, K->uv[2 * i], K->uv[2 * i + 1]);
-    const double2 g = green(k, x, y);
+    const double2 g = green(k, ki, x, y);
     acc[2 * i] -= K->w[i] * g.x;
     acc[2 * i + 1] -= K->w[i] * g.y;
   }
@@ -116,7 +118,8 @@ __device__ inline void subtract_rule(const NysConst* K, const double* X, double 
 __global__ void __launch_bounds__(256) k_nys_near(int64_t nitems, const int4* __restrict__ items,
                                                   const double* __restrict__ pts, const double* __restrict__ elem,
                                                   const NysConst* __restrict__ K, const double* __restrict__ rule,
-                                                  int nrule, double k, float2* __restrict__ val) {
+                                                  int nrule, double k, double ki,
+                                                  float2* __restrict__ val) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __shared__ double red[4][12][64];
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
@@ -128,7 +131,7 @@ __global__ void __launch_bounds__(256) k_nys_near(int64_t nitems, const int4* __
   for (int c = 0; c < 12; ++c) acc[c] = 0.0;
   for (int q = lane; q < nrule; q += 64) {
     const double u = rule[3 * q], v = rule[3 * q + 1], wq = rule[3 * q + 2];
-    const double2 g = green(k, x, qmap(X, u, v));
+    const double2 g = green(k, ki, x, qmap(X, u, v));
     double L[6];
     lagr(K->lagr, u, v, L);
     for (int i = 0; i < 6; ++i) {
@@ -138,7 +141,7 @@ __global__ void __launch_bounds__(256) k_nys_near(int64_t nitems, const int4* __
   }
   wave_sum12(acc, red[wave], lane);
   if (lane == 0) {
-    subtract_rule(K, X, k, x, -1, acc);
+    subtract_rule(K, X, k, ki, x, -1, acc);
     for (int i = 0; i < 6; ++i) val[w.z + i] = make_float2((float)acc[2 * i], (float)acc[2 * i + 1]);
   }
 }
@@ -148,7 +151,7 @@ __global__ void __launch_bounds__(256) k_nys_near(int64_t nitems, const int4* __
 // part), minus the rule terms of the element's other points.
 __global__ void __launch_bounds__(256) k_nys_self(int64_t npts, const double* __restrict__ pts,
                                                   const double* __restrict__ elem, const NysConst* __restrict__ K,
-                                                  int n, double k, double2* __restrict__ self6) {
+                                                  int n, double k, double ki, double2* __restrict__ self6) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __shared__ double red[4][12][64];
   const int64_t j = (int64_t)blockIdx.x * 4 + wave;
@@ -190,7 +193,7 @@ __global__ void __launch_bounds__(256) k_nys_self(int64_t npts, const double* __
     const double wt = (H / B) * mu * ch * K->gw[ib];
     const double wq = K->gw[ia] * wt * s * det;
     const double u = pu + s * (e0u + t * eu), v = pv + s * (e0v + t * ev);
-    const double2 g = green(k, x, qmap(X, u, v));
+    const double2 g = green(k, ki, x, qmap(X, u, v));
     double L[6];
     lagr(K->lagr, u, v, L);
     for (int i = 0; i < 6; ++i) {
@@ -200,7 +203,7 @@ __global__ void __launch_bounds__(256) k_nys_self(int64_t npts, const double* __
   }
   wave_sum12(acc, red[wave], lane);
   if (lane == 0) {
-    subtract_rule(K, X, k, x, jl, acc);
+    subtract_rule(K, X, k, ki, x, jl, acc);
     for (int i = 0; i < 6; ++i) self6[6 * j + i] = make_double2(acc[2 * i], acc[2 * i + 1]);
   }
 }
@@ -238,22 +241,25 @@ __global__ void k_from_c64_self6(int64_t n, const float2* __restrict__ y, const 
 }
 
 // b_j = exp(i k d . r_j)
-__global__ void k_plane_wave_pts(int64_t n, const double* __restrict__ pts, double k, double dx, double dy,
-                                 double dz, double2* __restrict__ b) {
+__global__ void k_plane_wave_pts(int64_t n, const double* __restrict__ pts, double k, double ki, double dx,
+                                 double dy, double dz, double2* __restrict__ b) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  const double ph = dx * pts[3 * j] + dy * pts[3 * j + 1] + dz * pts[3 * j + 2];
   double s, c;
-  sincos(k * (dx * pts[3 * j] + dy * pts[3 * j + 1] + dz * pts[3 * j + 2]), &s, &c);
-  b[j] = make_double2(c, s);
+  sincos(k * ph, &s, &c);
+  const double a = exp(-ki * ph);
+  b[j] = make_double2(a * c, a * s);
 }
 
 void launch_nys_near(int64_t nitems, const int4* items, const double* pts, const double* elem, const NysConst* K,
-                     const double* rule, int nrule, double k, float2* val, hipStream_t s) {
-  if (nitems > 0) k_nys_near<<<(nitems + 3) / 4, 256, 0, s>>>(nitems, items, pts, elem, K, rule, nrule, k, val);
+                     const double* rule, int nrule, double k, double ki, float2* val, hipStream_t s) {
+  if (nitems > 0)
+    k_nys_near<<<(nitems + 3) / 4, 256, 0, s>>>(nitems, items, pts, elem, K, rule, nrule, k, ki, val);
 }
 void launch_nys_self(int64_t npts, const double* pts, const double* elem, const NysConst* K, int n, double k,
-                     double2* self6, hipStream_t s) {
-  if (npts > 0) k_nys_self<<<(npts + 3) / 4, 256, 0, s>>>(npts, pts, elem, K, n, k, self6);
+                     double ki, double2* self6, hipStream_t s) {
+  if (npts > 0) k_nys_self<<<(npts + 3) / 4, 256, 0, s>>>(npts, pts, elem, K, n, k, ki, self6);
 }
 void launch_self6_apply_c64(int64_t n, const double2* S, const float2* x, float2* y, hipStream_t s) {
   if (n > 0) k_self6_apply_c64<<<(n + 255) / 256, 256, 0, s>>>(n, S, x, y);
@@ -262,8 +268,9 @@ void launch_from_c64_self6(int64_t n, const float2* y, const double2* S, const d
                            hipStream_t s) {
   if (n > 0) k_from_c64_self6<<<(n + 255) / 256, 256, 0, s>>>(n, y, S, v, out);
 }
-void launch_plane_wave_pts(int64_t n, const double* pts, double k, const double* d, double2* b, hipStream_t s) {
-  if (n > 0) k_plane_wave_pts<<<(n + 255) / 256, 256, 0, s>>>(n, pts, k, d[0], d[1], d[2], b);
+void launch_plane_wave_pts(int64_t n, const double* pts, double k, double ki, const double* d, double2* b,
+                           hipStream_t s) {
+  if (n > 0) k_plane_wave_pts<<<(n + 255) / 256, 256, 0, s>>>(n, pts, k, ki, d[0], d[1], d[2], b);
 }
 
 }  // namespace hfmm

@@ -33,7 +33,7 @@ class Opts(C.Structure):
     _fields_ = [("ncrit", C.c_int32), ("max_level", C.c_int32), ("theta", C.c_double),
                 ("kappa", C.c_double), ("eta", C.c_double), ("near_levels", C.c_int32),
                 ("near_order", C.c_int32), ("stage_mb", C.c_int32), ("bie_treatment", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("k_imag", C.c_double), ("reserved", C.c_int32 * 4)]
 
 
 class Stats(C.Structure):

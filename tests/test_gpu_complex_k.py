@@ -1,0 +1,93 @@
+"""GPU parity of the point-mode FMM at a complex wavenumber k + i k_imag
+(damped waves) against the FP64 oracle FMM at the same tree, lists and P."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.fmm import FMM, direct_sum
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1803_09948_amd import hfmm  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("n,k,ki,P,seed", [
+    (3000, 4.0, 1.5, 8, 61),     # moderate damping
+    (2500, 9.0, 4.0, 10, 62),    # strong damping, wavelength rule on |k|
+    (2000, 2.0, 1e-3, 6, 63),    # nearly real, near-zero radial arguments
+])
+def test_matvec_vs_oracle_fmm(n, k, ki, P, seed):
+    x = synth.sphere_points(n, seed)
+    q = synth.strengths(n, seed)
+    print(f"case n={n} k={k}+{ki}i P={P}", flush=True)
+    t = hfmm.Tree.from_points(x, ncrit=32, k_imag=ki)
+    y = t.matvec(k, P, torch.from_numpy(q).to("cuda")).cpu().numpy()
+    yo = FMM(x, k=k, k_imag=ki, P=P, ncrit=32).matvec(q)
+    e = rel(y, yo)
+    ed = rel(yo, direct_sum(complex(k, ki), x, x, q))
+    print(f"  gpu vs oracle FMM {e:.2e}; oracle FMM vs direct {ed:.2e}")
+    assert np.all(np.isfinite(y)) and e <= 1e-5
+
+
+def test_batch_mixes_damped_and_real_instances():
+    """One fused sequence over real and complex wavenumbers: every result is
+    bitwise the instance's own product."""
+    inst = synth.batch_instances(count=4, nmin=1024, nmax=4096, seed=17)
+    kis = [0.0, 0.8, 0.0, 2.5]
+    trees = [hfmm.Tree.from_points(d["points"], k_imag=ki) for d, ki in zip(inst, kis)]
+    ks = [d["k"] for d in inst]
+    xs = [torch.from_numpy(d["q"]).to("cuda") for d in inst]
+    ys = [torch.empty_like(x) for x in xs]
+    hfmm.batch_matvec(trees, ks, [10] * 4, xs, ys)
+    torch.cuda.synchronize()
+    for i in range(4):
+        alone = trees[i].matvec(ks[i], 10, xs[i]).cpu().numpy()
+        np.testing.assert_array_equal(ys[i].cpu().numpy(), alone, err_msg=f"instance {i}")
+
+
+def test_fp64_variant_refuses_complex_wavenumber():
+    x = synth.sphere_points(500, 3)
+    t = hfmm.Tree.from_points(x, k_imag=0.5)
+    with pytest.raises(hfmm.HfmmError):
+        t.matvec64(2.0, 6, torch.from_numpy(synth.strengths(500, 3).astype(np.complex128)).to("cuda"))
+
+
+def test_flat_bie_matvec_and_rhs_vs_dense_oracle():
+    """Flat-panel BIE handle at k = 3 + 1i: the product (FMM + near and self
+    corrections) and the damped plane wave against the oracle."""
+    from oracle import bie
+    V, T = synth.icosphere(2)
+    k, ki = 3.0, 1.0
+    A = bie.dense_matrix(complex(k, ki), V, T)
+    q = synth.strengths(len(T), 71)
+    t = hfmm.Tree.from_mesh(V, T, k_imag=ki)
+    y = t.matvec(k, 10, torch.from_numpy(q).to("cuda")).cpu().numpy()
+    e = rel(y, A @ q.astype(np.complex128))
+    b = t.plane_wave(k).cpu().numpy()
+    eb = rel(b, bie.plane_wave_rhs(complex(k, ki), V, T))
+    print("flat bie complex k: matvec", e, "rhs", eb)
+    assert e <= 1e-5 and eb <= 1e-14
+
+
+def test_nystrom_matvec_and_solve_vs_dense_oracle():
+    """Curved Nystrom handle at k = 3 + 1i: the product against the oracle's
+    dense matrix and GMRES against a dense solve."""
+    from oracle import nystrom as ny
+    nodes, tri6 = synth.curved_icosphere(1)
+    k, ki = 3.0, 1.0
+    Z = ny.dense_matrix(complex(k, ki), nodes, tri6, L=3, n_near=6, n_self=10)
+    t = hfmm.Tree.from_curved_mesh(nodes, tri6, ncrit=16, k_imag=ki)
+    rng = np.random.default_rng(8)
+    x = (rng.uniform(-1, 1, len(Z)) + 1j * rng.uniform(-1, 1, len(Z))).astype(np.complex64)
+    y = t.matvec(k, 10, torch.from_numpy(x).to("cuda")).cpu().numpy()
+    e = rel(y, Z @ x.astype(np.complex128))
+    b = t.plane_wave(k)
+    xs, info = t.gmres(k, 10, b, tol=1e-6, restart=30, maxit=500)
+    es = rel(xs.cpu().numpy(), np.linalg.solve(Z, ny.plane_wave_rhs(complex(k, ki), nodes, tri6)))
+    print("nystrom complex k: matvec", e, "solve", es, info["iters"])
+    assert e <= 1e-5 and es <= 1e-4

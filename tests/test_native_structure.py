@@ -132,3 +132,28 @@ def test_nystrom_invalid_mesh():
     V, T = synth.icosphere(1)
     with pytest.raises(hfmm.HfmmError):
         hfmm.Tree.from_mesh(V, T).nystrom_points()
+
+
+def test_complex_wavenumber_lists_and_options():
+    """k + i k_imag: cells and lists follow |k + i k_imag| exactly as the
+    oracle's; negative or non-finite k_imag is refused on every handle."""
+    from oracle.fmm import FMM
+    x = synth.sphere_points(2500, 8)
+    k, ki, P = 9.0, 4.0, 8
+    t = hfmm.Tree.from_points(x, ncrit=32, k_imag=ki)
+    m2l, p2p = t.lists(k, P)
+    f = FMM(x, k=k, k_imag=ki, P=P, ncrit=32)
+    assert sorted(map(tuple, m2l.tolist())) == sorted(f.m2l)
+    assert sorted(map(tuple, p2p.tolist())) == sorted(f.p2p)
+    # the rules see |k + i k_imag| only: the lists equal those of the real |k|
+    m2l_abs, _ = hfmm.Tree.from_points(x, ncrit=32).lists(float(np.hypot(k, ki)), P)
+    np.testing.assert_array_equal(m2l, m2l_abs)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(hfmm.HfmmError):
+            hfmm.Tree.from_points(x, k_imag=bad)
+    V, T = synth.icosphere(1)
+    hfmm.Tree.from_mesh(V, T, k_imag=0.5).free()
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.Tree.from_mesh(V, T, k_imag=-0.5)
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.Tree.from_curved_mesh(*synth.curved_icosphere(1), k_imag=-0.5)
