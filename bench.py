@@ -447,6 +447,7 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--P", type=int, default=10)
     ap.add_argument("--k", type=float, default=16.0 * math.pi)
+    ap.add_argument("--k-imag", type=float, default=0.0, help="imaginary part of the wavenumber (damped waves)")
     ap.add_argument("--ncrit", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare 200 sampled outputs with the FP64 direct sum")
@@ -479,7 +480,7 @@ def main():
     x = synth.sphere_points(a.n, 23)
     q = synth.strengths(a.n, 23)
     t0 = time.perf_counter()
-    tree = hfmm.Tree.from_points(x, ncrit=a.ncrit)
+    tree = hfmm.Tree.from_points(x, ncrit=a.ncrit, k_imag=a.k_imag)
     t_tree = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
@@ -550,8 +551,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"helmholtz FMM matvec, N={a.n} uniform on the unit sphere, k={a.k:.6g} "
-                               f"(16 wavelengths across), P={a.P}, ncrit={a.ncrit}, theta=0.5, kappa=0.4P",
-                   "n": a.n, "k": a.k, "P": a.P, "ncrit": a.ncrit},
+                               f"(16 wavelengths across)" + (f" + {a.k_imag:g}i (damped)" if a.k_imag else "") +
+                               f", P={a.P}, ncrit={a.ncrit}, theta=0.5, kappa=0.4P",
+                   "n": a.n, "k": a.k, "k_imag": a.k_imag, "P": a.P, "ncrit": a.ncrit},
         "roofline": roof,
         "phases_ms": phases,
         "secondary": {"p2p_tflops": p2p_ach / 1e12, "p2p_gpairs_per_s": st["p2p_body_pairs"] / phases["p2p"] / 1e6,
@@ -559,7 +561,7 @@ def main():
                       "n_tables": st["n_tables"], "setup_s": {"tree": t_tree, "prepare": t_prep},
                       "m2l_shapes": {"tuned": tuned, "ms": shape_ms}},
     }
-    if a.check:
+    if a.check and not a.k_imag:
         # the library's FP64 direct sum on the GPU over all sources, 200 targets
         rng = np.random.default_rng(1)
         idx = torch.from_numpy(np.sort(rng.choice(a.n, 200, replace=False))).to(dev)
