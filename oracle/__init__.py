@@ -19,8 +19,8 @@ Modules
   gmres     dense restarted GMRES with modified Gram-Schmidt
   mie       Mie series for the sound-soft sphere (Sec. 6.4 observable)
 
-Readings of the paper where it is silent or ambiguous are listed in the design doc
-of the repository; each function states the reading it implements.
+Where the paper is silent or ambiguous, each function states the reading it
+implements.
 
 Parity status: every function here is pinned by a CPU test against a closed
 form, an identity, brute force or a special case (tests/test_oracle_*.py);

@@ -5,7 +5,7 @@ Written from Sec. 2.3 (octree, upward/traverse/downward passes), Sec. 3.1
 bodies) and Sec. 3.2 (keys from cell positions; the dual tree traversal walks
 source and target trees together).  The paper leaves the box, the keys' bit
 layout, the split rule and the acceptance criterion unspecified; the readings
-implemented here (restated in the design doc) are:
+implemented here are:
 
 * Root cube.  he = max over axes of (max - min)/2 of all points (sources and
   targets); he = 1 if that is 0.  q = largest power of two <= he/64.  Centre

@@ -123,7 +123,7 @@ def curved_icosphere(subdiv: int, radius: float = 1.0):
 
 
 # --------------------------------------------------------------------------
-# Workloads (sizes and parameters; the recipe is restated in the design doc)
+# Workloads (sizes and parameters of the benchmark and test configurations)
 # --------------------------------------------------------------------------
 @dataclass(frozen=True)
 class Workload:
