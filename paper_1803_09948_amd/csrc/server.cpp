@@ -16,6 +16,7 @@
 #include <map>
 
 #include "bie_kernels.h"
+#include "nystrom_kernels.h"
 #include "hfmm_internal.h"
 
 namespace hfmm {
@@ -194,7 +195,10 @@ static int step(Server& sv, hipStream_t s) {
     double2* out = v.phase == PH_RESIDUAL ? v.r.as<double2>() : v.w.as<double2>();
     launch_near_apply(n, t.d_near_off.as<int32_t>(), t.d_near_col.as<int32_t>(), pl.d_near_val.as<float2>(),
                       nullptr, v.x64.as<float2>(), v.y64.as<float2>(), s);
-    launch_from_c64_diag(n, v.y64.as<float2>(), pl.d_diag.as<double2>(), in, out, s);
+    if (t.nystrom)  // curved elements: 6 x 6 self blocks in FP64
+      launch_from_c64_self6(n, v.y64.as<float2>(), pl.d_self6.as<double2>(), in, out, s);
+    else
+      launch_from_c64_diag(n, v.y64.as<float2>(), pl.d_diag.as<double2>(), in, out, s);
     if (v.phase == PH_RESIDUAL) {
       launch_residual(n, v.b, out, s);
       launch_mdot(n, 1, out, n, out, v.part.as<double2>(), v.dot.as<double2>(), 0, s);

@@ -47,3 +47,29 @@ def test_admission_by_memory_budget():
     with pytest.raises(hfmm.HfmmError) as e:
         srv.submit(t, 4.0, 10, b, x)
     assert e.value.code == hfmm.HFMM_ENOMEM
+
+
+def test_served_mix_of_flat_and_curved_handles():
+    """Flat-panel and curved-element (Nystrom) handles in one served mix:
+    every solution is bitwise the handle's own plain GMRES solution."""
+    flat = [hfmm.Tree.from_mesh(*synth.icosphere(2)), hfmm.Tree.from_mesh(*synth.icosphere(3))]
+    curved = [hfmm.Tree.from_curved_mesh(*synth.curved_icosphere(1)),
+              hfmm.Tree.from_curved_mesh(*synth.curved_icosphere(2))]
+    trees = flat + curved
+    ks = [3.0, 4.5, 2.0, 6.0]
+    bs = [t.plane_wave(k) for t, k in zip(trees, ks)]
+    alone = [t.gmres(k, 10, b, tol=1e-5)[0].cpu().numpy() for t, k, b in zip(trees, ks, bs)]
+    srv = hfmm.Server(max_active=4)
+    xs = [torch.zeros_like(b) for b in bs]
+    tickets = [srv.submit(t, k, 10, b, x, tol=1e-5)[0] for t, k, b, x in zip(trees, ks, bs, xs)]
+    for _ in range(100000):
+        na, nq = srv.step()
+        if na == 0 and nq == 0:
+            break
+    torch.cuda.synchronize()
+    for i, tk in enumerate(tickets):
+        state, info, _ = srv.poll(tk)
+        print("request", i, "state", state, "iters", info["iters"])
+        assert state == hfmm.Server.CONVERGED
+        np.testing.assert_array_equal(xs[i].cpu().numpy(), alone[i], err_msg=f"request {i}")
+    srv.free()
