@@ -161,6 +161,22 @@ def bench_batch(a):
             t.matvec(k, P, x, y)
     torch.cuda.synchronize()
     dt_s = (time.perf_counter() - t0) / a.steps
+    # the fused sequence with each M2L launch shape forced (the graph is
+    # re-captured per shape), against the autotuned choice timed above
+    shape_ms = []
+    try:
+        for v in range(hfmm.variant_count(P)):
+            hfmm.set_variant(v)
+            hfmm.batch_matvec(trees, ks, [P] * len(trees), xs, ys)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(max(1, a.steps // 2)):
+                hfmm.batch_matvec(trees, ks, [P] * len(trees), xs, ys)
+            torch.cuda.synchronize()
+            shape_ms.append(round((time.perf_counter() - t0) / max(1, a.steps // 2) * 1e3, 3))
+    finally:
+        hfmm.set_variant(-1)
+    log("batch ms per forced M2L shape:", shape_ms, "autotuned:", round(dt_b * 1e3, 3))
     out = {
         "metric": "batched FMM matvecs/s (64 instances, one fused graph launch)",
         "value": len(trees) / dt_b, "unit": "matvec/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -171,6 +187,7 @@ def bench_batch(a):
                                "spheres and ellipsoids alternating"},
         "sequential": {"value": len(trees) / dt_s, "ms_per_step": dt_s * 1e3},
         "speedup_vs_sequential": dt_s / dt_b,
+        "m2l_shapes_ms": {"autotuned": dt_b * 1e3, "forced": shape_ms},
     }
     print(json.dumps(out))
 
