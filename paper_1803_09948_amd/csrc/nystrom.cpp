@@ -175,9 +175,17 @@ int prepare_nystrom(Tree& t, Plan& pl, hipStream_t s) {
     }
     lagrange_coeffs(K.lagr);
     gauss01(kNysSelfOrder, K.gx, K.gw);
-    std::vector<NysConst> kv{K};
-    std::vector<double> rule = subdivided_rule(t.near_levels, t.near_order);
+    // near rules of 4^0 .. 4^near_levels sub-triangles, one after the other
+    std::vector<double> rule;
+    K.max_level = t.near_levels;
+    for (int L = 0; L <= t.near_levels; ++L) {
+      std::vector<double> r = subdivided_rule(L, t.near_order);
+      K.rule_off[L] = (int)(rule.size() / 3);
+      K.rule_cnt[L] = (int)(r.size() / 3);
+      rule.insert(rule.end(), r.begin(), r.end());
+    }
     t.nys_nrule = (int)(rule.size() / 3);
+    std::vector<NysConst> kv{K};
     std::vector<int32_t> rows(t.near_col.size());
     for (int64_t i = 0; i < N; ++i)
       for (int q = t.near_off[i]; q < t.near_off[i + 1]; ++q) rows[q] = (int32_t)i;
@@ -194,7 +202,7 @@ int prepare_nystrom(Tree& t, Plan& pl, hipStream_t s) {
   const NysConst* K = t.d_nys_K.as<NysConst>();
   if (t.bie_treatment == 0)
     launch_nys_near((int64_t)t.nys_items.size(), t.d_nys_items.as<int4>(), t.d_nys_pts.as<double>(),
-                    t.d_nys_elem.as<double>(), K, t.d_nys_rule.as<double>(), t.nys_nrule, pl.k, pl.ki,
+                    t.d_nys_elem.as<double>(), K, t.d_nys_rule.as<double>(), pl.k, pl.ki,
                     pl.d_near_val.as<float2>(), s);
   else
     HIP_TRY(hipMemsetAsync(pl.d_near_val.p, 0, pl.d_near_val.bytes, s));

@@ -18,12 +18,15 @@ struct NysConst {
   double w[6];
   double lagr[36];
   double gx[kNysMaxGauss], gw[kNysMaxGauss];
+  int rule_off[6], rule_cnt[6];  // near rule with 4^L sub-triangles: points [off, off + cnt) of the table
+  int max_level;                 // deepest near rule (near_levels)
 };
 
-// items: (target point, element, position of its six values in val, -)
+// items: (target point, element, position of its six values in val, -);
+// rule: the near rules of 4^0 .. 4^max_level sub-triangles, concatenated;
 // k + i ki: the wavenumber (ki >= 0 damps)
 void launch_nys_near(int64_t nitems, const int4* items, const double* pts, const double* elem, const NysConst* K,
-                     const double* rule, int nrule, double k, double ki, float2* val, hipStream_t s);
+                     const double* rule, double k, double ki, float2* val, hipStream_t s);
 // self6[6 j + i] for every point j (n x n points per Duffy part, n <= kNysMaxGauss)
 void launch_nys_self(int64_t npts, const double* pts, const double* elem, const NysConst* K, int n, double k,
                      double ki, double2* self6, hipStream_t s);
