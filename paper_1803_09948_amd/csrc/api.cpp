@@ -267,8 +267,8 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
   pl.n_ops = (int64_t)ops.size();
   // staging slots: pairs ordered by (target, source), so each target's
   // slots are contiguous and summed in a fixed order
-  int Kp0, Rp0;
-  table_dims(P, &Kp0, &Rp0);
+  int Sm0, St0;
+  stage_dims(P, &Sm0, &St0);
   std::vector<int32_t> slot(npair);
   {
     std::vector<int32_t> bytgt(npair);
@@ -293,7 +293,7 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
   std::vector<int32_t> seg_of(h.ncell(), 0);
   pl.m2l_segs.clear();
   {
-    const int64_t budget = std::max<int64_t>(1, t.stage_bytes / ((int64_t)Rp0 * (int64_t)sizeof(float2)));
+    const int64_t budget = std::max<int64_t>(1, t.stage_bytes / ((int64_t)(Sm0 + St0) * (int64_t)sizeof(float2)));
     M2LSeg cur{};
     for (size_t i = 0; i < pl.m2l_targets.size(); ++i) {
       const int c = pl.m2l_targets[i];
@@ -403,12 +403,13 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
   pl.n_ops = (int64_t)ops.size();
   // exact device footprint of this plan (and of the bodies if not yet resident)
   {
-    int Kp, Rp;
+    int Kp, Rp, Sm, St;
     table_dims(P, &Kp, &Rp);
+    stage_dims(P, &Sm, &St);
     const int64_t nc = h.ncell();
     int64_t b = nc * (int64_t)(sizeof(int4) * 2 + sizeof(float4) + sizeof(int32_t) + sizeof(int2));
     b += (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)Kp * Rp * sizeof(float2));
-    b += (int64_t)spairs.size() * 17 + pl.max_seg_slots * (int64_t)Rp * (int64_t)sizeof(float2) + (nc + 1) * 4;
+    b += (int64_t)spairs.size() * 17 + pl.max_seg_slots * (int64_t)(Sm + St) * (int64_t)sizeof(float2) + (nc + 1) * 4;
     b += (int64_t)pl.rho.size() * 8 + (int64_t)spairs.size() * 16 + (int64_t)work.size() * 20 +
          (int64_t)ivals.size() * 8 + (17 * (int64_t)Kp + 16 * P2) * 4 + 2 * nc * P2 * (int64_t)sizeof(float2);
     if (t.bie) b += (int64_t)t.near_col.size() * 8 + t.npanel * (t.nystrom ? 96 : 16);
@@ -429,12 +430,13 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   const HostTree& h = pl.ct;
   const int P = pl.P, P2 = P * P;
   const double k = pl.k;
-  int Kp, Rp;
+  int Kp, Rp, Sm, St;
   table_dims(P, &Kp, &Rp);
+  stage_dims(P, &Sm, &St);
   if ((rc = upload(pl.d_ops, hd.ops)) || (rc = upload(pl.d_rho, pl.rho)) ||
       (rc = upload(pl.d_m2l_pairs, hd.spairs)) || (rc = upload(pl.d_cops, hd.cops)) ||
       (rc = upload(pl.d_m2l_soff, hd.soff)) ||
-      (rc = pl.d_stage.alloc((size_t)std::max<int64_t>(1, pl.max_seg_slots) * (size_t)Rp * sizeof(float2))) ||
+      (rc = pl.d_stage.alloc((size_t)std::max<int64_t>(1, pl.max_seg_slots) * (size_t)(Sm + St) * sizeof(float2))) ||
       (rc = upload(pl.d_p2p_work, hd.work)) || (rc = upload(pl.d_p2p_ivals, hd.ivals)) ||
       (rc = upload(pl.d_p2p_total, hd.totals)))
     return rc;

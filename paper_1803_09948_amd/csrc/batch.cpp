@@ -53,7 +53,12 @@ static InstDev make_inst(Tree& t, Plan& pl) {
   I.M = pl.d_M.as<float2>();
   I.L = pl.d_L.as<float2>();
   I.m2l_pairs = pl.d_m2l_pairs.as<int4>();
-  I.stage = pl.d_stage.as<float2>();
+  {
+    int Sm, St;
+    stage_dims(pl.P, &Sm, &St);
+    I.stage = pl.d_stage.as<float2>();  // [slots][Sm], then the tails [slots][St]
+    I.stage_tail = I.stage + std::max<int64_t>(1, pl.max_seg_slots) * Sm;
+  }
   I.slot_g = pl.d_slot_g.as<uint8_t>();
   I.m2l_soff = pl.d_m2l_soff.as<int32_t>();
   I.p2p_work = pl.d_p2p_work.as<int4>();

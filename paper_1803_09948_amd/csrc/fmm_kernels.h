@@ -18,6 +18,10 @@ struct OpDescDev {         // translation operator descriptor (48 bytes)
 
 // Padded table dimensions: Kp = 4 ceil(P^2/4) inputs, Rp = 16 ceil(P^2/16) outputs.
 void table_dims(int P, int* Kp, int* Rp);
+// Rows of an M2L staging slot: Sm rows in whole 16-row tiles (whole 128-byte
+// lines) and St rows of a partly filled last tile (P^2 mod 16, rounded up to
+// even), kept in a separate dense tail array; St = 0 when 16 divides P^2.
+void stage_dims(int P, int* Sm, int* St);
 // k + i ki: complex wavenumber (ki = 0: real)
 void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, double ki, const int32_t* cp_off,
                        const int32_t* cp_lm, const double2* cp_val, float2* tables,
@@ -46,7 +50,8 @@ struct InstDev {
   float2* M;                // multipoles [ncell][P^2]
   float2* L;                // locals [ncell][P^2]
   const int4* m2l_pairs;    // (target, source, symmetry, staging slot)
-  float2* stage;            // M2L staging [slots][Rp] (canonical frame), slots ordered by target
+  float2* stage;            // M2L staging [slots][Sm] (canonical frame), slots ordered by target
+  float2* stage_tail;       // the last St rows of each slot [slots][St] (see stage_dims)
   const uint8_t* slot_g;    // per staging slot: reflection of its pair
   const int32_t* m2l_soff;  // per cell: first staging slot (ncell + 1 entries)
   const int4* p2p_work;     // (tgt begin, tgt end, interval begin, interval end)

@@ -613,6 +613,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
            const InstDev* __restrict__ insts, const int32_t* __restrict__ bmap, int Rp) {
   constexpr int P2 = P * P, RT = (P2 + 15) / 16, KS = (P2 + 3) / 4, Kp = 4 * KS;
+  // staging rows per slot: SM_M in whole 16-row tiles, and SM_T tail rows of
+  // a partly filled last tile (P^2 - 16 (RT - 1), rounded up to even)
+  constexpr int SM_REM = P2 - 16 * (RT - 1), SM_T = SM_REM == 16 ? 0 : 2 * ((SM_REM + 1) / 2);
+  constexpr int SM_M = SM_T ? 16 * (RT - 1) : 16 * RT;
   extern __shared__ int smap[];     // [17][Kp] input codes (see m2l_input_codes)
   const int b = blockIdx.x;
   const int w = (b & 7) * per_xcd + (b >> 3);
@@ -785,8 +789,17 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
           const int sv = __shfl(slots[t], col & 15);
           if ((col >> 4) == t) slot = sv;
         }
+        if constexpr (SM_T > 0) {
+          if (r == RT - 1) {  // the partly filled last tile: its SM_T rows go to the tail
+            if (slot >= 0 && piece < SM_T / 2) {
+              gfloat4* St = (gfloat4*)(I.stage_tail + (size_t)slot * SM_T);
+              __builtin_nontemporal_store(sout[col * 8 + piece], &St[piece]);
+            }
+            continue;
+          }
+        }
         if (slot >= 0) {
-          gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * Rp + 16 * r);
+          gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * SM_M + 16 * r);
           __builtin_nontemporal_store(sout[col * 8 + piece], &St[piece]);  // written once, read once
         }
       }
@@ -890,7 +903,7 @@ constexpr int kRedGroup = 512;
 
 __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ items,
                                                     const InstDev* __restrict__ insts,
-                                                    const int32_t* __restrict__ omap, int P2, int Sp,
+                                                    const int32_t* __restrict__ omap, int P2, int Sm, int St,
                                                     int64_t slot_base) {
   extern __shared__ int red_lds[];
   int* som = red_lds;              // [16][P2] output codes
@@ -921,15 +934,18 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ ite
     for (int e = tid; e < ng; e += nth) sgo[e] = (int)I.slot_g[g0 + e] * P2;
     __syncthreads();
     if (c < P2) {
-      gcfloat2* S = (gcfloat2*)(I.stage + (size_t)(g0 - slot_base) * Sp);
+      // row r of a slot: main part for r < Sm, else the tail
+      gcfloat2* S = (gcfloat2*)(I.stage + (size_t)(g0 - slot_base) * Sm);
+      gcfloat2* T = (gcfloat2*)(I.stage_tail + (size_t)(g0 - slot_base) * St) - Sm;
+      auto at = [&](int u, int r) { return r < Sm ? S + (size_t)u * Sm + r : T + (size_t)u * St + r; };
       int q = 0;
-      for (; q + 8 <= ng; q += 8, S += 8 * Sp) {  // eight loads in flight, added in slot order
+      for (; q + 8 <= ng; q += 8, S += 8 * Sm, T += 8 * St) {  // eight loads in flight, added in slot order
         int e[8];
         float2 v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) e[u] = som[sgo[q + u] + c];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = ld2_once(S + u * Sp + (e[u] & 0xffff));
+        for (int u = 0; u < 8; ++u) v[u] = ld2_once(at(u, e[u] & 0xffff));
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const float2 w = apply_code(v[u].x, v[u].y, e[u]);
@@ -937,9 +953,9 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ ite
           si += w.y;
         }
       }
-      for (; q < ng; ++q, S += Sp) {
+      for (; q < ng; ++q, S += Sm, T += St) {
         const int e = som[sgo[q] + c];
-        const float2 v = ld2_once(S + (e & 0xffff));
+        const float2 v = ld2_once(at(0, e & 0xffff));
         const float2 w = apply_code(v.x, v.y, e);
         sr += w.x;
         si += w.y;
@@ -1154,6 +1170,11 @@ void table_dims(int P, int* Kp, int* Rp) {
   *Kp = 4 * ((P * P + 3) / 4);
   *Rp = 16 * ((P * P + 15) / 16);
 }
+void stage_dims(int P, int* Sm, int* St) {
+  const int RT = (P * P + 15) / 16, rem = P * P - 16 * (RT - 1);
+  *St = rem == 16 ? 0 : 2 * ((rem + 1) / 2);
+  *Sm = *St ? 16 * (RT - 1) : 16 * RT;
+}
 void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, double ki, const int32_t* cp_off,
                        const int32_t* cp_lm, const double2* cp_val, float2* tables,
                        hipStream_t s) {
@@ -1243,7 +1264,9 @@ void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int
   table_dims(P, &Kp, &Rp);
   const int nth = 64 * ((P * P + 63) / 64);  // one thread per coefficient
   const size_t lds = (16 * (size_t)P * P + kRedGroup) * sizeof(int);
-  if (n > 0) k_m2l_reduce<<<n, nth, lds, s>>>(items, insts, omap, P * P, Rp, slot_base);
+  int Sm, St;
+  stage_dims(P, &Sm, &St);
+  if (n > 0) k_m2l_reduce<<<n, nth, lds, s>>>(items, insts, omap, P * P, Sm, St, slot_base);
 }
 void launch_p2p(const int2* items, int n, const InstDev* insts, bool damped, hipStream_t s) {
   if (n <= 0) return;

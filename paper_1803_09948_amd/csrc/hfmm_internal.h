@@ -147,7 +147,7 @@ struct Plan {
   DevBuf d_slot_g;               // uint8 per staging slot: the pair's reflection
   DevBuf d_M, d_L;               // float2 [ncell][P^2]
   DevBuf d_cops;                 // int2 per cell: (M2M op as child, L2L op as child)
-  DevBuf d_stage;                // float2 [slots of the largest segment][Rp] staging, slots ordered by target
+  DevBuf d_stage;                // float2 staging, slots of the largest segment ordered by target: [slots][Sm] then [slots][St]
   DevBuf d_m2l_soff;             // int32 [ncell + 1]: first staging slot of each target cell
   std::vector<int32_t> m2l_targets;  // cells that receive M2L
   std::vector<M2LSeg> m2l_segs;      // staging segments (one unless the staging budget is exceeded)
