@@ -642,10 +642,12 @@ int hfmm_matvec(hfmm_tree* tree, double k, int32_t P, const void* x, void* y, vo
     HIP_TRY(hipEventSynchronize(t.ev[8]));
     float ms;
     // phases: P2M (0-1), M2M (1-2), M2L matrix-core kernel (2-3), M2L
-    // reduction (3-4), L2L (4-5), L2P (5-6), P2P (6-7), output scatter and
-    // BIE corrections (7-8), total (0-8)
+    // reduction (3-4), L2L (4-5), P2P (5-6), L2P (6-7), output scatter and
+    // BIE corrections (7-8), total (0-8); reported in the order P2M, M2M,
+    // M2L, reduction, L2L, L2P, P2P, scatter
+    static const int span[8] = {0, 1, 2, 3, 4, 6, 5, 7};
     for (int i = 0; i < 8; ++i) {
-      HIP_TRY(hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]));
+      HIP_TRY(hipEventElapsedTime(&ms, t.ev[span[i]], t.ev[span[i] + 1]));
       t.phase_ms[i] = ms;
     }
     HIP_TRY(hipEventElapsedTime(&ms, t.ev[0], t.ev[8]));

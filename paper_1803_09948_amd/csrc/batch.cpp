@@ -32,6 +32,9 @@ Batch::~Batch() {
   if (ev_in) (void)hipEventDestroy(ev_in);
   if (ev_out) (void)hipEventDestroy(ev_out);
   if (stream) (void)hipStreamDestroy(stream);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (side) (void)hipStreamDestroy(side);
 }
 
 static InstDev make_inst(Tree& t, Plan& pl) {
@@ -98,7 +101,7 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
     b.damped = b.damped || pl.ki != 0.0;
     b.maxlev = std::max(b.maxlev, pl.ct.nlevels());
     const InstDev& I = b.hinst.back();
-    for (int64_t e = 0; e * ch < I.ncellP2; ++e) zero.push_back(make_int2(i, (int)e));
+    for (int64_t e = 0; e * ch < std::max<int64_t>(I.ncellP2, I.ntgt); ++e) zero.push_back(make_int2(i, (int)e));
     for (int64_t e = 0; e * ch < I.nsrc; ++e) gather.push_back(make_int2(i, (int)e));
     for (int64_t e = 0; e * ch < I.ntgt; ++e) scatter.push_back(make_int2(i, (int)e));
     for (int c : pl.src_leaves) p2m.push_back(make_int2(i, c));
@@ -198,8 +201,12 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
   return HFMM_OK;
 }
 
-// The fused sequence: zero, gather, P2M, M2M (levels up), M2L, L2L (levels
-// down), L2P, P2P, scatter.  Events are recorded only when `ev` is given.
+// The fused sequence: zero (M, L and the sorted outputs), gather, then P2P
+// on the side stream while P2M, M2M (levels up), M2L and L2L (levels down)
+// run on `s`; L2P waits for P2P and adds the far field to its sums; scatter.
+// P2P and L2P each add into ys in this order on both paths.  With `ev`
+// (phase timing) everything runs on `s`, one phase after another, and the
+// events bracket the phases.
 static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   const InstDev* I = b.d_inst.as<InstDev>();
   const int P = b.P;
@@ -212,6 +219,13 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   if ((rc = mark(0))) return rc;
   launch_zero(b.d_zero.as<int2>(), b.n_zero, I, s);
   launch_gather(b.d_gather.as<int2>(), b.n_gather, I, s);
+  const bool fork = !ev;
+  if (fork) {
+    HIP_TRY(hipEventRecord(b.ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(b.side, b.ev_fork, 0));
+    launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, b.side);
+    HIP_TRY(hipEventRecord(b.ev_join, b.side));
+  }
   launch_p2m(b.d_p2m.as<int2>(), b.n_p2m, I, P, b.damped, s);
   if ((rc = mark(1))) return rc;
   for (int l = b.maxlev - 2; l >= 0; --l)
@@ -233,9 +247,13 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
     launch_l2l(b.d_l2l.as<int4>() + b.l2l_off[l], b.l2l_off[l + 1] - b.l2l_off[l], b.d_l2l_cols.as<int32_t>(), I,
                P, s);
   if ((rc = mark(5))) return rc;
-  launch_l2p(b.d_l2p.as<int2>(), b.n_l2p, I, P, b.damped, s);
+  if (fork) {
+    HIP_TRY(hipStreamWaitEvent(s, b.ev_join, 0));
+  } else {
+    launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, s);
+  }
   if ((rc = mark(6))) return rc;
-  launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, s);
+  launch_l2p(b.d_l2p.as<int2>(), b.n_l2p, I, P, b.damped, s);
   if ((rc = mark(7))) return rc;
   launch_scatter(b.d_scatter.as<int2>(), b.n_scatter, I, s);
   HIP_TRY(hipGetLastError());
@@ -336,6 +354,11 @@ int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t 
   int rc = tune_batch(b, s);
   if (rc) return rc;
   b.ran = true;
+  if (!b.side) {
+    HIP_TRY(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&b.ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&b.ev_join, hipEventDisableTiming));
+  }
   if (!use_graph) return sequence(b, s, timing ? timing->ev : nullptr);
   if (!b.stream) {
     HIP_TRY(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));

@@ -269,7 +269,8 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
 // ---------------------------------------------------------------------------
 constexpr int kChunk = 4096;   // elements per block for zero / gather / scatter
 
-// M = L = 0 for the listed instances (items: instance, element offset)
+// M = L = 0 and the sorted outputs ys = 0 for the listed instances (items:
+// instance, element offset over max(ncell P^2, ntgt))
 __global__ void k_zero(const int2* __restrict__ items, int n, const InstDev* __restrict__ insts) {
   const int2 it = items[blockIdx.x];
   const InstDev& I = insts[it.x];
@@ -279,6 +280,8 @@ __global__ void k_zero(const int2* __restrict__ items, int n, const InstDev* __r
     I.M[e] = make_float2(0.f, 0.f);
     I.L[e] = make_float2(0.f, 0.f);
   }
+  const int64_t t1 = min(e0 + kChunk, I.ntgt);
+  for (int64_t e = e0 + threadIdx.x; e < t1; e += blockDim.x) I.ys[e] = make_float2(0.f, 0.f);
 }
 
 // q_s = w_s x[unknown_s] in Morton order (items: instance, body offset)
@@ -1009,15 +1012,21 @@ __global__ void __launch_bounds__(64) k_l2p(const int2* __restrict__ items, cons
     if constexpr (DAMP) {
 #pragma unroll
       for (int n = 0; n < P; ++n) s = cfma(bc[n], u[n], s);
-      // times i (k + i ki) = -ki + i k
-      I.ys[i] = make_float2(-I.ki * s.x - k * s.y, k * s.x - I.ki * s.y);
+      // times i (k + i ki) = -ki + i k, added to the near field
+      float2 o = I.ys[i];
+      o.x = fmaf(-I.ki, s.x, fmaf(-k, s.y, o.x));
+      o.y = fmaf(-I.ki, s.y, fmaf(k, s.x, o.y));
+      I.ys[i] = o;
     } else {
 #pragma unroll
       for (int n = 0; n < P; ++n) {
         s.x = fmaf(b[n], u[n].x, s.x);
         s.y = fmaf(b[n], u[n].y, s.y);
       }
-      I.ys[i] = make_float2(-k * s.y, k * s.x);  // times i k
+      float2 o = I.ys[i];  // times i k, added to the near field
+      o.x = fmaf(-k, s.y, o.x);
+      o.y = fmaf(k, s.x, o.y);
+      I.ys[i] = o;
     }
   }
 }

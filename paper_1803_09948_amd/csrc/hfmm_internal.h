@@ -196,6 +196,8 @@ struct Batch {
   std::vector<int64_t> seg_slot_base;         // first staging slot of each segment
   hipStream_t stream = nullptr;       // private stream for graph capture / replay
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t side = nullptr;         // P2P, concurrent with the far field
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int m2l_variant = -1;               // launch shape chosen by the autotuner
