@@ -218,28 +218,33 @@ def bench_bie(a):
     """Sound-soft sphere, icosphere subdivision 5 (20480 flat panels), plane
     wave along z, P = 10, GMRES(30) to 1e-4 with FP64 Arnoldi: k = 2 pi (an
     interior resonance) and k = 6; then the singularity ablation at k = 6
-    (self + near corrections / self only / neither)."""
+    (self + near corrections / self only / neither); then the wing-fuselage
+    pair of intersecting ellipsoids (clipped union, subdivision 5) at k = 2 pi."""
     import torch
 
     import synth
     from paper_1803_09948_amd import hfmm
 
-    V, T = synth.icosphere(5)
+    sphere = synth.icosphere(5)
+    wingfus = synth.wing_fuselage(5)
     rows = []
-    for k, mode in ((2 * math.pi, 0), (6.0, 0), (6.0, 1), (6.0, 2)):
+    for geom, k, mode in (("sphere", 2 * math.pi, 0), ("sphere", 6.0, 0), ("sphere", 6.0, 1), ("sphere", 6.0, 2),
+                          ("wing-fuselage", 2 * math.pi, 0)):
+        V, T = sphere if geom == "sphere" else wingfus
         t = hfmm.Tree.from_mesh(V, T, bie_treatment=mode)
         t0 = time.perf_counter()
         t.prepare(k, 10)
         torch.cuda.synchronize()
         t_prep = time.perf_counter() - t0
         b = t.plane_wave(k)
-        t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=400)  # warm (tuning, workspace)
+        t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=2000)  # warm (tuning, workspace)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=400)
+        x, info = t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=2000)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        row = {"k": k, "treatment": ["self+near", "self", "none"][mode], "iters": info["iters"],
+        row = {"geometry": geom, "panels": len(T), "k": k, "treatment": ["self+near", "self", "none"][mode],
+               "iters": info["iters"],
                "converged": info["converged"], "resid_true": info["resid_true"], "solve_ms": dt * 1e3,
                "ms_per_iter": dt * 1e3 / max(1, info["iters"]), "setup_s": t_prep}
         rows.append(row)
@@ -345,10 +350,10 @@ def bench_nystrom(a):
             torch.cuda.synchronize()
             t_prep = time.perf_counter() - t0
             b = t.plane_wave(k)
-            t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=400)  # warm (tuning, workspace)
+            t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=2000)  # warm (tuning, workspace)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            x, info = t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=400)
+            x, info = t.gmres(k, 10, b, tol=1e-4, restart=30, maxit=2000)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             row = {"subdiv": s, "unknowns": 6 * len(tri6), "k": k, "iters": info["iters"],

@@ -112,19 +112,29 @@ def _ref_rule_centroid(n: int):
 _RULES: dict = {}
 
 
-def self_integral(k: float, a, b, c, n: int = 24) -> complex:
+def self_integral(k: float, a, b, c, n: int = 32) -> complex:
     """Integral over triangle (a,b,c) of G(x, y) dS_y with x its centroid.
 
     G = 1/(4 pi R) + (e^{ikR} - 1)/(4 pi R): the first part by the closed form
-    of `laplace_panel_analytic`, the bounded second part by the Duffy rule
-    collapsed at x over the three sub-triangles (x,a,b), (x,b,c), (x,c,a)."""
-    lam, w = _ref_rule_centroid(n)
+    of `laplace_panel_analytic`, the bounded second part by Duffy rules
+    collapsed at x.  Each sub-triangle (x, q, r) over an edge qr is cut at
+    the foot F of the perpendicular from x onto qr (clamped to the edge) into
+    (x, q, F) and (x, F, r): along the edge the distance from x has its
+    minimum at F, and on an elongated panel, where x lies close to its long
+    edge, that minimum is sharp; with the cut each piece sees a monotone
+    distance and the rule converges as it does on a well-shaped panel."""
     a, b, c = (np.asarray(z, np.float64) for z in (a, b, c))
-    area = 0.5 * np.linalg.norm(np.cross(b - a, c - a))
     x = (a + b + c) / 3.0
-    pts = lam @ np.stack([a, b, c])
-    R = np.linalg.norm(pts - x, axis=1)
-    smooth = (w * area * np.expm1(1j * k * R) / (4 * np.pi * R)).sum()
+    smooth = 0.0
+    for q, r in ((a, b), (b, c), (c, a)):
+        e = r - q
+        F = q + min(max(float((x - q) @ e) / float(e @ e), 0.0), 1.0) * e
+        for p1, p2 in ((q, F), (F, r)):
+            if np.linalg.norm(np.cross(p1 - x, p2 - x)) == 0.0:
+                continue
+            pts, w = duffy_rule(x, p1, p2, n)
+            R = np.linalg.norm(pts - x, axis=1)
+            smooth += (w * np.expm1(1j * k * R) / (4 * np.pi * R)).sum()
     return complex(laplace_panel_analytic(x, a, b, c) / (4 * np.pi) + smooth)
 
 

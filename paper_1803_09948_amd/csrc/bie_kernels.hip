@@ -91,12 +91,21 @@ __global__ void k_self(int64_t npan, const double* __restrict__ pan, double k, d
   d3 a = vtx(pan, i, 0), b = vtx(pan, i, 1), c = vtx(pan, i, 2);
   d3 x = scl(add(add(a, b), c), 1.0 / 3.0);
   double lap = laplace_inplane(x, a, b, c) / (4.0 * M_PI);
-  // remainder (e^{ikR} - 1) / (4 pi R) over (x,a,b), (x,b,c), (x,c,a), Duffy-collapsed at x
+  // remainder (e^{ikR} - 1) / (4 pi R), Duffy-collapsed at x over the six
+  // pieces of (x,a,b), (x,b,c), (x,c,a) cut at the foot of the perpendicular
+  // from x onto each edge: along an edge the distance from x is smallest at
+  // that foot, sharply so on an elongated panel, and each piece then sees a
+  // monotone distance (the rule keeps its accuracy on such panels)
   double sr = 0.0, si = 0.0;
   d3 V[3] = {a, b, c};
-  for (int e = 0; e < 3; ++e) {
-    d3 q = V[e], r = V[(e + 1) % 3];
-    double a2 = nrm(cross(sub(q, x), sub(r, x)));  // twice the sub-triangle area
+  for (int e = 0; e < 6; ++e) {
+    const d3 q0 = V[e >> 1], r0 = V[((e >> 1) + 1) % 3];
+    const d3 ed = sub(r0, q0);
+    const double tf = fmin(fmax(dot(sub(x, q0), ed) / dot(ed, ed), 0.0), 1.0);
+    const d3 F = add(q0, scl(ed, tf));
+    const d3 q = (e & 1) ? F : q0, r = (e & 1) ? r0 : F;
+    double a2 = nrm(cross(sub(q, x), sub(r, x)));  // twice the piece's area
+    if (a2 == 0.0) continue;
     for (int iu = 0; iu < ng; ++iu)
       for (int iv = 0; iv < ng; ++iv) {
         double u = gx[iu], v = gx[iv];

@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "sphere_points", "strengths", "icosphere", "scale_axes",
+    "sphere_points", "strengths", "icosphere", "scale_axes", "curved_icosphere", "wing_fuselage",
     "WORKLOADS", "batch_instances", "serve_trace",
 ]
 
@@ -120,6 +120,80 @@ def curved_icosphere(subdiv: int, radius: float = 1.0):
 
     tri6 = np.array([[a, b, c, mid(a, b), mid(b, c), mid(c, a)] for (a, b, c) in T.tolist()], dtype=np.int32)
     return np.asarray(nodes, dtype=np.float64), tri6
+
+
+def _clip_outside(V, T, centre, axes, min_area, snap):
+    """Keep the part of each triangle outside the solid ellipsoid
+    sum(((x - centre) / axes)^2) <= 1.  An edge that crosses the surface is
+    cut at its exact crossing (a quadratic in the edge parameter), moved to
+    the nearer end when it lies within `snap` of it (no sliver pieces); the
+    kept polygon (3 or 4 corners, same winding) is fanned into triangles, and
+    pieces smaller than min_area are dropped.  Returns new (verts, tris),
+    vertices not shared between triangles."""
+    c = np.asarray(centre, dtype=np.float64)
+    ax = np.asarray(axes, dtype=np.float64)
+
+    def f(x):
+        u = (x - c) / ax
+        return float(u @ u) - 1.0
+
+    def cross(p, q):
+        u, w = (p - c) / ax, (q - p) / ax
+        A, B, C = float(w @ w), 2.0 * float(u @ w), float(u @ u) - 1.0
+        d = math.sqrt(max(B * B - 4.0 * A * C, 0.0))
+        for t in ((-B - d) / (2.0 * A), (-B + d) / (2.0 * A)):
+            if -1e-12 <= t <= 1.0 + 1e-12:
+                t = 0.0 if t < snap else 1.0 if t > 1.0 - snap else t
+                return p + t * (q - p)
+        raise ValueError("no crossing on a sign-changing edge")
+
+    out_v, out_t = [], []
+    for tri in T:
+        P = [V[i] for i in tri]
+        keep = [f(x) >= 0.0 for x in P]
+        if not any(keep):
+            continue
+        poly = []
+        for j in range(3):
+            p, q = P[j], P[(j + 1) % 3]
+            if keep[j]:
+                poly.append(p)
+            if keep[j] != keep[(j + 1) % 3]:
+                poly.append(cross(p, q))
+        for j in range(1, len(poly) - 1):
+            a, b, cc = poly[0], poly[j], poly[j + 1]
+            if 0.5 * np.linalg.norm(np.cross(b - a, cc - a)) < min_area:
+                continue
+            base = len(out_v)
+            out_v += [a, b, cc]
+            out_t.append([base, base + 1, base + 2])
+    return np.asarray(out_v, dtype=np.float64).reshape(-1, 3), np.asarray(out_t, dtype=np.int32).reshape(-1, 3)
+
+
+WING_FUSELAGE = {"fuselage": (2.0, 0.4, 0.4), "wing": (0.6, 1.8, 0.12)}
+
+
+def wing_fuselage(subdiv: int, fuselage=WING_FUSELAGE["fuselage"], wing=WING_FUSELAGE["wing"],
+                  min_frac: float = 0.02, snap: float = 0.3):
+    """A wing-fuselage configuration emulated by two intersecting ellipsoids
+    centred at the origin (the geometry the paper names as its next target,
+    Sec. 7): a fuselage along x and a thin wing along y.  Each body is the
+    icosphere(subdiv) scaled to its semi-axes, with the triangles (or parts
+    of triangles) inside the other body removed, so the union's surface is
+    covered by flat triangles, outward counter-clockwise.  The two clipped
+    surfaces meet along the intersection curve without sharing vertices (a
+    collocation method needs no conforming mesh); cut pieces smaller than
+    min_frac of a body's median triangle are dropped.  Returns (verts
+    float64 (nv,3), tris int32 (nt,3))."""
+    V0, T0 = icosphere(subdiv)
+    parts = []
+    for mine, other in ((fuselage, wing), (wing, fuselage)):
+        V = V0 * np.asarray(mine, dtype=np.float64).reshape(1, 3)
+        a, b, c = V[T0[:, 0]], V[T0[:, 1]], V[T0[:, 2]]
+        med = float(np.median(0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)))
+        parts.append(_clip_outside(V, T0, (0.0, 0.0, 0.0), other, min_frac * med, snap))
+    (Va, Ta), (Vb, Tb) = parts
+    return np.concatenate([Va, Vb]), np.concatenate([Ta, Tb + len(Va)]).astype(np.int32)
 
 
 # --------------------------------------------------------------------------

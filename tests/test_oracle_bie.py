@@ -133,3 +133,30 @@ def test_bie_solve_converges_toward_mie():
         us = bie.scattered_field(k, V, T, q, xo)
         errs.append(np.linalg.norm(us - um) / np.linalg.norm(um))
     assert errs[1] < 0.6 * errs[0], errs
+
+
+@pytest.mark.parametrize("height,k", [(0.06, 2 * math.pi), (0.01, 2 * math.pi), (0.01, 20.0)])
+def test_self_integral_elongated_panels(height, k):
+    """Elongated panels (unit base, apex at the given height; area / longest
+    edge^2 = height / 2): the bounded part (e^{ikR} - 1)/(4 pi R) of the self
+    integral against a composite rule with no singular treatment at all, 4^7
+    uniform sub-triangles with a 7-point rule each (the integrand is bounded
+    and continuous, so the composite rule converges)."""
+    a = np.array([0.0, 0, 0]); b = np.array([1.0, 0, 0]); c = np.array([0.37, height, 0])
+    x = (a + b + c) / 3
+    # 7-point degree-5 rule on the reference triangle (barycentric, weights sum 1)
+    s15 = math.sqrt(15.0)
+    a1, b1 = (6 - s15) / 21, (9 + 2 * s15) / 21
+    a2, b2 = (6 + s15) / 21, (9 - 2 * s15) / 21
+    lam = np.array([[1 / 3, 1 / 3, 1 / 3], [a1, a1, b1], [a1, b1, a1], [b1, a1, a1],
+                    [a2, a2, b2], [a2, b2, a2], [b2, a2, a2]])
+    wts = np.array([9 / 40] + [(155 - s15) / 1200] * 3 + [(155 + s15) / 1200] * 3)
+    tri = np.array(bie.subdivide(a, b, c, 7))                  # (4^7, 3, 3)
+    pts = np.einsum("gv,tvd->tgd", lam, tri)
+    R = np.linalg.norm(pts - x, axis=2)
+    sub_area = 0.5 * np.linalg.norm(np.cross(b - a, c - a)) / len(tri)
+    brute = (np.expm1(1j * k * R) / (4 * np.pi * R) * wts).sum() * sub_area
+    smooth = bie.self_integral(k, a, b, c) - bie.laplace_panel_analytic(x, a, b, c) / (4 * math.pi)
+    err = abs(smooth - brute) / abs(bie.self_integral(k, a, b, c))
+    print(height, k, err)
+    assert err < 1e-7
