@@ -738,7 +738,12 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
         load_b(min(4 * (ks + j + 1), klast), bv[(j + 1) & 1], cv[(j + 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);  // loads issue before this step's MFMAs
         finish_b(bv[j & 1], cv[j & 1]);
+        // the wave issuing its MFMAs goes first when both waves of the SIMD
+        // are ready, so its matrix-core block is not split by the other
+        // wave's loads and epilogue
+        __builtin_amdgcn_s_setprio(1);
         mma(av[j & AM]);
+        __builtin_amdgcn_s_setprio(0);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -749,7 +754,9 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
       if (st + 1 < KS) load_b(4 * (st + 1), bv[(j + 1) & 1], cv[(j + 1) & 1]);
       __builtin_amdgcn_sched_barrier(0);
       finish_b(bv[j & 1], cv[j & 1]);
+      __builtin_amdgcn_s_setprio(1);
       mma(av[j & AM]);
+      __builtin_amdgcn_s_setprio(0);
       __builtin_amdgcn_sched_barrier(0);
     }
     // each pair owns a staging slot (slots are ordered by target) holding its
