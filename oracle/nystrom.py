@@ -205,39 +205,42 @@ def element_integrals(k: float, x, Xe, uv, wq):
     return (g * wq) @ lagrange(uv[:, 0], uv[:, 1])
 
 
-def near_elements(d, eta: float):
-    """For each point, the elements other than its own whose centroid lies
-    within eta h of it (list of arrays)."""
+def near_elements(d, eta: float, rows=None):
+    """For each point (or each of `rows`), the elements other than its own
+    whose centroid lies within eta h of it (list of arrays)."""
     r, cen, h = d["r"], d["centroid"], d["h"]
     out = []
-    for j in range(len(r)):
+    for j in (range(len(r)) if rows is None else rows):
         dist = np.linalg.norm(cen - r[j], axis=1)
         es = np.flatnonzero(dist < eta * h)
         out.append(es[es != j // 6])
     return out
 
 
-def dense_matrix(k: float, nodes, tri6, eta: float = 2.0, L: int = 3, n_near: int = 8, n_self: int = 12):
-    """The Nystrom matrix Z (N, N), N = 6 x elements, complex128."""
+def dense_matrix(k: float, nodes, tri6, eta: float = 2.0, L: int = 3, n_near: int = 8, n_self: int = 12,
+                 rows=None):
+    """The Nystrom matrix Z (N, N), N = 6 x elements, complex128, or its
+    selected rows (len(rows), N)."""
     d = discretise(nodes, tri6)
     r, w, X = d["r"], d["w"], d["X"]
     N = len(r)
-    Z = green(k, r[:, None, :], r[None, :, :]) * w[None, :]
-    near = near_elements(d, eta)
+    rows = np.arange(N) if rows is None else np.asarray(rows)
+    Z = green(k, r[rows][:, None, :], r[None, :, :]) * w[None, :]
+    near = near_elements(d, eta, rows)
     uv_near, w_near = subdivided(L, n_near)
     lag_near = lagrange(uv_near[:, 0], uv_near[:, 1])
-    y_near, _ = map_points(X, uv_near[:, 0], uv_near[:, 1])   # (nt, M, 3)
-    for j in range(N):
+    for t, j in enumerate(rows):
         m = j // 6
         p = RULE_UV[j % 6]
         uv, wq = duffy_at(p, n_self, X[m])
-        Z[j, 6 * m:6 * m + 6] = element_integrals(k, r[j], X[m], uv, wq)
-        es = near[j]
+        Z[t, 6 * m:6 * m + 6] = element_integrals(k, r[j], X[m], uv, wq)
+        es = near[t]
         if len(es):
-            g = green(k, r[j][None, None, :], y_near[es])          # (ne, M)
-            vals = (g * w_near[None, :]) @ lag_near                # (ne, 6)
+            y_es, _ = map_points(X[es], uv_near[:, 0], uv_near[:, 1])     # (ne, M, 3)
+            g = green(k, r[j][None, None, :], y_es)                      # (ne, M)
+            vals = (g * w_near[None, :]) @ lag_near                      # (ne, 6)
             for e, v in zip(es, vals):
-                Z[j, 6 * e:6 * e + 6] = v
+                Z[t, 6 * e:6 * e + 6] = v
     return Z
 
 
