@@ -25,7 +25,8 @@
  *    after eq. (14)).  1 <= P <= 16.
  *  - A tree handle owns its device memory (allocated at build time and when
  *    a new (k, P) operator is first prepared; never inside a matvec that
- *    reuses a prepared operator).  Handles may be used from several host
+ *    reuses a prepared operator; GMRES adds its Krylov workspace on the first
+ *    solve with a given restart).  Handles may be used from several host
  *    threads only with external serialisation.
  */
 #ifndef HFMM_H
@@ -142,7 +143,11 @@ int hfmm_nystrom_points(const hfmm_tree* tree, double* xyz_host, double* weight_
                         double* jac_host);
 
 /* Builds (once) the traversal lists, translation operators and, for a BIE
- * handle, the near and self corrections for wavenumber k and order P.
+ * handle, the near and self corrections for wavenumber k and order P, and
+ * the execution state of a product: its work lists, its M2L launch shape
+ * (the first call times each shape on this work; see hfmm_variant_count)
+ * and a second stream with two events (the near field runs beside the far
+ * field).  Afterwards hfmm_matvec on (k, P) allocates nothing.
  * Called implicitly by hfmm_matvec / hfmm_gmres_solve.
  *  EINVAL: k <= 0 or non-finite, P outside [1, 16]. */
 int hfmm_prepare(hfmm_tree* tree, double k, int32_t P, void* stream);

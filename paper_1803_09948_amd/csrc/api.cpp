@@ -476,11 +476,22 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   return HFMM_OK;
 }
 
+// Everything a product on (k, P) needs, so that a product allocates nothing:
+// host lists, device operators and corrections, and the single-instance
+// batch (work lists, launch shape, side stream).
 int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
   Plan* pl;
   int rc = prepare_host(t, k, P, &pl);
   if (rc) return rc;
   if ((rc = prepare_device(t, *pl, s))) return rc;
+  if (!pl->self) {
+    pl->self = std::make_unique<Batch>();
+    if ((rc = build_batch({&t}, {pl}, *pl->self))) {
+      pl->self.reset();
+      return rc;
+    }
+  }
+  if ((rc = ready_batch(*pl->self, s))) return rc;
   *out = pl;
   return HFMM_OK;
 }
@@ -498,14 +509,7 @@ int check_kP(double k, int P) {
 }
 
 int matvec_impl(Tree& t, Plan& pl, const float2* x, float2* y, hipStream_t s) {
-  if (!pl.self) {
-    pl.self = std::make_unique<Batch>();
-    int rc = build_batch({&t}, {&pl}, *pl.self);
-    if (rc) {
-      pl.self.reset();
-      return rc;
-    }
-  }
+  if (!pl.self) return set_error("internal: product on an unprepared plan"), HFMM_EINVAL;
   const float2* xs[1] = {x};
   float2* ys[1] = {y};
   return run_batch(*pl.self, xs, ys, s, false, t.timing ? &t : nullptr);

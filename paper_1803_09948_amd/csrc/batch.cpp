@@ -339,6 +339,17 @@ static int tune_batch(Batch& b, hipStream_t s) {
   return HFMM_OK;
 }
 
+int ready_batch(Batch& b, hipStream_t s) {
+  int rc = tune_batch(b, s);
+  if (rc) return rc;
+  if (!b.side) {
+    HIP_TRY(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&b.ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&b.ev_join, hipEventDisableTiming));
+  }
+  return HFMM_OK;
+}
+
 int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t s, bool use_graph,
               Tree* timing) {
   for (int base = 0; base < b.count; base += 64) {
@@ -351,14 +362,9 @@ int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t 
     launch_set_xy(n, base, p, b.d_inst.as<InstDev>(), s);
   }
   HIP_TRY(hipGetLastError());
-  int rc = tune_batch(b, s);
+  int rc = ready_batch(b, s);
   if (rc) return rc;
   b.ran = true;
-  if (!b.side) {
-    HIP_TRY(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&b.ev_fork, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&b.ev_join, hipEventDisableTiming));
-  }
   if (!use_graph) return sequence(b, s, timing ? timing->ev : nullptr);
   if (!b.stream) {
     HIP_TRY(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));

@@ -212,6 +212,10 @@ int build_batch(const std::vector<struct Tree*>& trees, const std::vector<Plan*>
 enum { kPhaseM2L = 0, kNumTunedPhases = 1 };
 int set_variant_override(int phase, int variant);
 int batch_variant(const Batch& b, int phase);
+// First-use setup of a batch: the autotuned launch shape (times the shapes on
+// the batch's own work), the side stream and its events.  run_batch calls it;
+// calling it earlier keeps that work out of the first product.
+int ready_batch(Batch& b, hipStream_t s);
 // Runs the fused FMM sequence; xs/ys are caller vectors per instance.  With
 // use_graph the sequence is captured once and replayed on a private stream.
 int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t s, bool use_graph,
