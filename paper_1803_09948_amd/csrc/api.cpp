@@ -270,14 +270,21 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
   int Sm0, St0;
   stage_dims(P, &Sm0, &St0);
   std::vector<int32_t> slot(npair);
+  // bytgt: pair indices ordered by (target, source), a counting sort by
+  // target and a short sort by source within each target ((target, source)
+  // is unique, so the order is total)
+  std::vector<int32_t> bytgt(npair);
   {
-    std::vector<int32_t> bytgt(npair);
-    std::iota(bytgt.begin(), bytgt.end(), 0);
-    std::sort(bytgt.begin(), bytgt.end(), [&](int32_t x, int32_t y) {
-      const int4 &p = pairs[x], &q = pairs[y];
-      if (p.x != q.x) return p.x < q.x;
-      return p.y < q.y;
-    });
+    std::vector<int64_t> pos(h.ncell() + 1, 0);
+    for (size_t i = 0; i < npair; ++i) pos[pairs[i].x + 1]++;
+    for (int c = 0; c < h.ncell(); ++c) pos[c + 1] += pos[c];
+    std::vector<int64_t> fill(pos.begin(), pos.end() - 1);
+    for (size_t i = 0; i < npair; ++i) bytgt[fill[pairs[i].x]++] = (int32_t)i;
+    for (int c = 0; c < h.ncell(); ++c)
+      std::sort(bytgt.begin() + pos[c], bytgt.begin() + pos[c + 1],
+                [&](int32_t x, int32_t y) { return pairs[x].y < pairs[y].y; });
+  }
+  {
     hd.soff.assign(h.ncell() + 1, 0);
     for (size_t r = 0; r < npair; ++r) {
       slot[bytgt[r]] = (int32_t)r;
@@ -314,16 +321,19 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     }
     if (cur.tgt_e > cur.tgt_b) pl.m2l_segs.push_back(cur);
   }
-  // group pairs by segment, then operator, then target, then source
+  // group pairs by segment, then operator, then target, then source: a
+  // stable counting sort by (segment, operator) of the (target, source)
+  // order (segments are runs of consecutive targets)
   std::vector<int32_t> order(npair);
-  std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    const int4 &p = pairs[x], &q = pairs[y];
-    if (seg_of[p.x] != seg_of[q.x]) return seg_of[p.x] < seg_of[q.x];
-    if (p.w != q.w) return p.w < q.w;
-    if (p.x != q.x) return p.x < q.x;
-    return p.y < q.y;
-  });
+  {
+    const int64_t nops = (int64_t)ops.size();
+    std::vector<int64_t> pos((int64_t)pl.m2l_segs.size() * nops + 1, 0);
+    auto key = [&](int32_t i) { return (int64_t)seg_of[pairs[i].x] * nops + pairs[i].w; };
+    for (size_t i = 0; i < npair; ++i) pos[key((int32_t)i) + 1]++;
+    for (size_t e = 1; e < pos.size(); ++e) pos[e] += pos[e - 1];
+    for (size_t r = 0; r < npair; ++r) order[pos[key(bytgt[r])]++] = bytgt[r];
+  }
+  std::vector<int32_t>().swap(bytgt);
   std::vector<int4>& spairs = hd.spairs;
   spairs.resize(npair);
   std::vector<int4> chunks;

@@ -760,9 +760,10 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
       __builtin_amdgcn_sched_barrier(0);
     }
     // each pair owns a staging slot (slots are ordered by target) holding its
-    // result in the canonical frame, all Rp rows (a whole number of 128-byte
-    // lines); the reduction kernel below maps it back and adds a target's
-    // slots in a fixed order.  Lane (j, q) holds rows 4q..4q+3 of every
+    // result in the canonical frame: the SM_M rows of the full 16-row tiles
+    // (whole 128-byte lines) in the main array, the SM_T rows of a partly
+    // filled last tile in the dense tail array; the reduction kernel below
+    // maps it back and adds a target's slots in a fixed order.  Lane (j, q) holds rows 4q..4q+3 of every
     // 16-row tile of column j; tile by tile the results pass through 4 KiB of
     // LDS ([column][16 rows]) so that every store instruction writes whole
     // 128-byte lines (8 lanes x 16 bytes per column).

@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 
 #include "hfmm_internal.h"
@@ -287,7 +289,11 @@ static void legendre_norm(int L, double x, std::vector<double>& p) {
 }
 
 const Coupling& coupling(int P) {
+  // shared by every handle: handles may be prepared from several threads at
+  // once (entries are never removed, so references stay valid)
+  static std::mutex mu;
   static std::map<int, Coupling> cache;
+  std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(P);
   if (it != cache.end()) return it->second;
   Coupling cp;
