@@ -950,15 +950,16 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ ite
       gcfloat2* T = (gcfloat2*)(I.stage_tail + (size_t)(g0 - slot_base) * St) - Sm;
       auto at = [&](int u, int r) { return r < Sm ? S + (size_t)u * Sm + r : T + (size_t)u * St + r; };
       int q = 0;
-      for (; q + 8 <= ng; q += 8, S += 8 * Sm, T += 8 * St) {  // eight loads in flight, added in slot order
-        int e[8];
-        float2 v[8];
+      constexpr int U = 16;  // loads in flight per thread, added in slot order
+      for (; q + U <= ng; q += U, S += U * Sm, T += U * St) {
+        int e[U];
+        float2 v[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) e[u] = som[sgo[q + u] + c];
+        for (int u = 0; u < U; ++u) e[u] = som[sgo[q + u] + c];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = ld2_once(at(u, e[u] & 0xffff));
+        for (int u = 0; u < U; ++u) v[u] = ld2_once(at(u, e[u] & 0xffff));
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < U; ++u) {
           const float2 w = apply_code(v[u].x, v[u].y, e[u]);
           sr += w.x;
           si += w.y;
