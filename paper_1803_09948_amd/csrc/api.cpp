@@ -5,6 +5,7 @@
 #include <cstring>
 #include <numeric>
 #include <atomic>
+#include <thread>
 #include <unordered_map>
 
 #include "bie_kernels.h"
@@ -157,6 +158,23 @@ struct Key128Hash {
   }
 };
 
+// fn(begin, end) over [0, n) in static contiguous chunks, one per thread
+// (chunk t is [t n / T, (t + 1) n / T)); small ranges run inline
+static int host_threads(size_t n) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  return (int)std::max<size_t>(1, std::min<size_t>({(size_t)std::min(hw, 16u), n / 65536 + 1}));
+}
+template <class F>
+static void parallel_for(size_t n, int T, F fn) {
+  if (T <= 1) {
+    fn(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t) th.emplace_back(fn, n * t / T, n * (t + 1) / T, t);
+  for (auto& x : th) x.join();
+}
+
 double kappa_of(const Tree& t, int P) { return t.kappa < 0 ? 0.4 * P : t.kappa; }
 
 int build_plan_host(Tree& t, double k, int P, Plan& pl) {
@@ -221,48 +239,63 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
       ops.push_back(d);
     }
   }
-  // M2L: canonical offsets under the 16 reflections
+  // M2L: canonical offsets under the 16 reflections.  Each pair's key and
+  // reflection are computed in parallel; operators are numbered in the order
+  // their key first occurs in the pair list (each chunk lists its new keys in
+  // order, the chunks are merged in order), then every pair looks its up.
   const size_t npair = pl.lists.m2l_a.size();
   std::unordered_map<Key128, int32_t, Key128Hash> opmap;
   std::vector<int4> pairs(npair);
+  std::vector<Key128> keys(npair);
   int32_t m2l_base = (int32_t)ops.size();
-  for (size_t i = 0; i < npair; ++i) {
-    int a = pl.lists.m2l_a[i], b = pl.lists.m2l_b[i];
-    int la = h.level[a], lb = h.level[b];
-    int L = std::max(la, lb);
-    int64_t d[3];
-    for (int dd = 0; dd < 3; ++dd) {
-      int64_t ca = -(int64_t(1) << L) + (2 * (int64_t)h.ijk[3 * a + dd] + 1) * (int64_t(1) << (L - la));
-      int64_t cb = -(int64_t(1) << L) + (2 * (int64_t)h.ijk[3 * b + dd] + 1) * (int64_t(1) << (L - lb));
-      d[dd] = ca - cb;
+  const int TH = host_threads(npair);
+  std::vector<std::vector<Key128>> firsts(TH);
+  parallel_for(npair, TH, [&](size_t i0, size_t i1, int tid) {
+    std::unordered_map<Key128, char, Key128Hash> seen;
+    for (size_t i = i0; i < i1; ++i) {
+      int a = pl.lists.m2l_a[i], b = pl.lists.m2l_b[i];
+      int la = h.level[a], lb = h.level[b];
+      int L = std::max(la, lb);
+      int64_t d[3];
+      for (int dd = 0; dd < 3; ++dd) {
+        int64_t ca = -(int64_t(1) << L) + (2 * (int64_t)h.ijk[3 * a + dd] + 1) * (int64_t(1) << (L - la));
+        int64_t cb = -(int64_t(1) << L) + (2 * (int64_t)h.ijk[3 * b + dd] + 1) * (int64_t(1) << (L - lb));
+        d[dd] = ca - cb;
+      }
+      int g = (d[0] < 0 ? 1 : 0) | (d[1] < 0 ? 2 : 0) | (d[2] < 0 ? 4 : 0);
+      int64_t w[3] = {std::llabs(d[0]), std::llabs(d[1]), std::llabs(d[2])};
+      if (w[0] < w[1]) {
+        std::swap(w[0], w[1]);
+        g |= 8;
+      }
+      keys[i] = Key128{(uint64_t)la | ((uint64_t)lb << 8) | ((uint64_t)w[2] << 16),
+                       (uint64_t)w[0] | ((uint64_t)w[1] << 32)};
+      pairs[i] = make_int4(a, b, g, -1);
+      if (seen.find(keys[i]) == seen.end()) {  // look up first: emplace would allocate a node
+        seen.emplace(keys[i], 0);
+        firsts[tid].push_back(keys[i]);
+      }
     }
-    int g = (d[0] < 0 ? 1 : 0) | (d[1] < 0 ? 2 : 0) | (d[2] < 0 ? 4 : 0);
-    int64_t w[3] = {std::llabs(d[0]), std::llabs(d[1]), std::llabs(d[2])};
-    if (w[0] < w[1]) {
-      std::swap(w[0], w[1]);
-      g |= 8;
-    }
-    Key128 kk{(uint64_t)la | ((uint64_t)lb << 8) | ((uint64_t)w[2] << 16),
-              (uint64_t)w[0] | ((uint64_t)w[1] << 32)};
-    auto f = opmap.find(kk);
-    int32_t op;
-    if (f == opmap.end()) {
-      op = (int32_t)ops.size();
-      opmap.emplace(kk, op);
+  });
+  for (int tid = 0; tid < TH; ++tid)
+    for (const Key128& kk : firsts[tid]) {
+      if (opmap.count(kk)) continue;
+      const int la = (int)(kk.a & 0xff), lb = (int)((kk.a >> 8) & 0xff), L = std::max(la, lb);
       OpDesc dsc{};
       double u = h.H / double(1 << L);
-      dsc.t[0] = (double)w[0] * u;
-      dsc.t[1] = (double)w[1] * u;
-      dsc.t[2] = (double)w[2] * u;
+      dsc.t[0] = (double)(kk.b & 0xffffffffull) * u;
+      dsc.t[1] = (double)(kk.b >> 32) * u;
+      dsc.t[2] = (double)(kk.a >> 16) * u;
       dsc.rho_in = pl.rho[lb];
       dsc.rho_out = pl.rho[la];
       dsc.kind = OP_M2L;
+      opmap.emplace(kk, (int32_t)ops.size());
       ops.push_back(dsc);
-    } else {
-      op = f->second;
     }
-    pairs[i] = make_int4(a, b, g, op);
-  }
+  parallel_for(npair, TH, [&](size_t i0, size_t i1, int) {
+    for (size_t i = i0; i < i1; ++i) pairs[i].w = opmap.find(keys[i])->second;
+  });
+  std::vector<Key128>().swap(keys);
   pl.n_tables = (int64_t)ops.size() - m2l_base;
   pl.n_ops = (int64_t)ops.size();
   // staging slots: pairs ordered by (target, source), so each target's
@@ -280,9 +313,11 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     for (int c = 0; c < h.ncell(); ++c) pos[c + 1] += pos[c];
     std::vector<int64_t> fill(pos.begin(), pos.end() - 1);
     for (size_t i = 0; i < npair; ++i) bytgt[fill[pairs[i].x]++] = (int32_t)i;
-    for (int c = 0; c < h.ncell(); ++c)
-      std::sort(bytgt.begin() + pos[c], bytgt.begin() + pos[c + 1],
-                [&](int32_t x, int32_t y) { return pairs[x].y < pairs[y].y; });
+    parallel_for((size_t)h.ncell(), host_threads(npair), [&](size_t c0, size_t c1, int) {
+      for (size_t c = c0; c < c1; ++c)
+        std::sort(bytgt.begin() + pos[c], bytgt.begin() + pos[c + 1],
+                  [&](int32_t x, int32_t y) { return pairs[x].y < pairs[y].y; });
+    });
   }
   {
     hd.soff.assign(h.ncell() + 1, 0);
@@ -338,11 +373,13 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
   spairs.resize(npair);
   std::vector<int4> chunks;
   hd.slot_g.assign(std::max<size_t>(1, npair), 0);
-  for (size_t i = 0; i < npair; ++i) {  // slots are local to the pair's segment
-    const int4& p = pairs[order[i]];
-    spairs[i] = make_int4(p.x, p.y, p.z, slot[order[i]] - pl.m2l_segs[seg_of[p.x]].slot_b);
-    hd.slot_g[slot[order[i]]] = (uint8_t)p.z;
-  }
+  parallel_for(npair, TH, [&](size_t i0, size_t i1, int) {
+    for (size_t i = i0; i < i1; ++i) {  // slots are local to the pair's segment
+      const int4& p = pairs[order[i]];
+      spairs[i] = make_int4(p.x, p.y, p.z, slot[order[i]] - pl.m2l_segs[seg_of[p.x]].slot_b);
+      hd.slot_g[slot[order[i]]] = (uint8_t)p.z;
+    }
+  });
   const int CH = m2l_pairs_per_chunk(P);
   for (size_t i = 0; i < npair;) {
     size_t j = i;
