@@ -523,14 +523,23 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   return HFMM_OK;
 }
 
-// Everything a product on (k, P) needs, so that a product allocates nothing:
-// host lists, device operators and corrections, and the single-instance
-// batch (work lists, launch shape, side stream).
-int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
+// Host lists, device operators and (BIE) corrections for (k, P).
+int prepare_operators(Tree& t, double k, int P, hipStream_t s, Plan** out) {
   Plan* pl;
   int rc = prepare_host(t, k, P, &pl);
   if (rc) return rc;
   if ((rc = prepare_device(t, *pl, s))) return rc;
+  *out = pl;
+  return HFMM_OK;
+}
+
+// Everything a product on (k, P) needs, so that a product allocates nothing:
+// the operators, and the single-instance batch (work lists, launch shape,
+// side stream).
+int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out) {
+  Plan* pl;
+  int rc = prepare_operators(t, k, P, s, &pl);
+  if (rc) return rc;
   if (!pl->self) {
     pl->self = std::make_unique<Batch>();
     if ((rc = build_batch({&t}, {pl}, *pl->self))) {

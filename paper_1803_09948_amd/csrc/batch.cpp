@@ -447,7 +447,7 @@ extern "C" int hfmm_batch_matvec(int32_t count, hfmm_tree* const* trees, const d
       for (int i = 0; i < count; ++i) {
         Tree& t = *reinterpret_cast<Tree*>(trees[i]);
         Plan* pl;
-        int rc = prepare(t, ks[i], Ps[i], s, &pl);
+        int rc = prepare_operators(t, ks[i], Ps[i], s, &pl);
         if (rc) return rc;
         tv.push_back(&t);
         pv.push_back(pl);

@@ -132,7 +132,7 @@ int hfmm_matvec64(hfmm_tree* tree, double k, int32_t P, const void* x_dev, void*
     if (t.k_imag != 0.0) return set_error("the FP64 variant takes a real wavenumber"), HFMM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     Plan* pl;
-    if ((rc = prepare(t, k, P, s, &pl))) return rc;
+    if ((rc = prepare_operators(t, k, P, s, &pl))) return rc;
     return matvec64_impl(t, *pl, (const double2*)x_dev, (double2*)y_dev, s);
   } catch (const std::bad_alloc&) {
     set_error("host allocation failed");

@@ -271,6 +271,11 @@ struct Tree {
 
 double kappa_of(const Tree& t, int P);
 int build_plan_host(Tree& t, double k, int P, Plan& pl);   // cells + lists (host only)
+// Host lists, device operators and (BIE) corrections for (k, P).
+int prepare_operators(Tree& t, double k, int P, hipStream_t s, Plan** out);
+// prepare_operators plus the execution state of a single product (its work
+// lists, autotuned launch shape and side stream): a product then allocates
+// nothing.
 int prepare(Tree& t, double k, int P, hipStream_t s, Plan** out);
 int prepare_host(Tree& t, double k, int P, Plan** out);   // lists, operators, work (host only)
 int prepare_device(Tree& t, Plan& pl, hipStream_t s);      // upload and table generation
