@@ -141,3 +141,13 @@ def test_mie_accuracy_beats_flat_panels():
     ef = np.linalg.norm(bie.scattered_field(k, V, F, q, xobs) - ref) / np.linalg.norm(ref)
     print("nystrom s=1", e, "flat s=2", ef)
     assert e < 3e-3 and e * 10 < ef
+
+
+def test_dense_matrix_rows_subset():
+    """The rows= form of the oracle's Nystrom matrix is the full matrix's
+    rows, bit for bit (used for sampled rows at sizes the full matrix cannot
+    reach)."""
+    nodes, tri6 = synth.curved_icosphere(1)
+    Z = ny.dense_matrix(3.0, nodes, tri6)
+    rows = np.array([0, 5, 77, 400, 479])
+    assert np.array_equal(ny.dense_matrix(3.0, nodes, tri6, rows=rows), Z[rows])
