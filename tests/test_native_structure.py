@@ -157,3 +157,24 @@ def test_complex_wavenumber_lists_and_options():
         hfmm.Tree.from_mesh(V, T, k_imag=-0.5)
     with pytest.raises(hfmm.HfmmError):
         hfmm.Tree.from_curved_mesh(*synth.curved_icosphere(1), k_imag=-0.5)
+
+
+def test_host_plans_concurrent_equal_serial():
+    """Host plans (lists, operators, M2L pair orders) of several handles built
+    from a thread pool at once, each itself multi-threaded, have the same
+    footprints and statistics as the same plans built one after another."""
+    from concurrent.futures import ThreadPoolExecutor
+    cases = [(1 << 14, 11, 30.0), (1 << 15, 12, 20.0), (20000, 13, 45.0), (1 << 14, 14, 8.0)]
+
+    def plan(c):
+        n, seed, k = c
+        t = hfmm.Tree.from_points(synth.sphere_points(n, seed), ncrit=64)
+        fp = t.prepare_host(k, 10)
+        st = t.stats(k, 10)
+        t.free()
+        return fp, st["n_m2l"], st["n_tables"], st["p2p_body_pairs"]
+
+    serial = [plan(c) for c in cases]
+    with ThreadPoolExecutor(4) as ex:
+        concurrent = list(ex.map(plan, cases))
+    assert concurrent == serial
