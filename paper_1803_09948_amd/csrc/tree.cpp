@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -207,11 +209,13 @@ static inline bool mac(const HostTree& t, int a, int b, double k, double theta,
   return geo && (k * (2.0 * hmax) <= kappa);
 }
 
-void dual_tree_traversal(const HostTree& t, double k, double theta, double kappa, Lists& out) {
-  out = Lists();
+// Serial depth-first traversal of the pair (a0, b0), appending to out: the
+// stack pops children in the order they are stored.
+static void dtt_from(const HostTree& t, int32_t a0, int32_t b0, double k, double theta, double kappa,
+                     Lists& out) {
   std::vector<std::pair<int32_t, int32_t>> stack;
   stack.reserve(4096);
-  stack.push_back({0, 0});
+  stack.push_back({a0, b0});
   while (!stack.empty()) {
     auto [a, b] = stack.back();
     stack.pop_back();
@@ -232,6 +236,79 @@ void dual_tree_traversal(const HostTree& t, double k, double theta, double kappa
       for (int ch = t.ce[a] - 1; ch >= t.cb[a]; --ch) stack.push_back({ch, b});
     } else {
       for (int ch = t.ce[b] - 1; ch >= t.cb[b]; --ch) stack.push_back({a, ch});
+    }
+  }
+}
+
+// The traversal from (root, root).  The first levels are expanded into a
+// frontier in depth-first order (finished pairs stay in place); the frontier's
+// subtrees are then traversed on several threads and their lists appended in
+// frontier order, which is exactly the serial depth-first order.
+void dual_tree_traversal(const HostTree& t, double k, double theta, double kappa, Lists& out) {
+  out = Lists();
+  const int T = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  struct Item {
+    int32_t a, b;
+    int8_t kind;  // 0 open, 1 M2L, 2 P2P, 3 empty
+  };
+  std::vector<Item> front{{0, 0, 0}};
+  for (int round = 0; round < 12; ++round) {
+    size_t open = 0;
+    for (const Item& it : front) open += it.kind == 0;
+    if (open == 0 || open >= (size_t)64 * T) break;
+    std::vector<Item> next;
+    next.reserve(front.size() * 8);
+    for (const Item& it : front) {
+      if (it.kind != 0) {
+        next.push_back(it);
+        continue;
+      }
+      const int32_t a = it.a, b = it.b;
+      if (t.te[a] == t.tb[a] || t.se[b] == t.sb[b]) continue;
+      if (mac(t, a, b, k, theta, kappa)) {
+        next.push_back({a, b, 1});
+        continue;
+      }
+      bool la = t.leaf(a), lb = t.leaf(b);
+      if (la && lb) {
+        next.push_back({a, b, 2});
+        continue;
+      }
+      bool split_a = !la && (t.level[a] <= t.level[b] || lb);
+      if (split_a) {
+        for (int ch = t.cb[a]; ch < t.ce[a]; ++ch) next.push_back({ch, b, 0});
+      } else {
+        for (int ch = t.cb[b]; ch < t.ce[b]; ++ch) next.push_back({a, ch, 0});
+      }
+    }
+    front.swap(next);
+  }
+  std::vector<Lists> part(front.size());
+  std::atomic<size_t> cursor{0};
+  auto work = [&]() {
+    for (size_t i; (i = cursor.fetch_add(1)) < front.size();) {
+      const Item& it = front[i];
+      if (it.kind == 0) dtt_from(t, it.a, it.b, k, theta, kappa, part[i]);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int i = 1; i < T; ++i) th.emplace_back(work);
+  work();
+  for (auto& x : th) x.join();
+  for (size_t i = 0; i < front.size(); ++i) {
+    const Item& it = front[i];
+    if (it.kind == 1) {
+      out.m2l_a.push_back(it.a);
+      out.m2l_b.push_back(it.b);
+    } else if (it.kind == 2) {
+      out.p2p_a.push_back(it.a);
+      out.p2p_b.push_back(it.b);
+    } else if (it.kind == 0) {
+      const Lists& L = part[i];
+      out.m2l_a.insert(out.m2l_a.end(), L.m2l_a.begin(), L.m2l_a.end());
+      out.m2l_b.insert(out.m2l_b.end(), L.m2l_b.begin(), L.m2l_b.end());
+      out.p2p_a.insert(out.p2p_a.end(), L.p2p_a.begin(), L.p2p_a.end());
+      out.p2p_b.insert(out.p2p_b.end(), L.p2p_b.begin(), L.p2p_b.end());
     }
   }
 }
