@@ -148,7 +148,9 @@ int hfmm_nystrom_points(const hfmm_tree* tree, double* xyz_host, double* weight_
  * (the first call times each shape on this work; see hfmm_variant_count)
  * and a second stream with two events (the near field runs beside the far
  * field).  Afterwards hfmm_matvec on (k, P) allocates nothing.
- * Called implicitly by hfmm_matvec / hfmm_gmres_solve.
+ * Called implicitly by hfmm_matvec / hfmm_gmres_solve.  It allocates and
+ * waits on `stream`, so it must not run while `stream` is being captured
+ * into a graph.
  *  EINVAL: k <= 0 or non-finite, P outside [1, 16]. */
 int hfmm_prepare(hfmm_tree* tree, double k, int32_t P, void* stream);
 
