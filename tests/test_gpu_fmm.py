@@ -169,3 +169,27 @@ def test_m2l_staging_segments_bit_identical():
     y1 = hfmm.Tree.from_points(x).matvec(k, P, q).cpu().numpy()
     y2 = hfmm.Tree.from_points(x, stage_mb=1).matvec(k, P, q).cpu().numpy()
     np.testing.assert_array_equal(y1, y2)
+
+
+def test_overlapped_and_serial_sequences_bit_identical():
+    """The near field (P2P) runs on a second stream beside the far field, and
+    L2P adds the far field after it; with phase timing on, every phase runs
+    on one stream in the same order.  Both give the same bits, for a point
+    handle and for a BIE handle."""
+    n, k, P = 30000, 12.0, 10
+    x = synth.sphere_points(n, 41)
+    q = torch.from_numpy(synth.strengths(n, 41)).to("cuda")
+    t = hfmm.Tree.from_points(x, ncrit=32)
+    y0 = t.matvec(k, P, q).cpu().numpy()
+    t.set_timing(True)
+    y1 = t.matvec(k, P, q).cpu().numpy()
+    t.set_timing(False)
+    y2 = t.matvec(k, P, q).cpu().numpy()
+    assert np.array_equal(y0, y1) and np.array_equal(y0, y2)
+    V, T = synth.icosphere(4)
+    b = hfmm.Tree.from_mesh(V, T)
+    qb = torch.from_numpy(synth.strengths(len(T), 42)).to("cuda")
+    z0 = b.matvec(6.0, P, qb).cpu().numpy()
+    b.set_timing(True)
+    z1 = b.matvec(6.0, P, qb).cpu().numpy()
+    assert np.array_equal(z0, z1)
