@@ -194,17 +194,6 @@ def laplace_panel_analytic(x, a, b, c) -> float:
     return tot
 
 
-def near_pattern(pan, eta: float = 2.0):
-    """List of (i, j), j != i, with |c_i - c_j| < eta h_j."""
-    cen, h = pan["centroid"], pan["h"]
-    out = []
-    for i in range(len(cen)):
-        d = np.linalg.norm(cen - cen[i], axis=1)
-        js = np.flatnonzero(d < eta * h)
-        out += [(i, int(j)) for j in js if j != i]
-    return out
-
-
 def gauss_sources(pan):
     """Flattened 3 Gauss points per panel (panel-major) and their weights A/3."""
     nt = len(pan["area"])

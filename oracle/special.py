@@ -20,11 +20,6 @@ def idx(n: int, m: int) -> int:
     return n * n + n + m
 
 
-def nm_list(P: int):
-    """[(n, m)] in coefficient-index order for degrees 0..P-1."""
-    return [(n, m) for n in range(P) for m in range(-n, n + 1)]
-
-
 def sph_jn(n, x):
     return sp.spherical_jn(n, x)
 

@@ -209,12 +209,3 @@ def dual_tree_traversal(tree: Tree, k: float, theta: float, kappa: float):
         # push in reverse so that children are visited in Morton order
         stack.extend(reversed(kids))
     return m2l, p2p
-
-
-def tree_stats(tree: Tree, m2l, p2p) -> dict:
-    leaves = np.flatnonzero(tree.cb == tree.ce)
-    pp = sum(int(tree.te[a] - tree.tb[a]) * int(tree.se[b] - tree.sb[b]) for a, b in p2p)
-    return dict(ncell=tree.ncell, nleaf=len(leaves), nlevels=int(tree.level.max()) + 1,
-                n_m2l=len(m2l), n_p2p=len(p2p), p2p_body_pairs=pp)
-
-

@@ -160,3 +160,18 @@ def test_self_integral_elongated_panels(height, k):
     err = abs(smooth - brute) / abs(bie.self_integral(k, a, b, c))
     print(height, k, err)
     assert err < 1e-7
+
+
+@pytest.mark.parametrize("k", [2.0, 2 * np.pi, 6.0])
+def test_mie_density_modes_are_its_legendre_coefficients(k):
+    """The n-th Legendre coefficient of the Mie density (density_mode),
+    recovered independently by Gauss-Legendre projection of the density
+    itself: c_n = (2n+1)/2 * integral of q(theta) P_n(cos theta) over
+    cos theta in [-1, 1]."""
+    from scipy.special import eval_legendre
+    a = 1.0
+    x, w = np.polynomial.legendre.leggauss(120)
+    q = mie.density(k, a, np.arccos(x))
+    for n in range(0, mie.nmax_for(k * a) + 1):
+        cn = (2 * n + 1) / 2.0 * np.sum(w * q * eval_legendre(n, x))
+        assert abs(cn - mie.density_mode(k, a, n)) <= 1e-12 * max(1.0, abs(cn)), (n, cn)

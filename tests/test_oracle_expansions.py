@@ -124,3 +124,25 @@ def test_p2m_m2l_l2p_complex_wavenumber():
         errs.append(np.linalg.norm(ex.l2p(P, k, ct, L, xt) - ref) / np.linalg.norm(ref))
     assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
     assert errs[-1] < 1e-7
+
+
+def test_m2p_equals_direct_sum_far_from_the_sources():
+    """The multipole expansion evaluated at far points (M2P) converges to the
+    direct sum as P grows: the other half of the addition theorem, eq. (12),
+    with the roles of source and target exchanged (|x - c| > |y - c|)."""
+    k = 1.9
+    rng = np.random.default_rng(11)
+    c = np.array([0.1, -0.2, 0.05])
+    ys = c + rng.uniform(-0.15, 0.15, (25, 3))
+    q = rng.normal(size=25) + 1j * rng.normal(size=25)
+    xt = c + np.array([[1.2, 0.3, -0.4], [-0.9, 0.8, 0.2], [0.1, -0.2, 1.1]])
+    ref = direct_sum(k, xt, ys, q)
+    errs = []
+    for P in (2, 4, 6, 8, 10, 12):
+        M = ex.p2m(P, k, c, ys, q)
+        errs.append(np.linalg.norm(ex.m2p(P, k, c, M, xt) - ref) / np.linalg.norm(ref))
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+    assert errs[-1] < 1e-9
+    # a dropped factor (ik) or a conjugated multipole would be O(1) wrong
+    M = ex.p2m(12, k, c, ys, q)
+    assert np.linalg.norm(ex.m2p(12, k, c, np.conj(M), xt) - ref) > 0.1 * np.linalg.norm(ref)
