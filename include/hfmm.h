@@ -6,8 +6,10 @@
  * arXiv 1803.09948) with a spherical-harmonic fast multipole method over an
  * adaptive Morton-ordered octree (Sec. 2.3: upward P2M/M2M, traversal M2L/P2P,
  * downward L2L/L2P), and solves the sound-soft boundary integral equation
- * eq. (7) with restarted GMRES (Sec. 5.1, Sec. 6.4).  Every step runs as a
- * hand-written HIP kernel for gfx950.
+ * eq. (7) with restarted GMRES (Sec. 5.1, Sec. 6.4).  The tree build and the
+ * dual tree traversal (Sec. 3.1, Sec. 3.2) are setup and run in host C++;
+ * every step of the product and of GMRES runs as a hand-written HIP kernel
+ * for gfx950.
  *
  * Conventions shared by all calls
  *  - Return value: HFMM_OK (0) on success, a negative code on error, or
@@ -23,11 +25,17 @@
  *    (or panel) order; the Morton order is internal.
  *  - Expansion order P counts degrees 0..P-1 (P^2 coefficients; the text
  *    after eq. (14)).  1 <= P <= 16.
- *  - A tree handle owns its device memory (allocated at build time and when
- *    a new (k, P) operator is first prepared; never inside a matvec that
- *    reuses a prepared operator; GMRES adds its Krylov workspace on the first
- *    solve with a given restart).  Handles may be used from several host
- *    threads only with external serialisation.
+ *  - A tree handle owns its device memory.  Building a handle touches no
+ *    device memory; the bodies are uploaded and the operators of a (k, P)
+ *    are built on the device when that (k, P) is first prepared (explicitly
+ *    by hfmm_prepare, or implicitly by the first product or solve); a
+ *    product that reuses a prepared (k, P) allocates nothing; GMRES adds its
+ *    Krylov workspace on the first solve with a given restart.
+ *    hfmm_tree_plan reports every one of these sizes beforehand, on the
+ *    host.  A handle keeps one set of product buffers (strengths, sorted
+ *    outputs, expansions, staging), so calls on one handle must not overlap:
+ *    from several host threads or on several streams they need external
+ *    serialisation (a stream-ordered wait between them suffices).
  */
 #ifndef HFMM_H
 #define HFMM_H
@@ -83,6 +91,26 @@ typedef struct {
   int64_t n_near;             /* BIE near-correction nonzeros */
   int64_t device_bytes;       /* device memory held by the handle */
 } hfmm_stats;
+
+/* Sizes of a (k, P) plan, computed on the host before any device memory is
+ * touched (hfmm_tree_plan).  Bytes are device bytes. */
+typedef struct {
+  int64_t n_src, n_tgt;       /* bodies */
+  int32_t n_cell, n_leaf, n_level;  /* cells of the tree used at (k, P) */
+  int32_t resident;           /* 1 when the (k, P) operators are already on the device */
+  int64_t n_m2l, n_p2p;       /* traversal cell pairs */
+  int64_t p2p_body_pairs;     /* sum over P2P pairs of n_tgt * n_src */
+  int64_t n_tables;           /* distinct M2L translation operators */
+  int64_t n_near;             /* BIE near-correction nonzeros */
+  int64_t bytes_tree;         /* resident bodies, permutations, BIE geometry and near
+                                 pattern, and the cells of the (k, P) tree */
+  int64_t bytes_lists;        /* M2L pair records, P2P work and source intervals */
+  int64_t bytes_expansions;   /* translation tables, multipole and local expansions
+                                 M, L (2 x cells x P^2 complex64), M2L staging */
+  int64_t bytes_corrections;  /* BIE near values and self terms at k (0 for points) */
+  int64_t bytes_gmres;        /* GMRES(restart) workspace (0 for point handles) */
+  int64_t bytes_total;        /* sum of the five above */
+} hfmm_plan_info;
 
 typedef struct {
   int32_t iters;       /* matrix-vector products inside Arnoldi steps */
@@ -212,7 +240,8 @@ int hfmm_bie_plane_wave(hfmm_tree* tree, double k, const double* dir_host,
  * equal to hfmm_matvec on that instance alone: every phase sums in a fixed
  * order (the M2L through staging slots reduced per target).
  * trees, ks, Ps, xs_dev, ys_dev: arrays of length count.  EINVAL as for
- * hfmm_matvec, count < 1, differing P, or a BIE handle. */
+ * hfmm_matvec, count < 1, differing P, a BIE handle, or a handle that appears
+ * twice (its instances would share the handle's product buffers). */
 int hfmm_batch_matvec(int32_t count, hfmm_tree* const* trees, const double* ks,
                       const int32_t* Ps, const void* const* xs_dev,
                       void* const* ys_dev, void* stream);
@@ -224,27 +253,51 @@ int hfmm_batch_matvec(int32_t count, hfmm_tree* const* trees, const double* ks,
  * threads.  footprint_bytes may be NULL.  EINVAL as for hfmm_prepare. */
 int hfmm_prepare_host(hfmm_tree* tree, double k, int32_t P, int64_t* footprint_bytes);
 
+/* Plan of a (k, P) product and solve on the host (the admission question
+ * of a matrix-free GMRES, Sec. 1 and Sec. 2.3): builds the tree used at
+ * (k, P), the traversal lists and the work lists (as hfmm_prepare_host; kept
+ * for the later device half), and reports counts and the device bytes of
+ * each part.  Touches no device memory.  restart: the GMRES restart the
+ * workspace is sized for (1..200 for BIE handles, 0 allowed for point
+ * handles, whose bytes_gmres is 0).  The counts are those hfmm_tree_stats
+ * reports after preparation; the bytes are what the library allocates.
+ *  EINVAL: NULL, k or P as for hfmm_prepare, restart out of range. */
+int hfmm_tree_plan(hfmm_tree* tree, double k, int32_t P, int32_t restart,
+                   hfmm_plan_info* out);
+
 /* ---- Continuous-batching solve server -----------------------------------
  * Serves many BIE solves at once.  Submitted solves wait in a queue; every
  * hfmm_server_step admits queued solves (first come, first served) while
  * fewer than max_active run and their device footprint fits the budget
  * (0 = no limit), then advances each running solve by one GMRES product: a
- * single fused FMM launch sequence for all of them, then each solve's FP64
- * Arnoldi / residual work, and one host synchronisation for all.  Solves
- * join and leave at step boundaries; each result is that of
- * hfmm_gmres_solve on the same system up to FP32 rounding in the fused M2L.
- * Handles, b and x must stay valid until the solve is done; one solve per
- * handle at a time.  Not thread-safe: drive a server from one thread. */
+ * fused FMM launch sequence per expansion order P present among them, then
+ * each solve's FP64 Arnoldi / residual work, and one host synchronisation
+ * for all.  Solves join and leave at step boundaries; each result is
+ * bitwise that of hfmm_gmres_solve on the same system (every accumulation
+ * of the fused sequence has the order of the single product).  Handles, b
+ * and x must stay valid until the solve is done; one solve per handle at a
+ * time.  Not thread-safe: drive a server from one thread. */
 typedef struct hfmm_server hfmm_server;
 
 int hfmm_server_create(int64_t hbm_budget_bytes, int32_t max_active, hfmm_server** out);
+/* Early-stop policy (failure detection for solves that cannot converge in
+ * reasonable time; off by default).  At each restart boundary, after the
+ * true residual is known, a solve stops in state 4 when
+ *  - stall_restarts > 0 and its true relative residual is not below
+ *    stall_factor times its value stall_restarts restarts earlier, or
+ *  - max_seconds > 0 and it has been active longer than max_seconds.
+ * x then holds the last iterate and info its residuals.
+ *  EINVAL: stall_restarts < 0, stall_factor outside (0, 1], max_seconds < 0. */
+int hfmm_server_set_limits(hfmm_server* server, int32_t stall_restarts, double stall_factor,
+                           double max_seconds);
 /* Queues a solve; *ticket identifies it, *footprint_bytes (may be NULL) is
  * the device memory it will hold while active.  ENOMEM if it can never fit. */
 int hfmm_server_submit(hfmm_server* server, hfmm_tree* tree, double k, int32_t P,
                        const void* b_dev, void* x_dev, double tol, int32_t restart,
                        int32_t maxit, int64_t* ticket, int64_t* footprint_bytes);
 int hfmm_server_step(hfmm_server* server, void* stream, int32_t* n_active, int32_t* n_queued);
-/* state: 0 queued, 1 active, 2 converged, 3 not converged (maxit), -1 failed.
+/* state: 0 queued, 1 active, 2 converged, 3 not converged (maxit), 4 stopped
+ * early (hfmm_server_set_limits), -1 failed.
  * times3 (may be NULL): submit, admit and completion times (seconds, steady
  * clock). */
 int hfmm_server_poll(hfmm_server* server, int64_t ticket, int32_t* state,
@@ -304,6 +357,12 @@ int hfmm_tree_variant(hfmm_tree* tree, double k, int32_t P, int32_t phase, int32
 void hfmm_tree_free(hfmm_tree* tree);
 const char* hfmm_last_error(void);
 int hfmm_version(void);
+
+/* Test hook for the error paths: after = n >= 0 makes the (n+1)-th next
+ * device allocation of the library fail with HFMM_ENOMEM without calling
+ * hipMalloc (then the hook turns itself off); -1 turns it off.
+ * Process-wide.  EINVAL: after < -1. */
+int hfmm_debug_fail_alloc(int64_t after);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,11 @@ uint64_t next_uid() { return g_uid.fetch_add(1); }
     }                                                                              \
   } while (0)
 
+// Allocation-failure hook for tests of the error paths: when >= 0, the
+// countdown reaches the allocation to fail, which then reports ENOMEM
+// without calling hipMalloc.
+static std::atomic<int64_t> g_fail_alloc{-1};
+
 DevBuf::~DevBuf() { reset(); }
 int DevBuf::ensure(size_t n) {
   if (p && bytes >= n) return HFMM_OK;
@@ -46,6 +51,10 @@ int DevBuf::alloc(size_t n) {
     bytes = 0;
   }
   if (n == 0) n = 16;
+  if (g_fail_alloc.load() >= 0 && g_fail_alloc.fetch_sub(1) == 0) {
+    set_error(std::string("hipMalloc(") + std::to_string(n) + "): failure injected by hfmm_debug_fail_alloc");
+    return HFMM_ENOMEM;
+  }
   hipError_t e = hipMalloc(&p, n);
   if (e != hipSuccess) {
     p = nullptr;
@@ -67,6 +76,22 @@ static int upload(DevBuf& b, const std::vector<T>& v) {
 Tree::~Tree() {
   if (ev_made)
     for (auto& e : ev) (void)hipEventDestroy(e);
+}
+
+// Device bytes of a handle's resident data: sorted float4 positions, source
+// indices, weights (BIE) and target permutation, float2 strengths and sorted
+// outputs (what upload_bodies allocates); BIE handles add the near pattern
+// (CSR offsets, columns and rows) and the panel geometry (flat: 9 doubles
+// per panel; curved: the element nodes, points and near work items).
+int64_t body_bytes(const Tree& t) {
+  const int64_t ns = t.h.nsrc, nt = t.h.ntgt;
+  int64_t b = ns * (16 + 4 + 8) + nt * (16 + 4 + 8);
+  if (t.bie) {
+    const int64_t nnz = (int64_t)t.near_col.size();
+    b += ns * 4 + (t.npanel + 1) * 4 + nnz * 8;
+    b += t.nystrom ? t.npanel * (24 + 24) + (int64_t)t.nys_items.size() * 16 + 4096 : t.npanel * 72 + 1024;
+  }
+  return b;
 }
 
 int upload_bodies(Tree& t) {
@@ -454,14 +479,23 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     table_dims(P, &Kp, &Rp);
     stage_dims(P, &Sm, &St);
     const int64_t nc = h.ncell();
-    int64_t b = nc * (int64_t)(sizeof(int4) * 2 + sizeof(float4) + sizeof(int32_t) + sizeof(int2));
-    b += (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)Kp * Rp * sizeof(float2));
-    b += (int64_t)spairs.size() * 17 + pl.max_seg_slots * (int64_t)(Sm + St) * (int64_t)sizeof(float2) + (nc + 1) * 4;
-    b += (int64_t)pl.rho.size() * 8 + (int64_t)spairs.size() * 16 + (int64_t)work.size() * 20 +
-         (int64_t)ivals.size() * 8 + (17 * (int64_t)Kp + 16 * P2) * 4 + 2 * nc * P2 * (int64_t)sizeof(float2);
-    if (t.bie) b += (int64_t)t.near_col.size() * 8 + t.npanel * (t.nystrom ? 96 : 16);
-    if (!t.uploaded) b += t.h.nsrc * 40 + t.h.ntgt * 32;
-    pl.est_bytes = b;
+    // cells (int4 bodies, float4 geometry, level, int4 topology, int2 operators)
+    pl.bytes_cells = nc * (int64_t)(sizeof(int4) * 2 + sizeof(float4) + sizeof(int32_t) + sizeof(int2));
+    // work lists: M2L pair records (int4) and slot reflections (uint8), the
+    // per-target slot offsets, P2P work items, source intervals and totals,
+    // the reflection code tables
+    pl.bytes_lists = (int64_t)spairs.size() * 17 + (nc + 1) * 4 + (int64_t)work.size() * 20 +
+                     (int64_t)ivals.size() * 8 + (17 * (int64_t)Kp + 16 * P2) * 4;
+    // operators (descriptors and padded tables), level scales, M and L, the
+    // M2L staging of the largest segment
+    pl.bytes_exp = (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)Kp * Rp * sizeof(float2)) +
+                   (int64_t)pl.rho.size() * 8 + 2 * nc * P2 * (int64_t)sizeof(float2) +
+                   std::max<int64_t>(1, pl.max_seg_slots) * (int64_t)(Sm + St) * (int64_t)sizeof(float2);
+    // BIE corrections: near values (float2) and the self term (double2 per
+    // panel, or a 6 x 6 double2 block row per curved-element point)
+    pl.bytes_corr = t.bie ? (int64_t)t.near_col.size() * 8 + t.npanel * (t.nystrom ? 96 : 16) : 0;
+    pl.est_bytes = pl.bytes_cells + pl.bytes_lists + pl.bytes_exp + pl.bytes_corr +
+                   (t.uploaded ? 0 : body_bytes(t));
   }
   t.plans[key] = std::move(plp);
   *out = t.plans[key].get();
@@ -469,7 +503,10 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
 }
 
 int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
-  if (pl.d_tables.p) return HFMM_OK;
+  // device_ready is set only after every step below succeeded: a failed
+  // step leaves the plan not ready, and the next call redoes it from the
+  // start (each buffer's alloc replaces what an earlier attempt left).
+  if (pl.device_ready) return HFMM_OK;
   int rc;
   if (!t.uploaded && (rc = upload_bodies(t))) return rc;
   if ((rc = upload_cells(pl))) return rc;
@@ -514,12 +551,10 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
                     &pl.d_L, &pl.d_cops, &pl.d_stage, &pl.d_m2l_soff, &pl.d_bmap, &pl.d_omap,
                     &pl.d_slot_g})
     pl.device_bytes += (int64_t)b->bytes;
-  if (t.bie && (rc = (t.nystrom ? prepare_nystrom(t, pl, s) : prepare_bie(t, pl, s)))) {
-    pl.d_tables.reset();  // not device-ready: the next prepare retries
-    return rc;
-  }
+  if (t.bie && (rc = (t.nystrom ? prepare_nystrom(t, pl, s) : prepare_bie(t, pl, s)))) return rc;
   pl.device_bytes += (int64_t)(pl.d_near_val.bytes + pl.d_diag.bytes);
   pl.hd.reset();
+  pl.device_ready = true;
   return HFMM_OK;
 }
 
@@ -594,6 +629,12 @@ using namespace hfmm;
 extern "C" {
 
 int hfmm_version(void) { return 100; }
+
+int hfmm_debug_fail_alloc(int64_t after) {
+  if (after < -1) return set_error("after must be >= -1"), HFMM_EINVAL;
+  g_fail_alloc.store(after);
+  return HFMM_OK;
+}
 const char* hfmm_last_error(void) { return g_err.c_str(); }
 
 int hfmm_default_opts(hfmm_opts* o) {
@@ -660,7 +701,41 @@ int hfmm_prepare_host(hfmm_tree* tree, double k, int32_t P, int64_t* footprint) 
   Plan* pl;
   Tree& t = *reinterpret_cast<Tree*>(tree);
   if ((rc = prepare_host(t, k, P, &pl))) return rc;
-  if (footprint) *footprint = pl->d_tables.p ? 0 : pl->est_bytes;
+  if (footprint) *footprint = pl->device_ready ? 0 : pl->est_bytes;
+  return HFMM_OK;
+  API_GUARD_END
+}
+
+int hfmm_tree_plan(hfmm_tree* tree, double k, int32_t P, int32_t restart, hfmm_plan_info* out) {
+  API_GUARD_BEGIN
+  if (!tree || !out) return set_error("NULL argument"), HFMM_EINVAL;
+  int rc = check_kP(k, P);
+  if (rc) return rc;
+  Tree& t = *reinterpret_cast<Tree*>(tree);
+  if (restart < 0 || restart > 200 || (t.bie && restart < 1))
+    return set_error("restart in [1, 200] (0 for point handles)"), HFMM_EINVAL;
+  Plan* pl;
+  if ((rc = prepare_host(t, k, P, &pl))) return rc;
+  hfmm_plan_info info{};
+  info.n_src = t.h.nsrc;
+  info.n_tgt = t.h.ntgt;
+  info.n_cell = pl->ct.ncell();
+  for (int i = 0; i < pl->ct.ncell(); ++i) info.n_leaf += pl->ct.leaf(i) ? 1 : 0;
+  info.n_level = pl->ct.nlevels();
+  info.n_m2l = (int64_t)pl->lists.m2l_a.size();
+  info.n_p2p = (int64_t)pl->lists.p2p_a.size();
+  info.p2p_body_pairs = pl->p2p_body_pairs;
+  info.n_tables = pl->n_tables;
+  info.n_near = t.bie ? (int64_t)t.near_col.size() : 0;
+  info.bytes_tree = body_bytes(t) + pl->bytes_cells;
+  info.bytes_lists = pl->bytes_lists;
+  info.bytes_expansions = pl->bytes_exp;
+  info.bytes_corrections = pl->bytes_corr;
+  info.bytes_gmres = t.bie && restart > 0 ? gmres_workspace_bytes(t.npanel, restart) : 0;
+  info.bytes_total = info.bytes_tree + info.bytes_lists + info.bytes_expansions + info.bytes_corrections +
+                     info.bytes_gmres;
+  info.resident = pl->device_ready ? 1 : 0;
+  *out = info;
   return HFMM_OK;
   API_GUARD_END
 }

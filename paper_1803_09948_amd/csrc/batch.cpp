@@ -87,6 +87,20 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
   b.graph = nullptr;
   b.count = (int)trees.size();
   b.P = plans[0]->P;
+  // the kernels of one sequence are instantiated for one P, and each
+  // instance gathers, accumulates and scatters through its tree's own
+  // buffers: differing P or a tree that appears twice cannot share a batch
+  for (int i = 0; i < b.count; ++i) {
+    if (plans[i]->P != b.P) {
+      set_error("all instances of a fused batch need the same P");
+      return HFMM_EINVAL;
+    }
+    for (int j = 0; j < i; ++j)
+      if (trees[j] == trees[i]) {
+        set_error("a tree handle appears twice in one fused batch");
+        return HFMM_EINVAL;
+      }
+  }
   b.trees = trees;
   b.plans = plans;
   b.hinst.clear();
@@ -432,6 +446,10 @@ extern "C" int hfmm_batch_matvec(int32_t count, hfmm_tree* const* trees, const d
       if (Ps[i] != Ps[0]) return set_error("all instances of a batch need the same P"), HFMM_EINVAL;
       Tree& t = *reinterpret_cast<Tree*>(trees[i]);
       if (t.bie) return set_error("batched products take point-mode handles"), HFMM_EINVAL;
+      for (int j = 0; j < i; ++j)
+        if (trees[j] == trees[i])
+          return set_error("a tree handle appears twice in one batch (its instances would share buffers)"),
+                 HFMM_EINVAL;
       uint64_t kb;
       std::memcpy(&kb, &ks[i], 8);
       key.push_back(t.uid);

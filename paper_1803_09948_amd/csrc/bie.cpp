@@ -99,7 +99,7 @@ static void near_pattern(const std::vector<double>& cen, const std::vector<doubl
 int prepare_bie(Tree& t, Plan& pl, hipStream_t s) {
   int rc;
   const int64_t n = t.npanel;
-  if (!t.d_near_off.p) {
+  if (!t.near_ready) {  // set only once every upload below succeeded
     std::vector<int32_t> rows(t.near_col.size());
     for (int64_t i = 0; i < n; ++i)
       for (int q = t.near_off[i]; q < t.near_off[i + 1]; ++q) rows[q] = (int32_t)i;
@@ -118,7 +118,8 @@ int prepare_bie(Tree& t, Plan& pl, hipStream_t s) {
     if ((rc = upload_vec(t.d_near_off, t.near_off)) || (rc = upload_vec(t.d_near_col, t.near_col)) ||
         (rc = upload_vec(t.d_near_row, rows)) || (rc = upload_vec(t.d_gl, gl)))
       return rc;
-    if (!t.d_panels.p && (rc = upload_vec(t.d_panels, panels))) return rc;
+    if ((rc = upload_vec(t.d_panels, panels))) return rc;
+    t.near_ready = true;
   }
   const int ng = t.near_order;
   const double* gl = t.d_gl.as<double>();
@@ -148,6 +149,7 @@ int prepare_bie(Tree& t, Plan& pl, hipStream_t s) {
 // ---------------------------------------------------------------------------
 static int gm_workspace(Tree& t, int m) {
   if (t.gm_m == m && t.g_V.p) return HFMM_OK;
+  t.gm_m = 0;  // not sized for any restart until every buffer below is allocated
   const size_t n = (size_t)t.npanel;
   int rc;
   if ((rc = t.g_V.alloc((size_t)(m + 1) * n * sizeof(double2))) || (rc = t.g_w.alloc(n * sizeof(double2))) ||
@@ -162,6 +164,15 @@ static int gm_workspace(Tree& t, int m) {
     return rc;
   t.gm_m = m;
   return HFMM_OK;
+}
+
+// Krylov basis V [m+1][n], work vectors w, r (double2) and x64, y64
+// (float2), Hessenberg H [m+1][m], Givens cs, sn, right-hand side g,
+// projections h, h2, partial sums, a dot product, status and the small
+// solution y: what gm_workspace and the server's solves allocate.
+int64_t gmres_workspace_bytes(int64_t n, int m) {
+  return (int64_t)(m + 1) * n * 16 + 2 * n * 16 + 2 * n * 8 + (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 +
+         (int64_t)(m + 1) * 16 * 2 + 2 * (int64_t)(m + 32) * 16 + (int64_t)mdot_blocks() * 32 * 16 + 16 + 16;
 }
 
 // out = A v (FP64 in/out; FMM and near corrections in FP32, self term in FP64)

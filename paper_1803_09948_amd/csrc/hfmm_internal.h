@@ -166,6 +166,8 @@ struct Plan {
   int64_t n_near = 0;
   int64_t device_bytes = 0;
   int64_t est_bytes = 0;                 // footprint computed before any allocation
+  int64_t bytes_cells = 0, bytes_lists = 0, bytes_exp = 0, bytes_corr = 0;  // its parts
+  bool device_ready = false;             // prepare_device completed (set last)
   std::unique_ptr<HostPlanData> hd;      // present between host and device preparation
 };
 
@@ -244,6 +246,7 @@ struct Tree {
   // BIE near pattern (geometry only), caller panel order
   std::vector<int32_t> near_off, near_col;
   DevBuf d_near_off, d_near_row, d_near_col;
+  bool near_ready = false;      // near pattern and geometry are on the device
   DevBuf d_gl;                  // Gauss-Legendre nodes/weights on [0,1]: near (n), self (10)
   // curved-element Nystrom handle: unknowns are the six points of each
   // element (npanel = 6 x elements), element-major
@@ -298,5 +301,8 @@ int upload_vec(DevBuf& b, const std::vector<T>& v, bool grow_only = false) {
   return HFMM_OK;
 }
 int upload_bodies(Tree& t);
+int64_t body_bytes(const Tree& t);
+// Device bytes of the GMRES workspace of an n-unknown system at restart m.
+int64_t gmres_workspace_bytes(int64_t n, int m);
 
 }  // namespace hfmm

@@ -165,7 +165,7 @@ float nystrom_weight(int64_t p) { return (float)rule6().w[p % 6]; }
 int prepare_nystrom(Tree& t, Plan& pl, hipStream_t s) {
   int rc;
   const int64_t N = t.npanel;
-  if (!t.d_nys_K.p) {
+  if (!t.near_ready) {  // set only once every upload below succeeded
     NysConst K{};
     const Rule6& R = rule6();
     for (int i = 0; i < 6; ++i) {
@@ -194,6 +194,7 @@ int prepare_nystrom(Tree& t, Plan& pl, hipStream_t s) {
         (rc = upload_vec(t.d_nys_items, t.nys_items)) || (rc = upload_vec(t.d_near_off, t.near_off)) ||
         (rc = upload_vec(t.d_near_col, t.near_col)) || (rc = upload_vec(t.d_near_row, rows)))
       return rc;
+    t.near_ready = true;
   }
   pl.n_near = (int64_t)t.near_col.size();
   if ((rc = pl.d_near_val.alloc(std::max<size_t>(1, t.near_col.size()) * sizeof(float2))) ||

@@ -34,7 +34,9 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-enum SolveState : int32_t { S_QUEUED = 0, S_ACTIVE = 1, S_CONVERGED = 2, S_NOTCONV = 3, S_FAILED = -1 };
+enum SolveState : int32_t {
+  S_QUEUED = 0, S_ACTIVE = 1, S_CONVERGED = 2, S_NOTCONV = 3, S_STOPPED = 4, S_FAILED = -1
+};
 enum Phase : int { PH_RESIDUAL = 0, PH_ARNOLDI = 1 };
 
 struct Solve {
@@ -49,6 +51,7 @@ struct Solve {
   int state = S_QUEUED, phase = PH_RESIDUAL, j = 0, iters = 0, restarts = 0;
   double bnorm = 0, est = INFINITY, resid_true = INFINITY;
   double t_submit = 0, t_admit = 0, t_done = 0;
+  std::vector<double> restart_resid;  // true relative residual at each restart boundary
   DevBuf V, w, r, x64, y64, H, cs, sn, g, h, h2, part, dot, st, yv;
   double* slot = nullptr;  // 2 doubles in the server's pinned read-back area
 };
@@ -60,19 +63,19 @@ struct Server {
   std::deque<Solve*> queue;
   std::vector<Solve*> active;
   std::map<int64_t, std::unique_ptr<Solve>> solves;
-  std::unique_ptr<Batch> batch;
+  std::map<int, std::unique_ptr<Batch>> batches;  // one fused sequence per expansion order P
   bool composition_changed = true;
+  // early stop (0 = off): a solve whose true residual has not fallen below
+  // stall_factor times its value stall_restarts restarts earlier, or that
+  // has run longer than max_seconds since admission, ends in S_STOPPED
+  int stall_restarts = 0;
+  double stall_factor = 0.5, max_seconds = 0.0;
   double* pinned = nullptr;  // 2 doubles per slot
   int pinned_slots = 0;
   ~Server() {
     if (pinned) (void)hipHostFree(pinned);
   }
 };
-
-static int64_t workspace_bytes(int64_t n, int m) {
-  return (int64_t)(m + 1) * n * 16 + 2 * n * 16 + 2 * n * 8 + (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 +
-         (int64_t)(m + 1) * 16 * 2 + 2 * (m + 32) * 16 + (int64_t)mdot_blocks() * 32 * 16 + 64;
-}
 
 static int alloc_workspace(Solve& v) {
   const size_t n = (size_t)v.t->npanel;
@@ -158,34 +161,57 @@ static int admit(Server& sv, hipStream_t s) {
   return HFMM_OK;
 }
 
+// Early-stop policy, checked at each restart boundary after the true
+// residual is known (and recorded).
+static bool stop_early(Server& sv, Solve& v) {
+  v.restart_resid.push_back(v.resid_true);
+  const int nr = (int)v.restart_resid.size();
+  if (sv.stall_restarts > 0 && nr > sv.stall_restarts &&
+      !(v.resid_true < sv.stall_factor * v.restart_resid[nr - 1 - sv.stall_restarts]))
+    return true;
+  return sv.max_seconds > 0.0 && now_s() - v.t_admit > sv.max_seconds;
+}
+
 static int step(Server& sv, hipStream_t s) {
   int rc = admit(sv, s);
   if (rc) return rc;
   if (sv.active.empty()) return HFMM_OK;
-  if (sv.composition_changed || !sv.batch) {
-    std::vector<Tree*> tv;
-    std::vector<Plan*> pv;
-    for (Solve* v : sv.active) {
-      tv.push_back(v->t);
-      pv.push_back(v->pl);
-    }
-    if (!sv.batch) sv.batch = std::make_unique<Batch>();
-    if ((rc = build_batch(tv, pv, *sv.batch))) {
-      sv.batch.reset();
-      return rc;
+  // Active solves grouped by expansion order: the kernels of a fused
+  // sequence are instantiated for one P, so each P present gets its own
+  // sequence (in increasing P, solves in admission order within a group).
+  std::map<int, std::vector<Solve*>> groups;
+  for (Solve* v : sv.active) groups[v->P].push_back(v);
+  if (sv.composition_changed) {
+    for (auto it = sv.batches.begin(); it != sv.batches.end();)
+      it = groups.count(it->first) ? std::next(it) : sv.batches.erase(it);
+    for (auto& kv : groups) {
+      std::vector<Tree*> tv;
+      std::vector<Plan*> pv;
+      for (Solve* v : kv.second) {
+        tv.push_back(v->t);
+        pv.push_back(v->pl);
+      }
+      std::unique_ptr<Batch>& b = sv.batches[kv.first];
+      if (!b) b = std::make_unique<Batch>();
+      if ((rc = build_batch(tv, pv, *b))) {
+        sv.batches.clear();
+        return rc;
+      }
     }
     sv.composition_changed = false;
   }
-  // inputs of this step's product: x (residual phase) or v_j (Arnoldi phase)
-  std::vector<const float2*> xs;
-  std::vector<float2*> ys;
-  for (Solve* v : sv.active) {
-    const double2* in = v->phase == PH_RESIDUAL ? v->x : v->V.as<double2>() + (size_t)v->j * v->t->npanel;
-    launch_to_c64(v->t->npanel, in, v->x64.as<float2>(), s);
-    xs.push_back(v->x64.as<float2>());
-    ys.push_back(v->y64.as<float2>());
+  // inputs of this step's products: x (residual phase) or v_j (Arnoldi phase)
+  for (auto& kv : groups) {
+    std::vector<const float2*> xs;
+    std::vector<float2*> ys;
+    for (Solve* v : kv.second) {
+      const double2* in = v->phase == PH_RESIDUAL ? v->x : v->V.as<double2>() + (size_t)v->j * v->t->npanel;
+      launch_to_c64(v->t->npanel, in, v->x64.as<float2>(), s);
+      xs.push_back(v->x64.as<float2>());
+      ys.push_back(v->y64.as<float2>());
+    }
+    if ((rc = run_batch(*sv.batches[kv.first], xs.data(), ys.data(), s, false, nullptr))) return rc;
   }
-  if ((rc = run_batch(*sv.batch, xs.data(), ys.data(), s, false, nullptr))) return rc;
   for (size_t i = 0; i < sv.active.size(); ++i) {
     Solve& v = *sv.active[i];
     Tree& t = *v.t;
@@ -233,6 +259,8 @@ static int step(Server& sv, hipStream_t s) {
         finish(sv, v, S_CONVERGED);
       } else if (v.iters >= v.maxit) {
         finish(sv, v, S_NOTCONV);
+      } else if (stop_early(sv, v)) {
+        finish(sv, v, S_STOPPED);
       } else {
         launch_scale_by_norm(n, v.r.as<double2>(), v.dot.as<double2>(), v.V.as<double2>(), s);
         launch_init_g(v.m, v.dot.as<double2>(), v.g.as<double2>(), s);
@@ -278,6 +306,17 @@ int hfmm_server_create(int64_t hbm_budget_bytes, int32_t max_active, hfmm_server
   return HFMM_OK;
 }
 
+int hfmm_server_set_limits(hfmm_server* server, int32_t stall_restarts, double stall_factor,
+                           double max_seconds) {
+  if (!server || stall_restarts < 0 || !(stall_factor > 0.0 && stall_factor <= 1.0) || !(max_seconds >= 0.0))
+    return set_error("need stall_restarts >= 0, 0 < stall_factor <= 1, max_seconds >= 0"), HFMM_EINVAL;
+  Server& sv = *reinterpret_cast<Server*>(server);
+  sv.stall_restarts = stall_restarts;
+  sv.stall_factor = stall_factor;
+  sv.max_seconds = max_seconds;
+  return HFMM_OK;
+}
+
 int hfmm_server_submit(hfmm_server* server, hfmm_tree* tree, double k, int32_t P, const void* b_dev,
                        void* x_dev, double tol, int32_t restart, int32_t maxit, int64_t* ticket,
                        int64_t* footprint) {
@@ -307,7 +346,7 @@ int hfmm_server_submit(hfmm_server* server, hfmm_tree* tree, double k, int32_t P
     v->maxit = maxit;
     v->b = (const double2*)b_dev;
     v->x = (double2*)x_dev;
-    v->bytes = (pl->d_tables.p ? 0 : pl->est_bytes) + workspace_bytes(t.npanel, restart);
+    v->bytes = (pl->device_ready ? 0 : pl->est_bytes) + gmres_workspace_bytes(t.npanel, restart);
     if (sv.budget > 0 && v->bytes > sv.budget) return set_error("solve exceeds the memory budget"), HFMM_ENOMEM;
     v->t_submit = now_s();
     *ticket = v->ticket;

@@ -25,7 +25,8 @@ EXPORTS = [
     "hfmm_server_create", "hfmm_server_submit", "hfmm_server_step", "hfmm_server_poll",
     "hfmm_server_release", "hfmm_server_used_bytes", "hfmm_server_free",
     "hfmm_variant_count", "hfmm_set_variant", "hfmm_tree_variant", "hfmm_matvec64", "hfmm_direct64",
-    "hfmm_build_nystrom", "hfmm_nystrom_points",
+    "hfmm_build_nystrom", "hfmm_nystrom_points", "hfmm_tree_plan", "hfmm_server_set_limits",
+    "hfmm_debug_fail_alloc",
 ]
 
 
@@ -47,6 +48,18 @@ class Stats(C.Structure):
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["centre"] = list(self.centre)
         return d
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("n_src", C.c_int64), ("n_tgt", C.c_int64), ("n_cell", C.c_int32),
+                ("n_leaf", C.c_int32), ("n_level", C.c_int32), ("resident", C.c_int32),
+                ("n_m2l", C.c_int64), ("n_p2p", C.c_int64), ("p2p_body_pairs", C.c_int64),
+                ("n_tables", C.c_int64), ("n_near", C.c_int64), ("bytes_tree", C.c_int64),
+                ("bytes_lists", C.c_int64), ("bytes_expansions", C.c_int64),
+                ("bytes_corrections", C.c_int64), ("bytes_gmres", C.c_int64), ("bytes_total", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class GmresInfo(C.Structure):
@@ -106,6 +119,9 @@ def lib():
             "hfmm_direct64": [vp, vp, i64, vp, i64, dbl, vp, vp],
             "hfmm_build_nystrom": [vp, i64, vp, i64, C.POINTER(Opts), C.POINTER(vp)],
             "hfmm_nystrom_points": [vp, vp, vp, vp],
+            "hfmm_tree_plan": [vp, dbl, i32, i32, C.POINTER(PlanInfo)],
+            "hfmm_server_set_limits": [vp, i32, dbl, dbl],
+            "hfmm_debug_fail_alloc": [i64],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -130,6 +146,24 @@ def default_opts(**kw) -> Opts:
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def _dev_vec(v, dtype, n, name):
+    """Checks a device vector before its pointer crosses the ABI: dtype,
+    contiguity, placement on the GPU and length (the library reads and writes
+    exactly n entries through the pointer)."""
+    import torch
+    if not isinstance(v, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor")
+    if v.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {v.dtype}")
+    if not v.is_cuda:
+        raise ValueError(f"{name}: must be on the GPU")
+    if not v.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if v.numel() != n:
+        raise ValueError(f"{name}: expected {n} entries, got {v.numel()}")
+    return C.c_void_p(v.data_ptr())
 
 
 def _stream(torch, stream):
@@ -202,6 +236,13 @@ class Tree:
         _check(lib().hfmm_prepare_host(self._h, float(k), int(P), C.byref(fp)))
         return fp.value
 
+    def plan(self, k: float, P: int, restart: int = 30) -> dict:
+        """Counts and device bytes of the (k, P) plan (host only; see hfmm_tree_plan)."""
+        info = PlanInfo()
+        r = int(restart) if self.bie else 0
+        _check(lib().hfmm_tree_plan(self._h, float(k), int(P), r, C.byref(info)))
+        return info.as_dict()
+
     def prepare(self, k: float, P: int, stream=None):
         import torch
         _check(lib().hfmm_prepare(self._h, float(k), int(P), _stream(torch, stream)))
@@ -209,29 +250,31 @@ class Tree:
     def matvec(self, k: float, P: int, x, y=None, stream=None):
         """y = A x on the GPU; x: complex64 CUDA tensor of length n."""
         import torch
-        assert x.dtype == torch.complex64 and x.is_cuda and x.is_contiguous() and x.numel() == self.n_in
+        xp = _dev_vec(x, torch.complex64, self.n_in, "x")
         if y is None:
             y = torch.empty(self.n_out, dtype=torch.complex64, device=x.device)
-        _check(lib().hfmm_matvec(self._h, float(k), int(P), C.c_void_p(x.data_ptr()),
-                                 C.c_void_p(y.data_ptr()), _stream(torch, stream)))
+        yp = _dev_vec(y, torch.complex64, self.n_out, "y")
+        _check(lib().hfmm_matvec(self._h, float(k), int(P), xp, yp, _stream(torch, stream)))
         return y
 
     def matvec64(self, k: float, P: int, x, y=None, stream=None):
         """FP64 variant of matvec (same tree, lists and P); x: complex128 CUDA tensor."""
         import torch
-        assert x.dtype == torch.complex128 and x.is_cuda and x.is_contiguous() and x.numel() == self.n_in
+        xp = _dev_vec(x, torch.complex128, self.n_in, "x")
         if y is None:
             y = torch.empty(self.n_out, dtype=torch.complex128, device=x.device)
-        _check(lib().hfmm_matvec64(self._h, float(k), int(P), C.c_void_p(x.data_ptr()),
-                                   C.c_void_p(y.data_ptr()), _stream(torch, stream)))
+        yp = _dev_vec(y, torch.complex128, self.n_out, "y")
+        _check(lib().hfmm_matvec64(self._h, float(k), int(P), xp, yp, _stream(torch, stream)))
         return y
 
     def gmres(self, k: float, P: int, b, x0=None, tol=1e-4, restart=30, maxit=2000, stream=None):
         import torch
-        assert b.dtype == torch.complex128 and b.is_cuda and b.numel() == self.n_out
+        bp = _dev_vec(b, torch.complex128, self.n_out, "b")
+        if x0 is not None:
+            _dev_vec(x0, torch.complex128, self.n_in, "x0")
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         info = GmresInfo()
-        rc = _check(lib().hfmm_gmres_solve(self._h, float(k), int(P), C.c_void_p(b.data_ptr()),
+        rc = _check(lib().hfmm_gmres_solve(self._h, float(k), int(P), bp,
                                            C.c_void_p(x.data_ptr()), float(tol), int(restart),
                                            int(maxit), C.byref(info), _stream(torch, stream)))
         d = info.as_dict()
@@ -295,14 +338,22 @@ def direct64(src, q, tgt, k, stream=None):
     """FP64 direct sum on the GPU: src, tgt float32 CUDA tensors [n][3], [m][3];
     q complex128 CUDA tensor [n]; returns complex128 [m]."""
     import torch
-    assert src.dtype == torch.float32 and tgt.dtype == torch.float32 and q.dtype == torch.complex128
-    assert src.is_cuda and tgt.is_cuda and q.is_cuda
     src, tgt, q = src.contiguous(), tgt.contiguous(), q.contiguous()
+    if src.dim() != 2 or src.shape[1] != 3 or tgt.dim() != 2 or tgt.shape[1] != 3:
+        raise ValueError("src and tgt must have shape [n][3]")
+    _dev_vec(src, torch.float32, 3 * src.shape[0], "src")
+    _dev_vec(tgt, torch.float32, 3 * tgt.shape[0], "tgt")
+    _dev_vec(q, torch.complex128, src.shape[0], "q")
     y = torch.empty(tgt.shape[0], dtype=torch.complex128, device=tgt.device)
     _check(lib().hfmm_direct64(C.c_void_p(src.data_ptr()), C.c_void_p(q.data_ptr()), int(src.shape[0]),
                                C.c_void_p(tgt.data_ptr()), int(tgt.shape[0]), float(k),
                                C.c_void_p(y.data_ptr()), _stream(torch, stream)))
     return y
+
+
+def debug_fail_alloc(after: int):
+    """Test hook: the (after+1)-th next device allocation fails with ENOMEM (-1: off)."""
+    _check(lib().hfmm_debug_fail_alloc(int(after)))
 
 
 def variant_count(P: int, phase: int = PHASE_M2L) -> int:
@@ -322,6 +373,11 @@ def batch_matvec(trees, ks, Ps, xs, ys, stream=None):
     """Fused product over independent point-mode trees: ys[i] = A_i xs[i]."""
     import torch
     n = len(trees)
+    if not (len(ks) == len(Ps) == len(xs) == len(ys) == n):
+        raise ValueError("trees, ks, Ps, xs and ys need the same length")
+    for i, t in enumerate(trees):
+        _dev_vec(xs[i], torch.complex64, t.n_in, f"xs[{i}]")
+        _dev_vec(ys[i], torch.complex64, t.n_out, f"ys[{i}]")
     H = (C.c_void_p * n)(*[t._h.value for t in trees])
     K = (C.c_double * n)(*[float(k) for k in ks])
     PP = (C.c_int32 * n)(*[int(p) for p in Ps])
@@ -334,21 +390,27 @@ def batch_matvec(trees, ks, Ps, xs, ys, stream=None):
 class Server:
     """Continuous-batching solve server (see hfmm_server_* in include/hfmm.h)."""
 
-    QUEUED, ACTIVE, CONVERGED, NOTCONV, FAILED = 0, 1, 2, 3, -1
+    QUEUED, ACTIVE, CONVERGED, NOTCONV, STOPPED, FAILED = 0, 1, 2, 3, 4, -1
 
     def __init__(self, hbm_budget_bytes: int = 0, max_active: int = 16):
         h = C.c_void_p()
         _check(lib().hfmm_server_create(int(hbm_budget_bytes), int(max_active), C.byref(h)))
         self._h = h
 
+    def set_limits(self, stall_restarts: int = 0, stall_factor: float = 0.5, max_seconds: float = 0.0):
+        """Early stop of solves that stagnate or run too long (state STOPPED)."""
+        _check(lib().hfmm_server_set_limits(self._h, int(stall_restarts), float(stall_factor),
+                                            float(max_seconds)))
+
     def submit(self, tree: Tree, k: float, P: int, b, x, tol=1e-4, restart=30, maxit=2000):
         """Queues A x = b on a BIE handle; b, x complex128 CUDA tensors."""
         import torch
-        assert b.dtype == torch.complex128 and x.dtype == torch.complex128 and b.is_cuda and x.is_cuda
+        bp = _dev_vec(b, torch.complex128, tree.n_out, "b")
+        xp = _dev_vec(x, torch.complex128, tree.n_in, "x")
         t = C.c_int64()
         fp = C.c_int64()
-        _check(lib().hfmm_server_submit(self._h, tree._h, float(k), int(P), C.c_void_p(b.data_ptr()),
-                                        C.c_void_p(x.data_ptr()), float(tol), int(restart), int(maxit),
+        _check(lib().hfmm_server_submit(self._h, tree._h, float(k), int(P), bp,
+                                        xp, float(tol), int(restart), int(maxit),
                                         C.byref(t), C.byref(fp)))
         return t.value, fp.value
 

@@ -35,34 +35,54 @@ def _build(req, meshes, P):
     return tree, fp
 
 
-def _stats(lat, makespan, iters, statuses):
+def _pct(v, q):
+    return float(np.percentile(v, q) * 1e3) if len(v) else None
+
+
+def _stats(lat, makespan, iters, statuses, records):
+    """Throughput and latency over all solves, and latency over the converged
+    ones alone (the non-converged count beside them)."""
     lat = np.asarray(lat)
+    ok = np.asarray([s == hfmm.Server.CONVERGED for s in statuses], bool)
     return {
         "n": int(len(lat)),
         "solves_per_s": float(len(lat) / makespan) if makespan > 0 else 0.0,
-        "p50_ms": float(np.percentile(lat, 50) * 1e3) if len(lat) else None,
-        "p99_ms": float(np.percentile(lat, 99) * 1e3) if len(lat) else None,
+        "p50_ms": _pct(lat, 50),
+        "p99_ms": _pct(lat, 99),
         "mean_ms": float(lat.mean() * 1e3) if len(lat) else None,
+        "converged": int(ok.sum()),
+        "p50_converged_ms": _pct(lat[ok], 50) if len(lat) else None,
+        "p99_converged_ms": _pct(lat[ok], 99) if len(lat) else None,
         "makespan_s": float(makespan),
         "iters_p50": float(np.percentile(iters, 50)) if iters else None,
         "iters_max": int(max(iters)) if iters else None,
         "not_converged": int(sum(1 for s in statuses if s != hfmm.Server.CONVERGED)),
+        "stopped_early": int(sum(1 for s in statuses if s == hfmm.Server.STOPPED)),
+        "records": records,
     }
 
 
+def _record(req, st, info, latency):
+    return dict(id=req["id"], subdiv=req["subdiv"], axes=list(req["axes"]), k=req["k"], state=int(st),
+                iters=int(info["iters"]), resid_true=float(info["resid_true"]), latency_ms=latency * 1e3)
+
+
 def serve(trace, P=10, tol=1e-4, restart=30, maxit=2000, max_active=16, hbm_budget=0, workers=8,
-          keep_solutions=False, log=None):
+          keep_solutions=False, log=None, stall_restarts=0, stall_factor=0.5, max_seconds=0.0):
     """Runs the trace through the continuous-batching server; returns stats
-    (and, with keep_solutions, {request id: x as numpy})."""
+    (and, with keep_solutions, {request id: x as numpy}).  stall_restarts,
+    stall_factor and max_seconds set the server's early-stop policy
+    (hfmm_server_set_limits; off by default)."""
     import torch
 
     meshes = _meshes(trace)
     reqs = sorted(trace, key=lambda r: r["t_arrival"])
     server = hfmm.Server(hbm_budget, max_active)
+    server.set_limits(stall_restarts, stall_factor, max_seconds)
     pool = ThreadPoolExecutor(max_workers=workers)
     building = {}
     inflight = {}          # ticket -> (req, tree, b, x)
-    lat, iters, statuses = [], [], []
+    lat, iters, statuses, records = [], [], [], []
     sols = {}
     peak_active = 0
     t0 = time.perf_counter()
@@ -93,6 +113,7 @@ def serve(trace, P=10, tol=1e-4, restart=30, maxit=2000, max_active=16, hbm_budg
                 lat.append(tnow - req["t_arrival"])
                 iters.append(info["iters"])
                 statuses.append(st)
+                records.append(_record(req, st, info, lat[-1]))
                 if keep_solutions:
                     sols[req["id"]] = x.cpu().numpy()
                 server.release(ticket)
@@ -108,7 +129,7 @@ def serve(trace, P=10, tol=1e-4, restart=30, maxit=2000, max_active=16, hbm_budg
     makespan = time.perf_counter() - t0
     pool.shutdown()
     server.free()
-    out = _stats(lat, makespan, iters, statuses)
+    out = _stats(lat, makespan, iters, statuses, records)
     out.update(steps=steps, peak_active=peak_active)
     return (out, sols) if keep_solutions else out
 
@@ -119,7 +140,7 @@ def serve_plain(trace, P=10, tol=1e-4, restart=30, maxit=2000, keep_solutions=Fa
 
     meshes = _meshes(trace)
     reqs = sorted(trace, key=lambda r: r["t_arrival"])
-    lat, iters, statuses = [], [], []
+    lat, iters, statuses, records = [], [], [], []
     sols = {}
     t0 = time.perf_counter()
     for req in reqs:
@@ -133,11 +154,12 @@ def serve_plain(trace, P=10, tol=1e-4, restart=30, maxit=2000, keep_solutions=Fa
         lat.append(time.perf_counter() - t0 - req["t_arrival"])
         iters.append(info["iters"])
         statuses.append(hfmm.Server.CONVERGED if info["converged"] else hfmm.Server.NOTCONV)
+        records.append(_record(req, statuses[-1], info, lat[-1]))
         if keep_solutions:
             sols[req["id"]] = x.cpu().numpy()
         tree.free()
         if log:
             log(f"plain id={req['id']} it={info['iters']} lat={lat[-1]*1e3:.1f} ms")
     makespan = time.perf_counter() - t0
-    out = _stats(lat, makespan, iters, statuses)
+    out = _stats(lat, makespan, iters, statuses, records)
     return (out, sols) if keep_solutions else out

@@ -178,3 +178,56 @@ def test_host_plans_concurrent_equal_serial():
     with ThreadPoolExecutor(4) as ex:
         concurrent = list(ex.map(plan, cases))
     assert concurrent == serial
+
+
+def test_tree_plan_counts_and_bytes():
+    """hfmm_tree_plan (host only): its counts are those of the oracle's tree
+    and traversal at (k, P), its bytes add up, M and L take 2 x cells x P^2
+    complex64, the GMRES workspace grows with the restart, and bad arguments
+    are refused."""
+    x = synth.sphere_points(3000, 21)
+    k, P = 9.0, 8
+    t = hfmm.Tree.from_points(x, ncrit=32)
+    pl = t.plan(k, P)
+    o = build_tree(x, None, 32, split_side=0.4 * P / k)
+    om2l, op2p = dual_tree_traversal(o, k, 0.5, 0.4 * P)
+    assert pl["n_cell"] == len(o.level) and pl["n_leaf"] == int(np.sum(o.cb == o.ce))
+    assert pl["n_m2l"] == len(om2l) and pl["n_p2p"] == len(op2p)
+    npairs = sum(int((o.te[a] - o.tb[a]) * (o.se[b] - o.sb[b])) for a, b in op2p)
+    assert pl["p2p_body_pairs"] == npairs
+    assert pl["n_src"] == pl["n_tgt"] == 3000 and pl["resident"] == 0 and pl["bytes_gmres"] == 0
+    parts = ("bytes_tree", "bytes_lists", "bytes_expansions", "bytes_corrections", "bytes_gmres")
+    assert pl["bytes_total"] == sum(pl[p] for p in parts)
+    assert pl["bytes_expansions"] >= 2 * pl["n_cell"] * P * P * 8
+    assert pl["bytes_total"] == t.prepare_host(k, P)       # the footprint the device half allocates
+    st = t.stats(k, P)
+    assert (st["n_m2l"], st["n_tables"], st["p2p_body_pairs"]) == (pl["n_m2l"], pl["n_tables"],
+                                                                   pl["p2p_body_pairs"])
+    V, T = synth.icosphere(2)
+    tb = hfmm.Tree.from_mesh(V, T)
+    a, b = tb.plan(3.0, 6, restart=10), tb.plan(3.0, 6, restart=30)
+    assert 0 < a["bytes_gmres"] < b["bytes_gmres"] and a["bytes_corrections"] > 0
+    assert b["bytes_gmres"] >= 31 * len(T) * 16
+    for args in ((0.0, 8, 0), (1.0, 0, 0), (1.0, 17, 0), (1.0, 8, 201)):
+        with pytest.raises(hfmm.HfmmError) as e:
+            hfmm._check(hfmm.lib().hfmm_tree_plan(t._h, args[0], args[1], args[2], hfmm.C.byref(hfmm.PlanInfo())))
+        assert e.value.code == hfmm.HFMM_EINVAL
+    with pytest.raises(hfmm.HfmmError):
+        hfmm._check(hfmm.lib().hfmm_tree_plan(tb._h, 3.0, 6, 0, hfmm.C.byref(hfmm.PlanInfo())))
+
+
+def test_binding_checks_device_vectors():
+    """The binding refuses vectors of the wrong dtype, length or placement
+    before any pointer reaches the library (no device needed)."""
+    torch = pytest.importorskip("torch")
+    t = hfmm.Tree.from_points(synth.sphere_points(64, 2))
+    with pytest.raises((TypeError, ValueError)):
+        t.matvec(1.0, 4, torch.zeros(64, dtype=torch.complex64))           # host tensor
+    with pytest.raises((TypeError, ValueError)):
+        hfmm._dev_vec(torch.zeros(64, dtype=torch.complex128), torch.complex64, 64, "x")
+    with pytest.raises((TypeError, ValueError)):
+        hfmm.batch_matvec([t], [1.0], [4], [torch.zeros(63, dtype=torch.complex64)],
+                          [torch.zeros(64, dtype=torch.complex64)])
+    with pytest.raises(hfmm.HfmmError):
+        hfmm.debug_fail_alloc(-2)
+    hfmm.debug_fail_alloc(-1)
