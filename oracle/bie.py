@@ -19,6 +19,8 @@ triangles with one unknown per panel, collocated at the centroid):
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 from .fmm import green
@@ -42,9 +44,15 @@ def panels(verts, tris):
     return dict(centroid=cen, area=area, h=h, normal=nrm, gauss=gp, a=a, b=b, c=c)
 
 
+@functools.lru_cache(maxsize=None)
 def _gl01(n: int):
+    """Gauss-Legendre nodes and weights on [0, 1] (computed once per n; the
+    arrays are read-only)."""
     x, w = np.polynomial.legendre.leggauss(n)
-    return 0.5 * (x + 1.0), 0.5 * w
+    u, wu = 0.5 * (x + 1.0), 0.5 * w
+    u.flags.writeable = False
+    wu.flags.writeable = False
+    return u, wu
 
 
 def duffy_rule(p, q, r, n: int):
