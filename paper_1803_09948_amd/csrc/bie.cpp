@@ -63,10 +63,18 @@ static void near_pattern(const std::vector<double>& cen, const std::vector<doubl
     hmax = std::max(hmax, h[i]);
     for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], cen[3 * i + d]);
   }
-  const double cs = std::max(eta * hmax, 1e-300);
+  double ext = 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) ext = std::max(ext, cen[3 * i + d] - lo[d]);
+  // cells no smaller than eta * max h (a larger cell only adds candidates,
+  // which the distance test filters), and at most 2^20 of them per axis, so
+  // that a cell index plus one and its neighbours fit 21 bits of the key
+  const double cs = std::max({eta * hmax, ext / double(1 << 20), 1e-300});
   auto cell = [&](int64_t i, int d) { return (int64_t)std::floor((cen[3 * i + d] - lo[d]) / cs); };
-  auto key = [](int64_t a, int64_t b, int64_t c) { return (a << 42) ^ (b << 21) ^ c; };
-  std::unordered_map<int64_t, std::vector<int32_t>> grid;
+  auto key = [](int64_t a, int64_t b, int64_t c) {  // cells -1 .. 2^20 + 1 -> distinct keys
+    return ((uint64_t)(a + 1) << 42) ^ ((uint64_t)(b + 1) << 21) ^ (uint64_t)(c + 1);
+  };
+  std::unordered_map<uint64_t, std::vector<int32_t>> grid;
   grid.reserve((size_t)n);
   for (int64_t i = 0; i < n; ++i) grid[key(cell(i, 0), cell(i, 1), cell(i, 2))].push_back((int32_t)i);
   off.assign(n + 1, 0);
@@ -147,46 +155,69 @@ int prepare_bie(Tree& t, Plan& pl, hipStream_t s) {
 // GMRES(m) in FP64 with two passes of classical Gram-Schmidt (CGS2) and
 // complex Givens rotations; the FMM product in FP32, the self term in FP64.
 // ---------------------------------------------------------------------------
-static int gm_workspace(Tree& t, int m) {
-  if (t.gm_m == m && t.g_V.p) return HFMM_OK;
-  t.gm_m = 0;  // not sized for any restart until every buffer below is allocated
-  const size_t n = (size_t)t.npanel;
-  int rc;
-  if ((rc = t.g_V.alloc((size_t)(m + 1) * n * sizeof(double2))) || (rc = t.g_w.alloc(n * sizeof(double2))) ||
-      (rc = t.g_r.alloc(n * sizeof(double2))) || (rc = t.g_x64.alloc(n * sizeof(float2))) ||
-      (rc = t.g_y64.alloc(n * sizeof(float2))) || (rc = t.g_H.alloc((size_t)(m + 1) * m * sizeof(double2))) ||
-      (rc = t.g_cs.alloc((size_t)m * sizeof(double))) || (rc = t.g_sn.alloc((size_t)m * sizeof(double2))) ||
-      (rc = t.g_g.alloc((size_t)(m + 1) * sizeof(double2))) || (rc = t.g_h.alloc((size_t)(m + 32) * sizeof(double2))) ||
-      (rc = t.g_h2.alloc((size_t)(m + 32) * sizeof(double2))) ||
-      (rc = t.g_part.alloc((size_t)mdot_blocks() * 32 * sizeof(double2))) ||
-      (rc = t.g_dot.alloc(sizeof(double2))) || (rc = t.g_st.alloc(2 * sizeof(double))) ||
-      (rc = t.g_yv.alloc((size_t)(m + 1) * sizeof(double2))))
-    return rc;
-  t.gm_m = m;
+// Layout of the workspace of one GMRES(m) solve on n unknowns, each array
+// 256-byte aligned: Krylov basis V [m+1][n], work vectors w, r (double2) and
+// x64, y64 (float2), Hessenberg H [m+1][m], Givens cs, sn, right-hand side
+// g, projections h, h2, partial sums, a dot product, status st and the small
+// solution yv.  With base == nullptr only the size is computed.
+static int64_t gmres_layout(char* base, int64_t n, int m, GmresWork* W) {
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  GmresWork w{};
+  w.V = (double2*)take((int64_t)(m + 1) * n * 16);
+  w.w = (double2*)take(n * 16);
+  w.r = (double2*)take(n * 16);
+  w.x64 = (float2*)take(n * 8);
+  w.y64 = (float2*)take(n * 8);
+  w.H = (double2*)take((int64_t)(m + 1) * m * 16);
+  w.cs = (double*)take((int64_t)m * 8);
+  w.sn = (double2*)take((int64_t)m * 16);
+  w.g = (double2*)take((int64_t)(m + 1) * 16);
+  w.h = (double2*)take((int64_t)(m + 32) * 16);
+  w.h2 = (double2*)take((int64_t)(m + 32) * 16);
+  w.part = (double2*)take((int64_t)mdot_blocks() * 32 * 16);
+  w.dot = (double2*)take(16);
+  w.st = (double*)take(16);
+  w.yv = (double2*)take((int64_t)(m + 1) * 16);
+  if (W) *W = w;
+  return off;
+}
+
+int64_t gmres_workspace_bytes(int64_t n, int m) { return gmres_layout(nullptr, n, m, nullptr); }
+
+GmresWork gmres_carve(void* base, int64_t n, int m) {
+  GmresWork w;
+  gmres_layout((char*)base, n, m, &w);
+  return w;
+}
+
+static int gm_workspace(Tree& t, int m, GmresWork* W) {
+  if (t.gm_m != m || !t.g_ws.p) {
+    t.gm_m = 0;  // not sized for any restart until the buffer is allocated
+    int rc = t.g_ws.alloc((size_t)gmres_workspace_bytes(t.npanel, m));
+    if (rc) return rc;
+    t.gm_m = m;
+  }
+  *W = gmres_carve(t.g_ws.p, t.npanel, m);
   return HFMM_OK;
 }
 
-// Krylov basis V [m+1][n], work vectors w, r (double2) and x64, y64
-// (float2), Hessenberg H [m+1][m], Givens cs, sn, right-hand side g,
-// projections h, h2, partial sums, a dot product, status and the small
-// solution y: what gm_workspace and the server's solves allocate.
-int64_t gmres_workspace_bytes(int64_t n, int m) {
-  return (int64_t)(m + 1) * n * 16 + 2 * n * 16 + 2 * n * 8 + (int64_t)(m + 1) * m * 16 + (int64_t)m * 24 +
-         (int64_t)(m + 1) * 16 * 2 + 2 * (int64_t)(m + 32) * 16 + (int64_t)mdot_blocks() * 32 * 16 + 16 + 16;
-}
-
 // out = A v (FP64 in/out; FMM and near corrections in FP32, self term in FP64)
-static int apply_A(Tree& t, Plan& pl, const double2* v, double2* out, hipStream_t s) {
+static int apply_A(Tree& t, Plan& pl, const GmresWork& W, const double2* v, double2* out, hipStream_t s) {
   const int64_t n = t.npanel;
-  launch_to_c64(n, v, t.g_x64.as<float2>(), s);
-  int rc = matvec_impl(t, pl, t.g_x64.as<float2>(), t.g_y64.as<float2>(), s);
+  launch_to_c64(n, v, W.x64, s);
+  int rc = matvec_impl(t, pl, W.x64, W.y64, s);
   if (rc) return rc;
   launch_near_apply(n, t.d_near_off.as<int32_t>(), t.d_near_col.as<int32_t>(), pl.d_near_val.as<float2>(),
-                    nullptr, t.g_x64.as<float2>(), t.g_y64.as<float2>(), s);
+                    nullptr, W.x64, W.y64, s);
   if (t.nystrom)
-    launch_from_c64_self6(n, t.g_y64.as<float2>(), pl.d_self6.as<double2>(), v, out, s);
+    launch_from_c64_self6(n, W.y64, pl.d_self6.as<double2>(), v, out, s);
   else
-    launch_from_c64_diag(n, t.g_y64.as<float2>(), pl.d_diag.as<double2>(), v, out, s);
+    launch_from_c64_diag(n, W.y64, pl.d_diag.as<double2>(), v, out, s);
   HIP_TRY(hipGetLastError());
   return HFMM_OK;
 }
@@ -204,19 +235,18 @@ static int read_doubles(const void* dev, double* host, int cnt, hipStream_t s) {
   return HFMM_OK;
 }
 
-static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, int m, int maxit,
-                 hfmm_gmres_info* info, hipStream_t s) {
+int gmres_run(Tree& t, Plan& pl, const GmresWork& W, int m, const double2* b, double2* x, double tol,
+              int maxit, hfmm_gmres_info* info, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   const int64_t n = t.npanel;
-  int rc = gm_workspace(t, m);
-  if (rc) return rc;
-  double2* V = t.g_V.as<double2>();
-  double2* w = t.g_w.as<double2>();
-  double2* r = t.g_r.as<double2>();
-  double2* h = t.g_h.as<double2>();
-  double2* h2 = t.g_h2.as<double2>();
-  double2* part = t.g_part.as<double2>();
-  double2* dotv = t.g_dot.as<double2>();
+  int rc;
+  double2* V = W.V;
+  double2* w = W.w;
+  double2* r = W.r;
+  double2* h = W.h;
+  double2* h2 = W.h2;
+  double2* part = W.part;
+  double2* dotv = W.dot;
   double hv[2];
   // ||b||
   launch_mdot(n, 1, b, n, b, part, dotv, 0, s);
@@ -224,7 +254,8 @@ static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, in
   const double bnorm = std::sqrt(hv[0]);
   hfmm_gmres_info inf{};
   if (bnorm == 0.0) {
-    HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double2), s));
+    launch_zero_c128(n, x, s);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     if (info) *info = inf;
     return HFMM_OK;
@@ -234,7 +265,7 @@ static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, in
   int status = HFMM_ENOTCONV;
   for (;;) {
     // true residual r = b - A x
-    if ((rc = apply_A(t, pl, x, r, s))) return rc;
+    if ((rc = apply_A(t, pl, W, x, r, s))) return rc;
     launch_residual(n, b, r, s);
     launch_mdot(n, 1, r, n, r, part, dotv, 0, s);
     if ((rc = read_doubles(dotv, hv, 1, s))) return rc;
@@ -250,11 +281,11 @@ static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, in
     }
     if (iters >= maxit) break;
     launch_scale_by_norm(n, r, dotv, V, s);
-    launch_init_g(m, dotv, t.g_g.as<double2>(), s);
+    launch_init_g(m, dotv, W.g, s);
     int done = 0;
     for (int j = 0; j < m; ++j) {
       double2* vj = V + (size_t)j * n;
-      if ((rc = apply_A(t, pl, vj, w, s))) return rc;
+      if ((rc = apply_A(t, pl, W, vj, w, s))) return rc;
       // CGS2: two passes of classical Gram-Schmidt against V[0..j]
       mdot_all(n, j + 1, V, w, part, h, 0, s);
       launch_mupdate(n, j + 1, V, n, h, w, -1.0, s);
@@ -262,13 +293,12 @@ static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, in
       launch_mupdate(n, j + 1, V, n, h2, w, -1.0, s);
       launch_vec_add(j + 1, h2, h, s);  // h += h2
       launch_mdot(n, 1, w, n, w, part, dotv, 0, s);
-      launch_givens(j, m, h, dotv, t.g_H.as<double2>(), t.g_cs.as<double>(), t.g_sn.as<double2>(),
-                    t.g_g.as<double2>(), t.g_st.as<double>(), s);
+      launch_givens(j, m, h, dotv, W.H, W.cs, W.sn, W.g, W.st, s);
       launch_scale_by_norm(n, w, dotv, V + (size_t)(j + 1) * n, s);
       HIP_TRY(hipGetLastError());
       ++iters;
       done = j + 1;
-      if ((rc = read_doubles(t.g_st.p, hv, 2, s))) return rc;
+      if ((rc = read_doubles(W.st, hv, 2, s))) return rc;
       est = hv[0] / bnorm;
       if (!std::isfinite(est)) {
         set_error("GMRES Arnoldi residual estimate is not finite");
@@ -276,8 +306,8 @@ static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, in
       }
       if (est <= tol || iters >= maxit || hv[1] == 0.0) break;
     }
-    launch_backsolve(done, m, t.g_H.as<double2>(), t.g_g.as<double2>(), t.g_yv.as<double2>(), s);
-    launch_mupdate(n, done, V, n, t.g_yv.as<double2>(), x, 1.0, s);
+    launch_backsolve(done, m, W.H, W.g, W.yv, s);
+    launch_mupdate(n, done, V, n, W.yv, x, 1.0, s);
     HIP_TRY(hipGetLastError());
     ++restarts;
   }
@@ -288,6 +318,14 @@ static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, in
   inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = inf;
   return status;
+}
+
+static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, int m, int maxit,
+                 hfmm_gmres_info* info, hipStream_t s) {
+  GmresWork W;
+  int rc = gm_workspace(t, m, &W);
+  if (rc) return rc;
+  return gmres_run(t, pl, W, m, b, x, tol, maxit, info, s);
 }
 
 }  // namespace hfmm

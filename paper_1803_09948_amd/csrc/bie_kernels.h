@@ -28,6 +28,7 @@ void launch_mupdate(int64_t n, int nv, const double2* V, int64_t ld, const doubl
                     double sign, hipStream_t s);
 void launch_scale_by_norm(int64_t n, const double2* src, const double2* dotval, double2* dst, hipStream_t s);
 void launch_residual(int64_t n, const double2* b, double2* r, hipStream_t s);
+void launch_zero_c128(int64_t n, double2* x, hipStream_t s);  // x[0..n) = 0 (a kernel, capture-safe)
 void launch_givens(int j, int m, const double2* h, const double2* wn, double2* H, double* cs, double2* sn,
                    double2* g, double* st, hipStream_t s);
 void launch_backsolve(int kk, int m, const double2* H, const double2* g, double2* y, hipStream_t s);

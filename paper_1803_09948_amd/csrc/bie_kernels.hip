@@ -366,6 +366,11 @@ __global__ void k_residual(int64_t n, const double2* __restrict__ b, double2* __
   r[e] = make_double2(b[e].x - r[e].x, b[e].y - r[e].y);
 }
 
+__global__ void k_zero_c128(int64_t n, double2* __restrict__ x) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] = make_double2(0.0, 0.0);
+}
+
 // Arnoldi column j: H[0..j][j] = h, H[j+1][j] = ||w||; apply the previous
 // Givens rotations, form rotation j, update g.  One thread.
 // Layout: H column-major (m+1) x m; cs, sn: m entries; g: m+1 entries.
@@ -484,6 +489,9 @@ void launch_mupdate(int64_t n, int nv, const double2* V, int64_t ld, const doubl
 }
 void launch_scale_by_norm(int64_t n, const double2* src, const double2* dotval, double2* dst, hipStream_t s) {
   if (n > 0) k_scale_by_norm<<<nblk(n, 256), 256, 0, s>>>(n, src, dotval, dst);
+}
+void launch_zero_c128(int64_t n, double2* x, hipStream_t s) {
+  if (n > 0) k_zero_c128<<<nblk(n, 256), 256, 0, s>>>(n, x);
 }
 void launch_residual(int64_t n, const double2* b, double2* r, hipStream_t s) {
   if (n > 0) k_residual<<<nblk(n, 256), 256, 0, s>>>(n, b, r);

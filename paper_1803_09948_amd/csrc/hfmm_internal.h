@@ -259,7 +259,7 @@ struct Tree {
   int nys_nrule = 0;
   // GMRES workspace (kept between solves)
   int gm_m = 0;
-  DevBuf g_V, g_w, g_r, g_x64, g_y64, g_H, g_cs, g_sn, g_g, g_h, g_h2, g_part, g_dot, g_st, g_yv;
+  DevBuf g_ws;                  // one buffer, carved by gmres_carve
   DevBuf d_q, d_ys;             // float2 per source / target
   DevBuf d_q64, d_ys64;         // double2 per source / target (FP64 variant)
   int64_t body_bytes = 0;
@@ -302,7 +302,18 @@ int upload_vec(DevBuf& b, const std::vector<T>& v, bool grow_only = false) {
 }
 int upload_bodies(Tree& t);
 int64_t body_bytes(const Tree& t);
-// Device bytes of the GMRES workspace of an n-unknown system at restart m.
+// Device workspace of one GMRES(m) solve on n unknowns: pointers into one
+// buffer of gmres_workspace_bytes(n, m) bytes (256-byte aligned parts).
+struct GmresWork {
+  double2 *V, *w, *r, *H, *sn, *g, *h, *h2, *part, *dot, *yv;
+  float2 *x64, *y64;
+  double *cs, *st;
+};
 int64_t gmres_workspace_bytes(int64_t n, int m);
+GmresWork gmres_carve(void* base, int64_t n, int m);
+// Restarted GMRES(m) of a BIE handle on a prepared plan, in workspace W
+// (contents on entry do not matter).  Allocates nothing.
+int gmres_run(Tree& t, Plan& pl, const GmresWork& W, int m, const double2* b, double2* x, double tol,
+              int maxit, hfmm_gmres_info* info, hipStream_t s);
 
 }  // namespace hfmm

@@ -297,10 +297,18 @@ int hfmm_build_nystrom(const double* nodes, int64_t nn, const int32_t* tri6, int
       hmax = std::max(hmax, h[e]);
       for (int dd = 0; dd < 3; ++dd) lo[dd] = std::min(lo[dd], cen[3 * e + dd]);
     }
-    const double cs = std::max(t->eta * hmax, 1e-300);
+    double ext = 0.0;
+    for (int64_t e = 0; e < nt; ++e)
+      for (int dd = 0; dd < 3; ++dd) ext = std::max(ext, cen[3 * e + dd] - lo[dd]);
+    // cells no smaller than eta * max h, at most 2^20 per axis; a point lies
+    // within h of its element's centroid, so its cell is at most one outside
+    // the centroids' range and its neighbours two: keys of cell + 2 fit 21 bits
+    const double cs = std::max({t->eta * hmax, ext / double(1 << 20), 1e-300});
     auto cell = [&](double x, int dd) { return (int64_t)std::floor((x - lo[dd]) / cs); };
-    auto key = [](int64_t a, int64_t b, int64_t c) { return (a << 42) ^ (b << 21) ^ c; };
-    std::unordered_map<int64_t, std::vector<int32_t>> grid;
+    auto key = [](int64_t a, int64_t b, int64_t c) {
+      return ((uint64_t)(a + 2) << 42) ^ ((uint64_t)(b + 2) << 21) ^ (uint64_t)(c + 2);
+    };
+    std::unordered_map<uint64_t, std::vector<int32_t>> grid;
     grid.reserve((size_t)nt);
     for (int64_t e = 0; e < nt; ++e)
       grid[key(cell(cen[3 * e], 0), cell(cen[3 * e + 1], 1), cell(cen[3 * e + 2], 2))].push_back((int32_t)e);

@@ -52,8 +52,8 @@ struct Solve {
   double bnorm = 0, est = INFINITY, resid_true = INFINITY;
   double t_submit = 0, t_admit = 0, t_done = 0;
   std::vector<double> restart_resid;  // true relative residual at each restart boundary
-  DevBuf V, w, r, x64, y64, H, cs, sn, g, h, h2, part, dot, st, yv;
-  double* slot = nullptr;  // 2 doubles in the server's pinned read-back area
+  DevBuf ws;       // GMRES workspace (one buffer)
+  GmresWork W{};   // its parts
 };
 
 struct Server {
@@ -78,25 +78,15 @@ struct Server {
 };
 
 static int alloc_workspace(Solve& v) {
-  const size_t n = (size_t)v.t->npanel;
-  const int m = v.m;
-  int rc;
-  if ((rc = v.V.alloc((size_t)(m + 1) * n * sizeof(double2))) || (rc = v.w.alloc(n * sizeof(double2))) ||
-      (rc = v.r.alloc(n * sizeof(double2))) || (rc = v.x64.alloc(n * sizeof(float2))) ||
-      (rc = v.y64.alloc(n * sizeof(float2))) || (rc = v.H.alloc((size_t)(m + 1) * m * sizeof(double2))) ||
-      (rc = v.cs.alloc((size_t)m * sizeof(double))) || (rc = v.sn.alloc((size_t)m * sizeof(double2))) ||
-      (rc = v.g.alloc((size_t)(m + 1) * sizeof(double2))) || (rc = v.h.alloc((size_t)(m + 32) * sizeof(double2))) ||
-      (rc = v.h2.alloc((size_t)(m + 32) * sizeof(double2))) ||
-      (rc = v.part.alloc((size_t)mdot_blocks() * 32 * sizeof(double2))) || (rc = v.dot.alloc(sizeof(double2))) ||
-      (rc = v.st.alloc(2 * sizeof(double))) || (rc = v.yv.alloc((size_t)(m + 1) * sizeof(double2))))
-    return rc;
+  int rc = v.ws.alloc((size_t)gmres_workspace_bytes(v.t->npanel, v.m));
+  if (rc) return rc;
+  v.W = gmres_carve(v.ws.p, v.t->npanel, v.m);
   return HFMM_OK;
 }
 
 static void free_workspace(Solve& v) {
-  for (DevBuf* b : {&v.V, &v.w, &v.r, &v.x64, &v.y64, &v.H, &v.cs, &v.sn, &v.g, &v.h, &v.h2, &v.part, &v.dot,
-                    &v.st, &v.yv})
-    b->reset();
+  v.ws.reset();
+  v.W = GmresWork{};
 }
 
 static void mdot_chunks(int64_t n, int nv, const double2* V, const double2* w, double2* part, double2* h,
@@ -143,15 +133,15 @@ static int admit(Server& sv, hipStream_t s) {
     HIP_TRY(hipHostMalloc((void**)&sv.pinned, (size_t)sv.max_active * 2 * sizeof(double), hipHostMallocDefault));
     sv.pinned_slots = sv.max_active;
   }
-  for (Solve* v : fresh) launch_mdot(v->t->npanel, 1, v->b, v->t->npanel, v->b, v->part.as<double2>(),
-                                     v->dot.as<double2>(), 0, s);
+  for (Solve* v : fresh) launch_mdot(v->t->npanel, 1, v->b, v->t->npanel, v->b, v->W.part,
+                                     v->W.dot, 0, s);
   for (size_t i = 0; i < fresh.size(); ++i)
-    HIP_TRY(hipMemcpyAsync(sv.pinned + 2 * i, fresh[i]->dot.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(sv.pinned + 2 * i, fresh[i]->W.dot, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (size_t i = 0; i < fresh.size(); ++i) fresh[i]->bnorm = std::sqrt(sv.pinned[2 * i]);
   for (Solve* v : fresh)
     if (v->bnorm == 0.0) {
-      HIP_TRY(hipMemsetAsync(v->x, 0, (size_t)v->t->npanel * sizeof(double2), s));
+      launch_zero_c128(v->t->npanel, v->x, s);
       v->resid_true = 0.0;
       v->est = 0.0;
       finish(sv, *v, S_CONVERGED);
@@ -205,10 +195,10 @@ static int step(Server& sv, hipStream_t s) {
     std::vector<const float2*> xs;
     std::vector<float2*> ys;
     for (Solve* v : kv.second) {
-      const double2* in = v->phase == PH_RESIDUAL ? v->x : v->V.as<double2>() + (size_t)v->j * v->t->npanel;
-      launch_to_c64(v->t->npanel, in, v->x64.as<float2>(), s);
-      xs.push_back(v->x64.as<float2>());
-      ys.push_back(v->y64.as<float2>());
+      const double2* in = v->phase == PH_RESIDUAL ? v->x : v->W.V + (size_t)v->j * v->t->npanel;
+      launch_to_c64(v->t->npanel, in, v->W.x64, s);
+      xs.push_back(v->W.x64);
+      ys.push_back(v->W.y64);
     }
     if ((rc = run_batch(*sv.batches[kv.first], xs.data(), ys.data(), s, false, nullptr))) return rc;
   }
@@ -217,31 +207,31 @@ static int step(Server& sv, hipStream_t s) {
     Tree& t = *v.t;
     Plan& pl = *v.pl;
     const int64_t n = t.npanel;
-    const double2* in = v.phase == PH_RESIDUAL ? v.x : v.V.as<double2>() + (size_t)v.j * n;
-    double2* out = v.phase == PH_RESIDUAL ? v.r.as<double2>() : v.w.as<double2>();
+    const double2* in = v.phase == PH_RESIDUAL ? v.x : v.W.V + (size_t)v.j * n;
+    double2* out = v.phase == PH_RESIDUAL ? v.W.r : v.W.w;
     launch_near_apply(n, t.d_near_off.as<int32_t>(), t.d_near_col.as<int32_t>(), pl.d_near_val.as<float2>(),
-                      nullptr, v.x64.as<float2>(), v.y64.as<float2>(), s);
+                      nullptr, v.W.x64, v.W.y64, s);
     if (t.nystrom)  // curved elements: 6 x 6 self blocks in FP64
-      launch_from_c64_self6(n, v.y64.as<float2>(), pl.d_self6.as<double2>(), in, out, s);
+      launch_from_c64_self6(n, v.W.y64, pl.d_self6.as<double2>(), in, out, s);
     else
-      launch_from_c64_diag(n, v.y64.as<float2>(), pl.d_diag.as<double2>(), in, out, s);
+      launch_from_c64_diag(n, v.W.y64, pl.d_diag.as<double2>(), in, out, s);
     if (v.phase == PH_RESIDUAL) {
       launch_residual(n, v.b, out, s);
-      launch_mdot(n, 1, out, n, out, v.part.as<double2>(), v.dot.as<double2>(), 0, s);
-      HIP_TRY(hipMemcpyAsync(sv.pinned + 2 * i, v.dot.p, sizeof(double), hipMemcpyDeviceToHost, s));
+      launch_mdot(n, 1, out, n, out, v.W.part, v.W.dot, 0, s);
+      HIP_TRY(hipMemcpyAsync(sv.pinned + 2 * i, v.W.dot, sizeof(double), hipMemcpyDeviceToHost, s));
     } else {
-      double2* V = v.V.as<double2>();
-      double2* w = v.w.as<double2>();
-      mdot_chunks(n, v.j + 1, V, w, v.part.as<double2>(), v.h.as<double2>(), s);
-      launch_mupdate(n, v.j + 1, V, n, v.h.as<double2>(), w, -1.0, s);
-      mdot_chunks(n, v.j + 1, V, w, v.part.as<double2>(), v.h2.as<double2>(), s);
-      launch_mupdate(n, v.j + 1, V, n, v.h2.as<double2>(), w, -1.0, s);
-      launch_vec_add(v.j + 1, v.h2.as<double2>(), v.h.as<double2>(), s);
-      launch_mdot(n, 1, w, n, w, v.part.as<double2>(), v.dot.as<double2>(), 0, s);
-      launch_givens(v.j, v.m, v.h.as<double2>(), v.dot.as<double2>(), v.H.as<double2>(), v.cs.as<double>(),
-                    v.sn.as<double2>(), v.g.as<double2>(), v.st.as<double>(), s);
-      launch_scale_by_norm(n, w, v.dot.as<double2>(), V + (size_t)(v.j + 1) * n, s);
-      HIP_TRY(hipMemcpyAsync(sv.pinned + 2 * i, v.st.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      double2* V = v.W.V;
+      double2* w = v.W.w;
+      mdot_chunks(n, v.j + 1, V, w, v.W.part, v.W.h, s);
+      launch_mupdate(n, v.j + 1, V, n, v.W.h, w, -1.0, s);
+      mdot_chunks(n, v.j + 1, V, w, v.W.part, v.W.h2, s);
+      launch_mupdate(n, v.j + 1, V, n, v.W.h2, w, -1.0, s);
+      launch_vec_add(v.j + 1, v.W.h2, v.W.h, s);
+      launch_mdot(n, 1, w, n, w, v.W.part, v.W.dot, 0, s);
+      launch_givens(v.j, v.m, v.W.h, v.W.dot, v.W.H, v.W.cs,
+                    v.W.sn, v.W.g, v.W.st, s);
+      launch_scale_by_norm(n, w, v.W.dot, V + (size_t)(v.j + 1) * n, s);
+      HIP_TRY(hipMemcpyAsync(sv.pinned + 2 * i, v.W.st, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     }
   }
   HIP_TRY(hipGetLastError());
@@ -262,8 +252,8 @@ static int step(Server& sv, hipStream_t s) {
       } else if (stop_early(sv, v)) {
         finish(sv, v, S_STOPPED);
       } else {
-        launch_scale_by_norm(n, v.r.as<double2>(), v.dot.as<double2>(), v.V.as<double2>(), s);
-        launch_init_g(v.m, v.dot.as<double2>(), v.g.as<double2>(), s);
+        launch_scale_by_norm(n, v.W.r, v.W.dot, v.W.V, s);
+        launch_init_g(v.m, v.W.dot, v.W.g, s);
         v.j = 0;
         v.phase = PH_ARNOLDI;
       }
@@ -274,8 +264,8 @@ static int step(Server& sv, hipStream_t s) {
       if (!std::isfinite(v.est)) {
         finish(sv, v, S_FAILED);
       } else if (v.est <= v.tol || v.iters >= v.maxit || breakdown || v.j + 1 == v.m) {
-        launch_backsolve(v.j + 1, v.m, v.H.as<double2>(), v.g.as<double2>(), v.yv.as<double2>(), s);
-        launch_mupdate(n, v.j + 1, v.V.as<double2>(), n, v.yv.as<double2>(), v.x, 1.0, s);
+        launch_backsolve(v.j + 1, v.m, v.W.H, v.W.g, v.W.yv, s);
+        launch_mupdate(n, v.j + 1, v.W.V, n, v.W.yv, v.x, 1.0, s);
         ++v.restarts;
         v.phase = PH_RESIDUAL;
       } else {
