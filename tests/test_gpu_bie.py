@@ -13,10 +13,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_1803_09948_amd import hfmm  # noqa: E402
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+from parity import check, rel  # noqa: E402
 
 
 @pytest.mark.parametrize("s,k", [(2, 3.0), (3, 2 * math.pi), (3, 6.0)])
@@ -27,9 +24,7 @@ def test_bie_matvec_vs_dense_oracle(s, k):
     q = synth.strengths(len(T), 40 + s)
     t = hfmm.Tree.from_mesh(V, T)
     y = t.matvec(k, 10, torch.from_numpy(q).to("cuda")).cpu().numpy()
-    e = rel(y, A @ q.astype(np.complex128))
-    print("  bie matvec vs dense", e)
-    assert e <= 1e-5
+    check(y, A @ q.astype(np.complex128), 1e-5, "bie matvec vs dense")
 
 
 def test_plane_wave_rhs():
@@ -79,7 +74,10 @@ def test_mie_error_falls_with_refinement():
 
 def test_icosphere5_resonant_solve_and_mie():
     """Subdivision 5 (20480 panels), k = 2 pi (an interior resonance of the
-    sphere: the n = 0 density mode is free, the scattered field is not)."""
+    sphere: the n = 0 density mode is free, the scattered field is not).
+    The scattered field at r = 4 against the Mie series (measured 9.3e-4),
+    and the density against the Mie density with the free n = 0 mode
+    projected out of both (the area-weighted mean removed)."""
     s, k = 5, 2 * math.pi
     V, T = synth.icosphere(s)
     t = hfmm.Tree.from_mesh(V, T)
@@ -97,7 +95,15 @@ def test_icosphere5_resonant_solve_and_mie():
     xo = 4.0 * np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
     e = rel(bie.scattered_field(k, V, T, xq, xo), mie.scattered(k, 1.0, 4.0, th))
     print("u_s error vs Mie at r=4:", e)
-    assert e < 0.02
+    assert e < 1.5e-3
+    # density without its n = 0 mode
+    pn = bie.panels(V, T)
+    cen, area = pn["centroid"], pn["area"]
+    qm = mie.density(k, 1.0, np.arccos(cen[:, 2] / np.linalg.norm(cen, axis=1)))
+    strip = lambda q: q - np.sum(area * q) / np.sum(area)
+    ed = rel(strip(xq), strip(qm))
+    print("density error vs Mie, n = 0 mode removed:", ed)
+    assert ed < 5e-3    # measured 2.8e-3; the oracle's dense solves give 2.0e-2 (s = 3), 5.8e-3 (s = 4)
 
 
 def test_gmres_errors_and_nonconvergence():
@@ -148,10 +154,9 @@ def test_singular_treatment_ablation():
 def test_wing_fuselage_matvec_vs_dense_rows(k):
     """Two intersecting ellipsoids (wing and fuselage), clipped union surface
     at subdivision 2 (572 flat panels, the thin wing's panels all near one
-    another): the product on 96 sampled rows against the oracle's dense rows.
-    Against a dense matrix the P = 10 product carries the expansion's
-    truncation error, which on this elongated body is 4e-6 (k = 3) to 2e-5
-    (k = 2 pi); at P = 16 it must fall to the FP32 and quadrature floor."""
+    another): the product on 96 sampled rows against the oracle's dense rows,
+    at P = 10 and P = 16 (measured 3.8e-7 at both once the self rule cuts its
+    Duffy pieces at the perpendicular foot): the FP32 floor, bar 1e-5."""
     V, T = synth.wing_fuselage(2)
     print(f"case wing-fuselage subdiv=2 panels={len(T)} k={k}", flush=True)
     rows = np.sort(np.random.default_rng(5).choice(len(T), 96, replace=False))
@@ -159,9 +164,9 @@ def test_wing_fuselage_matvec_vs_dense_rows(k):
     t = hfmm.Tree.from_mesh(V, T)
     q = synth.strengths(len(T), 77)
     ref = A @ q.astype(np.complex128)
-    e = {P: rel(t.matvec(k, P, torch.from_numpy(q).to("cuda")).cpu().numpy()[rows], ref) for P in (10, 16)}
-    print("  matvec rows vs dense by P", e)
-    assert e[10] <= 1e-4 and e[16] <= 1e-6
+    for P in (10, 16):
+        y = t.matvec(k, P, torch.from_numpy(q).to("cuda")).cpu().numpy()[rows]
+        check(y, ref, 1e-5, f"matvec rows vs dense P={P}")
 
 
 def test_wing_fuselage_solve_vs_dense():

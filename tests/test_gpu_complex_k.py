@@ -10,10 +10,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_1803_09948_amd import hfmm  # noqa: E402
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+from parity import check, rel  # noqa: E402
 
 
 @pytest.mark.parametrize("n,k,ki,P,seed", [
@@ -28,10 +25,9 @@ def test_matvec_vs_oracle_fmm(n, k, ki, P, seed):
     t = hfmm.Tree.from_points(x, ncrit=32, k_imag=ki)
     y = t.matvec(k, P, torch.from_numpy(q).to("cuda")).cpu().numpy()
     yo = FMM(x, k=k, k_imag=ki, P=P, ncrit=32).matvec(q)
-    e = rel(y, yo)
     ed = rel(yo, direct_sum(complex(k, ki), x, x, q))
-    print(f"  gpu vs oracle FMM {e:.2e}; oracle FMM vs direct {ed:.2e}")
-    assert np.all(np.isfinite(y)) and e <= 1e-5
+    print(f"  oracle FMM vs direct {ed:.2e}")
+    check(y, yo, 1e-5, "gpu vs oracle FMM")
 
 
 def test_batch_mixes_damped_and_real_instances():
@@ -67,11 +63,11 @@ def test_flat_bie_matvec_and_rhs_vs_dense_oracle():
     q = synth.strengths(len(T), 71)
     t = hfmm.Tree.from_mesh(V, T, k_imag=ki)
     y = t.matvec(k, 10, torch.from_numpy(q).to("cuda")).cpu().numpy()
-    e = rel(y, A @ q.astype(np.complex128))
+    check(y, A @ q.astype(np.complex128), 1e-5, "flat bie complex k matvec")
     b = t.plane_wave(k).cpu().numpy()
     eb = rel(b, bie.plane_wave_rhs(complex(k, ki), V, T))
-    print("flat bie complex k: matvec", e, "rhs", eb)
-    assert e <= 1e-5 and eb <= 1e-14
+    print("flat bie complex k: rhs", eb)
+    assert eb <= 1e-14
 
 
 def test_nystrom_matvec_and_solve_vs_dense_oracle():
@@ -85,9 +81,9 @@ def test_nystrom_matvec_and_solve_vs_dense_oracle():
     rng = np.random.default_rng(8)
     x = (rng.uniform(-1, 1, len(Z)) + 1j * rng.uniform(-1, 1, len(Z))).astype(np.complex64)
     y = t.matvec(k, 10, torch.from_numpy(x).to("cuda")).cpu().numpy()
-    e = rel(y, Z @ x.astype(np.complex128))
+    check(y, Z @ x.astype(np.complex128), 1e-5, "nystrom complex k matvec")
     b = t.plane_wave(k)
     xs, info = t.gmres(k, 10, b, tol=1e-6, restart=30, maxit=500)
     es = rel(xs.cpu().numpy(), np.linalg.solve(Z, ny.plane_wave_rhs(complex(k, ki), nodes, tri6)))
-    print("nystrom complex k: matvec", e, "solve", es, info["iters"])
-    assert e <= 1e-5 and es <= 1e-4
+    print("nystrom complex k: solve", es, info["iters"])
+    assert es <= 1e-4

@@ -1,8 +1,9 @@
 """GPU parity of the point-mode FMM matvec against the FP64 oracle.
 
 Bar (stated for FP32 arithmetic): relative 2-norm difference to the CPU FP64
-FMM at the same tree, lists and P <= 1e-5; the FMM truncation error against
-the FP64 direct sum is reported and bounded loosely."""
+FMM at the same tree, lists and P <= 1e-5, and every element within 1e-5 of
+the largest output (relative infinity norm); the FMM truncation error
+against the FP64 direct sum is reported and bounded loosely."""
 import math
 
 import numpy as np
@@ -15,6 +16,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_1803_09948_amd import hfmm  # noqa: E402
+from parity import check, rel  # noqa: E402
 
 
 def _gpu_matvec(x, q, k, P, **opts):
@@ -23,10 +25,6 @@ def _gpu_matvec(x, q, k, P, **opts):
     y = t.matvec(k, P, qd)
     torch.cuda.synchronize()
     return y.cpu().numpy(), t
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 @pytest.mark.parametrize("n,k,P,ncrit,seed", [
@@ -42,11 +40,9 @@ def test_matvec_vs_oracle_fmm(n, k, P, ncrit, seed):
     y, t = _gpu_matvec(x, q, k, P, ncrit=ncrit)
     f = FMM(x, k=k, P=P, ncrit=ncrit)
     yo = f.matvec(q)
-    e = rel(y, yo)
     ed = rel(yo, direct_sum(k, x, x, q))
-    print(f"  gpu vs oracle FMM {e:.3e}; oracle FMM vs direct {ed:.3e}")
-    assert np.all(np.isfinite(y))
-    assert e <= 1e-5
+    print(f"  oracle FMM vs direct {ed:.3e}")
+    check(y, yo, 1e-5, "gpu vs oracle FMM")
 
 
 @pytest.mark.parametrize("P", [3, 5, 6, 7, 9])
@@ -59,9 +55,7 @@ def test_orders_vs_oracle_fmm(P):
     q = synth.strengths(n, 40 + P)
     y, t = _gpu_matvec(x, q, k, P, ncrit=32)
     assert t.stats(k, P)["n_m2l"] > 0
-    e = rel(y, FMM(x, k=k, P=P, ncrit=32).matvec(q))
-    print(f"P={P} gpu vs oracle FMM {e:.3e}")
-    assert e <= 1e-5
+    check(y, FMM(x, k=k, P=P, ncrit=32).matvec(q), 1e-5, f"P={P} gpu vs oracle FMM")
 
 
 @pytest.mark.parametrize("P", [11, 13, 14, 15])
@@ -73,9 +67,7 @@ def test_high_orders_vs_direct_sum(P):
     q = synth.strengths(n, 50 + P)
     y, t = _gpu_matvec(x, q, k, P, ncrit=32)
     assert t.stats(k, P)["n_m2l"] > 0
-    e = rel(y, direct_sum(k, x, x, q))
-    print(f"P={P} vs direct {e:.3e}")
-    assert e <= 1e-5
+    check(y, direct_sum(k, x, x, q), 1e-5, f"P={P} vs direct")
 
 
 def test_largest_P_vs_direct_sum():
@@ -84,9 +76,7 @@ def test_largest_P_vs_direct_sum():
     x = synth.sphere_points(n, 15)
     q = synth.strengths(n, 15)
     y, _ = _gpu_matvec(x, q, k, 16, ncrit=32)
-    e = rel(y, direct_sum(k, x, x, q))
-    print("P=16 vs direct", e)
-    assert e <= 1e-5
+    check(y, direct_sum(k, x, x, q), 1e-5, "P=16 vs direct")
 
 
 def test_p2p_only_equals_direct_sum():
@@ -97,9 +87,7 @@ def test_p2p_only_equals_direct_sum():
     q = synth.strengths(n, 21)
     y, t = _gpu_matvec(x, q, 5.0, 4, ncrit=40, theta=1e-9)
     assert t.stats(5.0, 4)["n_m2l"] == 0
-    e = rel(y, direct_sum(5.0, x, x, q))
-    print("p2p only vs direct", e)
-    assert e <= 2e-6
+    check(y, direct_sum(5.0, x, x, q), 2e-6, "p2p only vs direct", barinf=5e-6)
 
 
 def test_edge_cases():
@@ -110,18 +98,18 @@ def test_edge_cases():
     x = synth.sphere_points(40, 2)
     q = synth.strengths(40, 2)
     y, _ = _gpu_matvec(x, q, 2.0, 6)
-    assert rel(y, direct_sum(2.0, x, x, q)) < 2e-6
+    check(y, direct_sum(2.0, x, x, q), 2e-6, "one leaf vs direct", barinf=5e-6)
     # duplicated points contribute nothing to each other
     x = np.repeat(synth.sphere_points(300, 3), 2, axis=0)
     q = synth.strengths(600, 3)
     y, _ = _gpu_matvec(x, q, 2.0, 6, ncrit=16)
     yo = FMM(x, k=2.0, P=6, ncrit=16).matvec(q)
-    assert rel(y, yo) < 1e-5
+    check(y, yo, 1e-5, "duplicates vs oracle FMM")
     # ellipsoid, non-unit root cube
     x = synth.scale_axes(synth.sphere_points(2500, 4), (0.5, 2.0, 1.3))
     q = synth.strengths(2500, 4)
     y, _ = _gpu_matvec(x, q, 3.0, 8, ncrit=32)
-    assert rel(y, FMM(x, k=3.0, P=8, ncrit=32).matvec(q)) < 1e-5
+    check(y, FMM(x, k=3.0, P=8, ncrit=32).matvec(q), 1e-5, "ellipsoid vs oracle FMM")
 
 
 def test_repeat_and_determinism_of_near_field():
@@ -131,7 +119,7 @@ def test_repeat_and_determinism_of_near_field():
     qd = torch.from_numpy(q).to("cuda")
     y1 = t.matvec(1.0, 8, qd).cpu().numpy()
     y2 = t.matvec(1.0, 8, qd).cpu().numpy()
-    assert rel(y1, y2) < 1e-6
+    np.testing.assert_array_equal(y1, y2)   # fixed accumulation order: the same bits
 
 
 @pytest.mark.parametrize("P", [4, 8, 10, 12])

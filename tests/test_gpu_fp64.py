@@ -16,10 +16,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_1803_09948_amd import hfmm  # noqa: E402
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+from parity import check, rel  # noqa: E402
 
 
 @pytest.mark.parametrize("n,k,P,ncrit,seed", [
@@ -35,10 +32,8 @@ def test_fp64_variant_vs_oracle_fmm(n, k, P, ncrit, seed):
     y64 = t.matvec64(k, P, torch.from_numpy(q.astype(np.complex128)).to("cuda")).cpu().numpy()
     y32 = t.matvec(k, P, torch.from_numpy(q).to("cuda")).cpu().numpy()
     yo = FMM(x, k=k, P=P, ncrit=ncrit).matvec(q)
-    e64, e32 = rel(y64, yo), rel(y32, y64)
-    print(f"  fp64 gpu vs oracle {e64:.3e}; fp32 gpu vs fp64 gpu {e32:.3e}")
-    assert e64 <= 1e-11
-    assert e32 <= 1e-5
+    check(y64, yo, 1e-11, "fp64 gpu vs oracle")
+    check(y32, y64, 1e-5, "fp32 gpu vs fp64 gpu")
 
 
 def test_direct64_vs_oracle():
@@ -48,7 +43,7 @@ def test_direct64_vs_oracle():
     y = hfmm.direct64(torch.from_numpy(xs).to("cuda"), torch.from_numpy(q).to("cuda"),
                       torch.from_numpy(tg).to("cuda"), 7.0).cpu().numpy()
     yo = direct_sum(7.0, tg, xs, q)
-    assert rel(y, yo) <= 1e-12
+    check(y, yo, 1e-12, "direct64 vs oracle")
     # no sources: zeros
     z = hfmm.direct64(torch.zeros((0, 3), dtype=torch.float32, device="cuda"),
                       torch.zeros(0, dtype=torch.complex128, device="cuda"),

@@ -17,10 +17,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_1803_09948_amd import hfmm  # noqa: E402
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+from parity import check  # noqa: E402
 
 
 def test_headline_1m_sampled_vs_direct_sum():
@@ -36,9 +33,26 @@ def test_headline_1m_sampled_vs_direct_sum():
     y = t.matvec(k, P, torch.from_numpy(q).to("cuda")).cpu().numpy()
     idx = np.sort(np.random.default_rng(3).choice(n, 32, replace=False))
     ref = direct_sum(k, x[idx], x, q, chunk=4)
-    e = rel(y[idx], ref)
-    print("  sampled vs direct", e, "stats", t.stats(k, P))
-    assert e <= 5e-6
+    print("  stats", t.stats(k, P))
+    check(y[idx], ref, 5e-6, "sampled vs direct")
+
+
+def test_8m_sampled_vs_direct_sum():
+    """N = 2^23 on the unit sphere, k = 16 pi, P = 10 (the larger size of
+    the precision study): 24 sampled outputs against the FP64 direct sum
+    over all 8M sources.  The measured P = 10 error over 1000 targets is
+    8.7e-7; bound 5e-6."""
+    n, k, P = 1 << 23, 16 * math.pi, 10
+    print(f"case n={n} k={k:.4f} P={P}", flush=True)
+    x = synth.sphere_points(n, 29)
+    q = synth.strengths(n, 29)
+    t = hfmm.Tree.from_points(x, ncrit=64)
+    y = t.matvec(k, P, torch.from_numpy(q).to("cuda")).cpu().numpy()
+    idx = np.sort(np.random.default_rng(6).choice(n, 24, replace=False))
+    ref = direct_sum(k, x[idx], x, q, chunk=2)
+    print("  stats", t.stats(k, P), flush=True)
+    check(y[idx], ref, 5e-6, "8M sampled vs direct")
+    t.free()
 
 
 def test_bie_icosphere5_sampled_rows():
@@ -52,9 +66,7 @@ def test_bie_icosphere5_sampled_rows():
     q = synth.strengths(len(T), 91)
     y = t.matvec(k, 10, torch.from_numpy(q).to("cuda")).cpu().numpy()
     rows = np.sort(np.random.default_rng(4).choice(len(T), 32, replace=False))
-    e = rel(y[rows], bie.dense_matrix(k, V, T, rows=rows) @ q.astype(np.complex128))
-    print("  sampled rows vs dense", e)
-    assert e <= 1e-5
+    check(y[rows], bie.dense_matrix(k, V, T, rows=rows) @ q.astype(np.complex128), 1e-5, "sampled rows vs dense")
 
 
 def test_nystrom_s5_sampled_rows():
@@ -70,6 +82,5 @@ def test_nystrom_s5_sampled_rows():
     x = (rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)).astype(np.complex64)
     y = t.matvec(k, 10, torch.from_numpy(x).to("cuda")).cpu().numpy()
     rows = np.sort(rng.choice(n, 32, replace=False))
-    e = rel(y[rows], ny.dense_matrix(k, nodes, tri6, rows=rows) @ x.astype(np.complex128))
-    print("  sampled rows vs oracle", e)
-    assert e <= 1e-5
+    check(y[rows], ny.dense_matrix(k, nodes, tri6, rows=rows) @ x.astype(np.complex128), 1e-5,
+          "sampled rows vs oracle")

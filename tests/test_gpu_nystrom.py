@@ -12,10 +12,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_1803_09948_amd import hfmm  # noqa: E402
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+from parity import check, rel  # noqa: E402
 
 
 def _mesh(s, axes=None):
@@ -36,11 +33,9 @@ def test_matvec_vs_dense_oracle(k, axes):
     x = (rng.uniform(-1, 1, 6 * len(tri6)) + 1j * rng.uniform(-1, 1, 6 * len(tri6))).astype(np.complex64)
     y = t.matvec(k, 10, torch.from_numpy(x).to("cuda")).cpu().numpy()
     Z = ny.dense_matrix(k, nodes, tri6, L=3, n_near=6, n_self=10)
-    e = rel(y, Z @ x.astype(np.complex128))
+    check(y, Z @ x.astype(np.complex128), 1e-5, "vs oracle at the GPU orders")
     # the oracle at its own (finer) quadrature orders: the GPU rules are converged
-    e_fine = rel(y, ny.dense_matrix(k, nodes, tri6) @ x.astype(np.complex128))
-    print(f"  vs oracle at the GPU orders {e:.2e}, at the oracle's orders {e_fine:.2e}")
-    assert e <= 1e-5 and e_fine <= 1e-5
+    check(y, ny.dense_matrix(k, nodes, tri6) @ x.astype(np.complex128), 1e-5, "at the oracle's orders")
 
 
 def test_gmres_vs_dense_solve():
