@@ -26,7 +26,7 @@ EXPORTS = [
     "hfmm_server_release", "hfmm_server_used_bytes", "hfmm_server_free",
     "hfmm_variant_count", "hfmm_set_variant", "hfmm_tree_variant", "hfmm_matvec64", "hfmm_direct64",
     "hfmm_build_nystrom", "hfmm_nystrom_points", "hfmm_tree_plan", "hfmm_server_set_limits",
-    "hfmm_debug_fail_alloc",
+    "hfmm_debug_fail_alloc", "hfmm_gmres_solve_noalloc",
 ]
 
 
@@ -122,6 +122,7 @@ def lib():
             "hfmm_tree_plan": [vp, dbl, i32, i32, C.POINTER(PlanInfo)],
             "hfmm_server_set_limits": [vp, i32, dbl, dbl],
             "hfmm_debug_fail_alloc": [i64],
+            "hfmm_gmres_solve_noalloc": [vp, dbl, i32, vp, vp, dbl, i32, i32, C.POINTER(GmresInfo), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -277,6 +278,20 @@ class Tree:
         rc = _check(lib().hfmm_gmres_solve(self._h, float(k), int(P), bp,
                                            C.c_void_p(x.data_ptr()), float(tol), int(restart),
                                            int(maxit), C.byref(info), _stream(torch, stream)))
+        d = info.as_dict()
+        d["converged"] = rc == HFMM_OK
+        return x, d
+
+    def gmres_noalloc(self, k: float, P: int, b, x, tol=1e-4, restart=30, maxit=2000, stream=None):
+        """GMRES with the Krylov workspace in the library's static device
+        scratch (hfmm_gmres_solve_noalloc): allocates no device memory; (k, P)
+        must be prepared.  x (complex128, in: initial guess) is overwritten."""
+        import torch
+        bp = _dev_vec(b, torch.complex128, self.n_out, "b")
+        xp = _dev_vec(x, torch.complex128, self.n_in, "x")
+        info = GmresInfo()
+        rc = _check(lib().hfmm_gmres_solve_noalloc(self._h, float(k), int(P), bp, xp, float(tol), int(restart),
+                                                   int(maxit), C.byref(info), _stream(torch, stream)))
         d = info.as_dict()
         d["converged"] = rc == HFMM_OK
         return x, d
