@@ -76,6 +76,10 @@ static int upload(DevBuf& b, const std::vector<T>& v) {
 Tree::~Tree() {
   if (ev_made)
     for (auto& e : ev) (void)hipEventDestroy(e);
+  if (g_pin) {
+    for (auto& e : g_ev) (void)hipEventDestroy(e);
+    (void)hipHostFree(g_pin);
+  }
 }
 
 // Device bytes of a handle's resident data: sorted float4 positions, source

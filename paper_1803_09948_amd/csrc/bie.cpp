@@ -206,6 +206,29 @@ static int gm_workspace(Tree& t, int m, GmresWork* W) {
   return HFMM_OK;
 }
 
+// Pinned status slots and events of the lagged convergence checks (once per
+// handle).
+static int gm_lag(Tree& t, GmresLag* lag) {
+  if (!t.g_pin) {
+    double* p = nullptr;
+    HIP_TRY(hipHostMalloc((void**)&p, 4 * sizeof(double), hipHostMallocDefault));
+    for (int i = 0; i < 2; ++i) {
+      hipError_t e = hipEventCreateWithFlags(&t.g_ev[i], hipEventDisableTiming);
+      if (e != hipSuccess) {
+        for (int q = 0; q < i; ++q) (void)hipEventDestroy(t.g_ev[q]);
+        (void)hipHostFree(p);
+        set_error(std::string("hipEventCreateWithFlags: ") + hipGetErrorString(e));
+        return HFMM_EHIP;
+      }
+    }
+    t.g_pin = p;
+  }
+  lag->pin = t.g_pin;
+  lag->ev[0] = t.g_ev[0];
+  lag->ev[1] = t.g_ev[1];
+  return HFMM_OK;
+}
+
 // out = A v (FP64 in/out; FMM and near corrections in FP32, self term in FP64)
 static int apply_A(Tree& t, Plan& pl, const GmresWork& W, const double2* v, double2* out, hipStream_t s) {
   const int64_t n = t.npanel;
@@ -235,16 +258,33 @@ static int read_doubles(const void* dev, double* host, int cnt, hipStream_t s) {
   return HFMM_OK;
 }
 
+// One Arnoldi step j: w = A v_j, two passes of classical Gram-Schmidt
+// against V[0..j], the Givens update of column j (its status -- residual
+// estimate and breakdown flag -- in W.st) and v_{j+1} = w / ||w||.
+static int arnoldi_step(Tree& t, Plan& pl, const GmresWork& W, int m, int j, hipStream_t s) {
+  const int64_t n = t.npanel;
+  double2* V = W.V;
+  int rc = apply_A(t, pl, W, V + (size_t)j * n, W.w, s);
+  if (rc) return rc;
+  mdot_all(n, j + 1, V, W.w, W.part, W.h, 0, s);
+  launch_mupdate(n, j + 1, V, n, W.h, W.w, -1.0, s);
+  mdot_all(n, j + 1, V, W.w, W.part, W.h2, 0, s);
+  launch_mupdate(n, j + 1, V, n, W.h2, W.w, -1.0, s);
+  launch_vec_add(j + 1, W.h2, W.h, s);  // h += h2
+  launch_mdot(n, 1, W.w, n, W.w, W.part, W.dot, 0, s);
+  launch_givens(j, m, W.h, W.dot, W.H, W.cs, W.sn, W.g, W.st, s);
+  launch_scale_by_norm(n, W.w, W.dot, V + (size_t)(j + 1) * n, s);
+  HIP_TRY(hipGetLastError());
+  return HFMM_OK;
+}
+
 int gmres_run(Tree& t, Plan& pl, const GmresWork& W, int m, const double2* b, double2* x, double tol,
-              int maxit, hfmm_gmres_info* info, hipStream_t s) {
+              int maxit, hfmm_gmres_info* info, hipStream_t s, const GmresLag* lag) {
   auto t0 = std::chrono::steady_clock::now();
   const int64_t n = t.npanel;
   int rc;
   double2* V = W.V;
-  double2* w = W.w;
   double2* r = W.r;
-  double2* h = W.h;
-  double2* h2 = W.h2;
   double2* part = W.part;
   double2* dotv = W.dot;
   double hv[2];
@@ -282,30 +322,52 @@ int gmres_run(Tree& t, Plan& pl, const GmresWork& W, int m, const double2* b, do
     if (iters >= maxit) break;
     launch_scale_by_norm(n, r, dotv, V, s);
     launch_init_g(m, dotv, W.g, s);
-    int done = 0;
-    for (int j = 0; j < m; ++j) {
-      double2* vj = V + (size_t)j * n;
-      if ((rc = apply_A(t, pl, W, vj, w, s))) return rc;
-      // CGS2: two passes of classical Gram-Schmidt against V[0..j]
-      mdot_all(n, j + 1, V, w, part, h, 0, s);
-      launch_mupdate(n, j + 1, V, n, h, w, -1.0, s);
-      mdot_all(n, j + 1, V, w, part, h2, 0, s);
-      launch_mupdate(n, j + 1, V, n, h2, w, -1.0, s);
-      launch_vec_add(j + 1, h2, h, s);  // h += h2
-      launch_mdot(n, 1, w, n, w, part, dotv, 0, s);
-      launch_givens(j, m, h, dotv, W.H, W.cs, W.sn, W.g, W.st, s);
-      launch_scale_by_norm(n, w, dotv, V + (size_t)(j + 1) * n, s);
-      HIP_TRY(hipGetLastError());
+    // Each step's status decides whether the cycle goes on.  Without `lag`
+    // the host reads it right after the step; with `lag` the status is
+    // copied to a pinned slot and read one step later, after the next step
+    // has been queued, so the device never waits for the host.  A step
+    // queued past the stopping one is discarded: it changes only H column
+    // j, g[j], g[j+1] and V[j+1], which the update of x with `done` columns
+    // does not read, so both ways give the same bits.
+    int done = 0, decided = 0, queued = 0;
+    bool stop = false;
+    auto decide = [&](const double* st) -> int {
       ++iters;
-      done = j + 1;
-      if ((rc = read_doubles(W.st, hv, 2, s))) return rc;
-      est = hv[0] / bnorm;
+      ++decided;
+      est = st[0] / bnorm;
       if (!std::isfinite(est)) {
         set_error("GMRES Arnoldi residual estimate is not finite");
         return HFMM_EINTERNAL;
       }
-      if (est <= tol || iters >= maxit || hv[1] == 0.0) break;
+      if (est <= tol || iters >= maxit || st[1] == 0.0) stop = true;
+      return HFMM_OK;
+    };
+    if (!lag) {
+      for (int j = 0; j < m && !stop; ++j) {
+        if ((rc = arnoldi_step(t, pl, W, m, j, s))) return rc;
+        if ((rc = read_doubles(W.st, hv, 2, s)) || (rc = decide(hv))) return rc;
+      }
+    } else {
+      for (int j = 0; j < m && !stop; ++j) {
+        if (iters + (queued - decided) >= maxit) break;  // no step beyond maxit products
+        if ((rc = arnoldi_step(t, pl, W, m, j, s))) return rc;
+        HIP_TRY(hipMemcpyAsync(lag->pin + 2 * (j & 1), W.st, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(lag->ev[j & 1], s));
+        ++queued;
+        if (queued - decided == 2) {  // step j is queued: decide step j - 1
+          const int q = decided;
+          HIP_TRY(hipEventSynchronize(lag->ev[q & 1]));
+          if ((rc = decide(lag->pin + 2 * (q & 1)))) return rc;
+        }
+      }
+      while (!stop && decided < queued) {
+        const int q = decided;
+        HIP_TRY(hipEventSynchronize(lag->ev[q & 1]));
+        if ((rc = decide(lag->pin + 2 * (q & 1)))) return rc;
+      }
+      HIP_TRY(hipStreamSynchronize(s));  // a discarded step finishes before its buffers are reused
     }
+    done = decided;
     launch_backsolve(done, m, W.H, W.g, W.yv, s);
     launch_mupdate(n, done, V, n, W.yv, x, 1.0, s);
     HIP_TRY(hipGetLastError());
@@ -323,9 +385,10 @@ int gmres_run(Tree& t, Plan& pl, const GmresWork& W, int m, const double2* b, do
 static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, int m, int maxit,
                  hfmm_gmres_info* info, hipStream_t s) {
   GmresWork W;
+  GmresLag lag;
   int rc = gm_workspace(t, m, &W);
-  if (rc) return rc;
-  return gmres_run(t, pl, W, m, b, x, tol, maxit, info, s);
+  if (rc || (rc = gm_lag(t, &lag))) return rc;
+  return gmres_run(t, pl, W, m, b, x, tol, maxit, info, s, &lag);
 }
 
 }  // namespace hfmm

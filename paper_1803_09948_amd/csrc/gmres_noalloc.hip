@@ -74,7 +74,7 @@ extern "C" int hfmm_gmres_solve_noalloc(hfmm_tree* tree, double k, int32_t P, co
     if ((rc = scratch_address(&base))) return rc;
     const GmresWork W = gmres_carve(base, t.npanel, restart);
     return gmres_run(t, *it->second, W, restart, (const double2*)b, (double2*)x, tol, maxit, info,
-                     (hipStream_t)stream);
+                     (hipStream_t)stream, nullptr);
   } catch (const std::bad_alloc&) {
     set_error("host allocation failed");
     return HFMM_ENOMEM;

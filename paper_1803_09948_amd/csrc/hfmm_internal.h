@@ -260,6 +260,8 @@ struct Tree {
   // GMRES workspace (kept between solves)
   int gm_m = 0;
   DevBuf g_ws;                  // one buffer, carved by gmres_carve
+  double* g_pin = nullptr;      // pinned status slots of the lagged checks (4 doubles)
+  hipEvent_t g_ev[2] = {};
   DevBuf d_q, d_ys;             // float2 per source / target
   DevBuf d_q64, d_ys64;         // double2 per source / target (FP64 variant)
   int64_t body_bytes = 0;
@@ -311,9 +313,17 @@ struct GmresWork {
 };
 int64_t gmres_workspace_bytes(int64_t n, int m);
 GmresWork gmres_carve(void* base, int64_t n, int m);
+// Lagged convergence checks of GMRES: two pinned status slots (2 doubles
+// each) and their events.
+struct GmresLag {
+  double* pin = nullptr;
+  hipEvent_t ev[2] = {};
+};
 // Restarted GMRES(m) of a BIE handle on a prepared plan, in workspace W
-// (contents on entry do not matter).  Allocates nothing.
+// (contents on entry do not matter).  Allocates nothing.  With lag, each
+// Arnoldi step's status is read one step late (no host wait between
+// steps); without, right after the step.  Both give the same bits.
 int gmres_run(Tree& t, Plan& pl, const GmresWork& W, int m, const double2* b, double2* x, double tol,
-              int maxit, hfmm_gmres_info* info, hipStream_t s);
+              int maxit, hfmm_gmres_info* info, hipStream_t s, const GmresLag* lag);
 
 }  // namespace hfmm
