@@ -49,48 +49,126 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(x, q, k, P, ncrit, stats, budget_s=15.0):
-    """The FP64 oracle timed on a bounded sample of the same workload, scaled
-    to a full matvec with the traversal's counts (single thread)."""
+def _host_cores():
+    """Threads the CPU baseline may use: this process's CPU affinity, capped at
+    16 (the host share of one GPU on the boxes)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_job(job):
+    """One worker's share of the oracle sample (runs in a forked process with
+    one BLAS thread).  Returns (kind, units, seconds)."""
+    from threadpoolctl import threadpool_limits
     import oracle.expansions as ex
     from oracle.fmm import direct_sum
+    kind, args = job
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        if kind == "p2p":
+            k, xt, xs, q = args
+            direct_sum(k, xt, xs, q, chunk=8)
+            units = len(xt) * len(xs)
+        elif kind == "m2l":
+            k, P, i0, cnt, M = args
+            for i in range(i0, i0 + cnt):
+                ex.sr_matrix(np.array([0.5, 0.2, 0.1]) + 0.01 * i, k, P) @ M
+            units = cnt
+        elif kind == "p2m":
+            k, P, xb, qb = args
+            ex.p2m(P, k, np.zeros(3), xb * 0.01, qb)
+            units = len(xb)
+        else:  # m2m
+            k, P, i0, cnt, M = args
+            for i in range(i0, i0 + cnt):
+                ex.rr_matrix(np.array([0.01, -0.01, 0.01]) * (i + 1), k, P) @ M
+            units = cnt
+        return kind, units, time.perf_counter() - t0
+
+
+def _pool_rates(jobs, cores):
+    """Runs the jobs on `cores` forked workers; rate per kind = units / summed
+    worker seconds x cores (the throughput of all cores), and the wall time."""
+    import multiprocessing as mp
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_job, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    units, secs = {}, {}
+    for kind, u, sec in res:
+        units[kind] = units.get(kind, 0) + u
+        secs[kind] = secs.get(kind, 0.0) + sec
+    return {kd: units[kd] / secs[kd] * cores for kd in units}, wall
+
+
+def cpu_baseline(x, q, k, P, stats):
+    """The FP64 oracle, as it stands, timed on a bounded sample of the
+    workload on all host cores (forked worker processes, one BLAS thread
+    each; run before the GPU is touched) and scaled to one full matvec with
+    the traversal's counts: direct-sum pairs for P2P, operator build + apply
+    per M2L pair, P2M / L2P per body, M2M / L2L per cell."""
+    cores = _host_cores()
     rng = np.random.default_rng(0)
     n = len(x)
-    t0 = time.perf_counter()
-    # P2P: direct sum over a sample of targets against all sources
-    nt = 192
-    ti = rng.choice(n, nt, replace=False)
-    ta = time.perf_counter()
-    direct_sum(k, x[ti], x, q, chunk=8)
-    p2p_rate = nt * n / (time.perf_counter() - ta)                 # pairs / s
-    # M2L: operator construction + apply for a sample of well-separated pairs
-    nm = 160
-    M = (rng.normal(size=P * P) + 1j * rng.normal(size=P * P))
-    ta = time.perf_counter()
-    for i in range(nm):
-        t = np.array([0.5, 0.2, 0.1]) + 0.01 * i
-        ex.sr_matrix(t, k, P) @ M
-    m2l_per_pair = (time.perf_counter() - ta) / nm
-    # P2M / L2P per body, M2M / L2L per cell
-    ta = time.perf_counter()
-    nb = 16384
-    ex.p2m(P, k, np.zeros(3), x[:nb] * 0.01, q[:nb])
-    p2m_per_body = (time.perf_counter() - ta) / nb
-    ta = time.perf_counter()
-    for i in range(8):
-        ex.rr_matrix(np.array([0.01, -0.01, 0.01]) * (i + 1), k, P) @ M
-    m2m_per_cell = (time.perf_counter() - ta) / 8
-    est = (stats["p2p_body_pairs"] / p2p_rate + stats["n_m2l"] * m2l_per_pair
-           + 2 * n * p2m_per_body + 2 * stats["n_cell"] * m2m_per_cell)
-    used = time.perf_counter() - t0
+    M = rng.normal(size=P * P) + 1j * rng.normal(size=P * P)
+    jobs = []
+    nt = 12                                   # targets per P2P job
+    for j in range(cores):
+        ti = rng.choice(n, nt, replace=False)
+        jobs.append(("p2p", (k, x[ti], x, q)))
+        jobs.append(("m2l", (k, P, 10 * j, 10, M)))
+        jobs.append(("p2m", (k, P, x[4096 * j:4096 * (j + 1)], q[4096 * j:4096 * (j + 1)])))
+        jobs.append(("m2m", (k, P, j, 1, M)))
+    rate, wall = _pool_rates(jobs, cores)
+    est = (stats["p2p_body_pairs"] / rate["p2p"] + stats["n_m2l"] / rate["m2l"]
+           + 2 * n / rate["p2m"] + 2 * stats["n_cell"] / rate["m2m"])
     return {
-        "value": 1.0 / est, "unit": "matvec/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle (numpy FP64, 1 thread) timed on {nt} targets x {n} sources of the direct "
-                   f"sum, {nm} M2L operator builds+applies, {nb} P2M bodies and 8 M2M operators "
-                   f"({used:.1f} s), scaled by this workload's counts: {stats['p2p_body_pairs']} P2P "
-                   f"body pairs, {stats['n_m2l']} M2L pairs, {stats['n_cell']} cells"),
+        "value": 1.0 / est, "unit": "matvec/s", "cores": cores, "kind": "oracle",
+        "nproc": os.cpu_count(),
+        "sample": (f"oracle (numpy/scipy FP64) on {cores} forked workers x 1 BLAS thread, {wall:.1f} s wall: "
+                   f"{nt * cores} targets x {n} sources of the direct sum, {10 * cores} M2L operator "
+                   f"builds+applies, {4096 * cores} P2M bodies and {cores} M2M operators; scaled by this "
+                   f"workload's counts: {stats['p2p_body_pairs']} P2P body pairs, {stats['n_m2l']} M2L "
+                   f"pairs, {stats['n_cell']} cells"),
         "seconds_per_matvec": est,
+        "rates": {"p2p_pairs_per_s": rate["p2p"], "m2l_pairs_per_s": rate["m2l"],
+                  "p2m_bodies_per_s": rate["p2m"], "m2m_cells_per_s": rate["m2m"]},
     }
+
+
+def bench_oracle(a):
+    """The oracle measured end to end at the small plain-matvec workload
+    (N = 4096 on the unit sphere, k = 1, P = 8, ncrit 64): the direct sum
+    over all 4096 x 4096 pairs on all host cores, and the oracle FMM (tree,
+    lists, operators, matvec; a single sequential process, minutes)."""
+    import synth
+    from oracle.fmm import FMM
+    n, k, P = 4096, 1.0, 8
+    x = synth.sphere_points(n, 11)
+    q = synth.strengths(n, 11)
+    cores = _host_cores()
+    jobs = [("p2p", (k, x[b], x, q)) for b in np.array_split(np.arange(n), 4 * cores)]
+    rate, wall = _pool_rates(jobs, cores)
+    t0 = time.perf_counter()
+    f = FMM(x, k=k, P=P, ncrit=64)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    f.matvec(q)
+    t_mv = time.perf_counter() - t0
+    out = {
+        "metric": "oracle FMM matvec seconds, N=4096, k=1, P=8 (one process)",
+        "value": t_build + t_mv, "unit": "s", "n_gpus": 0, "steps": 1, "warmup": 0,
+        "ms_per_step": (t_build + t_mv) * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "plain matvec, N=4096 uniform on the unit sphere, k=1, P=8, ncrit=64"},
+        "oracle_fmm": {"tree_lists_s": t_build, "matvec_s": t_mv, "cores": 1},
+        "direct_sum": {"pairs_per_s": rate["p2p"], "cores": cores, "wall_s": wall, "pairs": n * n},
+        "nproc": os.cpu_count(),
+    }
+    print(json.dumps(out))
 
 
 def traffic_of(a, kernel):
@@ -192,15 +270,61 @@ def bench_batch(a):
     print(json.dumps(out))
 
 
+def _spherical_jn_zero_distance(x, nmax):
+    """Distance from x to the nearest zero of j_n, n = 0..nmax (interior
+    Dirichlet eigenvalues of the unit sphere, where the single-layer
+    operator of a sphere is singular)."""
+    from scipy.optimize import brentq
+    from scipy.special import spherical_jn
+    best = np.inf
+    grid = np.linspace(max(1e-3, x - 4.0), x + 4.0, 801)
+    for n in range(nmax + 1):
+        v = spherical_jn(n, grid)
+        for i in np.nonzero(np.sign(v[:-1]) * np.sign(v[1:]) < 0)[0]:
+            z = brentq(lambda u: spherical_jn(n, u), grid[i], grid[i + 1])
+            best = min(best, abs(z - x))
+    return float(best)
+
+
+def serve_diagnostics(records):
+    """For each request that did not converge: k h_max, panels per wavelength
+    (wavelength over the longest edge) and, for spheres, the distance of k a
+    to the nearest zero of j_n."""
+    import synth
+    out = []
+    meshes = {}
+    for r in records:
+        if r["state"] == 2:
+            continue
+        if r["subdiv"] not in meshes:
+            meshes[r["subdiv"]] = synth.icosphere(r["subdiv"])
+        V, T = meshes[r["subdiv"]]
+        V = V * np.asarray(r["axes"]).reshape(1, 3)
+        e = np.concatenate([np.linalg.norm(V[T[:, i]] - V[T[:, (i + 1) % 3]], axis=1) for i in range(3)])
+        hmax = float(e.max())
+        d = dict(id=r["id"], subdiv=r["subdiv"], k=r["k"], axes=[round(v, 3) for v in r["axes"]], state=r["state"],
+                 iters=r["iters"], resid_true=r["resid_true"], k_hmax=r["k"] * hmax,
+                 panels_per_wavelength=2 * math.pi / r["k"] / hmax)
+        if all(abs(v - 1.0) < 1e-12 for v in r["axes"]):
+            d["ka_to_jn_zero"] = _spherical_jn_zero_distance(r["k"], int(r["k"]) + 10)
+        out.append(d)
+    return out
+
+
 def bench_serve(a):
     import synth
     from paper_1803_09948_amd import serve
 
     trace = synth.serve_trace(nreq=a.nreq, rate=50.0, seed=777)
     log(f"serving {a.nreq} requests")
-    st = serve.serve(trace, max_active=a.slots, log=log)
+    st = serve.serve(trace, max_active=a.slots, log=log, stall_restarts=a.stall_restarts, stall_factor=0.5)
+    recs = st.pop("records")
+    st["diagnostics"] = serve_diagnostics(recs)
     log("served", st)
-    sp = serve.serve_plain(trace, log=log) if not a.no_plain else None
+    sp = None
+    if not a.no_plain:
+        sp = serve.serve_plain(trace, log=log)
+        sp["diagnostics"] = serve_diagnostics(sp.pop("records"))
     log("plain", sp)
     out = {
         "metric": "served BIE solves/s and p99 latency (Poisson 50 req/s)",
@@ -208,7 +332,8 @@ def bench_serve(a):
         "ms_per_step": st["mean_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{a.nreq} requests, Poisson 50/s, icosphere subdivision 3..6, sphere or "
-                               "ellipsoid, k uniform [1, 30], P=10, GMRES(30) to 1e-4", "slots": a.slots},
+                               "ellipsoid, k uniform [1, 30], P=10, GMRES(30) to 1e-4", "slots": a.slots,
+                   "stall_restarts": a.stall_restarts},
         "served": st, "plain": sp,
     }
     print(json.dumps(out))
@@ -451,7 +576,8 @@ def bench_scaling(a):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "precision", "bie", "copy", "scaling", "nystrom"],
+    ap.add_argument("--workload", choices=["matvec", "batch", "serve", "precision", "bie", "copy", "scaling", "nystrom",
+                                           "oracle"],
                     default="matvec")
     ap.add_argument("--prec-n", default="1048576,8388608", help="sizes of the precision workload")
     ap.add_argument("--prec-P", default="8,10,12", help="orders of the precision workload")
@@ -463,6 +589,9 @@ def main():
     ap.add_argument("--nreq", type=int, default=24, help="requests (serve workload)")
     ap.add_argument("--slots", type=int, default=16, help="concurrent solves (serve workload)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--stall-restarts", type=int, default=10,
+                    help="serve workload: stop a solve whose true residual has not halved over this many "
+                         "restarts (0: off)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
@@ -471,8 +600,12 @@ def main():
     ap.add_argument("--k", type=float, default=16.0 * math.pi)
     ap.add_argument("--k-imag", type=float, default=0.0, help="imaginary part of the wavenumber (damped waves)")
     ap.add_argument("--ncrit", type=int, default=64)
+    ap.add_argument("--stage-mb", type=int, default=0,
+                    help="M2L staging budget in MiB (0: the library default); smaller budgets run the "
+                         "M2L and its reduction in target segments")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check", action="store_true", help="compare 200 sampled outputs with the FP64 direct sum")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip comparing 200 sampled outputs with the FP64 direct sum on the GPU")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: the library runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -492,23 +625,33 @@ def main():
         return bench_scaling(a)
     if a.workload == "nystrom":
         return bench_nystrom(a)
+    if a.workload == "oracle":
+        return bench_oracle(a)
 
     import torch
 
     import synth
     from paper_1803_09948_amd import hfmm
 
-    dev = torch.device("cuda:0")
     x = synth.sphere_points(a.n, 23)
     q = synth.strengths(a.n, 23)
     t0 = time.perf_counter()
-    tree = hfmm.Tree.from_points(x, ncrit=a.ncrit, k_imag=a.k_imag)
+    tree = hfmm.Tree.from_points(x, ncrit=a.ncrit, k_imag=a.k_imag, stage_mb=a.stage_mb)
     t_tree = time.perf_counter() - t0
-    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    plan = tree.plan(a.k, a.P)               # host only: tree at (k, P), lists, work lists
+    t_plan = time.perf_counter() - t0
+    # the oracle on the host cores first, in forked workers, before this
+    # process touches the GPU
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(x, q, a.k, a.P, plan)
+        log("cpu baseline:", json.dumps(cpu))
+    dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     tree.prepare(a.k, a.P)
     torch.cuda.synchronize()
-    t_prep = time.perf_counter() - t0
+    t_prep = t_plan + time.perf_counter() - t0
     st = tree.stats(a.k, a.P)
     log(f"setup: tree {t_tree:.2f} s, lists+operators {t_prep:.2f} s; {json.dumps(st)}")
     qd = torch.from_numpy(q).to(dev)
@@ -575,7 +718,8 @@ def main():
         "config": {"workload": f"helmholtz FMM matvec, N={a.n} uniform on the unit sphere, k={a.k:.6g} "
                                f"(16 wavelengths across)" + (f" + {a.k_imag:g}i (damped)" if a.k_imag else "") +
                                f", P={a.P}, ncrit={a.ncrit}, theta=0.5, kappa=0.4P",
-                   "n": a.n, "k": a.k, "k_imag": a.k_imag, "P": a.P, "ncrit": a.ncrit},
+                   "n": a.n, "k": a.k, "k_imag": a.k_imag, "P": a.P, "ncrit": a.ncrit,
+                   **({"stage_mb": a.stage_mb} if a.stage_mb else {})},
         "roofline": roof,
         "phases_ms": phases,
         "secondary": {"p2p_tflops": p2p_ach / 1e12, "p2p_gpairs_per_s": st["p2p_body_pairs"] / phases["p2p"] / 1e6,
@@ -583,7 +727,7 @@ def main():
                       "n_tables": st["n_tables"], "setup_s": {"tree": t_tree, "prepare": t_prep},
                       "m2l_shapes": {"tuned": tuned, "ms": shape_ms}},
     }
-    if a.check and not a.k_imag:
+    if not a.no_check and not a.k_imag:
         # the library's FP64 direct sum on the GPU over all sources, 200 targets
         rng = np.random.default_rng(1)
         idx = torch.from_numpy(np.sort(rng.choice(a.n, 200, replace=False))).to(dev)
@@ -592,8 +736,8 @@ def main():
         y = yd[idx].to(torch.complex128)
         out["secondary"]["rel_err_vs_direct64_200"] = float(torch.linalg.vector_norm(y - ref) /
                                                             torch.linalg.vector_norm(ref))
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x, q, a.k, a.P, a.ncrit, st)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 
