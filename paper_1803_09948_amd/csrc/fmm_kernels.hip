@@ -1042,12 +1042,15 @@ __global__ void __launch_bounds__(64) k_l2p(const int2* __restrict__ items, cons
 
 // ---------------------------------------------------------------------------
 // P2P (Listing 1 without the near branch): y_i += sum_j q_j e^{ikR}/(4 pi R),
-// R > 0.  One wave per target leaf.  Each lane owns up to two targets and a
-// residue class of sources (lane = target pair + npair * split).  The source
-// stream of the leaf (its merged source intervals) is cut into full tiles of
-// 64; each tile is staged through LDS while the next one is already being
-// loaded into registers.  Coordinates stay unscaled so that the difference of
-// two nearby FP32 points is exact; the phase in revolutions is R k/(2 pi).
+// R > 0.  One wave per target leaf, its targets taken in blocks of up to 64.
+// Each lane owns T targets of a block (T = 1..4, chosen per block so that
+// the most lanes are busy) and a residue class of sources (lane = target
+// group + ngroup * split).  The source stream of the leaf (its merged source
+// intervals) is cut into tiles of L <= 64 sources, L a multiple of the
+// number of splits, so every busy lane runs the same number of iterations;
+// each tile is staged through LDS while the next one is already being
+// loaded into registers.  Coordinates stay unscaled so that the difference
+// of two nearby FP32 points is exact; the phase in revolutions is R k/(2 pi).
 // Deterministic: each target is owned by one wave and the split partial sums
 // are added in a fixed order.
 // ---------------------------------------------------------------------------
@@ -1070,6 +1073,113 @@ __device__ inline void p2p_fetch(const int2* __restrict__ ivals, int iv, int ie,
   w = make_float2(0.f, 0.f);
 }
 
+// Targets per lane for a block of tc targets: the T in 1..4 with the most
+// busy lane slots, tc nsplit / (64 T) with nsplit = floor(64 / ceil(tc / T))
+// (ties: the larger T, whose source loads serve more targets).
+__device__ inline int p2p_targets_per_lane(int tc) {
+  int best = 1;
+  int bnum = -1, bden = 1;
+  for (int T = 1; T <= 4; ++T) {
+    const int ng = (tc + T - 1) / T;
+    const int num = tc * (64 / ng), den = 64 * T;
+    if (num * bden >= bnum * den) {
+      bnum = num;
+      bden = den;
+      best = T;
+    }
+  }
+  return best;
+}
+
+// One pair: a += q G(x, y) up to the 1/(4 pi) applied at the end.
+template <bool DAMP>
+__device__ inline void p2p_pair(float xx, float xy, float xz, float4 yj, float2 qj, float krev, float kdec,
+                                float& ar, float& ai) {
+  float dx = xx - yj.x, dy = xy - yj.y, dz = xz - yj.z;
+  float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  float rinv = (r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
+  float rev = r2 * rinv * krev;
+  float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
+  if constexpr (DAMP) rinv *= __builtin_amdgcn_exp2f(r2 * rinv * kdec);
+  float gr = cs * rinv, gi = sn * rinv;
+  ar = fmaf(qj.x, gr, fmaf(-qj.y, gi, ar));
+  ai = fmaf(qj.x, gi, fmaf(qj.y, gr, ai));
+}
+
+// Targets [t0, t0 + tc) of the leaf against all its sources, T per lane.
+template <int T, bool DAMP>
+__device__ inline void p2p_block(const InstDev& I, int4 wk, int total, int t0, int tc, int lane, float4 (*sp)[64],
+                                 float2 (*sq)[64], float2* red, float krev, float kdec) {
+  const int ng = (tc + T - 1) / T;            // target groups
+  const int nsplit = 64 / ng;
+  const int L = nsplit * (64 / nsplit);       // sources per tile
+  const int g = lane % ng, s = lane / ng;
+  const bool active = s < nsplit;
+  float xx[T], xy[T], xz[T], ar[T], ai[T];
+#pragma unroll
+  for (int i = 0; i < T; ++i) {
+    const float4 p = I.tpos[min(t0 + T * g + i, t0 + tc - 1)];
+    xx[i] = p.x;
+    xy[i] = p.y;
+    xz[i] = p.z;
+    ar[i] = 0.f;
+    ai[i] = 0.f;
+  }
+  const int2* __restrict__ ivals = I.p2p_ivals;
+  int iv = wk.z, off = 0;
+  float4 np4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float2 nq = make_float2(0.f, 0.f);
+  if (lane < L) p2p_fetch(ivals, iv, wk.w, off, lane, I.spos, I.q, np4, nq);
+  int tile = 0;
+  for (int base = 0; base < total; base += L, ++tile) {
+    const int nj = min(L, total - base);
+    const int buf = tile & 1;
+    sp[buf][lane] = np4;
+    sq[buf][lane] = nq;
+    off += L;
+    while (iv < wk.w && off >= ivals[iv].y - ivals[iv].x) {
+      off -= ivals[iv].y - ivals[iv].x;
+      ++iv;
+    }
+    if (base + L < total && lane < L) p2p_fetch(ivals, iv, wk.w, off, lane, I.spos, I.q, np4, nq);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (active) {
+      const float4* P = sp[buf];
+      const float2* Q = sq[buf];
+      for (int j = s; j < nj; j += nsplit) {
+        const float4 yj = P[j];
+        const float2 qj = Q[j];
+#pragma unroll
+        for (int i = 0; i < T; ++i) p2p_pair<DAMP>(xx[i], xy[i], xz[i], yj, qj, krev, kdec, ar[i], ai[i]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // target T g + i of this block sums red[(g + ss ng) T + i] over the splits
+#pragma unroll
+  for (int i = 0; i < T; ++i) red[lane * T + i] = make_float2(ar[i], ai[i]);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane < tc) {
+    const int gg = lane / T, ii = lane - T * gg;
+    float sr = 0.f, si = 0.f;
+    for (int ss = 0; ss < nsplit; ++ss) {
+      const float2 v = red[(gg + ss * ng) * T + ii];
+      sr += v.x;
+      si += v.y;
+    }
+    const float scale = 0.07957747154594767f;  // 1 / (4 pi)
+    float2 o = I.ys[t0 + lane];
+    o.x = fmaf(sr, scale, o.x);
+    o.y = fmaf(si, scale, o.y);
+    I.ys[t0 + lane] = o;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // DAMP: complex wavenumber k + i ki, G times the decay e^{-ki R} (the
 // imaginary wavenumber of the listing's exponential).
 template <bool DAMP>
@@ -1079,96 +1189,22 @@ __global__ void __launch_bounds__(256) k_p2p(const int2* __restrict__ items, int
   const int w = blockIdx.x * 4 + wave;
   __shared__ float4 sp[4][2][64];
   __shared__ float2 sq[4][2][64];
-  __shared__ float4 red[4][64];
+  __shared__ float2 red[4][64 * 4];
   if (w >= nitems) return;
   const int2 it = items[w];
   const InstDev& I = insts[it.x];
   const int4 wk = I.p2p_work[it.y];
   const int total = I.p2p_total[it.y];
-  const int2* __restrict__ ivals = I.p2p_ivals;
-  const float4* __restrict__ spos = I.spos;
-  const float2* __restrict__ q = I.q;
   const float krev = I.k * 0.15915494309189535f;  // k / (2 pi)
   const float kdec = -I.ki * 1.4426950408889634f;  // -ki log2(e): decay 2^(kdec R)
   for (int t0 = wk.x; t0 < wk.y; t0 += 64) {
     const int tc = min(64, wk.y - t0);
-    const int np = (tc + 1) >> 1;                 // target pairs
-    const int nsplit = 64 / np;
-    const int pi = lane % np, s = lane / np;
-    const bool active = s < nsplit;
-    const int ia = t0 + 2 * pi, ib = min(ia + 1, t0 + tc - 1);
-    const float4 xa = I.tpos[ia], xb = I.tpos[ib];
-    float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
-    int iv = wk.z, off = 0;
-    float4 np4;
-    float2 nq;
-    p2p_fetch(ivals, iv, wk.w, off, lane, spos, q, np4, nq);
-    for (int base = 0; base < total; base += 64) {
-      const int nj = min(64, total - base);
-      const int buf = (base >> 6) & 1;
-      sp[wave][buf][lane] = np4;
-      sq[wave][buf][lane] = nq;
-      off += 64;
-      while (iv < wk.w && off >= ivals[iv].y - ivals[iv].x) {
-        off -= ivals[iv].y - ivals[iv].x;
-        ++iv;
-      }
-      if (base + 64 < total) p2p_fetch(ivals, iv, wk.w, off, lane, spos, q, np4, nq);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (active) {
-        const float4* P = sp[wave][buf];
-        const float2* Q = sq[wave][buf];
-        for (int j = s; j < nj; j += nsplit) {
-          const float4 yj = P[j];
-          const float2 qj = Q[j];
-          {
-            float dx = xa.x - yj.x, dy = xa.y - yj.y, dz = xa.z - yj.z;
-            float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            float rinv = (r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
-            float rev = r2 * rinv * krev;
-            float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
-            if constexpr (DAMP) rinv *= __builtin_amdgcn_exp2f(r2 * rinv * kdec);
-            float gr = cs * rinv, gi = sn * rinv;
-            ar = fmaf(qj.x, gr, fmaf(-qj.y, gi, ar));
-            ai = fmaf(qj.x, gi, fmaf(qj.y, gr, ai));
-          }
-          {
-            float dx = xb.x - yj.x, dy = xb.y - yj.y, dz = xb.z - yj.z;
-            float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            float rinv = (r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
-            float rev = r2 * rinv * krev;
-            float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
-            if constexpr (DAMP) rinv *= __builtin_amdgcn_exp2f(r2 * rinv * kdec);
-            float gr = cs * rinv, gi = sn * rinv;
-            br = fmaf(qj.x, gr, fmaf(-qj.y, gi, br));
-            bi = fmaf(qj.x, gi, fmaf(qj.y, gr, bi));
-          }
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
+    switch (p2p_targets_per_lane(tc)) {
+      case 1: p2p_block<1, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
+      case 2: p2p_block<2, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
+      case 3: p2p_block<3, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
+      default: p2p_block<4, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
     }
-    __builtin_amdgcn_wave_barrier();
-    red[wave][lane] = make_float4(ar, ai, br, bi);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < tc) {
-      const int pp = lane >> 1, slot = lane & 1;
-      float sr = 0.f, si = 0.f;
-      for (int ss = 0; ss < nsplit; ++ss) {
-        float4 v = red[wave][pp + ss * np];
-        sr += slot ? v.z : v.x;
-        si += slot ? v.w : v.y;
-      }
-      const float scale = 0.07957747154594767f;  // 1 / (4 pi)
-      float2 o = I.ys[t0 + lane];
-      o.x = fmaf(sr, scale, o.x);
-      o.y = fmaf(si, scale, o.y);
-      I.ys[t0 + lane] = o;
-    }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
