@@ -723,7 +723,12 @@ def main():
         "roofline": roof,
         "phases_ms": phases,
         "secondary": {"p2p_tflops": p2p_ach / 1e12, "p2p_gpairs_per_s": st["p2p_body_pairs"] / phases["p2p"] / 1e6,
-                      "m2l_tflops": m2l_ach / 1e12, "n_m2l": st["n_m2l"], "p2p_body_pairs": st["p2p_body_pairs"],
+                      "m2l_tflops": m2l_ach / 1e12,
+                      # what the matrix cores execute: 3 real products per complex tile (Gauss) over
+                      # P^2 inputs and the outputs padded to whole 16-row tiles
+                      "m2l_issued_tflops": 3 * 2 * (16 * ((a.P * a.P + 15) // 16)) * (4 * ((a.P * a.P + 3) // 4))
+                                           * st["n_m2l"] / (phases["m2l"] * 1e-3) / 1e12,
+                      "n_m2l": st["n_m2l"], "p2p_body_pairs": st["p2p_body_pairs"],
                       "n_tables": st["n_tables"], "setup_s": {"tree": t_tree, "prepare": t_prep},
                       "m2l_shapes": {"tuned": tuned, "ms": shape_ms}},
     }

@@ -375,6 +375,24 @@ void hfmm_tree_free(hfmm_tree* tree);
 const char* hfmm_last_error(void);
 int hfmm_version(void);
 
+/* Test hook: one M2L translation (eq. (12)-(14) translated between cells,
+ * Sec. 2.3) applied to `count` expansion vectors through the product's own
+ * translation-table generator, reflection codes, matrix-core M2L kernel and
+ * fixed-order reduction, so the M2L can be checked coefficient by
+ * coefficient.  Column c is the pair (target c, source c) whose offset,
+ * target centre minus source centre, is the canonical vector t_host
+ * (t0 >= t1 >= 0, t2 >= 0, not zero) under reflection refl_host[c] (bit 3:
+ * swap x and y, then bits 0, 1, 2: negate x, y, z).  Coefficients are in the
+ * product's scaled basis: in = M_n / s_n(rho_in), out = s_n'(rho_out) L_n',
+ * with s_n(rho) = rho^n / (2n + 1)!!.
+ *  in_dev, out_dev: complex64 [count][P^2] device memory (must not alias).
+ *  Allocates, and waits on `stream` before returning.
+ *  EINVAL: k, P as for hfmm_prepare, k_imag < 0, rho outside (0, 1], t not
+ *  canonical, a reflection outside 0..15, count outside [1, 2^20], NULL. */
+int hfmm_debug_m2l(int32_t P, double k, double k_imag, const double* t_host, double rho_in,
+                   double rho_out, int32_t count, const int32_t* refl_host, const void* in_dev,
+                   void* out_dev, void* stream);
+
 /* Test hook for the error paths: after = n >= 0 makes the (n+1)-th next
  * device allocation of the library fail with HFMM_ENOMEM without calling
  * hipMalloc (then the hook turns itself off); -1 turns it off.

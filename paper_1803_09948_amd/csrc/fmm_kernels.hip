@@ -655,6 +655,13 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
     if (np <= 0) continue;
     // column t of this lane is pair 16 t + li: (target, source, reflection,
     // slot); a column past the item's end reads the all-zero code row 16
+    // the multipoles of column t: a 64-bit address per column, or (the
+    // one-chunk shapes, whose register budget is tightest) a 32-bit byte
+    // offset msb[t] beside the wave-uniform base Mb, one register per column
+    // (M of an instance is < 4 GiB); the shapes that run several chunks per
+    // wave keep the 64-bit form, with which they allocate without spills
+    const char* Mb = reinterpret_cast<const char*>(I.M);
+    uint32_t msb[NCT];
     gcfloat2* Ms[NCT];
     int gs[NCT], goff[NCT];
 #pragma unroll
@@ -662,7 +669,10 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
       const int p = 16 * t + li;
       const bool ok = p < np;
       const int4 pr = ld_int4(I.m2l_pairs + pb + (ok ? p : 0));
-      Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
+      if constexpr (CPW == 1)
+        msb[t] = (uint32_t)pr.y * (uint32_t)(P2 * sizeof(float2));
+      else
+        Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
       gs[t] = ok ? pr.z : 16;
       goff[t] = gs[t] * Kp + lk;
     }
@@ -672,7 +682,10 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 #pragma unroll
       for (int t = 0; t < NCT; ++t) {
         const int e = smap[goff[t] + k4];
-        raw[t] = ld2(Ms[t] + (e & 0xffff));
+        if constexpr (CPW == 1)
+          raw[t] = ld2((gcfloat2*)(Mb + (msb[t] + (uint32_t)(e & 0xffff) * (uint32_t)sizeof(float2))));
+        else
+          raw[t] = ld2(Ms[t] + (e & 0xffff));
         code[t] = e;
       }
     };
@@ -699,6 +712,11 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
         k2[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
         k3[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
+    // the operator's table: a 64-bit address per lane, or (one-chunk shapes)
+    // the wave-uniform base Tb and this lane's 32-bit byte offset (a table
+    // is < 4 GiB)
+    const char* Tb = reinterpret_cast<const char*>(I.tables + (size_t)op * Kp * Rp);
+    const uint32_t tlane = (uint32_t)li * (uint32_t)sizeof(float2);
     gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li;
     // the table operand (A) is loaded AD k-steps ahead (2 AD register
     // buffers), the gathered multipoles (B) one step ahead; a straight-line
@@ -707,8 +725,14 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
     float2 av[2 * AD][RT], bv[2][NCT];
     int cv[2][NCT];
     auto load_a = [&](int k, float2* out) {
+      if constexpr (CPW == 1) {
+        const uint32_t off = tlane + (uint32_t)(k * Rp) * (uint32_t)sizeof(float2);
 #pragma unroll
-      for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * r);
+        for (int r = 0; r < RT; ++r) out[r] = ld2((gcfloat2*)(Tb + (off + (uint32_t)(16 * r * sizeof(float2)))));
+      } else {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * r);
+      }
     };
     auto mma = [&](const float2* a) {
 #pragma unroll

@@ -26,7 +26,7 @@ EXPORTS = [
     "hfmm_server_release", "hfmm_server_used_bytes", "hfmm_server_free",
     "hfmm_variant_count", "hfmm_set_variant", "hfmm_tree_variant", "hfmm_matvec64", "hfmm_direct64",
     "hfmm_build_nystrom", "hfmm_nystrom_points", "hfmm_tree_plan", "hfmm_server_set_limits",
-    "hfmm_debug_fail_alloc", "hfmm_gmres_solve_noalloc",
+    "hfmm_debug_fail_alloc", "hfmm_gmres_solve_noalloc", "hfmm_debug_m2l",
 ]
 
 
@@ -123,6 +123,7 @@ def lib():
             "hfmm_server_set_limits": [vp, i32, dbl, dbl],
             "hfmm_debug_fail_alloc": [i64],
             "hfmm_gmres_solve_noalloc": [vp, dbl, i32, vp, vp, dbl, i32, i32, C.POINTER(GmresInfo), vp],
+            "hfmm_debug_m2l": [i32, dbl, dbl, vp, dbl, dbl, i32, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -364,6 +365,22 @@ def direct64(src, q, tgt, k, stream=None):
                                C.c_void_p(tgt.data_ptr()), int(tgt.shape[0]), float(k),
                                C.c_void_p(y.data_ptr()), _stream(torch, stream)))
     return y
+
+
+def debug_m2l(P: int, k: float, t, rho_in: float, rho_out: float, refl, m_in, k_imag: float = 0.0, stream=None):
+    """Test hook: one canonical M2L operator (offset t) under the reflections
+    `refl` (one per column) applied to the scaled expansions m_in
+    (complex64 CUDA tensor [count][P^2]) through the product's kernels;
+    returns the scaled local expansions (see hfmm_debug_m2l)."""
+    import torch
+    tt = np.ascontiguousarray(t, dtype=np.float64)
+    rr = np.ascontiguousarray(refl, dtype=np.int32)
+    n = len(rr)
+    ip = _dev_vec(m_in, torch.complex64, n * P * P, "m_in")
+    out = torch.empty_like(m_in)
+    _check(lib().hfmm_debug_m2l(int(P), float(k), float(k_imag), tt.ctypes.data, float(rho_in), float(rho_out), n,
+                                rr.ctypes.data, ip, C.c_void_p(out.data_ptr()), _stream(torch, stream)))
+    return out
 
 
 def debug_fail_alloc(after: int):
