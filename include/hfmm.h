@@ -68,7 +68,9 @@ typedef struct {
   int32_t near_levels; /* BIE near integrals: 4^near_levels sub-triangles (default 3) */
   int32_t near_order;  /* BIE near integrals: n x n collapsed Gauss rule (default 6) */
   int32_t stage_mb;    /* M2L staging budget in MiB (default 32768; <= 0: default): larger
-                          problems run the M2L in segments of targets whose staging fits */
+                          problems run the M2L in segments of targets whose staging fits;
+                          the staging then holds two segments, so that one segment's
+                          reduction overlaps the next segment's M2L */
   int32_t bie_treatment; /* BIE singular-integral treatment: 0 self + near corrections
                             (default), 1 self-panel integral only, 2 none (the 3-point rule
                             everywhere, the listing without its near branch) */
@@ -366,7 +368,10 @@ int hfmm_phase_times(const hfmm_tree* tree, float* ms10);
  *    not exist for P); -1 restores tuning.  Process-wide; a captured graph
  *    is re-captured when its shape changes.
  *  hfmm_tree_variant: the shape the plain matvec of (tree, k, P) uses, or -1
- *    before its first product. */
+ *    before its first product.
+ * With the environment variable HFMM_TUNE_CACHE naming a file, the choices
+ * are read from it on first use (lines "phase P log2size variant") and each
+ * new choice is appended, so later processes reuse them without timing. */
 int hfmm_variant_count(int32_t phase, int32_t P);
 int hfmm_set_variant(int32_t phase, int32_t variant);
 int hfmm_tree_variant(hfmm_tree* tree, double k, int32_t P, int32_t phase, int32_t* variant);

@@ -402,10 +402,17 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
   spairs.resize(npair);
   std::vector<int4> chunks;
   hd.slot_g.assign(std::max<size_t>(1, npair), 0);
+  // With several segments the staging holds two segment buffers, used in
+  // turn, so that the reduction of one segment overlaps the M2L of the next.
+  pl.max_seg_slots = 0;
+  for (const M2LSeg& sgm : pl.m2l_segs) pl.max_seg_slots = std::max<int64_t>(pl.max_seg_slots, sgm.slot_e - sgm.slot_b);
+  pl.stage_bufs = pl.m2l_segs.size() > 1 ? 2 : 1;
   parallel_for(npair, TH, [&](size_t i0, size_t i1, int) {
-    for (size_t i = i0; i < i1; ++i) {  // slots are local to the pair's segment
+    for (size_t i = i0; i < i1; ++i) {  // slots are local to the pair's segment and its buffer
       const int4& p = pairs[order[i]];
-      spairs[i] = make_int4(p.x, p.y, p.z, slot[order[i]] - pl.m2l_segs[seg_of[p.x]].slot_b);
+      const int sg = seg_of[p.x];
+      const int64_t rel = slot[order[i]] - pl.m2l_segs[sg].slot_b + (sg % pl.stage_bufs) * pl.max_seg_slots;
+      spairs[i] = make_int4(p.x, p.y, p.z, (int32_t)rel);
       hd.slot_g[slot[order[i]]] = (uint8_t)p.z;
     }
   });
@@ -420,8 +427,6 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     pl.m2l_segs[sg].chunk_e = (int)chunks.size();
     i = j;
   }
-  pl.max_seg_slots = 0;
-  for (const M2LSeg& sgm : pl.m2l_segs) pl.max_seg_slots = std::max<int64_t>(pl.max_seg_slots, sgm.slot_e - sgm.slot_b);
   pl.n_m2l_chunks = (int32_t)chunks.size();
   pl.m2l_chunks_h = chunks;
   // per-cell operator indices and per-level work lists
@@ -494,7 +499,8 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     // M2L staging of the largest segment
     pl.bytes_exp = (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)Kp * Rp * sizeof(float2)) +
                    (int64_t)pl.rho.size() * 8 + 2 * nc * P2 * (int64_t)sizeof(float2) +
-                   std::max<int64_t>(1, pl.max_seg_slots) * (int64_t)(Sm + St) * (int64_t)sizeof(float2);
+                   pl.stage_bufs * std::max<int64_t>(1, pl.max_seg_slots) * (int64_t)(Sm + St) *
+                       (int64_t)sizeof(float2);
     // BIE corrections: near values (float2) and the self term (double2 per
     // panel, or a 6 x 6 double2 block row per curved-element point)
     pl.bytes_corr = t.bie ? (int64_t)t.near_col.size() * 8 + t.npanel * (t.nystrom ? 96 : 16) : 0;
@@ -524,7 +530,8 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   if ((rc = upload(pl.d_ops, hd.ops)) || (rc = upload(pl.d_rho, pl.rho)) ||
       (rc = upload(pl.d_m2l_pairs, hd.spairs)) || (rc = upload(pl.d_cops, hd.cops)) ||
       (rc = upload(pl.d_m2l_soff, hd.soff)) ||
-      (rc = pl.d_stage.alloc((size_t)std::max<int64_t>(1, pl.max_seg_slots) * (size_t)(Sm + St) * sizeof(float2))) ||
+      (rc = pl.d_stage.alloc((size_t)pl.stage_bufs * (size_t)std::max<int64_t>(1, pl.max_seg_slots) *
+                             (size_t)(Sm + St) * sizeof(float2))) ||
       (rc = upload(pl.d_p2p_work, hd.work)) || (rc = upload(pl.d_p2p_ivals, hd.ivals)) ||
       (rc = upload(pl.d_p2p_total, hd.totals)))
     return rc;

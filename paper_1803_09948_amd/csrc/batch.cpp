@@ -7,6 +7,8 @@
 // one launch per phase and level for all instances together, and can be
 // captured once as a hipGraph and replayed.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <atomic>
 #include <cstring>
 #include <map>
@@ -27,6 +29,9 @@ namespace hfmm {
   } while (0)
 
 Batch::~Batch() {
+  for (hipEvent_t e : ev_m2l) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ev_red) (void)hipEventDestroy(e);
+  if (red) (void)hipStreamDestroy(red);
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (ev_in) (void)hipEventDestroy(ev_in);
@@ -60,7 +65,7 @@ static InstDev make_inst(Tree& t, Plan& pl) {
     int Sm, St;
     stage_dims(pl.P, &Sm, &St);
     I.stage = pl.d_stage.as<float2>();  // [slots][Sm], then the tails [slots][St]
-    I.stage_tail = I.stage + std::max<int64_t>(1, pl.max_seg_slots) * Sm;
+    I.stage_tail = I.stage + pl.stage_bufs * std::max<int64_t>(1, pl.max_seg_slots) * Sm;
   }
   I.slot_g = pl.d_slot_g.as<uint8_t>();
   I.m2l_soff = pl.d_m2l_soff.as<int32_t>();
@@ -145,7 +150,9 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
         m2l.push_back(make_int4(i, ch.x, ch.y, ch.z));
       }
       for (int t = S.tgt_b; t < S.tgt_e; ++t) red.push_back(make_int2(i, pl.m2l_targets[t]));
-      if (b.count == 1) b.seg_slot_base[sg] = S.slot_b;
+      // the reduction finds slot g of the segment at staging position
+      // g - base: the segment's buffer holds its slots from slot_b on
+      if (b.count == 1) b.seg_slot_base[sg] = S.slot_b - (int64_t)(sg % pl.stage_bufs) * pl.max_seg_slots;
     }
   }
   b.m2l_seg_off[b.nseg] = (int)m2l.size();
@@ -247,14 +254,29 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
                P, s);
   if ((rc = mark(2))) return rc;
   // M2L and its reduction per staging segment (marks 3 and 4 split the two
-  // phases when there is one segment; with several, phase 3 holds both)
+  // phases when there is one segment; with several, phase 3 holds both).
+  // With several segments (and no phase timing) the reduction of segment
+  // sg runs on the reduction stream beside the M2L of segment sg + 1; the
+  // two staging buffers alternate, so the M2L of segment sg waits for the
+  // reduction of segment sg - 2, and the L2L waits for every reduction.
+  const bool overlap = fork && b.nseg > 1;
   for (int sg = 0; sg < b.nseg; ++sg) {
+    if (overlap && sg >= 2) HIP_TRY(hipStreamWaitEvent(s, b.ev_red[sg - 2], 0));
     launch_m2l(b.d_m2l.as<int4>() + b.m2l_seg_off[sg], b.m2l_seg_off[sg + 1] - b.m2l_seg_off[sg], I,
                p0.d_bmap.as<int32_t>(), P, batch_variant(b, kPhaseM2L), s);
     if (b.nseg == 1 && (rc = mark(3))) return rc;
+    hipStream_t rs = s;
+    if (overlap) {
+      HIP_TRY(hipEventRecord(b.ev_m2l[sg], s));
+      HIP_TRY(hipStreamWaitEvent(b.red, b.ev_m2l[sg], 0));
+      rs = b.red;
+    }
     launch_m2l_reduce(b.d_red.as<int2>() + b.red_seg_off[sg], b.red_seg_off[sg + 1] - b.red_seg_off[sg], I,
-                      p0.d_omap.as<int32_t>(), P, b.seg_slot_base[sg], s);
+                      p0.d_omap.as<int32_t>(), P, b.seg_slot_base[sg], rs);
+    if (overlap) HIP_TRY(hipEventRecord(b.ev_red[sg], b.red));
   }
+  if (overlap)
+    for (int sg = std::max(0, b.nseg - 2); sg < b.nseg; ++sg) HIP_TRY(hipStreamWaitEvent(s, b.ev_red[sg], 0));
   if (b.nseg > 1 && (rc = mark(3))) return rc;
   if ((rc = mark(4))) return rc;
   for (int l = 1; l < b.maxlev; ++l)
@@ -285,6 +307,37 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
 static std::atomic<int> g_override[kNumTunedPhases] = {{-1}};
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, int> g_tuned;
+static bool g_tuned_loaded = false;
+
+// Persistent choices: with HFMM_TUNE_CACHE naming a file, the choices are
+// read from it once (lines "phase P log2size variant") and every new choice
+// is appended, so later processes skip the timing.  Unreadable or malformed
+// lines are ignored.  Call with g_tune_mu held.
+static const char* tune_cache_path() {
+  const char* p = std::getenv("HFMM_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+static void tune_cache_load() {
+  if (g_tuned_loaded) return;
+  g_tuned_loaded = true;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  int ph, P, lg, v;
+  while (std::fscanf(f, "%d %d %d %d", &ph, &P, &lg, &v) == 4)
+    if (ph >= 0 && ph < kNumTunedPhases && P >= 1 && P <= kMaxP && v >= 0 && v < m2l_variant_count(P))
+      g_tuned[std::make_tuple(ph, P, lg)] = v;
+  std::fclose(f);
+}
+static void tune_cache_append(int ph, int P, int lg, int v) {
+  const char* path = tune_cache_path();
+  if (!path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%d %d %d %d\n", ph, P, lg, v);
+    std::fclose(f);
+  }
+}
 
 int set_variant_override(int phase, int variant) {
   if (phase < 0 || phase >= kNumTunedPhases || variant < -1) return set_error("bad phase or variant"), HFMM_EINVAL;
@@ -310,6 +363,7 @@ static int tune_batch(Batch& b, hipStream_t s) {
   const auto key = std::make_tuple((int)kPhaseM2L, b.P, lg);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
       b.m2l_variant = it->second;
@@ -350,6 +404,7 @@ static int tune_batch(Batch& b, hipStream_t s) {
   b.m2l_variant = pick;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned[key] = pick;
+  tune_cache_append(kPhaseM2L, b.P, lg, pick);
   return HFMM_OK;
 }
 
@@ -360,6 +415,16 @@ int ready_batch(Batch& b, hipStream_t s) {
     HIP_TRY(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&b.ev_fork, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&b.ev_join, hipEventDisableTiming));
+  }
+  if (b.nseg > 1) {
+    if (!b.red) HIP_TRY(hipStreamCreateWithFlags(&b.red, hipStreamNonBlocking));
+    for (int sg = (int)b.ev_m2l.size(); sg < b.nseg; ++sg) {
+      hipEvent_t e1, e2;
+      HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
+      b.ev_m2l.push_back(e1);
+      HIP_TRY(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
+      b.ev_red.push_back(e2);
+    }
   }
   return HFMM_OK;
 }

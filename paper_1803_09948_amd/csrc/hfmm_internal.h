@@ -152,6 +152,7 @@ struct Plan {
   std::vector<int32_t> m2l_targets;  // cells that receive M2L
   std::vector<M2LSeg> m2l_segs;      // staging segments (one unless the staging budget is exceeded)
   int64_t max_seg_slots = 0;
+  int stage_bufs = 1;                // segment buffers in the staging (2 with several segments)
   // host work lists (cells / chunks of this instance)
   std::vector<int32_t> src_leaves, tgt_leaves;
   std::vector<std::vector<int32_t>> m2m_cells, l2l_cells;  // per level
@@ -200,6 +201,8 @@ struct Batch {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipStream_t side = nullptr;         // P2P, concurrent with the far field
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t red = nullptr;          // M2L reductions of earlier segments beside the M2L of later ones
+  std::vector<hipEvent_t> ev_m2l, ev_red;  // per segment: its M2L done, its reduction done
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int m2l_variant = -1;               // launch shape chosen by the autotuner

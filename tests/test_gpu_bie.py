@@ -203,3 +203,23 @@ def test_wing_fuselage_scattered_field_converges():
     d1, d2 = rel(us[1], us[0]), rel(us[2], us[1])
     print("  changes", d1, d2)
     assert d2 < d1 / 2 and d2 < 2e-2
+
+
+def test_gmres_checkpoint_resume_bitwise():
+    """A restart boundary is a checkpoint: stopping after whole cycles
+    (maxit a multiple of the restart) and resuming from the returned x gives
+    bitwise the uninterrupted solve, with the same total iteration count
+    (the resumed call recomputes the true residual of x, as the
+    uninterrupted solve does at that boundary)."""
+    k, m = 5.0, 8
+    V, T = synth.icosphere(3)
+    t = hfmm.Tree.from_mesh(V, T)
+    b = t.plane_wave(k)
+    x_ref, i_ref = t.gmres(k, 10, b, tol=1e-6, restart=m, maxit=2000)
+    assert i_ref["converged"] and i_ref["iters"] > 2 * m
+    x1, i1 = t.gmres(k, 10, b, tol=1e-6, restart=m, maxit=2 * m)          # checkpoint after two cycles
+    assert not i1["converged"] and i1["iters"] == 2 * m
+    x2, i2 = t.gmres(k, 10, b, x0=x1, tol=1e-6, restart=m, maxit=2000)    # resume
+    print("uninterrupted", i_ref, "checkpoint", i1, "resumed", i2)
+    assert i2["converged"] and i1["iters"] + i2["iters"] == i_ref["iters"]
+    np.testing.assert_array_equal(x2.cpu().numpy(), x_ref.cpu().numpy())

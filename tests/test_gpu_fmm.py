@@ -181,3 +181,36 @@ def test_overlapped_and_serial_sequences_bit_identical():
     b.set_timing(True)
     z1 = b.matvec(6.0, P, qb).cpu().numpy()
     assert np.array_equal(z0, z1)
+
+
+def test_autotune_cache_file(tmp_path):
+    """HFMM_TUNE_CACHE: a first process times the M2L shapes and appends its
+    choice to the file; a later process takes the shape from the file
+    without timing (shown by editing the file to another valid shape)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = str(tmp_path / "tune.txt")
+    prog = ("import sys; sys.path.insert(0, %r)\n"
+            "import torch, synth\n"
+            "from paper_1803_09948_amd import hfmm\n"
+            "x = synth.sphere_points(20000, 31)\n"
+            "q = torch.from_numpy(synth.strengths(20000, 31)).cuda()\n"
+            "t = hfmm.Tree.from_points(x)\n"
+            "t.matvec(12.0, 10, q)\n"
+            "print('variant', t.variant(12.0, 10))\n") % root
+    env = dict(os.environ, HFMM_TUNE_CACHE=cache)
+
+    def run():
+        r = subprocess.run([sys.executable, "-c", prog], capture_output=True, text=True, env=env, timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return int(r.stdout.split("variant")[-1])
+
+    v1 = run()
+    lines = open(cache).read().split()
+    assert len(lines) == 4 and int(lines[0]) == 0 and int(lines[1]) == 10 and int(lines[3]) == v1
+    other = (v1 + 1) % hfmm.variant_count(10)
+    open(cache, "w").write(f"{lines[0]} {lines[1]} {lines[2]} {other}\n")
+    assert run() == other
+    assert open(cache).read().split() == [lines[0], lines[1], lines[2], str(other)]   # nothing re-timed
