@@ -693,7 +693,18 @@ def main():
     tree.set_timing(False)
     phases = {n: round(v, 4) for n, v in acc.items()}
     log("phases (ms):", phases, "M2L shapes (ms):", shape_ms, "tuned:", tuned)
-    m2l_flops = 8.0 * a.P ** 4 * st["n_m2l"]
+    # the M2L as the kernel computes it (xz-plane form): the C and S blocks,
+    # 8 (C^2 + S^2) = 4 P^4 + 4 P^2 FLOP, plus 16 FLOP per m > 0 entry to turn
+    # the input by the azimuth phase and 16 per m' > 0 row to turn the output
+    P = a.P
+    xs = P * (P - 1) // 2
+    xc = xs + P
+    m2l_flops = (8.0 * (xc * xc + xs * xs) + 32.0 * xs) * st["n_m2l"]
+    # what the matrix cores execute: 3 real products (Gauss) per 16-row tile
+    # and k-step, the first KSS k-steps on all RTC + RTS tiles, the rest on the
+    # RTC tiles of the C block; 2 * 16 * 16 * 4 FLOP each, per 16 pairs
+    kss, ksc, rts, rtc = (xs + 3) // 4, (xc + 3) // 4, (xs + 15) // 16, (xc + 15) // 16
+    m2l_issued = 3 * (kss * (rtc + rts) + (ksc - kss) * rtc) * 2048 / 16 * st["n_m2l"]
     p2p_flops = 20.0 * st["p2p_body_pairs"]
     m2l_ach = m2l_flops / (phases["m2l"] * 1e-3)
     p2p_ach = p2p_flops / (phases["p2p"] * 1e-3)
@@ -701,7 +712,9 @@ def main():
     if dominant == "m2l":
         roof = {"kernel": "k_m2l_mfma", "bound": "mfma", "achieved": m2l_ach / 1e12, "peak": PEAK_FP32 / 1e12,
                 "unit": "TFLOP/s", "frac": m2l_ach / PEAK_FP32, "traffic": traffic_of(a, "k_m2l_mfma"),
-                "per_unit": "8 P^4 FLOP per M2L pair (dense P^2 x P^2 complex operator, FP32 MFMA)",
+                "per_unit": "4 P^4 + 20 P^2 - 16 P FLOP per M2L pair (the operator turned into the xz-plane: "
+                            "C and S blocks of P(P+1)/2 and P(P-1)/2 complex entries squared, plus the "
+                            "azimuth turns; FP32 MFMA)",
                 "units_per_launch": st["n_m2l"], "launch_ms": phases["m2l"]}
     else:
         roof = {"kernel": "k_p2p", "bound": "alu", "achieved": p2p_ach / 1e12, "peak": PEAK_FP32 / 1e12,
@@ -724,10 +737,9 @@ def main():
         "phases_ms": phases,
         "secondary": {"p2p_tflops": p2p_ach / 1e12, "p2p_gpairs_per_s": st["p2p_body_pairs"] / phases["p2p"] / 1e6,
                       "m2l_tflops": m2l_ach / 1e12,
-                      # what the matrix cores execute: 3 real products per complex tile (Gauss) over
-                      # P^2 inputs and the outputs padded to whole 16-row tiles
-                      "m2l_issued_tflops": 3 * 2 * (16 * ((a.P * a.P + 15) // 16)) * (4 * ((a.P * a.P + 3) // 4))
-                                           * st["n_m2l"] / (phases["m2l"] * 1e-3) / 1e12,
+                      "m2l_issued_tflops": m2l_issued / (phases["m2l"] * 1e-3) / 1e12,
+                      # the same launch counted as the dense P^2 x P^2 operator (8 P^4 per pair)
+                      "m2l_dense_equivalent_tflops": 8.0 * P ** 4 * st["n_m2l"] / (phases["m2l"] * 1e-3) / 1e12,
                       "n_m2l": st["n_m2l"], "p2p_body_pairs": st["p2p_body_pairs"],
                       "n_tables": st["n_tables"], "setup_s": {"tree": t_tree, "prepare": t_prep},
                       "m2l_shapes": {"tuned": tuned, "ms": shape_ms}},

@@ -493,11 +493,13 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     // work lists: M2L pair records (int4) and slot reflections (uint8), the
     // per-target slot offsets, P2P work items, source intervals and totals,
     // the reflection code tables
+    const XzDims xd = xz_dims(P);
     pl.bytes_lists = (int64_t)spairs.size() * 17 + (nc + 1) * 4 + (int64_t)work.size() * 20 +
-                     (int64_t)ivals.size() * 8 + (17 * (int64_t)Kp + 16 * P2) * 4;
+                     (int64_t)ivals.size() * 8 + (17 * (int64_t)xd.Kx + 16 * xd.RTS + 16 * P2) * 4 +
+                     17 * (int64_t)Kp * 4;
     // operators (descriptors and padded tables), level scales, M and L, the
     // M2L staging of the largest segment
-    pl.bytes_exp = (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)Kp * Rp * sizeof(float2)) +
+    pl.bytes_exp = (int64_t)ops.size() * (int64_t)(sizeof(OpDesc) + (size_t)xz_table_stride(P) * sizeof(float2)) +
                    (int64_t)pl.rho.size() * 8 + 2 * nc * P2 * (int64_t)sizeof(float2) +
                    pl.stage_bufs * std::max<int64_t>(1, pl.max_seg_slots) * (int64_t)(Sm + St) *
                        (int64_t)sizeof(float2);
@@ -536,9 +538,11 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
       (rc = upload(pl.d_p2p_total, hd.totals)))
     return rc;
   {
-    std::vector<int32_t> in, out;
-    m2l_reflection_codes(P, Kp, in, out);
-    if ((rc = upload(pl.d_bmap, in)) || (rc = upload(pl.d_omap, out)) || (rc = upload(pl.d_slot_g, hd.slot_g)))
+    std::vector<int32_t> in, out, din, dout;
+    m2l_xz_codes(P, in, out);
+    m2l_reflection_codes(P, Kp, din, dout);
+    if ((rc = upload(pl.d_bmap, in)) || (rc = upload(pl.d_omap, out)) || (rc = upload(pl.d_bmap64, din)) ||
+        (rc = upload(pl.d_slot_g, hd.slot_g)))
       return rc;
   }
   // coupling coefficients and tables
@@ -548,7 +552,7 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   DevBuf d_off, d_lm, d_val;
   if ((rc = upload(d_off, cp.off)) || (rc = upload(d_lm, cp.lm)) || (rc = upload(d_val, cv)))
     return rc;
-  if ((rc = pl.d_tables.alloc((size_t)pl.n_ops * Kp * Rp * sizeof(float2)))) return rc;
+  if ((rc = pl.d_tables.alloc((size_t)pl.n_ops * xz_table_stride(P) * sizeof(float2)))) return rc;
   launch_gen_tables(pl.d_ops.as<OpDesc>(), (int)pl.n_ops, P, k, pl.ki, d_off.as<int32_t>(),
                     d_lm.as<int32_t>(), d_val.as<double2>(), pl.d_tables.as<float2>(), s);
   HIP_TRY(hipGetLastError());
@@ -560,7 +564,7 @@ int prepare_device(Tree& t, Plan& pl, hipStream_t s) {
   for (DevBuf* b : {&pl.d_cells, &pl.d_geo, &pl.d_clev, &pl.d_topo, &pl.d_ops, &pl.d_tables, &pl.d_rho,
                     &pl.d_m2l_pairs, &pl.d_p2p_work, &pl.d_p2p_ivals, &pl.d_p2p_total, &pl.d_M,
                     &pl.d_L, &pl.d_cops, &pl.d_stage, &pl.d_m2l_soff, &pl.d_bmap, &pl.d_omap,
-                    &pl.d_slot_g})
+                    &pl.d_bmap64, &pl.d_slot_g})
     pl.device_bytes += (int64_t)b->bytes;
   if (t.bie && (rc = (t.nystrom ? prepare_nystrom(t, pl, s) : prepare_bie(t, pl, s)))) return rc;
   pl.device_bytes += (int64_t)(pl.d_near_val.bytes + pl.d_diag.bytes);

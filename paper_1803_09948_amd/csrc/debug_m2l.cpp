@@ -22,8 +22,7 @@ namespace hfmm {
 // reduction into out.
 static int debug_m2l(int P, double k, double ki, const double* t, double rho_in, double rho_out, int count,
                      const int32_t* refl, const float2* in, float2* out, hipStream_t s) {
-  int Kp, Rp, Sm, St;
-  table_dims(P, &Kp, &Rp);
+  int Sm, St;
   stage_dims(P, &Sm, &St);
   const int P2 = P * P;
   OpDesc d{};
@@ -48,14 +47,14 @@ static int debug_m2l(int P, double k, double ki, const double* t, double rho_in,
   const int CH = m2l_pairs_per_chunk(P);
   for (int b = 0; b < count; b += CH) chunks.push_back(make_int4(0, 0, b, std::min(count, b + CH)));
   std::vector<int32_t> bmap, omap;
-  m2l_reflection_codes(P, Kp, bmap, omap);
+  m2l_xz_codes(P, bmap, omap);
   DevBuf d_ops, d_off, d_lm, d_val, d_tab, d_pairs, d_chunks, d_slotg, d_soff, d_red, d_bmap, d_omap, d_stage, d_inst;
   int rc;
   if ((rc = upload_vec(d_ops, std::vector<OpDesc>{d})) || (rc = upload_vec(d_off, cp.off)) ||
       (rc = upload_vec(d_lm, cp.lm)) || (rc = upload_vec(d_val, cv)) || (rc = upload_vec(d_pairs, pairs)) ||
       (rc = upload_vec(d_chunks, chunks)) || (rc = upload_vec(d_slotg, slot_g)) || (rc = upload_vec(d_soff, soff)) ||
       (rc = upload_vec(d_red, red)) || (rc = upload_vec(d_bmap, bmap)) || (rc = upload_vec(d_omap, omap)) ||
-      (rc = d_tab.alloc((size_t)Kp * Rp * sizeof(float2))) ||
+      (rc = d_tab.alloc((size_t)xz_table_stride(P) * sizeof(float2))) ||
       (rc = d_stage.alloc((size_t)count * (Sm + St) * sizeof(float2))))
     return rc;
   InstDev I{};

@@ -18,15 +18,111 @@ struct OpDescDev {         // translation operator descriptor (48 bytes)
 
 // Padded table dimensions: Kp = 4 ceil(P^2/4) inputs, Rp = 16 ceil(P^2/16) outputs.
 void table_dims(int P, int* Kp, int* Rp);
-// Rows of an M2L staging slot: Sm rows in whole 16-row tiles (whole 128-byte
-// lines) and St rows of a partly filled last tile (P^2 mod 16, rounded up to
-// even), kept in a separate dense tail array; St = 0 when 16 divides P^2.
+
+// M2L in the xz-plane frame.  A translation by t with azimuth phi equals
+// D^-1 T(t') D, where t' is t turned about the z axis into the xz-plane
+// (t'_y = 0) and D = diag(e^{i m phi}) acts on the (n, m) coefficients.  An
+// operator with t'_y = 0 commutes with the exchange m <-> -m, so in the
+// basis u = M^m + M^-m, v = M^m - M^-m it splits into a block C on the
+// entries with m >= 0 and a block S on the entries with m > 0 (the
+// translations of eqs. (12)-(14) under the symmetry of the plane y = 0).
+// Entry lists, in this order:
+//   S-list: (n, m) for n = 1..P-1, m = 1..n          (S = P(P-1)/2 entries)
+//   C-list: the S-list, then (n, 0) for n = 0..P-1   (C = S + P entries)
+// for inputs (k) and outputs (rows) alike.  The table of an M2L operator is
+// [Kx][Rx]: row r < 16 RTC is C-list output r, row 16 RTC + r is S-list
+// output r; input k < 4 KSS feeds both blocks (u for C, v for S), inputs
+// 4 KSS <= k < Kx only C (zero padded elsewhere).
+struct XzDims {
+  int S, C, KSS, KSC, Kx, RTS, RTC, RT, Rx;
+};
+__host__ __device__ constexpr XzDims xz_dims(int P) {
+  const int S = P * (P - 1) / 2, C = S + P;
+  const int KSS = (S + 3) / 4, KSC = (C + 3) / 4, RTS = (S + 15) / 16, RTC = (C + 15) / 16;
+  return XzDims{S, C, KSS, KSC, 4 * KSC, RTS, RTC, RTC + RTS, 16 * (RTC + RTS)};
+}
+// Entries per operator in the FP32 tables: the dense Kp x Rp operator
+// (M2M, L2L), or the [Kx][Rx] blocks of an M2L operator followed by its P
+// azimuth phases e^{i m phi} (m < P), whichever is larger (16-entry aligned).
+__host__ __device__ constexpr int xz_table_stride(int P) {
+  const XzDims d = xz_dims(P);
+  const int dense = (4 * ((P * P + 3) / 4)) * (16 * ((P * P + 15) / 16)), xz = d.Kx * d.Rx + 16;
+  return dense > xz ? dense : xz;
+}
+// (n, m) of entry e of the C-list (m >= 0; the S-list is its first S entries)
+__host__ __device__ constexpr void xz_entry(int P, int e, int* n, int* m) {
+  const int S = P * (P - 1) / 2;
+  if (e >= S) {
+    *n = e - S;
+    *m = 0;
+    return;
+  }
+  int nn = 1, base = 0;
+  while (base + nn <= e) {
+    base += nn;
+    ++nn;
+  }
+  *n = nn;
+  *m = e - base + 1;
+}
+// Output tiles of one pair, in the order the kernel writes them: for r <
+// RTS the "plus" tile r (C-list rows 16r.., giving L^{+m'} and, past the
+// S-list, L^{n'0}) and the "minus" tile r (S-list rows 16r.., giving
+// L^{-m'}), then the C-only tiles r = RTS..RTC-1 (rows of L^{n'0}).  Tile
+// i has xz_tile_rows(P, i) valid rows.  A staging slot holds the tiles with
+// 16 valid rows as whole 16-row blocks (Sm rows, whole 128-byte lines) and
+// the others, each padded to an even row count, in a dense tail (St rows).
+__host__ __device__ constexpr int xz_ntiles(int P) {
+  const XzDims d = xz_dims(P);
+  return 2 * d.RTS + (d.RTC - d.RTS);
+}
+__host__ __device__ constexpr int xz_tile_rows(int P, int i) {
+  const XzDims d = xz_dims(P);
+  if (i < 2 * d.RTS) {
+    const int r = i / 2, lim = (i & 1) ? d.S : d.C;
+    return lim - 16 * r < 16 ? lim - 16 * r : 16;
+  }
+  const int r = d.RTS + (i - 2 * d.RTS);
+  return d.C - 16 * r < 16 ? d.C - 16 * r : 16;
+}
+// first staging row of tile i: full tiles in [0, Sm), the others at Sm + ...
+__host__ __device__ constexpr int xz_tile_dest(int P, int i) {
+  int full = 0, tail = 0;
+  for (int j = 0; j < i; ++j) {
+    const int v = xz_tile_rows(P, j);
+    if (v == 16)
+      ++full;
+    else
+      tail += 2 * ((v + 1) / 2);
+  }
+  if (xz_tile_rows(P, i) == 16) return 16 * full;
+  int nfull = 0;
+  for (int j = 0; j < xz_ntiles(P); ++j) nfull += xz_tile_rows(P, j) == 16;
+  return 16 * nfull + tail;
+}
+__host__ __device__ constexpr int xz_stage_sm(int P) {
+  int full = 0;
+  for (int i = 0; i < xz_ntiles(P); ++i) full += xz_tile_rows(P, i) == 16;
+  return 16 * full;
+}
+__host__ __device__ constexpr int xz_stage_st(int P) {
+  int tail = 0;
+  for (int i = 0; i < xz_ntiles(P); ++i) {
+    const int v = xz_tile_rows(P, i);
+    if (v != 16) tail += 2 * ((v + 1) / 2);
+  }
+  return tail;
+}
+// Rows of an M2L staging slot: Sm in whole 16-row tiles, St in the tail
+// (see xz_tile_dest); Sm + St >= P^2.
 void stage_dims(int P, int* Sm, int* St);
-// k + i ki: complex wavenumber (ki = 0: real)
+// k + i ki: complex wavenumber (ki = 0: real).  FP32 tables, xz_table_stride
+// entries per operator; the M2L operators (t the canonical offset) are
+// stored in the xz-plane form with their azimuth phases.
 void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, double ki, const int32_t* cp_off,
                        const int32_t* cp_lm, const double2* cp_val, float2* tables,
                        hipStream_t s);
-// The same tables in FP64 (precision reference).
+// The dense tables in FP64 (precision reference), Kp * Rp entries per operator.
 void launch_gen_tables64(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
                          const int32_t* cp_lm, const double2* cp_val, double2* tables, hipStream_t s);
 // Pointers of one problem instance, read by every instance-aware kernel.
@@ -49,7 +145,7 @@ struct InstDev {
   const float2* tables;     // [op][Kp][Rp]
   float2* M;                // multipoles [ncell][P^2]
   float2* L;                // locals [ncell][P^2]
-  const int4* m2l_pairs;    // (target, source, symmetry, staging slot)
+  const int4* m2l_pairs;    // (target, source, reflection, staging slot)
   float2* stage;            // M2L staging [slots][Sm] (canonical frame), slots ordered by target
   float2* stage_tail;       // the last St rows of each slot [slots][St] (see stage_dims)
   const uint8_t* slot_g;    // per staging slot: reflection of its pair
@@ -86,7 +182,7 @@ void launch_p2p(const int2* items, int n, const InstDev* insts, bool damped, hip
 int m2l_pairs_per_chunk(int P);
 // chunks: (instance, op, pair begin, pair end), sorted by (instance, op)
 // L[t] = sum of the staging slots of t, each mapped back by its reflection's
-// output codes omap [16][P^2] (items: instance, target cell)
+// output codes omap [16][P^2] (m2l_xz_codes; items: instance, target cell)
 // slot_base: first staging slot of the segment (the staging buffer holds
 // slots [slot_base, ...) of the targets in items)
 void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int32_t* omap, int P,
@@ -94,7 +190,8 @@ void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int
 // per pair: reflected multipoles through the canonical operator into the pair's staging slot
 // variant < m2l_variant_count(P) selects the launch shape (results are identical)
 int m2l_variant_count(int P);
-// bmap: [17][Kp] input codes of the reflections (m2l_input_codes)
+// bmap: [17][Kx][2] input codes of the reflections, then the m' of the
+// S-list rows (m2l_xz_codes)
 void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, const int32_t* bmap, int P, int variant,
                 hipStream_t s);
 

@@ -153,14 +153,18 @@ __device__ void hankel_all_c(int nm, zd z, zd* h) {
 //   T[o][c][r] = sum_l coef * H_l^{m-m'}(t) * scale(n, n'),
 // with H = S (M2L) or R (M2M, L2L) and coef = 4 pi i^{n'+l-n} Gaunt.
 // One block per operator; the harmonics of t are built in LDS in FP64.
+// XZ: the M2L operators (t in the xz-plane) are stored as the C and S
+// blocks of XzDims: C[k][r] = (T[r][(n,m)] + T[r][(n,-m)]) / 2 for m > 0,
+// T[r][(n,0)] for m = 0, and S[k][r] = (T[r][(n,m)] - T[r][(n,-m)]) / 2, with
+// k = (n, m) and r = (n', m') the C- or S-list entries.
 // ---------------------------------------------------------------------------
 __device__ inline void store_entry(float2* p, double re, double im) { *p = make_float2((float)re, (float)im); }
 __device__ inline void store_entry(double2* p, double re, double im) { *p = make_double2(re, im); }
 
-template <class C2>
+template <class C2, bool XZ>
 __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P, double k, double ki,
                              const int32_t* __restrict__ cp_off, const int32_t* __restrict__ cp_lm,
-                             const double2* __restrict__ cp_val, int Kp, int Rp,
+                             const double2* __restrict__ cp_val, int Kp, int Rp, int stride,
                              C2* __restrict__ tables) {
   const int o = blockIdx.x;
   if (o >= nops) return;
@@ -168,7 +172,10 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
   __shared__ double2 harm[(2 * kMaxP - 1) * (2 * kMaxP - 1)];
   __shared__ double sig_in[kMaxP], sig_out[kMaxP];
   const OpDescDev d = ops[o];
-  const double tx = d.t[0], ty = d.t[1], tz = d.t[2];
+  // an M2L operator in the xz-plane form is built at t turned into the plane
+  const bool xzop = XZ && d.kind == 2;
+  const double tx = xzop ? sqrt(d.t[0] * d.t[0] + d.t[1] * d.t[1]) : d.t[0], ty = xzop ? 0.0 : d.t[1],
+               tz = d.t[2];
   const double r = sqrt(tx * tx + ty * ty + tz * tz);
   if (threadIdx.x == 0) {
     // radial functions
@@ -238,16 +245,13 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
   }
   __syncthreads();
   const int P2 = P * P;
-  C2* T = tables + (size_t)o * Kp * Rp;
-  for (int f = threadIdx.x; f < Kp * Rp; f += blockDim.x) {
-    const int col = f / Rp, row = f % Rp;  // col (n,m) = input, row (n',m') = output
-    if (col >= P2 || row >= P2) {
-      store_entry(T + f, 0.0, 0.0);
-      continue;
-    }
+  C2* T = tables + (size_t)o * stride;
+  // dense entry (row (n',m'), col (n,m)), scaled
+  auto dense = [&](int row, int col, double& re, double& im) {
     const int e = row * P2 + col;
-    int n2 = (int)sqrt((double)row), n = (int)sqrt((double)col);
-    double re = 0.0, im = 0.0;
+    const int n2 = (int)sqrt((double)row), n = (int)sqrt((double)col);
+    re = 0.0;
+    im = 0.0;
     for (int q = cp_off[e]; q < cp_off[e + 1]; ++q) {
       double2 cv = cp_val[q];
       double2 h = harm[cp_lm[q]];
@@ -258,7 +262,50 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
     if (d.kind == 0) sc = sig_in[n] / sig_out[n2];        // M2M
     else if (d.kind == 1) sc = sig_out[n2] / sig_in[n];   // L2L
     else sc = sig_out[n2] * sig_in[n];                    // M2L
-    store_entry(T + f, re * sc, im * sc);
+    re *= sc;
+    im *= sc;
+  };
+  if (xzop) {
+    const XzDims xd = xz_dims(P);
+    // azimuth phases e^{i m phi} of t, m < P
+    const double phi = atan2(d.t[1], d.t[0]);
+    for (int m = threadIdx.x; m < P; m += blockDim.x) store_entry(T + xd.Kx * xd.Rx + m, cos(m * phi), sin(m * phi));
+    for (int f = threadIdx.x; f < xd.Kx * xd.Rx; f += blockDim.x) {
+      const int kk = f / xd.Rx, r = f % xd.Rx;
+      const bool sb = r >= 16 * xd.RTC;
+      const int rr = sb ? r - 16 * xd.RTC : r, lim = sb ? xd.S : xd.C;
+      if (kk >= lim || rr >= lim) {
+        store_entry(T + f, 0.0, 0.0);
+        continue;
+      }
+      int n, m, n2, m2;
+      xz_entry(P, kk, &n, &m);
+      xz_entry(P, rr, &n2, &m2);
+      const int row = n2 * n2 + n2 + m2;
+      double ar, ai;
+      dense(row, n * n + n + m, ar, ai);
+      if (m == 0) {
+        store_entry(T + f, ar, ai);
+        continue;
+      }
+      double br, bi;
+      dense(row, n * n + n - m, br, bi);
+      if (sb)
+        store_entry(T + f, 0.5 * (ar - br), 0.5 * (ai - bi));
+      else
+        store_entry(T + f, 0.5 * (ar + br), 0.5 * (ai + bi));
+    }
+    return;
+  }
+  for (int f = threadIdx.x; f < Kp * Rp; f += blockDim.x) {
+    const int col = f / Rp, row = f % Rp;  // col (n,m) = input, row (n',m') = output
+    if (col >= P2 || row >= P2) {
+      store_entry(T + f, 0.0, 0.0);
+      continue;
+    }
+    double re, im;
+    dense(row, col, re, im);
+    store_entry(T + f, re, im);
   }
 }
 
@@ -549,14 +596,15 @@ __global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items, cons
 
 // ---------------------------------------------------------------------------
 // M2L on the matrix cores.  One wave takes up to 16*NCT pairs that share one
-// canonical operator T (P^2 x P^2 complex).  The B matrix (k = input
-// coefficient, column = pair) holds M' = D^T M, gathered straight from the
-// multipoles through the pair's reflection codes; T streams from memory as
-// the A matrix (row = output coefficient), with A and B prefetched one
-// k-step ahead.  Each pair's result goes, in the canonical frame, to the
-// pair's staging slot (the reduction maps it back); the only LDS is the
-// reflection code table and a 4 KiB output tile.  Tables are [op][k < Kp]
-// [r < Rp] with zero padding.  Blocks are mapped so that each XCD walks a
+// canonical operator: a translation in the xz-plane, held as its C and S
+// blocks (XzDims; together about half the P^2 x P^2 complex entries of the
+// full operator).  The B matrix (k = input entry, column = pair) is gathered
+// straight from the multipoles through the pair's reflection codes and
+// turned by the pair's azimuth phase; the table streams from memory as the
+// A matrix (row = output entry), with A and B prefetched ahead.  Each pair's
+// result goes, in the reflected frame, to the pair's staging slot (the
+// reduction maps it back); the only LDS is the code table and two 2 KiB
+// output tiles per 16 columns.  Blocks are mapped so that each XCD walks a
 // contiguous range of chunks (sorted by operator), keeping an operator's
 // table in that XCD's L2 while its chunks run.
 //
@@ -610,17 +658,26 @@ __device__ inline float2 mul_ipow_sel(float2 a, int code) {
 // uses three real MFMAs per tile and k-step (Gauss):
 //   K1 += (Tr + Ti) Br,  K2 += Tr (Bi - Br),  K3 += Ti (Br + Bi),
 //   C = (K1 - K3) + i (K1 + K2).
+// The RTC C-block tiles take B = u, the RTS S-block tiles B = v, where for
+// input (n, m) of the C-list and the operator's azimuth phase p = e^{i m phi}:
+//   u = p B[(n,m)] + conj(p) B[(n,-m)],  v = p B[(n,m)] - conj(p) B[(n,-m)]
+// with B the reflected multipoles (B[(n,-m)] = 0 for m = 0).  The first KSS
+// k-steps feed both blocks, the last KSC - KSS only C.  Outputs: for S-list
+// row (n', m'), L^{m'} = conj(p') (A + B) and L^{-m'} = p' (A - B) with
+// p' = e^{i m' phi}, A the C-block and B the S-block result; the m' = 0 rows
+// are A.
 // WPE is the number of waves per SIMD the register budget is sized for.
 template <int P, int NCT, int WPE, int CPW, int AD>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
-           const InstDev* __restrict__ insts, const int32_t* __restrict__ bmap, int Rp) {
-  constexpr int P2 = P * P, RT = (P2 + 15) / 16, KS = (P2 + 3) / 4, Kp = 4 * KS;
-  // staging rows per slot: SM_M in whole 16-row tiles, and SM_T tail rows of
-  // a partly filled last tile (P^2 - 16 (RT - 1), rounded up to even)
-  constexpr int SM_REM = P2 - 16 * (RT - 1), SM_T = SM_REM == 16 ? 0 : 2 * ((SM_REM + 1) / 2);
-  constexpr int SM_M = SM_T ? 16 * (RT - 1) : 16 * RT;
-  extern __shared__ int smap[];     // [17][Kp] input codes (see m2l_input_codes)
+           const InstDev* __restrict__ insts, const int32_t* __restrict__ bmap) {
+  constexpr XzDims X = xz_dims(P);
+  constexpr int P2 = P * P, RT = X.RT, RTC = X.RTC, RTS = X.RTS, KSS = X.KSS, KSC = X.KSC, Kx = X.Kx,
+                Rx = X.Rx;
+  constexpr int TSTRIDE = xz_table_stride(P);  // table entries per operator
+  constexpr int SM = xz_stage_sm(P), ST = xz_stage_st(P);
+  constexpr int NCODE = 17 * Kx;
+  extern __shared__ int smap[];     // [17][Kx] input codes (m2l_xz_codes), then [16 RTS] m' of the S-list rows
   const int b = blockIdx.x;
   const int w = (b & 7) * per_xcd + (b >> 3);
   if (w * CPW >= nitems) return;
@@ -630,7 +687,7 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
      // are clamped, so a lane past the end copies the last entry again)
     const int4* src = reinterpret_cast<const int4*>(bmap);
     int4* dst = reinterpret_cast<int4*>(smap);
-    const int n4 = 17 * Kp / 4;
+    constexpr int n4 = (NCODE + 16 * RTS) / 4;
     constexpr int U = 8;
     for (int base = 0; base < n4; base += 64 * U) {
       int4 v[U];
@@ -641,6 +698,7 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
     }
   }
   __syncthreads();
+  const int* mrow = smap + NCODE;
   // the wave runs CPW consecutive items (one operator's table stays hot in
   // L2 and one item's result stores drain while the next item computes)
 #pragma unroll
@@ -654,16 +712,15 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
     const int np = min(ch.w - pb, 16 * NCT);
     if (np <= 0) continue;
     // column t of this lane is pair 16 t + li: (target, source, reflection,
-    // slot); a column past the item's end reads the all-zero code row 16
-    // the multipoles of column t: a 64-bit address per column, or (the
+    // slot); a column past the item's end reads the all-zero code row 16.
+    // The multipoles of column t: a 64-bit address per column, or (the
     // one-chunk shapes, whose register budget is tightest) a 32-bit byte
-    // offset msb[t] beside the wave-uniform base Mb, one register per column
-    // (M of an instance is < 4 GiB); the shapes that run several chunks per
-    // wave keep the 64-bit form, with which they allocate without spills
+    // offset msb[t] beside the wave-uniform base Mb (M of an instance is
+    // < 4 GiB)
     const char* Mb = reinterpret_cast<const char*>(I.M);
     uint32_t msb[NCT];
     gcfloat2* Ms[NCT];
-    int gs[NCT], goff[NCT];
+    int goff[NCT];
 #pragma unroll
     for (int t = 0; t < NCT; ++t) {
       const int p = 16 * t + li;
@@ -673,34 +730,59 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
         msb[t] = (uint32_t)pr.y * (uint32_t)(P2 * sizeof(float2));
       else
         Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
-      gs[t] = ok ? pr.z : 16;
-      goff[t] = gs[t] * Kp + lk;
+      goff[t] = (ok ? pr.z : 16) * Kx + lk;
     }
-    // B gather: B[k] = i^ph M[c] from the column's code; the loads issue now,
-    // phase and zeroing apply when the step runs
-    auto load_b = [&](int k4, float2* raw, int* code) {
+    // the operator's table ([Kx][Rx], then its phases e^{i m phi}, m < P): a
+    // 64-bit address per lane, or (one-chunk shapes) the wave-uniform base
+    // Tb and this lane's 32-bit byte offset (a table is < 4 GiB)
+    const char* Tb = reinterpret_cast<const char*>(I.tables + (size_t)op * TSTRIDE);
+    auto lds_sync = [&]() {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // the operator's phases, copied to LDS (read per k-step and per output row)
+    __shared__ float2 sph[kMaxP];
+    if (lane < P) sph[lane] = ld2((gcfloat2*)(I.tables + (size_t)op * TSTRIDE + Kx * Rx) + lane);
+    lds_sync();
+    // B gather: the two reflected multipoles of each column's input and the
+    // input's phase (the same for every column: m depends on k only); the
+    // loads issue now, codes and phases apply when the step runs
+    auto load_b = [&](int k4, float2* rx, float2* ry, float2& rp) {
 #pragma unroll
       for (int t = 0; t < NCT; ++t) {
         const int e = smap[goff[t] + k4];
-        if constexpr (CPW == 1)
-          raw[t] = ld2((gcfloat2*)(Mb + (msb[t] + (uint32_t)(e & 0xffff) * (uint32_t)sizeof(float2))));
-        else
-          raw[t] = ld2(Ms[t] + (e & 0xffff));
-        code[t] = e;
+        if constexpr (CPW == 1) {
+          rx[t] = ld2((gcfloat2*)(Mb + (msb[t] + (uint32_t)(e & 0xff) * (uint32_t)sizeof(float2))));
+          ry[t] = ld2((gcfloat2*)(Mb + (msb[t] + (uint32_t)((e >> 18) & 0xff) * (uint32_t)sizeof(float2))));
+        } else {
+          rx[t] = ld2(Ms[t] + (e & 0xff));
+          ry[t] = ld2(Ms[t] + ((e >> 18) & 0xff));
+        }
       }
+      rp = sph[(smap[goff[0] + k4] >> 8) & 15];
     };
-    // the three B operands of the Gauss product
-    float bu[NCT], bd[NCT], bs[NCT];
-    auto finish_b = [&](const float2* raw, const int* code) {
+    // the Gauss operands of u (C block) and v (S block)
+    float uu[NCT], ud[NCT], us[NCT], vu[NCT], vd[NCT], vs[NCT];
+    auto finish_b = [&](int k4, const float2* rx, const float2* ry, float2 rp) {
 #pragma unroll
       for (int t = 0; t < NCT; ++t) {
-        const int e = code[t];
-        const bool zero = e & (1 << 17);
-        const float2 v = apply_code(raw[t].x, raw[t].y, e);
-        const float x = zero ? 0.f : v.x, y = zero ? 0.f : v.y;
-        bu[t] = x;
-        bd[t] = y - x;
-        bs[t] = x + y;
+        const int e = smap[goff[t] + k4], ey = e << 4;  // the second code sits 4 bits lower
+        const float2 x0 = apply_code(rx[t].x, rx[t].y, e);
+        const float2 y0 = apply_code(ry[t].x, ry[t].y, ey);
+        const bool zx = e & (1 << 17), zy = ey & (1 << 17);
+        const float xr = zx ? 0.f : x0.x, xi = zx ? 0.f : x0.y;
+        const float yr = zy ? 0.f : y0.x, yi = zy ? 0.f : y0.y;
+        const float sr = xr + yr, si = xi + yi, dr = xr - yr, di = xi - yi;
+        const float pr = rp.x, pi = rp.y;
+        const float ur = fmaf(pr, sr, -pi * di), ui = fmaf(pr, si, pi * dr);
+        const float wr = fmaf(pr, dr, -pi * si), wi = fmaf(pr, di, pi * sr);
+        uu[t] = ur;
+        ud[t] = ui - ur;
+        us[t] = ur + ui;
+        vu[t] = wr;
+        vd[t] = wi - wr;
+        vs[t] = wr + wi;
       }
     };
     floatx4 k1[NCT][RT], k2[NCT][RT], k3[NCT][RT];
@@ -712,109 +794,94 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
         k2[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
         k3[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
-    // the operator's table: a 64-bit address per lane, or (one-chunk shapes)
-    // the wave-uniform base Tb and this lane's 32-bit byte offset (a table
-    // is < 4 GiB)
-    const char* Tb = reinterpret_cast<const char*>(I.tables + (size_t)op * Kp * Rp);
     const uint32_t tlane = (uint32_t)li * (uint32_t)sizeof(float2);
-    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li;
+    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * TSTRIDE) + li;
     // the table operand (A) is loaded AD k-steps ahead (2 AD register
-    // buffers), the gathered multipoles (B) one step ahead; a straight-line
-    // loop body of four steps keeps the compiler's wait counts exact
+    // buffers), the gathered multipoles (B) one step ahead into one buffer
+    // that each step first turns into its operands; a straight-line loop
+    // body of four steps keeps the compiler's wait counts exact
     constexpr int AM = 2 * AD - 1;
-    float2 av[2 * AD][RT], bv[2][NCT];
-    int cv[2][NCT];
+    float2 av[2 * AD][RT], bx[NCT], by[NCT], bp;
     auto load_a = [&](int k, float2* out) {
       if constexpr (CPW == 1) {
-        const uint32_t off = tlane + (uint32_t)(k * Rp) * (uint32_t)sizeof(float2);
+        const uint32_t off = tlane + (uint32_t)(k * Rx) * (uint32_t)sizeof(float2);
 #pragma unroll
         for (int r = 0; r < RT; ++r) out[r] = ld2((gcfloat2*)(Tb + (off + (uint32_t)(16 * r * sizeof(float2)))));
       } else {
 #pragma unroll
-        for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rp + 16 * r);
+        for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rx + 16 * r);
       }
     };
-    auto mma = [&](const float2* a) {
+    auto mma = [&](const float2* a, bool joint) {
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
+        if (r >= RTC && !joint) break;
         const float ar = a[r].x, ai = a[r].y, as = ar + ai;
+        const bool sb = r >= RTC;
 #pragma unroll
-        for (int t = 0; t < NCT; ++t) k1[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bu[t], k1[t][r], 0, 0, 0);
+        for (int t = 0; t < NCT; ++t)
+          k1[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, sb ? vu[t] : uu[t], k1[t][r], 0, 0, 0);
 #pragma unroll
-        for (int t = 0; t < NCT; ++t) k2[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bd[t], k2[t][r], 0, 0, 0);
+        for (int t = 0; t < NCT; ++t)
+          k2[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, sb ? vd[t] : ud[t], k2[t][r], 0, 0, 0);
 #pragma unroll
-        for (int t = 0; t < NCT; ++t) k3[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bs[t], k3[t][r], 0, 0, 0);
+        for (int t = 0; t < NCT; ++t)
+          k3[t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, sb ? vs[t] : us[t], k3[t][r], 0, 0, 0);
       }
     };
-    // step s: issue A(s + AD) and B(s + 1), then the MFMAs of step s; the
-    // loop runs whole groups of four steps and clamps k (redundant in-bounds
-    // loads past the end are unused), the last KS mod 4 steps follow
-    constexpr int klast = Kp - 4;
+    // step s: issue A(s + AD), form step s's B operands, issue B(s + 1),
+    // then the MFMAs of step s; the
+    // loop runs whole groups of four joint steps and clamps k (redundant
+    // in-bounds loads past the end are unused), the remaining steps follow
+    // unrolled (joint while s < KSS, then C only)
+    constexpr int klast = Kx - 4, KS4 = (KSS / 4) * 4;
 #pragma unroll
     for (int d = 0; d < AD; ++d)
-      if (d < KS) load_a(4 * d + lk, av[d]);
-    load_b(0, bv[0], cv[0]);
-    int ks = 0;
-    for (; ks + 4 <= KS; ks += 4) {
+      if (d < KSC) load_a(4 * d + lk, av[d]);
+    load_b(0, bx, by, bp);
+    for (int ks = 0; ks < KS4; ks += 4) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         load_a(min(4 * (ks + j + AD), klast) + lk, av[(j + AD) & AM]);
-        load_b(min(4 * (ks + j + 1), klast), bv[(j + 1) & 1], cv[(j + 1) & 1]);
+        finish_b(4 * (ks + j), bx, by, bp);
+        __builtin_amdgcn_sched_barrier(0);  // the raw B registers are free again
+        load_b(min(4 * (ks + j + 1), klast), bx, by, bp);
         __builtin_amdgcn_sched_barrier(0);  // loads issue before this step's MFMAs
-        finish_b(bv[j & 1], cv[j & 1]);
         // the wave issuing its MFMAs goes first when both waves of the SIMD
         // are ready, so its matrix-core block is not split by the other
         // wave's loads and epilogue
         __builtin_amdgcn_s_setprio(1);
-        mma(av[j & AM]);
+        mma(av[j & AM], true);
         __builtin_amdgcn_s_setprio(0);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
 #pragma unroll
-    for (int j = 0; j < KS % 4; ++j) {
-      const int st = (KS / 4) * 4 + j;
-      if (st + AD < KS) load_a(4 * (st + AD) + lk, av[(j + AD) & AM]);
-      if (st + 1 < KS) load_b(4 * (st + 1), bv[(j + 1) & 1], cv[(j + 1) & 1]);
+    for (int st = KS4; st < KSC; ++st) {
+      if (st + AD < KSC) load_a(4 * (st + AD) + lk, av[(st + AD) & AM]);
+      finish_b(4 * st, bx, by, bp);
       __builtin_amdgcn_sched_barrier(0);
-      finish_b(bv[j & 1], cv[j & 1]);
+      if (st + 1 < KSC) load_b(4 * (st + 1), bx, by, bp);
+      __builtin_amdgcn_sched_barrier(0);
       __builtin_amdgcn_s_setprio(1);
-      mma(av[j & AM]);
+      mma(av[st & AM], st < KSS);
       __builtin_amdgcn_s_setprio(0);
       __builtin_amdgcn_sched_barrier(0);
     }
     // each pair owns a staging slot (slots are ordered by target) holding its
-    // result in the canonical frame: the SM_M rows of the full 16-row tiles
-    // (whole 128-byte lines) in the main array, the SM_T rows of a partly
-    // filled last tile in the dense tail array; the reduction kernel below
-    // maps it back and adds a target's slots in a fixed order.  Lane (j, q) holds rows 4q..4q+3 of every
-    // 16-row tile of column j; tile by tile the results pass through 4 KiB of
+    // result in the reflected frame, tile by tile (xz_tile_dest: tiles with
+    // 16 valid rows as whole 128-byte lines in the main array, the others in
+    // the dense tail array); the reduction kernel below maps it back and adds
+    // a target's slots in a fixed order.  Lane (j, q) holds rows 4q..4q+3 of
+    // every 16-row tile of column j; the plus and minus tiles pass through
     // LDS ([column][16 rows]) so that every store instruction writes whole
     // 128-byte lines (8 lanes x 16 bytes per column).
-    __shared__ f4v sout[16 * NCT * 8];
+    __shared__ f4v sout[2][16 * NCT * 8];
     int slots[NCT];
 #pragma unroll
-    for (int t = 0; t < NCT; ++t) slots[t] = (gs[t] == 16) ? -1 : ld_int4(I.m2l_pairs + pb + 16 * t + li).w;
-#pragma unroll
-    for (int r = 0; r < RT; ++r) {
-#pragma unroll
-      for (int t = 0; t < NCT; ++t) {
-        f4v lo, hi;
-        lo.x = k1[t][r][0] - k3[t][r][0];
-        lo.y = k1[t][r][0] + k2[t][r][0];
-        lo.z = k1[t][r][1] - k3[t][r][1];
-        lo.w = k1[t][r][1] + k2[t][r][1];
-        hi.x = k1[t][r][2] - k3[t][r][2];
-        hi.y = k1[t][r][2] + k2[t][r][2];
-        hi.z = k1[t][r][3] - k3[t][r][3];
-        hi.w = k1[t][r][3] + k2[t][r][3];
-        const int col = 16 * t + li;
-        sout[col * 8 + 2 * lk] = lo;      // rows 4 lk, 4 lk + 1 of the tile
-        sout[col * 8 + 2 * lk + 1] = hi;  // rows 4 lk + 2, 4 lk + 3
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int t = 0; t < NCT; ++t) slots[t] = (16 * t + li < np) ? ld_int4(I.m2l_pairs + pb + 16 * t + li).w : -1;
+    auto store_tile = [&](int tile, int half) {
+      const int vr = xz_tile_rows(P, tile), dst = xz_tile_dest(P, tile);
 #pragma unroll
       for (int u = 0; u < 2 * NCT; ++u) {  // 16 NCT columns x 8 pieces over 64 lanes
         const int e = 64 * u + lane, col = e >> 3, piece = e & 7;
@@ -824,23 +891,58 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
           const int sv = __shfl(slots[t], col & 15);
           if ((col >> 4) == t) slot = sv;
         }
-        if constexpr (SM_T > 0) {
-          if (r == RT - 1) {  // the partly filled last tile: its SM_T rows go to the tail
-            if (slot >= 0 && piece < SM_T / 2) {
-              gfloat4* St = (gfloat4*)(I.stage_tail + (size_t)slot * SM_T);
-              __builtin_nontemporal_store(sout[col * 8 + piece], &St[piece]);
-            }
-            continue;
-          }
-        }
-        if (slot >= 0) {
-          gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * SM_M + 16 * r);
-          __builtin_nontemporal_store(sout[col * 8 + piece], &St[piece]);  // written once, read once
+        if (slot < 0) continue;
+        if (vr == 16) {
+          gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * SM + dst);
+          __builtin_nontemporal_store(sout[half][col * 8 + piece], &St[piece]);  // written once, read once
+        } else if (piece < (vr + 1) / 2) {
+          gfloat4* St = (gfloat4*)(I.stage_tail + (size_t)slot * ST + (dst - SM));
+          __builtin_nontemporal_store(sout[half][col * 8 + piece], &St[piece]);
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+#pragma unroll
+    for (int r = 0; r < RTC; ++r) {
+      const bool pm = r < RTS;  // plus and minus tiles, else a C-only tile
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) {
+        float o[2][8];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float Ar = k1[t][r][v] - k3[t][r][v], Ai = k1[t][r][v] + k2[t][r][v];
+          if (pm) {
+            const int rs = pm ? RTC + r : 0;
+            const float Br = k1[t][rs][v] - k3[t][rs][v], Bi = k1[t][rs][v] + k2[t][rs][v];
+            const int e = 16 * r + 4 * lk + v;
+            const bool srow = e < X.S;
+            const float2 p = srow ? sph[mrow[e]] : make_float2(1.f, 0.f);
+            const float sr = Ar + Br, si = Ai + Bi, dr = Ar - Br, di = Ai - Bi;
+            // plus: conj(p) (A + B) (A alone past the S-list); minus: p (A - B)
+            o[0][2 * v] = srow ? fmaf(p.x, sr, p.y * si) : Ar;
+            o[0][2 * v + 1] = srow ? fmaf(p.x, si, -p.y * sr) : Ai;
+            o[1][2 * v] = fmaf(p.x, dr, -p.y * di);
+            o[1][2 * v + 1] = fmaf(p.x, di, p.y * dr);
+          } else {
+            o[0][2 * v] = Ar;
+            o[0][2 * v + 1] = Ai;
+          }
+        }
+        const int col = 16 * t + li;
+        sout[0][col * 8 + 2 * lk] = f4v{o[0][0], o[0][1], o[0][2], o[0][3]};      // rows 4 lk, 4 lk + 1
+        sout[0][col * 8 + 2 * lk + 1] = f4v{o[0][4], o[0][5], o[0][6], o[0][7]};  // rows 4 lk + 2, 4 lk + 3
+        if (pm) {
+          sout[1][col * 8 + 2 * lk] = f4v{o[1][0], o[1][1], o[1][2], o[1][3]};
+          sout[1][col * 8 + 2 * lk + 1] = f4v{o[1][4], o[1][5], o[1][6], o[1][7]};
+        }
+      }
+      lds_sync();
+      if (pm) {
+        store_tile(2 * r, 0);
+        store_tile(2 * r + 1, 1);
+      } else {
+        store_tile(2 * RTS + (r - RTS), 0);
+      }
+      lds_sync();
     }
   }
 }
@@ -863,7 +965,7 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 template <int RT, int KS, int MODE>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT >= 10 ? 1 : 2)))
 k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
-          const InstDev* __restrict__ insts, int Kp, int Rp, int P2) {
+          const InstDev* __restrict__ insts, int tstride, int Rp, int P2) {
   constexpr int STRIDE = MODE == 0 ? 9 : 2;
   constexpr int G = KS < 16 ? KS : 16;
   const int r0 = blockIdx.x % RT;
@@ -877,7 +979,7 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
   float2* X = MODE == 0 ? I.M : I.L;
   floatx4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = k1, k3 = k1;
   auto run = [&](int op, int src) {  // acc += T_op X[src] (src < 0: zero column)
-    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * Kp * Rp) + li + 16 * r0;
+    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * tstride) + li + 16 * r0;
     const bool zc = !ok || src < 0;
     gcfloat2* B = (gcfloat2*)(X + (size_t)(zc ? 0 : src) * P2);
     for (int g0 = 0; g0 < KS; g0 += G) {
@@ -929,17 +1031,22 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
 }
 
 // L[t] = sum of t's staging slots in slot order (deterministic), each slot's
-// canonical-frame result mapped back by the output codes of its pair's
-// reflection.  Items: (instance, target cell); the cell's slots are
-// [soff[t], soff[t+1]).  One thread per output coefficient; the slots'
-// reflections are staged in LDS per group of kRedGroup slots, and eight
-// slots' loads are in flight per thread.
+// result mapped back by the output codes of its pair's reflection.  Items:
+// (instance, target cell); the cell's slots are [soff[t], soff[t+1]).  A
+// reflection sends the staging rows of (n', m') and (n', -m') onto the same
+// two coefficients (straight or exchanged), so thread j < S owns both
+// coefficients of S-list entry j and thread S + n' owns (n', 0): C threads,
+// one wave per target up to P = 10, each wave reading whole slots.  The
+// slots' reflections are staged in LDS per group of kRedGroup slots, and
+// the loads of U slots are in flight per thread.
 constexpr int kRedGroup = 512;
 
-__global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ items,
-                                                    const InstDev* __restrict__ insts,
-                                                    const int32_t* __restrict__ omap, int P2, int Sm, int St,
-                                                    int64_t slot_base) {
+template <int P>
+__global__ void __launch_bounds__(64 * ((xz_dims(P).C + 63) / 64))
+k_m2l_reduce(const int2* __restrict__ items, const InstDev* __restrict__ insts, const int32_t* __restrict__ omap,
+             int64_t slot_base) {
+  constexpr XzDims X = xz_dims(P);
+  constexpr int P2 = P * P, SM = xz_stage_sm(P), ST = xz_stage_st(P);
   extern __shared__ int red_lds[];
   int* som = red_lds;              // [16][P2] output codes
   int* sgo = red_lds + 16 * P2;    // [kRedGroup] reflection * P2 of each slot of the group
@@ -947,7 +1054,7 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ ite
   {  // all loads of the code table in flight before the LDS writes (clamped indices)
     const int4* src = reinterpret_cast<const int4*>(omap);
     int4* dst = reinterpret_cast<int4*>(som);
-    const int n4 = 4 * P2;
+    constexpr int n4 = 4 * P2;
     constexpr int U = 4;
     for (int base = 0; base < n4; base += nth * U) {
       int4 v[U];
@@ -961,44 +1068,71 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int2* __restrict__ ite
   const InstDev& I = insts[it.x];
   const int cell = it.y;
   const int s0 = I.m2l_soff[cell], s1 = I.m2l_soff[cell + 1];
-  const int c = tid;
-  float sr = 0.f, si = 0.f;
+  // this thread's coefficients: c0 = (n', m'), c1 = (n', -m') (none for m' = 0)
+  int c0 = -1, c1 = -1;
+  if (tid < X.C) {
+    int n, m;
+    xz_entry(P, tid, &n, &m);
+    c0 = n * n + n + m;
+    if (m > 0) c1 = n * n + n - m;
+  }
+  const bool two = c1 >= 0;
+  const int c1r = two ? c1 : max(c0, 0);
+  float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
   for (int g0 = s0; g0 < s1; g0 += kRedGroup) {
     const int ng = min(kRedGroup, s1 - g0);
     __syncthreads();
     for (int e = tid; e < ng; e += nth) sgo[e] = (int)I.slot_g[g0 + e] * P2;
     __syncthreads();
-    if (c < P2) {
-      // row r of a slot: main part for r < Sm, else the tail
-      gcfloat2* S = (gcfloat2*)(I.stage + (size_t)(g0 - slot_base) * Sm);
-      gcfloat2* T = (gcfloat2*)(I.stage_tail + (size_t)(g0 - slot_base) * St) - Sm;
-      auto at = [&](int u, int r) { return r < Sm ? S + (size_t)u * Sm + r : T + (size_t)u * St + r; };
+    if (c0 >= 0) {
+      // row r of a slot: main part for r < SM, else the tail
+      gcfloat2* S = (gcfloat2*)(I.stage + (size_t)(g0 - slot_base) * SM);
+      gcfloat2* T = (gcfloat2*)(I.stage_tail + (size_t)(g0 - slot_base) * ST) - SM;
+      auto at = [&](int u, int r) { return r < SM ? S + (size_t)u * SM + r : T + (size_t)u * ST + r; };
       int q = 0;
-      constexpr int U = 16;  // loads in flight per thread, added in slot order
-      for (; q + U <= ng; q += U, S += U * Sm, T += U * St) {
-        int e[U];
-        float2 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) e[u] = som[sgo[q + u] + c];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = ld2_once(at(u, e[u] & 0xffff));
+      constexpr int U = 12;  // slots in flight per thread, added in slot order
+      for (; q + U <= ng; q += U, S += U * SM, T += U * ST) {
+        int e[U], f[U];
+        float2 v[U], w[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const float2 w = apply_code(v[u].x, v[u].y, e[u]);
-          sr += w.x;
-          si += w.y;
+          e[u] = som[sgo[q + u] + c0];
+          f[u] = som[sgo[q + u] + c1r];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          v[u] = ld2_once(at(u, e[u] & 0xffff));
+          if (two) w[u] = ld2_once(at(u, f[u] & 0xffff));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const float2 x = apply_code(v[u].x, v[u].y, e[u]);
+          ar += x.x;
+          ai += x.y;
+          if (two) {
+            const float2 y = apply_code(w[u].x, w[u].y, f[u]);
+            br += y.x;
+            bi += y.y;
+          }
         }
       }
-      for (; q < ng; ++q, S += Sm, T += St) {
-        const int e = som[sgo[q] + c];
+      for (; q < ng; ++q, S += SM, T += ST) {
+        const int e = som[sgo[q] + c0], f = som[sgo[q] + c1r];
         const float2 v = ld2_once(at(0, e & 0xffff));
-        const float2 w = apply_code(v.x, v.y, e);
-        sr += w.x;
-        si += w.y;
+        const float2 x = apply_code(v.x, v.y, e);
+        ar += x.x;
+        ai += x.y;
+        if (two) {
+          const float2 w = ld2_once(at(0, f & 0xffff));
+          const float2 y = apply_code(w.x, w.y, f);
+          br += y.x;
+          bi += y.y;
+        }
       }
     }
   }
-  if (c < P2) I.L[(size_t)cell * P2 + c] = make_float2(sr, si);
+  if (c0 >= 0) I.L[(size_t)cell * P2 + c0] = make_float2(ar, ai);
+  if (two) I.L[(size_t)cell * P2 + c1] = make_float2(br, bi);
 }
 
 // ---------------------------------------------------------------------------
@@ -1249,9 +1383,8 @@ void table_dims(int P, int* Kp, int* Rp) {
   *Rp = 16 * ((P * P + 15) / 16);
 }
 void stage_dims(int P, int* Sm, int* St) {
-  const int RT = (P * P + 15) / 16, rem = P * P - 16 * (RT - 1);
-  *St = rem == 16 ? 0 : 2 * ((rem + 1) / 2);
-  *Sm = *St ? 16 * (RT - 1) : 16 * RT;
+  *Sm = xz_stage_sm(P);
+  *St = xz_stage_st(P);
 }
 void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, double ki, const int32_t* cp_off,
                        const int32_t* cp_lm, const double2* cp_val, float2* tables,
@@ -1259,14 +1392,16 @@ void launch_gen_tables(const OpDescDev* ops, int nops, int P, double k, double k
   if (nops <= 0) return;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  k_gen_tables<float2><<<nops, 256, 0, s>>>(ops, nops, P, k, ki, cp_off, cp_lm, cp_val, Kp, Rp, tables);
+  k_gen_tables<float2, true><<<nops, 256, 0, s>>>(ops, nops, P, k, ki, cp_off, cp_lm, cp_val, Kp, Rp,
+                                                   xz_table_stride(P), tables);
 }
 void launch_gen_tables64(const OpDescDev* ops, int nops, int P, double k, const int32_t* cp_off,
                          const int32_t* cp_lm, const double2* cp_val, double2* tables, hipStream_t s) {
   if (nops <= 0) return;
   int Kp, Rp;
   table_dims(P, &Kp, &Rp);
-  k_gen_tables<double2><<<nops, 256, 0, s>>>(ops, nops, P, k, 0.0, cp_off, cp_lm, cp_val, Kp, Rp, tables);
+  k_gen_tables<double2, false><<<nops, 256, 0, s>>>(ops, nops, P, k, 0.0, cp_off, cp_lm, cp_val, Kp, Rp, Kp * Rp,
+                                                    tables);
 }
 int elem_chunk() { return kChunk; }
 void launch_set_xy(int count, int base, const XYPtrs& p, InstDev* insts, hipStream_t s) {
@@ -1307,7 +1442,7 @@ static void launch_tr(const int4* items, int n, const int32_t* cols, const InstD
 #define X(p)                                                                                      \
   case p: {                                                                                       \
     constexpr int RT = (p * p + 15) / 16, KS = (p * p + 3) / 4;                                   \
-    k_tr_mfma<RT, KS, MODE><<<n * RT, 64, 0, s>>>(items, cols, insts, Kp, Rp, p * p);             \
+    k_tr_mfma<RT, KS, MODE><<<n * RT, 64, 0, s>>>(items, cols, insts, xz_table_stride(p), Rp, p * p); \
     break;                                                                                        \
   }
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
@@ -1338,13 +1473,17 @@ void launch_l2p(const int2* items, int n, const InstDev* insts, int P, bool damp
 }
 void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int32_t* omap, int P,
                        int64_t slot_base, hipStream_t s) {
-  int Kp, Rp;
-  table_dims(P, &Kp, &Rp);
-  const int nth = 64 * ((P * P + 63) / 64);  // one thread per coefficient
+  if (n <= 0) return;
   const size_t lds = (16 * (size_t)P * P + kRedGroup) * sizeof(int);
-  int Sm, St;
-  stage_dims(P, &Sm, &St);
-  if (n > 0) k_m2l_reduce<<<n, nth, lds, s>>>(items, insts, omap, P * P, Sm, St, slot_base);
+  switch (P) {
+#define X(p)                                                                                    \
+  case p:                                                                                       \
+    k_m2l_reduce<p><<<n, 64 * ((xz_dims(p).C + 63) / 64), lds, s>>>(items, insts, omap, slot_base); \
+    break;
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#undef X
+    default: break;
+  }
 }
 void launch_p2p(const int2* items, int n, const InstDev* insts, bool damped, hipStream_t s) {
   if (n <= 0) return;
@@ -1356,21 +1495,18 @@ void launch_p2p(const int2* items, int n, const InstDev* insts, bool damped, hip
 
 template <int P, int NCT, int WPE, int CPW, int AD>
 static void launch_m2l_t(const int4* chunks, int nchunks, int sub, const InstDev* insts, const int32_t* bmap,
-                         int Kp, int Rp, hipStream_t s) {
+                         hipStream_t s) {
+  constexpr XzDims X = xz_dims(P);
   const int nitems = nchunks * sub;
   const int nwaves = (nitems + CPW - 1) / CPW;
   const int per = (nwaves + 7) / 8;
-  k_m2l_mfma<P, NCT, WPE, CPW, AD><<<8 * per, 64, 17 * Kp * sizeof(int), s>>>(chunks, nitems, per, sub, insts,
-                                                                              bmap, Rp);
+  const size_t lds = (17 * (size_t)X.Kx + 16 * (size_t)X.RTS) * sizeof(int);
+  k_m2l_mfma<P, NCT, WPE, CPW, AD><<<8 * per, 64, lds, s>>>(chunks, nitems, per, sub, insts, bmap);
 }
 
 // Chunks hold 32 pairs while two 16-pair column tiles of three accumulator
-// sets fit two waves per SIMD (RT <= 7, P <= 10), else 16.
-int m2l_pairs_per_chunk(int P) {
-  int Kp, Rp;
-  table_dims(P, &Kp, &Rp);
-  return Rp / 16 <= 7 ? 32 : 16;
-}
+// sets fit two waves per SIMD (RTC + RTS <= 7, P <= 10), else 16.
+int m2l_pairs_per_chunk(int P) { return xz_dims(P).RT <= 7 ? 32 : 16; }
 
 // Launch shapes (all give the same bits).  With 32-pair chunks:
 //   0: one wave per chunk (two column tiles), tables two k-steps ahead;
@@ -1388,34 +1524,32 @@ constexpr int m2l_narrow_wpe(int RT) { return RT <= 3 ? 4 : RT <= 7 ? 3 : RT <= 
 
 template <int P>
 static void launch_m2l_p(int variant, int sub, const int4* chunks, int nchunks, const InstDev* insts,
-                         const int32_t* bmap, int Kp, int Rp, hipStream_t s) {
-  constexpr int RT = (P * P + 15) / 16, NW = m2l_narrow_wpe(RT);
+                         const int32_t* bmap, hipStream_t s) {
+  constexpr int RT = xz_dims(P).RT, NW = m2l_narrow_wpe(RT);
   if constexpr (RT <= 7) {
     if (sub == 2) {
       switch (variant) {
-        case 1: return launch_m2l_t<P, 1, NW, 1, 1>(chunks, nchunks, 2, insts, bmap, Kp, Rp, s);
-        case 2: return launch_m2l_t<P, 2, 2, 2, 1>(chunks, nchunks, 1, insts, bmap, Kp, Rp, s);
-        case 3: return launch_m2l_t<P, 2, 2, 4, 1>(chunks, nchunks, 1, insts, bmap, Kp, Rp, s);
-        default: return launch_m2l_t<P, 2, 2, 1, 2>(chunks, nchunks, 1, insts, bmap, Kp, Rp, s);
+        case 1: return launch_m2l_t<P, 1, NW, 1, 1>(chunks, nchunks, 2, insts, bmap, s);
+        case 2: return launch_m2l_t<P, 2, 2, 2, 1>(chunks, nchunks, 1, insts, bmap, s);
+        case 3: return launch_m2l_t<P, 2, 2, 4, 1>(chunks, nchunks, 1, insts, bmap, s);
+        default: return launch_m2l_t<P, 2, 2, 1, 2>(chunks, nchunks, 1, insts, bmap, s);
       }
     }
   }
   switch (variant) {
-    case 1: return launch_m2l_t<P, 1, NW, 2, 1>(chunks, nchunks, sub, insts, bmap, Kp, Rp, s);
-    case 2: return launch_m2l_t<P, 1, NW, 4, 1>(chunks, nchunks, sub, insts, bmap, Kp, Rp, s);
-    default: return launch_m2l_t<P, 1, NW, 1, 1>(chunks, nchunks, sub, insts, bmap, Kp, Rp, s);
+    case 1: return launch_m2l_t<P, 1, NW, 2, 1>(chunks, nchunks, sub, insts, bmap, s);
+    case 2: return launch_m2l_t<P, 1, NW, 4, 1>(chunks, nchunks, sub, insts, bmap, s);
+    default: return launch_m2l_t<P, 1, NW, 1, 1>(chunks, nchunks, sub, insts, bmap, s);
   }
 }
 
 void launch_m2l(const int4* chunks, int nchunks, const InstDev* insts, const int32_t* bmap, int P, int variant,
                 hipStream_t s) {
   if (nchunks <= 0) return;
-  int Kp, Rp;
-  table_dims(P, &Kp, &Rp);
   const int sub = m2l_pairs_per_chunk(P) / 16;
   switch (P) {
 #define X(p) \
-  case p: launch_m2l_p<p>(variant, sub, chunks, nchunks, insts, bmap, Kp, Rp, s); break;
+  case p: launch_m2l_p<p>(variant, sub, chunks, nchunks, insts, bmap, s); break;
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 #undef X
     default: break;

@@ -89,7 +89,7 @@ static int matvec64_impl(Tree& t, Plan& pl, const double2* x, double2* y, hipStr
   D.q = t.d_q64.as<double2>();
   D.ys = t.d_ys64.as<double2>();
   D.m2l_pairs = pl.d_m2l_pairs.as<int4>();
-  D.bmap = pl.d_bmap.as<int32_t>();
+  D.bmap = pl.d_bmap64.as<int32_t>();
   D.p2p_work = pl.d_p2p_work.as<int4>();
   D.p2p_ivals = pl.d_p2p_ivals.as<int2>();
   D.nsrc = t.h.nsrc;

@@ -84,6 +84,7 @@ const Coupling& coupling(int P);
 // reflection g is B[k] = i^ph M[idx].  out[g][c], c < P^2: output
 // coefficient c of such a pair is i^-ph C[idx].
 void m2l_reflection_codes(int P, int Kp, std::vector<int32_t>& in, std::vector<int32_t>& out);
+void m2l_xz_codes(int P, std::vector<int32_t>& in, std::vector<int32_t>& out);
 
 // ---------------------------------------------------------------------------
 // Device-side plan for one (k, P)
@@ -134,16 +135,17 @@ struct Plan {
   DevBuf d_clev;                 // int32 level
   DevBuf d_topo;                 // int4 (child begin, child end, parent, octant | level << 3)
   // operators and work lists
-  DevBuf d_ops, d_tables;        // OpDesc[n_ops]; float2 [n_ops][P^2 in][P^2 out]
+  DevBuf d_ops, d_tables;        // OpDesc[n_ops]; float2 [n_ops][xz_table_stride(P)]
   DevBuf d_rho;                  // double per level
-  DevBuf d_m2l_pairs;            // int4 (target cell, source cell, symmetry, op)
+  DevBuf d_m2l_pairs;            // int4 (target cell, source cell, reflection, staging slot)
   int32_t n_m2l_chunks = 0;
   DevBuf d_p2p_work;             // int4 (tgt begin, tgt end, interval begin, interval end)
   DevBuf d_p2p_ivals;            // int2 (src begin, src end)
   DevBuf d_p2p_total;            // int32 sources per work item
   int32_t n_p2p_work = 0;
-  DevBuf d_bmap;                 // int32 [17][Kp]: M2L input codes
-  DevBuf d_omap;                 // int32 [16][P^2]: M2L output codes
+  DevBuf d_bmap;                 // int32 [17][Kx] + [16 RTS]: M2L input codes (m2l_xz_codes)
+  DevBuf d_omap;                 // int32 [16][P^2]: M2L output codes (m2l_xz_codes)
+  DevBuf d_bmap64;               // int32 [17][Kp]: dense input codes (FP64 variant)
   DevBuf d_slot_g;               // uint8 per staging slot: the pair's reflection
   DevBuf d_M, d_L;               // float2 [ncell][P^2]
   DevBuf d_cops;                 // int2 per cell: (M2M op as child, L2L op as child)

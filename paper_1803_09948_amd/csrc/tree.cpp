@@ -444,4 +444,63 @@ void m2l_reflection_codes(int P, int Kp, std::vector<int32_t>& in, std::vector<i
       }
 }
 
+
+// Codes of the xz-plane M2L (XzDims).  in: [17][Kx], for reflection g and
+// C-list input k = (n, m), one word holding the codes of the two reflected
+// multipoles B[(n, m)] (x) and B[(n, -m)] (y) and m:
+//   bits 0..7 x index, 16 x swap, 17 x zero, 30 x neg_im, 31 x neg_re,
+//   bits 8..11 m, 12 y swap, 13 y zero, 18..25 y index, 26 y neg_im,
+//   27 y neg_re
+// (so that the word shifted left by 4 carries y's flags where x's are); y is
+// marked zero when m = 0, both when k >= C.  Row 16 (columns past a chunk's
+// end) has both marked zero.  Then 16 RTS entries: m' of S-list output row
+// r (0 past the list).  out: [16][P^2], for target coefficient c = (n, m)
+// under reflection g: the staging row of the canonical (n, m') it comes
+// from (xz_tile_dest) and the phase i^-ph, in the code format above.
+void m2l_xz_codes(int P, std::vector<int32_t>& in, std::vector<int32_t>& out) {
+  const XzDims d = xz_dims(P);
+  const int P2 = P * P, Kp = 4 * ((P2 + 3) / 4);
+  const uint32_t zx = 1u << 17, zy = 1u << 13;
+  std::vector<int32_t> dense_in, dense_out;
+  m2l_reflection_codes(P, Kp, dense_in, dense_out);
+  auto xpart = [](uint32_t c) { return (c & 0xffu) | (c & (3u << 16)) | (c & (3u << 30)); };
+  auto ypart = [](uint32_t c) { return ((c & 0xffu) << 18) | ((c >> 4) & (3u << 12)) | ((c >> 4) & (3u << 26)); };
+  in.assign(17 * (size_t)d.Kx + 16 * (size_t)d.RTS, (int32_t)(zx | zy));
+  for (int g = 0; g < 17; ++g)
+    for (int e = 0; e < d.C; ++e) {
+      int n, m;
+      xz_entry(P, e, &n, &m);
+      uint32_t w = (uint32_t)m << 8;
+      if (g == 16) {
+        w |= zx | zy;
+      } else {
+        w |= xpart((uint32_t)dense_in[(size_t)g * Kp + n * n + n + m]);
+        w |= m > 0 ? ypart((uint32_t)dense_in[(size_t)g * Kp + n * n + n - m]) : zy;
+      }
+      in[(size_t)g * d.Kx + e] = (int32_t)w;
+    }
+  int32_t* mrow = in.data() + 17 * (size_t)d.Kx;
+  for (int r = 0; r < 16 * d.RTS; ++r) {
+    int n = 0, m = 0;
+    if (r < d.S) xz_entry(P, r, &n, &m);
+    mrow[r] = m;
+  }
+  // staging row of each canonical coefficient (n, m')
+  std::vector<int32_t> srow(P2, -1);
+  for (int e = 0; e < d.C; ++e) {
+    int n, m;
+    xz_entry(P, e, &n, &m);
+    const int r = e / 16;
+    const int plus = r < d.RTS ? 2 * r : 2 * d.RTS + (r - d.RTS);
+    srow[n * n + n + m] = xz_tile_dest(P, plus) + e % 16;
+    if (m > 0) srow[n * n + n - m] = xz_tile_dest(P, 2 * r + 1) + e % 16;
+  }
+  out.assign(16 * (size_t)P2, 0);
+  for (int g = 0; g < 16; ++g)
+    for (int c = 0; c < P2; ++c) {
+      const int32_t code = dense_out[(size_t)g * P2 + c];  // canonical row in bits 0..15, phase above
+      out[(size_t)g * P2 + c] = (code & ~0xffff) | srow[code & 0xffff];
+    }
+}
+
 }  // namespace hfmm
