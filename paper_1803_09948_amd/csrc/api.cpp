@@ -495,7 +495,7 @@ int prepare_host(Tree& t, double k, int P, Plan** out) {
     // the reflection code tables
     const XzDims xd = xz_dims(P);
     pl.bytes_lists = (int64_t)spairs.size() * 17 + (nc + 1) * 4 + (int64_t)work.size() * 20 +
-                     (int64_t)ivals.size() * 8 + (17 * (int64_t)xd.Kx + 16 * xd.RTS + 16 * P2) * 4 +
+                     (int64_t)ivals.size() * 8 + (17 * (int64_t)xz_code_stride(P) + 16 * xd.RTS + 16 * P2) * 4 +
                      17 * (int64_t)Kp * 4;
     // operators (descriptors and padded tables), level scales, M and L, the
     // M2L staging of the largest segment

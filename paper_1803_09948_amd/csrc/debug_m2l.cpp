@@ -48,8 +48,18 @@ static int debug_m2l(int P, double k, double ki, const double* t, double rho_in,
   for (int b = 0; b < count; b += CH) chunks.push_back(make_int4(0, 0, b, std::min(count, b + CH)));
   std::vector<int32_t> bmap, omap;
   m2l_xz_codes(P, bmap, omap);
-  DevBuf d_ops, d_off, d_lm, d_val, d_tab, d_pairs, d_chunks, d_slotg, d_soff, d_red, d_bmap, d_omap, d_stage, d_inst;
+  DevBuf d_ops, d_off, d_lm, d_val, d_tab, d_pairs, d_chunks, d_slotg, d_soff, d_red, d_bmap, d_omap, d_stage, d_inst,
+      d_min;
   int rc;
+  // the product stores multipoles in mpos order: reorder the caller's columns
+  std::vector<float2> hin((size_t)count * P2), hperm((size_t)count * P2);
+  HIP_TRY(hipMemcpyAsync(hin.data(), in, hin.size() * sizeof(float2), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int c = 0; c < count; ++c)
+    for (int n = 0; n < P; ++n)
+      for (int m = -n; m <= n; ++m)
+        hperm[(size_t)c * P2 + mpos(P, n, m)] = hin[(size_t)c * P2 + n * n + n + m];
+  if ((rc = upload_vec(d_min, hperm))) return rc;
   if ((rc = upload_vec(d_ops, std::vector<OpDesc>{d})) || (rc = upload_vec(d_off, cp.off)) ||
       (rc = upload_vec(d_lm, cp.lm)) || (rc = upload_vec(d_val, cv)) || (rc = upload_vec(d_pairs, pairs)) ||
       (rc = upload_vec(d_chunks, chunks)) || (rc = upload_vec(d_slotg, slot_g)) || (rc = upload_vec(d_soff, soff)) ||
@@ -59,7 +69,7 @@ static int debug_m2l(int P, double k, double ki, const double* t, double rho_in,
     return rc;
   InstDev I{};
   I.tables = d_tab.as<float2>();
-  I.M = const_cast<float2*>(in);
+  I.M = d_min.as<float2>();
   I.L = out;
   I.m2l_pairs = d_pairs.as<int4>();
   I.stage = d_stage.as<float2>();

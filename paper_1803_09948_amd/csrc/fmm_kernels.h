@@ -41,6 +41,24 @@ __host__ __device__ constexpr XzDims xz_dims(int P) {
   const int KSS = (S + 3) / 4, KSC = (C + 3) / 4, RTS = (S + 15) / 16, RTC = (C + 15) / 16;
   return XzDims{S, C, KSS, KSC, 4 * KSC, RTS, RTC, RTC + RTS, 16 * (RTC + RTS)};
 }
+// Storage order of the coefficients of a multipole M in the FP32 path: the
+// pairs (n, m), (n, -m) for the S-list entries e = (n, m), m > 0, at 2e and
+// 2e + 1, then (n, 0) at 2S + n, so that the M2L reads both members of a
+// pair with one 16-byte load (the local expansions L keep the order
+// n^2 + n + m).
+__host__ __device__ constexpr int mpos(int P, int n, int m) {
+  const int S = P * (P - 1) / 2;
+  if (m == 0) return 2 * S + n;
+  const int a = m > 0 ? m : -m, e = (n - 1) * n / 2 + (a - 1);
+  return 2 * e + (m > 0 ? 0 : 1);
+}
+// Row stride of the M2L input code table ([17][stride] words): at least Kx
+// and 4 more than a multiple of 64, so that the 16 reflections x 4 k-lanes of
+// one read fall in distinct LDS banks.
+__host__ __device__ constexpr int xz_code_stride(int P) {
+  const int kx = xz_dims(P).Kx;
+  return kx + ((4 - kx) % 64 + 64) % 64;
+}
 // Entries per operator in the FP32 tables: the dense Kp x Rp operator
 // (M2M, L2L), or the [Kx][Rx] blocks of an M2L operator followed by its P
 // azimuth phases e^{i m phi} (m < P), whichever is larger (16-entry aligned).

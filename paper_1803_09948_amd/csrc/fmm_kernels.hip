@@ -297,6 +297,15 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
     }
     return;
   }
+  // standard index n^2 + n + m of storage position pos of a multipole (FP32
+  // M2M: input and output multipoles are stored in mpos order)
+  auto mstd = [&](int pos) {
+    for (int n = 0; n < P; ++n)
+      for (int m = -n; m <= n; ++m)
+        if (mpos(P, n, m) == pos) return n * n + n + m;
+    return 0;
+  };
+  const bool mperm = XZ && d.kind == 0;
   for (int f = threadIdx.x; f < Kp * Rp; f += blockDim.x) {
     const int col = f / Rp, row = f % Rp;  // col (n,m) = input, row (n',m') = output
     if (col >= P2 || row >= P2) {
@@ -304,7 +313,10 @@ __global__ void k_gen_tables(const OpDescDev* __restrict__ ops, int nops, int P,
       continue;
     }
     double re, im;
-    dense(row, col, re, im);
+    if (mperm)
+      dense(mstd(row), mstd(col), re, im);
+    else
+      dense(row, col, re, im);
     store_entry(T + f, re, im);
   }
 }
@@ -590,7 +602,10 @@ __global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items, cons
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int e = lane + 64 * t;
-    if (e < P2) I.M[(size_t)cell * P2 + e] = acc[t];
+    if (e < P2) {
+      const int n = (int)sqrtf((float)e + 0.5f);
+      I.M[(size_t)cell * P2 + mpos(P, n, e - n * n - n)] = acc[t];
+    }
   }
 }
 
@@ -676,8 +691,8 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
                 Rx = X.Rx;
   constexpr int TSTRIDE = xz_table_stride(P);  // table entries per operator
   constexpr int SM = xz_stage_sm(P), ST = xz_stage_st(P);
-  constexpr int NCODE = 17 * Kx;
-  extern __shared__ int smap[];     // [17][Kx] input codes (m2l_xz_codes), then [16 RTS] m' of the S-list rows
+  constexpr int KXS = xz_code_stride(P), NCODE = 17 * KXS;
+  extern __shared__ int smap[];     // [17][KXS] input codes (m2l_xz_codes), then [16 RTS] m' of the S-list rows
   const int b = blockIdx.x;
   const int w = (b & 7) * per_xcd + (b >> 3);
   if (w * CPW >= nitems) return;
@@ -713,28 +728,21 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
     if (np <= 0) continue;
     // column t of this lane is pair 16 t + li: (target, source, reflection,
     // slot); a column past the item's end reads the all-zero code row 16.
-    // The multipoles of column t: a 64-bit address per column, or (the
-    // one-chunk shapes, whose register budget is tightest) a 32-bit byte
-    // offset msb[t] beside the wave-uniform base Mb (M of an instance is
-    // < 4 GiB)
+    // The multipoles of column t: a 32-bit byte offset msb[t] beside the
+    // wave-uniform base Mb (M of an instance is < 4 GiB)
     const char* Mb = reinterpret_cast<const char*>(I.M);
     uint32_t msb[NCT];
-    gcfloat2* Ms[NCT];
     int goff[NCT];
 #pragma unroll
     for (int t = 0; t < NCT; ++t) {
       const int p = 16 * t + li;
       const bool ok = p < np;
       const int4 pr = ld_int4(I.m2l_pairs + pb + (ok ? p : 0));
-      if constexpr (CPW == 1)
-        msb[t] = (uint32_t)pr.y * (uint32_t)(P2 * sizeof(float2));
-      else
-        Ms[t] = (gcfloat2*)(I.M + (size_t)pr.y * P2);
-      goff[t] = (ok ? pr.z : 16) * Kx + lk;
+      msb[t] = (uint32_t)pr.y * (uint32_t)(P2 * sizeof(float2));
+      goff[t] = (ok ? pr.z : 16) * KXS + lk;
     }
-    // the operator's table ([Kx][Rx], then its phases e^{i m phi}, m < P): a
-    // 64-bit address per lane, or (one-chunk shapes) the wave-uniform base
-    // Tb and this lane's 32-bit byte offset (a table is < 4 GiB)
+    // the operator's table ([Kx][Rx], then its phases e^{i m phi}, m < P):
+    // the wave-uniform base Tb and this lane's 32-bit byte offset
     const char* Tb = reinterpret_cast<const char*>(I.tables + (size_t)op * TSTRIDE);
     auto lds_sync = [&]() {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -745,31 +753,38 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
     __shared__ float2 sph[kMaxP];
     if (lane < P) sph[lane] = ld2((gcfloat2*)(I.tables + (size_t)op * TSTRIDE + Kx * Rx) + lane);
     lds_sync();
-    // B gather: the two reflected multipoles of each column's input and the
+    // B gather: the aligned pair of float2 holding the two reflected
+    // multipoles of each column's input (one 16-byte load when P^2 is even,
+    // so that every pair is 16-byte aligned, else two 8-byte loads) and the
     // input's phase (the same for every column: m depends on k only); the
     // loads issue now, codes and phases apply when the step runs
-    auto load_b = [&](int k4, float2* rx, float2* ry, float2& rp) {
+    auto load_b = [&](int k4, float2* rx, float2* ry, float2& rp, int* ce) {
 #pragma unroll
       for (int t = 0; t < NCT; ++t) {
         const int e = smap[goff[t] + k4];
-        if constexpr (CPW == 1) {
-          rx[t] = ld2((gcfloat2*)(Mb + (msb[t] + (uint32_t)(e & 0xff) * (uint32_t)sizeof(float2))));
-          ry[t] = ld2((gcfloat2*)(Mb + (msb[t] + (uint32_t)((e >> 18) & 0xff) * (uint32_t)sizeof(float2))));
+        ce[t] = e;
+        const uint32_t off = msb[t] + (uint32_t)(e & 0xff) * (uint32_t)sizeof(float2);
+        if constexpr (P2 % 2 == 0) {
+          const f4v v = *(const __attribute__((address_space(1))) f4v*)(Mb + off);
+          rx[t] = make_float2(v.x, v.y);
+          ry[t] = make_float2(v.z, v.w);
         } else {
-          rx[t] = ld2(Ms[t] + (e & 0xff));
-          ry[t] = ld2(Ms[t] + ((e >> 18) & 0xff));
+          rx[t] = ld2((gcfloat2*)(Mb + off));
+          ry[t] = ld2((gcfloat2*)(Mb + off + sizeof(float2)));
         }
       }
-      rp = sph[(smap[goff[0] + k4] >> 8) & 15];
+      rp = sph[(ce[0] >> 9) & 15];
     };
     // the Gauss operands of u (C block) and v (S block)
     float uu[NCT], ud[NCT], us[NCT], vu[NCT], vd[NCT], vs[NCT];
-    auto finish_b = [&](int k4, const float2* rx, const float2* ry, float2 rp) {
+    auto finish_b = [&](const float2* rx, const float2* ry, float2 rp, const int* ce) {
 #pragma unroll
       for (int t = 0; t < NCT; ++t) {
-        const int e = smap[goff[t] + k4], ey = e << 4;  // the second code sits 4 bits lower
-        const float2 x0 = apply_code(rx[t].x, rx[t].y, e);
-        const float2 y0 = apply_code(ry[t].x, ry[t].y, ey);
+        const int e = ce[t], ey = e << 3;  // y's flags sit 3 bits lower
+        const bool hi = e & (1 << 8);      // x is the high float2 of the pair
+        const float2 lo2 = rx[t], hi2 = ry[t];
+        const float2 x0 = apply_code(hi ? hi2.x : lo2.x, hi ? hi2.y : lo2.y, e);
+        const float2 y0 = apply_code(hi ? lo2.x : hi2.x, hi ? lo2.y : hi2.y, ey);
         const bool zx = e & (1 << 17), zy = ey & (1 << 17);
         const float xr = zx ? 0.f : x0.x, xi = zx ? 0.f : x0.y;
         const float yr = zy ? 0.f : y0.x, yi = zy ? 0.f : y0.y;
@@ -795,22 +810,17 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
         k3[t][r] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
     const uint32_t tlane = (uint32_t)li * (uint32_t)sizeof(float2);
-    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * TSTRIDE) + li;
     // the table operand (A) is loaded AD k-steps ahead (2 AD register
     // buffers), the gathered multipoles (B) one step ahead into one buffer
     // that each step first turns into its operands; a straight-line loop
     // body of four steps keeps the compiler's wait counts exact
     constexpr int AM = 2 * AD - 1;
     float2 av[2 * AD][RT], bx[NCT], by[NCT], bp;
+    int ce[NCT];
     auto load_a = [&](int k, float2* out) {
-      if constexpr (CPW == 1) {
-        const uint32_t off = tlane + (uint32_t)(k * Rx) * (uint32_t)sizeof(float2);
+      const uint32_t off = tlane + (uint32_t)(k * Rx) * (uint32_t)sizeof(float2);
 #pragma unroll
-        for (int r = 0; r < RT; ++r) out[r] = ld2((gcfloat2*)(Tb + (off + (uint32_t)(16 * r * sizeof(float2)))));
-      } else {
-#pragma unroll
-        for (int r = 0; r < RT; ++r) out[r] = ld2(T + (size_t)k * Rx + 16 * r);
-      }
+      for (int r = 0; r < RT; ++r) out[r] = ld2((gcfloat2*)(Tb + (off + (uint32_t)(16 * r * sizeof(float2)))));
     };
     auto mma = [&](const float2* a, bool joint) {
 #pragma unroll
@@ -838,14 +848,14 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 #pragma unroll
     for (int d = 0; d < AD; ++d)
       if (d < KSC) load_a(4 * d + lk, av[d]);
-    load_b(0, bx, by, bp);
+    load_b(0, bx, by, bp, ce);
     for (int ks = 0; ks < KS4; ks += 4) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         load_a(min(4 * (ks + j + AD), klast) + lk, av[(j + AD) & AM]);
-        finish_b(4 * (ks + j), bx, by, bp);
+        finish_b(bx, by, bp, ce);
         __builtin_amdgcn_sched_barrier(0);  // the raw B registers are free again
-        load_b(min(4 * (ks + j + 1), klast), bx, by, bp);
+        load_b(min(4 * (ks + j + 1), klast), bx, by, bp, ce);
         __builtin_amdgcn_sched_barrier(0);  // loads issue before this step's MFMAs
         // the wave issuing its MFMAs goes first when both waves of the SIMD
         // are ready, so its matrix-core block is not split by the other
@@ -859,9 +869,9 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 #pragma unroll
     for (int st = KS4; st < KSC; ++st) {
       if (st + AD < KSC) load_a(4 * (st + AD) + lk, av[(st + AD) & AM]);
-      finish_b(4 * st, bx, by, bp);
+      finish_b(bx, by, bp, ce);
       __builtin_amdgcn_sched_barrier(0);
-      if (st + 1 < KSC) load_b(4 * (st + 1), bx, by, bp);
+      if (st + 1 < KSC) load_b(4 * (st + 1), bx, by, bp, ce);
       __builtin_amdgcn_sched_barrier(0);
       __builtin_amdgcn_s_setprio(1);
       mma(av[st & AM], st < KSS);
@@ -1500,7 +1510,7 @@ static void launch_m2l_t(const int4* chunks, int nchunks, int sub, const InstDev
   const int nitems = nchunks * sub;
   const int nwaves = (nitems + CPW - 1) / CPW;
   const int per = (nwaves + 7) / 8;
-  const size_t lds = (17 * (size_t)X.Kx + 16 * (size_t)X.RTS) * sizeof(int);
+  const size_t lds = (17 * (size_t)xz_code_stride(P) + 16 * (size_t)X.RTS) * sizeof(int);
   k_m2l_mfma<P, NCT, WPE, CPW, AD><<<8 * per, 64, lds, s>>>(chunks, nitems, per, sub, insts, bmap);
 }
 
@@ -1532,7 +1542,7 @@ static void launch_m2l_p(int variant, int sub, const int4* chunks, int nchunks, 
         case 1: return launch_m2l_t<P, 1, NW, 1, 1>(chunks, nchunks, 2, insts, bmap, s);
         case 2: return launch_m2l_t<P, 2, 2, 2, 1>(chunks, nchunks, 1, insts, bmap, s);
         case 3: return launch_m2l_t<P, 2, 2, 4, 1>(chunks, nchunks, 1, insts, bmap, s);
-        default: return launch_m2l_t<P, 2, 2, 1, 2>(chunks, nchunks, 1, insts, bmap, s);
+        default: return launch_m2l_t<P, 2, 2, 1, 1>(chunks, nchunks, 1, insts, bmap, s);
       }
     }
   }

@@ -25,6 +25,7 @@
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <stdexcept>
 
 #include "hfmm_internal.h"
 
@@ -445,41 +446,54 @@ void m2l_reflection_codes(int P, int Kp, std::vector<int32_t>& in, std::vector<i
 }
 
 
-// Codes of the xz-plane M2L (XzDims).  in: [17][Kx], for reflection g and
-// C-list input k = (n, m), one word holding the codes of the two reflected
-// multipoles B[(n, m)] (x) and B[(n, -m)] (y) and m:
-//   bits 0..7 x index, 16 x swap, 17 x zero, 30 x neg_im, 31 x neg_re,
-//   bits 8..11 m, 12 y swap, 13 y zero, 18..25 y index, 26 y neg_im,
-//   27 y neg_re
-// (so that the word shifted left by 4 carries y's flags where x's are); y is
-// marked zero when m = 0, both when k >= C.  Row 16 (columns past a chunk's
-// end) has both marked zero.  Then 16 RTS entries: m' of S-list output row
-// r (0 past the list).  out: [16][P^2], for target coefficient c = (n, m)
-// under reflection g: the staging row of the canonical (n, m') it comes
-// from (xz_tile_dest) and the phase i^-ph, in the code format above.
+// Codes of the xz-plane M2L (XzDims).  in: [17][xz_code_stride(P)], for
+// reflection g and C-list input k = (n, m), one word holding where the two
+// reflected multipoles B[(n, m)] (x) and B[(n, -m)] (y) are found in the
+// source's multipole (stored in mpos order: one aligned pair of float2 at
+// `base` holds x, and y unless m = 0) and their phases:
+//   bits 0..7 base (even), 8 x is the high float2 of the pair, 9..12 m,
+//   13 y swap, 14 y zero, 16 x swap, 17 x zero, 27 y neg_im, 28 y neg_re,
+//   30 x neg_im, 31 x neg_re
+// (the word shifted left by 3 carries y's flags where x's are); y is marked
+// zero when m = 0, both when k >= C.  Row 16 (columns past a chunk's end)
+// has both marked zero.  Then 16 RTS entries: m' of S-list output row r (0
+// past the list).  out: [16][P^2], for target coefficient c = (n, m) under
+// reflection g: the staging row of the canonical (n, m') it comes from
+// (xz_tile_dest) and the phase i^-ph (swap bit 16, signs in bits 30, 31).
 void m2l_xz_codes(int P, std::vector<int32_t>& in, std::vector<int32_t>& out) {
   const XzDims d = xz_dims(P);
   const int P2 = P * P, Kp = 4 * ((P2 + 3) / 4);
-  const uint32_t zx = 1u << 17, zy = 1u << 13;
+  const uint32_t zx = 1u << 17, zy = 1u << 14;
   std::vector<int32_t> dense_in, dense_out;
   m2l_reflection_codes(P, Kp, dense_in, dense_out);
-  auto xpart = [](uint32_t c) { return (c & 0xffu) | (c & (3u << 16)) | (c & (3u << 30)); };
-  auto ypart = [](uint32_t c) { return ((c & 0xffu) << 18) | ((c >> 4) & (3u << 12)) | ((c >> 4) & (3u << 26)); };
-  in.assign(17 * (size_t)d.Kx + 16 * (size_t)d.RTS, (int32_t)(zx | zy));
+  // storage position of standard index c = n^2 + n + m
+  std::vector<int> pos(P2);
+  for (int n = 0; n < P; ++n)
+    for (int m = -n; m <= n; ++m) pos[n * n + n + m] = mpos(P, n, m);
+  const int ks = xz_code_stride(P);
+  in.assign(17 * (size_t)ks + 16 * (size_t)d.RTS, (int32_t)(zx | zy));
   for (int g = 0; g < 17; ++g)
     for (int e = 0; e < d.C; ++e) {
       int n, m;
       xz_entry(P, e, &n, &m);
-      uint32_t w = (uint32_t)m << 8;
+      uint32_t w = (uint32_t)m << 9;
       if (g == 16) {
         w |= zx | zy;
       } else {
-        w |= xpart((uint32_t)dense_in[(size_t)g * Kp + n * n + n + m]);
-        w |= m > 0 ? ypart((uint32_t)dense_in[(size_t)g * Kp + n * n + n - m]) : zy;
+        const uint32_t dx = (uint32_t)dense_in[(size_t)g * Kp + n * n + n + m];
+        const int px = pos[dx & 0xffff];
+        w |= (uint32_t)(px & ~1) | ((uint32_t)(px & 1) << 8) | (dx & ((1u << 16) | (3u << 30)));
+        if (m > 0) {
+          const uint32_t dy = (uint32_t)dense_in[(size_t)g * Kp + n * n + n - m];
+          if ((pos[dy & 0xffff] ^ px) != 1) throw std::logic_error("M2L code table: x and y not one pair");
+          w |= (dy >> 3) & ((1u << 13) | (3u << 27));
+        } else {
+          w |= zy;
+        }
       }
-      in[(size_t)g * d.Kx + e] = (int32_t)w;
+      in[(size_t)g * ks + e] = (int32_t)w;
     }
-  int32_t* mrow = in.data() + 17 * (size_t)d.Kx;
+  int32_t* mrow = in.data() + 17 * (size_t)ks;
   for (int r = 0; r < 16 * d.RTS; ++r) {
     int n = 0, m = 0;
     if (r < d.S) xz_entry(P, r, &n, &m);
