@@ -14,6 +14,8 @@
 #include <cmath>
 #include <cstdint>
 
+#include <type_traits>
+
 #include "fmm_kernels.h"
 
 namespace hfmm {
@@ -775,21 +777,29 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
       }
       rp = sph[(ce[0] >> 9) & 15];
     };
-    // the Gauss operands of u (C block) and v (S block)
+    // the Gauss operands of u (C block) and v (S block), from the pair's
+    // turned halves lo', hi' (m2l_xz_codes): u = q lo' + conj(q) hi',
+    // v = q lo' - conj(q) hi', q = p or conj(p); ZERO: apply the codes' zero
+    // marks (needed only where the C-list reaches m = 0 or its end: the
+    // columns past a chunk's end are never stored, whatever they compute)
     float uu[NCT], ud[NCT], us[NCT], vu[NCT], vd[NCT], vs[NCT];
-    auto finish_b = [&](const float2* rx, const float2* ry, float2 rp, const int* ce) {
+    auto finish_b = [&](const float2* rx, const float2* ry, float2 rp, const int* ce, auto zero_tag) {
+      constexpr bool ZERO = decltype(zero_tag)::value;
 #pragma unroll
       for (int t = 0; t < NCT; ++t) {
-        const int e = ce[t], ey = e << 3;  // y's flags sit 3 bits lower
-        const bool hi = e & (1 << 8);      // x is the high float2 of the pair
-        const float2 lo2 = rx[t], hi2 = ry[t];
-        const float2 x0 = apply_code(hi ? hi2.x : lo2.x, hi ? hi2.y : lo2.y, e);
-        const float2 y0 = apply_code(hi ? lo2.x : hi2.x, hi ? lo2.y : hi2.y, ey);
-        const bool zx = e & (1 << 17), zy = ey & (1 << 17);
-        const float xr = zx ? 0.f : x0.x, xi = zx ? 0.f : x0.y;
-        const float yr = zy ? 0.f : y0.x, yi = zy ? 0.f : y0.y;
-        const float sr = xr + yr, si = xi + yi, dr = xr - yr, di = xi - yi;
-        const float pr = rp.x, pi = rp.y;
+        const int e = ce[t], he = e << 3;  // hi's flags sit 3 bits lower
+        const float2 l0 = apply_code(rx[t].x, rx[t].y, e);
+        const float2 h0 = apply_code(ry[t].x, ry[t].y, he);
+        float lr = l0.x, lim = l0.y, hr = h0.x, him = h0.y;
+        if constexpr (ZERO) {
+          const bool zl = e & (1 << 17), zh = he & (1 << 17);
+          lr = zl ? 0.f : lr;
+          lim = zl ? 0.f : lim;
+          hr = zh ? 0.f : hr;
+          him = zh ? 0.f : him;
+        }
+        const float sr = lr + hr, si = lim + him, dr = lr - hr, di = lim - him;
+        const float pr = rp.x, pi = __int_as_float(__float_as_int(rp.y) ^ ((e << 23) & (int)0x80000000));
         const float ur = fmaf(pr, sr, -pi * di), ui = fmaf(pr, si, pi * dr);
         const float wr = fmaf(pr, dr, -pi * si), wi = fmaf(pr, di, pi * sr);
         uu[t] = ur;
@@ -840,11 +850,13 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
       }
     };
     // step s: issue A(s + AD), form step s's B operands, issue B(s + 1),
-    // then the MFMAs of step s; the
-    // loop runs whole groups of four joint steps and clamps k (redundant
-    // in-bounds loads past the end are unused), the remaining steps follow
-    // unrolled (joint while s < KSS, then C only)
+    // then the MFMAs of step s; the loop runs whole groups of four joint
+    // steps and clamps k (redundant in-bounds loads past the end are unused),
+    // the remaining steps follow unrolled (joint while s < KSS, then C only).
+    // Every step applies the zero marks: a zero-free variant for the steps
+    // inside the S-list costs registers (the straight-line remainder grows)
     constexpr int klast = Kx - 4, KS4 = (KSS / 4) * 4;
+    using withzero = std::integral_constant<bool, true>;
 #pragma unroll
     for (int d = 0; d < AD; ++d)
       if (d < KSC) load_a(4 * d + lk, av[d]);
@@ -853,7 +865,7 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         load_a(min(4 * (ks + j + AD), klast) + lk, av[(j + AD) & AM]);
-        finish_b(bx, by, bp, ce);
+        finish_b(bx, by, bp, ce, withzero{});
         __builtin_amdgcn_sched_barrier(0);  // the raw B registers are free again
         load_b(min(4 * (ks + j + 1), klast), bx, by, bp, ce);
         __builtin_amdgcn_sched_barrier(0);  // loads issue before this step's MFMAs
@@ -869,7 +881,7 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 #pragma unroll
     for (int st = KS4; st < KSC; ++st) {
       if (st + AD < KSC) load_a(4 * (st + AD) + lk, av[(st + AD) & AM]);
-      finish_b(bx, by, bp, ce);
+      finish_b(bx, by, bp, ce, withzero{});
       __builtin_amdgcn_sched_barrier(0);
       if (st + 1 < KSC) load_b(4 * (st + 1), bx, by, bp, ce);
       __builtin_amdgcn_sched_barrier(0);
@@ -887,9 +899,17 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
     // LDS ([column][16 rows]) so that every store instruction writes whole
     // 128-byte lines (8 lanes x 16 bytes per column).
     __shared__ f4v sout[2][16 * NCT * 8];
+    // slot of each column (-1 past the chunk's end) and the sign of its S
+    // block: -1 when its reflection flips the sign of m (m2l_xz_codes)
     int slots[NCT];
+    float ssgn[NCT];
 #pragma unroll
-    for (int t = 0; t < NCT; ++t) slots[t] = (16 * t + li < np) ? ld_int4(I.m2l_pairs + pb + 16 * t + li).w : -1;
+    for (int t = 0; t < NCT; ++t) {
+      const bool ok = 16 * t + li < np;
+      const int4 pr = ld_int4(I.m2l_pairs + pb + (ok ? 16 * t + li : 0));
+      slots[t] = ok ? pr.w : -1;
+      ssgn[t] = (__builtin_popcount(pr.z & 11) & 1) ? -1.f : 1.f;
+    }
     auto store_tile = [&](int tile, int half) {
       const int vr = xz_tile_rows(P, tile), dst = xz_tile_dest(P, tile);
 #pragma unroll
@@ -922,7 +942,7 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
           const float Ar = k1[t][r][v] - k3[t][r][v], Ai = k1[t][r][v] + k2[t][r][v];
           if (pm) {
             const int rs = pm ? RTC + r : 0;
-            const float Br = k1[t][rs][v] - k3[t][rs][v], Bi = k1[t][rs][v] + k2[t][rs][v];
+            const float Br = ssgn[t] * (k1[t][rs][v] - k3[t][rs][v]), Bi = ssgn[t] * (k1[t][rs][v] + k2[t][rs][v]);
             const int e = 16 * r + 4 * lk + v;
             const bool srow = e < X.S;
             const float2 p = srow ? sph[mrow[e]] : make_float2(1.f, 0.f);

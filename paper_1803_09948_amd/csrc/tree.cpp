@@ -447,23 +447,31 @@ void m2l_reflection_codes(int P, int Kp, std::vector<int32_t>& in, std::vector<i
 
 
 // Codes of the xz-plane M2L (XzDims).  in: [17][xz_code_stride(P)], for
-// reflection g and C-list input k = (n, m), one word holding where the two
-// reflected multipoles B[(n, m)] (x) and B[(n, -m)] (y) are found in the
-// source's multipole (stored in mpos order: one aligned pair of float2 at
-// `base` holds x, and y unless m = 0) and their phases:
-//   bits 0..7 base (even), 8 x is the high float2 of the pair, 9..12 m,
-//   13 y swap, 14 y zero, 16 x swap, 17 x zero, 27 y neg_im, 28 y neg_re,
-//   30 x neg_im, 31 x neg_re
-// (the word shifted left by 3 carries y's flags where x's are); y is marked
-// zero when m = 0, both when k >= C.  Row 16 (columns past a chunk's end)
-// has both marked zero.  Then 16 RTS entries: m' of S-list output row r (0
-// past the list).  out: [16][P^2], for target coefficient c = (n, m) under
-// reflection g: the staging row of the canonical (n, m') it comes from
-// (xz_tile_dest) and the phase i^-ph (swap bit 16, signs in bits 30, 31).
+// reflection g and C-list input k = (n, m), one word telling where the two
+// reflected multipoles B[(n, m)] = i^a M[(n, s m)] (x) and B[(n, -m)] =
+// i^b M[(n, -s m)] (y) are found and how to turn them.  The source's
+// multipole is stored in mpos order, so one aligned pair of float2 at
+// `base` holds lo = M[(n, |m|)] and hi = M[(n, -|m|)]; s = -1 when g flips
+// the sign of m, and then x is hi:
+//   bits 0..7 base (even), 8 conj (s = -1, m > 0), 9..12 m,
+//   lo's phase: 16 swap, 17 zero, 30 neg_im, 31 neg_re,
+//   hi's phase: 13 swap, 14 zero, 27 neg_im, 28 neg_re
+// (the word shifted left by 3 carries hi's flags where lo's are).  With
+// p = e^{i m phi} and q = conj(p) if conj else p, the kernel forms
+//   u = q lo' + conj(q) hi',  v = q lo' - conj(q) hi'
+// from the turned lo', hi', which equals p x + conj(p) y and, up to the
+// sign s of the whole column, p x - conj(p) y.  For m = 0, x is lo or hi of
+// the pair holding (n, 0) and the other is marked zero; for k >= C both.
+// Row 16 (columns past a chunk's end) has both marked zero.  Then 16 RTS
+// entries: m' of S-list output row r (0 past the list).  out: [16][P^2],
+// for target coefficient c = (n, m) under reflection g: the staging row of
+// the canonical (n, m') it comes from (xz_tile_dest) and the phase i^-ph
+// (swap bit 16, signs in bits 30, 31).
 void m2l_xz_codes(int P, std::vector<int32_t>& in, std::vector<int32_t>& out) {
   const XzDims d = xz_dims(P);
   const int P2 = P * P, Kp = 4 * ((P2 + 3) / 4);
-  const uint32_t zx = 1u << 17, zy = 1u << 14;
+  const uint32_t zlo = 1u << 17, zhi = 1u << 14;
+  const uint32_t lo_ph = (1u << 16) | (3u << 30);  // a dense code's phase bits, in lo's place
   std::vector<int32_t> dense_in, dense_out;
   m2l_reflection_codes(P, Kp, dense_in, dense_out);
   // storage position of standard index c = n^2 + n + m
@@ -471,24 +479,27 @@ void m2l_xz_codes(int P, std::vector<int32_t>& in, std::vector<int32_t>& out) {
   for (int n = 0; n < P; ++n)
     for (int m = -n; m <= n; ++m) pos[n * n + n + m] = mpos(P, n, m);
   const int ks = xz_code_stride(P);
-  in.assign(17 * (size_t)ks + 16 * (size_t)d.RTS, (int32_t)(zx | zy));
+  in.assign(17 * (size_t)ks + 16 * (size_t)d.RTS, (int32_t)(zlo | zhi));
   for (int g = 0; g < 17; ++g)
     for (int e = 0; e < d.C; ++e) {
       int n, m;
       xz_entry(P, e, &n, &m);
       uint32_t w = (uint32_t)m << 9;
       if (g == 16) {
-        w |= zx | zy;
+        w |= zlo | zhi;
       } else {
         const uint32_t dx = (uint32_t)dense_in[(size_t)g * Kp + n * n + n + m];
         const int px = pos[dx & 0xffff];
-        w |= (uint32_t)(px & ~1) | ((uint32_t)(px & 1) << 8) | (dx & ((1u << 16) | (3u << 30)));
+        const bool xhi = px & 1;
+        w |= (uint32_t)(px & ~1);
         if (m > 0) {
           const uint32_t dy = (uint32_t)dense_in[(size_t)g * Kp + n * n + n - m];
           if ((pos[dy & 0xffff] ^ px) != 1) throw std::logic_error("M2L code table: x and y not one pair");
-          w |= (dy >> 3) & ((1u << 13) | (3u << 27));
+          const uint32_t clo = xhi ? dy : dx, chi = xhi ? dx : dy;
+          w |= (clo & lo_ph) | ((chi & lo_ph) >> 3) | (xhi ? 1u << 8 : 0u);
         } else {
-          w |= zy;
+          // x alone, in lo's or hi's place
+          w |= xhi ? (((dx & lo_ph) >> 3) | zlo) : ((dx & lo_ph) | zhi);
         }
       }
       in[(size_t)g * ks + e] = (int32_t)w;
