@@ -83,56 +83,35 @@ __host__ __device__ constexpr void xz_entry(int P, int e, int* n, int* m) {
   *n = nn;
   *m = e - base + 1;
 }
-// Output tiles of one pair, in the order the kernel writes them: for r <
-// RTS the "plus" tile r (C-list rows 16r.., giving L^{+m'} and, past the
-// S-list, L^{n'0}) and the "minus" tile r (S-list rows 16r.., giving
-// L^{-m'}), then the C-only tiles r = RTS..RTC-1 (rows of L^{n'0}).  Tile
-// i has xz_tile_rows(P, i) valid rows.  A staging slot holds the tiles with
-// 16 valid rows as whole 16-row blocks (Sm rows, whole 128-byte lines) and
-// the others, each padded to an even row count, in a dense tail (St rows).
-__host__ __device__ constexpr int xz_ntiles(int P) {
+// Layout of one pair's M2L result in its staging slot (float2 positions).
+// First the "pm block": for C-list entry e < 16 RTS, position 2e holds
+// L^{+m'} (or L^{n'0} for e >= S) and 2e + 1 holds L^{-m'} (unused for
+// e >= S), so that the two outputs of an S-list row are one aligned 16-byte
+// pair; RTS whole 32-row tiles.  Then the C-only rows e = 16 RTS..C-1
+// (L^{n'0}), in 16-row tiles: the whole ones follow the pm block, a last
+// partial one (padded to an even row count) goes to a dense tail array.
+// Sm = 32 RTS + 16 (whole C-only tiles) positions per slot in the main array
+// (whole 128-byte lines), St in the tail.
+__host__ __device__ constexpr int xz_co_rows(int P) {  // C-only rows
   const XzDims d = xz_dims(P);
-  return 2 * d.RTS + (d.RTC - d.RTS);
-}
-__host__ __device__ constexpr int xz_tile_rows(int P, int i) {
-  const XzDims d = xz_dims(P);
-  if (i < 2 * d.RTS) {
-    const int r = i / 2, lim = (i & 1) ? d.S : d.C;
-    return lim - 16 * r < 16 ? lim - 16 * r : 16;
-  }
-  const int r = d.RTS + (i - 2 * d.RTS);
-  return d.C - 16 * r < 16 ? d.C - 16 * r : 16;
-}
-// first staging row of tile i: full tiles in [0, Sm), the others at Sm + ...
-__host__ __device__ constexpr int xz_tile_dest(int P, int i) {
-  int full = 0, tail = 0;
-  for (int j = 0; j < i; ++j) {
-    const int v = xz_tile_rows(P, j);
-    if (v == 16)
-      ++full;
-    else
-      tail += 2 * ((v + 1) / 2);
-  }
-  if (xz_tile_rows(P, i) == 16) return 16 * full;
-  int nfull = 0;
-  for (int j = 0; j < xz_ntiles(P); ++j) nfull += xz_tile_rows(P, j) == 16;
-  return 16 * nfull + tail;
+  return d.C - 16 * d.RTS > 0 ? d.C - 16 * d.RTS : 0;
 }
 __host__ __device__ constexpr int xz_stage_sm(int P) {
-  int full = 0;
-  for (int i = 0; i < xz_ntiles(P); ++i) full += xz_tile_rows(P, i) == 16;
-  return 16 * full;
+  return 32 * xz_dims(P).RTS + 16 * (xz_co_rows(P) / 16);
 }
 __host__ __device__ constexpr int xz_stage_st(int P) {
-  int tail = 0;
-  for (int i = 0; i < xz_ntiles(P); ++i) {
-    const int v = xz_tile_rows(P, i);
-    if (v != 16) tail += 2 * ((v + 1) / 2);
-  }
-  return tail;
+  const int rem = xz_co_rows(P) % 16;
+  return 2 * ((rem + 1) / 2);
 }
-// Rows of an M2L staging slot: Sm in whole 16-row tiles, St in the tail
-// (see xz_tile_dest); Sm + St >= P^2.
+// staging position of C-list entry e's output: sign +1 (L^{+m'}, or L^{n'0}
+// for m' = 0) or -1 (L^{-m'}); positions >= Sm are in the tail
+__host__ __device__ constexpr int xz_stage_pos(int P, int e, int sign) {
+  const XzDims d = xz_dims(P);
+  if (e < 16 * d.RTS) return 2 * e + (sign < 0 ? 1 : 0);
+  return 32 * d.RTS + (e - 16 * d.RTS);
+}
+// Positions of an M2L staging slot: Sm in the main array, St in the tail
+// (see xz_stage_pos); Sm + St >= P^2.
 void stage_dims(int P, int* Sm, int* St);
 // k + i ki: complex wavenumber (ki = 0: real).  FP32 tables, xz_table_stride
 // entries per operator; the M2L operators (t the canonical offset) are

@@ -891,14 +891,13 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
       __builtin_amdgcn_sched_barrier(0);
     }
     // each pair owns a staging slot (slots are ordered by target) holding its
-    // result in the reflected frame, tile by tile (xz_tile_dest: tiles with
-    // 16 valid rows as whole 128-byte lines in the main array, the others in
-    // the dense tail array); the reduction kernel below maps it back and adds
-    // a target's slots in a fixed order.  Lane (j, q) holds rows 4q..4q+3 of
-    // every 16-row tile of column j; the plus and minus tiles pass through
-    // LDS ([column][16 rows]) so that every store instruction writes whole
-    // 128-byte lines (8 lanes x 16 bytes per column).
-    __shared__ f4v sout[2][16 * NCT * 8];
+    // result in the reflected frame (xz_stage_pos: the pm block, whose
+    // 16-byte pairs hold an S-list row's L^{+m'} and L^{-m'}, then the C-only
+    // rows); the reduction kernel below maps it back and adds a target's
+    // slots in a fixed order.  Lane (j, q) holds rows 4q..4q+3 of every
+    // 16-row tile of column j; the results pass through LDS ([column][tile])
+    // so that every store instruction writes whole 128-byte lines.
+    __shared__ f4v sout[16 * NCT * 17];  // [col][pieces], a column's row padded by one piece (LDS banks)
     // slot of each column (-1 past the chunk's end) and the sign of its S
     // block: -1 when its reflection flips the sign of m (m2l_xz_codes)
     int slots[NCT];
@@ -910,69 +909,75 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
       slots[t] = ok ? pr.w : -1;
       ssgn[t] = (__builtin_popcount(pr.z & 11) & 1) ? -1.f : 1.f;
     }
-    auto store_tile = [&](int tile, int half) {
-      const int vr = xz_tile_rows(P, tile), dst = xz_tile_dest(P, tile);
+    // store NP 16-byte pieces per column from LDS ([col][NP + 1]) to position
+    // dst (main array) or, if tail, to position dst - SM of the tail array,
+    // pieces past `valid` skipped
+    auto store_lds = [&](auto np_tag, int dst, bool tail, int valid) {
+      constexpr int NP = decltype(np_tag)::value;
 #pragma unroll
-      for (int u = 0; u < 2 * NCT; ++u) {  // 16 NCT columns x 8 pieces over 64 lanes
-        const int e = 64 * u + lane, col = e >> 3, piece = e & 7;
+      for (int u = 0; u < NP * NCT / 4; ++u) {  // 16 NCT columns x NP pieces over 64 lanes
+        const int e = 64 * u + lane, col = e / NP, piece = e % NP;
         int slot = -1;
 #pragma unroll
         for (int t = 0; t < NCT; ++t) {
           const int sv = __shfl(slots[t], col & 15);
           if ((col >> 4) == t) slot = sv;
         }
-        if (slot < 0) continue;
-        if (vr == 16) {
-          gfloat4* St = (gfloat4*)(I.stage + (size_t)slot * SM + dst);
-          __builtin_nontemporal_store(sout[half][col * 8 + piece], &St[piece]);  // written once, read once
-        } else if (piece < (vr + 1) / 2) {
-          gfloat4* St = (gfloat4*)(I.stage_tail + (size_t)slot * ST + (dst - SM));
-          __builtin_nontemporal_store(sout[half][col * 8 + piece], &St[piece]);
-        }
+        if (slot < 0 || piece >= valid) continue;
+        gfloat4* St = tail ? (gfloat4*)(I.stage_tail + (size_t)slot * ST + (dst - SM))
+                           : (gfloat4*)(I.stage + (size_t)slot * SM + dst);
+        __builtin_nontemporal_store(sout[col * (NP + 1) + piece], &St[piece]);  // written once, read once
       }
     };
+    auto lds_sync2 = [&]() {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // the pm tiles: row e of tile r gives the piece (L^{+m'}, L^{-m'})
 #pragma unroll
-    for (int r = 0; r < RTC; ++r) {
-      const bool pm = r < RTS;  // plus and minus tiles, else a C-only tile
+    for (int r = 0; r < RTS; ++r) {
 #pragma unroll
       for (int t = 0; t < NCT; ++t) {
-        float o[2][8];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float Ar = k1[t][r][v] - k3[t][r][v], Ai = k1[t][r][v] + k2[t][r][v];
-          if (pm) {
-            const int rs = pm ? RTC + r : 0;
-            const float Br = ssgn[t] * (k1[t][rs][v] - k3[t][rs][v]), Bi = ssgn[t] * (k1[t][rs][v] + k2[t][rs][v]);
-            const int e = 16 * r + 4 * lk + v;
-            const bool srow = e < X.S;
-            const float2 p = srow ? sph[mrow[e]] : make_float2(1.f, 0.f);
-            const float sr = Ar + Br, si = Ai + Bi, dr = Ar - Br, di = Ai - Bi;
-            // plus: conj(p) (A + B) (A alone past the S-list); minus: p (A - B)
-            o[0][2 * v] = srow ? fmaf(p.x, sr, p.y * si) : Ar;
-            o[0][2 * v + 1] = srow ? fmaf(p.x, si, -p.y * sr) : Ai;
-            o[1][2 * v] = fmaf(p.x, dr, -p.y * di);
-            o[1][2 * v + 1] = fmaf(p.x, di, p.y * dr);
-          } else {
-            o[0][2 * v] = Ar;
-            o[0][2 * v + 1] = Ai;
-          }
+          const int rs = RTC + r;
+          const float Br = ssgn[t] * (k1[t][rs][v] - k3[t][rs][v]), Bi = ssgn[t] * (k1[t][rs][v] + k2[t][rs][v]);
+          const int e = 16 * r + 4 * lk + v;
+          const bool srow = e < X.S;
+          const float2 p = srow ? sph[mrow[e]] : make_float2(1.f, 0.f);
+          const float sr = Ar + Br, si = Ai + Bi, dr = Ar - Br, di = Ai - Bi;
+          // plus: conj(p) (A + B) (A alone past the S-list); minus: p (A - B)
+          sout[(16 * t + li) * 17 + 4 * lk + v] =
+              f4v{srow ? fmaf(p.x, sr, p.y * si) : Ar, srow ? fmaf(p.x, si, -p.y * sr) : Ai,
+                  fmaf(p.x, dr, -p.y * di), fmaf(p.x, di, p.y * dr)};
+        }
+      }
+      lds_sync2();
+      store_lds(std::integral_constant<int, 16>{}, 32 * r, false, 16);
+      lds_sync2();
+    }
+    // the C-only tiles: rows of L^{n'0}
+#pragma unroll
+    for (int r = RTS; r < RTC; ++r) {
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) {
+        float o[8];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          o[2 * v] = k1[t][r][v] - k3[t][r][v];
+          o[2 * v + 1] = k1[t][r][v] + k2[t][r][v];
         }
         const int col = 16 * t + li;
-        sout[0][col * 8 + 2 * lk] = f4v{o[0][0], o[0][1], o[0][2], o[0][3]};      // rows 4 lk, 4 lk + 1
-        sout[0][col * 8 + 2 * lk + 1] = f4v{o[0][4], o[0][5], o[0][6], o[0][7]};  // rows 4 lk + 2, 4 lk + 3
-        if (pm) {
-          sout[1][col * 8 + 2 * lk] = f4v{o[1][0], o[1][1], o[1][2], o[1][3]};
-          sout[1][col * 8 + 2 * lk + 1] = f4v{o[1][4], o[1][5], o[1][6], o[1][7]};
-        }
+        sout[col * 9 + 2 * lk] = f4v{o[0], o[1], o[2], o[3]};      // rows 4 lk, 4 lk + 1
+        sout[col * 9 + 2 * lk + 1] = f4v{o[4], o[5], o[6], o[7]};  // rows 4 lk + 2, 4 lk + 3
       }
-      lds_sync();
-      if (pm) {
-        store_tile(2 * r, 0);
-        store_tile(2 * r + 1, 1);
-      } else {
-        store_tile(2 * RTS + (r - RTS), 0);
-      }
-      lds_sync();
+      lds_sync2();
+      const int first = 16 * (r - RTS), rows = xz_co_rows(P) - first < 16 ? xz_co_rows(P) - first : 16;
+      const int dst = xz_stage_pos(P, 16 * r, 1);
+      store_lds(std::integral_constant<int, 8>{}, rows == 16 ? dst : SM, rows != 16, (rows + 1) / 2);
+      lds_sync2();
     }
   }
 }
@@ -1063,12 +1068,13 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
 // L[t] = sum of t's staging slots in slot order (deterministic), each slot's
 // result mapped back by the output codes of its pair's reflection.  Items:
 // (instance, target cell); the cell's slots are [soff[t], soff[t+1]).  A
-// reflection sends the staging rows of (n', m') and (n', -m') onto the same
-// two coefficients (straight or exchanged), so thread j < S owns both
-// coefficients of S-list entry j and thread S + n' owns (n', 0): C threads,
-// one wave per target up to P = 10, each wave reading whole slots.  The
-// slots' reflections are staged in LDS per group of kRedGroup slots, and
-// the loads of U slots are in flight per thread.
+// reflection sends the staging positions of (n', m') and (n', -m') onto the
+// same two coefficients (straight or exchanged), and those positions are one
+// aligned 16-byte pair (xz_stage_pos): thread j < S owns both coefficients of
+// S-list entry j and reads the pair with one load, thread S + n' owns
+// (n', 0).  C threads, one wave per target up to P = 10.  The slots'
+// reflections are staged in LDS per group of kRedGroup slots, and the loads
+// of U slots are in flight per thread.
 constexpr int kRedGroup = 512;
 
 template <int P>
@@ -1115,49 +1121,43 @@ k_m2l_reduce(const int2* __restrict__ items, const InstDev* __restrict__ insts, 
     for (int e = tid; e < ng; e += nth) sgo[e] = (int)I.slot_g[g0 + e] * P2;
     __syncthreads();
     if (c0 >= 0) {
-      // row r of a slot: main part for r < SM, else the tail
+      // position r of a slot: main array for r < SM, else the tail
       gcfloat2* S = (gcfloat2*)(I.stage + (size_t)(g0 - slot_base) * SM);
       gcfloat2* T = (gcfloat2*)(I.stage_tail + (size_t)(g0 - slot_base) * ST) - SM;
       auto at = [&](int u, int r) { return r < SM ? S + (size_t)u * SM + r : T + (size_t)u * ST + r; };
+      // the aligned 16-byte pair holding position e (main and tail arrays
+      // both have an even count of positions per slot); c0 takes its half e
+      // & 1, c1 (if any) the other
+      auto pair_at = [&](int u, int e) {
+        return __builtin_nontemporal_load((const __attribute__((address_space(1))) f4v*)at(u, (e & 0xffff) & ~1));
+      };
+      auto add = [&](const f4v& w, int e, int f) {
+        const bool sw = e & 1;
+        const float2 x = apply_code(sw ? w.z : w.x, sw ? w.w : w.y, e);
+        const float2 y = apply_code(sw ? w.x : w.z, sw ? w.y : w.w, f);
+        ar += x.x;
+        ai += x.y;
+        br += y.x;  // unused by the (n', 0) threads
+        bi += y.y;
+      };
       int q = 0;
       constexpr int U = 12;  // slots in flight per thread, added in slot order
       for (; q + U <= ng; q += U, S += U * SM, T += U * ST) {
         int e[U], f[U];
-        float2 v[U], w[U];
+        f4v w[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           e[u] = som[sgo[q + u] + c0];
           f[u] = som[sgo[q + u] + c1r];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          v[u] = ld2_once(at(u, e[u] & 0xffff));
-          if (two) w[u] = ld2_once(at(u, f[u] & 0xffff));
-        }
+        for (int u = 0; u < U; ++u) w[u] = pair_at(u, e[u]);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const float2 x = apply_code(v[u].x, v[u].y, e[u]);
-          ar += x.x;
-          ai += x.y;
-          if (two) {
-            const float2 y = apply_code(w[u].x, w[u].y, f[u]);
-            br += y.x;
-            bi += y.y;
-          }
-        }
+        for (int u = 0; u < U; ++u) add(w[u], e[u], f[u]);
       }
       for (; q < ng; ++q, S += SM, T += ST) {
         const int e = som[sgo[q] + c0], f = som[sgo[q] + c1r];
-        const float2 v = ld2_once(at(0, e & 0xffff));
-        const float2 x = apply_code(v.x, v.y, e);
-        ar += x.x;
-        ai += x.y;
-        if (two) {
-          const float2 w = ld2_once(at(0, f & 0xffff));
-          const float2 y = apply_code(w.x, w.y, f);
-          br += y.x;
-          bi += y.y;
-        }
+        add(pair_at(0, e), e, f);
       }
     }
   }

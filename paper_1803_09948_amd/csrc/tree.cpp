@@ -464,8 +464,8 @@ void m2l_reflection_codes(int P, int Kp, std::vector<int32_t>& in, std::vector<i
 // the pair holding (n, 0) and the other is marked zero; for k >= C both.
 // Row 16 (columns past a chunk's end) has both marked zero.  Then 16 RTS
 // entries: m' of S-list output row r (0 past the list).  out: [16][P^2],
-// for target coefficient c = (n, m) under reflection g: the staging row of
-// the canonical (n, m') it comes from (xz_tile_dest) and the phase i^-ph
+// for target coefficient c = (n, m) under reflection g: the staging position
+// of the canonical (n, m') it comes from (xz_stage_pos) and the phase i^-ph
 // (swap bit 16, signs in bits 30, 31).
 void m2l_xz_codes(int P, std::vector<int32_t>& in, std::vector<int32_t>& out) {
   const XzDims d = xz_dims(P);
@@ -510,15 +510,13 @@ void m2l_xz_codes(int P, std::vector<int32_t>& in, std::vector<int32_t>& out) {
     if (r < d.S) xz_entry(P, r, &n, &m);
     mrow[r] = m;
   }
-  // staging row of each canonical coefficient (n, m')
+  // staging position of each canonical coefficient (n, m')
   std::vector<int32_t> srow(P2, -1);
   for (int e = 0; e < d.C; ++e) {
     int n, m;
     xz_entry(P, e, &n, &m);
-    const int r = e / 16;
-    const int plus = r < d.RTS ? 2 * r : 2 * d.RTS + (r - d.RTS);
-    srow[n * n + n + m] = xz_tile_dest(P, plus) + e % 16;
-    if (m > 0) srow[n * n + n - m] = xz_tile_dest(P, 2 * r + 1) + e % 16;
+    srow[n * n + n + m] = xz_stage_pos(P, e, 1);
+    if (m > 0) srow[n * n + n - m] = xz_stage_pos(P, e, -1);
   }
   out.assign(16 * (size_t)P2, 0);
   for (int g = 0; g < 16; ++g)
