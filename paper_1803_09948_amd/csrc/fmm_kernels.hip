@@ -757,7 +757,8 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
     lds_sync();
     // B gather: the aligned pair of float2 holding the two reflected
     // multipoles of each column's input (one 16-byte load when P^2 is even,
-    // so that every pair is 16-byte aligned, else two 8-byte loads) and the
+    // so that every pair is 16-byte aligned and inside the multipole, else
+    // two 8-byte loads) and the
     // input's phase (the same for every column: m depends on k only); the
     // loads issue now, codes and phases apply when the step runs
     auto load_b = [&](int k4, float2* rx, float2* ry, float2& rp, int* ce) {
@@ -771,8 +772,10 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
           rx[t] = make_float2(v.x, v.y);
           ry[t] = make_float2(v.z, v.w);
         } else {
+          // odd P^2: the pair of the last (n, 0) entry would end past the
+          // multipole; its high half is marked zero, so read the low one again
           rx[t] = ld2((gcfloat2*)(Mb + off));
-          ry[t] = ld2((gcfloat2*)(Mb + off + sizeof(float2)));
+          ry[t] = ld2((gcfloat2*)(Mb + off + ((e & 0xff) + 1 < P2 ? sizeof(float2) : 0)));
         }
       }
       rp = sph[(ce[0] >> 9) & 15];
@@ -1539,13 +1542,13 @@ static void launch_m2l_t(const int4* chunks, int nchunks, int sub, const InstDev
 int m2l_pairs_per_chunk(int P) { return xz_dims(P).RT <= 7 ? 32 : 16; }
 
 // Launch shapes (all give the same bits).  With 32-pair chunks:
-//   0: one wave per chunk (two column tiles), tables two k-steps ahead;
+//   0: one wave per chunk (two column tiles), tables one k-step ahead;
 //   1: one wave per 16-pair column tile (smaller register budget, more
 //      waves per SIMD), tables one step ahead;
-//   2, 3: shape 0 with each wave running 2 or 4 consecutive chunks, tables
-//      one step ahead (the register budget of two prefetch steps leaves no
-//      room for the second chunk's state).
-// With 16-pair chunks: one wave per chunk running 1, 2 or 4 chunks.
+//   2, 3: shapes 0 and 1 with the tables two k-steps ahead.
+// (Waves running several chunks each spill registers in the two-tile
+// shape.)  With 16-pair chunks: one wave per chunk running 1, 2 or 4
+// chunks.
 int m2l_variant_count(int P) { return m2l_pairs_per_chunk(P) == 32 ? 4 : 3; }
 
 // waves per SIMD of the one-tile shape: accumulators and A buffers take
@@ -1560,8 +1563,8 @@ static void launch_m2l_p(int variant, int sub, const int4* chunks, int nchunks, 
     if (sub == 2) {
       switch (variant) {
         case 1: return launch_m2l_t<P, 1, NW, 1, 1>(chunks, nchunks, 2, insts, bmap, s);
-        case 2: return launch_m2l_t<P, 2, 2, 2, 1>(chunks, nchunks, 1, insts, bmap, s);
-        case 3: return launch_m2l_t<P, 2, 2, 4, 1>(chunks, nchunks, 1, insts, bmap, s);
+        case 2: return launch_m2l_t<P, 2, 2, 1, 2>(chunks, nchunks, 1, insts, bmap, s);
+        case 3: return launch_m2l_t<P, 1, NW, 1, 2>(chunks, nchunks, 2, insts, bmap, s);
         default: return launch_m2l_t<P, 2, 2, 1, 1>(chunks, nchunks, 1, insts, bmap, s);
       }
     }

@@ -63,7 +63,46 @@ static void point_work(const std::vector<float>& xyz, int64_t n, double k, int P
   hfmm_tree_free(t);
 }
 
+// The matrix-core M2L's code tables (library internals, host side): for every
+// order, each reflection maps the P^2 target coefficients to distinct
+// staging positions inside a slot, and every input code addresses an
+// aligned pair inside a multipole (the builder checks that x and y are one
+// pair and throws otherwise).
+namespace hfmm {
+void m2l_xz_codes(int P, std::vector<int32_t>& in, std::vector<int32_t>& out);
+void stage_dims(int P, int* Sm, int* St);
+}  // namespace hfmm
+
+static void code_tables() {
+  for (int P = 1; P <= 16; ++P) {
+    std::vector<int32_t> in, out;
+    hfmm::m2l_xz_codes(P, in, out);
+    int Sm = 0, St = 0;
+    hfmm::stage_dims(P, &Sm, &St);
+    const int P2 = P * P;
+    CHECK((int)out.size() == 16 * P2);
+    CHECK(Sm + St >= P2 && Sm % 16 == 0 && St % 2 == 0);
+    for (int g = 0; g < 16; ++g) {
+      std::vector<char> seen(Sm + St, 0);
+      for (int c = 0; c < P2; ++c) {
+        const int pos = out[(size_t)g * P2 + c] & 0xffff;
+        CHECK(pos >= 0 && pos < Sm + St && !seen[pos]);
+        if (pos >= 0 && pos < Sm + St) seen[pos] = 1;
+      }
+    }
+    // the input codes ([17][stride], then 16 ceil(S/16) m' entries): an even
+    // base inside the multipole, and for even P^2 the whole pair inside it
+    const int S = P * (P - 1) / 2, mrows = 16 * ((S + 15) / 16);
+    CHECK((in.size() - mrows) % 17 == 0);
+    for (size_t i = 0; i + mrows < in.size(); ++i) {
+      const int base = in[i] & 0xff;
+      CHECK(base % 2 == 0 && base < P2 && (P2 % 2 == 1 || base + 1 < P2));
+    }
+  }
+}
+
 int main(int argc, char** argv) {
+  code_tables();
   if (argc != 6) {
     std::fprintf(stderr, "usage: host_driver points.f32 ico.f64 ico.i32 curved.f64 curved.i32\n");
     return 2;

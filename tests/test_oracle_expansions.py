@@ -146,3 +146,49 @@ def test_m2p_equals_direct_sum_far_from_the_sources():
     # a dropped factor (ik) or a conjugated multipole would be O(1) wrong
     M = ex.p2m(12, k, c, ys, q)
     assert np.linalg.norm(ex.m2p(12, k, c, np.conj(M), xt) - ref) > 0.1 * np.linalg.norm(ref)
+
+
+def _m_of(P):
+    return np.array([m for n in range(P) for m in range(-n, n + 1)])
+
+
+@pytest.mark.parametrize("t,k,P", [((1.1, 0.6, -0.9), 2.5, 7), ((-0.4, 1.3, 0.8), 6.0, 9),
+                                   ((0.0, 0.0, 1.5), 3.0, 6), ((2.0, -2.0, 0.0), 1.0, 8)])
+def test_translation_turned_into_the_xz_plane(t, k, P):
+    """The M2L translation (S|R)(t) of eq. (14) equals D^-1 (S|R)(t') D with
+    t' = t turned about the z axis into the xz-plane and D = diag(e^{i m
+    phi}), phi the azimuth of t; (S|R)(t') commutes with the exchange
+    m <-> -m, so it splits into a block on M^m + M^-m (m >= 0) and one on
+    M^m - M^-m (m > 0) whose sizes are P(P+1)/2 and P(P-1)/2."""
+    t = np.asarray(t, np.float64)
+    phi = np.arctan2(t[1], t[0])
+    tp = np.array([np.hypot(t[0], t[1]), 0.0, t[2]])
+    T = ex.sr_matrix(t, k, P)
+    Tp = ex.sr_matrix(tp, k, P)
+    D = np.diag(np.exp(1j * _m_of(P) * phi))
+    assert np.abs(np.linalg.inv(D) @ Tp @ D - T).max() <= 1e-13 * np.abs(T).max()
+    # the exchange m <-> -m
+    Pi = np.zeros((P * P, P * P))
+    for n in range(P):
+        for m in range(-n, n + 1):
+            Pi[n * n + n - m, n * n + n + m] = 1.0
+    assert np.abs(Pi @ Tp - Tp @ Pi).max() <= 1e-14 * np.abs(Tp).max()
+    # the symmetric and antisymmetric bases split (S|R)(t') into two blocks
+    sym, anti = [], []
+    for n in range(P):
+        for m in range(0, n + 1):
+            u = np.zeros(P * P)
+            u[n * n + n + m] += 1.0
+            u[n * n + n - m] += 1.0
+            sym.append(u / np.linalg.norm(u))
+            if m > 0:
+                v = np.zeros(P * P)
+                v[n * n + n + m] = 1.0
+                v[n * n + n - m] = -1.0
+                anti.append(v / np.sqrt(2.0))
+    B = np.array(sym + anti).T             # orthogonal change of basis
+    Tb = B.T @ Tp @ B
+    ns = len(sym)
+    assert ns == P * (P + 1) // 2 and len(anti) == P * (P - 1) // 2
+    off = max(np.abs(Tb[:ns, ns:]).max(), np.abs(Tb[ns:, :ns]).max())
+    assert off <= 1e-13 * np.abs(Tb).max()
