@@ -143,8 +143,8 @@ struct InstDev {
   float2* M;                // multipoles [ncell][P^2]
   float2* L;                // locals [ncell][P^2]
   const int4* m2l_pairs;    // (target, source, reflection, staging slot)
-  float2* stage;            // M2L staging [slots][Sm] (canonical frame), slots ordered by target
-  float2* stage_tail;       // the last St rows of each slot [slots][St] (see stage_dims)
+  float2* stage;            // M2L staging [slots][Sm] (reflected frame, xz_stage_pos), slots ordered by target
+  float2* stage_tail;       // the tail positions of each slot [slots][St] (see stage_dims)
   const uint8_t* slot_g;    // per staging slot: reflection of its pair
   const int32_t* m2l_soff;  // per cell: first staging slot (ncell + 1 entries)
   const int4* p2p_work;     // (tgt begin, tgt end, interval begin, interval end)

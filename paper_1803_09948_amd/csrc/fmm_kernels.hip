@@ -617,11 +617,11 @@ __global__ void __launch_bounds__(64) k_p2m(const int2* __restrict__ items, cons
 // blocks (XzDims; together about half the P^2 x P^2 complex entries of the
 // full operator).  The B matrix (k = input entry, column = pair) is gathered
 // straight from the multipoles through the pair's reflection codes and
-// turned by the pair's azimuth phase; the table streams from memory as the
-// A matrix (row = output entry), with A and B prefetched ahead.  Each pair's
-// result goes, in the reflected frame, to the pair's staging slot (the
-// reduction maps it back); the only LDS is the code table and two 2 KiB
-// output tiles per 16 columns.  Blocks are mapped so that each XCD walks a
+// turned by the operator's azimuth phase; the table streams from memory as
+// the A matrix (row = output entry), with A and B prefetched ahead.  Each
+// pair's result goes, in the reflected frame, to the pair's staging slot
+// (the reduction maps it back); the LDS holds the code table, the
+// operator's phases and one output tile.  Blocks are mapped so that each XCD walks a
 // contiguous range of chunks (sorted by operator), keeping an operator's
 // table in that XCD's L2 while its chunks run.
 //
@@ -647,12 +647,6 @@ __device__ inline float2 ld2(gcfloat2* p) {
   const f2v v = *p;
   return make_float2(v.x, v.y);
 }
-// load of data read once (non-temporal: no reuse expected in the caches)
-__device__ inline float2 ld2_once(gcfloat2* p) {
-  const f2v v = __builtin_nontemporal_load(p);
-  return make_float2(v.x, v.y);
-}
-
 // i^ph (x + iy) for a reflection code (swap bit 16, sign of the real part
 // bit 31, of the imaginary part bit 30).
 __device__ inline float2 apply_code(float x0, float y0, int e) {
@@ -660,14 +654,6 @@ __device__ inline float2 apply_code(float x0, float y0, int e) {
   const float x = swap ? y0 : x0, y = swap ? x0 : y0;
   return make_float2(__int_as_float(__float_as_int(x) ^ (e & (int)0x80000000)),
                      __int_as_float(__float_as_int(y) ^ ((e << 1) & (int)0x80000000)));
-}
-
-// Branch-free multiply by i^code.
-__device__ inline float2 mul_ipow_sel(float2 a, int code) {
-  const bool sw = code & 1;
-  const float x = sw ? a.y : a.x, y = sw ? a.x : a.y;
-  const bool nx = (code == 1) | (code == 2), ny = code >= 2;
-  return make_float2(nx ? -x : x, ny ? -y : y);
 }
 
 // One wave per item; an item is column group h < sub of chunk item / sub,
