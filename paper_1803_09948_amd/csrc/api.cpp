@@ -821,16 +821,16 @@ int hfmm_phase_times(const hfmm_tree* tree, float* ms10) {
 }
 
 int hfmm_variant_count(int32_t phase, int32_t P) {
-  if (phase != kPhaseM2L) return set_error("unknown tuned phase"), HFMM_EINVAL;
+  if (phase < 0 || phase >= kNumTunedPhases) return set_error("unknown tuned phase"), HFMM_EINVAL;
   if (P < 1 || P > kMaxP) return set_error("P must be in [1, 16]"), HFMM_EINVAL;
-  return m2l_variant_count(P);
+  return phase_variant_count(phase, P);
 }
 
 int hfmm_set_variant(int32_t phase, int32_t variant) { return set_variant_override(phase, variant); }
 
 int hfmm_tree_variant(hfmm_tree* tree, double k, int32_t P, int32_t phase, int32_t* variant) {
   if (!tree || !variant) return set_error("NULL argument"), HFMM_EINVAL;
-  if (phase != kPhaseM2L) return set_error("unknown tuned phase"), HFMM_EINVAL;
+  if (phase < 0 || phase >= kNumTunedPhases) return set_error("unknown tuned phase"), HFMM_EINVAL;
   Tree& t = *reinterpret_cast<Tree*>(tree);
   uint64_t kb;
   std::memcpy(&kb, &k, 8);

@@ -227,8 +227,11 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
 // run on `s`; L2P waits for P2P and adds the far field to its sums; scatter.
 // P2P and L2P each add into ys in this order on both paths.  With `ev`
 // (phase timing) everything runs on `s`, one phase after another, and the
-// events bracket the phases.
-static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
+// events bracket the phases.  Without `io` the gather from the caller's
+// vectors and the scatter into them are left out (the autotuner's runs, which
+// may come before any caller vector is bound; every other step reads and
+// writes only the batch's own buffers).
+static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev, bool io = true) {
   const InstDev* I = b.d_inst.as<InstDev>();
   const int P = b.P;
   const Plan& p0 = *b.plans[0];
@@ -239,12 +242,12 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   int rc;
   if ((rc = mark(0))) return rc;
   launch_zero(b.d_zero.as<int2>(), b.n_zero, I, s);
-  launch_gather(b.d_gather.as<int2>(), b.n_gather, I, s);
+  if (io) launch_gather(b.d_gather.as<int2>(), b.n_gather, I, s);
   const bool fork = !ev;
   if (fork) {
     HIP_TRY(hipEventRecord(b.ev_fork, s));
     HIP_TRY(hipStreamWaitEvent(b.side, b.ev_fork, 0));
-    launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, b.side);
+    launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, batch_variant(b, kPhaseP2P), b.side);
     HIP_TRY(hipEventRecord(b.ev_join, b.side));
   }
   launch_p2m(b.d_p2m.as<int2>(), b.n_p2m, I, P, b.damped, s);
@@ -286,28 +289,39 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev) {
   if (fork) {
     HIP_TRY(hipStreamWaitEvent(s, b.ev_join, 0));
   } else {
-    launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, s);
+    launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, batch_variant(b, kPhaseP2P), s);
   }
   if ((rc = mark(6))) return rc;
   launch_l2p(b.d_l2p.as<int2>(), b.n_l2p, I, P, b.damped, s);
   if ((rc = mark(7))) return rc;
-  launch_scatter(b.d_scatter.as<int2>(), b.n_scatter, I, s);
+  if (io) launch_scatter(b.d_scatter.as<int2>(), b.n_scatter, I, s);
   HIP_TRY(hipGetLastError());
   return HFMM_OK;
 }
 
 // ---------------------------------------------------------------------------
 // Autotuner.  Shapes of a phase compute identical results; the first run of
-// a batch times every shape of the phase on the batch's own work (eagerly,
-// outside any capture: M2L only writes its staging slots, which the real
-// sequence overwrites) and keeps the fastest.  Choices are cached per
-// (phase, P, log2 of the work size), so rebuilt batches of similar size do
-// not time again.
+// a batch times every shape of each phase on the batch's own work (eagerly,
+// outside any capture) and keeps the fastest.  The M2L shapes are timed
+// alone (the M2L only writes its staging slots, which the real sequence
+// overwrites).  The P2P runs beside the far field, and a shape that is
+// faster alone can share the GPU worse, so its shapes are timed inside the
+// whole sequence without the caller's vectors (sequence with io off; the
+// real sequence clears what those runs wrote).  Choices are cached per
+// (phase, P, log2 of the phase's work items), so rebuilt batches of similar
+// size do not time again.
 // ---------------------------------------------------------------------------
-static std::atomic<int> g_override[kNumTunedPhases] = {{-1}};
+static std::atomic<int> g_override[kNumTunedPhases] = {{-1}, {-1}};
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, int> g_tuned;
 static bool g_tuned_loaded = false;
+
+int phase_variant_count(int phase, int P) {
+  if (P < 1 || P > kMaxP) return 0;
+  if (phase == kPhaseM2L) return m2l_variant_count(P);
+  if (phase == kPhaseP2P) return p2p_variant_count();
+  return 0;
+}
 
 // Persistent choices: with HFMM_TUNE_CACHE naming a file, the choices are
 // read from it once (lines "phase P log2size variant") and every new choice
@@ -326,7 +340,7 @@ static void tune_cache_load() {
   if (!f) return;
   int ph, P, lg, v;
   while (std::fscanf(f, "%d %d %d %d", &ph, &P, &lg, &v) == 4)
-    if (ph >= 0 && ph < kNumTunedPhases && P >= 1 && P <= kMaxP && v >= 0 && v < m2l_variant_count(P))
+    if (ph >= 0 && ph < kNumTunedPhases && v >= 0 && v < phase_variant_count(ph, P))
       g_tuned[std::make_tuple(ph, P, lg)] = v;
   std::fclose(f);
 }
@@ -347,41 +361,44 @@ int set_variant_override(int phase, int variant) {
 
 int batch_variant(const Batch& b, int phase) {
   const int o = g_override[phase].load();
-  if (phase == kPhaseM2L && o >= 0 && o < m2l_variant_count(b.P)) return o;
-  return b.m2l_variant < 0 ? 0 : b.m2l_variant;
+  if (o >= 0 && o < phase_variant_count(phase, b.P)) return o;
+  return b.variant[phase] < 0 ? 0 : b.variant[phase];
 }
 
-static int tune_batch(Batch& b, hipStream_t s) {
-  const int nv = m2l_variant_count(b.P);
-  if (b.m2l_variant >= 0 || g_override[kPhaseM2L].load() >= 0) return HFMM_OK;
-  if (nv <= 1 || b.n_m2l == 0) {
-    b.m2l_variant = 0;
+// Times the shapes of one phase (launch(v) enqueues work that runs shape v
+// of the phase on s and returns a status): one warm-up round, then `timed`
+// rounds, each shape scored by its fastest round; records the fastest shape
+// in b.variant[phase].
+template <class Launch>
+static int tune_phase(Batch& b, int phase, int nwork, int timed, Launch launch, hipStream_t s) {
+  const int nv = phase_variant_count(phase, b.P);
+  if (b.variant[phase] >= 0 || g_override[phase].load() >= 0) return HFMM_OK;
+  if (nv <= 1 || nwork == 0) {
+    b.variant[phase] = 0;
     return HFMM_OK;
   }
   int lg = 0;
-  while ((1 << (lg + 1)) <= b.n_m2l) ++lg;
-  const auto key = std::make_tuple((int)kPhaseM2L, b.P, lg);
+  while ((1 << (lg + 1)) <= nwork) ++lg;
+  const auto key = std::make_tuple(phase, b.P, lg);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache_load();
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
-      b.m2l_variant = it->second;
+      b.variant[phase] = it->second;
       return HFMM_OK;
     }
   }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  const InstDev* I = b.d_inst.as<InstDev>();
-  float best = 0.f;
-  int pick = 0;
+  std::vector<float> score(nv, 0.f);
   int rc = HFMM_OK;
-  for (int rep = 0; rep < 2 && rc == HFMM_OK; ++rep)  // the first round warms caches and code
+  for (int rep = 0; rep <= timed && rc == HFMM_OK; ++rep)  // the first round warms caches and code
     for (int v = 0; v < nv; ++v) {
       hipError_t e = hipEventRecord(e0, s);
       if (e == hipSuccess) {
-        launch_m2l(b.d_m2l.as<int4>(), b.m2l_seg_off[1], I, b.plans[0]->d_bmap.as<int32_t>(), b.P, v, s);
+        if ((rc = launch(v))) break;
         e = hipGetLastError();
       }
       if (e == hipSuccess) e = hipEventRecord(e1, s);
@@ -393,24 +410,43 @@ static int tune_batch(Batch& b, hipStream_t s) {
         rc = HFMM_EHIP;
         break;
       }
-      if (rep == 1 && (v == 0 || ms < best)) {
-        best = ms;
-        pick = v;
-      }
+      if (rep == 1 || (rep > 1 && ms < score[v])) score[v] = ms;
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  b.m2l_variant = pick;
+  int pick = 0;
+  for (int v = 1; v < nv; ++v)
+    if (score[v] < score[pick]) pick = v;
+  b.variant[phase] = pick;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned[key] = pick;
-  tune_cache_append(kPhaseM2L, b.P, lg, pick);
+  tune_cache_append(phase, b.P, lg, pick);
   return HFMM_OK;
 }
 
-int ready_batch(Batch& b, hipStream_t s) {
-  int rc = tune_batch(b, s);
+static int tune_batch(Batch& b, hipStream_t s) {
+  const InstDev* I = b.d_inst.as<InstDev>();
+  int rc = tune_phase(
+      b, kPhaseM2L, b.n_m2l, 1,
+      [&](int v) {
+        launch_m2l(b.d_m2l.as<int4>(), b.m2l_seg_off[1], I, b.plans[0]->d_bmap.as<int32_t>(), b.P, v, s);
+        return (int)HFMM_OK;
+      },
+      s);
   if (rc) return rc;
+  return tune_phase(
+      b, kPhaseP2P, b.n_p2p, 2,
+      [&](int v) {
+        b.variant[kPhaseP2P] = v;
+        const int r = sequence(b, s, nullptr, false);
+        b.variant[kPhaseP2P] = -1;
+        return r;
+      },
+      s);
+}
+
+int ready_batch(Batch& b, hipStream_t s) {
   if (!b.side) {
     HIP_TRY(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&b.ev_fork, hipEventDisableTiming));
@@ -426,7 +462,7 @@ int ready_batch(Batch& b, hipStream_t s) {
       b.ev_red.push_back(e2);
     }
   }
-  return HFMM_OK;
+  return tune_batch(b, s);
 }
 
 int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t s, bool use_graph,
@@ -450,7 +486,9 @@ int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t 
     HIP_TRY(hipEventCreateWithFlags(&b.ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&b.ev_out, hipEventDisableTiming));
   }
-  if (b.exec && b.graph_m2l_variant != batch_variant(b, kPhaseM2L)) {  // shape forced since capture
+  bool stale = false;  // a shape forced since capture
+  for (int ph = 0; ph < kNumTunedPhases; ++ph) stale = stale || b.graph_variant[ph] != batch_variant(b, ph);
+  if (b.exec && stale) {
     (void)hipGraphExecDestroy(b.exec);
     (void)hipGraphDestroy(b.graph);
     b.exec = nullptr;
@@ -458,7 +496,7 @@ int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t 
   }
   if (!b.exec) {
     HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
-    b.graph_m2l_variant = batch_variant(b, kPhaseM2L);
+    for (int ph = 0; ph < kNumTunedPhases; ++ph) b.graph_variant[ph] = batch_variant(b, ph);
     rc = sequence(b, b.stream, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b.stream, &g);

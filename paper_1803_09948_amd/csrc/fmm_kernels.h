@@ -175,7 +175,9 @@ void launch_p2m(const int2* items, int n, const InstDev* insts, int P, bool damp
 void launch_m2m(const int4* items, int n, const int32_t* cols, const InstDev* insts, int P, hipStream_t s);
 void launch_l2l(const int4* items, int n, const int32_t* cols, const InstDev* insts, int P, hipStream_t s);
 void launch_l2p(const int2* items, int n, const InstDev* insts, int P, bool damped, hipStream_t s);
-void launch_p2p(const int2* items, int n, const InstDev* insts, bool damped, hipStream_t s);
+// variant < p2p_variant_count() selects the launch shape (results are identical)
+int p2p_variant_count();
+void launch_p2p(const int2* items, int n, const InstDev* insts, bool damped, int variant, hipStream_t s);
 int m2l_pairs_per_chunk(int P);
 // chunks: (instance, op, pair begin, pair end), sorted by (instance, op)
 // L[t] = sum of the staging slots of t, each mapped back by its reflection's

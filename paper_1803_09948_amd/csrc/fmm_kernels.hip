@@ -1284,12 +1284,17 @@ __device__ inline void p2p_pair(float xx, float xy, float xz, float4 yj, float2 
 }
 
 // Targets [t0, t0 + tc) of the leaf against all its sources, T per lane.
-template <int T, bool DAMP>
-__device__ inline void p2p_block(const InstDev& I, int4 wk, int total, int t0, int tc, int lane, float4 (*sp)[64],
-                                 float2 (*sq)[64], float2* red, float krev, float kdec) {
+// A tile holds TS stages of L sources (lane l < L loads source u L + l of
+// stage u); since L is a multiple of the split count, split s still takes
+// the sources whose index is s modulo the split count, in increasing order,
+// so every TS gives the same sums bit for bit.
+template <int T, int TS, bool DAMP>
+__device__ inline void p2p_block(const InstDev& I, int4 wk, int total, int t0, int tc, int lane,
+                                 float4 (*sp)[64 * TS], float2 (*sq)[64 * TS], float2* red, float krev, float kdec) {
   const int ng = (tc + T - 1) / T;            // target groups
   const int nsplit = 64 / ng;
-  const int L = nsplit * (64 / nsplit);       // sources per tile
+  const int L = nsplit * (64 / nsplit);       // sources per stage
+  const int LT = TS * L;                      // sources per tile
   const int g = lane % ng, s = lane / ng;
   const bool active = s < nsplit;
   float xx[T], xy[T], xz[T], ar[T], ai[T];
@@ -1304,21 +1309,34 @@ __device__ inline void p2p_block(const InstDev& I, int4 wk, int total, int t0, i
   }
   const int2* __restrict__ ivals = I.p2p_ivals;
   int iv = wk.z, off = 0;
-  float4 np4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  float2 nq = make_float2(0.f, 0.f);
-  if (lane < L) p2p_fetch(ivals, iv, wk.w, off, lane, I.spos, I.q, np4, nq);
+  float4 np4[TS];
+  float2 nq[TS];
+#pragma unroll
+  for (int u = 0; u < TS; ++u) {
+    np4[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    nq[u] = make_float2(0.f, 0.f);
+    if (lane < L) p2p_fetch(ivals, iv, wk.w, off + u * L, lane, I.spos, I.q, np4[u], nq[u]);
+  }
   int tile = 0;
-  for (int base = 0; base < total; base += L, ++tile) {
-    const int nj = min(L, total - base);
+  for (int base = 0; base < total; base += LT, ++tile) {
+    const int nj = min(LT, total - base);
     const int buf = tile & 1;
-    sp[buf][lane] = np4;
-    sq[buf][lane] = nq;
-    off += L;
+    if (lane < L) {
+#pragma unroll
+      for (int u = 0; u < TS; ++u) {
+        sp[buf][u * L + lane] = np4[u];
+        sq[buf][u * L + lane] = nq[u];
+      }
+    }
+    off += LT;
     while (iv < wk.w && off >= ivals[iv].y - ivals[iv].x) {
       off -= ivals[iv].y - ivals[iv].x;
       ++iv;
     }
-    if (base + L < total && lane < L) p2p_fetch(ivals, iv, wk.w, off, lane, I.spos, I.q, np4, nq);
+    if (base + LT < total && lane < L) {
+#pragma unroll
+      for (int u = 0; u < TS; ++u) p2p_fetch(ivals, iv, wk.w, off + u * L, lane, I.spos, I.q, np4[u], nq[u]);
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1358,15 +1376,16 @@ __device__ inline void p2p_block(const InstDev& I, int4 wk, int total, int t0, i
 }
 
 // DAMP: complex wavenumber k + i ki, G times the decay e^{-ki R} (the
-// imaginary wavenumber of the listing's exponential).
-template <bool DAMP>
-__global__ void __launch_bounds__(256) k_p2p(const int2* __restrict__ items, int nitems,
-                                             const InstDev* __restrict__ insts) {
+// imaginary wavenumber of the listing's exponential).  W waves per block,
+// one leaf block per wave; TS source stages per tile (p2p_block).
+template <bool DAMP, int W, int TS>
+__global__ void __launch_bounds__(64 * W) k_p2p(const int2* __restrict__ items, int nitems,
+                                                const InstDev* __restrict__ insts) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int w = blockIdx.x * 4 + wave;
-  __shared__ float4 sp[4][2][64];
-  __shared__ float2 sq[4][2][64];
-  __shared__ float2 red[4][64 * 4];
+  const int w = blockIdx.x * W + wave;
+  __shared__ float4 sp[W][2][64 * TS];
+  __shared__ float2 sq[W][2][64 * TS];
+  __shared__ float2 red[W][64 * 4];
   if (w >= nitems) return;
   const int2 it = items[w];
   const InstDev& I = insts[it.x];
@@ -1377,10 +1396,10 @@ __global__ void __launch_bounds__(256) k_p2p(const int2* __restrict__ items, int
   for (int t0 = wk.x; t0 < wk.y; t0 += 64) {
     const int tc = min(64, wk.y - t0);
     switch (p2p_targets_per_lane(tc)) {
-      case 1: p2p_block<1, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
-      case 2: p2p_block<2, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
-      case 3: p2p_block<3, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
-      default: p2p_block<4, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
+      case 1: p2p_block<1, TS, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
+      case 2: p2p_block<2, TS, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
+      case 3: p2p_block<3, TS, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
+      default: p2p_block<4, TS, DAMP>(I, wk, total, t0, tc, lane, sp[wave], sq[wave], red[wave], krev, kdec); break;
     }
   }
 }
@@ -1504,12 +1523,33 @@ void launch_m2l_reduce(const int2* items, int n, const InstDev* insts, const int
     default: break;
   }
 }
-void launch_p2p(const int2* items, int n, const InstDev* insts, bool damped, hipStream_t s) {
+// P2P launch shapes (all give the same bits): waves per block and source
+// stages per tile.
+//   0: 4 waves, 1 stage;  1: 1 wave, 1 stage;  2: 4 waves, 2 stages;
+//   3: 1 wave, 2 stages.
+int p2p_variant_count() { return 4; }
+
+template <bool DAMP, int W, int TS>
+static void launch_p2p_t(const int2* items, int n, const InstDev* insts, hipStream_t s) {
+  k_p2p<DAMP, W, TS><<<(n + W - 1) / W, 64 * W, 0, s>>>(items, n, insts);
+}
+
+template <bool DAMP>
+static void launch_p2p_d(const int2* items, int n, const InstDev* insts, int variant, hipStream_t s) {
+  switch (variant) {
+    case 1: return launch_p2p_t<DAMP, 1, 1>(items, n, insts, s);
+    case 2: return launch_p2p_t<DAMP, 4, 2>(items, n, insts, s);
+    case 3: return launch_p2p_t<DAMP, 1, 2>(items, n, insts, s);
+    default: return launch_p2p_t<DAMP, 4, 1>(items, n, insts, s);
+  }
+}
+
+void launch_p2p(const int2* items, int n, const InstDev* insts, bool damped, int variant, hipStream_t s) {
   if (n <= 0) return;
   if (damped)
-    k_p2p<true><<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
+    launch_p2p_d<true>(items, n, insts, variant, s);
   else
-    k_p2p<false><<<(n + 3) / 4, 256, 0, s>>>(items, n, insts);
+    launch_p2p_d<false>(items, n, insts, variant, s);
 }
 
 template <int P, int NCT, int WPE, int CPW, int AD>

@@ -185,6 +185,9 @@ struct Plan64 {
 };
 
 // Fused execution of one or more instances (instance-aware kernels).
+// Launch-shape autotuning phases: the M2L matrix-core kernel and the P2P.
+enum { kPhaseM2L = 0, kPhaseP2P = 1, kNumTunedPhases = 2 };
+
 struct Batch {
   int count = 0, P = 0, maxlev = 0;
   bool damped = false;                // some instance has a complex wavenumber
@@ -207,8 +210,8 @@ struct Batch {
   std::vector<hipEvent_t> ev_m2l, ev_red;  // per segment: its M2L done, its reduction done
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int m2l_variant = -1;               // launch shape chosen by the autotuner
-  int graph_m2l_variant = -1;         // shape captured in the graph
+  int variant[kNumTunedPhases] = {-1, -1};        // launch shapes chosen by the autotuner
+  int graph_variant[kNumTunedPhases] = {-1, -1};  // shapes captured in the graph
   bool ran = false;                   // has run at least once
   ~Batch();
 };
@@ -216,10 +219,10 @@ struct Batch {
 int build_batch(const std::vector<struct Tree*>& trees, const std::vector<Plan*>& plans, Batch& b);
 // Launch-shape autotuning: forced shape per phase (-1: tuned), the shape a
 // batch uses, and the per-phase shape counts.
-enum { kPhaseM2L = 0, kNumTunedPhases = 1 };
+int phase_variant_count(int phase, int P);
 int set_variant_override(int phase, int variant);
 int batch_variant(const Batch& b, int phase);
-// First-use setup of a batch: the autotuned launch shape (times the shapes on
+// First-use setup of a batch: the autotuned launch shapes (times the shapes on
 // the batch's own work), the side stream and its events.  run_batch calls it;
 // calling it earlier keeps that work out of the first product.
 int ready_batch(Batch& b, hipStream_t s);

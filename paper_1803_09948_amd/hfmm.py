@@ -347,7 +347,8 @@ class Tree:
         return v.value
 
 
-PHASE_M2L = 0
+PHASE_M2L = 0   # tuned phases: the M2L matrix-core kernel
+PHASE_P2P = 1   # and the P2P near-field kernel
 
 
 def direct64(src, q, tgt, k, stream=None):

@@ -148,6 +148,36 @@ def test_m2l_launch_shapes_bit_identical(P):
     np.testing.assert_array_equal(y, outs[0])
 
 
+def test_p2p_launch_shapes_bit_identical():
+    """Every launch shape of the P2P (waves per block, source stages per LDS
+    tile) gives the same bits, for a point handle with leaves of ragged sizes,
+    a damped one and a BIE handle; the autotuner reports the shape used."""
+    n, k, P = 20000, 12.0, 8
+    x = synth.sphere_points(n, 32)
+    q = torch.from_numpy(synth.strengths(n, 32)).to("cuda")
+    nv = hfmm.variant_count(P, hfmm.PHASE_P2P)
+    assert nv >= 2
+    V, T = synth.icosphere(4)
+    qb = torch.from_numpy(synth.strengths(len(T), 34)).to("cuda")
+    cases = [(hfmm.Tree.from_points(x, ncrit=48), k, q), (hfmm.Tree.from_points(x, k_imag=0.5), k, q),
+             (hfmm.Tree.from_mesh(V, T), 6.0, qb)]
+    for t, kk, qq in cases:
+        outs = []
+        try:
+            for v in range(nv):
+                hfmm.set_variant(v, hfmm.PHASE_P2P)
+                outs.append(t.matvec(kk, P, qq).cpu().numpy())
+                assert t.variant(kk, P, hfmm.PHASE_P2P) == v
+        finally:
+            hfmm.set_variant(-1, hfmm.PHASE_P2P)
+        for v, o in enumerate(outs[1:], 1):
+            np.testing.assert_array_equal(o, outs[0], err_msg=f"P2P shape {v}")
+    t2 = hfmm.Tree.from_points(x, ncrit=48)
+    y = t2.matvec(k, P, q).cpu().numpy()
+    assert 0 <= t2.variant(k, P, hfmm.PHASE_P2P) < nv
+    assert np.array_equal(y, hfmm.Tree.from_points(x, ncrit=48).matvec(k, P, q).cpu().numpy())
+
+
 def test_m2l_staging_segments_bit_identical():
     """A staging budget far below the M2L's needs splits the M2L and its
     reduction into many target segments; results are the same bits."""
@@ -184,9 +214,10 @@ def test_overlapped_and_serial_sequences_bit_identical():
 
 
 def test_autotune_cache_file(tmp_path):
-    """HFMM_TUNE_CACHE: a first process times the M2L shapes and appends its
-    choice to the file; a later process takes the shape from the file
-    without timing (shown by editing the file to another valid shape)."""
+    """HFMM_TUNE_CACHE: a first process times the M2L and P2P shapes and
+    appends its choices to the file (one line per phase); a later process
+    takes the shapes from the file without timing (shown by editing the
+    file to other valid shapes)."""
     import os
     import subprocess
     import sys
@@ -199,18 +230,22 @@ def test_autotune_cache_file(tmp_path):
             "q = torch.from_numpy(synth.strengths(20000, 31)).cuda()\n"
             "t = hfmm.Tree.from_points(x)\n"
             "t.matvec(12.0, 10, q)\n"
-            "print('variant', t.variant(12.0, 10))\n") % root
+            "print('variant', t.variant(12.0, 10, 0), t.variant(12.0, 10, 1))\n") % root
     env = dict(os.environ, HFMM_TUNE_CACHE=cache)
 
     def run():
         r = subprocess.run([sys.executable, "-c", prog], capture_output=True, text=True, env=env, timeout=240)
         assert r.returncode == 0, r.stderr[-2000:]
-        return int(r.stdout.split("variant")[-1])
+        return tuple(int(v) for v in r.stdout.split("variant")[-1].split())
 
     v1 = run()
-    lines = open(cache).read().split()
-    assert len(lines) == 4 and int(lines[0]) == 0 and int(lines[1]) == 10 and int(lines[3]) == v1
-    other = (v1 + 1) % hfmm.variant_count(10)
-    open(cache, "w").write(f"{lines[0]} {lines[1]} {lines[2]} {other}\n")
+    rows = [ln.split() for ln in open(cache).read().splitlines()]
+    assert sorted(int(r[0]) for r in rows) == [0, 1]
+    byph = {int(r[0]): r for r in rows}
+    for ph in (0, 1):
+        assert len(byph[ph]) == 4 and int(byph[ph][1]) == 10 and int(byph[ph][3]) == v1[ph]
+    other = tuple((v1[ph] + 1) % hfmm.variant_count(10, ph) for ph in (0, 1))
+    text = "".join(f"{ph} {byph[ph][1]} {byph[ph][2]} {other[ph]}\n" for ph in (0, 1))
+    open(cache, "w").write(text)
     assert run() == other
-    assert open(cache).read().split() == [lines[0], lines[1], lines[2], str(other)]   # nothing re-timed
+    assert open(cache).read() == text   # nothing re-timed
