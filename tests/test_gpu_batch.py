@@ -44,6 +44,34 @@ def test_batch_matches_alone_and_oracle():
         check(ys[i].cpu().numpy() / complex(3, -2), yo, 1e-5, f"instance {i} n {d['n']} k {d['k']:.2f} vs oracle")
 
 
+def test_batch_forced_shapes_recapture_same_bits():
+    """Forcing any M2L or P2P launch shape on a graph-replayed batch
+    re-captures its graph with that shape; every shape gives the same bits
+    as the autotuned batch."""
+    inst = synth.batch_instances(count=6, nmin=2048, nmax=16384, seed=7)
+    trees = [hfmm.Tree.from_points(d["points"]) for d in inst]
+    ks = [d["k"] for d in inst]
+    P = 10
+    xs = [torch.from_numpy(d["q"]).to("cuda") for d in inst]
+    ys = [torch.empty_like(x) for x in xs]
+    hfmm.batch_matvec(trees, ks, [P] * len(trees), xs, ys)
+    torch.cuda.synchronize()
+    ref = [y.cpu().numpy() for y in ys]
+    for phase in (hfmm.PHASE_M2L, hfmm.PHASE_P2P):
+        try:
+            for v in range(hfmm.variant_count(P, phase)):
+                hfmm.set_variant(v, phase)
+                for y in ys:
+                    y.zero_()
+                hfmm.batch_matvec(trees, ks, [P] * len(trees), xs, ys)
+                torch.cuda.synchronize()
+                for i, y in enumerate(ys):
+                    np.testing.assert_array_equal(y.cpu().numpy(), ref[i], err_msg=f"phase {phase} shape {v} "
+                                                                                     f"instance {i}")
+        finally:
+            hfmm.set_variant(-1, phase)
+
+
 def test_batch64_full_workload():
     """The batched workload at its full size: 64 instances (N log-uniform in
     [2048, 65536], k uniform in [1, 20], spheres and ellipsoids alternating,
