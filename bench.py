@@ -239,8 +239,9 @@ def bench_batch(a):
             t.matvec(k, P, x, y)
     torch.cuda.synchronize()
     dt_s = (time.perf_counter() - t0) / a.steps
-    # the fused sequence with each M2L and each P2P launch shape forced (the
-    # graph is re-captured per shape), against the autotuned choice timed above
+    # the fused sequence with each M2L launch shape and each P2P variant
+    # forced (the graph is re-captured each time), against the autotuned
+    # choice timed above
     def forced(phase):
         ms = []
         try:
@@ -258,7 +259,7 @@ def bench_batch(a):
         return ms
     shape_ms = forced(hfmm.PHASE_M2L)
     p2p_shape_ms = forced(hfmm.PHASE_P2P)
-    log("batch ms per forced M2L shape:", shape_ms, "per forced P2P shape:", p2p_shape_ms, "autotuned:",
+    log("batch ms per forced M2L shape:", shape_ms, "per forced P2P variant:", p2p_shape_ms, "autotuned:",
         round(dt_b * 1e3, 3))
     out = {
         "metric": "batched FMM matvecs/s (64 instances, one fused graph launch)",
@@ -271,7 +272,7 @@ def bench_batch(a):
         "sequential": {"value": len(trees) / dt_s, "ms_per_step": dt_s * 1e3},
         "speedup_vs_sequential": dt_s / dt_b,
         "m2l_shapes_ms": {"autotuned": dt_b * 1e3, "forced": shape_ms},
-        "p2p_shapes_ms": {"autotuned": dt_b * 1e3, "forced": p2p_shape_ms},
+        "p2p_variants_ms": {"autotuned": dt_b * 1e3, "forced": p2p_shape_ms},
     }
     print(json.dumps(out))
 
@@ -683,28 +684,41 @@ def main():
         tree.matvec(a.k, a.P, qd, yd)
         for kk, v in tree.phase_times().items():
             acc[kk] = acc.get(kk, 0.0) + v / nrep
-    # M2L and P2P times of every launch shape (the autotuner picked one per
-    # phase on the first product)
-    def shapes(phase, name):
-        tuned = tree.variant(a.k, a.P, phase)
-        ms = []
-        try:
-            for v in range(hfmm.variant_count(a.P, phase)):
-                hfmm.set_variant(v, phase)
-                s = 0.0
-                for _ in range(3):
-                    tree.matvec(a.k, a.P, qd, yd)
-                    s += tree.phase_times()[name] / 3
-                ms.append(round(s, 4))
-        finally:
-            hfmm.set_variant(-1, phase)
-        return tuned, ms
-    tuned, shape_ms = shapes(hfmm.PHASE_M2L, "m2l")
-    p2p_tuned, p2p_shape_ms = shapes(hfmm.PHASE_P2P, "p2p")
+    # the M2L time of every launch shape, phases one after another (the
+    # autotuner picked one on the first product)
+    tuned = tree.variant(a.k, a.P, hfmm.PHASE_M2L)
+    shape_ms = []
+    try:
+        for v in range(hfmm.variant_count(a.P, hfmm.PHASE_M2L)):
+            hfmm.set_variant(v, hfmm.PHASE_M2L)
+            s = 0.0
+            for _ in range(3):
+                tree.matvec(a.k, a.P, qd, yd)
+                s += tree.phase_times()["m2l"] / 3
+            shape_ms.append(round(s, 4))
+    finally:
+        hfmm.set_variant(-1, hfmm.PHASE_M2L)
     tree.set_timing(False)
+    # the overlapped product with every P2P variant (launch shape x fork
+    # point) forced: the P2P's cost is how it shares the GPU with the far field
+    p2p_tuned = tree.variant(a.k, a.P, hfmm.PHASE_P2P)
+    p2p_shape_ms = []
+    try:
+        for v in range(hfmm.variant_count(a.P, hfmm.PHASE_P2P)):
+            hfmm.set_variant(v, hfmm.PHASE_P2P)
+            for _ in range(2):
+                tree.matvec(a.k, a.P, qd, yd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                tree.matvec(a.k, a.P, qd, yd)
+            torch.cuda.synchronize()
+            p2p_shape_ms.append(round((time.perf_counter() - t0) / 5 * 1e3, 3))
+    finally:
+        hfmm.set_variant(-1, hfmm.PHASE_P2P)
     phases = {n: round(v, 4) for n, v in acc.items()}
-    log("phases (ms):", phases, "M2L shapes (ms):", shape_ms, "tuned:", tuned, "P2P shapes (ms):", p2p_shape_ms,
-        "tuned:", p2p_tuned)
+    log("phases (ms):", phases, "M2L shapes (ms):", shape_ms, "tuned:", tuned,
+        "matvec per P2P variant (ms):", p2p_shape_ms, "tuned:", p2p_tuned)
     # the M2L as the kernel computes it (xz-plane form): the C and S blocks,
     # 8 (C^2 + S^2) = 4 P^4 + 4 P^2 FLOP, plus 16 FLOP per m > 0 entry to turn
     # the input by the azimuth phase and 16 per m' > 0 row to turn the output
@@ -755,7 +769,7 @@ def main():
                       "n_m2l": st["n_m2l"], "p2p_body_pairs": st["p2p_body_pairs"],
                       "n_tables": st["n_tables"], "setup_s": {"tree": t_tree, "prepare": t_prep},
                       "m2l_shapes": {"tuned": tuned, "ms": shape_ms},
-                      "p2p_shapes": {"tuned": p2p_tuned, "ms": p2p_shape_ms}},
+                      "p2p_variants": {"tuned": p2p_tuned, "matvec_ms": p2p_shape_ms}},
     }
     if not a.no_check and not a.k_imag:
         # the library's FP64 direct sum on the GPU over all sources, 200 targets

@@ -358,12 +358,14 @@ int hfmm_phase_times(const hfmm_tree* tree, float* ms10);
 /* Launch-shape autotuning of the fused matvec.  Phase 0 is the M2L
  * matrix-core kernel (shapes: pairs per wave, waves per SIMD, chunks per
  * wave, table prefetch distance); phase 1 is the P2P near-field kernel
- * (shapes: waves per block, source stages per LDS tile).  The shapes of a
- * phase compute bit-identical results; by default the first product of
- * each fused sequence (a tree's plain matvec, a batch, a server
- * composition) times every shape of each phase on its own work, outside
- * any graph capture, and keeps the fastest, cached per (phase, P, log2 of
- * the phase's work items).
+ * (variants: waves per block x source stages per LDS tile x where the P2P
+ * forks off beside the far field: right after the gather, or after the
+ * M2L, beside its reduction).  The variants of a phase compute
+ * bit-identical results; by default the first product of each fused
+ * sequence (a tree's plain matvec, a batch, a server composition) times
+ * every variant of each phase on its own work (the M2L alone, the P2P
+ * inside the whole product), outside any graph capture, and keeps the
+ * fastest, cached per (phase, P, log2 of the phase's work items).
  *  hfmm_variant_count: number of shapes of `phase` at order P (>= 1), or
  *    HFMM_EINVAL.
  *  hfmm_set_variant: variant >= 0 forces that shape (ignored where it does

@@ -222,10 +222,14 @@ int build_batch(const std::vector<Tree*>& trees, const std::vector<Plan*>& plans
   return HFMM_OK;
 }
 
-// The fused sequence: zero (M, L and the sorted outputs), gather, then P2P
-// on the side stream while P2M, M2M (levels up), M2L and L2L (levels down)
-// run on `s`; L2P waits for P2P and adds the far field to its sums; scatter.
-// P2P and L2P each add into ys in this order on both paths.  With `ev`
+// The fused sequence: zero (M, L and the sorted outputs), gather, P2M, M2M
+// (levels up), M2L and its reduction, L2L (levels down) on `s`, with P2P on
+// the side stream, forked either right after the gather (beside the whole
+// far field) or after the first M2L launch (beside the reduction, which
+// leaves the vector units idle); L2P waits for P2P and adds the far field
+// to its sums; scatter.  The P2P variant (autotuned) is its launch shape
+// and its fork point.  P2P and L2P each add into ys in this order on every
+// path.  With `ev`
 // (phase timing) everything runs on `s`, one phase after another, and the
 // events bracket the phases.  Without `io` the gather from the caller's
 // vectors and the scatter into them are left out (the autotuner's runs, which
@@ -244,12 +248,16 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev, bool io = true) {
   launch_zero(b.d_zero.as<int2>(), b.n_zero, I, s);
   if (io) launch_gather(b.d_gather.as<int2>(), b.n_gather, I, s);
   const bool fork = !ev;
-  if (fork) {
+  const int p2p_v = batch_variant(b, kPhaseP2P), p2p_shape = p2p_v % p2p_variant_count();
+  const bool late_fork = p2p_v >= p2p_variant_count();
+  auto fork_p2p = [&]() -> int {
     HIP_TRY(hipEventRecord(b.ev_fork, s));
     HIP_TRY(hipStreamWaitEvent(b.side, b.ev_fork, 0));
-    launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, batch_variant(b, kPhaseP2P), b.side);
+    launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, p2p_shape, b.side);
     HIP_TRY(hipEventRecord(b.ev_join, b.side));
-  }
+    return HFMM_OK;
+  };
+  if (fork && !late_fork && (rc = fork_p2p())) return rc;
   launch_p2m(b.d_p2m.as<int2>(), b.n_p2m, I, P, b.damped, s);
   if ((rc = mark(1))) return rc;
   for (int l = b.maxlev - 2; l >= 0; --l)
@@ -267,6 +275,7 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev, bool io = true) {
     if (overlap && sg >= 2) HIP_TRY(hipStreamWaitEvent(s, b.ev_red[sg - 2], 0));
     launch_m2l(b.d_m2l.as<int4>() + b.m2l_seg_off[sg], b.m2l_seg_off[sg + 1] - b.m2l_seg_off[sg], I,
                p0.d_bmap.as<int32_t>(), P, batch_variant(b, kPhaseM2L), s);
+    if (fork && late_fork && sg == 0 && (rc = fork_p2p())) return rc;
     if (b.nseg == 1 && (rc = mark(3))) return rc;
     hipStream_t rs = s;
     if (overlap) {
@@ -289,7 +298,7 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev, bool io = true) {
   if (fork) {
     HIP_TRY(hipStreamWaitEvent(s, b.ev_join, 0));
   } else {
-    launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, batch_variant(b, kPhaseP2P), s);
+    launch_p2p(b.d_p2p.as<int2>(), b.n_p2p, I, b.damped, p2p_shape, s);
   }
   if ((rc = mark(6))) return rc;
   launch_l2p(b.d_l2p.as<int2>(), b.n_l2p, I, P, b.damped, s);
@@ -305,9 +314,10 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev, bool io = true) {
 // outside any capture) and keeps the fastest.  The M2L shapes are timed
 // alone (the M2L only writes its staging slots, which the real sequence
 // overwrites).  The P2P runs beside the far field, and a shape that is
-// faster alone can share the GPU worse, so its shapes are timed inside the
-// whole sequence without the caller's vectors (sequence with io off; the
-// real sequence clears what those runs wrote).  Choices are cached per
+// faster alone can share the GPU worse, so its variants (launch shape and
+// fork point) are timed inside the whole sequence without the caller's
+// vectors (sequence with io off; the real sequence clears what those runs
+// wrote).  Choices are cached per
 // (phase, P, log2 of the phase's work items), so rebuilt batches of similar
 // size do not time again.
 // ---------------------------------------------------------------------------
@@ -319,7 +329,7 @@ static bool g_tuned_loaded = false;
 int phase_variant_count(int phase, int P) {
   if (P < 1 || P > kMaxP) return 0;
   if (phase == kPhaseM2L) return m2l_variant_count(P);
-  if (phase == kPhaseP2P) return p2p_variant_count();
+  if (phase == kPhaseP2P) return 2 * p2p_variant_count();  // launch shape x fork point
   return 0;
 }
 

@@ -149,9 +149,10 @@ def test_m2l_launch_shapes_bit_identical(P):
 
 
 def test_p2p_launch_shapes_bit_identical():
-    """Every launch shape of the P2P (waves per block, source stages per LDS
-    tile) gives the same bits, for a point handle with leaves of ragged sizes,
-    a damped one and a BIE handle; the autotuner reports the shape used."""
+    """Every variant of the P2P (waves per block, source stages per LDS tile,
+    and where it forks off beside the far field) gives the same bits, for a
+    point handle with leaves of ragged sizes, a damped one and a BIE handle;
+    the autotuner reports the variant used."""
     n, k, P = 20000, 12.0, 8
     x = synth.sphere_points(n, 32)
     q = torch.from_numpy(synth.strengths(n, 32)).to("cuda")
@@ -171,7 +172,7 @@ def test_p2p_launch_shapes_bit_identical():
         finally:
             hfmm.set_variant(-1, hfmm.PHASE_P2P)
         for v, o in enumerate(outs[1:], 1):
-            np.testing.assert_array_equal(o, outs[0], err_msg=f"P2P shape {v}")
+            np.testing.assert_array_equal(o, outs[0], err_msg=f"P2P variant {v}")
     t2 = hfmm.Tree.from_points(x, ncrit=48)
     y = t2.matvec(k, P, q).cpu().numpy()
     assert 0 <= t2.variant(k, P, hfmm.PHASE_P2P) < nv
