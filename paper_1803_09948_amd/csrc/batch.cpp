@@ -7,6 +7,7 @@
 // one launch per phase and level for all instances together, and can be
 // captured once as a hipGraph and replayed.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <atomic>
@@ -378,7 +379,9 @@ int batch_variant(const Batch& b, int phase) {
 // Times the shapes of one phase (launch(v) enqueues work that runs shape v
 // of the phase on s and returns a status): one warm-up round, then `timed`
 // rounds, each shape scored by its fastest round; records the fastest shape
-// in b.variant[phase].
+// in b.variant[phase].  A timed round runs each shape's work reps times in a
+// row, reps sized from the warm-up round so that a round spans about 2 ms
+// (short products would otherwise be ranked by launch jitter).
 template <class Launch>
 static int tune_phase(Batch& b, int phase, int nwork, int timed, Launch launch, hipStream_t s) {
   const int nv = phase_variant_count(phase, b.P);
@@ -403,14 +406,19 @@ static int tune_phase(Batch& b, int phase, int nwork, int timed, Launch launch, 
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   std::vector<float> score(nv, 0.f);
-  int rc = HFMM_OK;
-  for (int rep = 0; rep <= timed && rc == HFMM_OK; ++rep)  // the first round warms caches and code
-    for (int v = 0; v < nv; ++v) {
+  int rc = HFMM_OK, reps = 1;
+  for (int rep = 0; rep <= timed && rc == HFMM_OK; ++rep) {  // the first round warms caches and code
+    if (rep == 1) {
+      const float fastest = *std::min_element(score.begin(), score.end());
+      reps = fastest >= 2.f ? 1 : std::min(64, (int)std::ceil(2.f / std::max(fastest, 0.03f)));
+    }
+    for (int v = 0; v < nv && rc == HFMM_OK; ++v) {
       hipError_t e = hipEventRecord(e0, s);
-      if (e == hipSuccess) {
+      for (int r = 0; r < reps && e == hipSuccess; ++r) {
         if ((rc = launch(v))) break;
         e = hipGetLastError();
       }
+      if (rc) break;
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
@@ -420,8 +428,10 @@ static int tune_phase(Batch& b, int phase, int nwork, int timed, Launch launch, 
         rc = HFMM_EHIP;
         break;
       }
-      if (rep == 1 || (rep > 1 && ms < score[v])) score[v] = ms;
+      ms /= (float)reps;
+      if (rep <= 1 || ms < score[v]) score[v] = ms;
     }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
