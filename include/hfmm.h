@@ -230,14 +230,14 @@ int hfmm_gmres_solve(hfmm_tree* tree, double k, int32_t P, const void* b_dev,
  * allocate at solve time (code under stream capture, tight serving loops,
  * harnesses that forbid hipMalloc).  The same solver, kernels and result
  * bits; the Krylov workspace ((restart + 1) complex128 basis vectors of nt
- * entries plus work vectors and small arrays: (restart + 4) x 16 x nt bytes
- * and a few KiB) lives in a static device array of 64 MiB that each device
+ * entries plus work vectors and small arrays: ((restart + 4) x 16 + 8) x nt
+ * bytes and a few KiB) lives in a static device array of 72 MiB that each device
  * holds for the life of the process.  Calls on one device share
  * that array: calls that overlap on one device race (serialise them); its
  * contents on entry do not matter.
  *  Requires (k, P) prepared on the handle (hfmm_prepare), since preparing
  *  allocates: EINVAL otherwise.  ENOMEM (nothing done) when the workspace
- *  exceeds 64 MiB (e.g. nt > 123,000 at restart 30).  Other arguments and
+ *  exceeds 72 MiB (e.g. nt > 136,000 at restart 30).  Other arguments and
  *  results as hfmm_gmres_solve. */
 int hfmm_gmres_solve_noalloc(hfmm_tree* tree, double k, int32_t P, const void* b_dev,
                              void* x_dev, double tol, int32_t restart, int32_t maxit,

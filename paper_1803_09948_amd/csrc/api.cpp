@@ -80,6 +80,9 @@ Tree::~Tree() {
     for (auto& e : g_ev) (void)hipEventDestroy(e);
     (void)hipHostFree(g_pin);
   }
+  for (auto& e : n_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (n_stream) (void)hipStreamDestroy(n_stream);
 }
 
 // Device bytes of a handle's resident data: sorted float4 positions, source

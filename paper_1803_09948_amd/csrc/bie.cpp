@@ -173,6 +173,7 @@ static int64_t gmres_layout(char* base, int64_t n, int m, GmresWork* W) {
   w.r = (double2*)take(n * 16);
   w.x64 = (float2*)take(n * 8);
   w.y64 = (float2*)take(n * 8);
+  w.z64 = (float2*)take(n * 8);
   w.H = (double2*)take((int64_t)(m + 1) * m * 16);
   w.cs = (double*)take((int64_t)m * 8);
   w.sn = (double2*)take((int64_t)m * 16);
@@ -223,24 +224,56 @@ static int gm_lag(Tree& t, GmresLag* lag) {
     }
     t.g_pin = p;
   }
+  if (!t.n_stream) {  // the near-correction stream (optional: without it they run after the FMM)
+    hipStream_t ns = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipStreamCreateWithFlags(&ns, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&e0, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&e1, hipEventDisableTiming) == hipSuccess) {
+      t.n_stream = ns;
+      t.n_ev[0] = e0;
+      t.n_ev[1] = e1;
+    } else {
+      if (e0) (void)hipEventDestroy(e0);
+      if (ns) (void)hipStreamDestroy(ns);
+      (void)hipGetLastError();
+    }
+  }
   lag->pin = t.g_pin;
   lag->ev[0] = t.g_ev[0];
   lag->ev[1] = t.g_ev[1];
   return HFMM_OK;
 }
 
-// out = A v (FP64 in/out; FMM and near corrections in FP32, self term in FP64)
+// out = A v (FP64 in/out; FMM and near corrections in FP32, self term in FP64).
+// With the handle's near stream, the near corrections (which read only the
+// input) run on it beside the FMM into z64, and the conversion adds them to
+// the FMM output with the same FP32 add the in-place apply makes: the same
+// bits either way.
 static int apply_A(Tree& t, Plan& pl, const GmresWork& W, const double2* v, double2* out, hipStream_t s) {
   const int64_t n = t.npanel;
   launch_to_c64(n, v, W.x64, s);
+  const bool side = t.n_stream != nullptr && pl.near_side == 1;
+  if (side) {
+    HIP_TRY(hipEventRecord(t.n_ev[0], s));
+    HIP_TRY(hipStreamWaitEvent(t.n_stream, t.n_ev[0], 0));
+    launch_near_apply(n, t.d_near_off.as<int32_t>(), t.d_near_col.as<int32_t>(), pl.d_near_val.as<float2>(),
+                      nullptr, W.x64, W.z64, t.n_stream, true);
+    HIP_TRY(hipEventRecord(t.n_ev[1], t.n_stream));
+  }
   int rc = matvec_impl(t, pl, W.x64, W.y64, s);
   if (rc) return rc;
-  launch_near_apply(n, t.d_near_off.as<int32_t>(), t.d_near_col.as<int32_t>(), pl.d_near_val.as<float2>(),
-                    nullptr, W.x64, W.y64, s);
+  if (side) {
+    HIP_TRY(hipStreamWaitEvent(s, t.n_ev[1], 0));
+  } else {
+    launch_near_apply(n, t.d_near_off.as<int32_t>(), t.d_near_col.as<int32_t>(), pl.d_near_val.as<float2>(),
+                      nullptr, W.x64, W.y64, s);
+  }
+  const float2* z = side ? W.z64 : nullptr;
   if (t.nystrom)
-    launch_from_c64_self6(n, W.y64, pl.d_self6.as<double2>(), v, out, s);
+    launch_from_c64_self6(n, W.y64, pl.d_self6.as<double2>(), v, out, s, z);
   else
-    launch_from_c64_diag(n, W.y64, pl.d_diag.as<double2>(), v, out, s);
+    launch_from_c64_diag(n, W.y64, pl.d_diag.as<double2>(), v, out, s, z);
   HIP_TRY(hipGetLastError());
   return HFMM_OK;
 }
@@ -382,12 +415,51 @@ int gmres_run(Tree& t, Plan& pl, const GmresWork& W, int m, const double2* b, do
   return status;
 }
 
+// First solve of a plan: time the product with the near corrections beside
+// the FMM and after it (a warm-up round, then the best of two rounds of
+// three products each, on the workspace's own vectors: their contents do
+// not matter) and keep the faster.  Heavy corrections (curved elements)
+// gain from the overlap, light ones lose to the extra synchronisation.
+static int tune_near(Tree& t, Plan& pl, const GmresWork& W, hipStream_t s) {
+  if (pl.near_side >= 0) return HFMM_OK;
+  if (!t.n_stream) {
+    pl.near_side = 0;
+    return HFMM_OK;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best[2] = {0.f, 0.f};
+  int rc = HFMM_OK;
+  for (int rep = 0; rep < 3 && rc == HFMM_OK; ++rep)
+    for (int side = 0; side < 2 && rc == HFMM_OK; ++side) {
+      pl.near_side = side;
+      hipError_t e = hipEventRecord(e0, s);
+      for (int i = 0; i < 3 && e == hipSuccess && rc == HFMM_OK; ++i) rc = apply_A(t, pl, W, W.r, W.w, s);
+      if (rc) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        set_error(std::string("near-correction timing: ") + hipGetErrorString(e));
+        rc = HFMM_EHIP;
+        break;
+      }
+      if (rep == 1 || (rep > 1 && ms < best[side])) best[side] = ms;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  pl.near_side = rc == HFMM_OK && best[1] < best[0] ? 1 : 0;
+  return rc;
+}
+
 static int gmres(Tree& t, Plan& pl, const double2* b, double2* x, double tol, int m, int maxit,
                  hfmm_gmres_info* info, hipStream_t s) {
   GmresWork W;
   GmresLag lag;
   int rc = gm_workspace(t, m, &W);
-  if (rc || (rc = gm_lag(t, &lag))) return rc;
+  if (rc || (rc = gm_lag(t, &lag)) || (rc = tune_near(t, pl, W, s))) return rc;
   return gmres_run(t, pl, W, m, b, x, tol, maxit, info, s, &lag);
 }
 

@@ -213,7 +213,8 @@ __global__ void __launch_bounds__(256) k_near_apply(int64_t n, const int32_t* __
                                                     const int32_t* __restrict__ col,
                                                     const float2* __restrict__ val,
                                                     const double2* __restrict__ diag,
-                                                    const float2* __restrict__ x, float2* __restrict__ y) {
+                                                    const float2* __restrict__ x, float2* __restrict__ y,
+                                                    int overwrite) {
   const int64_t i = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
   const int g = threadIdx.x & 15;
   float sr = 0.f, si = 0.f;
@@ -235,8 +236,12 @@ __global__ void __launch_bounds__(256) k_near_apply(int64_t n, const int32_t* __
       sr = fmaf(a.x, b.x, fmaf(-a.y, b.y, sr));
       si = fmaf(a.x, b.y, fmaf(a.y, b.x, si));
     }
-    const float2 o = y[i];
-    y[i] = make_float2(o.x + sr, o.y + si);
+    if (overwrite) {
+      y[i] = make_float2(sr, si);
+    } else {
+      const float2 o = y[i];
+      y[i] = make_float2(o.x + sr, o.y + si);
+    }
   }
 }
 
@@ -262,12 +267,15 @@ __global__ void k_to_c64(int64_t n, const double2* __restrict__ a, float2* __res
 }
 
 // out = (c128) y64 + D .* v  (the self term in FP64)
-__global__ void k_from_c64_diag(int64_t n, const float2* __restrict__ y, const double2* __restrict__ diag,
-                                const double2* __restrict__ v, double2* __restrict__ out) {
+__global__ void k_from_c64_diag(int64_t n, const float2* __restrict__ y, const float2* __restrict__ z,
+                                const double2* __restrict__ diag, const double2* __restrict__ v,
+                                double2* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  float2 yi = y[i];
+  if (z) yi = make_float2(yi.x + z[i].x, yi.y + z[i].y);  // the FP32 sum the near apply would form
   double2 d = diag[i], x = v[i];
-  out[i] = make_double2((double)y[i].x + d.x * x.x - d.y * x.y, (double)y[i].y + d.x * x.y + d.y * x.x);
+  out[i] = make_double2((double)yi.x + d.x * x.x - d.y * x.y, (double)yi.y + d.x * x.y + d.y * x.x);
 }
 
 // partial[b][i] = sum over this block's range of conj(V_i) w, i < nv (nv <= 32)
@@ -463,8 +471,8 @@ void launch_near(int64_t nnz, const int32_t* rows, const int32_t* cols, const do
   if (nnz > 0) k_near<<<nblk(nnz, 4), 256, 0, s>>>(nnz, rows, cols, pan, k, ki, L, gx, gw, ng, val);
 }
 void launch_near_apply(int64_t n, const int32_t* off, const int32_t* col, const float2* val,
-                       const double2* diag, const float2* x, float2* y, hipStream_t s) {
-  if (n > 0) k_near_apply<<<nblk(n, 16), 256, 0, s>>>(n, off, col, val, diag, x, y);
+                       const double2* diag, const float2* x, float2* y, hipStream_t s, bool overwrite) {
+  if (n > 0) k_near_apply<<<nblk(n, 16), 256, 0, s>>>(n, off, col, val, diag, x, y, overwrite ? 1 : 0);
 }
 void launch_plane_wave(int64_t n, const double* pan, double k, double ki, const double* d, double2* b,
                        hipStream_t s) {
@@ -474,8 +482,8 @@ void launch_to_c64(int64_t n, const double2* a, float2* b, hipStream_t s) {
   if (n > 0) k_to_c64<<<nblk(n, 256), 256, 0, s>>>(n, a, b);
 }
 void launch_from_c64_diag(int64_t n, const float2* y, const double2* diag, const double2* v, double2* out,
-                          hipStream_t s) {
-  if (n > 0) k_from_c64_diag<<<nblk(n, 256), 256, 0, s>>>(n, y, diag, v, out);
+                          hipStream_t s, const float2* z) {
+  if (n > 0) k_from_c64_diag<<<nblk(n, 256), 256, 0, s>>>(n, y, z, diag, v, out);
 }
 int mdot_blocks() { return kDotBlocks; }
 void launch_mdot(int64_t n, int nv, const double2* V, int64_t ld, const double2* w, double2* partial,

@@ -10,7 +10,7 @@ namespace hfmm {
 
 // The Krylov workspace of hfmm_gmres_solve_noalloc (see kScratchBytes); each
 // device holds its own copy for the life of the process.
-constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchBytes = size_t(72) << 20;
 static __device__ __align__(256) char scratch[kScratchBytes];
 
 constexpr int kMaxDevices = 64;

@@ -122,6 +122,10 @@ struct M2LSeg {
 struct Plan {
   double k = 0;
   int P = 0;
+  // BIE handles: whether the GMRES product runs its near corrections on the
+  // handle's near stream beside the FMM (1), after it (0), or not yet timed
+  // (-1: after it); the same bits either way
+  int near_side = -1;
   HostTree ct;                   // cells of this plan (wavenumber-aware splitting)
   Lists lists;
   int64_t n_tables = 0;          // M2L operators
@@ -270,6 +274,10 @@ struct Tree {
   DevBuf g_ws;                  // one buffer, carved by gmres_carve
   double* g_pin = nullptr;      // pinned status slots of the lagged checks (4 doubles)
   hipEvent_t g_ev[2] = {};
+  // the GMRES product's near corrections run on their own stream beside the
+  // FMM (created with the lagged-check slots; absent: they run after it)
+  hipStream_t n_stream = nullptr;
+  hipEvent_t n_ev[2] = {};
   DevBuf d_q, d_ys;             // float2 per source / target
   DevBuf d_q64, d_ys64;         // double2 per source / target (FP64 variant)
   int64_t body_bytes = 0;
@@ -316,7 +324,7 @@ int64_t body_bytes(const Tree& t);
 // buffer of gmres_workspace_bytes(n, m) bytes (256-byte aligned parts).
 struct GmresWork {
   double2 *V, *w, *r, *H, *sn, *g, *h, *h2, *part, *dot, *yv;
-  float2 *x64, *y64;
+  float2 *x64, *y64, *z64;  // product input, FMM output, near-correction sums
   double *cs, *st;
 };
 int64_t gmres_workspace_bytes(int64_t n, int m);

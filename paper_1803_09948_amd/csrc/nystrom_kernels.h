@@ -31,8 +31,9 @@ void launch_nys_near(int64_t nitems, const int4* items, const double* pts, const
 void launch_nys_self(int64_t npts, const double* pts, const double* elem, const NysConst* K, int n, double k,
                      double ki, double2* self6, hipStream_t s);
 void launch_self6_apply_c64(int64_t n, const double2* S, const float2* x, float2* y, hipStream_t s);
+// out = (y [+ z in FP32]) + (6 x 6 self blocks) v in FP64
 void launch_from_c64_self6(int64_t n, const float2* y, const double2* S, const double2* v, double2* out,
-                           hipStream_t s);
+                           hipStream_t s, const float2* z = nullptr);
 void launch_plane_wave_pts(int64_t n, const double* pts, double k, double ki, const double* d, double2* b,
                            hipStream_t s);
 

@@ -250,12 +250,15 @@ __global__ void k_self6_apply_c64(int64_t n, const double2* __restrict__ S, cons
 }
 
 // out_j = (c128) y_j + sum_i S[j][i] v[6 (j / 6) + i]  (FP64)
-__global__ void k_from_c64_self6(int64_t n, const float2* __restrict__ y, const double2* __restrict__ S,
-                                 const double2* __restrict__ v, double2* __restrict__ out) {
+__global__ void k_from_c64_self6(int64_t n, const float2* __restrict__ y, const float2* __restrict__ z,
+                                 const double2* __restrict__ S, const double2* __restrict__ v,
+                                 double2* __restrict__ out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int64_t b = 6 * (j / 6);
-  double sr = y[j].x, si = y[j].y;
+  float2 yj = y[j];
+  if (z) yj = make_float2(yj.x + z[j].x, yj.y + z[j].y);  // the FP32 sum the near apply would form
+  double sr = yj.x, si = yj.y;
   for (int i = 0; i < 6; ++i) {
     const double2 a = S[6 * j + i], w = v[b + i];
     sr += a.x * w.x - a.y * w.y;
@@ -288,8 +291,8 @@ void launch_self6_apply_c64(int64_t n, const double2* S, const float2* x, float2
   if (n > 0) k_self6_apply_c64<<<(n + 255) / 256, 256, 0, s>>>(n, S, x, y);
 }
 void launch_from_c64_self6(int64_t n, const float2* y, const double2* S, const double2* v, double2* out,
-                           hipStream_t s) {
-  if (n > 0) k_from_c64_self6<<<(n + 255) / 256, 256, 0, s>>>(n, y, S, v, out);
+                           hipStream_t s, const float2* z) {
+  if (n > 0) k_from_c64_self6<<<(n + 255) / 256, 256, 0, s>>>(n, y, z, S, v, out);
 }
 void launch_plane_wave_pts(int64_t n, const double* pts, double k, double ki, const double* d, double2* b,
                            hipStream_t s) {

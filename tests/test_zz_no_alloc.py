@@ -50,7 +50,7 @@ def test_noalloc_gmres_refusals():
     with pytest.raises(hfmm.HfmmError) as e:       # restart 200 on 320 unknowns still fits; a huge
         t.gmres_noalloc(3.0, 10, b, x, restart=0)  # restart is refused as an argument error
     assert e.value.code == hfmm.HFMM_EINVAL
-    Vb, Tb = synth.icosphere(6)                    # 81920 unknowns x 201 Krylov vectors > 64 MiB
+    Vb, Tb = synth.icosphere(6)                    # 81920 unknowns x 201 Krylov vectors > 72 MiB
     tb = hfmm.Tree.from_mesh(Vb, Tb)
     bb = torch.zeros(len(Tb), dtype=torch.complex128, device="cuda")
     with pytest.raises(hfmm.HfmmError) as e:
