@@ -373,6 +373,11 @@ int hfmm_phase_times(const hfmm_tree* tree, float* ms10);
  *    is re-captured when its shape changes.
  *  hfmm_tree_variant: the shape the plain matvec of (tree, k, P) uses, or -1
  *    before its first product.
+ * Phase 2 (BIE handles) is where the GMRES product adds the near
+ * corrections: 0 after the FMM, 1 on a stream of the handle's own beside
+ * it (the same bits); the first hfmm_gmres_solve of each (k, P) times both,
+ * and hfmm_tree_variant reports the placement its next product uses (-1
+ * for a (k, P) not yet prepared).
  * With the environment variable HFMM_TUNE_CACHE naming a file, the choices
  * are read from it on first use (lines "phase P log2size variant") and each
  * new choice is appended, so later processes reuse them without timing. */

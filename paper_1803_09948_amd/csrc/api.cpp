@@ -839,6 +839,12 @@ int hfmm_tree_variant(hfmm_tree* tree, double k, int32_t P, int32_t phase, int32
   std::memcpy(&kb, &k, 8);
   auto it = t.plans.find(std::make_pair(kb, (int)P));
   *variant = -1;
+  if (phase == kPhaseNear) {  // the placement the next GMRES product uses
+    const int o = variant_override(kPhaseNear);
+    if (it != t.plans.end() && t.bie) *variant = o >= 0 ? o : std::max(it->second->near_side, 0);
+    if (it != t.plans.end() && t.bie && !t.n_stream) *variant = 0;
+    return HFMM_OK;
+  }
   if (it != t.plans.end() && it->second->self && it->second->self->ran)
     *variant = batch_variant(*it->second->self, phase);
   return HFMM_OK;

@@ -322,7 +322,7 @@ static int sequence(Batch& b, hipStream_t s, hipEvent_t* ev, bool io = true) {
 // (phase, P, log2 of the phase's work items), so rebuilt batches of similar
 // size do not time again.
 // ---------------------------------------------------------------------------
-static std::atomic<int> g_override[kNumTunedPhases] = {{-1}, {-1}};
+static std::atomic<int> g_override[kNumTunedPhases] = {{-1}, {-1}, {-1}};
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, int> g_tuned;
 static bool g_tuned_loaded = false;
@@ -331,6 +331,7 @@ int phase_variant_count(int phase, int P) {
   if (P < 1 || P > kMaxP) return 0;
   if (phase == kPhaseM2L) return m2l_variant_count(P);
   if (phase == kPhaseP2P) return 2 * p2p_variant_count();  // launch shape x fork point
+  if (phase == kPhaseNear) return 2;                       // near corrections after / beside the FMM
   return 0;
 }
 
@@ -351,7 +352,7 @@ static void tune_cache_load() {
   if (!f) return;
   int ph, P, lg, v;
   while (std::fscanf(f, "%d %d %d %d", &ph, &P, &lg, &v) == 4)
-    if (ph >= 0 && ph < kNumTunedPhases && v >= 0 && v < phase_variant_count(ph, P))
+    if (ph >= 0 && ph < kNumBatchPhases && v >= 0 && v < phase_variant_count(ph, P))
       g_tuned[std::make_tuple(ph, P, lg)] = v;
   std::fclose(f);
 }
@@ -370,7 +371,10 @@ int set_variant_override(int phase, int variant) {
   return HFMM_OK;
 }
 
+int variant_override(int phase) { return phase >= 0 && phase < kNumTunedPhases ? g_override[phase].load() : -1; }
+
 int batch_variant(const Batch& b, int phase) {
+  if (phase < 0 || phase >= kNumBatchPhases) return 0;
   const int o = g_override[phase].load();
   if (o >= 0 && o < phase_variant_count(phase, b.P)) return o;
   return b.variant[phase] < 0 ? 0 : b.variant[phase];
@@ -507,7 +511,7 @@ int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t 
     HIP_TRY(hipEventCreateWithFlags(&b.ev_out, hipEventDisableTiming));
   }
   bool stale = false;  // a shape forced since capture
-  for (int ph = 0; ph < kNumTunedPhases; ++ph) stale = stale || b.graph_variant[ph] != batch_variant(b, ph);
+  for (int ph = 0; ph < kNumBatchPhases; ++ph) stale = stale || b.graph_variant[ph] != batch_variant(b, ph);
   if (b.exec && stale) {
     (void)hipGraphExecDestroy(b.exec);
     (void)hipGraphDestroy(b.graph);
@@ -516,7 +520,7 @@ int run_batch(Batch& b, const float2* const* xs, float2* const* ys, hipStream_t 
   }
   if (!b.exec) {
     HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
-    for (int ph = 0; ph < kNumTunedPhases; ++ph) b.graph_variant[ph] = batch_variant(b, ph);
+    for (int ph = 0; ph < kNumBatchPhases; ++ph) b.graph_variant[ph] = batch_variant(b, ph);
     rc = sequence(b, b.stream, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b.stream, &g);

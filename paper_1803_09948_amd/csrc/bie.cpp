@@ -253,7 +253,8 @@ static int gm_lag(Tree& t, GmresLag* lag) {
 static int apply_A(Tree& t, Plan& pl, const GmresWork& W, const double2* v, double2* out, hipStream_t s) {
   const int64_t n = t.npanel;
   launch_to_c64(n, v, W.x64, s);
-  const bool side = t.n_stream != nullptr && pl.near_side == 1;
+  const int forced = variant_override(kPhaseNear);
+  const bool side = t.n_stream != nullptr && (forced >= 0 ? forced == 1 : pl.near_side == 1);
   if (side) {
     HIP_TRY(hipEventRecord(t.n_ev[0], s));
     HIP_TRY(hipStreamWaitEvent(t.n_stream, t.n_ev[0], 0));
@@ -421,7 +422,7 @@ int gmres_run(Tree& t, Plan& pl, const GmresWork& W, int m, const double2* b, do
 // not matter) and keep the faster.  Heavy corrections (curved elements)
 // gain from the overlap, light ones lose to the extra synchronisation.
 static int tune_near(Tree& t, Plan& pl, const GmresWork& W, hipStream_t s) {
-  if (pl.near_side >= 0) return HFMM_OK;
+  if (pl.near_side >= 0 || variant_override(kPhaseNear) >= 0) return HFMM_OK;
   if (!t.n_stream) {
     pl.near_side = 0;
     return HFMM_OK;

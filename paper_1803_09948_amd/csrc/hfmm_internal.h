@@ -189,8 +189,10 @@ struct Plan64 {
 };
 
 // Fused execution of one or more instances (instance-aware kernels).
-// Launch-shape autotuning phases: the M2L matrix-core kernel and the P2P.
-enum { kPhaseM2L = 0, kPhaseP2P = 1, kNumTunedPhases = 2 };
+// Autotuned phases: the M2L matrix-core kernel and the P2P (per fused
+// sequence), and where a BIE handle's GMRES product adds its near
+// corrections (per plan).
+enum { kPhaseM2L = 0, kPhaseP2P = 1, kNumBatchPhases = 2, kPhaseNear = 2, kNumTunedPhases = 3 };
 
 struct Batch {
   int count = 0, P = 0, maxlev = 0;
@@ -214,8 +216,8 @@ struct Batch {
   std::vector<hipEvent_t> ev_m2l, ev_red;  // per segment: its M2L done, its reduction done
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int variant[kNumTunedPhases] = {-1, -1};        // launch shapes chosen by the autotuner
-  int graph_variant[kNumTunedPhases] = {-1, -1};  // shapes captured in the graph
+  int variant[kNumBatchPhases] = {-1, -1};        // launch shapes chosen by the autotuner
+  int graph_variant[kNumBatchPhases] = {-1, -1};  // shapes captured in the graph
   bool ran = false;                   // has run at least once
   ~Batch();
 };
@@ -225,6 +227,7 @@ int build_batch(const std::vector<struct Tree*>& trees, const std::vector<Plan*>
 // batch uses, and the per-phase shape counts.
 int phase_variant_count(int phase, int P);
 int set_variant_override(int phase, int variant);
+int variant_override(int phase);  // forced variant of a phase, -1 if none
 int batch_variant(const Batch& b, int phase);
 // First-use setup of a batch: the autotuned launch shapes (times the shapes on
 // the batch's own work), the side stream and its events.  run_batch calls it;

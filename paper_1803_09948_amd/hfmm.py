@@ -348,7 +348,8 @@ class Tree:
 
 
 PHASE_M2L = 0   # tuned phases: the M2L matrix-core kernel
-PHASE_P2P = 1   # and the P2P near-field kernel
+PHASE_P2P = 1   # the P2P near-field kernel
+PHASE_NEAR = 2  # and where a BIE handle's GMRES product adds its near corrections
 
 
 def direct64(src, q, tgt, k, stream=None):

@@ -223,3 +223,26 @@ def test_gmres_checkpoint_resume_bitwise():
     print("uninterrupted", i_ref, "checkpoint", i1, "resumed", i2)
     assert i2["converged"] and i1["iters"] + i2["iters"] == i_ref["iters"]
     np.testing.assert_array_equal(x2.cpu().numpy(), x_ref.cpu().numpy())
+
+
+def test_near_placement_same_bits():
+    """The GMRES product adds the near corrections after the FMM (variant 0
+    of phase 2) or on a stream of the handle's own beside it (variant 1),
+    into a buffer added with the same FP32 add: both give the same solution
+    bits and iteration counts, on a flat and on a curved handle; the first
+    solve timed both placements and reports the one it kept."""
+    cases = [(hfmm.Tree.from_mesh(*synth.icosphere(3)), 4.0),
+             (hfmm.Tree.from_curved_mesh(*synth.curved_icosphere(2)), 3.0)]
+    for t, k in cases:
+        b = t.plane_wave(k)
+        x0, i0 = t.gmres(k, 10, b, tol=1e-5)
+        assert t.variant(k, 10, hfmm.PHASE_NEAR) in (0, 1)
+        try:
+            for v in (0, 1):
+                hfmm.set_variant(v, hfmm.PHASE_NEAR)
+                x, info = t.gmres(k, 10, b, tol=1e-5)
+                assert t.variant(k, 10, hfmm.PHASE_NEAR) == v
+                assert info["iters"] == i0["iters"]
+                np.testing.assert_array_equal(x.cpu().numpy(), x0.cpu().numpy(), err_msg=f"placement {v}")
+        finally:
+            hfmm.set_variant(-1, hfmm.PHASE_NEAR)
