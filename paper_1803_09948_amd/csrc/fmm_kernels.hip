@@ -987,7 +987,7 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 // loads of a group in flight, so a wave waits about once per group instead
 // of once per k-step.
 template <int RT, int KS, int MODE>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT >= 10 ? 1 : 2)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2)))
 k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
           const InstDev* __restrict__ insts, int tstride, int Rp, int P2) {
   constexpr int STRIDE = MODE == 0 ? 9 : 2;
@@ -1002,40 +1002,75 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
   const int dst = cj[0];
   float2* X = MODE == 0 ? I.M : I.L;
   floatx4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = k1, k3 = k1;
-  auto run = [&](int op, int src) {  // acc += T_op X[src] (src < 0: zero column)
-    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)op * tstride) + li + 16 * r0;
-    const bool zc = !ok || src < 0;
-    gcfloat2* B = (gcfloat2*)(X + (size_t)(zc ? 0 : src) * P2);
-    for (int g0 = 0; g0 < KS; g0 += G) {
-      float2 a[G], bv[G];
+  // Rounds q = 0..R-1: operator o = q / NG of this item (M2M: the children
+  // of octant o = 0..7 in order, a column without that child reading zeros;
+  // L2L: its one operator) and group q % NG of G k-steps.  The next round's
+  // table and operand loads are issued before the current round's MFMAs, so
+  // a round's load latency hides under the previous one's matrix-core work;
+  // the accumulation order is that of running the rounds one after another.
+  // The rounds are unrolled (straight-line code keeps the wait counts exact).
+  constexpr int NO = MODE == 0 ? 8 : 1, NG = (KS + G - 1) / G, R = NO * NG;
+  constexpr int NB = RT <= 8 ? 2 : 1;  // operand buffers
+  float2 a[NB][G], bv[NB][G];
+  int srcb[NB];
+  // the source cells of every operator, read before any operand load (a
+  // source index read between rounds would make each round wait for the
+  // previous round's loads: the load counter retires in order)
+  int srcs[RT <= 8 ? NO : 1];
+  if constexpr (RT <= 8) {
 #pragma unroll
-      for (int u = 0; u < G; ++u) {  // steps past KS repeat the last one (unused)
-        const int k = 4 * min(g0 + u, KS - 1) + lk;
-        a[u] = ld2(T + (size_t)k * Rp);
-        bv[u] = ld2(B + min(k, P2 - 1));
-      }
-      __builtin_amdgcn_sched_barrier(0);  // the whole group's loads go out first
+    for (int o = 0; o < NO; ++o) srcs[o] = ok ? cj[1 + (MODE == 0 ? o : 0)] : -1;
+  }
+  auto load = [&](int q, int buf) {
+    const int o = q / NG, g0 = (q % NG) * G;
+    int src;
+    if constexpr (RT <= 8)
+      src = srcs[o];
+    else
+      src = ok ? cj[1 + (MODE == 0 ? o : 0)] : -1;
+    srcb[buf] = src;
+    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)(it.y + (MODE == 0 ? o : 0)) * tstride) + li + 16 * r0;
+    gcfloat2* B = (gcfloat2*)(X + (size_t)(src < 0 ? 0 : src) * P2);
 #pragma unroll
-      for (int u = 0; u < G; ++u) {
-        if (g0 + u < KS) {
-          const int k = 4 * (g0 + u) + lk;
-          const bool z = zc || k >= P2;
-          const float x = z ? 0.f : bv[u].x, y = z ? 0.f : bv[u].y;
-          const float ar = a[u].x, ai = a[u].y;
-          k1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar + ai, x, k1, 0, 0, 0);
-          k2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, y - x, k2, 0, 0, 0);
-          k3 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, x + y, k3, 0, 0, 0);
-        }
+    for (int u = 0; u < G; ++u) {  // steps past KS repeat the last one (unused)
+      const int k = 4 * min(g0 + u, KS - 1) + lk;
+      a[buf][u] = ld2(T + (size_t)k * Rp);
+      bv[buf][u] = ld2(B + min(k, P2 - 1));
+    }
+  };
+  auto compute = [&](int q, int buf) {
+    const int g0 = (q % NG) * G;
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (g0 + u < KS) {
+        const int k = 4 * (g0 + u) + lk;
+        const bool z = srcb[buf] < 0 || k >= P2;
+        const float x = z ? 0.f : bv[buf][u].x, y = z ? 0.f : bv[buf][u].y;
+        const float ar = a[buf][u].x, ai = a[buf][u].y;
+        k1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar + ai, x, k1, 0, 0, 0);
+        k2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, y - x, k2, 0, 0, 0);
+        k3 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, x + y, k3, 0, 0, 0);
       }
     }
   };
-  if constexpr (MODE == 0) {
-    for (int o = 0; o < 8; ++o) {
-      const int src = cj[1 + o];
-      if (__any(ok && src >= 0)) run(it.y + o, src);  // skip octants no column has
+  if constexpr (RT <= 8) {
+    load(0, 0);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (q + 1 < R) load(q + 1, (q + 1) & 1);
+      __builtin_amdgcn_sched_barrier(0);  // the next round's loads go out first
+      compute(q, q & 1);
+      __builtin_amdgcn_sched_barrier(0);
     }
   } else {
-    run(it.y, cj[1]);
+    // larger orders (P >= 12): the unrolled rounds no longer fit the
+    // registers; each round's loads, then its MFMAs
+    for (int q = 0; q < R; ++q) {
+      load(q, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(q, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   if (!ok) return;
   float2* D = X + (size_t)dst * P2;
