@@ -981,21 +981,29 @@ k_m2l_mfma(const int4* __restrict__ chunks, int nitems, int per_xcd, int sub,
 // L2L (MODE 1): an entry is (child, parent), all of one octant operator op;
 // L[child] += T_op L[parent].  Same tiles and Gauss product as M2L.
 // ---------------------------------------------------------------------------
-// One row tile per wave: wave (item, b) computes output tile b, so the
-// short operator chains of the coarse levels run on many waves at once.
+// One row tile per workgroup: workgroup (item, b) computes output tile b,
+// so the short operator chains of the coarse levels run on many waves at
+// once.  M2M up to P = 11 splits the eight octants over two waves
+// (octants 0-3 and 4-7), halving the chain of dependent MFMAs; the second
+// wave's sums are added to the first's through LDS, in that fixed order.
 // Each operator's A and B loads are issued in groups of 16 k-steps with all
 // loads of a group in flight, so a wave waits about once per group instead
 // of once per k-step.
+constexpr int tr_waves(int RT, int MODE) { return MODE == 0 && RT <= 8 ? 2 : 1; }
+
 template <int RT, int KS, int MODE>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2)))
+__global__ void __launch_bounds__(64 * tr_waves(RT, MODE))
+    __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2)))
 k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
           const InstDev* __restrict__ insts, int tstride, int Rp, int P2) {
   constexpr int STRIDE = MODE == 0 ? 9 : 2;
   constexpr int G = KS < 16 ? KS : 16;
+  constexpr bool SPLIT = tr_waves(RT, MODE) == 2;
   const int r0 = blockIdx.x % RT;
   const int4 it = items[blockIdx.x / RT];
   const InstDev& I = insts[it.x];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int half = SPLIT ? (int)(threadIdx.x >> 6) : 0;  // octants 4 half .. 4 half + 3
   const int li = lane & 15, lk = lane >> 4;
   const bool ok = li < it.w;
   const int32_t* cj = cols + (size_t)(it.z + (ok ? li : 0)) * STRIDE;
@@ -1009,7 +1017,8 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
   // a round's load latency hides under the previous one's matrix-core work;
   // the accumulation order is that of running the rounds one after another.
   // The rounds are unrolled (straight-line code keeps the wait counts exact).
-  constexpr int NO = MODE == 0 ? 8 : 1, NG = (KS + G - 1) / G, R = NO * NG;
+  constexpr int NO = MODE == 0 ? (SPLIT ? 4 : 8) : 1, NG = (KS + G - 1) / G, R = NO * NG;
+  const int obase = SPLIT ? 4 * half : 0;  // first octant of this wave
   constexpr int NB = RT <= 8 ? 2 : 1;  // operand buffers
   float2 a[NB][G], bv[NB][G];
   int srcb[NB];
@@ -1019,7 +1028,7 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
   int srcs[RT <= 8 ? NO : 1];
   if constexpr (RT <= 8) {
 #pragma unroll
-    for (int o = 0; o < NO; ++o) srcs[o] = ok ? cj[1 + (MODE == 0 ? o : 0)] : -1;
+    for (int o = 0; o < NO; ++o) srcs[o] = ok ? cj[1 + (MODE == 0 ? obase + o : 0)] : -1;
   }
   auto load = [&](int q, int buf) {
     const int o = q / NG, g0 = (q % NG) * G;
@@ -1027,9 +1036,10 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
     if constexpr (RT <= 8)
       src = srcs[o];
     else
-      src = ok ? cj[1 + (MODE == 0 ? o : 0)] : -1;
+      src = ok ? cj[1 + (MODE == 0 ? obase + o : 0)] : -1;
     srcb[buf] = src;
-    gcfloat2* T = (gcfloat2*)(I.tables + (size_t)(it.y + (MODE == 0 ? o : 0)) * tstride) + li + 16 * r0;
+    gcfloat2* T =
+        (gcfloat2*)(I.tables + (size_t)(it.y + (MODE == 0 ? obase + o : 0)) * tstride) + li + 16 * r0;
     gcfloat2* B = (gcfloat2*)(X + (size_t)(src < 0 ? 0 : src) * P2);
 #pragma unroll
     for (int u = 0; u < G; ++u) {  // steps past KS repeat the last one (unused)
@@ -1071,6 +1081,19 @@ k_tr_mfma(const int4* __restrict__ items, const int32_t* __restrict__ cols,
       compute(q, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
+  }
+  if constexpr (SPLIT) {  // sums of octants 0-3 + sums of octants 4-7
+    __shared__ floatx4 part[3][64];
+    if (half == 1) {
+      part[0][lane] = k1;
+      part[1][lane] = k2;
+      part[2][lane] = k3;
+    }
+    __syncthreads();
+    if (half == 1) return;
+    k1 += part[0][lane];
+    k2 += part[1][lane];
+    k3 += part[2][lane];
   }
   if (!ok) return;
   float2* D = X + (size_t)dst * P2;
@@ -1515,7 +1538,8 @@ static void launch_tr(const int4* items, int n, const int32_t* cols, const InstD
 #define X(p)                                                                                      \
   case p: {                                                                                       \
     constexpr int RT = (p * p + 15) / 16, KS = (p * p + 3) / 4;                                   \
-    k_tr_mfma<RT, KS, MODE><<<n * RT, 64, 0, s>>>(items, cols, insts, xz_table_stride(p), Rp, p * p); \
+    k_tr_mfma<RT, KS, MODE><<<n * RT, 64 * tr_waves(RT, MODE), 0, s>>>(items, cols, insts,               \
+                                                                              xz_table_stride(p), Rp, p * p); \
     break;                                                                                        \
   }
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
